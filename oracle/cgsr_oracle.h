@@ -1,0 +1,147 @@
+/*
+ * FP64 CPU oracle of the CG-SLAM differentiable Gaussian rasterizer.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code with
+ * the HIP library: it is a plain, slow restatement of the paper's equations.
+ *
+ * What it computes (paper, Sec. 3.1 and 3.2):
+ *   Eq. 1   covariance from scale and rotation, Sigma = R S S^T R^T
+ *   Eq. 2   EWA projection, Sigma2d = J W Sigma W^T J^T
+ *   Eq. 3-5 front-to-back alpha blending of colour
+ *   Eq. 6   alpha-blended depth, Eq. 7-8 median depth, Eq. 9 opacity
+ *   Eq. 10  uncertainty map  U = sum_i alpha_i T_i (d_i - D)^2
+ * plus the analytic gradient of all of them with respect to every Gaussian
+ * parameter and to the left se(3) perturbation of the world->camera pose
+ * (Sec. 3.4 names these pose derivatives; their derivation is restated from
+ * first principles here), and a frozen-decision finite-difference probe that
+ * pins that gradient.
+ *
+ * Layouts: every array is plain row-major double.  Gaussian i owns
+ * means[3i..3i+2], log_scales[3i..], quats[4i..] (w,x,y,z), opacity_logits[i],
+ * rgb[3i..].  Images are planar: colour [3][H][W], the others [H][W].
+ * pose = {R[9] row-major, t[3]} maps world to camera (OpenCV axes).
+ * cam  = {fx, fy, cx, cy}; pixel (u, v) has its centre at (u, v).
+ */
+#ifndef CGSR_ORACLE_H
+#define CGSR_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Readings of constants the paper leaves to the 3D Gaussian splatting
+ * rasterizer it builds on.  Kept identical, by value, on the HIP side. */
+#define ORC_NEAR_Z      0.2           /* cull if camera z <= this            */
+#define ORC_TAN_CLAMP   1.3           /* J uses x/z clamped to 1.3 x half-FOV */
+#define ORC_DILATION    0.3           /* added to the 2-D covariance diagonal */
+#define ORC_ALPHA_MAX   0.99          /* alpha is capped here                 */
+#define ORC_ALPHA_MIN   (1.0 / 255.0) /* alpha below this is skipped          */
+#define ORC_T_STOP      1.0e-4        /* stop before T would drop below this  */
+#define ORC_T_MEDIAN    0.5           /* Eq. 8 threshold                      */
+/* Binning rectangle: squared Mahalanobis radius of the alpha >= 1/255 support,
+ * widened by a relative and an absolute margin so a float32 alpha test can
+ * never accept a pixel outside the rectangle. */
+#define ORC_BIN_R2_REL  (1.0 + 1.0 / 128.0)
+#define ORC_BIN_R2_ABS  (1.0 / 256.0)
+
+typedef struct {
+    int64_t n;
+    const double *means, *log_scales, *quats, *opacity_logits, *rgb;
+} orc_gaussians;
+
+typedef struct {
+    int32_t width, height;
+    double fx, fy, cx, cy;
+} orc_camera;
+
+typedef struct {
+    double R[9];
+    double t[3];
+} orc_pose;
+
+/* Per-Gaussian projection, all outputs [n] or [n][k]. */
+typedef struct {
+    int32_t *visible;   /* [n]   1 if it can reach the image                     */
+    int32_t *clamp;     /* [n][2] -1/0/+1: tangent limit applied in J (x, y)       */
+    double *p_cam;      /* [n][3] camera-space mean                              */
+    double *mu;         /* [n][2] pixel-space mean                               */
+    double *cov2d;      /* [n][3] Sigma2d xx, xy, yy (dilated)                    */
+    double *conic;      /* [n][3] inverse of Sigma2d: a, b, c                     */
+    double *depth;      /* [n]                                                   */
+    double *opacity;    /* [n]   sigmoid(logit)                                  */
+    int32_t *rect;      /* [n][4] pixel bounds u0, u1, v0, v1 (inclusive), -1 if none */
+    double *rect_edges; /* [n][4] unrounded mu -/+ extent in x then y            */
+} orc_projection;
+
+/* Rendered maps; NULL members are not written. */
+typedef struct {
+    double *color;         /* [3][H][W] Eq. 3   */
+    double *depth;         /* [H][W]    Eq. 6   */
+    double *opacity;       /* [H][W]    Eq. 9   */
+    double *depth_median;  /* [H][W]    Eq. 7-8 */
+    double *uncertainty;   /* [H][W]    Eq. 10 (needs depth_obs) */
+    int32_t *n_contrib;    /* [H][W]    number of Gaussians blended */
+    double *t_final;       /* [H][W]    transmittance after the last blended one */
+    int32_t *median_id;    /* [H][W]    Gaussian index of the median, -1 if none */
+    double *decision_margin; /* [H][W] smallest relative distance of any alpha,
+                                stop or median decision to its threshold, and of
+                                any pair of blended depths to a tie */
+} orc_images;
+
+/* Upstream gradient images (dL/d maps); NULL members are zero. */
+typedef struct {
+    const double *color, *depth, *opacity, *depth_median, *uncertainty;
+} orc_image_grads;
+
+/* Gradients, accumulated with +=; NULL members are skipped. */
+typedef struct {
+    double *means, *log_scales, *quats, *opacity_logits, *rgb;
+    double *pose;          /* [6] (rho, phi): left perturbation exp(xi^) T_cw */
+    /* gradients with respect to the projected quantities, [n][k] */
+    double *mu, *conic, *opacity, *depth;
+} orc_grads;
+
+/* Projection of every Gaussian (Eq. 1-2). */
+int orc_project(const orc_gaussians *g, const orc_camera *cam, const orc_pose *pose,
+                orc_projection *out);
+
+/* Forward render.  candidates: 0 = every visible Gaussian at every pixel
+ * (brute force), 1 = only Gaussians whose binning rectangle holds the pixel
+ * (the rectangle bounds the alpha support, so the result is the same).
+ * pixels: optional list of n_pixels flat pixel indices v*W+u to render; then
+ * every image is [n_pixels] (colour [3][n_pixels]).  NULL renders all.
+ * depth_obs: [H][W] sensor depth or NULL (then no uncertainty). */
+int orc_render(const orc_gaussians *g, const orc_camera *cam, const orc_pose *pose,
+               const double *depth_obs, int candidates, const int64_t *pixels,
+               int64_t n_pixels, orc_images *out);
+
+/* Analytic backward of orc_render over the whole image. */
+int orc_backward(const orc_gaussians *g, const orc_camera *cam, const orc_pose *pose,
+                 const double *depth_obs, int candidates, const orc_image_grads *dimg,
+                 orc_grads *out);
+
+/* Frozen-decision central differences of the linear probe
+ *     L = sum over maps and pixels of dimg * map
+ * at n_coords coordinates.  Every discontinuous decision (culling, tangent
+ * clamp, skip, stop, alpha cap, median choice, blend order) is recorded at the
+ * unperturbed point and replayed at the perturbed ones, so the result is the
+ * derivative of one smooth branch.  kind: 0 means, 1 log_scales, 2 quats,
+ * 3 opacity_logits, 4 rgb, 5 pose; index = Gaussian index (ignored for pose);
+ * comp = component.  Step h = rel_step * max(1, |theta|) (pose: rel_step). */
+int orc_fd_linear(const orc_gaussians *g, const orc_camera *cam, const orc_pose *pose,
+                  const double *depth_obs, const orc_image_grads *dimg,
+                  int64_t n_coords, const int32_t *kind, const int64_t *index,
+                  const int32_t *comp, double rel_step, double *out);
+
+/* SE(3) exponential of xi = (rho, phi): T = [exp(phi^), V(phi) rho]. */
+void orc_se3_exp(const double xi[6], double R[9], double t[3]);
+
+/* Number of OpenMP threads the oracle uses. */
+int orc_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
