@@ -1,0 +1,229 @@
+/*
+ * cgsr -- a differentiable 3-D Gaussian rasterizer for the tracking and
+ * mapping of CG-SLAM (Hu et al., "CG-SLAM: Efficient Dense RGB-D SLAM in a
+ * Consistent Uncertainty-aware 3D Gaussian Field"), written for AMD Instinct
+ * MI355X (gfx950).
+ *
+ * C ABI.  Every pointer argument documented as "device" is HIP device memory
+ * owned by the caller; the library reads or writes it only during the call's
+ * stream-ordered work and never frees or retains it past the next call on the
+ * same state.  Every "host" pointer is read during the call only.  Streams
+ * are hipStream_t values passed as void* (NULL = the null stream).
+ *
+ * Errors: every call returns a cgsr_status and never aborts; cgsr_last_error()
+ * returns a message for the calling thread's last failure.  Argument checks are
+ * done on the host before any work is enqueued, so a failed call enqueues
+ * nothing.  Device-side capacity overflow of the pair buffer is reported by
+ * cgsr_state_check() (which synchronises the stream).
+ *
+ * Conventions shared by every entry point:
+ *  - Gaussians are SoA float32: means[n][3], log_scales[n][3] (scale = exp),
+ *    quats[n][4] as (w, x, y, z), normalised inside the forward pass,
+ *    opacity_logits[n] (opacity = sigmoid), rgb[n][3]  (Sec. 3.1, Eq. 1).
+ *  - A pose is float32[12] in device memory: a row-major 3x3 rotation followed
+ *    by a translation, mapping world points into the camera frame (x right,
+ *    y down, z forward).
+ *  - Pixel (u, v) has its centre at (u, v).
+ *  - Images are planar float32: colour [3][H][W], every other map [H][W].
+ *  - Pose gradients are the left se(3) perturbation T <- exp(xi^) T at xi = 0,
+ *    xi = (rho, phi): translation part first, then rotation (Sec. 3.4 optimises
+ *    the pose in its Lie algebra).
+ *  - Gradients are accumulated (+=) into caller-zeroed buffers.
+ */
+#ifndef CGSR_H
+#define CGSR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CGSR_OK = 0,
+    CGSR_ERR_INVALID_ARG = -1, /* bad pointer, size or combination of arguments */
+    CGSR_ERR_OOM = -2,         /* device or host allocation failed             */
+    CGSR_ERR_HIP = -3,         /* a HIP runtime call failed                    */
+    CGSR_ERR_CAPACITY = -4,    /* more (tile, Gaussian) pairs than reserved    */
+    CGSR_ERR_STATE = -5        /* backward without a matching forward, etc.    */
+} cgsr_status;
+
+/* Pinhole intrinsics of one view (host memory). */
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+} cgsr_camera;
+
+/* Gaussian parameters (device pointers, SoA float32, layouts above). */
+typedef struct {
+    int64_t n;
+    const float *means, *log_scales, *quats, *opacity_logits, *rgb;
+} cgsr_gaussians;
+
+/* Rendered maps of one view (device pointers; NULL = not written).
+ *   color        [3][H][W]  alpha-blended colour,          Eq. 3
+ *   depth        [H][W]     alpha-blended depth,           Eq. 6
+ *   opacity      [H][W]     accumulated opacity,           Eq. 9
+ *   depth_median [H][W]     depth of the median Gaussian,  Eq. 7-8 (0 if T never falls below 0.5)
+ *   uncertainty  [H][W]     sum alpha T (d - D)^2,         Eq. 10 (needs the sensor depth D) */
+typedef struct {
+    float *color, *depth, *opacity, *depth_median, *uncertainty;
+} cgsr_images;
+
+/* Upstream gradients of one view, same layouts (device; NULL = zero). */
+typedef struct {
+    const float *color, *depth, *opacity, *depth_median, *uncertainty;
+} cgsr_image_grads;
+
+/* Gradient outputs for the Gaussian parameters (device, +=).  All NULL (or
+ * the struct pointer NULL) selects the pose-only backward used by tracking. */
+typedef struct {
+    float *means, *log_scales, *quats, *opacity_logits, *rgb;
+} cgsr_gaussian_grads;
+
+/* Library settings; cgsr_default_settings() fills the defaults. */
+typedef struct {
+    int32_t sync_capacity;   /* 1: render reads the pair count back and grows the
+                                pair buffer as needed (one host sync per render),
+                                except while its stream is being captured into a
+                                graph.  0: never syncs; the pair buffer must be
+                                large enough, see cgsr_state_reserve().          */
+    int32_t sort_blocks;     /* upper bound of workgroups per radix-sort pass    */
+    int32_t timing;          /* 1: time every stage with HIP events on the call's
+                                stream (not while it is being captured); read
+                                the durations with cgsr_get_timings()            */
+} cgsr_settings;
+
+typedef struct {
+    int64_t visible;         /* (view, Gaussian) records that reach the image   */
+    int64_t pairs;           /* (tile, Gaussian) pairs of the last render       */
+    int64_t pair_capacity;   /* pairs the state can hold                         */
+    int32_t overflow;        /* 1 if the last render needed more than capacity   */
+    int32_t n_views;
+    int64_t processed;       /* (pixel, list entry) alpha evaluations of the
+                                forward blend, summed over pixels                */
+    int64_t blended;         /* (pixel, Gaussian) pairs actually blended          */
+} cgsr_stats;
+
+/* Stages timed when cgsr_settings.timing is set. */
+typedef enum {
+    CGSR_STAGE_PROJECT = 0,     /* EWA projection and pair count        */
+    CGSR_STAGE_EMIT = 1,        /* (tile | depth, record) pair emission  */
+    CGSR_STAGE_SORT = 2,        /* radix sort of the pairs               */
+    CGSR_STAGE_RANGES = 3,      /* per-tile list ranges                  */
+    CGSR_STAGE_BLEND_FWD = 4,   /* front-to-back blend                   */
+    CGSR_STAGE_BLEND_BWD = 5,   /* back-to-front blend backward          */
+    CGSR_STAGE_PROJECT_BWD = 6, /* projection backward and pose reduce   */
+    CGSR_NUM_STAGES = 7
+} cgsr_stage;
+
+typedef struct cgsr_state cgsr_state;
+
+/* Default settings. */
+void cgsr_default_settings(cgsr_settings *s);
+
+/* A state holds one forward pass's workspace and saved values: projected
+ * records, sort buffers, tile ranges and per-pixel transmittance.  It is
+ * bound to the device current at creation.  One state serves one stream at a
+ * time; a backward consumes the state of the forward that preceded it. */
+cgsr_status cgsr_state_create(const cgsr_settings *s /* NULL = defaults */, cgsr_state **out);
+cgsr_status cgsr_state_destroy(cgsr_state *st);
+
+/* Grow the workspace for up to max_records (views x Gaussians), max_pixels
+ * (summed over views), max_tiles (summed over views) and max_pairs; never
+ * shrinks.  Allocation happens here, so a render whose sizes fit does not
+ * allocate and can be captured into a HIP graph. */
+cgsr_status cgsr_state_reserve(cgsr_state *st, int64_t max_records, int64_t max_pixels,
+                               int64_t max_tiles, int64_t max_pairs);
+
+/*
+ * Forward render of n_views views of one Gaussian set (Sec. 3.1: EWA projection,
+ * Eq. 2; depth pre-sort; front-to-back alpha blending, Eq. 3-9; uncertainty,
+ * Eq. 10).  All views share one projection launch, one tile sort and one blend
+ * launch.
+ *   g          Gaussian parameters (device).
+ *   n_views    1 .. CGSR_MAX_VIEWS.
+ *   poses      device float[n_views][12].
+ *   cams       host cgsr_camera[n_views].
+ *   depth_obs  host array of n_views device pointers to [H][W] sensor depth,
+ *              or NULL; entry v required iff outs[v].uncertainty != NULL.
+ *   outs       host array of n_views cgsr_images.
+ * The state records the argument pointers for the backward pass: the caller
+ * keeps g, poses and depth_obs unchanged and alive until then.
+ */
+#define CGSR_MAX_VIEWS 64
+cgsr_status cgsr_render(cgsr_state *st, const cgsr_gaussians *g, int32_t n_views, const float *poses,
+                        const cgsr_camera *cams, const float *const *depth_obs,
+                        const cgsr_images *outs, void *stream);
+
+/*
+ * Backward of the last cgsr_render on this state: chain rule of Eq. 2-10 to
+ * every Gaussian parameter (accumulated over views) and to each view's pose.
+ *   dimgs   host array of n_views upstream gradients (device maps; NULL fields
+ *           are zero).  An uncertainty gradient needs that view's sensor depth.
+ *   dG      Gaussian gradients (device, +=), NULL or all-NULL for pose only.
+ *   dposes  device float[n_views][6] (+=), or NULL to skip pose gradients.
+ */
+cgsr_status cgsr_backward(cgsr_state *st, const cgsr_image_grads *dimgs, const cgsr_gaussian_grads *dG,
+                          float *dposes, void *stream);
+
+/*
+ * Gradient images of the tracking objective (Eq. 19):
+ *   L = lambda_color * L_color (Eq. 14) + lambda_depth * L_geo (Eq. 16),
+ * with L_color the mean over the H*W pixels of the L1 norm over RGB and L_geo
+ * the mean absolute depth error.  Writes dL/dcolor [3][H][W] and dL/ddepth
+ * [H][W] (device, overwritten) and adds L to *loss (device float, +=) if loss
+ * is non-NULL.  The subgradient of |x| at 0 is 0.
+ */
+cgsr_status cgsr_tracking_loss_grad(int32_t width, int32_t height, const float *color,
+                                    const float *depth, const float *target_color,
+                                    const float *target_depth, float lambda_color,
+                                    float lambda_depth, float *dcolor, float *ddepth, float *loss,
+                                    void *stream);
+
+/*
+ * One Adam step on each view's pose in its tangent space, then the left
+ * retraction T <- exp(delta^) T (Sec. 3.4, Eq. 20; Adam with bias correction).
+ *   poses      device float[n_views][12], updated in place.
+ *   dposes     device float[n_views][6], read then zeroed.
+ *   adam       device float[n_views][16]: m[6], v[6], step count, 3 unused;
+ *              zero-initialise before the first step.
+ *   lr_rho, lr_phi  learning rates of the translation and rotation parts.
+ */
+cgsr_status cgsr_pose_adam_step(int32_t n_views, float *poses, float *dposes, float *adam,
+                                float lr_rho, float lr_phi, float beta1, float beta2, float eps,
+                                void *stream);
+
+/* Synchronise the stream and report CGSR_ERR_CAPACITY if the last render on
+ * this state overflowed its pair buffer. */
+cgsr_status cgsr_state_check(cgsr_state *st, void *stream);
+
+/* Synchronise the stream and read the counters of the last render. */
+cgsr_status cgsr_get_stats(cgsr_state *st, void *stream, cgsr_stats *out);
+
+/* Durations in milliseconds of the stages of the last timed render (stages
+ * 0-4) and backward (stages 5-6) on this state; ms_out[CGSR_NUM_STAGES].
+ * Synchronises on the recorded events.  CGSR_ERR_STATE if timing is off or a
+ * stage has not run since timing was enabled. */
+cgsr_status cgsr_get_timings(cgsr_state *st, float *ms_out);
+
+/* Debug views of the last render (device buffers owned by the state; valid
+ * until the next render on it).  sorted_keys/values: [pairs] tile-and-depth
+ * keys and record ids after the sort; ranges: [tiles][2] start/end;
+ * records: [records][12] float32 projected record
+ * (mu_x, mu_y, conic a, b, c, opacity, depth, r, g, b, 0, 0).
+ * pixel_state: [pixels][4] (final T as float bits, entries walked,
+ * median position or -1, 0). */
+cgsr_status cgsr_debug_buffers(cgsr_state *st, const uint64_t **sorted_keys, const uint32_t **sorted_values,
+                               const uint32_t **ranges, const float **records, const uint32_t **pixel_state);
+
+/* Message of the calling thread's last failure ("" if none). */
+const char *cgsr_last_error(void);
+
+/* Library version string. */
+const char *cgsr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CGSR_H */

@@ -287,7 +287,7 @@ static void free_candidates(cand_lists *cl)
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
-    double color[3], depth, opacity, depth_median, uncertainty, t_final, margin;
+    double color[3], depth, opacity, depth_median, uncertainty, t_final, margin, order_margin;
     int64_t median;      /* Gaussian id, -1 if T never fell below 0.5 */
     int n;               /* blended Gaussians */
 } pixel_out;
@@ -327,6 +327,7 @@ static void pixel_forward(const gproj *pr, const int64_t *cand, int64_t ncand, d
     memset(po, 0, sizeof(*po));
     po->median = -1;
     po->margin = DBL_MAX;
+    po->order_margin = DBL_MAX;
     for (int64_t k = 0; k < ncand; ++k) {
         const int64_t i = cand[k];
         const gproj *o = &pr[i];
@@ -340,7 +341,7 @@ static void pixel_forward(const gproj *pr, const int64_t *cand, int64_t ncand, d
         const double Tn = T * (1.0 - alpha);
         po->margin = fmin(po->margin, rel_gap(Tn, ORC_T_STOP));
         if (Tn < ORC_T_STOP) break;
-        if (po->n > 0) po->margin = fmin(po->margin, fabs(o->depth - prev_depth) / o->depth);
+        if (po->n > 0) po->order_margin = fmin(po->order_margin, fabs(o->depth - prev_depth) / o->depth);
         const double w = alpha * T;
         for (int c = 0; c < 3; ++c) po->color[c] += w * o->color[c];
         po->depth += w * o->depth;
@@ -433,6 +434,7 @@ int orc_render(const orc_gaussians *g, const orc_camera *cam, const orc_pose *po
         if (out->t_final) out->t_final[k] = po.t_final;
         if (out->median_id) out->median_id[k] = (int32_t)po.median;
         if (out->decision_margin) out->decision_margin[k] = po.margin;
+        if (out->order_margin) out->order_margin[k] = po.order_margin;
     }
     render_teardown(&rc);
     return 0;

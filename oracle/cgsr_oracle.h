@@ -85,9 +85,10 @@ typedef struct {
     int32_t *n_contrib;    /* [H][W]    number of Gaussians blended */
     double *t_final;       /* [H][W]    transmittance after the last blended one */
     int32_t *median_id;    /* [H][W]    Gaussian index of the median, -1 if none */
-    double *decision_margin; /* [H][W] smallest relative distance of any alpha,
-                                stop or median decision to its threshold, and of
-                                any pair of blended depths to a tie */
+    double *decision_margin; /* [H][W] smallest relative distance of any alpha
+                                skip/cap, stop or median decision to its threshold */
+    double *order_margin;    /* [H][W] smallest relative depth gap between two
+                                consecutively blended Gaussians */
 } orc_images;
 
 /* Upstream gradient images (dL/d maps); NULL members are zero. */

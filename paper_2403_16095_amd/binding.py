@@ -1,0 +1,199 @@
+"""ctypes binding of the C ABI declared in include/cgsr.h.
+
+Argument marshalling only: every function here forwards to the symbol of the
+same name in ``libcgsr.so``.  Device pointers are passed as Python ints (a
+torch tensor's ``data_ptr()``), streams as ints (``torch.cuda.Stream.cuda_stream``).
+The library must be built (``paper_2403_16095_amd.build.build()``); there is no
+fallback of any kind when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcgsr.so")
+
+CGSR_OK = 0
+CGSR_ERR_INVALID_ARG = -1
+CGSR_ERR_OOM = -2
+CGSR_ERR_HIP = -3
+CGSR_ERR_CAPACITY = -4
+CGSR_ERR_STATE = -5
+CGSR_MAX_VIEWS = 64
+
+STATUS_NAMES = {0: "CGSR_OK", -1: "CGSR_ERR_INVALID_ARG", -2: "CGSR_ERR_OOM", -3: "CGSR_ERR_HIP",
+                -4: "CGSR_ERR_CAPACITY", -5: "CGSR_ERR_STATE"}
+
+EXPORTED = (
+    "cgsr_default_settings", "cgsr_state_create", "cgsr_state_destroy", "cgsr_state_reserve",
+    "cgsr_render", "cgsr_backward", "cgsr_tracking_loss_grad", "cgsr_pose_adam_step",
+    "cgsr_state_check", "cgsr_get_stats", "cgsr_get_timings", "cgsr_debug_buffers", "cgsr_last_error",
+    "cgsr_version",
+)
+STAGES = ("project", "emit", "sort", "ranges", "blend_fwd", "blend_bwd", "project_bwd")
+
+
+class CgsrError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class cgsr_camera(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float)]
+
+
+class cgsr_gaussians(C.Structure):
+    _fields_ = [("n", C.c_int64), ("means", C.c_void_p), ("log_scales", C.c_void_p),
+                ("quats", C.c_void_p), ("opacity_logits", C.c_void_p), ("rgb", C.c_void_p)]
+
+
+class cgsr_images(C.Structure):
+    _fields_ = [("color", C.c_void_p), ("depth", C.c_void_p), ("opacity", C.c_void_p),
+                ("depth_median", C.c_void_p), ("uncertainty", C.c_void_p)]
+
+
+cgsr_image_grads = cgsr_images  # same layout, const on the C side
+
+
+class cgsr_gaussian_grads(C.Structure):
+    _fields_ = [("means", C.c_void_p), ("log_scales", C.c_void_p), ("quats", C.c_void_p),
+                ("opacity_logits", C.c_void_p), ("rgb", C.c_void_p)]
+
+
+class cgsr_settings(C.Structure):
+    _fields_ = [("sync_capacity", C.c_int32), ("sort_blocks", C.c_int32), ("timing", C.c_int32)]
+
+
+class cgsr_stats(C.Structure):
+    _fields_ = [("visible", C.c_int64), ("pairs", C.c_int64), ("pair_capacity", C.c_int64),
+                ("overflow", C.c_int32), ("n_views", C.c_int32), ("processed", C.c_int64),
+                ("blended", C.c_int64)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libcgsr.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    # torch ships its own HIP runtime under the same soname as ROCm's; loading
+    # it first makes libcgsr.so bind to that one instance, so device pointers
+    # and streams from torch are valid here.
+    import torch  # noqa: F401
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2403_16095_amd.build.build()")
+    L = C.CDLL(LIB_PATH)
+    st = C.c_int
+    vp = C.c_void_p
+    L.cgsr_default_settings.argtypes = [C.POINTER(cgsr_settings)]
+    L.cgsr_default_settings.restype = None
+    L.cgsr_state_create.argtypes = [C.POINTER(cgsr_settings), C.POINTER(vp)]
+    L.cgsr_state_destroy.argtypes = [vp]
+    L.cgsr_state_reserve.argtypes = [vp, C.c_int64, C.c_int64, C.c_int64, C.c_int64]
+    L.cgsr_render.argtypes = [vp, C.POINTER(cgsr_gaussians), C.c_int32, vp, C.POINTER(cgsr_camera),
+                              C.POINTER(vp), C.POINTER(cgsr_images), vp]
+    L.cgsr_backward.argtypes = [vp, C.POINTER(cgsr_images), C.POINTER(cgsr_gaussian_grads), vp, vp]
+    L.cgsr_tracking_loss_grad.argtypes = [C.c_int32, C.c_int32, vp, vp, vp, vp, C.c_float, C.c_float, vp, vp,
+                                          vp, vp]
+    L.cgsr_pose_adam_step.argtypes = [C.c_int32, vp, vp, vp, C.c_float, C.c_float, C.c_float, C.c_float,
+                                      C.c_float, vp]
+    L.cgsr_state_check.argtypes = [vp, vp]
+    L.cgsr_get_stats.argtypes = [vp, vp, C.POINTER(cgsr_stats)]
+    L.cgsr_get_timings.argtypes = [vp, C.POINTER(C.c_float)]
+    L.cgsr_debug_buffers.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
+                                     C.POINTER(vp)]
+    L.cgsr_last_error.argtypes = []
+    L.cgsr_last_error.restype = C.c_char_p
+    L.cgsr_version.argtypes = []
+    L.cgsr_version.restype = C.c_char_p
+    for name in EXPORTED:
+        if name not in ("cgsr_default_settings", "cgsr_last_error", "cgsr_version"):
+            getattr(L, name).restype = st
+    _lib = L
+    return L
+
+
+def _check(status: int) -> None:
+    if status != CGSR_OK:
+        raise CgsrError(status, lib().cgsr_last_error().decode())
+
+
+def cgsr_default_settings() -> cgsr_settings:
+    s = cgsr_settings()
+    lib().cgsr_default_settings(C.byref(s))
+    return s
+
+
+def cgsr_state_create(settings: cgsr_settings | None = None) -> int:
+    out = C.c_void_p()
+    _check(lib().cgsr_state_create(C.byref(settings) if settings is not None else None, C.byref(out)))
+    return out.value
+
+
+def cgsr_state_destroy(state: int) -> None:
+    _check(lib().cgsr_state_destroy(state))
+
+
+def cgsr_state_reserve(state: int, max_records: int, max_pixels: int, max_tiles: int, max_pairs: int) -> None:
+    _check(lib().cgsr_state_reserve(state, max_records, max_pixels, max_tiles, max_pairs))
+
+
+def cgsr_render(state: int, g: cgsr_gaussians, n_views: int, poses: int, cams, depth_obs, outs,
+                stream: int) -> None:
+    """cams: sequence of cgsr_camera; depth_obs: sequence of device pointers (0/None) or None;
+    outs: sequence of cgsr_images."""
+    cam_arr = (cgsr_camera * n_views)(*cams)
+    out_arr = (cgsr_images * n_views)(*outs)
+    dep = None if depth_obs is None else (C.c_void_p * n_views)(*[p or None for p in depth_obs])
+    _check(lib().cgsr_render(state, C.byref(g), n_views, poses, cam_arr, dep, out_arr, stream))
+
+
+def cgsr_backward(state: int, dimgs, dG: cgsr_gaussian_grads | None, dposes: int | None, stream: int) -> None:
+    arr = (cgsr_images * len(dimgs))(*dimgs)
+    _check(lib().cgsr_backward(state, arr, C.byref(dG) if dG is not None else None, dposes, stream))
+
+
+def cgsr_tracking_loss_grad(width, height, color, depth, target_color, target_depth, lambda_color, lambda_depth,
+                            dcolor, ddepth, loss, stream) -> None:
+    _check(lib().cgsr_tracking_loss_grad(width, height, color, depth, target_color, target_depth, lambda_color,
+                                         lambda_depth, dcolor, ddepth, loss, stream))
+
+
+def cgsr_pose_adam_step(n_views, poses, dposes, adam, lr_rho, lr_phi, beta1, beta2, eps, stream) -> None:
+    _check(lib().cgsr_pose_adam_step(n_views, poses, dposes, adam, lr_rho, lr_phi, beta1, beta2, eps, stream))
+
+
+def cgsr_state_check(state: int, stream: int) -> None:
+    _check(lib().cgsr_state_check(state, stream))
+
+
+def cgsr_get_stats(state: int, stream: int) -> cgsr_stats:
+    out = cgsr_stats()
+    _check(lib().cgsr_get_stats(state, stream, C.byref(out)))
+    return out
+
+
+def cgsr_get_timings(state: int) -> dict:
+    """Stage durations (ms) of the last timed render and backward."""
+    out = (C.c_float * len(STAGES))()
+    _check(lib().cgsr_get_timings(state, out))
+    return dict(zip(STAGES, [float(v) for v in out]))
+
+
+def cgsr_debug_buffers(state: int):
+    ptrs = [C.c_void_p() for _ in range(5)]
+    _check(lib().cgsr_debug_buffers(state, *[C.byref(p) for p in ptrs]))
+    return [p.value for p in ptrs]
+
+
+def cgsr_last_error() -> str:
+    return lib().cgsr_last_error().decode()
+
+
+def cgsr_version() -> str:
+    return lib().cgsr_version().decode()

@@ -1,0 +1,607 @@
+// Host runtime behind the C ABI of include/cgsr.h: workspace ownership,
+// argument checks, and the launch sequence of a render and its backward.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "kernels.hpp"
+
+using namespace cgsr;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+cgsr_status fail(cgsr_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess) return fail(CGSR_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T>
+cgsr_status dev_alloc(T** p, int64_t count) {
+  *p = nullptr;
+  if (count <= 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, sizeof(T) * (size_t)count);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(CGSR_ERR_OOM, "hipMalloc of %lld bytes failed: %s", (long long)(sizeof(T) * count),
+                hipGetErrorString(e));
+  }
+  return CGSR_OK;
+}
+
+template <typename T>
+void dev_free(T*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+}  // namespace
+
+struct cgsr_state {
+  int device = 0;
+  cgsr_settings settings{};
+  // capacities
+  int64_t cap_records = 0, cap_pixels = 0, cap_tiles = 0, cap_pairs = 0, cap_blocks = 0;
+  // device workspace
+  float4* rec = nullptr;
+  uint32_t* tiles = nullptr;
+  uint2* rect = nullptr;
+  float* rec_grad = nullptr;
+  uint32_t* block_sum = nullptr;
+  uint32_t* group_sum = nullptr;
+  uint32_t* counters = nullptr;
+  uint2* ranges = nullptr;
+  uint64_t* keys[2] = {nullptr, nullptr};
+  uint32_t* vals[2] = {nullptr, nullptr};
+  uint32_t* hist = nullptr;
+  uint4* pixel_state = nullptr;
+  double* pose_acc = nullptr;
+  unsigned long long* stats_dev = nullptr;
+  uint32_t* pixel_count = nullptr;
+  uint32_t* counters_pinned = nullptr;
+  // stage timing: events[k] marks the start of stage k, events[k + 1] its end
+  // for the forward stages; the backward uses its own pair per stage.
+  hipEvent_t ev_fwd[CGSR_STAGE_BLEND_FWD + 2] = {};
+  hipEvent_t ev_bwd[3] = {};
+  bool fwd_timed = false, bwd_timed = false;
+  // Per-view pointer tables of the forward (slot 0) and the backward (slot 1),
+  // each re-uploaded only when its pointers change, so a steady loop of
+  // render + backward uploads nothing.
+  struct IoTable {
+    ViewIO* dev = nullptr;
+    ViewIO* pinned = nullptr;
+    hipEvent_t event = nullptr;
+    bool event_pending = false;
+    ViewIO cached[CGSR_MAX_VIEWS];
+    int cached_n = -1;
+  } io[2];
+  // last render
+  bool have_forward = false;
+  int32_t n_views = 0;
+  GaussianPtrs g{};
+  const float* poses = nullptr;
+  int sorted_buffer = 0;
+  int64_t total_pixels = 0;
+  int32_t total_tiles = 0;
+  int64_t records = 0;
+  ViewIO io_fwd[CGSR_MAX_VIEWS];
+};
+
+namespace {
+
+constexpr int64_t kCounterWords = kCntGroupTickets + kMaxGroups;
+constexpr int kProjThreads = 256;
+
+cgsr_status set_device(cgsr_state* st) {
+  int cur = -1;
+  HIP_TRY(hipGetDevice(&cur));
+  if (cur != st->device) HIP_TRY(hipSetDevice(st->device));
+  return CGSR_OK;
+}
+
+int64_t scan_blocks_for(int64_t records_per_view, int n_views) {
+  return std::max<int64_t>(1, (records_per_view + kProjThreads - 1) / kProjThreads) * n_views;
+}
+
+cgsr_status grow_pairs(cgsr_state* st, int64_t pairs) {
+  if (pairs <= st->cap_pairs) return CGSR_OK;
+  HIP_TRY(hipDeviceSynchronize());
+  for (int k = 0; k < 2; ++k) {
+    dev_free(st->keys[k]);
+    dev_free(st->vals[k]);
+  }
+  st->cap_pairs = 0;
+  const int64_t cap = std::max<int64_t>(pairs, 1);
+  for (int k = 0; k < 2; ++k) {
+    cgsr_status s = dev_alloc(&st->keys[k], cap);
+    if (s) return s;
+    s = dev_alloc(&st->vals[k], cap);
+    if (s) return s;
+  }
+  st->cap_pairs = cap;
+  return CGSR_OK;
+}
+
+cgsr_status reserve(cgsr_state* st, int64_t records, int64_t pixels, int64_t tiles, int64_t pairs,
+                    int64_t blocks) {
+  if (records > st->cap_records || pixels > st->cap_pixels || tiles > st->cap_tiles || blocks > st->cap_blocks)
+    HIP_TRY(hipDeviceSynchronize());
+  if (records > st->cap_records) {
+    dev_free(st->rec);
+    dev_free(st->tiles);
+    dev_free(st->rect);
+    dev_free(st->rec_grad);
+    st->cap_records = 0;
+    cgsr_status s;
+    if ((s = dev_alloc(&st->rec, kRecF4 * records))) return s;
+    if ((s = dev_alloc(&st->tiles, records))) return s;
+    if ((s = dev_alloc(&st->rect, records))) return s;
+    if ((s = dev_alloc(&st->rec_grad, kGradStride * records))) return s;
+    HIP_TRY(hipMemset(st->rec_grad, 0, sizeof(float) * kGradStride * (size_t)records));
+    st->cap_records = records;
+  }
+  if (pixels > st->cap_pixels) {
+    dev_free(st->pixel_state);
+    dev_free(st->pixel_count);
+    st->cap_pixels = 0;
+    cgsr_status s = dev_alloc(&st->pixel_state, pixels);
+    if (s) return s;
+    s = dev_alloc(&st->pixel_count, pixels);
+    if (s) return s;
+    st->cap_pixels = pixels;
+  }
+  if (tiles > st->cap_tiles) {
+    dev_free(st->ranges);
+    st->cap_tiles = 0;
+    cgsr_status s = dev_alloc(&st->ranges, tiles);
+    if (s) return s;
+    HIP_TRY(hipMemset(st->ranges, 0, sizeof(uint2) * (size_t)tiles));
+    st->cap_tiles = tiles;
+  }
+  if (blocks > st->cap_blocks) {
+    if ((blocks + kScanGroup - 1) / kScanGroup > kMaxGroups)
+      return fail(CGSR_ERR_INVALID_ARG, "too many records (%lld projection workgroups)", (long long)blocks);
+    dev_free(st->block_sum);
+    dev_free(st->group_sum);
+    st->cap_blocks = 0;
+    cgsr_status s;
+    if ((s = dev_alloc(&st->block_sum, blocks))) return s;
+    if ((s = dev_alloc(&st->group_sum, (blocks + kScanGroup - 1) / kScanGroup))) return s;
+    st->cap_blocks = blocks;
+  }
+  return grow_pairs(st, pairs);
+}
+
+bool bad_camera(const cgsr_camera& c) {
+  return c.width < 1 || c.height < 1 || c.width > 65535 * kTile || c.height > 65535 * kTile || !(c.fx > 0.f) ||
+         !(c.fy > 0.f) || !(c.cx == c.cx) || !(c.cy == c.cy);
+}
+
+// Uploads a per-view pointer table if it differs from its last upload.  Under
+// graph capture the tables must already be current: an upload there would be
+// a captured host-to-device copy of staging memory the next call overwrites.
+cgsr_status upload_io(cgsr_state* st, int slot, const ViewIO* io, int n, hipStream_t stream) {
+  auto& t = st->io[slot];
+  if (n == t.cached_n && std::memcmp(io, t.cached, sizeof(ViewIO) * n) == 0) return CGSR_OK;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(stream, &cap));
+  if (cap != hipStreamCaptureStatusNone)
+    return fail(CGSR_ERR_STATE,
+                "image or gradient pointers changed during graph capture; run the same call once "
+                "before capturing it");
+  if (t.event_pending) {
+    HIP_TRY(hipEventSynchronize(t.event));
+    t.event_pending = false;
+  }
+  std::memcpy(t.pinned, io, sizeof(ViewIO) * n);
+  HIP_TRY(hipMemcpyAsync(t.dev, t.pinned, sizeof(ViewIO) * n, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipEventRecord(t.event, stream));
+  t.event_pending = true;
+  std::memcpy(t.cached, io, sizeof(ViewIO) * n);
+  t.cached_n = n;
+  return CGSR_OK;
+}
+
+ProjectBufs project_bufs(cgsr_state* st) {
+  ProjectBufs b;
+  b.rec = st->rec;
+  b.tiles = st->tiles;
+  b.rect = st->rect;
+  b.block_sum = st->block_sum;
+  b.group_sum = st->group_sum;
+  b.counters = st->counters;
+  b.ranges = st->ranges;
+  b.total_tiles = st->total_tiles;
+  b.keys = st->keys[0];
+  b.vals = st->vals[0];
+  b.pair_cap = st->cap_pairs;
+  return b;
+}
+
+int key_bits_for(int32_t total_tiles) {
+  int tb = 0;
+  while ((1ll << tb) < total_tiles) ++tb;
+  return 32 + tb;
+}
+
+}  // namespace
+
+extern "C" {
+
+void cgsr_default_settings(cgsr_settings* s) {
+  if (!s) return;
+  s->sync_capacity = 1;
+  s->sort_blocks = 256;
+  s->timing = 0;
+}
+
+cgsr_status cgsr_state_create(const cgsr_settings* s, cgsr_state** out) {
+  if (!out) return fail(CGSR_ERR_INVALID_ARG, "cgsr_state_create: out is NULL");
+  *out = nullptr;
+  cgsr_state* st = new (std::nothrow) cgsr_state();
+  if (!st) return fail(CGSR_ERR_OOM, "cgsr_state_create: host allocation failed");
+  if (s) st->settings = *s;
+  else cgsr_default_settings(&st->settings);
+  if (st->settings.sort_blocks < 1 || st->settings.sort_blocks > 4096) {
+    delete st;
+    return fail(CGSR_ERR_INVALID_ARG, "sort_blocks must be in [1, 4096]");
+  }
+  cgsr_status r = CGSR_OK;
+  hipError_t e = hipGetDevice(&st->device);
+  if (e != hipSuccess) r = fail(CGSR_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+  if (!r) r = dev_alloc(&st->counters, kCounterWords);
+  if (!r && hipMemset(st->counters, 0, sizeof(uint32_t) * kCounterWords) != hipSuccess)
+    r = fail(CGSR_ERR_HIP, "hipMemset of counters failed");
+  if (!r) r = dev_alloc(&st->hist, (int64_t)st->settings.sort_blocks * 256);
+  if (!r) r = dev_alloc(&st->pose_acc, 6 * CGSR_MAX_VIEWS);
+  if (!r && hipMemset(st->pose_acc, 0, sizeof(double) * 6 * CGSR_MAX_VIEWS) != hipSuccess)
+    r = fail(CGSR_ERR_HIP, "hipMemset of pose accumulators failed");
+  for (int k = 0; k < 2 && !r; ++k) {
+    r = dev_alloc(&st->io[k].dev, CGSR_MAX_VIEWS);
+    if (!r && hipHostMalloc((void**)&st->io[k].pinned, sizeof(ViewIO) * CGSR_MAX_VIEWS, hipHostMallocDefault) !=
+                  hipSuccess)
+      r = fail(CGSR_ERR_OOM, "pinned allocation failed");
+    if (!r && hipEventCreateWithFlags(&st->io[k].event, hipEventDisableTiming) != hipSuccess)
+      r = fail(CGSR_ERR_HIP, "hipEventCreate failed");
+  }
+  if (!r) r = dev_alloc(&st->stats_dev, 3);
+  for (auto& e : st->ev_fwd)
+    if (!r && hipEventCreate(&e) != hipSuccess) r = fail(CGSR_ERR_HIP, "hipEventCreate failed");
+  for (auto& e : st->ev_bwd)
+    if (!r && hipEventCreate(&e) != hipSuccess) r = fail(CGSR_ERR_HIP, "hipEventCreate failed");
+  if (!r && hipHostMalloc((void**)&st->counters_pinned, sizeof(uint32_t) * 4, hipHostMallocDefault) != hipSuccess)
+    r = fail(CGSR_ERR_OOM, "pinned allocation failed");
+  if (r) {
+    cgsr_state_destroy(st);
+    return r;
+  }
+  *out = st;
+  return CGSR_OK;
+}
+
+cgsr_status cgsr_state_destroy(cgsr_state* st) {
+  if (!st) return CGSR_OK;
+  int cur = -1;
+  if (hipGetDevice(&cur) == hipSuccess && cur != st->device) (void)hipSetDevice(st->device);
+  (void)hipDeviceSynchronize();
+  dev_free(st->rec);
+  dev_free(st->tiles);
+  dev_free(st->rect);
+  dev_free(st->rec_grad);
+  dev_free(st->block_sum);
+  dev_free(st->group_sum);
+  dev_free(st->counters);
+  dev_free(st->ranges);
+  for (int k = 0; k < 2; ++k) {
+    dev_free(st->keys[k]);
+    dev_free(st->vals[k]);
+  }
+  dev_free(st->hist);
+  dev_free(st->pixel_state);
+  dev_free(st->pose_acc);
+  for (int k = 0; k < 2; ++k) {
+    dev_free(st->io[k].dev);
+    if (st->io[k].pinned) (void)hipHostFree(st->io[k].pinned);
+    if (st->io[k].event) (void)hipEventDestroy(st->io[k].event);
+  }
+  dev_free(st->stats_dev);
+  dev_free(st->pixel_count);
+  for (auto& e : st->ev_fwd)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& e : st->ev_bwd)
+    if (e) (void)hipEventDestroy(e);
+  if (st->counters_pinned) (void)hipHostFree(st->counters_pinned);
+  if (cur >= 0 && cur != st->device) (void)hipSetDevice(cur);
+  delete st;
+  return CGSR_OK;
+}
+
+cgsr_status cgsr_state_reserve(cgsr_state* st, int64_t max_records, int64_t max_pixels, int64_t max_tiles,
+                               int64_t max_pairs) {
+  if (!st) return fail(CGSR_ERR_INVALID_ARG, "state is NULL");
+  if (max_records < 0 || max_pixels < 0 || max_tiles < 0 || max_pairs < 0 || max_records >= (1ll << 32) ||
+      max_pairs >= (1ll << 32))
+    return fail(CGSR_ERR_INVALID_ARG, "reserve: sizes out of range");
+  cgsr_status s = set_device(st);
+  if (s) return s;
+  // Scan workgroups are bounded by records/256 plus one per view.
+  const int64_t blocks = (max_records + kProjThreads - 1) / kProjThreads + CGSR_MAX_VIEWS;
+  return reserve(st, max_records, max_pixels, max_tiles, max_pairs, blocks);
+}
+
+cgsr_status cgsr_render(cgsr_state* st, const cgsr_gaussians* g, int32_t n_views, const float* poses,
+                        const cgsr_camera* cams, const float* const* depth_obs, const cgsr_images* outs,
+                        void* stream_) {
+  hipStream_t stream = (hipStream_t)stream_;
+  if (!st || !g || !poses || !cams || !outs) return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: NULL argument");
+  if (n_views < 1 || n_views > CGSR_MAX_VIEWS)
+    return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: n_views must be in [1, %d]", CGSR_MAX_VIEWS);
+  if (g->n < 0) return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: negative Gaussian count");
+  if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->rgb))
+    return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: NULL Gaussian parameter pointer");
+  if ((int64_t)g->n * n_views >= (1ll << 32))
+    return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: more than 2^32 (view, Gaussian) records");
+  if (g->n > 0 && ((uintptr_t)g->quats & 15))
+    return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: quats must be 16-byte aligned");
+  int64_t tiles = 0, pixels = 0;
+  ViewIO io[CGSR_MAX_VIEWS];
+  for (int v = 0; v < n_views; ++v) {
+    const cgsr_camera& c = cams[v];
+    if (bad_camera(c)) return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: invalid camera for view %d", v);
+    std::memset(&io[v], 0, sizeof(ViewIO));
+    ViewInfo& vi = io[v].info;
+    vi.width = c.width;
+    vi.height = c.height;
+    vi.fx = c.fx;
+    vi.fy = c.fy;
+    vi.cx = c.cx;
+    vi.cy = c.cy;
+    vi.tiles_x = (c.width + kTile - 1) / kTile;
+    vi.tiles_y = (c.height + kTile - 1) / kTile;
+    vi.tile_base = (int32_t)tiles;
+    vi.pixel_base = (int32_t)pixels;
+    tiles += (int64_t)vi.tiles_x * vi.tiles_y;
+    pixels += (int64_t)c.width * c.height;
+    if (tiles >= INT32_MAX || pixels >= INT32_MAX)
+      return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: too many tiles or pixels");
+    io[v].depth_obs = depth_obs ? depth_obs[v] : nullptr;
+    io[v].color = outs[v].color;
+    io[v].depth = outs[v].depth;
+    io[v].opacity = outs[v].opacity;
+    io[v].depth_median = outs[v].depth_median;
+    io[v].uncertainty = outs[v].uncertainty;
+    if (io[v].uncertainty && !io[v].depth_obs)
+      return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: view %d asks for uncertainty without sensor depth", v);
+  }
+  if (g->n > INT32_MAX) return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: more than 2^31 Gaussians");
+  cgsr_status s = set_device(st);
+  if (s) return s;
+  const int64_t records = g->n * (int64_t)n_views;
+  const int64_t blocks = scan_blocks_for(g->n, n_views);
+  s = reserve(st, records, pixels, tiles, 0, blocks);
+  if (s) return s;
+  st->have_forward = false;
+  st->n_views = n_views;
+  st->g = GaussianPtrs{g->means, g->log_scales, g->quats, g->opacity_logits, g->rgb, g->n};
+  st->poses = poses;
+  st->total_pixels = pixels;
+  st->total_tiles = (int32_t)tiles;
+  st->records = records;
+  std::memcpy(st->io_fwd, io, sizeof(ViewIO) * n_views);
+  s = upload_io(st, 0, io, n_views, stream);
+  if (s) return s;
+
+  const ViewTable vt{st->io[0].dev, n_views, (int32_t)g->n};
+  hipStreamCaptureStatus capturing = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(stream, &capturing));
+  const bool timed = st->settings.timing && capturing == hipStreamCaptureStatusNone;
+  auto mark = [&](int k) -> cgsr_status {
+    if (timed) HIP_TRY(hipEventRecord(st->ev_fwd[k], stream));
+    return CGSR_OK;
+  };
+  st->fwd_timed = false;
+  if ((s = mark(0))) return s;
+  ProjectBufs pb = project_bufs(st);
+  launch_project(st->g, poses, vt, pb, stream);
+  HIP_TRY(hipGetLastError());
+  if (st->settings.sync_capacity && capturing == hipStreamCaptureStatusNone) {
+    HIP_TRY(hipMemcpyAsync(st->counters_pinned, st->counters, sizeof(uint32_t) * 2, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    const int64_t need = st->counters_pinned[kCntPairs];
+    if (need > st->cap_pairs) {
+      s = grow_pairs(st, std::max<int64_t>(need + need / 4, 1 << 16));
+      if (s) return s;
+      // The projection flagged an overflow against the old capacity; clear it.
+      HIP_TRY(hipMemsetAsync(st->counters + kCntOverflow, 0, sizeof(uint32_t), stream));
+      pb = project_bufs(st);
+    }
+  }
+  if ((s = mark(1))) return s;
+  launch_emit(vt, pb, stream);
+  if ((s = mark(2))) return s;
+  SortBufs sb;
+  sb.keys[0] = st->keys[0];
+  sb.keys[1] = st->keys[1];
+  sb.vals[0] = st->vals[0];
+  sb.vals[1] = st->vals[1];
+  sb.hist = st->hist;
+  sb.counters = st->counters;
+  sb.cap = st->cap_pairs;
+  sb.max_blocks = st->settings.sort_blocks;
+  launch_sort(sb, key_bits_for(st->total_tiles), stream, &st->sorted_buffer);
+  if ((s = mark(3))) return s;
+  launch_ranges(st->keys[st->sorted_buffer], st->counters, st->cap_pairs, st->ranges, stream);
+  if ((s = mark(4))) return s;
+  RasterBufs rb;
+  rb.rec = st->rec;
+  rb.vals = st->vals[st->sorted_buffer];
+  rb.ranges = st->ranges;
+  rb.pixel_state = st->pixel_state;
+  rb.rec_grad = st->rec_grad;
+  rb.pixel_count = st->pixel_count;
+  rb.views = vt;
+  rb.total_tiles = st->total_tiles;
+  launch_raster_forward(rb, stream);
+  HIP_TRY(hipGetLastError());
+  if ((s = mark(5))) return s;
+  st->fwd_timed = timed;
+  st->have_forward = true;
+  return CGSR_OK;
+}
+
+cgsr_status cgsr_backward(cgsr_state* st, const cgsr_image_grads* dimgs, const cgsr_gaussian_grads* dG,
+                          float* dposes, void* stream_) {
+  hipStream_t stream = (hipStream_t)stream_;
+  if (!st || !dimgs) return fail(CGSR_ERR_INVALID_ARG, "cgsr_backward: NULL argument");
+  if (!st->have_forward) return fail(CGSR_ERR_STATE, "cgsr_backward: no forward pass on this state");
+  const int n_views = st->n_views;
+  const bool params = dG && (dG->means || dG->log_scales || dG->quats || dG->opacity_logits || dG->rgb);
+  if (!params && !dposes) return CGSR_OK;
+  ViewIO io[CGSR_MAX_VIEWS];
+  for (int v = 0; v < n_views; ++v) {
+    io[v] = st->io_fwd[v];
+    io[v].g_color = dimgs[v].color;
+    io[v].g_depth = dimgs[v].depth;
+    io[v].g_opacity = dimgs[v].opacity;
+    io[v].g_median = dimgs[v].depth_median;
+    io[v].g_uncertainty = dimgs[v].uncertainty;
+    if (io[v].g_uncertainty && !io[v].depth_obs)
+      return fail(CGSR_ERR_INVALID_ARG, "cgsr_backward: view %d has an uncertainty gradient but no sensor depth", v);
+  }
+  cgsr_status s = set_device(st);
+  if (s) return s;
+  s = upload_io(st, 1, io, n_views, stream);
+  if (s) return s;
+  RasterBufs rb;
+  rb.rec = st->rec;
+  rb.vals = st->vals[st->sorted_buffer];
+  rb.ranges = st->ranges;
+  rb.pixel_state = st->pixel_state;
+  rb.rec_grad = st->rec_grad;
+  const ViewTable vt{st->io[1].dev, n_views, (int32_t)st->g.n};
+  rb.pixel_count = st->pixel_count;
+  rb.views = vt;
+  rb.total_tiles = st->total_tiles;
+  hipStreamCaptureStatus capturing = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(stream, &capturing));
+  const bool timed = st->settings.timing && capturing == hipStreamCaptureStatusNone;
+  st->bwd_timed = false;
+  if (timed) HIP_TRY(hipEventRecord(st->ev_bwd[0], stream));
+  launch_raster_backward(rb, params, stream);
+  if (timed) HIP_TRY(hipEventRecord(st->ev_bwd[1], stream));
+  GradPtrs gp{};
+  if (params) gp = GradPtrs{dG->means, dG->log_scales, dG->quats, dG->opacity_logits, dG->rgb};
+  launch_project_backward(st->g, st->poses, vt, st->rec_grad, st->tiles, gp, params, st->pose_acc, dposes,
+                          st->counters, stream);
+  HIP_TRY(hipGetLastError());
+  if (timed) HIP_TRY(hipEventRecord(st->ev_bwd[2], stream));
+  st->bwd_timed = timed;
+  return CGSR_OK;
+}
+
+cgsr_status cgsr_tracking_loss_grad(int32_t width, int32_t height, const float* color, const float* depth,
+                                    const float* target_color, const float* target_depth, float lambda_color,
+                                    float lambda_depth, float* dcolor, float* ddepth, float* loss, void* stream) {
+  if (width < 1 || height < 1) return fail(CGSR_ERR_INVALID_ARG, "tracking loss: empty image");
+  if (!color || !depth || !target_color || !target_depth || !dcolor || !ddepth)
+    return fail(CGSR_ERR_INVALID_ARG, "tracking loss: NULL argument");
+  launch_tracking_loss(width, height, color, depth, target_color, target_depth, lambda_color, lambda_depth, dcolor,
+                       ddepth, loss, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return CGSR_OK;
+}
+
+cgsr_status cgsr_pose_adam_step(int32_t n_views, float* poses, float* dposes, float* adam, float lr_rho,
+                                float lr_phi, float beta1, float beta2, float eps, void* stream) {
+  if (n_views < 1 || n_views > CGSR_MAX_VIEWS) return fail(CGSR_ERR_INVALID_ARG, "pose adam: bad view count");
+  if (!poses || !dposes || !adam) return fail(CGSR_ERR_INVALID_ARG, "pose adam: NULL argument");
+  if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return fail(CGSR_ERR_INVALID_ARG, "pose adam: bad hyper-parameters");
+  launch_pose_adam(n_views, poses, dposes, adam, lr_rho, lr_phi, beta1, beta2, eps, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return CGSR_OK;
+}
+
+cgsr_status cgsr_state_check(cgsr_state* st, void* stream) {
+  if (!st) return fail(CGSR_ERR_INVALID_ARG, "state is NULL");
+  cgsr_status s = set_device(st);
+  if (s) return s;
+  HIP_TRY(hipMemcpyAsync(st->counters_pinned, st->counters, sizeof(uint32_t) * 2, hipMemcpyDeviceToHost,
+                         (hipStream_t)stream));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  if (st->counters_pinned[kCntOverflow])
+    return fail(CGSR_ERR_CAPACITY, "render needed %u pairs, capacity is %lld", st->counters_pinned[kCntPairs],
+                (long long)st->cap_pairs);
+  return CGSR_OK;
+}
+
+cgsr_status cgsr_get_stats(cgsr_state* st, void* stream_, cgsr_stats* out) {
+  if (!st || !out) return fail(CGSR_ERR_INVALID_ARG, "cgsr_get_stats: NULL argument");
+  hipStream_t stream = (hipStream_t)stream_;
+  cgsr_status s = set_device(st);
+  if (s) return s;
+  std::memset(out, 0, sizeof(*out));
+  out->pair_capacity = st->cap_pairs;
+  out->n_views = st->n_views;
+  if (!st->have_forward) return CGSR_OK;
+  HIP_TRY(hipMemsetAsync(st->stats_dev, 0, sizeof(unsigned long long) * 3, stream));
+  launch_stats(st->tiles, st->records, st->pixel_state, st->pixel_count, st->total_pixels, st->stats_dev, stream);
+  unsigned long long host[3];
+  HIP_TRY(hipMemcpyAsync(st->counters_pinned, st->counters, sizeof(uint32_t) * 2, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipMemcpyAsync(host, st->stats_dev, sizeof(host), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  out->pairs = st->counters_pinned[kCntPairs];
+  out->overflow = (int32_t)st->counters_pinned[kCntOverflow];
+  out->visible = (int64_t)host[0];
+  out->processed = (int64_t)host[1];
+  out->blended = (int64_t)host[2];
+  return CGSR_OK;
+}
+
+cgsr_status cgsr_get_timings(cgsr_state* st, float* ms_out) {
+  if (!st || !ms_out) return fail(CGSR_ERR_INVALID_ARG, "cgsr_get_timings: NULL argument");
+  if (!st->settings.timing) return fail(CGSR_ERR_STATE, "cgsr_get_timings: timing is off for this state");
+  if (!st->fwd_timed || !st->bwd_timed)
+    return fail(CGSR_ERR_STATE, "cgsr_get_timings: no timed render and backward since timing was enabled");
+  cgsr_status s = set_device(st);
+  if (s) return s;
+  HIP_TRY(hipEventSynchronize(st->ev_fwd[CGSR_STAGE_BLEND_FWD + 1]));
+  HIP_TRY(hipEventSynchronize(st->ev_bwd[2]));
+  for (int k = 0; k <= CGSR_STAGE_BLEND_FWD; ++k) HIP_TRY(hipEventElapsedTime(&ms_out[k], st->ev_fwd[k], st->ev_fwd[k + 1]));
+  HIP_TRY(hipEventElapsedTime(&ms_out[CGSR_STAGE_BLEND_BWD], st->ev_bwd[0], st->ev_bwd[1]));
+  HIP_TRY(hipEventElapsedTime(&ms_out[CGSR_STAGE_PROJECT_BWD], st->ev_bwd[1], st->ev_bwd[2]));
+  return CGSR_OK;
+}
+
+cgsr_status cgsr_debug_buffers(cgsr_state* st, const uint64_t** sorted_keys, const uint32_t** sorted_values,
+                               const uint32_t** ranges, const float** records, const uint32_t** pixel_state) {
+  if (!st) return fail(CGSR_ERR_INVALID_ARG, "state is NULL");
+  if (!st->have_forward) return fail(CGSR_ERR_STATE, "no forward pass on this state");
+  if (sorted_keys) *sorted_keys = st->keys[st->sorted_buffer];
+  if (sorted_values) *sorted_values = st->vals[st->sorted_buffer];
+  if (ranges) *ranges = reinterpret_cast<const uint32_t*>(st->ranges);
+  if (records) *records = reinterpret_cast<const float*>(st->rec);
+  if (pixel_state) *pixel_state = reinterpret_cast<const uint32_t*>(st->pixel_state);
+  return CGSR_OK;
+}
+
+const char* cgsr_last_error(void) { return g_last_error.c_str(); }
+
+const char* cgsr_version(void) { return "cgsr 0.1 (gfx950)"; }
+
+}  // extern "C"

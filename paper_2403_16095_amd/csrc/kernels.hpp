@@ -1,0 +1,101 @@
+// Host-side launchers of the cgsr kernels (one translation unit per stage).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace cgsr {
+
+// Counters kept in device memory, one block of them per state.
+enum Counter : int {
+  kCntPairs = 0,        // (tile, Gaussian) pairs of the last render
+  kCntOverflow = 1,     // 1 if pairs exceeded the capacity
+  kCntTicketAll = 2,    // last-group detector of the projection scan
+  kCntTicketBwd = 3,    // last-block detector of the projection backward
+  kCntGroupTickets = 8  // per-group tickets start here (kMaxGroups of them)
+};
+constexpr int kScanGroup = 256;            // blocks per scan group
+constexpr int kMaxGroups = 1 << 16;
+
+struct ProjectBufs {
+  float4* rec;              // [M][3]
+  uint32_t* tiles;          // [M] tiles touched (0 = culled)
+  uint2* rect;              // [M] tile rect: x = tx0 | tx1 << 16, y = ty0 | ty1 << 16
+  uint32_t* block_sum;      // [nblocks] then in-group exclusive offsets
+  uint32_t* group_sum;      // [ngroups] then exclusive offsets
+  uint32_t* counters;       // Counter enum above
+  uint2* ranges;            // [total tiles], cleared by the projection
+  int32_t total_tiles;
+  uint64_t* keys;           // [cap] emitted pair keys
+  uint32_t* vals;           // [cap] emitted record ids
+  int64_t pair_cap;
+};
+
+struct GaussianPtrs {
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* opacity_logits;
+  const float* rgb;
+  int64_t n;
+};
+
+struct GradPtrs {
+  float* means;
+  float* log_scales;
+  float* quats;
+  float* opacity_logits;
+  float* rgb;
+};
+
+void launch_project(const GaussianPtrs& g, const float* poses, const ViewTable& vt, const ProjectBufs& b,
+                    hipStream_t s);
+void launch_emit(const ViewTable& vt, const ProjectBufs& b, hipStream_t s);
+// Chain rule from the per-record projected gradients to the parameters and
+// the poses.  pose_acc: device double[views][6] scratch, zero on entry and
+// left zero on exit; dposes (+=) may be null.
+void launch_project_backward(const GaussianPtrs& g, const float* poses, const ViewTable& vt, float* rec_grad,
+                             const uint32_t* tiles, const GradPtrs& dg, bool param_grads, double* pose_acc,
+                             float* dposes, uint32_t* counters, hipStream_t s);
+
+// Radix sort of (key, value) pairs, count read from counters[kCntPairs]
+// (clamped to capacity).  Sorts bits [0, key_bits).  Returns through
+// *result_in_alt whether the sorted data ended in the alternate buffers.
+struct SortBufs {
+  uint64_t* keys[2];
+  uint32_t* vals[2];
+  uint32_t* hist;           // [max_blocks][256]
+  const uint32_t* counters;
+  int64_t cap;
+  int max_blocks;
+};
+void launch_sort(const SortBufs& b, int key_bits, hipStream_t s, int* result_buffer);
+void launch_ranges(const uint64_t* keys, const uint32_t* counters, int64_t cap, uint2* ranges, hipStream_t s);
+
+struct RasterBufs {
+  const float4* rec;
+  const uint32_t* vals;     // sorted record ids
+  const uint2* ranges;
+  uint4* pixel_state;       // [total pixels]: final T bits, entries up to the last blended one,
+                            // median position or -1, alpha evaluations
+  uint32_t* pixel_count;    // [total pixels]: Gaussians blended
+  float* rec_grad;          // [M][kGradStride]
+  ViewTable views;          // device table of the pass (forward or backward pointers)
+  int32_t total_tiles;
+};
+void launch_raster_forward(const RasterBufs& b, hipStream_t s);
+void launch_raster_backward(const RasterBufs& b, bool param_grads, hipStream_t s);
+
+void launch_tracking_loss(int w, int h, const float* color, const float* depth, const float* tcolor,
+                          const float* tdepth, float lc, float ld, float* dcolor, float* ddepth, float* loss,
+                          hipStream_t s);
+void launch_pose_adam(int n_views, float* poses, float* dposes, float* adam, float lr_rho, float lr_phi,
+                      float b1, float b2, float eps, hipStream_t s);
+
+// Statistics: visible records, alpha evaluations and blended pairs.
+void launch_stats(const uint32_t* tiles, int64_t m, const uint4* pixel_state, const uint32_t* pixel_count,
+                  int64_t pixels, unsigned long long* out3, hipStream_t s);
+
+}  // namespace cgsr

@@ -1,0 +1,454 @@
+// Per-(view, Gaussian) projection (Sec. 3.1, Eq. 1-2), pair emission for the
+// tile sort, and the chain rule back from the projected quantities to the
+// Gaussian parameters and the camera pose.
+//
+// Grid layout: blockIdx.y = view, blockIdx.x covers the Gaussians, so every
+// workgroup sees one view and reads its camera from the view table with
+// uniform (scalar) loads.  Records are view-major: m = view * n + i.
+#include <algorithm>
+
+#include "kernels.hpp"
+
+namespace cgsr {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ uint32_t ld_acquire(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exclusive prefix sum over the 256 threads of a workgroup; *total gets the sum.
+__device__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* total, uint32_t* lds4) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t inc = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(inc, d);
+    if (lane >= d) inc += y;
+  }
+  if (lane == 63) lds4[w] = inc;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t t = lds4[k];
+    base += (k < w) ? t : 0u;
+    tot += t;
+  }
+  __syncthreads();
+  *total = tot;
+  return base + inc - x;
+}
+
+// Rotation matrix (row-major) of the unit quaternion (w, x, y, z).
+__device__ __forceinline__ void quat_rot(float w, float x, float y, float z, float R[9]) {
+  R[0] = 1.f - 2.f * (y * y + z * z);
+  R[1] = 2.f * (x * y - w * z);
+  R[2] = 2.f * (x * z + w * y);
+  R[3] = 2.f * (x * y + w * z);
+  R[4] = 1.f - 2.f * (x * x + z * z);
+  R[5] = 2.f * (y * z - w * x);
+  R[6] = 2.f * (x * z - w * y);
+  R[7] = 2.f * (y * z + w * x);
+  R[8] = 1.f - 2.f * (x * x + y * y);
+}
+
+// Everything the forward and backward projection share.
+struct Proj {
+  float qn[4], qinv;     // unit quaternion and 1/|q|
+  float R[9];            // rotation of the ellipsoid
+  float s[3];            // scales
+  float p[3];            // camera-space mean
+  float Sc[6];           // camera covariance W Sigma W^T: 00 01 02 11 12 22
+  float J00, J02, J11, J12;
+  int clampx, clampy;
+  float tx, ty;          // (possibly clamped) tangents used in J
+  float cov[3];          // Sigma2d xx, xy, yy (dilated)
+  float conic[3];
+  float opacity;
+};
+
+// Eq. 1-2 for Gaussian i under pose P.  Returns false if the Gaussian is
+// culled (non-finite or zero quaternion, behind the near plane, opacity under
+// 1/255, singular 2-D covariance).
+__device__ bool project_core(const GaussianPtrs& g, int64_t i, const float* P, const ViewInfo& cam,
+                             Proj& o) {
+  const float4 q = reinterpret_cast<const float4*>(g.quats)[i];
+  const float qn2 = q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w;
+  if (!(qn2 > 0.f) || !(qn2 < 3.0e38f)) return false;
+  o.qinv = 1.0f / sqrtf(qn2);
+  o.qn[0] = q.x * o.qinv; o.qn[1] = q.y * o.qinv; o.qn[2] = q.z * o.qinv; o.qn[3] = q.w * o.qinv;
+  quat_rot(o.qn[0], o.qn[1], o.qn[2], o.qn[3], o.R);
+  const float* ls = g.log_scales + 3 * i;
+  o.s[0] = expf(ls[0]); o.s[1] = expf(ls[1]); o.s[2] = expf(ls[2]);
+  const float* X = g.means + 3 * i;
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+    o.p[r] = __builtin_fmaf(P[3 * r + 0], X[0], __builtin_fmaf(P[3 * r + 1], X[1], __builtin_fmaf(P[3 * r + 2], X[2], P[9 + r])));
+  const float z = o.p[2];
+  if (!(z > kNearZ)) return false;
+  o.opacity = 1.0f / (1.0f + expf(-g.opacity_logits[i]));
+  if (!(o.opacity >= kAlphaMin)) return false;
+  // Sigma = (R S)(R S)^T, then Sc = W Sigma W^T with W the camera rotation.
+  float M[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) M[3 * r + k] = o.R[3 * r + k] * o.s[k];
+  float WM[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      WM[3 * r + k] = __builtin_fmaf(P[3 * r], M[k], __builtin_fmaf(P[3 * r + 1], M[3 + k], P[3 * r + 2] * M[6 + k]));
+  auto dot3 = [&](int r, int c) {
+    return __builtin_fmaf(WM[3 * r], WM[3 * c], __builtin_fmaf(WM[3 * r + 1], WM[3 * c + 1], WM[3 * r + 2] * WM[3 * c + 2]));
+  };
+  o.Sc[0] = dot3(0, 0); o.Sc[1] = dot3(0, 1); o.Sc[2] = dot3(0, 2);
+  o.Sc[3] = dot3(1, 1); o.Sc[4] = dot3(1, 2); o.Sc[5] = dot3(2, 2);
+  // Affine projection Jacobian at p with the tangent clamp.
+  const float limx = kTanClamp * 0.5f * (float)cam.width / cam.fx;
+  const float limy = kTanClamp * 0.5f * (float)cam.height / cam.fy;
+  const float zinv = 1.0f / z;
+  float tx = o.p[0] * zinv, ty = o.p[1] * zinv;
+  o.clampx = tx > limx ? 1 : (tx < -limx ? -1 : 0);
+  o.clampy = ty > limy ? 1 : (ty < -limy ? -1 : 0);
+  if (o.clampx) tx = o.clampx * limx;
+  if (o.clampy) ty = o.clampy * limy;
+  o.tx = tx; o.ty = ty;
+  o.J00 = cam.fx * zinv;
+  o.J02 = -cam.fx * tx * zinv;
+  o.J11 = cam.fy * zinv;
+  o.J12 = -cam.fy * ty * zinv;
+  const float* S = o.Sc;
+  o.cov[0] = o.J00 * o.J00 * S[0] + 2.f * o.J00 * o.J02 * S[2] + o.J02 * o.J02 * S[5] + kDilation;
+  o.cov[1] = o.J00 * o.J11 * S[1] + o.J00 * o.J12 * S[2] + o.J02 * o.J11 * S[4] + o.J02 * o.J12 * S[5];
+  o.cov[2] = o.J11 * o.J11 * S[3] + 2.f * o.J11 * o.J12 * S[4] + o.J12 * o.J12 * S[5] + kDilation;
+  const float det = o.cov[0] * o.cov[2] - o.cov[1] * o.cov[1];
+  if (!(det > 0.f)) return false;
+  const float dinv = 1.0f / det;
+  o.conic[0] = o.cov[2] * dinv;
+  o.conic[1] = -o.cov[1] * dinv;
+  o.conic[2] = o.cov[0] * dinv;
+  return true;
+}
+
+__global__ __launch_bounds__(kThreads) void project_kernel(GaussianPtrs g, const float* __restrict__ poses,
+                                                           ViewTable vt, ProjectBufs b) {
+  __shared__ uint32_t s_scan[4];
+  __shared__ int s_last;
+  const int v = blockIdx.y;
+  const int64_t N = g.n;
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const uint32_t blk = v * gridDim.x + blockIdx.x;
+  const uint32_t nblocks = gridDim.x * gridDim.y;
+
+  // Clear the tile ranges the sort's range pass fills in later.
+  for (int64_t t = (int64_t)blk * kThreads + threadIdx.x; t < b.total_tiles; t += (int64_t)nblocks * kThreads)
+    b.ranges[t] = make_uint2(0u, 0u);
+
+  uint32_t ntiles = 0;
+  if (i < N) {
+    const ViewInfo cam = vt.io[v].info;
+    const float* P = poses + 12 * v;
+    const int64_t m = (int64_t)v * N + i;
+    Proj o;
+    if (project_core(g, i, P, cam, o)) {
+      const float mux = __builtin_fmaf(cam.fx, o.p[0] / o.p[2], cam.cx);
+      const float muy = __builtin_fmaf(cam.fy, o.p[1] / o.p[2], cam.cy);
+      // Bounding box of the alpha >= 1/255 ellipse, widened by the margins.
+      const float r2 = __builtin_fmaf(2.0f * logf(255.0f * o.opacity), kBinR2Rel, kBinR2Abs);
+      const float ex = sqrtf(r2 * o.cov[0]), ey = sqrtf(r2 * o.cov[2]);
+      const float u0 = fmaxf(0.f, ceilf(mux - ex)), u1 = fminf((float)(cam.width - 1), floorf(mux + ex));
+      const float v0 = fmaxf(0.f, ceilf(muy - ey)), v1 = fminf((float)(cam.height - 1), floorf(muy + ey));
+      if (u0 <= u1 && v0 <= v1) {
+        const uint32_t tx0 = (uint32_t)u0 / kTile, tx1 = (uint32_t)u1 / kTile;
+        const uint32_t ty0 = (uint32_t)v0 / kTile, ty1 = (uint32_t)v1 / kTile;
+        ntiles = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+        const float* c = g.rgb + 3 * i;
+        float4* rec = b.rec + kRecF4 * m;
+        rec[0] = make_float4(mux, muy, o.conic[0], o.conic[1]);
+        rec[1] = make_float4(o.conic[2], o.opacity, o.p[2], c[0]);
+        rec[2] = make_float4(c[1], c[2], 0.f, 0.f);
+        b.rect[m] = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
+      }
+    }
+    b.tiles[m] = ntiles;
+  }
+
+  // Pairs per workgroup, then a two-level exclusive scan done by the last
+  // workgroup of each group of 256 and by the last group.
+  uint32_t total;
+  block_exclusive_scan(ntiles, &total, s_scan);
+  const uint32_t grp = blk / kScanGroup;
+  const uint32_t ngroups = (nblocks + kScanGroup - 1) / kScanGroup;
+  if (threadIdx.x == 0) {
+    b.block_sum[blk] = total;
+    __threadfence();
+    const uint32_t gsize = min((uint32_t)kScanGroup, nblocks - grp * kScanGroup);
+    const uint32_t t = atomicAdd(&b.counters[kCntGroupTickets + grp], 1u);
+    s_last = (t == gsize - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  {
+    const uint32_t first = grp * kScanGroup;
+    const uint32_t gsize = min((uint32_t)kScanGroup, nblocks - first);
+    const uint32_t x = threadIdx.x < gsize ? ld_acquire(&b.block_sum[first + threadIdx.x]) : 0u;
+    uint32_t gtot;
+    const uint32_t ex = block_exclusive_scan(x, &gtot, s_scan);
+    if (threadIdx.x < gsize) b.block_sum[first + threadIdx.x] = ex;
+    if (threadIdx.x == 0) {
+      b.group_sum[grp] = gtot;
+      b.counters[kCntGroupTickets + grp] = 0u;
+      __threadfence();
+      const uint32_t t = atomicAdd(&b.counters[kCntTicketAll], 1u);
+      s_last = (t == ngroups - 1);
+    }
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  uint32_t carry = 0;
+  for (uint32_t c0 = 0; c0 < ngroups; c0 += kThreads) {
+    const uint32_t k = c0 + threadIdx.x;
+    const uint32_t x = k < ngroups ? ld_acquire(&b.group_sum[k]) : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan(x, &tot, s_scan);
+    if (k < ngroups) b.group_sum[k] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    b.counters[kCntPairs] = carry;
+    b.counters[kCntOverflow] = (int64_t)carry > b.pair_cap ? 1u : 0u;
+    b.counters[kCntTicketAll] = 0u;
+  }
+}
+
+// Writes every (tile, record) pair in record order, tiles row-major within a
+// record: key = global tile << 32 | float bits of the camera depth (positive,
+// so the bits order like the values), value = record id.
+__global__ __launch_bounds__(kThreads) void emit_kernel(ViewTable vt, ProjectBufs b, int64_t N) {
+  __shared__ uint32_t s_scan[4];
+  const int v = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const uint32_t blk = v * gridDim.x + blockIdx.x;
+  const int64_t m = (int64_t)v * N + i;
+  const uint32_t n = i < N ? b.tiles[m] : 0u;
+  uint32_t total;
+  const uint32_t ex = block_exclusive_scan(n, &total, s_scan);
+  if (n == 0) return;
+  int64_t pos = (int64_t)b.group_sum[blk / kScanGroup] + b.block_sum[blk] + ex;
+  const uint2 r = b.rect[m];
+  const uint32_t tx0 = r.x & 0xFFFF, tx1 = r.x >> 16, ty0 = r.y & 0xFFFF, ty1 = r.y >> 16;
+  const uint64_t dkey = float_key(b.rec[kRecF4 * m + 1].z);
+  const int32_t tile_base = vt.io[v].info.tile_base, tiles_x = vt.io[v].info.tiles_x;
+  for (uint32_t ty = ty0; ty <= ty1; ++ty)
+    for (uint32_t tx = tx0; tx <= tx1; ++tx, ++pos) {
+      if (pos >= b.pair_cap) return;
+      const uint64_t gt = (uint64_t)(tile_base + ty * tiles_x + tx);
+      b.keys[pos] = (gt << 32) | dkey;
+      b.vals[pos] = (uint32_t)m;
+    }
+}
+
+// Backward of project_kernel for one record.  rec_grad holds dL/d(mu, conic,
+// opacity, depth, colour) accumulated by the blend backward; it is read and
+// cleared here so the next backward starts from zero.
+__global__ __launch_bounds__(kThreads) void project_backward_kernel(GaussianPtrs g, const float* __restrict__ poses,
+                                                                    ViewTable vt, float* rec_grad,
+                                                                    const uint32_t* __restrict__ tiles,
+                                                                    GradPtrs dg, int param_grads, int atomic_params,
+                                                                    double* pose_acc, float* dposes,
+                                                                    uint32_t* counters) {
+  __shared__ float s_pose[4][6];
+  __shared__ int s_last;
+  const int v = blockIdx.y;
+  const int64_t N = g.n;
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t m = (int64_t)v * N + i;
+  float gp[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (i < N && tiles[m] != 0u) {
+    float4* gr = reinterpret_cast<float4*>(rec_grad + (int64_t)kGradStride * m);
+    const float4 g0 = gr[0], g1 = gr[1], g2 = gr[2];
+    gr[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+    gr[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+    gr[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+    const float dmux = g0.x, dmuy = g0.y, da = g0.z, db = g0.w, dc = g1.x, dop = g1.y, dd = g1.z;
+    const ViewInfo cam = vt.io[v].info;
+    const float* P = poses + 12 * v;
+    Proj o;
+    if (project_core(g, i, P, cam, o)) {
+      const float x = o.p[0], y = o.p[1], z = o.p[2];
+      const float zinv = 1.0f / z, zinv2 = zinv * zinv;
+      // dL/dSigma2d = -Q dQ Q with the off-diagonal conic entry counted twice.
+      const float a = o.conic[0], b = o.conic[1], c = o.conic[2];
+      const float hb = 0.5f * db;
+      const float QG00 = a * da + b * hb, QG01 = a * hb + b * dc;
+      const float QG10 = b * da + c * hb, QG11 = b * hb + c * dc;
+      const float A00 = -(QG00 * a + QG01 * b);
+      const float A01 = -(QG00 * b + QG01 * c);
+      const float A11 = -(QG10 * b + QG11 * c);
+      // Sigma2d = J Sc J^T: dSc = J^T A J, dJ = 2 A J Sc.
+      const float J00 = o.J00, J02 = o.J02, J11 = o.J11, J12 = o.J12;
+      float dS[6];
+      dS[0] = J00 * J00 * A00;
+      dS[1] = J00 * A01 * J11;
+      dS[2] = J00 * (A00 * J02 + A01 * J12);
+      dS[3] = J11 * J11 * A11;
+      dS[4] = J11 * (A01 * J02 + A11 * J12);
+      dS[5] = J02 * J02 * A00 + 2.f * J02 * J12 * A01 + J12 * J12 * A11;
+      const float* S = o.Sc;
+      // (J Sc) rows
+      const float JS00 = J00 * S[0] + J02 * S[2], JS02 = J00 * S[2] + J02 * S[5];
+      const float JS11 = J11 * S[3] + J12 * S[4], JS12 = J11 * S[4] + J12 * S[5];
+      const float JS01 = J00 * S[1] + J02 * S[4], JS10 = J11 * S[1] + J12 * S[2];
+      const float dJ00 = 2.f * (A00 * JS00 + A01 * JS10);
+      const float dJ02 = 2.f * (A00 * JS02 + A01 * JS12);
+      const float dJ11 = 2.f * (A01 * JS01 + A11 * JS11);
+      const float dJ12 = 2.f * (A01 * JS02 + A11 * JS12);
+      // Camera-space mean.
+      float dp0 = dmux * cam.fx * zinv;
+      float dp1 = dmuy * cam.fy * zinv;
+      float dp2 = -(dmux * cam.fx * x + dmuy * cam.fy * y) * zinv2 + dd;
+      dp2 -= (dJ00 * cam.fx + dJ11 * cam.fy) * zinv2;
+      if (o.clampx == 0) {
+        dp0 -= dJ02 * cam.fx * zinv2;
+        dp2 += dJ02 * 2.f * cam.fx * x * zinv2 * zinv;
+      } else {
+        dp2 += dJ02 * cam.fx * o.tx * zinv2;
+      }
+      if (o.clampy == 0) {
+        dp1 -= dJ12 * cam.fy * zinv2;
+        dp2 += dJ12 * 2.f * cam.fy * y * zinv2 * zinv;
+      } else {
+        dp2 += dJ12 * cam.fy * o.ty * zinv2;
+      }
+      if (param_grads) {
+        // Means: p = W X + t.
+        float dX[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) dX[k] = P[k] * dp0 + P[3 + k] * dp1 + P[6 + k] * dp2;
+        // dSigma = W^T dSc W (symmetric, full 3x3 for the products below).
+        const float dSf[9] = {dS[0], dS[1], dS[2], dS[1], dS[3], dS[4], dS[2], dS[4], dS[5]};
+        float T1[9], dSig[9];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc)
+            T1[3 * r + cc] = P[r] * dSf[cc] + P[3 + r] * dSf[3 + cc] + P[6 + r] * dSf[6 + cc];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc)
+            dSig[3 * r + cc] = T1[3 * r] * P[cc] + T1[3 * r + 1] * P[3 + cc] + T1[3 * r + 2] * P[6 + cc];
+        // Sigma = sum_k s_k^2 r_k r_k^T.
+        float dls[3], dR[9];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          float quad = 0.f;
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) quad += o.R[3 * r + k] * dSig[3 * r + cc] * o.R[3 * cc + k];
+          dls[k] = 2.f * o.s[k] * o.s[k] * quad;
+        }
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc)
+            dR[3 * r + cc] = 2.f * (dSig[3 * r] * o.R[cc] + dSig[3 * r + 1] * o.R[3 + cc] + dSig[3 * r + 2] * o.R[6 + cc]) *
+                             o.s[cc] * o.s[cc];
+        const float w = o.qn[0], qx = o.qn[1], qy = o.qn[2], qz = o.qn[3];
+        float dq[4];
+        dq[0] = 2.f * (-qz * dR[1] + qy * dR[2] + qz * dR[3] - qx * dR[5] - qy * dR[6] + qx * dR[7]);
+        dq[1] = 2.f * (qy * dR[1] + qz * dR[2] + qy * dR[3] - 2.f * qx * dR[4] - w * dR[5] + qz * dR[6] + w * dR[7] -
+                       2.f * qx * dR[8]);
+        dq[2] = 2.f * (-2.f * qy * dR[0] + qx * dR[1] + w * dR[2] + qx * dR[3] + qz * dR[5] - w * dR[6] + qz * dR[7] -
+                       2.f * qy * dR[8]);
+        dq[3] = 2.f * (-2.f * qz * dR[0] - w * dR[1] + qx * dR[2] + w * dR[3] - 2.f * qz * dR[4] + qy * dR[5] +
+                       qx * dR[6] + qy * dR[7]);
+        const float dotq = o.qn[0] * dq[0] + o.qn[1] * dq[1] + o.qn[2] * dq[2] + o.qn[3] * dq[3];
+        const float dlogit = dop * o.opacity * (1.f - o.opacity);
+        float* outs[5] = {dg.means, dg.log_scales, dg.quats, dg.opacity_logits, dg.rgb};
+        const float vals_mean[3] = {dX[0], dX[1], dX[2]};
+        auto put = [&](float* base, int64_t idx, float val) {
+          if (!base) return;
+          if (atomic_params) unsafeAtomicAdd(base + idx, val);
+          else base[idx] += val;
+        };
+        for (int k = 0; k < 3; ++k) put(outs[0], 3 * i + k, vals_mean[k]);
+        for (int k = 0; k < 3; ++k) put(outs[1], 3 * i + k, dls[k]);
+        for (int k = 0; k < 4; ++k) put(outs[2], 4 * i + k, (dq[k] - o.qn[k] * dotq) * o.qinv);
+        put(outs[3], i, dlogit);
+        put(outs[4], 3 * i + 0, g1.w);
+        put(outs[4], 3 * i + 1, g2.x);
+        put(outs[4], 3 * i + 2, g2.y);
+      }
+      // Pose, left perturbation: drho = dp; dphi = p x dp + 2 vee(skew(Sc dSc)).
+      const float Sf[9] = {S[0], S[1], S[2], S[1], S[3], S[4], S[2], S[4], S[5]};
+      const float dSf[9] = {dS[0], dS[1], dS[2], dS[1], dS[3], dS[4], dS[2], dS[4], dS[5]};
+      auto Mrc = [&](int r, int cc) { return Sf[3 * r] * dSf[cc] + Sf[3 * r + 1] * dSf[3 + cc] + Sf[3 * r + 2] * dSf[6 + cc]; };
+      gp[0] = dp0;
+      gp[1] = dp1;
+      gp[2] = dp2;
+      gp[3] = y * dp2 - z * dp1 + 2.f * (Mrc(1, 2) - Mrc(2, 1));
+      gp[4] = z * dp0 - x * dp2 + 2.f * (Mrc(2, 0) - Mrc(0, 2));
+      gp[5] = x * dp1 - y * dp0 + 2.f * (Mrc(0, 1) - Mrc(1, 0));
+    }
+  }
+  if (!dposes) return;
+  // Workgroup reduction of the six pose terms, then one double atomic each.
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const float t = wave_sum(gp[k]);
+    if (lane == 0) s_pose[w][k] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const float t = s_pose[0][threadIdx.x] + s_pose[1][threadIdx.x] + s_pose[2][threadIdx.x] + s_pose[3][threadIdx.x];
+    if (t != 0.f) atomicAdd(pose_acc + 6 * v + threadIdx.x, (double)t);
+  }
+  // The last workgroup moves the accumulated pose gradients to the caller.
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const uint32_t t = atomicAdd(&counters[kCntTicketBwd], 1u);
+    s_last = (t == gridDim.x * gridDim.y - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  for (int k = threadIdx.x; k < 6 * vt.n; k += kThreads) {
+    const double acc = __hip_atomic_load(pose_acc + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    dposes[k] += (float)acc;
+    pose_acc[k] = 0.0;
+  }
+  if (threadIdx.x == 0) counters[kCntTicketBwd] = 0u;
+}
+
+}  // namespace
+
+void launch_project(const GaussianPtrs& g, const float* poses, const ViewTable& vt, const ProjectBufs& b,
+                    hipStream_t s) {
+  const dim3 grid((unsigned)std::max<int64_t>(1, (g.n + kThreads - 1) / kThreads), (unsigned)vt.n);
+  hipLaunchKernelGGL(project_kernel, grid, dim3(kThreads), 0, s, g, poses, vt, b);
+}
+
+void launch_emit(const ViewTable& vt, const ProjectBufs& b, hipStream_t s) {
+  const int64_t n = vt.n_gauss;
+  const dim3 grid((unsigned)std::max<int64_t>(1, (n + kThreads - 1) / kThreads), (unsigned)vt.n);
+  hipLaunchKernelGGL(emit_kernel, grid, dim3(kThreads), 0, s, vt, b, n);
+}
+
+void launch_project_backward(const GaussianPtrs& g, const float* poses, const ViewTable& vt, float* rec_grad,
+                             const uint32_t* tiles, const GradPtrs& dg, bool param_grads, double* pose_acc,
+                             float* dposes, uint32_t* counters, hipStream_t s) {
+  const dim3 grid((unsigned)std::max<int64_t>(1, (g.n + kThreads - 1) / kThreads), (unsigned)vt.n);
+  hipLaunchKernelGGL(project_backward_kernel, grid, dim3(kThreads), 0, s, g, poses, vt, rec_grad, tiles, dg,
+                     param_grads ? 1 : 0, vt.n > 1 ? 1 : 0, pose_acc, dposes, counters);
+}
+
+}  // namespace cgsr

@@ -1,0 +1,332 @@
+"""PyTorch-facing wrappers of the cgsr C ABI.
+
+PyTorch supplies device memory and streams; every step of rendering, its
+backward, the tracking loss gradient and the pose update runs in the HIP
+kernels of ``libcgsr.so``.  Functions here allocate output tensors, check
+shapes and dtypes, and pass raw pointers through :mod:`binding`.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import torch
+
+from . import binding as B
+
+MAP_NAMES = ("color", "depth", "opacity", "depth_median", "uncertainty")
+PARAM_NAMES = ("means", "log_scales", "quats", "opacity_logits", "rgb")
+PARAM_WIDTH = {"means": 3, "log_scales": 3, "quats": 4, "opacity_logits": 1, "rgb": 3}
+
+#: Learning rates of sequential tracking, rotation (so(3)) and translation
+#: parts (Sec. 4, Implementation Details).
+TRACK_LR_PHI = 0.0015
+TRACK_LR_RHO = 0.00215
+#: Replica weights of the tracking loss, Eq. 19 (Sec. 4).
+TRACK_LAMBDA = (0.2, 1.0)
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _check_f32(name, t, shape=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def gaussians_struct(scene: dict) -> B.cgsr_gaussians:
+    n = scene["means"].shape[0]
+    for k in PARAM_NAMES:
+        w = PARAM_WIDTH[k]
+        _check_f32(k, scene[k], (n,) if w == 1 else (n, w))
+    return B.cgsr_gaussians(n, *[scene[k].data_ptr() for k in PARAM_NAMES])
+
+
+def camera_struct(cam: dict) -> B.cgsr_camera:
+    return B.cgsr_camera(int(cam["width"]), int(cam["height"]), float(cam["fx"]), float(cam["fy"]),
+                         float(cam["cx"]), float(cam["cy"]))
+
+
+def pose_tensor(R, t, device="cuda") -> torch.Tensor:
+    """Pack a world->camera pose into the float32[12] layout of the ABI."""
+    R = torch.as_tensor(R, dtype=torch.float64).reshape(9)
+    t = torch.as_tensor(t, dtype=torch.float64).reshape(3)
+    return torch.cat([R, t]).to(torch.float32).to(device).contiguous()
+
+
+class State:
+    """Owns one cgsr_state (the workspace of a render and its backward)."""
+
+    def __init__(self, sync_capacity: bool = True, sort_blocks: int = 256, timing: bool = False):
+        s = B.cgsr_default_settings()
+        s.sync_capacity = int(sync_capacity)
+        s.sort_blocks = int(sort_blocks)
+        s.timing = int(timing)
+        self.handle = B.cgsr_state_create(s)
+        self.n_views = 0
+        self.n = 0
+
+    def reserve(self, records=0, pixels=0, tiles=0, pairs=0):
+        B.cgsr_state_reserve(self.handle, int(records), int(pixels), int(tiles), int(pairs))
+
+    def stats(self) -> B.cgsr_stats:
+        return B.cgsr_get_stats(self.handle, _stream())
+
+    def check(self):
+        B.cgsr_state_check(self.handle, _stream())
+
+    def timings(self) -> dict:
+        return B.cgsr_get_timings(self.handle)
+
+    def close(self):
+        if self.handle:
+            B.cgsr_state_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def render(state: State, scene: dict, poses: torch.Tensor, cams, depth_obs=None,
+           maps=MAP_NAMES) -> list:
+    """Render ``len(cams)`` views in one launch sequence.
+
+    poses: float32 CUDA tensor [V, 12] (or [12] for one view).  depth_obs:
+    None or a list of [H, W] tensors (None entries allowed).  Returns one dict
+    of maps per view (only those in ``maps``; ``uncertainty`` needs depth)."""
+    if isinstance(cams, dict):
+        cams = [cams]
+    V = len(cams)
+    poses = poses.reshape(V, 12)
+    _check_f32("poses", poses)
+    g = gaussians_struct(scene)
+    dev = poses.device
+    outs, structs, deps = [], [], []
+    for v, cam in enumerate(cams):
+        H, W = int(cam["height"]), int(cam["width"])
+        d = None if depth_obs is None else depth_obs[v]
+        if d is not None:
+            _check_f32(f"depth_obs[{v}]", d, (H, W))
+        o = {}
+        for k in maps:
+            if k == "uncertainty" and d is None:
+                continue
+            o[k] = torch.empty((3, H, W) if k == "color" else (H, W), dtype=torch.float32, device=dev)
+        outs.append(o)
+        structs.append(B.cgsr_images(*[_ptr(o.get(k)) for k in MAP_NAMES]))
+        deps.append(_ptr(d))
+    B.cgsr_render(state.handle, g, V, poses.data_ptr(), [camera_struct(c) for c in cams],
+                  None if depth_obs is None else deps, structs, _stream())
+    state.n_views, state.n = V, g.n
+    # The backward reads these through the pointers the state recorded.
+    state.inputs = (scene, poses, depth_obs)
+    return outs
+
+
+def backward(state: State, dimgs, param_grads: bool = True, pose_grads: bool = True):
+    """Backward of the last render on ``state``.
+
+    dimgs: list (one per view) of dicts of upstream gradient maps (missing =
+    zero).  Returns (dict of parameter gradients or None, dposes [V,6] or None)."""
+    V, n = state.n_views, state.n
+    if len(dimgs) != V:
+        raise ValueError(f"expected {V} gradient dicts, got {len(dimgs)}")
+    keep, structs = [], []
+    for d in dimgs:
+        dd = {k: (None if d.get(k) is None else d[k].contiguous().float()) for k in MAP_NAMES}
+        keep.append(dd)
+        structs.append(B.cgsr_images(*[_ptr(dd[k]) for k in MAP_NAMES]))
+    dev = next((t.device for d in keep for t in d.values() if t is not None), torch.device("cuda"))
+    grads = None
+    dG = None
+    if param_grads:
+        grads = {k: torch.zeros((n,) if PARAM_WIDTH[k] == 1 else (n, PARAM_WIDTH[k]), dtype=torch.float32,
+                                device=dev) for k in PARAM_NAMES}
+        dG = B.cgsr_gaussian_grads(*[grads[k].data_ptr() for k in PARAM_NAMES])
+    dposes = torch.zeros((V, 6), dtype=torch.float32, device=dev) if pose_grads else None
+    B.cgsr_backward(state.handle, structs, dG, _ptr(dposes), _stream())
+    return grads, dposes
+
+
+def tracking_loss_grad(color, depth, target_color, target_depth, lam=TRACK_LAMBDA, dcolor=None, ddepth=None,
+                       loss=None):
+    """Gradient images of Eq. 19 (lambda1 * L_color + lambda2 * L_geo) on the device."""
+    H, W = depth.shape
+    dcolor = torch.empty_like(color) if dcolor is None else dcolor
+    ddepth = torch.empty_like(depth) if ddepth is None else ddepth
+    B.cgsr_tracking_loss_grad(W, H, color.data_ptr(), depth.data_ptr(), target_color.data_ptr(),
+                              target_depth.data_ptr(), float(lam[0]), float(lam[1]), dcolor.data_ptr(),
+                              ddepth.data_ptr(), _ptr(loss), _stream())
+    return dcolor, ddepth
+
+
+def pose_adam_step(poses, dposes, adam, lr_rho=TRACK_LR_RHO, lr_phi=TRACK_LR_PHI, betas=(0.9, 0.999), eps=1e-8):
+    """In-place Adam step plus left retraction of every view's pose on the device."""
+    V = poses.reshape(-1, 12).shape[0]
+    B.cgsr_pose_adam_step(V, poses.data_ptr(), dposes.data_ptr(), adam.data_ptr(), float(lr_rho), float(lr_phi),
+                          float(betas[0]), float(betas[1]), float(eps), _stream())
+
+
+class RasterizeFunction(torch.autograd.Function):
+    """Differentiable single-view render.
+
+    Inputs: the five Gaussian parameter tensors, ``xi`` (a zero float32[6]
+    tangent probe at the pose: its gradient is dL/dxi of T <- exp(xi^) T; its
+    value is not read), the pose float32[12], the camera dict, the sensor
+    depth (or None) and a :class:`State`.  Outputs: colour, depth, opacity,
+    median depth and uncertainty (a zero-size tensor without sensor depth).
+    """
+
+    @staticmethod
+    def forward(ctx, means, log_scales, quats, opacity_logits, rgb, xi, pose, cam, depth_obs, state):
+        scene = dict(means=means.detach().contiguous(), log_scales=log_scales.detach().contiguous(),
+                     quats=quats.detach().contiguous(), opacity_logits=opacity_logits.detach().contiguous(),
+                     rgb=rgb.detach().contiguous())
+        pose = pose.detach().contiguous()
+        d = None if depth_obs is None else depth_obs.detach().contiguous()
+        out = render(state, scene, pose, [cam], None if d is None else [d])[0]
+        ctx.state = state
+        ctx.keep = (scene, pose, d)
+        ctx.generation = getattr(state, "generation", 0) + 1
+        state.generation = ctx.generation
+        unc = out.get("uncertainty")
+        if unc is None:
+            unc = torch.zeros(0, device=means.device)
+        return out["color"], out["depth"], out["opacity"], out["depth_median"], unc
+
+    @staticmethod
+    def backward(ctx, gc, gd, go, gm, gu):
+        state = ctx.state
+        if getattr(state, "generation", 0) != ctx.generation:
+            raise RuntimeError("the state was reused by another render before this backward; "
+                               "use a separate State per outstanding forward")
+        dimg = dict(color=gc, depth=gd, opacity=go, depth_median=gm,
+                    uncertainty=gu if (gu is not None and gu.numel()) else None)
+        need_params = any(ctx.needs_input_grad[:5])
+        grads, dposes = backward(state, [dimg], param_grads=need_params, pose_grads=ctx.needs_input_grad[5])
+        g = [None] * 5 if grads is None else [grads[k] for k in PARAM_NAMES]
+        return (*g, None if dposes is None else dposes[0], None, None, None, None)
+
+
+def rasterize(scene: dict, pose: torch.Tensor, cam: dict, depth_obs=None, xi=None, state: State | None = None):
+    """Autograd entry point; returns the dict of maps of one view."""
+    state = state or State()
+    if xi is None:
+        xi = torch.zeros(6, device=pose.device, dtype=torch.float32)
+    outs = RasterizeFunction.apply(scene["means"], scene["log_scales"], scene["quats"], scene["opacity_logits"],
+                                   scene["rgb"], xi, pose, cam, depth_obs, state)
+    res = dict(zip(MAP_NAMES, outs))
+    if depth_obs is None:
+        res["uncertainty"] = None
+    return res
+
+
+@dataclass
+class TrackingProblem:
+    scene: dict
+    cam: dict
+    target_color: torch.Tensor
+    target_depth: torch.Tensor
+    lam: tuple = TRACK_LAMBDA
+    lr_rho: float = TRACK_LR_RHO
+    lr_phi: float = TRACK_LR_PHI
+
+
+class TrackingSolver:
+    """Sequential tracking (Eq. 20) of one frame: ``iters`` iterations of
+    render -> tracking-loss gradient images -> pose-only backward -> Adam +
+    retraction, captured once into a HIP graph and replayed.  The host does no
+    work inside the loop."""
+
+    def __init__(self, prob: TrackingProblem, iters: int = 50, pair_margin: float = 1.5, use_graph: bool = True,
+                 reset_pose: torch.Tensor | None = None):
+        """reset_pose: if given, every solve (and every graph replay) starts
+        from this pose with fresh Adam moments; the reset is part of the graph."""
+        self.prob = prob
+        self.iters = int(iters)
+        cam = prob.cam
+        H, W = int(cam["height"]), int(cam["width"])
+        dev = prob.target_depth.device
+        self.pose = torch.zeros(12, dtype=torch.float32, device=dev)
+        self.dpose = torch.zeros((1, 6), dtype=torch.float32, device=dev)
+        self.adam = torch.zeros((1, 16), dtype=torch.float32, device=dev)
+        self.dcolor = torch.empty((3, H, W), dtype=torch.float32, device=dev)
+        self.ddepth = torch.empty((H, W), dtype=torch.float32, device=dev)
+        self.color = torch.empty((3, H, W), dtype=torch.float32, device=dev)
+        self.depth = torch.empty((H, W), dtype=torch.float32, device=dev)
+        self.state = State(sync_capacity=True)
+        self.g = gaussians_struct(prob.scene)
+        self.cam_s = camera_struct(cam)
+        self.out_s = B.cgsr_images(self.color.data_ptr(), self.depth.data_ptr(), None, None, None)
+        self.grad_s = B.cgsr_images(self.dcolor.data_ptr(), self.ddepth.data_ptr(), None, None, None)
+        self.pair_margin = pair_margin
+        self.graph = None
+        self.use_graph = use_graph
+        self.pose0 = None if reset_pose is None else reset_pose.reshape(12).clone()
+
+    def _reset_on_device(self):
+        # elementwise kernels only: a captured graph then holds no memcpy or
+        # memset nodes
+        torch.mul(self.pose0, 1.0, out=self.pose)
+        self.adam.zero_()
+        self.dpose.zero_()
+
+    def _iteration(self):
+        p = self.prob
+        s = _stream()
+        B.cgsr_render(self.state.handle, self.g, 1, self.pose.data_ptr(), [self.cam_s], None, [self.out_s], s)
+        H, W = self.depth.shape
+        B.cgsr_tracking_loss_grad(W, H, self.color.data_ptr(), self.depth.data_ptr(), p.target_color.data_ptr(),
+                                  p.target_depth.data_ptr(), float(p.lam[0]), float(p.lam[1]),
+                                  self.dcolor.data_ptr(), self.ddepth.data_ptr(), None, s)
+        B.cgsr_backward(self.state.handle, [self.grad_s], None, self.dpose.data_ptr(), s)
+        B.cgsr_pose_adam_step(1, self.pose.data_ptr(), self.dpose.data_ptr(), self.adam.data_ptr(),
+                              float(p.lr_rho), float(p.lr_phi), 0.9, 0.999, 1e-8, s)
+
+    def reset(self, pose0: torch.Tensor):
+        self.pose.copy_(pose0.reshape(12))
+        self.dpose.zero_()
+        self.adam.zero_()
+
+    def prepare(self, pose0: torch.Tensor):
+        """Size the pair buffer from an eager render at pose0 and capture the graph."""
+        self.reset(pose0)
+        self._iteration()                       # eager, grows the pair buffer
+        torch.cuda.synchronize()
+        st = self.state.stats()
+        self.state.reserve(pairs=int(st.pairs * self.pair_margin) + 4096)
+        self.reset(pose0)
+        if self.use_graph:
+            self.graph = torch.cuda.CUDAGraph()
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                with torch.cuda.graph(self.graph, stream=side):
+                    if self.pose0 is not None:
+                        self._reset_on_device()
+                    for _ in range(self.iters):
+                        self._iteration()
+            torch.cuda.current_stream().wait_stream(side)
+            torch.cuda.synchronize()
+
+    def run(self):
+        """One solve of ``iters`` iterations from the current pose."""
+        if self.graph is not None:
+            self.graph.replay()
+        else:
+            if self.pose0 is not None:
+                self._reset_on_device()
+            for _ in range(self.iters):
+                self._iteration()
+
+    def check(self):
+        self.state.check()

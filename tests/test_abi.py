@@ -1,0 +1,68 @@
+"""The C-ABI library loads, exports every declared symbol, and rejects bad
+arguments on the host (no GPU needed)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2403_16095_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "cgsr.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cgsr_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        pytest.fail("libcgsr.so is not built; run __graft_entry__.build()")
+    return B.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    decl = declared_symbols()
+    assert len(decl) >= 10
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True, text=True, check=True)
+    exported = {l.split()[-1] for l in out.stdout.splitlines() if " T " in l}
+    missing = [s for s in decl if s not in exported]
+    assert not missing, missing
+    assert set(decl) == set(B.EXPORTED)
+    for s in decl:
+        assert hasattr(lib, s)
+
+
+def test_version_and_defaults(lib):
+    assert "gfx950" in B.cgsr_version()
+    s = B.cgsr_default_settings()
+    assert s.sync_capacity == 1 and s.sort_blocks >= 1
+
+
+def test_host_side_argument_checks(lib):
+    # every one of these fails before any device work is enqueued
+    assert lib.cgsr_render(None, None, 1, None, None, None, None, None) == B.CGSR_ERR_INVALID_ARG
+    assert "NULL" in B.cgsr_last_error()
+    assert lib.cgsr_backward(None, None, None, None, None) == B.CGSR_ERR_INVALID_ARG
+    assert lib.cgsr_tracking_loss_grad(0, 10, None, None, None, None, 1.0, 1.0, None, None, None,
+                                       None) == B.CGSR_ERR_INVALID_ARG
+    assert lib.cgsr_pose_adam_step(0, None, None, None, 0.1, 0.1, 0.9, 0.999, 1e-8, None) == B.CGSR_ERR_INVALID_ARG
+    assert lib.cgsr_pose_adam_step(1, 8, 8, 8, 0.1, 0.1, 1.5, 0.999, 1e-8, None) == B.CGSR_ERR_INVALID_ARG
+    assert lib.cgsr_state_check(None, None) == B.CGSR_ERR_INVALID_ARG
+    assert lib.cgsr_get_stats(None, None, None) == B.CGSR_ERR_INVALID_ARG
+    assert lib.cgsr_state_reserve(None, 1, 1, 1, 1) == B.CGSR_ERR_INVALID_ARG
+    assert lib.cgsr_state_destroy(None) == B.CGSR_OK
+    bad = B.cgsr_settings(1, 0)
+    out = C.c_void_p()
+    assert lib.cgsr_state_create(C.byref(bad), C.byref(out)) == B.CGSR_ERR_INVALID_ARG
+    assert out.value is None
+
+
+def test_binding_raises_with_message(lib):
+    with pytest.raises(B.CgsrError) as e:
+        B.cgsr_tracking_loss_grad(0, 0, 0, 0, 0, 0, 1.0, 1.0, 0, 0, None, None)
+    assert e.value.status == B.CGSR_ERR_INVALID_ARG
