@@ -88,7 +88,6 @@ typedef struct {
                                 except while its stream is being captured into a
                                 graph.  0: never syncs; the pair buffer must be
                                 large enough, see cgsr_state_reserve().          */
-    int32_t sort_blocks;     /* upper bound of workgroups per radix-sort pass    */
     int32_t timing;          /* 1: time every stage with HIP events on the call's
                                 stream (not while it is being captured); read
                                 the durations with cgsr_get_timings()            */
@@ -107,14 +106,13 @@ typedef struct {
 
 /* Stages timed when cgsr_settings.timing is set. */
 typedef enum {
-    CGSR_STAGE_PROJECT = 0,     /* EWA projection and pair count        */
-    CGSR_STAGE_EMIT = 1,        /* (tile | depth, record) pair emission  */
-    CGSR_STAGE_SORT = 2,        /* radix sort of the pairs               */
-    CGSR_STAGE_RANGES = 3,      /* per-tile list ranges                  */
-    CGSR_STAGE_BLEND_FWD = 4,   /* front-to-back blend                   */
-    CGSR_STAGE_BLEND_BWD = 5,   /* back-to-front blend backward          */
-    CGSR_STAGE_PROJECT_BWD = 6, /* projection backward and pose reduce   */
-    CGSR_NUM_STAGES = 7
+    CGSR_STAGE_PROJECT = 0,     /* EWA projection and per-tile pair counts    */
+    CGSR_STAGE_EMIT = 1,        /* (depth, record) keys into tile segments    */
+    CGSR_STAGE_SORT = 2,        /* per-tile depth sort and tile ranges        */
+    CGSR_STAGE_BLEND_FWD = 3,   /* front-to-back blend                        */
+    CGSR_STAGE_BLEND_BWD = 4,   /* back-to-front blend backward               */
+    CGSR_STAGE_PROJECT_BWD = 5, /* projection backward and pose reduction     */
+    CGSR_NUM_STAGES = 6
 } cgsr_stage;
 
 typedef struct cgsr_state cgsr_state;
@@ -202,19 +200,20 @@ cgsr_status cgsr_state_check(cgsr_state *st, void *stream);
 cgsr_status cgsr_get_stats(cgsr_state *st, void *stream, cgsr_stats *out);
 
 /* Durations in milliseconds of the stages of the last timed render (stages
- * 0-4) and backward (stages 5-6) on this state; ms_out[CGSR_NUM_STAGES].
+ * 0-3) and backward (stages 4-5) on this state; ms_out[CGSR_NUM_STAGES].
  * Synchronises on the recorded events.  CGSR_ERR_STATE if timing is off or a
  * stage has not run since timing was enabled. */
 cgsr_status cgsr_get_timings(cgsr_state *st, float *ms_out);
 
 /* Debug views of the last render (device buffers owned by the state; valid
- * until the next render on it).  sorted_keys/values: [pairs] tile-and-depth
- * keys and record ids after the sort; ranges: [tiles][2] start/end;
- * records: [records][12] float32 projected record
- * (mu_x, mu_y, conic a, b, c, opacity, depth, r, g, b, 0, 0).
- * pixel_state: [pixels][4] (final T as float bits, entries walked,
- * median position or -1, 0). */
-cgsr_status cgsr_debug_buffers(cgsr_state *st, const uint64_t **sorted_keys, const uint32_t **sorted_values,
+ * until the next render on it).  keys: [pairs] emitted keys, depth bits << 32
+ * | record id, grouped by tile segment (unsorted within it); sorted_values:
+ * [pairs] record ids in (tile, depth, record id) order; ranges: [tiles][2]
+ * start/end into sorted_values; records: [records][12] float32 projected
+ * record (mu_x, mu_y, conic a, b, c, opacity, depth, r, g, b, 0, 0);
+ * pixel_state: [pixels][4] (final T as float bits, list entries up to the
+ * last blended one, median position or -1, alpha evaluations). */
+cgsr_status cgsr_debug_buffers(cgsr_state *st, const uint64_t **keys, const uint32_t **sorted_values,
                                const uint32_t **ranges, const float **records, const uint32_t **pixel_state);
 
 /* Message of the calling thread's last failure ("" if none). */

@@ -31,7 +31,7 @@ EXPORTED = (
     "cgsr_state_check", "cgsr_get_stats", "cgsr_get_timings", "cgsr_debug_buffers", "cgsr_last_error",
     "cgsr_version",
 )
-STAGES = ("project", "emit", "sort", "ranges", "blend_fwd", "blend_bwd", "project_bwd")
+STAGES = ("project", "emit", "sort", "blend_fwd", "blend_bwd", "project_bwd")
 
 
 class CgsrError(RuntimeError):
@@ -64,7 +64,7 @@ class cgsr_gaussian_grads(C.Structure):
 
 
 class cgsr_settings(C.Structure):
-    _fields_ = [("sync_capacity", C.c_int32), ("sort_blocks", C.c_int32), ("timing", C.c_int32)]
+    _fields_ = [("sync_capacity", C.c_int32), ("timing", C.c_int32)]
 
 
 class cgsr_stats(C.Structure):

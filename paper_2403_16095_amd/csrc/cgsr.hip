@@ -1,5 +1,9 @@
 // Host runtime behind the C ABI of include/cgsr.h: workspace ownership,
 // argument checks, and the launch sequence of a render and its backward.
+//
+// Render: project (counts pairs per tile) -> emit (keys into tile segments)
+// -> segment sort (depth order per tile, tile ranges) -> blend.
+// Backward: blend backward -> projection backward (parameters, pose).
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
@@ -24,9 +28,9 @@ cgsr_status fail(cgsr_status st, const char* fmt, ...) {
   return st;
 }
 
-#define HIP_TRY(expr)                                                                     \
-  do {                                                                                    \
-    hipError_t e_ = (expr);                                                               \
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
     if (e_ != hipSuccess) return fail(CGSR_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
@@ -56,32 +60,32 @@ struct cgsr_state {
   int device = 0;
   cgsr_settings settings{};
   // capacities
-  int64_t cap_records = 0, cap_pixels = 0, cap_tiles = 0, cap_pairs = 0, cap_blocks = 0;
-  // device workspace
+  int64_t cap_records = 0, cap_pixels = 0, cap_tiles = 0, cap_pairs = 0;
+  // per (view, Gaussian) record
   float4* rec = nullptr;
   uint32_t* tiles = nullptr;
   uint2* rect = nullptr;
   float* rec_grad = nullptr;
-  uint32_t* block_sum = nullptr;
-  uint32_t* group_sum = nullptr;
-  uint32_t* counters = nullptr;
+  // per tile
+  uint32_t* tile_count = nullptr;
+  uint32_t* tile_fill = nullptr;
+  uint32_t* tile_offset = nullptr;
   uint2* ranges = nullptr;
+  bool tiles_dirty = false;   // a render stopped between projection and sort
+  // per pair
   uint64_t* keys[2] = {nullptr, nullptr};
-  uint32_t* vals[2] = {nullptr, nullptr};
-  uint32_t* hist = nullptr;
+  uint32_t* sorted_vals = nullptr;
+  // per pixel
   uint4* pixel_state = nullptr;
+  uint32_t* pixel_count = nullptr;
+  // small buffers
+  uint32_t* counters = nullptr;
   double* pose_acc = nullptr;
   unsigned long long* stats_dev = nullptr;
-  uint32_t* pixel_count = nullptr;
   uint32_t* counters_pinned = nullptr;
-  // stage timing: events[k] marks the start of stage k, events[k + 1] its end
-  // for the forward stages; the backward uses its own pair per stage.
-  hipEvent_t ev_fwd[CGSR_STAGE_BLEND_FWD + 2] = {};
-  hipEvent_t ev_bwd[3] = {};
-  bool fwd_timed = false, bwd_timed = false;
-  // Per-view pointer tables of the forward (slot 0) and the backward (slot 1),
-  // each re-uploaded only when its pointers change, so a steady loop of
-  // render + backward uploads nothing.
+  // Per-view tables of the forward (slot 0) and the backward (slot 1), each
+  // re-uploaded only when its contents change, so a steady loop of render +
+  // backward uploads nothing.
   struct IoTable {
     ViewIO* dev = nullptr;
     ViewIO* pinned = nullptr;
@@ -90,12 +94,15 @@ struct cgsr_state {
     ViewIO cached[CGSR_MAX_VIEWS];
     int cached_n = -1;
   } io[2];
+  // stage timing: ev_fwd[k] starts forward stage k, ev_fwd[k + 1] ends it
+  hipEvent_t ev_fwd[CGSR_STAGE_BLEND_FWD + 2] = {};
+  hipEvent_t ev_bwd[3] = {};
+  bool fwd_timed = false, bwd_timed = false;
   // last render
   bool have_forward = false;
   int32_t n_views = 0;
   GaussianPtrs g{};
   const float* poses = nullptr;
-  int sorted_buffer = 0;
   int64_t total_pixels = 0;
   int32_t total_tiles = 0;
   int64_t records = 0;
@@ -114,40 +121,32 @@ cgsr_status set_device(cgsr_state* st) {
   return CGSR_OK;
 }
 
-int64_t scan_blocks_for(int64_t records_per_view, int n_views) {
-  return std::max<int64_t>(1, (records_per_view + kProjThreads - 1) / kProjThreads) * n_views;
-}
-
 cgsr_status grow_pairs(cgsr_state* st, int64_t pairs) {
   if (pairs <= st->cap_pairs) return CGSR_OK;
   HIP_TRY(hipDeviceSynchronize());
-  for (int k = 0; k < 2; ++k) {
-    dev_free(st->keys[k]);
-    dev_free(st->vals[k]);
-  }
+  dev_free(st->keys[0]);
+  dev_free(st->keys[1]);
+  dev_free(st->sorted_vals);
   st->cap_pairs = 0;
   const int64_t cap = std::max<int64_t>(pairs, 1);
-  for (int k = 0; k < 2; ++k) {
-    cgsr_status s = dev_alloc(&st->keys[k], cap);
-    if (s) return s;
-    s = dev_alloc(&st->vals[k], cap);
-    if (s) return s;
-  }
+  cgsr_status s;
+  if ((s = dev_alloc(&st->keys[0], cap))) return s;
+  if ((s = dev_alloc(&st->keys[1], cap))) return s;
+  if ((s = dev_alloc(&st->sorted_vals, cap))) return s;
   st->cap_pairs = cap;
   return CGSR_OK;
 }
 
-cgsr_status reserve(cgsr_state* st, int64_t records, int64_t pixels, int64_t tiles, int64_t pairs,
-                    int64_t blocks) {
-  if (records > st->cap_records || pixels > st->cap_pixels || tiles > st->cap_tiles || blocks > st->cap_blocks)
+cgsr_status reserve(cgsr_state* st, int64_t records, int64_t pixels, int64_t tiles, int64_t pairs) {
+  if (records > st->cap_records || pixels > st->cap_pixels || tiles > st->cap_tiles)
     HIP_TRY(hipDeviceSynchronize());
+  cgsr_status s;
   if (records > st->cap_records) {
     dev_free(st->rec);
     dev_free(st->tiles);
     dev_free(st->rect);
     dev_free(st->rec_grad);
     st->cap_records = 0;
-    cgsr_status s;
     if ((s = dev_alloc(&st->rec, kRecF4 * records))) return s;
     if ((s = dev_alloc(&st->tiles, records))) return s;
     if ((s = dev_alloc(&st->rect, records))) return s;
@@ -159,30 +158,25 @@ cgsr_status reserve(cgsr_state* st, int64_t records, int64_t pixels, int64_t til
     dev_free(st->pixel_state);
     dev_free(st->pixel_count);
     st->cap_pixels = 0;
-    cgsr_status s = dev_alloc(&st->pixel_state, pixels);
-    if (s) return s;
-    s = dev_alloc(&st->pixel_count, pixels);
-    if (s) return s;
+    if ((s = dev_alloc(&st->pixel_state, pixels))) return s;
+    if ((s = dev_alloc(&st->pixel_count, pixels))) return s;
     st->cap_pixels = pixels;
   }
   if (tiles > st->cap_tiles) {
     dev_free(st->ranges);
+    dev_free(st->tile_count);
+    dev_free(st->tile_fill);
+    dev_free(st->tile_offset);
     st->cap_tiles = 0;
-    cgsr_status s = dev_alloc(&st->ranges, tiles);
-    if (s) return s;
+    if ((s = dev_alloc(&st->ranges, tiles))) return s;
+    if ((s = dev_alloc(&st->tile_count, tiles))) return s;
+    if ((s = dev_alloc(&st->tile_fill, tiles))) return s;
+    if ((s = dev_alloc(&st->tile_offset, tiles + 1))) return s;
     HIP_TRY(hipMemset(st->ranges, 0, sizeof(uint2) * (size_t)tiles));
+    HIP_TRY(hipMemset(st->tile_count, 0, sizeof(uint32_t) * (size_t)tiles));
+    HIP_TRY(hipMemset(st->tile_fill, 0, sizeof(uint32_t) * (size_t)tiles));
+    st->tiles_dirty = false;
     st->cap_tiles = tiles;
-  }
-  if (blocks > st->cap_blocks) {
-    if ((blocks + kScanGroup - 1) / kScanGroup > kMaxGroups)
-      return fail(CGSR_ERR_INVALID_ARG, "too many records (%lld projection workgroups)", (long long)blocks);
-    dev_free(st->block_sum);
-    dev_free(st->group_sum);
-    st->cap_blocks = 0;
-    cgsr_status s;
-    if ((s = dev_alloc(&st->block_sum, blocks))) return s;
-    if ((s = dev_alloc(&st->group_sum, (blocks + kScanGroup - 1) / kScanGroup))) return s;
-    st->cap_blocks = blocks;
   }
   return grow_pairs(st, pairs);
 }
@@ -192,9 +186,9 @@ bool bad_camera(const cgsr_camera& c) {
          !(c.fy > 0.f) || !(c.cx == c.cx) || !(c.cy == c.cy);
 }
 
-// Uploads a per-view pointer table if it differs from its last upload.  Under
-// graph capture the tables must already be current: an upload there would be
-// a captured host-to-device copy of staging memory the next call overwrites.
+// Uploads a per-view table if it differs from its last upload.  Under graph
+// capture the tables must already be current: an upload there would be a
+// captured host-to-device copy of staging memory the next call overwrites.
 cgsr_status upload_io(cgsr_state* st, int slot, const ViewIO* io, int n, hipStream_t stream) {
   auto& t = st->io[slot];
   if (n == t.cached_n && std::memcmp(io, t.cached, sizeof(ViewIO) * n) == 0) return CGSR_OK;
@@ -202,7 +196,7 @@ cgsr_status upload_io(cgsr_state* st, int slot, const ViewIO* io, int n, hipStre
   HIP_TRY(hipStreamIsCapturing(stream, &cap));
   if (cap != hipStreamCaptureStatusNone)
     return fail(CGSR_ERR_STATE,
-                "image or gradient pointers changed during graph capture; run the same call once "
+                "cameras or image pointers changed during graph capture; run the same call once "
                 "before capturing it");
   if (t.event_pending) {
     HIP_TRY(hipEventSynchronize(t.event));
@@ -222,21 +216,27 @@ ProjectBufs project_bufs(cgsr_state* st) {
   b.rec = st->rec;
   b.tiles = st->tiles;
   b.rect = st->rect;
-  b.block_sum = st->block_sum;
-  b.group_sum = st->group_sum;
+  b.tile_count = st->tile_count;
+  b.tile_fill = st->tile_fill;
+  b.tile_offset = st->tile_offset;
   b.counters = st->counters;
-  b.ranges = st->ranges;
   b.total_tiles = st->total_tiles;
   b.keys = st->keys[0];
-  b.vals = st->vals[0];
   b.pair_cap = st->cap_pairs;
   return b;
 }
 
-int key_bits_for(int32_t total_tiles) {
-  int tb = 0;
-  while ((1ll << tb) < total_tiles) ++tb;
-  return 32 + tb;
+RasterBufs raster_bufs(cgsr_state* st, int slot) {
+  RasterBufs rb;
+  rb.rec = st->rec;
+  rb.vals = st->sorted_vals;
+  rb.ranges = st->ranges;
+  rb.pixel_state = st->pixel_state;
+  rb.pixel_count = st->pixel_count;
+  rb.rec_grad = st->rec_grad;
+  rb.views = ViewTable{st->io[slot].dev, st->n_views, (int32_t)st->g.n};
+  rb.total_tiles = st->total_tiles;
+  return rb;
 }
 
 }  // namespace
@@ -246,7 +246,6 @@ extern "C" {
 void cgsr_default_settings(cgsr_settings* s) {
   if (!s) return;
   s->sync_capacity = 1;
-  s->sort_blocks = 256;
   s->timing = 0;
 }
 
@@ -257,9 +256,10 @@ cgsr_status cgsr_state_create(const cgsr_settings* s, cgsr_state** out) {
   if (!st) return fail(CGSR_ERR_OOM, "cgsr_state_create: host allocation failed");
   if (s) st->settings = *s;
   else cgsr_default_settings(&st->settings);
-  if (st->settings.sort_blocks < 1 || st->settings.sort_blocks > 4096) {
+  if (st->settings.sync_capacity < 0 || st->settings.sync_capacity > 1 || st->settings.timing < 0 ||
+      st->settings.timing > 1) {
     delete st;
-    return fail(CGSR_ERR_INVALID_ARG, "sort_blocks must be in [1, 4096]");
+    return fail(CGSR_ERR_INVALID_ARG, "settings: sync_capacity and timing must be 0 or 1");
   }
   cgsr_status r = CGSR_OK;
   hipError_t e = hipGetDevice(&st->device);
@@ -267,7 +267,6 @@ cgsr_status cgsr_state_create(const cgsr_settings* s, cgsr_state** out) {
   if (!r) r = dev_alloc(&st->counters, kCounterWords);
   if (!r && hipMemset(st->counters, 0, sizeof(uint32_t) * kCounterWords) != hipSuccess)
     r = fail(CGSR_ERR_HIP, "hipMemset of counters failed");
-  if (!r) r = dev_alloc(&st->hist, (int64_t)st->settings.sort_blocks * 256);
   if (!r) r = dev_alloc(&st->pose_acc, 6 * CGSR_MAX_VIEWS);
   if (!r && hipMemset(st->pose_acc, 0, sizeof(double) * 6 * CGSR_MAX_VIEWS) != hipSuccess)
     r = fail(CGSR_ERR_HIP, "hipMemset of pose accumulators failed");
@@ -280,10 +279,10 @@ cgsr_status cgsr_state_create(const cgsr_settings* s, cgsr_state** out) {
       r = fail(CGSR_ERR_HIP, "hipEventCreate failed");
   }
   if (!r) r = dev_alloc(&st->stats_dev, 3);
-  for (auto& e : st->ev_fwd)
-    if (!r && hipEventCreate(&e) != hipSuccess) r = fail(CGSR_ERR_HIP, "hipEventCreate failed");
-  for (auto& e : st->ev_bwd)
-    if (!r && hipEventCreate(&e) != hipSuccess) r = fail(CGSR_ERR_HIP, "hipEventCreate failed");
+  for (auto& ev : st->ev_fwd)
+    if (!r && hipEventCreate(&ev) != hipSuccess) r = fail(CGSR_ERR_HIP, "hipEventCreate failed");
+  for (auto& ev : st->ev_bwd)
+    if (!r && hipEventCreate(&ev) != hipSuccess) r = fail(CGSR_ERR_HIP, "hipEventCreate failed");
   if (!r && hipHostMalloc((void**)&st->counters_pinned, sizeof(uint32_t) * 4, hipHostMallocDefault) != hipSuccess)
     r = fail(CGSR_ERR_OOM, "pinned allocation failed");
   if (r) {
@@ -303,28 +302,27 @@ cgsr_status cgsr_state_destroy(cgsr_state* st) {
   dev_free(st->tiles);
   dev_free(st->rect);
   dev_free(st->rec_grad);
-  dev_free(st->block_sum);
-  dev_free(st->group_sum);
-  dev_free(st->counters);
+  dev_free(st->tile_count);
+  dev_free(st->tile_fill);
+  dev_free(st->tile_offset);
   dev_free(st->ranges);
-  for (int k = 0; k < 2; ++k) {
-    dev_free(st->keys[k]);
-    dev_free(st->vals[k]);
-  }
-  dev_free(st->hist);
+  dev_free(st->keys[0]);
+  dev_free(st->keys[1]);
+  dev_free(st->sorted_vals);
   dev_free(st->pixel_state);
+  dev_free(st->pixel_count);
+  dev_free(st->counters);
   dev_free(st->pose_acc);
+  dev_free(st->stats_dev);
   for (int k = 0; k < 2; ++k) {
     dev_free(st->io[k].dev);
     if (st->io[k].pinned) (void)hipHostFree(st->io[k].pinned);
     if (st->io[k].event) (void)hipEventDestroy(st->io[k].event);
   }
-  dev_free(st->stats_dev);
-  dev_free(st->pixel_count);
-  for (auto& e : st->ev_fwd)
-    if (e) (void)hipEventDestroy(e);
-  for (auto& e : st->ev_bwd)
-    if (e) (void)hipEventDestroy(e);
+  for (auto& ev : st->ev_fwd)
+    if (ev) (void)hipEventDestroy(ev);
+  for (auto& ev : st->ev_bwd)
+    if (ev) (void)hipEventDestroy(ev);
   if (st->counters_pinned) (void)hipHostFree(st->counters_pinned);
   if (cur >= 0 && cur != st->device) (void)hipSetDevice(cur);
   delete st;
@@ -335,13 +333,11 @@ cgsr_status cgsr_state_reserve(cgsr_state* st, int64_t max_records, int64_t max_
                                int64_t max_pairs) {
   if (!st) return fail(CGSR_ERR_INVALID_ARG, "state is NULL");
   if (max_records < 0 || max_pixels < 0 || max_tiles < 0 || max_pairs < 0 || max_records >= (1ll << 32) ||
-      max_pairs >= (1ll << 32))
+      max_pairs >= (1ll << 32) || max_tiles >= INT32_MAX || max_pixels >= INT32_MAX)
     return fail(CGSR_ERR_INVALID_ARG, "reserve: sizes out of range");
   cgsr_status s = set_device(st);
   if (s) return s;
-  // Scan workgroups are bounded by records/256 plus one per view.
-  const int64_t blocks = (max_records + kProjThreads - 1) / kProjThreads + CGSR_MAX_VIEWS;
-  return reserve(st, max_records, max_pixels, max_tiles, max_pairs, blocks);
+  return reserve(st, max_records, max_pixels, max_tiles, max_pairs);
 }
 
 cgsr_status cgsr_render(cgsr_state* st, const cgsr_gaussians* g, int32_t n_views, const float* poses,
@@ -352,12 +348,16 @@ cgsr_status cgsr_render(cgsr_state* st, const cgsr_gaussians* g, int32_t n_views
   if (n_views < 1 || n_views > CGSR_MAX_VIEWS)
     return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: n_views must be in [1, %d]", CGSR_MAX_VIEWS);
   if (g->n < 0) return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: negative Gaussian count");
+  if (g->n > INT32_MAX) return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: more than 2^31 Gaussians");
   if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->rgb))
     return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: NULL Gaussian parameter pointer");
   if ((int64_t)g->n * n_views >= (1ll << 32))
     return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: more than 2^32 (view, Gaussian) records");
   if (g->n > 0 && ((uintptr_t)g->quats & 15))
     return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: quats must be 16-byte aligned");
+  const int64_t blocks = std::max<int64_t>(1, (g->n + kProjThreads - 1) / kProjThreads) * n_views;
+  if ((blocks + kScanGroup - 1) / kScanGroup > kMaxGroups)
+    return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: too many (view, Gaussian) records");
   int64_t tiles = 0, pixels = 0;
   ViewIO io[CGSR_MAX_VIEWS];
   for (int v = 0; v < n_views; ++v) {
@@ -388,12 +388,15 @@ cgsr_status cgsr_render(cgsr_state* st, const cgsr_gaussians* g, int32_t n_views
     if (io[v].uncertainty && !io[v].depth_obs)
       return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: view %d asks for uncertainty without sensor depth", v);
   }
-  if (g->n > INT32_MAX) return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: more than 2^31 Gaussians");
   cgsr_status s = set_device(st);
   if (s) return s;
   const int64_t records = g->n * (int64_t)n_views;
-  const int64_t blocks = scan_blocks_for(g->n, n_views);
-  s = reserve(st, records, pixels, tiles, 0, blocks);
+  hipStreamCaptureStatus capturing = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(stream, &capturing));
+  const bool in_capture = capturing != hipStreamCaptureStatusNone;
+  if (in_capture && (records > st->cap_records || pixels > st->cap_pixels || tiles > st->cap_tiles))
+    return fail(CGSR_ERR_STATE, "cgsr_render: workspace too small for graph capture; reserve it first");
+  s = reserve(st, records, pixels, tiles, 0);
   if (s) return s;
   st->have_forward = false;
   st->n_views = n_views;
@@ -405,21 +408,25 @@ cgsr_status cgsr_render(cgsr_state* st, const cgsr_gaussians* g, int32_t n_views
   std::memcpy(st->io_fwd, io, sizeof(ViewIO) * n_views);
   s = upload_io(st, 0, io, n_views, stream);
   if (s) return s;
+  if (st->tiles_dirty) {
+    // A previous render stopped before its sort reset the per-tile counters.
+    launch_clear_u32(st->tile_count, st->cap_tiles, stream);
+    launch_clear_u32(st->tile_fill, st->cap_tiles, stream);
+  }
 
   const ViewTable vt{st->io[0].dev, n_views, (int32_t)g->n};
-  hipStreamCaptureStatus capturing = hipStreamCaptureStatusNone;
-  HIP_TRY(hipStreamIsCapturing(stream, &capturing));
-  const bool timed = st->settings.timing && capturing == hipStreamCaptureStatusNone;
+  const bool timed = st->settings.timing && !in_capture;
   auto mark = [&](int k) -> cgsr_status {
     if (timed) HIP_TRY(hipEventRecord(st->ev_fwd[k], stream));
     return CGSR_OK;
   };
   st->fwd_timed = false;
-  if ((s = mark(0))) return s;
+  if ((s = mark(CGSR_STAGE_PROJECT))) return s;
+  st->tiles_dirty = true;
   ProjectBufs pb = project_bufs(st);
   launch_project(st->g, poses, vt, pb, stream);
   HIP_TRY(hipGetLastError());
-  if (st->settings.sync_capacity && capturing == hipStreamCaptureStatusNone) {
+  if (st->settings.sync_capacity && !in_capture) {
     HIP_TRY(hipMemcpyAsync(st->counters_pinned, st->counters, sizeof(uint32_t) * 2, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
     const int64_t need = st->counters_pinned[kCntPairs];
@@ -427,38 +434,29 @@ cgsr_status cgsr_render(cgsr_state* st, const cgsr_gaussians* g, int32_t n_views
       s = grow_pairs(st, std::max<int64_t>(need + need / 4, 1 << 16));
       if (s) return s;
       // The projection flagged an overflow against the old capacity; clear it.
-      HIP_TRY(hipMemsetAsync(st->counters + kCntOverflow, 0, sizeof(uint32_t), stream));
+      launch_clear_u32(st->counters + kCntOverflow, 1, stream);
       pb = project_bufs(st);
     }
   }
-  if ((s = mark(1))) return s;
+  if ((s = mark(CGSR_STAGE_EMIT))) return s;
   launch_emit(vt, pb, stream);
-  if ((s = mark(2))) return s;
-  SortBufs sb;
+  if ((s = mark(CGSR_STAGE_SORT))) return s;
+  SegSortBufs sb;
   sb.keys[0] = st->keys[0];
   sb.keys[1] = st->keys[1];
-  sb.vals[0] = st->vals[0];
-  sb.vals[1] = st->vals[1];
-  sb.hist = st->hist;
-  sb.counters = st->counters;
+  sb.sorted_vals = st->sorted_vals;
+  sb.tile_offset = st->tile_offset;
+  sb.tile_count = st->tile_count;
+  sb.tile_fill = st->tile_fill;
+  sb.ranges = st->ranges;
   sb.cap = st->cap_pairs;
-  sb.max_blocks = st->settings.sort_blocks;
-  launch_sort(sb, key_bits_for(st->total_tiles), stream, &st->sorted_buffer);
-  if ((s = mark(3))) return s;
-  launch_ranges(st->keys[st->sorted_buffer], st->counters, st->cap_pairs, st->ranges, stream);
-  if ((s = mark(4))) return s;
-  RasterBufs rb;
-  rb.rec = st->rec;
-  rb.vals = st->vals[st->sorted_buffer];
-  rb.ranges = st->ranges;
-  rb.pixel_state = st->pixel_state;
-  rb.rec_grad = st->rec_grad;
-  rb.pixel_count = st->pixel_count;
-  rb.views = vt;
-  rb.total_tiles = st->total_tiles;
-  launch_raster_forward(rb, stream);
+  launch_segment_sort(sb, st->total_tiles, stream);
   HIP_TRY(hipGetLastError());
-  if ((s = mark(5))) return s;
+  st->tiles_dirty = false;
+  if ((s = mark(CGSR_STAGE_BLEND_FWD))) return s;
+  launch_raster_forward(raster_bufs(st, 0), stream);
+  HIP_TRY(hipGetLastError());
+  if ((s = mark(CGSR_STAGE_BLEND_FWD + 1))) return s;
   st->fwd_timed = timed;
   st->have_forward = true;
   return CGSR_OK;
@@ -487,26 +485,17 @@ cgsr_status cgsr_backward(cgsr_state* st, const cgsr_image_grads* dimgs, const c
   if (s) return s;
   s = upload_io(st, 1, io, n_views, stream);
   if (s) return s;
-  RasterBufs rb;
-  rb.rec = st->rec;
-  rb.vals = st->vals[st->sorted_buffer];
-  rb.ranges = st->ranges;
-  rb.pixel_state = st->pixel_state;
-  rb.rec_grad = st->rec_grad;
-  const ViewTable vt{st->io[1].dev, n_views, (int32_t)st->g.n};
-  rb.pixel_count = st->pixel_count;
-  rb.views = vt;
-  rb.total_tiles = st->total_tiles;
   hipStreamCaptureStatus capturing = hipStreamCaptureStatusNone;
   HIP_TRY(hipStreamIsCapturing(stream, &capturing));
   const bool timed = st->settings.timing && capturing == hipStreamCaptureStatusNone;
   st->bwd_timed = false;
   if (timed) HIP_TRY(hipEventRecord(st->ev_bwd[0], stream));
+  const RasterBufs rb = raster_bufs(st, 1);
   launch_raster_backward(rb, params, stream);
   if (timed) HIP_TRY(hipEventRecord(st->ev_bwd[1], stream));
   GradPtrs gp{};
   if (params) gp = GradPtrs{dG->means, dG->log_scales, dG->quats, dG->opacity_logits, dG->rgb};
-  launch_project_backward(st->g, st->poses, vt, st->rec_grad, st->tiles, gp, params, st->pose_acc, dposes,
+  launch_project_backward(st->g, st->poses, rb.views, st->rec_grad, st->tiles, gp, params, st->pose_acc, dposes,
                           st->counters, stream);
   HIP_TRY(hipGetLastError());
   if (timed) HIP_TRY(hipEventRecord(st->ev_bwd[2], stream));
@@ -559,9 +548,9 @@ cgsr_status cgsr_get_stats(cgsr_state* st, void* stream_, cgsr_stats* out) {
   out->pair_capacity = st->cap_pairs;
   out->n_views = st->n_views;
   if (!st->have_forward) return CGSR_OK;
-  HIP_TRY(hipMemsetAsync(st->stats_dev, 0, sizeof(unsigned long long) * 3, stream));
-  launch_stats(st->tiles, st->records, st->pixel_state, st->pixel_count, st->total_pixels, st->stats_dev, stream);
   unsigned long long host[3];
+  launch_clear_u32(reinterpret_cast<uint32_t*>(st->stats_dev), 6, stream);
+  launch_stats(st->tiles, st->records, st->pixel_state, st->pixel_count, st->total_pixels, st->stats_dev, stream);
   HIP_TRY(hipMemcpyAsync(st->counters_pinned, st->counters, sizeof(uint32_t) * 2, hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipMemcpyAsync(host, st->stats_dev, sizeof(host), hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
@@ -582,18 +571,19 @@ cgsr_status cgsr_get_timings(cgsr_state* st, float* ms_out) {
   if (s) return s;
   HIP_TRY(hipEventSynchronize(st->ev_fwd[CGSR_STAGE_BLEND_FWD + 1]));
   HIP_TRY(hipEventSynchronize(st->ev_bwd[2]));
-  for (int k = 0; k <= CGSR_STAGE_BLEND_FWD; ++k) HIP_TRY(hipEventElapsedTime(&ms_out[k], st->ev_fwd[k], st->ev_fwd[k + 1]));
+  for (int k = 0; k <= CGSR_STAGE_BLEND_FWD; ++k)
+    HIP_TRY(hipEventElapsedTime(&ms_out[k], st->ev_fwd[k], st->ev_fwd[k + 1]));
   HIP_TRY(hipEventElapsedTime(&ms_out[CGSR_STAGE_BLEND_BWD], st->ev_bwd[0], st->ev_bwd[1]));
   HIP_TRY(hipEventElapsedTime(&ms_out[CGSR_STAGE_PROJECT_BWD], st->ev_bwd[1], st->ev_bwd[2]));
   return CGSR_OK;
 }
 
-cgsr_status cgsr_debug_buffers(cgsr_state* st, const uint64_t** sorted_keys, const uint32_t** sorted_values,
+cgsr_status cgsr_debug_buffers(cgsr_state* st, const uint64_t** keys, const uint32_t** sorted_values,
                                const uint32_t** ranges, const float** records, const uint32_t** pixel_state) {
   if (!st) return fail(CGSR_ERR_INVALID_ARG, "state is NULL");
   if (!st->have_forward) return fail(CGSR_ERR_STATE, "no forward pass on this state");
-  if (sorted_keys) *sorted_keys = st->keys[st->sorted_buffer];
-  if (sorted_values) *sorted_values = st->vals[st->sorted_buffer];
+  if (keys) *keys = st->keys[0];
+  if (sorted_values) *sorted_values = st->sorted_vals;
   if (ranges) *ranges = reinterpret_cast<const uint32_t*>(st->ranges);
   if (records) *records = reinterpret_cast<const float*>(st->rec);
   if (pixel_state) *pixel_state = reinterpret_cast<const uint32_t*>(st->pixel_state);
@@ -602,6 +592,6 @@ cgsr_status cgsr_debug_buffers(cgsr_state* st, const uint64_t** sorted_keys, con
 
 const char* cgsr_last_error(void) { return g_last_error.c_str(); }
 
-const char* cgsr_version(void) { return "cgsr 0.1 (gfx950)"; }
+const char* cgsr_version(void) { return "cgsr 0.2 (gfx950)"; }
 
 }  // extern "C"

@@ -12,7 +12,7 @@ namespace cgsr {
 enum Counter : int {
   kCntPairs = 0,        // (tile, Gaussian) pairs of the last render
   kCntOverflow = 1,     // 1 if pairs exceeded the capacity
-  kCntTicketAll = 2,    // last-group detector of the projection scan
+  kCntTicketAll = 2,    // last-group detector of the projection's tile scan
   kCntTicketBwd = 3,    // last-block detector of the projection backward
   kCntGroupTickets = 8  // per-group tickets start here (kMaxGroups of them)
 };
@@ -23,13 +23,12 @@ struct ProjectBufs {
   float4* rec;              // [M][3]
   uint32_t* tiles;          // [M] tiles touched (0 = culled)
   uint2* rect;              // [M] tile rect: x = tx0 | tx1 << 16, y = ty0 | ty1 << 16
-  uint32_t* block_sum;      // [nblocks] then in-group exclusive offsets
-  uint32_t* group_sum;      // [ngroups] then exclusive offsets
+  uint32_t* tile_count;     // [T] pairs per tile (zero on entry; reset by the segment sort)
+  uint32_t* tile_fill;      // [T] emission slots taken (zero on entry; reset by the segment sort)
+  uint32_t* tile_offset;    // [T + 1] exclusive offsets of the tile segments
   uint32_t* counters;       // Counter enum above
-  uint2* ranges;            // [total tiles], cleared by the projection
   int32_t total_tiles;
-  uint64_t* keys;           // [cap] emitted pair keys
-  uint32_t* vals;           // [cap] emitted record ids
+  uint64_t* keys;           // [cap] emitted pair keys: depth bits << 32 | record id
   int64_t pair_cap;
 };
 
@@ -60,19 +59,20 @@ void launch_project_backward(const GaussianPtrs& g, const float* poses, const Vi
                              const uint32_t* tiles, const GradPtrs& dg, bool param_grads, double* pose_acc,
                              float* dposes, uint32_t* counters, hipStream_t s);
 
-// Radix sort of (key, value) pairs, count read from counters[kCntPairs]
-// (clamped to capacity).  Sorts bits [0, key_bits).  Returns through
-// *result_in_alt whether the sorted data ended in the alternate buffers.
-struct SortBufs {
-  uint64_t* keys[2];
-  uint32_t* vals[2];
-  uint32_t* hist;           // [max_blocks][256]
-  const uint32_t* counters;
+// Segmented sort: one workgroup per tile orders its segment of keys and
+// writes the record ids in depth order plus the tile's range.
+struct SegSortBufs {
+  uint64_t* keys[2];        // [cap] emitted keys, and scratch for long segments
+  uint32_t* sorted_vals;    // [cap] record ids in (tile, depth, id) order
+  const uint32_t* tile_offset;  // [T + 1]
+  uint32_t* tile_count;     // [T] reset to zero here
+  uint32_t* tile_fill;      // [T] reset to zero here
+  uint2* ranges;            // [T]
   int64_t cap;
-  int max_blocks;
 };
-void launch_sort(const SortBufs& b, int key_bits, hipStream_t s, int* result_buffer);
-void launch_ranges(const uint64_t* keys, const uint32_t* counters, int64_t cap, uint2* ranges, hipStream_t s);
+void launch_segment_sort(const SegSortBufs& b, int32_t total_tiles, hipStream_t s);
+// Fill n uint32 with zero (a kernel, so it can sit in a captured graph).
+void launch_clear_u32(uint32_t* p, int64_t n, hipStream_t s);
 
 struct RasterBufs {
   const float4* rec;

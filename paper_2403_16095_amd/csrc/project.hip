@@ -144,15 +144,11 @@ __global__ __launch_bounds__(kThreads) void project_kernel(GaussianPtrs g, const
   const uint32_t blk = v * gridDim.x + blockIdx.x;
   const uint32_t nblocks = gridDim.x * gridDim.y;
 
-  // Clear the tile ranges the sort's range pass fills in later.
-  for (int64_t t = (int64_t)blk * kThreads + threadIdx.x; t < b.total_tiles; t += (int64_t)nblocks * kThreads)
-    b.ranges[t] = make_uint2(0u, 0u);
-
-  uint32_t ntiles = 0;
   if (i < N) {
     const ViewInfo cam = vt.io[v].info;
     const float* P = poses + 12 * v;
     const int64_t m = (int64_t)v * N + i;
+    uint32_t ntiles = 0;
     Proj o;
     if (project_core(g, i, P, cam, o)) {
       const float mux = __builtin_fmaf(cam.fx, o.p[0] / o.p[2], cam.cx);
@@ -172,85 +168,73 @@ __global__ __launch_bounds__(kThreads) void project_kernel(GaussianPtrs g, const
         rec[1] = make_float4(o.conic[2], o.opacity, o.p[2], c[0]);
         rec[2] = make_float4(c[1], c[2], 0.f, 0.f);
         b.rect[m] = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
+        for (uint32_t ty = ty0; ty <= ty1; ++ty)
+          for (uint32_t tx = tx0; tx <= tx1; ++tx)
+            atomicAdd(&b.tile_count[cam.tile_base + ty * cam.tiles_x + tx], 1u);
       }
     }
     b.tiles[m] = ntiles;
   }
 
-  // Pairs per workgroup, then a two-level exclusive scan done by the last
-  // workgroup of each group of 256 and by the last group.
-  uint32_t total;
-  block_exclusive_scan(ntiles, &total, s_scan);
+  // The last workgroup (two-level ticket: groups of 256, then the groups)
+  // turns the per-tile counts into segment offsets.  Every lane fences its
+  // own count atomics before the barrier that precedes the ticket.
   const uint32_t grp = blk / kScanGroup;
   const uint32_t ngroups = (nblocks + kScanGroup - 1) / kScanGroup;
-  if (threadIdx.x == 0) {
-    b.block_sum[blk] = total;
-    __threadfence();
-    const uint32_t gsize = min((uint32_t)kScanGroup, nblocks - grp * kScanGroup);
-    const uint32_t t = atomicAdd(&b.counters[kCntGroupTickets + grp], 1u);
-    s_last = (t == gsize - 1);
-  }
-  __syncthreads();
-  if (!s_last) return;
   __threadfence();
-  {
-    const uint32_t first = grp * kScanGroup;
-    const uint32_t gsize = min((uint32_t)kScanGroup, nblocks - first);
-    const uint32_t x = threadIdx.x < gsize ? ld_acquire(&b.block_sum[first + threadIdx.x]) : 0u;
-    uint32_t gtot;
-    const uint32_t ex = block_exclusive_scan(x, &gtot, s_scan);
-    if (threadIdx.x < gsize) b.block_sum[first + threadIdx.x] = ex;
-    if (threadIdx.x == 0) {
-      b.group_sum[grp] = gtot;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t gsize = min((uint32_t)kScanGroup, nblocks - grp * kScanGroup);
+    bool last = atomicAdd(&b.counters[kCntGroupTickets + grp], 1u) == gsize - 1;
+    if (last) {
       b.counters[kCntGroupTickets + grp] = 0u;
       __threadfence();
-      const uint32_t t = atomicAdd(&b.counters[kCntTicketAll], 1u);
-      s_last = (t == ngroups - 1);
+      last = atomicAdd(&b.counters[kCntTicketAll], 1u) == ngroups - 1;
     }
+    s_last = last;
   }
   __syncthreads();
   if (!s_last) return;
   __threadfence();
-  uint32_t carry = 0;
-  for (uint32_t c0 = 0; c0 < ngroups; c0 += kThreads) {
-    const uint32_t k = c0 + threadIdx.x;
-    const uint32_t x = k < ngroups ? ld_acquire(&b.group_sum[k]) : 0u;
-    uint32_t tot;
-    const uint32_t ex = block_exclusive_scan(x, &tot, s_scan);
-    if (k < ngroups) b.group_sum[k] = carry + ex;
-    carry += tot;
+  // Exclusive scan of tile_count[0, T) into tile_offset[0, T], each lane
+  // taking a contiguous run of tiles.
+  const uint32_t T = (uint32_t)b.total_tiles;
+  const uint32_t per = (T + kThreads - 1) / kThreads;
+  const uint32_t t0 = min(T, threadIdx.x * per), t1 = min(T, t0 + per);
+  uint32_t run = 0;
+  for (uint32_t t = t0; t < t1; ++t) run += ld_acquire(&b.tile_count[t]);
+  uint32_t total;
+  uint32_t acc = block_exclusive_scan(run, &total, s_scan);
+  for (uint32_t t = t0; t < t1; ++t) {
+    b.tile_offset[t] = acc;
+    acc += ld_acquire(&b.tile_count[t]);
   }
   if (threadIdx.x == 0) {
-    b.counters[kCntPairs] = carry;
-    b.counters[kCntOverflow] = (int64_t)carry > b.pair_cap ? 1u : 0u;
+    b.tile_offset[T] = total;
+    b.counters[kCntPairs] = total;
+    b.counters[kCntOverflow] = (int64_t)total > b.pair_cap ? 1u : 0u;
     b.counters[kCntTicketAll] = 0u;
   }
 }
 
-// Writes every (tile, record) pair in record order, tiles row-major within a
-// record: key = global tile << 32 | float bits of the camera depth (positive,
-// so the bits order like the values), value = record id.
+// Drops every (tile, record) pair into its tile's segment at a slot taken
+// with an atomic: key = float bits of the camera depth (positive, so the bits
+// order like the values) << 32 | record id.
 __global__ __launch_bounds__(kThreads) void emit_kernel(ViewTable vt, ProjectBufs b, int64_t N) {
-  __shared__ uint32_t s_scan[4];
   const int v = blockIdx.y;
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  const uint32_t blk = v * gridDim.x + blockIdx.x;
+  if (i >= N) return;
   const int64_t m = (int64_t)v * N + i;
-  const uint32_t n = i < N ? b.tiles[m] : 0u;
-  uint32_t total;
-  const uint32_t ex = block_exclusive_scan(n, &total, s_scan);
-  if (n == 0) return;
-  int64_t pos = (int64_t)b.group_sum[blk / kScanGroup] + b.block_sum[blk] + ex;
+  if (b.tiles[m] == 0u) return;
   const uint2 r = b.rect[m];
   const uint32_t tx0 = r.x & 0xFFFF, tx1 = r.x >> 16, ty0 = r.y & 0xFFFF, ty1 = r.y >> 16;
-  const uint64_t dkey = float_key(b.rec[kRecF4 * m + 1].z);
+  const uint64_t key = ((uint64_t)float_key(b.rec[kRecF4 * m + 1].z) << 32) | (uint64_t)m;
   const int32_t tile_base = vt.io[v].info.tile_base, tiles_x = vt.io[v].info.tiles_x;
   for (uint32_t ty = ty0; ty <= ty1; ++ty)
-    for (uint32_t tx = tx0; tx <= tx1; ++tx, ++pos) {
-      if (pos >= b.pair_cap) return;
-      const uint64_t gt = (uint64_t)(tile_base + ty * tiles_x + tx);
-      b.keys[pos] = (gt << 32) | dkey;
-      b.vals[pos] = (uint32_t)m;
+    for (uint32_t tx = tx0; tx <= tx1; ++tx) {
+      const uint32_t t = tile_base + ty * tiles_x + tx;
+      const uint64_t pos = (uint64_t)b.tile_offset[t] + atomicAdd(&b.tile_fill[t], 1u);
+      if (pos < (uint64_t)b.pair_cap) b.keys[pos] = key;
     }
 }
 
@@ -411,10 +395,11 @@ __global__ __launch_bounds__(kThreads) void project_backward_kernel(GaussianPtrs
   if (threadIdx.x < 6) {
     const float t = s_pose[0][threadIdx.x] + s_pose[1][threadIdx.x] + s_pose[2][threadIdx.x] + s_pose[3][threadIdx.x];
     if (t != 0.f) atomicAdd(pose_acc + 6 * v + threadIdx.x, (double)t);
+    __threadfence();
   }
+  __syncthreads();
   // The last workgroup moves the accumulated pose gradients to the caller.
   if (threadIdx.x == 0) {
-    __threadfence();
     const uint32_t t = atomicAdd(&counters[kCntTicketBwd], 1u);
     s_last = (t == gridDim.x * gridDim.y - 1);
   }

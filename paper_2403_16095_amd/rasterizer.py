@@ -63,10 +63,9 @@ def pose_tensor(R, t, device="cuda") -> torch.Tensor:
 class State:
     """Owns one cgsr_state (the workspace of a render and its backward)."""
 
-    def __init__(self, sync_capacity: bool = True, sort_blocks: int = 256, timing: bool = False):
+    def __init__(self, sync_capacity: bool = True, timing: bool = False):
         s = B.cgsr_default_settings()
         s.sync_capacity = int(sync_capacity)
-        s.sort_blocks = int(sort_blocks)
         s.timing = int(timing)
         self.handle = B.cgsr_state_create(s)
         self.n_views = 0

@@ -40,7 +40,7 @@ def test_every_declared_symbol_is_exported(lib):
 def test_version_and_defaults(lib):
     assert "gfx950" in B.cgsr_version()
     s = B.cgsr_default_settings()
-    assert s.sync_capacity == 1 and s.sort_blocks >= 1
+    assert s.sync_capacity == 1 and s.timing == 0
 
 
 def test_host_side_argument_checks(lib):
@@ -56,7 +56,7 @@ def test_host_side_argument_checks(lib):
     assert lib.cgsr_get_stats(None, None, None) == B.CGSR_ERR_INVALID_ARG
     assert lib.cgsr_state_reserve(None, 1, 1, 1, 1) == B.CGSR_ERR_INVALID_ARG
     assert lib.cgsr_state_destroy(None) == B.CGSR_OK
-    bad = B.cgsr_settings(1, 0)
+    bad = B.cgsr_settings(2, 0)
     out = C.c_void_p()
     assert lib.cgsr_state_create(C.byref(bad), C.byref(out)) == B.CGSR_ERR_INVALID_ARG
     assert out.value is None

@@ -164,6 +164,33 @@ def test_tile_assignment_bit_exact_tracking_size(R):
     assert K > 10_000
 
 
+def test_long_tile_segments_take_the_merge_path(R):
+    """More than 4096 Gaussians in one tile: the segment sort goes through its
+    chunked LDS sort plus in-workgroup merges; lists and maps must still match."""
+    say("case: 10000 Gaussians crowding four tiles of a 64x48 image")
+    sc = synth.uniform_box_scene(7, 10_000, xy=(-0.06, 0.06), z=(2.0, 3.0), log_scale=(-5.5, 0.3),
+                                 opacity=(-3.0, 1.0))
+    cam = synth.SMALL_CAMERA
+    st = R.State()
+    gpu, _ = gpu_render(R, st, dev(sc), identity_pose(), cam)
+    tiles_x, tiles_y = (cam["width"] + 15) // 16, (cam["height"] + 15) // 16
+    gl, K = tile_lists_from_gpu(R, st, tiles_x * tiles_y)
+    longest = max(len(v) for v in gl.values())
+    say("pairs", K, "longest tile list", longest)
+    assert longest > 2 * 4096
+    proj = oracle.project(sc, cam, identity_pose())
+    d = proj["depth"]
+    for t, ids in gl.items():
+        key = d[ids]
+        assert np.all((np.diff(key) > 0) | ((np.diff(key) == 0) & (np.diff(ids) > 0)) |
+                      (np.abs(np.diff(key)) <= 1e-6 * key[1:])), t
+    check_tiles(R, sc, cam, identity_pose())
+    ref = oracle.render(sc, cam, identity_pose(), None)
+    mask = unambiguous(ref)
+    worst = compare_maps(gpu, ref, mask)
+    say("max abs err", worst, "excluded px", int((~mask).sum()))
+
+
 def test_backward_config1_all_params(R, config1):
     sc, cam, tc, td = config1
     say("case: config1 full backward")
