@@ -29,19 +29,21 @@ METRIC = "tracking iters/s (fwd+pose-bwd) 640x480 100k Gaussians; % of HBM roofl
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (256 CUs x 2.4 GHz)
 
-# Algorithmic FP32 operations per (pixel, list entry), counted from the
-# equations (a fused multiply-add counts 2, exp counts 1):
-#   alpha evaluation, Eq. 5: mu - p (2), quadratic form (8), * -1/2 (1),
-#   exp (1), * opacity (1)                                          = 13
-#   blending one Gaussian, Eq. 3, 4, 6, 9, 10: 1 - alpha, T (1 - alpha),
-#   w = alpha T (3), colour (6), depth (2), opacity (1), (d - D)^2 w (4) = 16
-#   backward of one blended Gaussian (pose gradients): T_j (2), w (1),
-#   (d - D)^2 (2), dL/dalpha over 6 blended quantities (13), behind sums (18),
-#   dL/dpower and dL/dopacity (2), dL/dmu (8), dL/dconic (9), dL/ddepth (5),
-#   dL/dcolour (3)                                                  = 63
+# Algorithmic FP32 operations, counted from the equations (a fused
+# multiply-add counts 2, exp counts 1):
+#   alpha of one (pixel, list entry), Eq. 5: mu - p (2), quadratic form (8),
+#   * -1/2 (1), exp (1), * opacity (1)                                   = 13
+#   blending one Gaussian, Eq. 3, 4, 6, 9 (tracking needs no Eq. 10):
+#   1 - alpha, T (1 - alpha), w = alpha T (3), colour (6), depth (2),
+#   opacity (1)                                                          = 12
+#   backward of one blended Gaussian with colour and depth gradients:
+#   T_j (2), w (1), dL/dalpha over the 4 blended quantities (9), behind
+#   sums (12), dL/dpower (1), dL/dmu (8), dL/dconic (9), dL/ddepth (2)   = 44
+# The forward evaluates alpha for every entry up to where it stops; the
+# backward re-evaluates it for every entry up to the last blended one.
 FLOP_EVAL = 13
-FLOP_BLEND = 16
-FLOP_BLEND_BWD = 63
+FLOP_BLEND = 12
+FLOP_BLEND_BWD = 44
 
 
 def log(*a):
@@ -168,9 +170,8 @@ def main():
         reps = 20
         dpose = torch.zeros((1, 6), device="cuda")
         for r in range(reps + 2):
-            out = R.render(tst, prob.scene, pose, [prob.cam], maps=("color", "depth"))[0]
-            dc, dd = R.tracking_loss_grad(out["color"], out["depth"], prob.target_color, prob.target_depth)
-            R.backward(tst, [dict(color=dc, depth=dd)], param_grads=False)
+            R.tracking_step(tst, prob.scene, pose, [prob.cam], [prob.target_color], [prob.target_depth],
+                            dposes=dpose)
             t = tst.timings()
             if r >= 2:
                 for k, v in t.items():
@@ -178,7 +179,7 @@ def main():
         stages = acc
         s = tst.stats()
         stats = dict(visible=int(s.visible), pairs=int(s.pairs), evaluations=int(s.processed),
-                     blended=int(s.blended))
+                     blended=int(s.blended), walked=int(s.walked))
         log("stage ms:", {k: round(v, 4) for k, v in stages.items()}, "stats:", stats)
 
     result = {
@@ -204,7 +205,7 @@ def main():
         # The dominant single kernel and its roofline.
         blend_f, blend_b = stages["blend_fwd"], stages["blend_bwd"]
         flops_fwd = FLOP_EVAL * stats["evaluations"] + FLOP_BLEND * stats["blended"]
-        flops_bwd = (FLOP_EVAL + FLOP_BLEND_BWD) * stats["blended"]
+        flops_bwd = FLOP_EVAL * stats["walked"] + FLOP_BLEND_BWD * stats["blended"]
         cand = {"blend_fwd": (blend_f, flops_fwd), "blend_bwd": (blend_b, flops_bwd)}
         name = max(cand, key=lambda k: cand[k][0])
         ms, fl = cand[name]

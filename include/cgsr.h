@@ -102,6 +102,8 @@ typedef struct {
     int64_t processed;       /* (pixel, list entry) alpha evaluations of the
                                 forward blend, summed over pixels                */
     int64_t blended;         /* (pixel, Gaussian) pairs actually blended          */
+    int64_t walked;          /* (pixel, list entry) pairs up to each pixel's last
+                                blended Gaussian: what the backward revisits    */
 } cgsr_stats;
 
 /* Stages timed when cgsr_settings.timing is set. */
@@ -179,6 +181,13 @@ cgsr_status cgsr_tracking_loss_grad(int32_t width, int32_t height, const float *
                                     float lambda_depth, float *dcolor, float *ddepth, float *loss,
                                     void *stream);
 
+/* Adam hyper-parameters of the pose update; the paper uses learning rates
+ * 0.0015 for the rotation (so(3)) part and 0.00215 for the translation part
+ * (Sec. 4, Implementation Details).  beta1, beta2, eps as in Adam. */
+typedef struct {
+    float lr_rho, lr_phi, beta1, beta2, eps;
+} cgsr_adam_params;
+
 /*
  * One Adam step on each view's pose in its tangent space, then the left
  * retraction T <- exp(delta^) T (Sec. 3.4, Eq. 20; Adam with bias correction).
@@ -186,11 +195,31 @@ cgsr_status cgsr_tracking_loss_grad(int32_t width, int32_t height, const float *
  *   dposes     device float[n_views][6], read then zeroed.
  *   adam       device float[n_views][16]: m[6], v[6], step count, 3 unused;
  *              zero-initialise before the first step.
- *   lr_rho, lr_phi  learning rates of the translation and rotation parts.
  */
 cgsr_status cgsr_pose_adam_step(int32_t n_views, float *poses, float *dposes, float *adam,
-                                float lr_rho, float lr_phi, float beta1, float beta2, float eps,
-                                void *stream);
+                                const cgsr_adam_params *params, void *stream);
+
+/*
+ * One sequential-tracking iteration (Sec. 3.4, Eq. 19-20) of n_views
+ * independent frames in one launch sequence: render; the gradient images of
+ *   L = lambda_color * L_color (Eq. 14) + lambda_depth * L_geo (Eq. 16)
+ * formed inside the blend from the blended values (no maps are written);
+ * pose-only backward; then, if adam is non-NULL, an Adam step with left
+ * retraction of every pose.
+ *   poses         device float[n_views][12]; updated in place when adam != NULL.
+ *   target_color  host array of n_views device pointers to [3][H][W].
+ *   target_depth  host array of n_views device pointers to [H][W].
+ *   dposes        device float[n_views][6] (+= the pose gradient) or NULL.
+ *   adam          device float[n_views][16] Adam state (as for
+ *                 cgsr_pose_adam_step) or NULL; params required with it.
+ *   loss          device float[n_views] (+= each frame's L) or NULL.
+ * The state is left as after a render; cgsr_backward on it is an error.
+ */
+cgsr_status cgsr_tracking_step(cgsr_state *st, const cgsr_gaussians *g, int32_t n_views, float *poses,
+                               const cgsr_camera *cams, const float *const *target_color,
+                               const float *const *target_depth, float lambda_color, float lambda_depth,
+                               float *dposes, float *adam, const cgsr_adam_params *adam_params,
+                               float *loss, void *stream);
 
 /* Synchronise the stream and report CGSR_ERR_CAPACITY if the last render on
  * this state overflowed its pair buffer. */

@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "CGSR_OK", -1: "CGSR_ERR_INVALID_ARG", -2: "CGSR_ERR_OOM", -3
 
 EXPORTED = (
     "cgsr_default_settings", "cgsr_state_create", "cgsr_state_destroy", "cgsr_state_reserve",
-    "cgsr_render", "cgsr_backward", "cgsr_tracking_loss_grad", "cgsr_pose_adam_step",
+    "cgsr_render", "cgsr_backward", "cgsr_tracking_loss_grad", "cgsr_pose_adam_step", "cgsr_tracking_step",
     "cgsr_state_check", "cgsr_get_stats", "cgsr_get_timings", "cgsr_debug_buffers", "cgsr_last_error",
     "cgsr_version",
 )
@@ -67,10 +67,15 @@ class cgsr_settings(C.Structure):
     _fields_ = [("sync_capacity", C.c_int32), ("timing", C.c_int32)]
 
 
+class cgsr_adam_params(C.Structure):
+    _fields_ = [("lr_rho", C.c_float), ("lr_phi", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float)]
+
+
 class cgsr_stats(C.Structure):
     _fields_ = [("visible", C.c_int64), ("pairs", C.c_int64), ("pair_capacity", C.c_int64),
                 ("overflow", C.c_int32), ("n_views", C.c_int32), ("processed", C.c_int64),
-                ("blended", C.c_int64)]
+                ("blended", C.c_int64), ("walked", C.c_int64)]
 
 
 _lib = None
@@ -100,8 +105,10 @@ def lib() -> C.CDLL:
     L.cgsr_backward.argtypes = [vp, C.POINTER(cgsr_images), C.POINTER(cgsr_gaussian_grads), vp, vp]
     L.cgsr_tracking_loss_grad.argtypes = [C.c_int32, C.c_int32, vp, vp, vp, vp, C.c_float, C.c_float, vp, vp,
                                           vp, vp]
-    L.cgsr_pose_adam_step.argtypes = [C.c_int32, vp, vp, vp, C.c_float, C.c_float, C.c_float, C.c_float,
-                                      C.c_float, vp]
+    L.cgsr_pose_adam_step.argtypes = [C.c_int32, vp, vp, vp, C.POINTER(cgsr_adam_params), vp]
+    L.cgsr_tracking_step.argtypes = [vp, C.POINTER(cgsr_gaussians), C.c_int32, vp, C.POINTER(cgsr_camera),
+                                     C.POINTER(vp), C.POINTER(vp), C.c_float, C.c_float, vp, vp,
+                                     C.POINTER(cgsr_adam_params), vp, vp]
     L.cgsr_state_check.argtypes = [vp, vp]
     L.cgsr_get_stats.argtypes = [vp, vp, C.POINTER(cgsr_stats)]
     L.cgsr_get_timings.argtypes = [vp, C.POINTER(C.c_float)]
@@ -164,8 +171,18 @@ def cgsr_tracking_loss_grad(width, height, color, depth, target_color, target_de
                                          lambda_depth, dcolor, ddepth, loss, stream))
 
 
-def cgsr_pose_adam_step(n_views, poses, dposes, adam, lr_rho, lr_phi, beta1, beta2, eps, stream) -> None:
-    _check(lib().cgsr_pose_adam_step(n_views, poses, dposes, adam, lr_rho, lr_phi, beta1, beta2, eps, stream))
+def cgsr_pose_adam_step(n_views, poses, dposes, adam, params: cgsr_adam_params, stream) -> None:
+    _check(lib().cgsr_pose_adam_step(n_views, poses, dposes, adam, C.byref(params), stream))
+
+
+def cgsr_tracking_step(state: int, g: cgsr_gaussians, n_views: int, poses: int, cams, target_color, target_depth,
+                       lambda_color: float, lambda_depth: float, dposes, adam, params, loss, stream: int) -> None:
+    """cams: sequence of cgsr_camera; target_color/target_depth: sequences of device pointers."""
+    cam_arr = (cgsr_camera * n_views)(*cams)
+    tc = (C.c_void_p * n_views)(*target_color)
+    td = (C.c_void_p * n_views)(*target_depth)
+    _check(lib().cgsr_tracking_step(state, C.byref(g), n_views, poses, cam_arr, tc, td, lambda_color, lambda_depth,
+                                    dposes, adam, C.byref(params) if params is not None else None, loss, stream))
 
 
 def cgsr_state_check(state: int, stream: int) -> None:

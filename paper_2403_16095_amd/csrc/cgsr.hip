@@ -78,6 +78,7 @@ struct cgsr_state {
   // per pixel
   uint4* pixel_state = nullptr;
   uint32_t* pixel_count = nullptr;
+  float4* pixel_grad = nullptr;
   // small buffers
   uint32_t* counters = nullptr;
   double* pose_acc = nullptr;
@@ -100,6 +101,7 @@ struct cgsr_state {
   bool fwd_timed = false, bwd_timed = false;
   // last render
   bool have_forward = false;
+  bool tracked = false;   // the last forward was a tracking step
   int32_t n_views = 0;
   GaussianPtrs g{};
   const float* poses = nullptr;
@@ -110,9 +112,6 @@ struct cgsr_state {
 };
 
 namespace {
-
-constexpr int64_t kCounterWords = kCntGroupTickets + kMaxGroups;
-constexpr int kProjThreads = 256;
 
 cgsr_status set_device(cgsr_state* st) {
   int cur = -1;
@@ -157,9 +156,11 @@ cgsr_status reserve(cgsr_state* st, int64_t records, int64_t pixels, int64_t til
   if (pixels > st->cap_pixels) {
     dev_free(st->pixel_state);
     dev_free(st->pixel_count);
+    dev_free(st->pixel_grad);
     st->cap_pixels = 0;
     if ((s = dev_alloc(&st->pixel_state, pixels))) return s;
     if ((s = dev_alloc(&st->pixel_count, pixels))) return s;
+    if ((s = dev_alloc(&st->pixel_grad, pixels))) return s;
     st->cap_pixels = pixels;
   }
   if (tiles > st->cap_tiles) {
@@ -233,7 +234,10 @@ RasterBufs raster_bufs(cgsr_state* st, int slot) {
   rb.ranges = st->ranges;
   rb.pixel_state = st->pixel_state;
   rb.pixel_count = st->pixel_count;
+  rb.pixel_grad = st->pixel_grad;
   rb.rec_grad = st->rec_grad;
+  rb.lambda_color = rb.lambda_depth = 0.f;
+  rb.loss = nullptr;
   rb.views = ViewTable{st->io[slot].dev, st->n_views, (int32_t)st->g.n};
   rb.total_tiles = st->total_tiles;
   return rb;
@@ -278,7 +282,7 @@ cgsr_status cgsr_state_create(const cgsr_settings* s, cgsr_state** out) {
     if (!r && hipEventCreateWithFlags(&st->io[k].event, hipEventDisableTiming) != hipSuccess)
       r = fail(CGSR_ERR_HIP, "hipEventCreate failed");
   }
-  if (!r) r = dev_alloc(&st->stats_dev, 3);
+  if (!r) r = dev_alloc(&st->stats_dev, 4);
   for (auto& ev : st->ev_fwd)
     if (!r && hipEventCreate(&ev) != hipSuccess) r = fail(CGSR_ERR_HIP, "hipEventCreate failed");
   for (auto& ev : st->ev_bwd)
@@ -311,6 +315,7 @@ cgsr_status cgsr_state_destroy(cgsr_state* st) {
   dev_free(st->sorted_vals);
   dev_free(st->pixel_state);
   dev_free(st->pixel_count);
+  dev_free(st->pixel_grad);
   dev_free(st->counters);
   dev_free(st->pose_acc);
   dev_free(st->stats_dev);
@@ -340,29 +345,29 @@ cgsr_status cgsr_state_reserve(cgsr_state* st, int64_t max_records, int64_t max_
   return reserve(st, max_records, max_pixels, max_tiles, max_pairs);
 }
 
-cgsr_status cgsr_render(cgsr_state* st, const cgsr_gaussians* g, int32_t n_views, const float* poses,
-                        const cgsr_camera* cams, const float* const* depth_obs, const cgsr_images* outs,
-                        void* stream_) {
-  hipStream_t stream = (hipStream_t)stream_;
-  if (!st || !g || !poses || !cams || !outs) return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: NULL argument");
+}  // extern "C"
+
+namespace {
+
+// Checks the Gaussians and cameras of a render and fills the per-view table
+// (camera constants; the caller adds the image pointers).
+cgsr_status check_views(const cgsr_gaussians* g, int32_t n_views, const float* poses, const cgsr_camera* cams,
+                        ViewIO* io, int64_t* tiles_out, int64_t* pixels_out) {
+  if (!g || !poses || !cams) return fail(CGSR_ERR_INVALID_ARG, "render: NULL argument");
   if (n_views < 1 || n_views > CGSR_MAX_VIEWS)
-    return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: n_views must be in [1, %d]", CGSR_MAX_VIEWS);
-  if (g->n < 0) return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: negative Gaussian count");
-  if (g->n > INT32_MAX) return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: more than 2^31 Gaussians");
+    return fail(CGSR_ERR_INVALID_ARG, "render: n_views must be in [1, %d]", CGSR_MAX_VIEWS);
+  if (g->n < 0) return fail(CGSR_ERR_INVALID_ARG, "render: negative Gaussian count");
+  if (g->n > INT32_MAX) return fail(CGSR_ERR_INVALID_ARG, "render: more than 2^31 Gaussians");
   if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->rgb))
-    return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: NULL Gaussian parameter pointer");
+    return fail(CGSR_ERR_INVALID_ARG, "render: NULL Gaussian parameter pointer");
   if ((int64_t)g->n * n_views >= (1ll << 32))
-    return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: more than 2^32 (view, Gaussian) records");
+    return fail(CGSR_ERR_INVALID_ARG, "render: more than 2^32 (view, Gaussian) records");
   if (g->n > 0 && ((uintptr_t)g->quats & 15))
-    return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: quats must be 16-byte aligned");
-  const int64_t blocks = std::max<int64_t>(1, (g->n + kProjThreads - 1) / kProjThreads) * n_views;
-  if ((blocks + kScanGroup - 1) / kScanGroup > kMaxGroups)
-    return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: too many (view, Gaussian) records");
+    return fail(CGSR_ERR_INVALID_ARG, "render: quats must be 16-byte aligned");
   int64_t tiles = 0, pixels = 0;
-  ViewIO io[CGSR_MAX_VIEWS];
   for (int v = 0; v < n_views; ++v) {
     const cgsr_camera& c = cams[v];
-    if (bad_camera(c)) return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: invalid camera for view %d", v);
+    if (bad_camera(c)) return fail(CGSR_ERR_INVALID_ARG, "render: invalid camera for view %d", v);
     std::memset(&io[v], 0, sizeof(ViewIO));
     ViewInfo& vi = io[v].info;
     vi.width = c.width;
@@ -378,35 +383,46 @@ cgsr_status cgsr_render(cgsr_state* st, const cgsr_gaussians* g, int32_t n_views
     tiles += (int64_t)vi.tiles_x * vi.tiles_y;
     pixels += (int64_t)c.width * c.height;
     if (tiles >= INT32_MAX || pixels >= INT32_MAX)
-      return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: too many tiles or pixels");
-    io[v].depth_obs = depth_obs ? depth_obs[v] : nullptr;
-    io[v].color = outs[v].color;
-    io[v].depth = outs[v].depth;
-    io[v].opacity = outs[v].opacity;
-    io[v].depth_median = outs[v].depth_median;
-    io[v].uncertainty = outs[v].uncertainty;
-    if (io[v].uncertainty && !io[v].depth_obs)
-      return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: view %d asks for uncertainty without sensor depth", v);
+      return fail(CGSR_ERR_INVALID_ARG, "render: too many tiles or pixels");
   }
+  *tiles_out = tiles;
+  *pixels_out = pixels;
+  return CGSR_OK;
+}
+
+struct RenderArgs {
+  const cgsr_gaussians* g;
+  int32_t n_views;
+  const float* poses;
+  const ViewIO* io;
+  int64_t tiles, pixels;
+  bool track;
+  float lambda_color, lambda_depth;
+  float* loss;
+};
+
+// Projection -> tile-count scan -> emission -> segment sort -> blend.
+cgsr_status render_impl(cgsr_state* st, const RenderArgs& a, hipStream_t stream) {
   cgsr_status s = set_device(st);
   if (s) return s;
-  const int64_t records = g->n * (int64_t)n_views;
+  const int64_t records = a.g->n * (int64_t)a.n_views;
   hipStreamCaptureStatus capturing = hipStreamCaptureStatusNone;
   HIP_TRY(hipStreamIsCapturing(stream, &capturing));
   const bool in_capture = capturing != hipStreamCaptureStatusNone;
-  if (in_capture && (records > st->cap_records || pixels > st->cap_pixels || tiles > st->cap_tiles))
-    return fail(CGSR_ERR_STATE, "cgsr_render: workspace too small for graph capture; reserve it first");
-  s = reserve(st, records, pixels, tiles, 0);
+  if (in_capture && (records > st->cap_records || a.pixels > st->cap_pixels || a.tiles > st->cap_tiles))
+    return fail(CGSR_ERR_STATE, "render: workspace too small for graph capture; reserve it first");
+  s = reserve(st, records, a.pixels, a.tiles, 0);
   if (s) return s;
   st->have_forward = false;
-  st->n_views = n_views;
-  st->g = GaussianPtrs{g->means, g->log_scales, g->quats, g->opacity_logits, g->rgb, g->n};
-  st->poses = poses;
-  st->total_pixels = pixels;
-  st->total_tiles = (int32_t)tiles;
+  st->tracked = false;
+  st->n_views = a.n_views;
+  st->g = GaussianPtrs{a.g->means, a.g->log_scales, a.g->quats, a.g->opacity_logits, a.g->rgb, a.g->n};
+  st->poses = a.poses;
+  st->total_pixels = a.pixels;
+  st->total_tiles = (int32_t)a.tiles;
   st->records = records;
-  std::memcpy(st->io_fwd, io, sizeof(ViewIO) * n_views);
-  s = upload_io(st, 0, io, n_views, stream);
+  std::memcpy(st->io_fwd, a.io, sizeof(ViewIO) * a.n_views);
+  s = upload_io(st, 0, a.io, a.n_views, stream);
   if (s) return s;
   if (st->tiles_dirty) {
     // A previous render stopped before its sort reset the per-tile counters.
@@ -414,7 +430,7 @@ cgsr_status cgsr_render(cgsr_state* st, const cgsr_gaussians* g, int32_t n_views
     launch_clear_u32(st->tile_fill, st->cap_tiles, stream);
   }
 
-  const ViewTable vt{st->io[0].dev, n_views, (int32_t)g->n};
+  const ViewTable vt{st->io[0].dev, a.n_views, (int32_t)a.g->n};
   const bool timed = st->settings.timing && !in_capture;
   auto mark = [&](int k) -> cgsr_status {
     if (timed) HIP_TRY(hipEventRecord(st->ev_fwd[k], stream));
@@ -424,7 +440,7 @@ cgsr_status cgsr_render(cgsr_state* st, const cgsr_gaussians* g, int32_t n_views
   if ((s = mark(CGSR_STAGE_PROJECT))) return s;
   st->tiles_dirty = true;
   ProjectBufs pb = project_bufs(st);
-  launch_project(st->g, poses, vt, pb, stream);
+  launch_project(st->g, a.poses, vt, pb, stream);
   HIP_TRY(hipGetLastError());
   if (st->settings.sync_capacity && !in_capture) {
     HIP_TRY(hipMemcpyAsync(st->counters_pinned, st->counters, sizeof(uint32_t) * 2, hipMemcpyDeviceToHost, stream));
@@ -454,12 +470,67 @@ cgsr_status cgsr_render(cgsr_state* st, const cgsr_gaussians* g, int32_t n_views
   HIP_TRY(hipGetLastError());
   st->tiles_dirty = false;
   if ((s = mark(CGSR_STAGE_BLEND_FWD))) return s;
-  launch_raster_forward(raster_bufs(st, 0), stream);
+  RasterBufs rb = raster_bufs(st, 0);
+  rb.lambda_color = a.lambda_color;
+  rb.lambda_depth = a.lambda_depth;
+  rb.loss = a.loss;
+  launch_raster_forward(rb, a.track, stream);
   HIP_TRY(hipGetLastError());
   if ((s = mark(CGSR_STAGE_BLEND_FWD + 1))) return s;
   st->fwd_timed = timed;
+  st->tracked = a.track;
   st->have_forward = true;
   return CGSR_OK;
+}
+
+// Blend backward -> projection backward (-> pose hand-off / Adam step).
+cgsr_status backward_impl(cgsr_state* st, int slot, bool params, bool track, const GradPtrs& gp, float* dposes,
+                          const PoseStep* step, hipStream_t stream) {
+  hipStreamCaptureStatus capturing = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(stream, &capturing));
+  const bool timed = st->settings.timing && capturing == hipStreamCaptureStatusNone;
+  st->bwd_timed = false;
+  if (timed) HIP_TRY(hipEventRecord(st->ev_bwd[0], stream));
+  const RasterBufs rb = raster_bufs(st, slot);
+  launch_raster_backward(rb, params, track, stream);
+  if (timed) HIP_TRY(hipEventRecord(st->ev_bwd[1], stream));
+  launch_project_backward(st->g, st->poses, rb.views, st->rec_grad, st->tiles, gp, params, st->pose_acc, dposes, step,
+                          stream);
+  HIP_TRY(hipGetLastError());
+  if (timed) HIP_TRY(hipEventRecord(st->ev_bwd[2], stream));
+  st->bwd_timed = timed;
+  return CGSR_OK;
+}
+
+bool bad_adam(const cgsr_adam_params* p) {
+  return !p || !(p->beta1 >= 0.f && p->beta1 < 1.f) || !(p->beta2 >= 0.f && p->beta2 < 1.f) || !(p->eps > 0.f) ||
+         !(p->lr_rho >= 0.f) || !(p->lr_phi >= 0.f);
+}
+
+}  // namespace
+
+extern "C" {
+
+cgsr_status cgsr_render(cgsr_state* st, const cgsr_gaussians* g, int32_t n_views, const float* poses,
+                        const cgsr_camera* cams, const float* const* depth_obs, const cgsr_images* outs,
+                        void* stream) {
+  if (!st || !outs) return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: NULL argument");
+  ViewIO io[CGSR_MAX_VIEWS];
+  int64_t tiles = 0, pixels = 0;
+  cgsr_status s = check_views(g, n_views, poses, cams, io, &tiles, &pixels);
+  if (s) return s;
+  for (int v = 0; v < n_views; ++v) {
+    io[v].depth_obs = depth_obs ? depth_obs[v] : nullptr;
+    io[v].color = outs[v].color;
+    io[v].depth = outs[v].depth;
+    io[v].opacity = outs[v].opacity;
+    io[v].depth_median = outs[v].depth_median;
+    io[v].uncertainty = outs[v].uncertainty;
+    if (io[v].uncertainty && !io[v].depth_obs)
+      return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: view %d asks for uncertainty without sensor depth", v);
+  }
+  return render_impl(st, RenderArgs{g, n_views, poses, io, tiles, pixels, false, 0.f, 0.f, nullptr},
+                     (hipStream_t)stream);
 }
 
 cgsr_status cgsr_backward(cgsr_state* st, const cgsr_image_grads* dimgs, const cgsr_gaussian_grads* dG,
@@ -467,6 +538,7 @@ cgsr_status cgsr_backward(cgsr_state* st, const cgsr_image_grads* dimgs, const c
   hipStream_t stream = (hipStream_t)stream_;
   if (!st || !dimgs) return fail(CGSR_ERR_INVALID_ARG, "cgsr_backward: NULL argument");
   if (!st->have_forward) return fail(CGSR_ERR_STATE, "cgsr_backward: no forward pass on this state");
+  if (st->tracked) return fail(CGSR_ERR_STATE, "cgsr_backward: the last forward was a tracking step");
   const int n_views = st->n_views;
   const bool params = dG && (dG->means || dG->log_scales || dG->quats || dG->opacity_logits || dG->rgb);
   if (!params && !dposes) return CGSR_OK;
@@ -485,22 +557,40 @@ cgsr_status cgsr_backward(cgsr_state* st, const cgsr_image_grads* dimgs, const c
   if (s) return s;
   s = upload_io(st, 1, io, n_views, stream);
   if (s) return s;
-  hipStreamCaptureStatus capturing = hipStreamCaptureStatusNone;
-  HIP_TRY(hipStreamIsCapturing(stream, &capturing));
-  const bool timed = st->settings.timing && capturing == hipStreamCaptureStatusNone;
-  st->bwd_timed = false;
-  if (timed) HIP_TRY(hipEventRecord(st->ev_bwd[0], stream));
-  const RasterBufs rb = raster_bufs(st, 1);
-  launch_raster_backward(rb, params, stream);
-  if (timed) HIP_TRY(hipEventRecord(st->ev_bwd[1], stream));
   GradPtrs gp{};
   if (params) gp = GradPtrs{dG->means, dG->log_scales, dG->quats, dG->opacity_logits, dG->rgb};
-  launch_project_backward(st->g, st->poses, rb.views, st->rec_grad, st->tiles, gp, params, st->pose_acc, dposes,
-                          st->counters, stream);
-  HIP_TRY(hipGetLastError());
-  if (timed) HIP_TRY(hipEventRecord(st->ev_bwd[2], stream));
-  st->bwd_timed = timed;
-  return CGSR_OK;
+  return backward_impl(st, 1, params, false, gp, dposes, nullptr, stream);
+}
+
+cgsr_status cgsr_tracking_step(cgsr_state* st, const cgsr_gaussians* g, int32_t n_views, float* poses,
+                               const cgsr_camera* cams, const float* const* target_color,
+                               const float* const* target_depth, float lambda_color, float lambda_depth,
+                               float* dposes, float* adam, const cgsr_adam_params* adam_params, float* loss,
+                               void* stream_) {
+  hipStream_t stream = (hipStream_t)stream_;
+  if (!st || !target_color || !target_depth) return fail(CGSR_ERR_INVALID_ARG, "cgsr_tracking_step: NULL argument");
+  if (adam && bad_adam(adam_params)) return fail(CGSR_ERR_INVALID_ARG, "cgsr_tracking_step: bad Adam parameters");
+  if (!(lambda_color >= 0.f) || !(lambda_depth >= 0.f))
+    return fail(CGSR_ERR_INVALID_ARG, "cgsr_tracking_step: loss weights must be non-negative");
+  ViewIO io[CGSR_MAX_VIEWS];
+  int64_t tiles = 0, pixels = 0;
+  cgsr_status s = check_views(g, n_views, poses, cams, io, &tiles, &pixels);
+  if (s) return s;
+  for (int v = 0; v < n_views; ++v) {
+    if (!target_color[v] || !target_depth[v])
+      return fail(CGSR_ERR_INVALID_ARG, "cgsr_tracking_step: view %d has no target", v);
+    io[v].t_color = target_color[v];
+    io[v].t_depth = target_depth[v];
+  }
+  s = render_impl(st, RenderArgs{g, n_views, poses, io, tiles, pixels, true, lambda_color, lambda_depth, loss},
+                  stream);
+  if (s) return s;
+  if (!dposes && !adam) return CGSR_OK;
+  PoseStep step{poses, adam, AdamParams{}};
+  if (adam)
+    step.params = AdamParams{adam_params->lr_rho, adam_params->lr_phi, adam_params->beta1, adam_params->beta2,
+                             adam_params->eps};
+  return backward_impl(st, 0, false, true, GradPtrs{}, dposes, adam ? &step : nullptr, stream);
 }
 
 cgsr_status cgsr_tracking_loss_grad(int32_t width, int32_t height, const float* color, const float* depth,
@@ -515,13 +605,13 @@ cgsr_status cgsr_tracking_loss_grad(int32_t width, int32_t height, const float* 
   return CGSR_OK;
 }
 
-cgsr_status cgsr_pose_adam_step(int32_t n_views, float* poses, float* dposes, float* adam, float lr_rho,
-                                float lr_phi, float beta1, float beta2, float eps, void* stream) {
+cgsr_status cgsr_pose_adam_step(int32_t n_views, float* poses, float* dposes, float* adam,
+                                const cgsr_adam_params* p, void* stream) {
   if (n_views < 1 || n_views > CGSR_MAX_VIEWS) return fail(CGSR_ERR_INVALID_ARG, "pose adam: bad view count");
   if (!poses || !dposes || !adam) return fail(CGSR_ERR_INVALID_ARG, "pose adam: NULL argument");
-  if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
-    return fail(CGSR_ERR_INVALID_ARG, "pose adam: bad hyper-parameters");
-  launch_pose_adam(n_views, poses, dposes, adam, lr_rho, lr_phi, beta1, beta2, eps, (hipStream_t)stream);
+  if (bad_adam(p)) return fail(CGSR_ERR_INVALID_ARG, "pose adam: bad hyper-parameters");
+  launch_pose_adam(n_views, poses, dposes, adam, AdamParams{p->lr_rho, p->lr_phi, p->beta1, p->beta2, p->eps},
+                   (hipStream_t)stream);
   HIP_TRY(hipGetLastError());
   return CGSR_OK;
 }
@@ -548,8 +638,8 @@ cgsr_status cgsr_get_stats(cgsr_state* st, void* stream_, cgsr_stats* out) {
   out->pair_capacity = st->cap_pairs;
   out->n_views = st->n_views;
   if (!st->have_forward) return CGSR_OK;
-  unsigned long long host[3];
-  launch_clear_u32(reinterpret_cast<uint32_t*>(st->stats_dev), 6, stream);
+  unsigned long long host[4];
+  launch_clear_u32(reinterpret_cast<uint32_t*>(st->stats_dev), 8, stream);
   launch_stats(st->tiles, st->records, st->pixel_state, st->pixel_count, st->total_pixels, st->stats_dev, stream);
   HIP_TRY(hipMemcpyAsync(st->counters_pinned, st->counters, sizeof(uint32_t) * 2, hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipMemcpyAsync(host, st->stats_dev, sizeof(host), hipMemcpyDeviceToHost, stream));
@@ -559,6 +649,7 @@ cgsr_status cgsr_get_stats(cgsr_state* st, void* stream_, cgsr_stats* out) {
   out->visible = (int64_t)host[0];
   out->processed = (int64_t)host[1];
   out->blended = (int64_t)host[2];
+  out->walked = (int64_t)host[3];
   return CGSR_OK;
 }
 

@@ -50,6 +50,8 @@ struct ViewIO {
   const float* g_opacity;
   const float* g_median;
   const float* g_uncertainty;
+  const float* t_color;     // tracking targets: [3][H][W] colour and [H][W] depth
+  const float* t_depth;
 };
 
 struct ViewTable {
@@ -68,25 +70,32 @@ constexpr int kRecF4 = 3;
 //   0,1 mu   2,3,4 conic (a, b, c)   5 opacity   6 depth   7,8,9 colour
 constexpr int kGradStride = 12;  // floats per record (48 B, 16-B aligned)
 
-// alpha of a (Gaussian, pixel) pair, Eq. 5 with the 3DGS conventions.  Used by
-// the forward and the backward pass with identical operation order, so both
-// take the same skip, cap and stop decisions (the library is built without
-// floating-point contraction; every fused multiply-add here is explicit).
-struct PairAlpha {
-  float dx, dy;   // mu - pixel
-  float g;        // exp(power)
-  float raw;      // opacity * g (before the cap)
-};
+// A record as the blend kernels stage it in LDS, once per (tile, record):
+//   a = (mu_x, mu_y, qa, qb)       qa = -a/2 log2(e), qb = -b log2(e)
+//   b = (qc, opacity, depth, thr)  qc = -c/2 log2(e), thr = -log2(255 opacity)
+//   c = (r, g, b, -)
+// so that the exponent of Eq. 5 in base 2 is qa dx^2 + qb dx dy + qc dy^2 and
+// a pair is skipped (alpha < 1/255) exactly when that exponent is below thr.
+// The forward and the backward stage and evaluate with these same functions
+// (the library is built without floating-point contraction, every fused
+// multiply-add is explicit), so they take identical skip, cap and stop
+// decisions.
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
 
-__device__ __forceinline__ PairAlpha pair_alpha(float mux, float muy, float ca, float cb, float cc,
-                                                float opac, float px, float py) {
-  PairAlpha r;
-  r.dx = mux - px;
-  r.dy = muy - py;
-  const float q = __builtin_fmaf(ca * r.dx, r.dx, __builtin_fmaf(cc * r.dy, r.dy, 2.0f * cb * r.dx * r.dy));
-  r.g = __expf(-0.5f * q);
-  r.raw = opac * r.g;
-  return r;
+__device__ __forceinline__ void stage_record(const float4* __restrict__ rec, float4& A, float4& B, float4& C) {
+  const float4 r0 = rec[0], r1 = rec[1], r2 = rec[2];
+  A = make_float4(r0.x, r0.y, (-0.5f * kLog2e) * r0.z, -kLog2e * r0.w);
+  B = make_float4((-0.5f * kLog2e) * r1.x, r1.y, r1.z, -__log2f(255.0f * r1.y));
+  C = make_float4(r1.w, r2.x, r2.y, 0.f);
+}
+
+// Base-2 exponent of a staged record at pixel centre (px, py); dx, dy = mu - p.
+__device__ __forceinline__ float pair_exponent(const float4& A, const float4& B, float px, float py, float& dx,
+                                               float& dy) {
+  dx = A.x - px;
+  dy = A.y - py;
+  return __builtin_fmaf(A.z, dx * dx, __builtin_fmaf(A.w, dx * dy, B.x * (dy * dy)));
 }
 
 template <int kCtrl, int kRowMask>
@@ -120,6 +129,61 @@ __device__ __forceinline__ int view_of_tile(const ViewTable& vt, int gtile) {
   int v = 0;
   while (v + 1 < vt.n && gtile >= vt.io[v + 1].info.tile_base) ++v;
   return v;
+}
+
+struct AdamParams {
+  float lr_rho, lr_phi, beta1, beta2, eps;
+};
+
+// One Adam step (bias-corrected) on a pose's tangent vector xi = (rho, phi),
+// whose value is zero at the current pose, so the step is
+// delta = -lr m_hat / (sqrt(v_hat) + eps); then the left retraction
+// T <- exp(delta^) T with the closed-form SE(3) exponential.
+// P: pose[12] (row-major R, t); st: m[6], v[6], step count; g: gradient.
+__device__ inline void adam_retract(float* P, float* st, const float g[6], const AdamParams& ap) {
+  const float step = st[12] + 1.f;
+  st[12] = step;
+  const float c1 = 1.f - powf(ap.beta1, step), c2 = 1.f - powf(ap.beta2, step);
+  float d[6];
+  for (int k = 0; k < 6; ++k) {
+    const float m = ap.beta1 * st[k] + (1.f - ap.beta1) * g[k];
+    const float s = ap.beta2 * st[6 + k] + (1.f - ap.beta2) * g[k] * g[k];
+    st[k] = m;
+    st[6 + k] = s;
+    const float lr = k < 3 ? ap.lr_rho : ap.lr_phi;
+    d[k] = -lr * (m / c1) / (sqrtf(s / c2) + ap.eps);
+  }
+  // exp of (rho, phi): R = I + A K + B K^2, V = I + B K + C K^2, K = [phi]x.
+  const float p0 = d[3], p1 = d[4], p2 = d[5];
+  const float th2 = p0 * p0 + p1 * p1 + p2 * p2;
+  float A, Bc, Cc;
+  if (th2 < 1e-8f) {
+    A = 1.f - th2 / 6.f;
+    Bc = 0.5f - th2 / 24.f;
+    Cc = 1.f / 6.f - th2 / 120.f;
+  } else {
+    const float th = sqrtf(th2);
+    A = sinf(th) / th;
+    Bc = (1.f - cosf(th)) / th2;
+    Cc = (th - sinf(th)) / (th2 * th);
+  }
+  const float K[9] = {0.f, -p2, p1, p2, 0.f, -p0, -p1, p0, 0.f};
+  float K2[9], R[9], V[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) K2[3 * r + c] = K[3 * r] * K[c] + K[3 * r + 1] * K[3 + c] + K[3 * r + 2] * K[6 + c];
+  for (int k = 0; k < 9; ++k) {
+    const float I = (k % 4 == 0) ? 1.f : 0.f;
+    R[k] = I + A * K[k] + Bc * K2[k];
+    V[k] = I + Bc * K[k] + Cc * K2[k];
+  }
+  float Rn[9], tn[3];
+  for (int r = 0; r < 3; ++r) {
+    for (int c = 0; c < 3; ++c) Rn[3 * r + c] = R[3 * r] * P[c] + R[3 * r + 1] * P[3 + c] + R[3 * r + 2] * P[6 + c];
+    tn[r] = R[3 * r] * P[9] + R[3 * r + 1] * P[10] + R[3 * r + 2] * P[11] + V[3 * r] * d[0] + V[3 * r + 1] * d[1] +
+            V[3 * r + 2] * d[2];
+  }
+  for (int k = 0; k < 9; ++k) P[k] = Rn[k];
+  for (int k = 0; k < 3; ++k) P[9 + k] = tn[k];
 }
 
 }  // namespace cgsr

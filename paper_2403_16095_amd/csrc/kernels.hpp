@@ -12,12 +12,8 @@ namespace cgsr {
 enum Counter : int {
   kCntPairs = 0,        // (tile, Gaussian) pairs of the last render
   kCntOverflow = 1,     // 1 if pairs exceeded the capacity
-  kCntTicketAll = 2,    // last-group detector of the projection's tile scan
-  kCntTicketBwd = 3,    // last-block detector of the projection backward
-  kCntGroupTickets = 8  // per-group tickets start here (kMaxGroups of them)
 };
-constexpr int kScanGroup = 256;            // blocks per scan group
-constexpr int kMaxGroups = 1 << 16;
+constexpr int kCounterWords = 8;
 
 struct ProjectBufs {
   float4* rec;              // [M][3]
@@ -49,15 +45,22 @@ struct GradPtrs {
   float* rgb;
 };
 
+// Projection (one lane per (view, Gaussian)) followed by the tile-count scan.
 void launch_project(const GaussianPtrs& g, const float* poses, const ViewTable& vt, const ProjectBufs& b,
                     hipStream_t s);
 void launch_emit(const ViewTable& vt, const ProjectBufs& b, hipStream_t s);
 // Chain rule from the per-record projected gradients to the parameters and
 // the poses.  pose_acc: device double[views][6] scratch, zero on entry and
 // left zero on exit; dposes (+=) may be null.
+// Optional Adam step applied to the summed pose gradient right away.
+struct PoseStep {
+  float* poses;   // [views][12], updated in place
+  float* adam;    // [views][16]
+  AdamParams params;
+};
 void launch_project_backward(const GaussianPtrs& g, const float* poses, const ViewTable& vt, float* rec_grad,
                              const uint32_t* tiles, const GradPtrs& dg, bool param_grads, double* pose_acc,
-                             float* dposes, uint32_t* counters, hipStream_t s);
+                             float* dposes, const PoseStep* step, hipStream_t s);
 
 // Segmented sort: one workgroup per tile orders its segment of keys and
 // writes the record ids in depth order plus the tile's range.
@@ -81,21 +84,23 @@ struct RasterBufs {
   uint4* pixel_state;       // [total pixels]: final T bits, entries up to the last blended one,
                             // median position or -1, alpha evaluations
   uint32_t* pixel_count;    // [total pixels]: Gaussians blended
+  float4* pixel_grad;       // [total pixels]: tracking-loss gradient (colour, depth)
   float* rec_grad;          // [M][kGradStride]
   ViewTable views;          // device table of the pass (forward or backward pointers)
   int32_t total_tiles;
+  float lambda_color, lambda_depth;  // tracking loss weights (Eq. 19)
+  float* loss;              // [views] tracking loss (+=) or null
 };
-void launch_raster_forward(const RasterBufs& b, hipStream_t s);
-void launch_raster_backward(const RasterBufs& b, bool param_grads, hipStream_t s);
+void launch_raster_forward(const RasterBufs& b, bool track, hipStream_t s);
+void launch_raster_backward(const RasterBufs& b, bool param_grads, bool track, hipStream_t s);
 
 void launch_tracking_loss(int w, int h, const float* color, const float* depth, const float* tcolor,
                           const float* tdepth, float lc, float ld, float* dcolor, float* ddepth, float* loss,
                           hipStream_t s);
-void launch_pose_adam(int n_views, float* poses, float* dposes, float* adam, float lr_rho, float lr_phi,
-                      float b1, float b2, float eps, hipStream_t s);
+void launch_pose_adam(int n_views, float* poses, float* dposes, float* adam, const AdamParams& ap, hipStream_t s);
 
-// Statistics: visible records, alpha evaluations and blended pairs.
+// Statistics: visible records, alpha evaluations, blended pairs, walked entries.
 void launch_stats(const uint32_t* tiles, int64_t m, const uint4* pixel_state, const uint32_t* pixel_count,
-                  int64_t pixels, unsigned long long* out3, hipStream_t s);
+                  int64_t pixels, unsigned long long* out4, hipStream_t s);
 
 }  // namespace cgsr

@@ -14,10 +14,6 @@ namespace {
 
 constexpr int kThreads = 256;
 
-__device__ __forceinline__ uint32_t ld_acquire(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Exclusive prefix sum over the 256 threads of a workgroup; *total gets the sum.
 __device__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* total, uint32_t* lds4) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -136,14 +132,9 @@ __device__ bool project_core(const GaussianPtrs& g, int64_t i, const float* P, c
 
 __global__ __launch_bounds__(kThreads) void project_kernel(GaussianPtrs g, const float* __restrict__ poses,
                                                            ViewTable vt, ProjectBufs b) {
-  __shared__ uint32_t s_scan[4];
-  __shared__ int s_last;
   const int v = blockIdx.y;
   const int64_t N = g.n;
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  const uint32_t blk = v * gridDim.x + blockIdx.x;
-  const uint32_t nblocks = gridDim.x * gridDim.y;
-
   if (i < N) {
     const ViewInfo cam = vt.io[v].info;
     const float* P = poses + 12 * v;
@@ -175,45 +166,28 @@ __global__ __launch_bounds__(kThreads) void project_kernel(GaussianPtrs g, const
     }
     b.tiles[m] = ntiles;
   }
+}
 
-  // The last workgroup (two-level ticket: groups of 256, then the groups)
-  // turns the per-tile counts into segment offsets.  Every lane fences its
-  // own count atomics before the barrier that precedes the ticket.
-  const uint32_t grp = blk / kScanGroup;
-  const uint32_t ngroups = (nblocks + kScanGroup - 1) / kScanGroup;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t gsize = min((uint32_t)kScanGroup, nblocks - grp * kScanGroup);
-    bool last = atomicAdd(&b.counters[kCntGroupTickets + grp], 1u) == gsize - 1;
-    if (last) {
-      b.counters[kCntGroupTickets + grp] = 0u;
-      __threadfence();
-      last = atomicAdd(&b.counters[kCntTicketAll], 1u) == ngroups - 1;
-    }
-    s_last = last;
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  // Exclusive scan of tile_count[0, T) into tile_offset[0, T], each lane
-  // taking a contiguous run of tiles.
+// Exclusive scan of the per-tile pair counts into segment offsets, one
+// workgroup, each lane taking a contiguous run of tiles; also records the
+// pair total and whether it overflows the pair buffer.
+__global__ __launch_bounds__(kThreads) void tile_scan_kernel(ProjectBufs b) {
+  __shared__ uint32_t s_scan[4];
   const uint32_t T = (uint32_t)b.total_tiles;
   const uint32_t per = (T + kThreads - 1) / kThreads;
   const uint32_t t0 = min(T, threadIdx.x * per), t1 = min(T, t0 + per);
   uint32_t run = 0;
-  for (uint32_t t = t0; t < t1; ++t) run += ld_acquire(&b.tile_count[t]);
+  for (uint32_t t = t0; t < t1; ++t) run += b.tile_count[t];
   uint32_t total;
   uint32_t acc = block_exclusive_scan(run, &total, s_scan);
   for (uint32_t t = t0; t < t1; ++t) {
     b.tile_offset[t] = acc;
-    acc += ld_acquire(&b.tile_count[t]);
+    acc += b.tile_count[t];
   }
   if (threadIdx.x == 0) {
     b.tile_offset[T] = total;
     b.counters[kCntPairs] = total;
     b.counters[kCntOverflow] = (int64_t)total > b.pair_cap ? 1u : 0u;
-    b.counters[kCntTicketAll] = 0u;
   }
 }
 
@@ -230,12 +204,25 @@ __global__ __launch_bounds__(kThreads) void emit_kernel(ViewTable vt, ProjectBuf
   const uint32_t tx0 = r.x & 0xFFFF, tx1 = r.x >> 16, ty0 = r.y & 0xFFFF, ty1 = r.y >> 16;
   const uint64_t key = ((uint64_t)float_key(b.rec[kRecF4 * m + 1].z) << 32) | (uint64_t)m;
   const int32_t tile_base = vt.io[v].info.tile_base, tiles_x = vt.io[v].info.tiles_x;
-  for (uint32_t ty = ty0; ty <= ty1; ++ty)
-    for (uint32_t tx = tx0; tx <= tx1; ++tx) {
-      const uint32_t t = tile_base + ty * tiles_x + tx;
-      const uint64_t pos = (uint64_t)b.tile_offset[t] + atomicAdd(&b.tile_fill[t], 1u);
+  const uint32_t w = tx1 - tx0 + 1, n = w * (ty1 - ty0 + 1);
+  // Take the slots of up to 8 tiles before using any, so a lane waits for
+  // its returning atomics once per 8 tiles rather than once per tile.
+  constexpr uint32_t kBatchTiles = 8;
+  for (uint32_t k0 = 0; k0 < n; k0 += kBatchTiles) {
+    uint32_t tile[kBatchTiles], slot[kBatchTiles];
+#pragma unroll
+    for (uint32_t j = 0; j < kBatchTiles; ++j) {
+      const uint32_t k = k0 + j;
+      tile[j] = tile_base + (ty0 + k / w) * tiles_x + tx0 + k % w;
+      if (k < n) slot[j] = atomicAdd(&b.tile_fill[tile[j]], 1u);
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < kBatchTiles; ++j) {
+      if (k0 + j >= n) break;
+      const uint64_t pos = (uint64_t)b.tile_offset[tile[j]] + slot[j];
       if (pos < (uint64_t)b.pair_cap) b.keys[pos] = key;
     }
+  }
 }
 
 // Backward of project_kernel for one record.  rec_grad holds dL/d(mu, conic,
@@ -245,10 +232,8 @@ __global__ __launch_bounds__(kThreads) void project_backward_kernel(GaussianPtrs
                                                                     ViewTable vt, float* rec_grad,
                                                                     const uint32_t* __restrict__ tiles,
                                                                     GradPtrs dg, int param_grads, int atomic_params,
-                                                                    double* pose_acc, float* dposes,
-                                                                    uint32_t* counters) {
+                                                                    double* pose_acc) {
   __shared__ float s_pose[4][6];
-  __shared__ int s_last;
   const int v = blockIdx.y;
   const int64_t N = g.n;
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -383,8 +368,9 @@ __global__ __launch_bounds__(kThreads) void project_backward_kernel(GaussianPtrs
       gp[5] = x * dp1 - y * dp0 + 2.f * (Mrc(0, 1) - Mrc(1, 0));
     }
   }
-  if (!dposes) return;
-  // Workgroup reduction of the six pose terms, then one double atomic each.
+  if (!pose_acc) return;
+  // Workgroup reduction of the six pose terms, then one double atomic each;
+  // pose_finalize_kernel hands the sums to the caller.
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
@@ -395,23 +381,22 @@ __global__ __launch_bounds__(kThreads) void project_backward_kernel(GaussianPtrs
   if (threadIdx.x < 6) {
     const float t = s_pose[0][threadIdx.x] + s_pose[1][threadIdx.x] + s_pose[2][threadIdx.x] + s_pose[3][threadIdx.x];
     if (t != 0.f) atomicAdd(pose_acc + 6 * v + threadIdx.x, (double)t);
-    __threadfence();
   }
-  __syncthreads();
-  // The last workgroup moves the accumulated pose gradients to the caller.
-  if (threadIdx.x == 0) {
-    const uint32_t t = atomicAdd(&counters[kCntTicketBwd], 1u);
-    s_last = (t == gridDim.x * gridDim.y - 1);
+}
+
+// One lane per view: hands the summed pose gradient to the caller (dposes
+// +=) and/or to an Adam step with retraction, and clears the accumulator.
+__global__ void pose_finalize_kernel(double* pose_acc, float* dposes, int n_views, float* poses, float* adam,
+                                     AdamParams ap) {
+  const int v = threadIdx.x;
+  if (v >= n_views) return;
+  float g[6];
+  for (int k = 0; k < 6; ++k) {
+    g[k] = (float)pose_acc[6 * v + k];
+    pose_acc[6 * v + k] = 0.0;
+    if (dposes) dposes[6 * v + k] += g[k];
   }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  for (int k = threadIdx.x; k < 6 * vt.n; k += kThreads) {
-    const double acc = __hip_atomic_load(pose_acc + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    dposes[k] += (float)acc;
-    pose_acc[k] = 0.0;
-  }
-  if (threadIdx.x == 0) counters[kCntTicketBwd] = 0u;
+  if (adam) adam_retract(poses + 12 * v, adam + 16 * v, g, ap);
 }
 
 }  // namespace
@@ -420,6 +405,7 @@ void launch_project(const GaussianPtrs& g, const float* poses, const ViewTable& 
                     hipStream_t s) {
   const dim3 grid((unsigned)std::max<int64_t>(1, (g.n + kThreads - 1) / kThreads), (unsigned)vt.n);
   hipLaunchKernelGGL(project_kernel, grid, dim3(kThreads), 0, s, g, poses, vt, b);
+  hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(kThreads), 0, s, b);
 }
 
 void launch_emit(const ViewTable& vt, const ProjectBufs& b, hipStream_t s) {
@@ -430,10 +416,15 @@ void launch_emit(const ViewTable& vt, const ProjectBufs& b, hipStream_t s) {
 
 void launch_project_backward(const GaussianPtrs& g, const float* poses, const ViewTable& vt, float* rec_grad,
                              const uint32_t* tiles, const GradPtrs& dg, bool param_grads, double* pose_acc,
-                             float* dposes, uint32_t* counters, hipStream_t s) {
+                             float* dposes, const PoseStep* step, hipStream_t s) {
   const dim3 grid((unsigned)std::max<int64_t>(1, (g.n + kThreads - 1) / kThreads), (unsigned)vt.n);
+  const bool pose = dposes || step;
   hipLaunchKernelGGL(project_backward_kernel, grid, dim3(kThreads), 0, s, g, poses, vt, rec_grad, tiles, dg,
-                     param_grads ? 1 : 0, vt.n > 1 ? 1 : 0, pose_acc, dposes, counters);
+                     param_grads ? 1 : 0, vt.n > 1 ? 1 : 0, pose ? pose_acc : nullptr);
+  if (pose)
+    hipLaunchKernelGGL(pose_finalize_kernel, dim3(1), dim3(64), 0, s, pose_acc, dposes, vt.n,
+                       step ? step->poses : nullptr, step ? step->adam : nullptr,
+                       step ? step->params : AdamParams{0.f, 0.f, 0.f, 0.f, 1.f});
 }
 
 }  // namespace cgsr

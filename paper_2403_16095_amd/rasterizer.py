@@ -168,11 +168,37 @@ def tracking_loss_grad(color, depth, target_color, target_depth, lam=TRACK_LAMBD
     return dcolor, ddepth
 
 
+def adam_params(lr_rho=TRACK_LR_RHO, lr_phi=TRACK_LR_PHI, betas=(0.9, 0.999), eps=1e-8) -> B.cgsr_adam_params:
+    return B.cgsr_adam_params(float(lr_rho), float(lr_phi), float(betas[0]), float(betas[1]), float(eps))
+
+
 def pose_adam_step(poses, dposes, adam, lr_rho=TRACK_LR_RHO, lr_phi=TRACK_LR_PHI, betas=(0.9, 0.999), eps=1e-8):
     """In-place Adam step plus left retraction of every view's pose on the device."""
     V = poses.reshape(-1, 12).shape[0]
-    B.cgsr_pose_adam_step(V, poses.data_ptr(), dposes.data_ptr(), adam.data_ptr(), float(lr_rho), float(lr_phi),
-                          float(betas[0]), float(betas[1]), float(eps), _stream())
+    B.cgsr_pose_adam_step(V, poses.data_ptr(), dposes.data_ptr(), adam.data_ptr(),
+                          adam_params(lr_rho, lr_phi, betas, eps), _stream())
+
+
+def tracking_step(state: State, scene: dict, poses: torch.Tensor, cams, target_colors, target_depths,
+                  lam=TRACK_LAMBDA, dposes=None, adam=None, params=None, loss=None):
+    """One fused tracking iteration of ``len(cams)`` frames (render, tracking
+    loss gradient inside the blend, pose-only backward, optional Adam)."""
+    if isinstance(cams, dict):
+        cams = [cams]
+    V = len(cams)
+    poses = poses.reshape(V, 12)
+    _check_f32("poses", poses)
+    g = gaussians_struct(scene)
+    for v, c in enumerate(cams):
+        _check_f32(f"target_color[{v}]", target_colors[v], (3, int(c["height"]), int(c["width"])))
+        _check_f32(f"target_depth[{v}]", target_depths[v], (int(c["height"]), int(c["width"])))
+    if adam is not None and params is None:
+        params = adam_params()
+    B.cgsr_tracking_step(state.handle, g, V, poses.data_ptr(), [camera_struct(c) for c in cams],
+                         [t.data_ptr() for t in target_colors], [t.data_ptr() for t in target_depths],
+                         float(lam[0]), float(lam[1]), _ptr(dposes), _ptr(adam), params, _ptr(loss), _stream())
+    state.n_views, state.n = V, g.n
+    state.inputs = (scene, poses, target_colors, target_depths)
 
 
 class RasterizeFunction(torch.autograd.Function):
@@ -247,7 +273,7 @@ class TrackingSolver:
     work inside the loop."""
 
     def __init__(self, prob: TrackingProblem, iters: int = 50, pair_margin: float = 1.5, use_graph: bool = True,
-                 reset_pose: torch.Tensor | None = None):
+                 reset_pose: torch.Tensor | None = None, fused: bool = True):
         """reset_pose: if given, every solve (and every graph replay) starts
         from this pose with fresh Adam moments; the reset is part of the graph."""
         self.prob = prob
@@ -271,6 +297,9 @@ class TrackingSolver:
         self.graph = None
         self.use_graph = use_graph
         self.pose0 = None if reset_pose is None else reset_pose.reshape(12).clone()
+        self.fused = fused
+        self.params = adam_params(prob.lr_rho, prob.lr_phi)
+        self.cam_arr = [self.cam_s]
 
     def _reset_on_device(self):
         # elementwise kernels only: a captured graph then holds no memcpy or
@@ -282,14 +311,18 @@ class TrackingSolver:
     def _iteration(self):
         p = self.prob
         s = _stream()
+        if self.fused:
+            B.cgsr_tracking_step(self.state.handle, self.g, 1, self.pose.data_ptr(), self.cam_arr,
+                                 [p.target_color.data_ptr()], [p.target_depth.data_ptr()], float(p.lam[0]),
+                                 float(p.lam[1]), None, self.adam.data_ptr(), self.params, None, s)
+            return
         B.cgsr_render(self.state.handle, self.g, 1, self.pose.data_ptr(), [self.cam_s], None, [self.out_s], s)
         H, W = self.depth.shape
         B.cgsr_tracking_loss_grad(W, H, self.color.data_ptr(), self.depth.data_ptr(), p.target_color.data_ptr(),
                                   p.target_depth.data_ptr(), float(p.lam[0]), float(p.lam[1]),
                                   self.dcolor.data_ptr(), self.ddepth.data_ptr(), None, s)
         B.cgsr_backward(self.state.handle, [self.grad_s], None, self.dpose.data_ptr(), s)
-        B.cgsr_pose_adam_step(1, self.pose.data_ptr(), self.dpose.data_ptr(), self.adam.data_ptr(),
-                              float(p.lr_rho), float(p.lr_phi), 0.9, 0.999, 1e-8, s)
+        B.cgsr_pose_adam_step(1, self.pose.data_ptr(), self.dpose.data_ptr(), self.adam.data_ptr(), self.params, s)
 
     def reset(self, pose0: torch.Tensor):
         self.pose.copy_(pose0.reshape(12))

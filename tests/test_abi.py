@@ -50,8 +50,13 @@ def test_host_side_argument_checks(lib):
     assert lib.cgsr_backward(None, None, None, None, None) == B.CGSR_ERR_INVALID_ARG
     assert lib.cgsr_tracking_loss_grad(0, 10, None, None, None, None, 1.0, 1.0, None, None, None,
                                        None) == B.CGSR_ERR_INVALID_ARG
-    assert lib.cgsr_pose_adam_step(0, None, None, None, 0.1, 0.1, 0.9, 0.999, 1e-8, None) == B.CGSR_ERR_INVALID_ARG
-    assert lib.cgsr_pose_adam_step(1, 8, 8, 8, 0.1, 0.1, 1.5, 0.999, 1e-8, None) == B.CGSR_ERR_INVALID_ARG
+    good = B.cgsr_adam_params(0.1, 0.1, 0.9, 0.999, 1e-8)
+    bad_beta = B.cgsr_adam_params(0.1, 0.1, 1.5, 0.999, 1e-8)
+    assert lib.cgsr_pose_adam_step(0, None, None, None, C.byref(good), None) == B.CGSR_ERR_INVALID_ARG
+    assert lib.cgsr_pose_adam_step(1, 8, 8, 8, C.byref(bad_beta), None) == B.CGSR_ERR_INVALID_ARG
+    assert lib.cgsr_pose_adam_step(1, 8, 8, 8, None, None) == B.CGSR_ERR_INVALID_ARG
+    assert lib.cgsr_tracking_step(None, None, 1, None, None, None, None, 1.0, 1.0, None, None, None, None,
+                                  None) == B.CGSR_ERR_INVALID_ARG
     assert lib.cgsr_state_check(None, None) == B.CGSR_ERR_INVALID_ARG
     assert lib.cgsr_get_stats(None, None, None) == B.CGSR_ERR_INVALID_ARG
     assert lib.cgsr_state_reserve(None, 1, 1, 1, 1) == B.CGSR_ERR_INVALID_ARG

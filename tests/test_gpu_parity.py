@@ -426,6 +426,57 @@ def test_autograd_function_matches_explicit_backward(R, config1):
     assert np.abs(xi.grad.cpu().numpy() - ref["pose"]).max() <= 1e-3 * np.abs(ref["pose"]).max()
 
 
+def test_fused_tracking_step_matches_separate_calls(R):
+    """cgsr_tracking_step (loss gradient formed inside the blend, pose-only
+    backward, Adam) equals render -> tracking_loss_grad -> backward -> Adam."""
+    say("case: fused tracking step vs separate calls, 2 frames")
+    sc = synth.room_scene(4, 30_000, (5.0, 4.0, 3.0))
+    cams = [synth.camera(320, 240, 262.5, 262.5, 160, 120), synth.camera(160, 128, 131.25, 131.25, 80, 64)]
+    scd = dev(sc)
+    tgt_poses = [synth.level_room_pose(s) for s in (21, 22)]
+    st = R.State()
+    P_t = torch.stack([R.pose_tensor(*p) for p in tgt_poses])
+    tg = R.render(st, scd, P_t, cams)
+    tc = [t["color"].clone() for t in tg]
+    td = [t["depth"].clone() for t in tg]
+    P0 = torch.stack([R.pose_tensor(*synth.perturb_pose(*p, 30 + k)) for k, p in enumerate(tgt_poses)])
+    # separate calls
+    Ps, adam_s = P0.clone(), torch.zeros((2, 16), device="cuda")
+    losses_sep = []
+    for it in range(3):
+        outs = R.render(st, scd, Ps, cams, maps=("color", "depth"))
+        dimgs, Ls = [], []
+        for v in range(2):
+            L = torch.zeros(1, device="cuda")
+            dc, dd = R.tracking_loss_grad(outs[v]["color"], outs[v]["depth"], tc[v], td[v], loss=L)
+            dimgs.append(dict(color=dc, depth=dd))
+            Ls.append(L.item())
+        _, dp = R.backward(st, dimgs, param_grads=False)
+        R.pose_adam_step(Ps, dp, adam_s)
+        losses_sep.append(Ls)
+    # fused
+    Pf, adam_f = P0.clone(), torch.zeros((2, 16), device="cuda")
+    losses_fused = []
+    for it in range(3):
+        L = torch.zeros(2, device="cuda")
+        R.tracking_step(st, scd, Pf, cams, tc, td, adam=adam_f, loss=L)
+        losses_fused.append(L.cpu().tolist())
+    torch.cuda.synchronize()
+    say("losses separate", losses_sep, "fused", losses_fused)
+    np.testing.assert_allclose(np.array(losses_fused), np.array(losses_sep), rtol=2e-5)
+    assert (Pf - Ps).abs().max().item() < 1e-5
+    # the gradient alone (no Adam) equals the separate backward
+    dposes = torch.zeros((2, 6), device="cuda")
+    R.tracking_step(st, scd, P0, cams, tc, td, dposes=dposes)
+    outs = R.render(st, scd, P0, cams, maps=("color", "depth"))
+    dimgs = [dict(zip(("color", "depth"), R.tracking_loss_grad(outs[v]["color"], outs[v]["depth"], tc[v], td[v])))
+             for v in range(2)]
+    _, dp = R.backward(st, dimgs, param_grads=False)
+    e = ((dposes - dp).abs().max() / dp.abs().max()).item()
+    say("fused vs separate pose gradient", e)
+    assert e < 1e-4
+
+
 def test_graph_tracking_replays_match_eager(R):
     """The captured 50-iteration tracking solve replayed several times, with
     eager work in between, matches the same loop run eagerly."""
