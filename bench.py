@@ -112,6 +112,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stage-timing", action="store_true")
+    ap.add_argument("--eager", action="store_true",
+                    help="run the solves without graph capture (same kernels; for counter collection)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="only run a plain device copy of this many MB, 10 times (profiler byte-counter scale)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -126,10 +130,25 @@ def main():
     from paper_2403_16095_amd import synth
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(10):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": n * 4, "copy_calibration_bytes_written": n * 4}))
+        return
     log("building workload: 100k Gaussians, 640x480")
     sc, prob, P0, true_pose = build_workload(torch, R, synth)
     iters = args.solve_iters
-    solver = R.TrackingSolver(prob, iters=iters, use_graph=True, reset_pose=P0)
+    tune_state = R.State()
+    fppl, bppl = R.autotune_tracking(tune_state, prob.scene, P0, [prob.cam], [prob.target_color],
+                                     [prob.target_depth])
+    del tune_state
+    log(f"autotuned pixels per lane: forward {fppl}, backward {bppl}")
+    solver = R.TrackingSolver(prob, iters=iters, use_graph=not args.eager, reset_pose=P0, fwd_ppl=fppl,
+                              bwd_ppl=bppl)
     solver.prepare(P0)
     solves_w = max(1, math.ceil(args.warmup / iters))
     solves = max(1, math.ceil(args.steps / iters))
@@ -163,7 +182,7 @@ def main():
     # launch stream, over eager iterations of the same workload.
     stages, stats = {}, None
     if not args.no_stage_timing:
-        tst = R.State(timing=True)
+        tst = R.State(timing=True, fwd_ppl=fppl, bwd_ppl=bppl)
         tst.reserve(pairs=solver.state.stats().pairs * 2)
         pose = P0.clone().reshape(1, 12)
         acc = {}
@@ -199,6 +218,7 @@ def main():
                                "render + L1 colour/depth loss + pose-only backward + Adam, 50-iteration "
                                "solves replayed from one HIP graph",
                    "gaussians": 100_000, "width": 640, "height": 480, "solve_iters": iters,
+                   "pixels_per_lane": {"forward": fppl, "backward": bppl},
                    "loss_lambda": list(R.TRACK_LAMBDA)},
     }
     if stages:

@@ -91,6 +91,10 @@ typedef struct {
     int32_t timing;          /* 1: time every stage with HIP events on the call's
                                 stream (not while it is being captured); read
                                 the durations with cgsr_get_timings()            */
+    int32_t fwd_pixels_per_lane; /* 1, 2 or 4 pixels per lane in the forward blend:
+                                a 16x16 tile then takes 256 / that many lanes   */
+    int32_t bwd_pixels_per_lane; /* same for the backward blend; each lane sums its
+                                pixels before the per-Gaussian wave reduction   */
 } cgsr_settings;
 
 typedef struct {
@@ -181,6 +185,19 @@ cgsr_status cgsr_tracking_loss_grad(int32_t width, int32_t height, const float *
                                     float lambda_depth, float *dcolor, float *ddepth, float *loss,
                                     void *stream);
 
+/*
+ * Gradient images of the mapping objective of the 1200x680 workload:
+ *   L = L_color (Eq. 14) + mean_n U_n |D^_n - D_n|
+ * (Eq. 16's depth error weighted per pixel by the rendered uncertainty U of
+ * Eq. 10; the gradient flows through both factors).  Writes dL/dcolor
+ * [3][H][W], dL/ddepth and dL/duncertainty [H][W] (device, overwritten) and
+ * adds L to *loss (device float) if loss is non-NULL.
+ */
+cgsr_status cgsr_mapping_loss_grad(int32_t width, int32_t height, const float *color, const float *depth,
+                                   const float *uncertainty, const float *target_color,
+                                   const float *target_depth, float *dcolor, float *ddepth,
+                                   float *duncertainty, float *loss, void *stream);
+
 /* Adam hyper-parameters of the pose update; the paper uses learning rates
  * 0.0015 for the rotation (so(3)) part and 0.00215 for the translation part
  * (Sec. 4, Implementation Details).  beta1, beta2, eps as in Adam. */
@@ -220,6 +237,19 @@ cgsr_status cgsr_tracking_step(cgsr_state *st, const cgsr_gaussians *g, int32_t 
                                const float *const *target_depth, float lambda_color, float lambda_depth,
                                float *dposes, float *adam, const cgsr_adam_params *adam_params,
                                float *loss, void *stream);
+
+/*
+ * Autotuner: picks the blend kernels' pixels per lane (1, 2 or 4, forward and
+ * backward independently) for a tracking workload by timing
+ * cgsr_tracking_step on it with each candidate (HIP events on the stream,
+ * `repeats` timed runs after one warm-up, no Adam step, poses unchanged),
+ * stores the fastest in the state's settings and returns them in *out (may
+ * be NULL).  Synchronises; not for use under graph capture.
+ */
+cgsr_status cgsr_autotune_tracking(cgsr_state *st, const cgsr_gaussians *g, int32_t n_views, const float *poses,
+                                   const cgsr_camera *cams, const float *const *target_color,
+                                   const float *const *target_depth, int32_t repeats, cgsr_settings *out,
+                                   void *stream);
 
 /* Synchronise the stream and report CGSR_ERR_CAPACITY if the last render on
  * this state overflowed its pair buffer. */

@@ -27,8 +27,10 @@ STATUS_NAMES = {0: "CGSR_OK", -1: "CGSR_ERR_INVALID_ARG", -2: "CGSR_ERR_OOM", -3
 
 EXPORTED = (
     "cgsr_default_settings", "cgsr_state_create", "cgsr_state_destroy", "cgsr_state_reserve",
-    "cgsr_render", "cgsr_backward", "cgsr_tracking_loss_grad", "cgsr_pose_adam_step", "cgsr_tracking_step",
-    "cgsr_state_check", "cgsr_get_stats", "cgsr_get_timings", "cgsr_debug_buffers", "cgsr_last_error",
+    "cgsr_render", "cgsr_backward", "cgsr_tracking_loss_grad", "cgsr_mapping_loss_grad", "cgsr_pose_adam_step",
+    "cgsr_tracking_step",
+    "cgsr_autotune_tracking", "cgsr_state_check", "cgsr_get_stats", "cgsr_get_timings", "cgsr_debug_buffers",
+    "cgsr_last_error",
     "cgsr_version",
 )
 STAGES = ("project", "emit", "sort", "blend_fwd", "blend_bwd", "project_bwd")
@@ -64,7 +66,8 @@ class cgsr_gaussian_grads(C.Structure):
 
 
 class cgsr_settings(C.Structure):
-    _fields_ = [("sync_capacity", C.c_int32), ("timing", C.c_int32)]
+    _fields_ = [("sync_capacity", C.c_int32), ("timing", C.c_int32), ("fwd_pixels_per_lane", C.c_int32),
+                ("bwd_pixels_per_lane", C.c_int32)]
 
 
 class cgsr_adam_params(C.Structure):
@@ -105,10 +108,13 @@ def lib() -> C.CDLL:
     L.cgsr_backward.argtypes = [vp, C.POINTER(cgsr_images), C.POINTER(cgsr_gaussian_grads), vp, vp]
     L.cgsr_tracking_loss_grad.argtypes = [C.c_int32, C.c_int32, vp, vp, vp, vp, C.c_float, C.c_float, vp, vp,
                                           vp, vp]
+    L.cgsr_mapping_loss_grad.argtypes = [C.c_int32, C.c_int32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.cgsr_pose_adam_step.argtypes = [C.c_int32, vp, vp, vp, C.POINTER(cgsr_adam_params), vp]
     L.cgsr_tracking_step.argtypes = [vp, C.POINTER(cgsr_gaussians), C.c_int32, vp, C.POINTER(cgsr_camera),
                                      C.POINTER(vp), C.POINTER(vp), C.c_float, C.c_float, vp, vp,
                                      C.POINTER(cgsr_adam_params), vp, vp]
+    L.cgsr_autotune_tracking.argtypes = [vp, C.POINTER(cgsr_gaussians), C.c_int32, vp, C.POINTER(cgsr_camera),
+                                         C.POINTER(vp), C.POINTER(vp), C.c_int32, C.POINTER(cgsr_settings), vp]
     L.cgsr_state_check.argtypes = [vp, vp]
     L.cgsr_get_stats.argtypes = [vp, vp, C.POINTER(cgsr_stats)]
     L.cgsr_get_timings.argtypes = [vp, C.POINTER(C.c_float)]
@@ -171,6 +177,12 @@ def cgsr_tracking_loss_grad(width, height, color, depth, target_color, target_de
                                          lambda_depth, dcolor, ddepth, loss, stream))
 
 
+def cgsr_mapping_loss_grad(width, height, color, depth, uncertainty, target_color, target_depth, dcolor, ddepth,
+                           duncertainty, loss, stream) -> None:
+    _check(lib().cgsr_mapping_loss_grad(width, height, color, depth, uncertainty, target_color, target_depth, dcolor,
+                                        ddepth, duncertainty, loss, stream))
+
+
 def cgsr_pose_adam_step(n_views, poses, dposes, adam, params: cgsr_adam_params, stream) -> None:
     _check(lib().cgsr_pose_adam_step(n_views, poses, dposes, adam, C.byref(params), stream))
 
@@ -183,6 +195,17 @@ def cgsr_tracking_step(state: int, g: cgsr_gaussians, n_views: int, poses: int, 
     td = (C.c_void_p * n_views)(*target_depth)
     _check(lib().cgsr_tracking_step(state, C.byref(g), n_views, poses, cam_arr, tc, td, lambda_color, lambda_depth,
                                     dposes, adam, C.byref(params) if params is not None else None, loss, stream))
+
+
+def cgsr_autotune_tracking(state: int, g: cgsr_gaussians, n_views: int, poses: int, cams, target_color,
+                           target_depth, repeats: int, stream: int) -> cgsr_settings:
+    cam_arr = (cgsr_camera * n_views)(*cams)
+    tc = (C.c_void_p * n_views)(*target_color)
+    td = (C.c_void_p * n_views)(*target_depth)
+    out = cgsr_settings()
+    _check(lib().cgsr_autotune_tracking(state, C.byref(g), n_views, poses, cam_arr, tc, td, repeats, C.byref(out),
+                                        stream))
+    return out
 
 
 def cgsr_state_check(state: int, stream: int) -> None:

@@ -80,6 +80,7 @@ struct cgsr_state {
   uint32_t* pixel_count = nullptr;
   float4* pixel_grad = nullptr;
   // small buffers
+  float* tune_dposes = nullptr;   // [64][6] scratch pose gradients of the autotuner
   uint32_t* counters = nullptr;
   double* pose_acc = nullptr;
   unsigned long long* stats_dev = nullptr;
@@ -251,6 +252,8 @@ void cgsr_default_settings(cgsr_settings* s) {
   if (!s) return;
   s->sync_capacity = 1;
   s->timing = 0;
+  s->fwd_pixels_per_lane = 1;
+  s->bwd_pixels_per_lane = 1;
 }
 
 cgsr_status cgsr_state_create(const cgsr_settings* s, cgsr_state** out) {
@@ -260,10 +263,13 @@ cgsr_status cgsr_state_create(const cgsr_settings* s, cgsr_state** out) {
   if (!st) return fail(CGSR_ERR_OOM, "cgsr_state_create: host allocation failed");
   if (s) st->settings = *s;
   else cgsr_default_settings(&st->settings);
+  auto ppl_ok = [](int32_t p) { return p == 1 || p == 2 || p == 4; };
   if (st->settings.sync_capacity < 0 || st->settings.sync_capacity > 1 || st->settings.timing < 0 ||
-      st->settings.timing > 1) {
+      st->settings.timing > 1 || !ppl_ok(st->settings.fwd_pixels_per_lane) ||
+      !ppl_ok(st->settings.bwd_pixels_per_lane)) {
     delete st;
-    return fail(CGSR_ERR_INVALID_ARG, "settings: sync_capacity and timing must be 0 or 1");
+    return fail(CGSR_ERR_INVALID_ARG,
+                "settings: sync_capacity and timing must be 0 or 1, pixels per lane 1, 2 or 4");
   }
   cgsr_status r = CGSR_OK;
   hipError_t e = hipGetDevice(&st->device);
@@ -283,6 +289,7 @@ cgsr_status cgsr_state_create(const cgsr_settings* s, cgsr_state** out) {
       r = fail(CGSR_ERR_HIP, "hipEventCreate failed");
   }
   if (!r) r = dev_alloc(&st->stats_dev, 4);
+  if (!r) r = dev_alloc(&st->tune_dposes, 6 * CGSR_MAX_VIEWS);
   for (auto& ev : st->ev_fwd)
     if (!r && hipEventCreate(&ev) != hipSuccess) r = fail(CGSR_ERR_HIP, "hipEventCreate failed");
   for (auto& ev : st->ev_bwd)
@@ -319,6 +326,7 @@ cgsr_status cgsr_state_destroy(cgsr_state* st) {
   dev_free(st->counters);
   dev_free(st->pose_acc);
   dev_free(st->stats_dev);
+  dev_free(st->tune_dposes);
   for (int k = 0; k < 2; ++k) {
     dev_free(st->io[k].dev);
     if (st->io[k].pinned) (void)hipHostFree(st->io[k].pinned);
@@ -474,7 +482,7 @@ cgsr_status render_impl(cgsr_state* st, const RenderArgs& a, hipStream_t stream)
   rb.lambda_color = a.lambda_color;
   rb.lambda_depth = a.lambda_depth;
   rb.loss = a.loss;
-  launch_raster_forward(rb, a.track, stream);
+  launch_raster_forward(rb, a.track, st->settings.fwd_pixels_per_lane, stream);
   HIP_TRY(hipGetLastError());
   if ((s = mark(CGSR_STAGE_BLEND_FWD + 1))) return s;
   st->fwd_timed = timed;
@@ -492,7 +500,7 @@ cgsr_status backward_impl(cgsr_state* st, int slot, bool params, bool track, con
   st->bwd_timed = false;
   if (timed) HIP_TRY(hipEventRecord(st->ev_bwd[0], stream));
   const RasterBufs rb = raster_bufs(st, slot);
-  launch_raster_backward(rb, params, track, stream);
+  launch_raster_backward(rb, params, track, st->settings.bwd_pixels_per_lane, stream);
   if (timed) HIP_TRY(hipEventRecord(st->ev_bwd[1], stream));
   launch_project_backward(st->g, st->poses, rb.views, st->rec_grad, st->tiles, gp, params, st->pose_acc, dposes, step,
                           stream);
@@ -593,6 +601,54 @@ cgsr_status cgsr_tracking_step(cgsr_state* st, const cgsr_gaussians* g, int32_t 
   return backward_impl(st, 0, false, true, GradPtrs{}, dposes, adam ? &step : nullptr, stream);
 }
 
+cgsr_status cgsr_autotune_tracking(cgsr_state* st, const cgsr_gaussians* g, int32_t n_views, const float* poses,
+                                   const cgsr_camera* cams, const float* const* target_color,
+                                   const float* const* target_depth, int32_t repeats, cgsr_settings* out,
+                                   void* stream_) {
+  hipStream_t stream = (hipStream_t)stream_;
+  if (!st) return fail(CGSR_ERR_INVALID_ARG, "cgsr_autotune_tracking: NULL state");
+  if (repeats < 1 || repeats > 1000) return fail(CGSR_ERR_INVALID_ARG, "cgsr_autotune_tracking: repeats in [1, 1000]");
+  hipStreamCaptureStatus capturing = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(stream, &capturing));
+  if (capturing != hipStreamCaptureStatusNone)
+    return fail(CGSR_ERR_STATE, "cgsr_autotune_tracking: not under graph capture");
+  const cgsr_settings saved = st->settings;
+  st->settings.timing = 1;
+  const int32_t cand[3] = {1, 2, 4};
+  float best_f = 1e30f, best_b = 1e30f;
+  int32_t pick_f = saved.fwd_pixels_per_lane, pick_b = saved.bwd_pixels_per_lane;
+  cgsr_status s = CGSR_OK;
+  for (int c = 0; c < 3 && !s; ++c) {
+    st->settings.fwd_pixels_per_lane = cand[c];
+    st->settings.bwd_pixels_per_lane = cand[c];
+    float sum_f = 0.f, sum_b = 0.f;
+    for (int r = 0; r <= repeats && !s; ++r) {
+      s = cgsr_tracking_step(st, g, n_views, const_cast<float*>(poses), cams, target_color, target_depth, 1.f, 1.f,
+                             st->tune_dposes, nullptr, nullptr, nullptr, stream);
+      float ms[CGSR_NUM_STAGES];
+      if (!s) s = cgsr_get_timings(st, ms);
+      if (!s && r > 0) {
+        sum_f += ms[CGSR_STAGE_BLEND_FWD];
+        sum_b += ms[CGSR_STAGE_BLEND_BWD];
+      }
+    }
+    if (!s && sum_f < best_f) {
+      best_f = sum_f;
+      pick_f = cand[c];
+    }
+    if (!s && sum_b < best_b) {
+      best_b = sum_b;
+      pick_b = cand[c];
+    }
+  }
+  st->settings = saved;
+  if (s) return s;
+  st->settings.fwd_pixels_per_lane = pick_f;
+  st->settings.bwd_pixels_per_lane = pick_b;
+  if (out) *out = st->settings;
+  return CGSR_OK;
+}
+
 cgsr_status cgsr_tracking_loss_grad(int32_t width, int32_t height, const float* color, const float* depth,
                                     const float* target_color, const float* target_depth, float lambda_color,
                                     float lambda_depth, float* dcolor, float* ddepth, float* loss, void* stream) {
@@ -601,6 +657,18 @@ cgsr_status cgsr_tracking_loss_grad(int32_t width, int32_t height, const float* 
     return fail(CGSR_ERR_INVALID_ARG, "tracking loss: NULL argument");
   launch_tracking_loss(width, height, color, depth, target_color, target_depth, lambda_color, lambda_depth, dcolor,
                        ddepth, loss, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return CGSR_OK;
+}
+
+cgsr_status cgsr_mapping_loss_grad(int32_t width, int32_t height, const float* color, const float* depth,
+                                   const float* uncertainty, const float* target_color, const float* target_depth,
+                                   float* dcolor, float* ddepth, float* duncertainty, float* loss, void* stream) {
+  if (width < 1 || height < 1) return fail(CGSR_ERR_INVALID_ARG, "mapping loss: empty image");
+  if (!color || !depth || !uncertainty || !target_color || !target_depth || !dcolor || !ddepth || !duncertainty)
+    return fail(CGSR_ERR_INVALID_ARG, "mapping loss: NULL argument");
+  launch_mapping_loss(width, height, color, depth, uncertainty, target_color, target_depth, dcolor, ddepth,
+                      duncertainty, loss, (hipStream_t)stream);
   HIP_TRY(hipGetLastError());
   return CGSR_OK;
 }

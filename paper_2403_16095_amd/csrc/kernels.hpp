@@ -91,12 +91,16 @@ struct RasterBufs {
   float lambda_color, lambda_depth;  // tracking loss weights (Eq. 19)
   float* loss;              // [views] tracking loss (+=) or null
 };
-void launch_raster_forward(const RasterBufs& b, bool track, hipStream_t s);
-void launch_raster_backward(const RasterBufs& b, bool param_grads, bool track, hipStream_t s);
+// ppl: pixels per lane, 1, 2 or 4 (256 / ppl lanes per 16x16 tile).
+void launch_raster_forward(const RasterBufs& b, bool track, int ppl, hipStream_t s);
+void launch_raster_backward(const RasterBufs& b, bool param_grads, bool track, int ppl, hipStream_t s);
 
 void launch_tracking_loss(int w, int h, const float* color, const float* depth, const float* tcolor,
                           const float* tdepth, float lc, float ld, float* dcolor, float* ddepth, float* loss,
                           hipStream_t s);
+void launch_mapping_loss(int w, int h, const float* color, const float* depth, const float* unc,
+                         const float* tcolor, const float* tdepth, float* dcolor, float* ddepth, float* dunc,
+                         float* loss, hipStream_t s);
 void launch_pose_adam(int n_views, float* poses, float* dposes, float* adam, const AdamParams& ap, hipStream_t s);
 
 // Statistics: visible records, alpha evaluations, blended pairs, walked entries.

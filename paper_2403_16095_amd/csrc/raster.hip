@@ -1,11 +1,13 @@
 // Tile blending, forward (Sec. 3.1 Eq. 3-9, Sec. 3.2 Eq. 10) and backward.
 //
-// One 256-lane workgroup per 16x16 tile, one pixel per lane; each wave owns
-// an 8x8 quadrant so its lanes see nearby pixels and leave together.  The
-// tile's depth-ordered records are staged through LDS 256 at a time (see
-// stage_record); every lane then reads the same LDS address, a broadcast free
-// of bank conflicts.  A pair below the skip threshold costs one base-2
-// exponent and a compare; only blended pairs evaluate exp2.
+// One workgroup per 16x16 tile.  A lane owns kPPL pixels (1, 2 or 4), so a
+// tile takes 256 / kPPL lanes; pixel q of the tile lies in the 8x8 quadrant
+// q / 64, and lane t owns pixels t, t + L, t + 2L, ... (L lanes), so a wave's
+// pixels are whole quadrants and leave together.  The tile's depth-ordered
+// records are staged through LDS 256 at a time (see stage_record); every lane
+// then reads the same LDS address, a broadcast free of bank conflicts, and
+// uses it for all of its pixels.  A pair below the skip threshold costs one
+// base-2 exponent and a compare; only blended pairs evaluate exp2.
 //
 // Tracking mode (kTrack) forms the gradient images of the tracking loss
 // (Eq. 19: L1 colour, Eq. 14, and L1 depth, Eq. 16) at the end of the
@@ -16,7 +18,6 @@
 namespace cgsr {
 namespace {
 
-constexpr int kThreads = kTilePixels;
 constexpr int kBatch = 256;
 
 struct PixelCoord {
@@ -24,10 +25,11 @@ struct PixelCoord {
   bool inside;
 };
 
-__device__ __forceinline__ PixelCoord pixel_of_lane(const ViewInfo& cam, int gtile) {
+// Pixel q (0..255) of tile gtile: quadrant q / 64, row-major 8x8 inside it.
+__device__ __forceinline__ PixelCoord pixel_of(const ViewInfo& cam, int gtile, int q) {
   const int lt = gtile - cam.tile_base;
   const int tx = lt % cam.tiles_x, ty = lt / cam.tiles_x;
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int w = q >> 6, l = q & 63;
   PixelCoord c;
   c.px = tx * kTile + (w & 1) * 8 + (l & 7);
   c.py = ty * kTile + (w >> 1) * 8 + (l >> 3);
@@ -37,8 +39,9 @@ __device__ __forceinline__ PixelCoord pixel_of_lane(const ViewInfo& cam, int gti
 
 __device__ __forceinline__ float sgn(float x) { return (float)((x > 0.f) - (x < 0.f)); }
 
-template <bool kTrack>
-__global__ __launch_bounds__(kThreads) void raster_forward_kernel(RasterBufs b) {
+template <int kPPL, bool kTrack>
+__global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(RasterBufs b) {
+  constexpr int L = kTilePixels / kPPL;
   __shared__ float4 sA[kBatch];
   __shared__ float4 sB[kBatch];
   __shared__ float4 sC[kBatch];
@@ -46,100 +49,137 @@ __global__ __launch_bounds__(kThreads) void raster_forward_kernel(RasterBufs b) 
   const int v = view_of_tile(b.views, gtile);
   const ViewIO io = b.views.io[v];
   const ViewInfo cam = io.info;
-  const PixelCoord pc = pixel_of_lane(cam, gtile);
-  const int64_t pix = (int64_t)pc.py * cam.width + pc.px;
-  const float dobs = (io.depth_obs && pc.inside) ? io.depth_obs[pix] : 0.f;
   const uint2 range = b.ranges[gtile];
-  const float fx = (float)pc.px, fy = (float)pc.py;
+  const int64_t hw = (int64_t)cam.width * cam.height;
 
-  float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f, O = 0.f, U = 0.f, Dmed = 0.f;
-  int med = -1;
-  uint32_t last = 0, evaluated = range.y - range.x, blended = 0;
-  bool done = !pc.inside;
+  float fx[kPPL], fy[kPPL], dobs[kPPL], T[kPPL], C0[kPPL], C1[kPPL], C2[kPPL], D[kPPL], O[kPPL], U[kPPL],
+      Dmed[kPPL];
+  int64_t pix[kPPL];
+  int med[kPPL];
+  uint32_t last[kPPL], evaluated[kPPL], blended[kPPL];
+  bool inside[kPPL], done[kPPL];
+  bool lane_done = true;
+#pragma unroll
+  for (int k = 0; k < kPPL; ++k) {
+    const PixelCoord pc = pixel_of(cam, gtile, k * L + threadIdx.x);
+    fx[k] = (float)pc.px;
+    fy[k] = (float)pc.py;
+    inside[k] = pc.inside;
+    pix[k] = (int64_t)pc.py * cam.width + pc.px;
+    dobs[k] = (!kTrack && io.depth_obs && pc.inside) ? io.depth_obs[pix[k]] : 0.f;
+    T[k] = 1.f;
+    C0[k] = C1[k] = C2[k] = D[k] = O[k] = U[k] = Dmed[k] = 0.f;
+    med[k] = -1;
+    last[k] = 0;
+    blended[k] = 0;
+    evaluated[k] = range.y - range.x;
+    done[k] = !pc.inside;
+    lane_done = lane_done && done[k];
+  }
   for (uint32_t base = range.x; base < range.y; base += kBatch) {
     const int n = (int)min((uint32_t)kBatch, range.y - base);
     __syncthreads();
-    if ((int)threadIdx.x < n) {
-      const uint32_t m = b.vals[base + threadIdx.x];
-      stage_record(b.rec + (int64_t)kRecF4 * m, sA[threadIdx.x], sB[threadIdx.x], sC[threadIdx.x]);
+    for (int i = threadIdx.x; i < n; i += L) {
+      const uint32_t m = b.vals[base + i];
+      stage_record(b.rec + (int64_t)kRecF4 * m, sA[i], sB[i], sC[i]);
     }
     __syncthreads();
-    if (!done) {
+    if (!lane_done) {
       const uint32_t off = base - range.x;
       for (int j = 0; j < n; ++j) {
         const float4 A = sA[j];
         const float4 B = sB[j];
-        float dx, dy;
-        const float e = pair_exponent(A, B, fx, fy, dx, dy);
-        if (e < B.w) continue;
-        const float alpha = fminf(kAlphaMax, B.y * __builtin_amdgcn_exp2f(e));
-        const float Tn = T * (1.f - alpha);
-        if (Tn < kTStop) {
-          done = true;
-          evaluated = off + j + 1;
+#pragma unroll
+        for (int k = 0; k < kPPL; ++k) {
+          if (done[k]) continue;
+          float dx, dy;
+          const float e = pair_exponent(A, B, fx[k], fy[k], dx, dy);
+          if (e < B.w) continue;
+          const float alpha = fminf(kAlphaMax, B.y * __builtin_amdgcn_exp2f(e));
+          const float Tn = T[k] * (1.f - alpha);
+          if (Tn < kTStop) {
+            done[k] = true;
+            evaluated[k] = off + j + 1;
+            continue;
+          }
+          const float wgt = alpha * T[k];
+          const float4 Cc = sC[j];
+          C0[k] = __builtin_fmaf(wgt, Cc.x, C0[k]);
+          C1[k] = __builtin_fmaf(wgt, Cc.y, C1[k]);
+          C2[k] = __builtin_fmaf(wgt, Cc.z, C2[k]);
+          D[k] = __builtin_fmaf(wgt, B.z, D[k]);
+          O[k] += wgt;
+          if (!kTrack) {
+            const float dz = B.z - dobs[k];
+            U[k] = __builtin_fmaf(wgt * dz, dz, U[k]);
+          }
+          if (med[k] < 0 && Tn < kTMedian) {
+            med[k] = (int)(off + j);
+            Dmed[k] = B.z;
+          }
+          T[k] = Tn;
+          last[k] = off + j + 1;
+          ++blended[k];
+        }
+        bool all = true;
+#pragma unroll
+        for (int k = 0; k < kPPL; ++k) all = all && done[k];
+        if (all) {
+          lane_done = true;
           break;
         }
-        const float wgt = alpha * T;
-        const float4 Cc = sC[j];
-        C0 = __builtin_fmaf(wgt, Cc.x, C0);
-        C1 = __builtin_fmaf(wgt, Cc.y, C1);
-        C2 = __builtin_fmaf(wgt, Cc.z, C2);
-        D = __builtin_fmaf(wgt, B.z, D);
-        O += wgt;
-        if (!kTrack) {
-          const float dz = B.z - dobs;
-          U = __builtin_fmaf(wgt * dz, dz, U);
-        }
-        if (med < 0 && Tn < kTMedian) {
-          med = (int)(off + j);
-          Dmed = B.z;
-        }
-        T = Tn;
-        last = off + j + 1;
-        ++blended;
       }
     }
-    if (__syncthreads_count(done) == kThreads) break;
+    if (__syncthreads_count(lane_done) == L) break;
   }
-  const int64_t hw = (int64_t)cam.width * cam.height;
   if (kTrack) {
     // dL/dcolour and dL/ddepth of L = lc mean_n |I^ - I|_1 + ld mean_n |D^ - D|.
     float l = 0.f;
-    if (pc.inside) {
-      const float inv = 1.0f / (float)hw;
-      const float e0 = C0 - io.t_color[pix], e1 = C1 - io.t_color[hw + pix], e2 = C2 - io.t_color[2 * hw + pix];
-      const float ed = D - io.t_depth[pix];
-      const float lc = b.lambda_color * inv, ld = b.lambda_depth * inv;
-      b.pixel_grad[cam.pixel_base + pix] = make_float4(lc * sgn(e0), lc * sgn(e1), lc * sgn(e2), ld * sgn(ed));
-      l = lc * (fabsf(e0) + fabsf(e1) + fabsf(e2)) + ld * fabsf(ed);
+    const float inv = 1.0f / (float)hw;
+    const float lc = b.lambda_color * inv, ld = b.lambda_depth * inv;
+#pragma unroll
+    for (int k = 0; k < kPPL; ++k) {
+      if (!inside[k]) continue;
+      const int64_t p = pix[k];
+      const float e0 = C0[k] - io.t_color[p], e1 = C1[k] - io.t_color[hw + p], e2 = C2[k] - io.t_color[2 * hw + p];
+      const float ed = D[k] - io.t_depth[p];
+      b.pixel_grad[cam.pixel_base + p] = make_float4(lc * sgn(e0), lc * sgn(e1), lc * sgn(e2), ld * sgn(ed));
+      l += lc * (fabsf(e0) + fabsf(e1) + fabsf(e2)) + ld * fabsf(ed);
     }
     if (b.loss) {
       const float t = wave_sum(l);
       if ((threadIdx.x & 63) == 0 && t != 0.f) atomicAdd(b.loss + v, t);
     }
   }
-  if (!pc.inside) return;
-  if (io.color) {
-    io.color[pix] = C0;
-    io.color[hw + pix] = C1;
-    io.color[2 * hw + pix] = C2;
+#pragma unroll
+  for (int k = 0; k < kPPL; ++k) {
+    if (!inside[k]) continue;
+    const int64_t p = pix[k];
+    if (io.color) {
+      io.color[p] = C0[k];
+      io.color[hw + p] = C1[k];
+      io.color[2 * hw + p] = C2[k];
+    }
+    if (io.depth) io.depth[p] = D[k];
+    if (io.opacity) io.opacity[p] = O[k];
+    if (io.depth_median) io.depth_median[p] = Dmed[k];
+    if (io.uncertainty) io.uncertainty[p] = U[k];
+    b.pixel_state[cam.pixel_base + p] = make_uint4(__float_as_uint(T[k]), last[k], (uint32_t)med[k], evaluated[k]);
+    b.pixel_count[cam.pixel_base + p] = blended[k];
   }
-  if (io.depth) io.depth[pix] = D;
-  if (io.opacity) io.opacity[pix] = O;
-  if (io.depth_median) io.depth_median[pix] = Dmed;
-  if (io.uncertainty) io.uncertainty[pix] = U;
-  b.pixel_state[cam.pixel_base + pix] = make_uint4(__float_as_uint(T), last, (uint32_t)med, evaluated);
-  b.pixel_count[cam.pixel_base + pix] = blended;
 }
 
 // Back-to-front over each pixel's blended run.  With the normalised "behind"
 // sums Bx = sum_{k>j} w_k x_k / T_{j+1}, dL/dalpha_j = T_j sum_x g_x (x_j - Bx),
 // and Bx <- alpha_j x_j + (1 - alpha_j) Bx moves the sums one Gaussian forward;
 // T_j = T_{j+1} / (1 - alpha_j) recovers the transmittance from the final one.
-// kParams adds the opacity and colour gradients (mapping); kTrack takes the
-// upstream gradients from the tracking forward (colour and depth only).
-template <bool kParams, bool kTrack>
-__global__ __launch_bounds__(kThreads) void raster_backward_kernel(RasterBufs b) {
+// A lane first sums its pixels' contributions to a Gaussian, then the wave
+// reduces them (DPP) and issues one multi-lane atomic.  kParams adds the
+// opacity and colour gradients (mapping); kTrack takes the upstream
+// gradients from the tracking forward (colour and depth only).
+template <int kPPL, bool kParams, bool kTrack>
+__global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(RasterBufs b) {
+  constexpr int L = kTilePixels / kPPL;
   __shared__ float4 sA[kBatch];
   __shared__ float4 sB[kBatch];
   __shared__ float4 sC[kBatch];
@@ -149,109 +189,123 @@ __global__ __launch_bounds__(kThreads) void raster_backward_kernel(RasterBufs b)
   const int v = view_of_tile(b.views, gtile);
   const ViewIO io = b.views.io[v];
   const ViewInfo cam = io.info;
-  const PixelCoord pc = pixel_of_lane(cam, gtile);
-  const int64_t pix = (int64_t)pc.py * cam.width + pc.px;
   const int64_t hw = (int64_t)cam.width * cam.height;
   const uint2 range = b.ranges[gtile];
   const int lane = threadIdx.x & 63;
 
-  float T = 1.f;
-  uint32_t walked = 0;
-  int med = -1;
-  float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, gd = 0.f, go = 0.f, gm = 0.f, gu = 0.f, dobs = 0.f;
-  if (pc.inside) {
-    const uint4 ps = b.pixel_state[cam.pixel_base + pix];
-    T = __uint_as_float(ps.x);
-    walked = ps.y;
-    med = (int)ps.z;
-    if (kTrack) {
-      const float4 g4 = b.pixel_grad[cam.pixel_base + pix];
-      gc0 = g4.x;
-      gc1 = g4.y;
-      gc2 = g4.z;
-      gd = g4.w;
-    } else {
-      if (io.g_color) {
-        gc0 = io.g_color[pix];
-        gc1 = io.g_color[hw + pix];
-        gc2 = io.g_color[2 * hw + pix];
+  float fx[kPPL], fy[kPPL], T[kPPL], gc0[kPPL], gc1[kPPL], gc2[kPPL], gd[kPPL], go[kPPL], gm[kPPL], gu[kPPL],
+      dobs[kPPL];
+  float Bc0[kPPL], Bc1[kPPL], Bc2[kPPL], Bd[kPPL], Bo[kPPL], Bu[kPPL];
+  int walked[kPPL], med[kPPL];
+  uint32_t lane_max = 0;
+#pragma unroll
+  for (int k = 0; k < kPPL; ++k) {
+    const PixelCoord pc = pixel_of(cam, gtile, k * L + threadIdx.x);
+    const int64_t pix = (int64_t)pc.py * cam.width + pc.px;
+    fx[k] = (float)pc.px;
+    fy[k] = (float)pc.py;
+    T[k] = 1.f;
+    walked[k] = 0;
+    med[k] = -1;
+    gc0[k] = gc1[k] = gc2[k] = gd[k] = go[k] = gm[k] = gu[k] = dobs[k] = 0.f;
+    Bc0[k] = Bc1[k] = Bc2[k] = Bd[k] = Bo[k] = Bu[k] = 0.f;
+    if (pc.inside) {
+      const uint4 ps = b.pixel_state[cam.pixel_base + pix];
+      T[k] = __uint_as_float(ps.x);
+      walked[k] = (int)ps.y;
+      med[k] = (int)ps.z;
+      if (kTrack) {
+        const float4 g4 = b.pixel_grad[cam.pixel_base + pix];
+        gc0[k] = g4.x;
+        gc1[k] = g4.y;
+        gc2[k] = g4.z;
+        gd[k] = g4.w;
+      } else {
+        if (io.g_color) {
+          gc0[k] = io.g_color[pix];
+          gc1[k] = io.g_color[hw + pix];
+          gc2[k] = io.g_color[2 * hw + pix];
+        }
+        if (io.g_depth) gd[k] = io.g_depth[pix];
+        if (io.g_opacity) go[k] = io.g_opacity[pix];
+        if (io.g_median) gm[k] = io.g_median[pix];
+        if (io.g_uncertainty) gu[k] = io.g_uncertainty[pix];
+        if (io.depth_obs) dobs[k] = io.depth_obs[pix];
       }
-      if (io.g_depth) gd = io.g_depth[pix];
-      if (io.g_opacity) go = io.g_opacity[pix];
-      if (io.g_median) gm = io.g_median[pix];
-      if (io.g_uncertainty) gu = io.g_uncertainty[pix];
-      if (io.depth_obs) dobs = io.depth_obs[pix];
+      lane_max = max(lane_max, (uint32_t)walked[k]);
     }
   }
   if (threadIdx.x == 0) s_max = 0u;
   __syncthreads();
-  if (walked) atomicMax(&s_max, walked);
+  if (lane_max) atomicMax(&s_max, lane_max);
   __syncthreads();
   const int nmax = (int)s_max;
-  const float fx = (float)pc.px, fy = (float)pc.py;
 
-  float Bc0 = 0.f, Bc1 = 0.f, Bc2 = 0.f, Bd = 0.f, Bo = 0.f, Bu = 0.f;
   for (int end = nmax; end > 0; end -= kBatch) {
     const int start = max(0, end - kBatch);
     const int n = end - start;
     __syncthreads();
-    if ((int)threadIdx.x < n) {
-      const uint32_t m = b.vals[range.x + start + threadIdx.x];
-      sM[threadIdx.x] = m;
-      stage_record(b.rec + (int64_t)kRecF4 * m, sA[threadIdx.x], sB[threadIdx.x], sC[threadIdx.x]);
+    for (int i = threadIdx.x; i < n; i += L) {
+      const uint32_t m = b.vals[range.x + start + i];
+      sM[i] = m;
+      stage_record(b.rec + (int64_t)kRecF4 * m, sA[i], sB[i], sC[i]);
     }
     __syncthreads();
     for (int j = n - 1; j >= 0; --j) {
       const int pos = start + j;
       const float4 A = sA[j];
       const float4 B = sB[j];
-      float dx, dy;
-      const float e = pair_exponent(A, B, fx, fy, dx, dy);
-      const bool active = pos < (int)walked && e >= B.w;
       float gmx = 0.f, gmy = 0.f, ga = 0.f, gb = 0.f, gcc = 0.f, gop = 0.f, gdd = 0.f;
       float gr = 0.f, gg = 0.f, gbl = 0.f;
-      if (active) {
+      bool any = false;
+#pragma unroll
+      for (int k = 0; k < kPPL; ++k) {
+        float dx, dy;
+        const float e = pair_exponent(A, B, fx[k], fy[k], dx, dy);
+        if (pos >= walked[k] || e < B.w) continue;
+        any = true;
         const float4 Cc = sC[j];
         const float g = __builtin_amdgcn_exp2f(e);
         const float raw = B.y * g;
         const float alpha = fminf(kAlphaMax, raw);
         const float oma = 1.f - alpha;
-        const float Tj = T * __builtin_amdgcn_rcpf(oma);
+        const float Tj = T[k] * __builtin_amdgcn_rcpf(oma);
         const float wgt = alpha * Tj;
-        float dsum = gc0 * (Cc.x - Bc0) + gc1 * (Cc.y - Bc1) + gc2 * (Cc.z - Bc2) + gd * (B.z - Bd);
-        Bc0 = __builtin_fmaf(alpha, Cc.x, oma * Bc0);
-        Bc1 = __builtin_fmaf(alpha, Cc.y, oma * Bc1);
-        Bc2 = __builtin_fmaf(alpha, Cc.z, oma * Bc2);
-        Bd = __builtin_fmaf(alpha, B.z, oma * Bd);
+        float dsum = gc0[k] * (Cc.x - Bc0[k]) + gc1[k] * (Cc.y - Bc1[k]) + gc2[k] * (Cc.z - Bc2[k]) +
+                     gd[k] * (B.z - Bd[k]);
+        Bc0[k] = __builtin_fmaf(alpha, Cc.x, oma * Bc0[k]);
+        Bc1[k] = __builtin_fmaf(alpha, Cc.y, oma * Bc1[k]);
+        Bc2[k] = __builtin_fmaf(alpha, Cc.z, oma * Bc2[k]);
+        Bd[k] = __builtin_fmaf(alpha, B.z, oma * Bd[k]);
         float dz = 0.f;
         if (!kTrack) {
-          dz = B.z - dobs;
+          dz = B.z - dobs[k];
           const float u = dz * dz;
-          dsum += go * (1.f - Bo) + gu * (u - Bu);
-          Bo = __builtin_fmaf(alpha, 1.f, oma * Bo);
-          Bu = __builtin_fmaf(alpha, u, oma * Bu);
+          dsum += go[k] * (1.f - Bo[k]) + gu[k] * (u - Bu[k]);
+          Bo[k] = __builtin_fmaf(alpha, 1.f, oma * Bo[k]);
+          Bu[k] = __builtin_fmaf(alpha, u, oma * Bu[k]);
         }
         const float dalpha = Tj * dsum;
-        T = Tj;
+        T[k] = Tj;
         const bool capped = raw > kAlphaMax;
         const float dpower = capped ? 0.f : dalpha * raw;   // alpha = opacity * exp(power)
         // power = -(a dx^2 + 2 b dx dy + c dy^2) / 2, with the staged
         // qa = -a/2 log2 e etc.: d power/d mu = ln2 (2 qa dx + qb dy, qb dx + 2 qc dy)
-        gmx = dpower * kLn2 * __builtin_fmaf(2.f * A.z, dx, A.w * dy);
-        gmy = dpower * kLn2 * __builtin_fmaf(A.w, dx, 2.f * B.x * dy);
-        ga = -0.5f * dpower * dx * dx;
-        gb = -dpower * dx * dy;
-        gcc = -0.5f * dpower * dy * dy;
-        gdd = wgt * gd;
-        if (!kTrack) gdd += 2.f * wgt * dz * gu + (pos == med ? gm : 0.f);
+        gmx += dpower * kLn2 * __builtin_fmaf(2.f * A.z, dx, A.w * dy);
+        gmy += dpower * kLn2 * __builtin_fmaf(A.w, dx, 2.f * B.x * dy);
+        ga -= 0.5f * dpower * dx * dx;
+        gb -= dpower * dx * dy;
+        gcc -= 0.5f * dpower * dy * dy;
+        gdd += wgt * gd[k];
+        if (!kTrack) gdd += 2.f * wgt * dz * gu[k] + (pos == med[k] ? gm[k] : 0.f);
         if (kParams) {
-          gop = capped ? 0.f : dalpha * g;
-          gr = wgt * gc0;
-          gg = wgt * gc1;
-          gbl = wgt * gc2;
+          gop += capped ? 0.f : dalpha * g;
+          gr += wgt * gc0[k];
+          gg += wgt * gc1[k];
+          gbl += wgt * gc2[k];
         }
       }
-      if (__ballot(active)) {
+      if (__ballot(any)) {
         const uint32_t m = sM[j];
         float* dst = b.rec_grad + (int64_t)kGradStride * m;
         const float s0 = wave_sum(gmx), s1 = wave_sum(gmy), s2 = wave_sum(ga), s3 = wave_sum(gb);
@@ -283,24 +337,35 @@ __global__ __launch_bounds__(kThreads) void raster_backward_kernel(RasterBufs b)
   }
 }
 
-}  // namespace
-
-void launch_raster_forward(const RasterBufs& b, bool track, hipStream_t s) {
-  if (b.total_tiles <= 0) return;
-  if (track)
-    hipLaunchKernelGGL(raster_forward_kernel<true>, dim3(b.total_tiles), dim3(kThreads), 0, s, b);
-  else
-    hipLaunchKernelGGL(raster_forward_kernel<false>, dim3(b.total_tiles), dim3(kThreads), 0, s, b);
+template <int kPPL>
+void launch_fwd(const RasterBufs& b, bool track, hipStream_t s) {
+  const dim3 grid(b.total_tiles), block(kTilePixels / kPPL);
+  if (track) hipLaunchKernelGGL((raster_forward_kernel<kPPL, true>), grid, block, 0, s, b);
+  else hipLaunchKernelGGL((raster_forward_kernel<kPPL, false>), grid, block, 0, s, b);
 }
 
-void launch_raster_backward(const RasterBufs& b, bool param_grads, bool track, hipStream_t s) {
+template <int kPPL>
+void launch_bwd(const RasterBufs& b, bool params, bool track, hipStream_t s) {
+  const dim3 grid(b.total_tiles), block(kTilePixels / kPPL);
+  if (track) hipLaunchKernelGGL((raster_backward_kernel<kPPL, false, true>), grid, block, 0, s, b);
+  else if (params) hipLaunchKernelGGL((raster_backward_kernel<kPPL, true, false>), grid, block, 0, s, b);
+  else hipLaunchKernelGGL((raster_backward_kernel<kPPL, false, false>), grid, block, 0, s, b);
+}
+
+}  // namespace
+
+void launch_raster_forward(const RasterBufs& b, bool track, int ppl, hipStream_t s) {
   if (b.total_tiles <= 0) return;
-  if (track)
-    hipLaunchKernelGGL((raster_backward_kernel<false, true>), dim3(b.total_tiles), dim3(kThreads), 0, s, b);
-  else if (param_grads)
-    hipLaunchKernelGGL((raster_backward_kernel<true, false>), dim3(b.total_tiles), dim3(kThreads), 0, s, b);
-  else
-    hipLaunchKernelGGL((raster_backward_kernel<false, false>), dim3(b.total_tiles), dim3(kThreads), 0, s, b);
+  if (ppl == 4) launch_fwd<4>(b, track, s);
+  else if (ppl == 2) launch_fwd<2>(b, track, s);
+  else launch_fwd<1>(b, track, s);
+}
+
+void launch_raster_backward(const RasterBufs& b, bool param_grads, bool track, int ppl, hipStream_t s) {
+  if (b.total_tiles <= 0) return;
+  if (ppl == 4) launch_bwd<4>(b, param_grads, track, s);
+  else if (ppl == 2) launch_bwd<2>(b, param_grads, track, s);
+  else launch_bwd<1>(b, param_grads, track, s);
 }
 
 }  // namespace cgsr

@@ -41,6 +41,38 @@ __global__ __launch_bounds__(kThreads) void tracking_loss_kernel(int w, int h, c
   if (threadIdx.x == 0) atomicAdd(loss, s_part[0] + s_part[1] + s_part[2] + s_part[3]);
 }
 
+// Mapping loss L = mean_n |I^ - I|_1 + mean_n U |D^ - D|, per pixel.
+__global__ __launch_bounds__(kThreads) void mapping_loss_kernel(int w, int h, const float* __restrict__ color,
+                                                                const float* __restrict__ depth,
+                                                                const float* __restrict__ unc,
+                                                                const float* __restrict__ tcolor,
+                                                                const float* __restrict__ tdepth,
+                                                                float* __restrict__ dcolor, float* __restrict__ ddepth,
+                                                                float* __restrict__ dunc, float* loss) {
+  __shared__ float s_part[4];
+  const int64_t hw = (int64_t)w * h;
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const float inv = 1.0f / (float)hw;
+  float l = 0.f;
+  if (i < hw) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float diff = color[c * hw + i] - tcolor[c * hw + i];
+      dcolor[c * hw + i] = inv * sgn(diff);
+      l += fabsf(diff);
+    }
+    const float dd = depth[i] - tdepth[i];
+    ddepth[i] = inv * unc[i] * sgn(dd);
+    dunc[i] = inv * fabsf(dd);
+    l = (l + unc[i] * fabsf(dd)) * inv;
+  }
+  if (!loss) return;
+  const float t = wave_sum(l);
+  if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(loss, s_part[0] + s_part[1] + s_part[2] + s_part[3]);
+}
+
 // One lane per view: Adam step and retraction (adam_retract), then the
 // gradient buffer is cleared for the next iteration.
 __global__ void pose_adam_kernel(int n_views, float* poses, float* dposes, float* adam, AdamParams ap) {
@@ -81,6 +113,14 @@ void launch_tracking_loss(int w, int h, const float* color, const float* depth, 
   const int64_t hw = (int64_t)w * h;
   hipLaunchKernelGGL(tracking_loss_kernel, dim3((unsigned)((hw + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
                      w, h, color, depth, tcolor, tdepth, lc, ld, dcolor, ddepth, loss);
+}
+
+void launch_mapping_loss(int w, int h, const float* color, const float* depth, const float* unc,
+                         const float* tcolor, const float* tdepth, float* dcolor, float* ddepth, float* dunc,
+                         float* loss, hipStream_t s) {
+  const int64_t hw = (int64_t)w * h;
+  hipLaunchKernelGGL(mapping_loss_kernel, dim3((unsigned)((hw + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
+                     w, h, color, depth, unc, tcolor, tdepth, dcolor, ddepth, dunc, loss);
 }
 
 void launch_pose_adam(int n_views, float* poses, float* dposes, float* adam, const AdamParams& ap, hipStream_t s) {

@@ -63,10 +63,16 @@ def pose_tensor(R, t, device="cuda") -> torch.Tensor:
 class State:
     """Owns one cgsr_state (the workspace of a render and its backward)."""
 
-    def __init__(self, sync_capacity: bool = True, timing: bool = False):
+    def __init__(self, sync_capacity: bool = True, timing: bool = False, fwd_ppl: int | None = None,
+                 bwd_ppl: int | None = None):
         s = B.cgsr_default_settings()
         s.sync_capacity = int(sync_capacity)
         s.timing = int(timing)
+        if fwd_ppl is not None:
+            s.fwd_pixels_per_lane = int(fwd_ppl)
+        if bwd_ppl is not None:
+            s.bwd_pixels_per_lane = int(bwd_ppl)
+        self.settings = s
         self.handle = B.cgsr_state_create(s)
         self.n_views = 0
         self.n = 0
@@ -166,6 +172,32 @@ def tracking_loss_grad(color, depth, target_color, target_depth, lam=TRACK_LAMBD
                               target_depth.data_ptr(), float(lam[0]), float(lam[1]), dcolor.data_ptr(),
                               ddepth.data_ptr(), _ptr(loss), _stream())
     return dcolor, ddepth
+
+
+def mapping_loss_grad(color, depth, uncertainty, target_color, target_depth, loss=None):
+    """Gradient images of mean|I^ - I|_1 + mean U |D^ - D| on the device."""
+    H, W = depth.shape
+    dcolor, ddepth, dunc = torch.empty_like(color), torch.empty_like(depth), torch.empty_like(depth)
+    B.cgsr_mapping_loss_grad(W, H, color.data_ptr(), depth.data_ptr(), uncertainty.data_ptr(),
+                             target_color.data_ptr(), target_depth.data_ptr(), dcolor.data_ptr(), ddepth.data_ptr(),
+                             dunc.data_ptr(), _ptr(loss), _stream())
+    return dict(color=dcolor, depth=ddepth, uncertainty=dunc)
+
+
+def autotune_tracking(state: State, scene: dict, poses: torch.Tensor, cams, target_colors, target_depths,
+                      repeats: int = 5):
+    """Pick the blend kernels' pixels per lane for this tracking workload (the
+    library times each candidate); the state keeps the choice.  Returns
+    (fwd_pixels_per_lane, bwd_pixels_per_lane)."""
+    if isinstance(cams, dict):
+        cams = [cams]
+    V = len(cams)
+    poses = poses.reshape(V, 12)
+    s = B.cgsr_autotune_tracking(state.handle, gaussians_struct(scene), V, poses.data_ptr(),
+                                 [camera_struct(c) for c in cams], [t.data_ptr() for t in target_colors],
+                                 [t.data_ptr() for t in target_depths], int(repeats), _stream())
+    state.settings = s
+    return int(s.fwd_pixels_per_lane), int(s.bwd_pixels_per_lane)
 
 
 def adam_params(lr_rho=TRACK_LR_RHO, lr_phi=TRACK_LR_PHI, betas=(0.9, 0.999), eps=1e-8) -> B.cgsr_adam_params:
@@ -273,7 +305,8 @@ class TrackingSolver:
     work inside the loop."""
 
     def __init__(self, prob: TrackingProblem, iters: int = 50, pair_margin: float = 1.5, use_graph: bool = True,
-                 reset_pose: torch.Tensor | None = None, fused: bool = True):
+                 reset_pose: torch.Tensor | None = None, fused: bool = True, fwd_ppl: int | None = None,
+                 bwd_ppl: int | None = None):
         """reset_pose: if given, every solve (and every graph replay) starts
         from this pose with fresh Adam moments; the reset is part of the graph."""
         self.prob = prob
@@ -288,7 +321,7 @@ class TrackingSolver:
         self.ddepth = torch.empty((H, W), dtype=torch.float32, device=dev)
         self.color = torch.empty((3, H, W), dtype=torch.float32, device=dev)
         self.depth = torch.empty((H, W), dtype=torch.float32, device=dev)
-        self.state = State(sync_capacity=True)
+        self.state = State(sync_capacity=True, fwd_ppl=fwd_ppl, bwd_ppl=bwd_ppl)
         self.g = gaussians_struct(prob.scene)
         self.cam_s = camera_struct(cam)
         self.out_s = B.cgsr_images(self.color.data_ptr(), self.depth.data_ptr(), None, None, None)

@@ -32,6 +32,8 @@ __all__ = [
     "perturb_pose",
     "random_walk_poses",
     "random_targets",
+    "tracking_frames",
+    "TRACKING_RESOLUTIONS",
     "rot_about_axis",
     "TRACKING_CAMERA",
     "MAPPING_CAMERA",
@@ -197,3 +199,23 @@ def random_targets(seed: int, cam: dict, depth_range=(1.5, 4.0)):
     color = rng.uniform(0.0, 1.0, (3, H, W)).astype(np.float32)
     depth = rng.uniform(depth_range[0], depth_range[1], (H, W)).astype(np.float32)
     return color, depth
+
+
+#: Frame sizes of the many-frame tracking workload.
+TRACKING_RESOLUTIONS = ((320, 240), (640, 480), (960, 540), (1200, 680))
+
+
+def tracking_frames(seed: int, n_frames: int, radius: float = 1.0):
+    """Independent tracking frames of uneven resolution: each frame draws its
+    size uniformly from TRACKING_RESOLUTIONS, its focal length scales with the
+    width (f = 525 W / 640), its principal point is the image centre, and its
+    pose is a level room pose (level_room_pose) of its own seed.
+    Returns a list of (camera, (R, t))."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n_frames):
+        W, H = TRACKING_RESOLUTIONS[int(rng.integers(len(TRACKING_RESOLUTIONS)))]
+        f = 525.0 * W / 640.0
+        cam = camera(W, H, f, f, W / 2.0, H / 2.0)
+        out.append((cam, level_room_pose(int(rng.integers(1 << 30)), radius)))
+    return out

@@ -61,10 +61,12 @@ def test_host_side_argument_checks(lib):
     assert lib.cgsr_get_stats(None, None, None) == B.CGSR_ERR_INVALID_ARG
     assert lib.cgsr_state_reserve(None, 1, 1, 1, 1) == B.CGSR_ERR_INVALID_ARG
     assert lib.cgsr_state_destroy(None) == B.CGSR_OK
-    bad = B.cgsr_settings(2, 0)
+    bad = B.cgsr_settings(2, 0, 1, 1)
     out = C.c_void_p()
     assert lib.cgsr_state_create(C.byref(bad), C.byref(out)) == B.CGSR_ERR_INVALID_ARG
     assert out.value is None
+    bad_ppl = B.cgsr_settings(1, 0, 3, 1)
+    assert lib.cgsr_state_create(C.byref(bad_ppl), C.byref(out)) == B.CGSR_ERR_INVALID_ARG
 
 
 def test_binding_raises_with_message(lib):

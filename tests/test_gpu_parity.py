@@ -164,6 +164,54 @@ def test_tile_assignment_bit_exact_tracking_size(R):
     assert K > 10_000
 
 
+@pytest.mark.parametrize("ppl", [2, 4])
+def test_pixels_per_lane_variants(R, config1, ppl):
+    """Blend kernels with 2 or 4 pixels per lane: forward maps bitwise equal to
+    one pixel per lane, gradients within the oracle tolerance."""
+    sc, cam, tc, td = config1
+    say(f"case: config1 with {ppl} pixels per lane")
+    scd = dev(sc)
+    ref_state = R.State()
+    ref, _ = gpu_render(R, ref_state, scd, identity_pose(), cam, td)
+    st = R.State(fwd_ppl=ppl, bwd_ppl=ppl)
+    got, _ = gpu_render(R, st, scd, identity_pose(), cam, td)
+    for k in MAPS:
+        assert np.array_equal(got[k], ref[k]), k
+    rng = np.random.default_rng(22)
+    H, W = cam["height"], cam["width"]
+    dimg = dict(color=rng.standard_normal((3, H, W)), depth=rng.standard_normal((H, W)),
+                opacity=rng.standard_normal((H, W)), depth_median=rng.standard_normal((H, W)),
+                uncertainty=rng.standard_normal((H, W)))
+    grads, dposes = R.backward(st, [{k: t32(v) for k, v in dimg.items()}])
+    rb = oracle.backward(sc, cam, identity_pose(), td, dimg)
+    for k in PARAMS:
+        assert rel_l2(grads[k].cpu().numpy(), rb[k]) <= 1e-3, k
+    assert np.abs(dposes[0].cpu().numpy() - rb["pose"]).max() <= 1e-3 * np.abs(rb["pose"]).max()
+    # tracking-mode kernels
+    d1, d2 = torch.zeros((1, 6), device="cuda"), torch.zeros((1, 6), device="cuda")
+    P = R.pose_tensor(*identity_pose())
+    R.tracking_step(ref_state, scd, P, [cam], [t32(tc)], [t32(td)], dposes=d1)
+    R.tracking_step(st, scd, P, [cam], [t32(tc)], [t32(td)], dposes=d2)
+    assert ((d1 - d2).abs().max() / d1.abs().max()).item() < 1e-4
+
+
+def test_autotuner_picks_a_valid_setting(R):
+    say("case: autotuner on a small tracking workload")
+    sc = synth.room_scene(5, 20_000, (5.0, 4.0, 3.0))
+    cam = synth.camera(320, 240, 262.5, 262.5, 160, 120)
+    scd = dev(sc)
+    P = R.pose_tensor(*synth.level_room_pose(3))
+    st = R.State()
+    tgt = R.render(st, scd, P, [cam])[0]
+    P_before = P.clone()
+    f, b = R.autotune_tracking(st, scd, P, [cam], [tgt["color"]], [tgt["depth"]], repeats=2)
+    say("picked", f, b)
+    assert f in (1, 2, 4) and b in (1, 2, 4)
+    assert torch.equal(P, P_before)
+    out = R.render(st, scd, P, [cam])[0]
+    assert torch.equal(out["color"], tgt["color"])
+
+
 def test_long_tile_segments_take_the_merge_path(R):
     """More than 4096 Gaussians in one tile: the segment sort goes through its
     chunked LDS sort plus in-workgroup merges; lists and maps must still match."""
