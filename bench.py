@@ -11,6 +11,19 @@ of 50 iterations are captured into one HIP graph and replayed; the timed region
 is K iterations with all inputs resident in HBM.
 
 Prints one JSON line.  Only N = 1 GPU is supported.
+
+``--workload`` selects one of the other measured workloads instead (each
+prints its own JSON line, timed eagerly with inputs resident in HBM):
+
+* ``mapping``: 500k Gaussians in an 8 x 6 x 3 m room, one 1200x680 view
+  (f = 600); render with sensor depth, uncertainty-weighted L1 loss gradient
+  images, backward to every Gaussian parameter and the pose.
+* ``batched-mapping``: 1M Gaussians, 8 keyframe views of 1200x680 along a
+  random walk; the same iteration for all 8 views in one launch sequence
+  (per-Gaussian gradients summed over views) against 8 single-view sequences.
+* ``batched-tracking``: 1M Gaussians, 32 frames of uneven resolution; a
+  20-iteration Adam tracking loop over all frames at once captured in one HIP
+  graph, against 32 single-frame graphs of the same loop.
 """
 from __future__ import annotations
 
@@ -102,10 +115,320 @@ def cpu_baseline(prob_np, cam, pose0, budget_s: float):
                 sample=f"{it} full tracking iterations (render + tracking loss + pose backward + Adam) "
                        f"of the same 100k-Gaussian 640x480 workload in {el:.1f} s")
 
+# --------------------------------------------------------------------------
+# Mapping and batched workloads
+
+PARAM_WIDTHS = (("means", 3), ("log_scales", 3), ("quats", 4), ("opacity_logits", 1), ("rgb", 3))
+
+
+def _sync_timed(torch, fn, reps):
+    """Run fn() reps times between device synchronisations; returns (wall s,
+    event ms) of the whole run."""
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, e0.elapsed_time(e1)
+
+
+class MappingIteration:
+    """Render (colour, depth, uncertainty with sensor depth) -> uncertainty-
+    weighted L1 gradient images -> backward to every Gaussian parameter and
+    each view's pose, on preallocated buffers; gradients are cleared once per
+    iteration and summed over the views by the library."""
+
+    def __init__(self, torch, R, scene, poses, cams, target_colors, target_depths, batched: bool):
+        B = R.B
+        self.torch, self.R, self.B = torch, R, B
+        self.batched = batched
+        self.V = len(cams)
+        n = scene["means"].shape[0]
+        dev = poses.device
+        self.g = R.gaussians_struct(scene)
+        self.poses = poses
+        self.cams = [R.camera_struct(c) for c in cams]
+        self.tc, self.td = target_colors, target_depths
+        self.flat = torch.zeros(n * 14, dtype=torch.float32, device=dev)
+        off, views = 0, []
+        for name, w in PARAM_WIDTHS:
+            views.append(self.flat[off:off + n * w].data_ptr())
+            off += n * w
+        self.dG = B.cgsr_gaussian_grads(*views)
+        self.dposes = torch.zeros((self.V, 6), dtype=torch.float32, device=dev)
+        self.maps, self.grads, self.out_s, self.grad_s = [], [], [], []
+        for c in cams:
+            H, W = int(c["height"]), int(c["width"])
+            m = dict(color=torch.empty((3, H, W), device=dev), depth=torch.empty((H, W), device=dev),
+                     uncertainty=torch.empty((H, W), device=dev))
+            d = dict(color=torch.empty((3, H, W), device=dev), depth=torch.empty((H, W), device=dev),
+                     uncertainty=torch.empty((H, W), device=dev))
+            self.maps.append(m)
+            self.grads.append(d)
+            self.out_s.append(B.cgsr_images(m["color"].data_ptr(), m["depth"].data_ptr(), None, None,
+                                            m["uncertainty"].data_ptr()))
+            self.grad_s.append(B.cgsr_images(d["color"].data_ptr(), d["depth"].data_ptr(), None, None,
+                                             d["uncertainty"].data_ptr()))
+        self.states = [R.State(sync_capacity=True) for _ in range(1 if batched else self.V)]
+
+    def _views(self, st, vs):
+        B, s = self.B, self.R._stream()
+        B.cgsr_render(st.handle, self.g, len(vs), self.poses[vs[0]].data_ptr(), [self.cams[v] for v in vs],
+                      [self.td[v].data_ptr() for v in vs], [self.out_s[v] for v in vs], s)
+        for v in vs:
+            m, d, c = self.maps[v], self.grads[v], self.cams[v]
+            B.cgsr_mapping_loss_grad(c.width, c.height, m["color"].data_ptr(), m["depth"].data_ptr(),
+                                     m["uncertainty"].data_ptr(), self.tc[v].data_ptr(), self.td[v].data_ptr(),
+                                     d["color"].data_ptr(), d["depth"].data_ptr(), d["uncertainty"].data_ptr(),
+                                     None, s)
+        B.cgsr_backward(st.handle, [self.grad_s[v] for v in vs], self.dG, self.dposes[vs[0]].data_ptr(), s)
+
+    def __call__(self):
+        self.flat.zero_()
+        self.dposes.zero_()
+        if self.batched:
+            self._views(self.states[0], list(range(self.V)))
+        else:
+            for v in range(self.V):
+                self._views(self.states[v], [v])
+
+    def freeze_capacity(self, margin=1.25):
+        """After a sizing call: fixed pair capacity, no per-call readback."""
+        for k, st in enumerate(self.states):
+            pairs = st.stats().pairs
+            new = self.R.State(sync_capacity=False)
+            new.reserve(pairs=int(pairs * margin) + 4096)
+            self.states[k] = new
+            st.close()
+
+    def check(self):
+        for st in self.states:
+            st.check()
+
+    def stats(self):
+        tot = dict(visible=0, pairs=0, evaluations=0, blended=0, walked=0)
+        for st in self.states:
+            s = st.stats()
+            for k, a in (("visible", "visible"), ("pairs", "pairs"), ("evaluations", "processed"),
+                         ("blended", "blended"), ("walked", "walked")):
+                tot[k] += int(getattr(s, a))
+        return tot
+
+
+def mapping_bytes(n, visible, pairs, pixels):
+    """HBM bytes one mapping iteration must move: the tracking figures plus,
+    per pixel, the uncertainty map and its gradient (8 B) and the loss
+    gradient pass (read 3 maps + 4 targets, write 3 gradients: 40 B), and per
+    visible Gaussian the 14 parameter gradients written (56 B)."""
+    return algorithmic_bytes(n, visible, pairs, pixels) + 48 * pixels + 56 * visible
+
+
+def oracle_mapping_seconds(sc, cam, pose, tc, td):
+    import oracle
+    t0 = time.perf_counter()
+    maps = oracle.render(sc, cam, pose, td)
+    _, dimg = oracle.uncertainty_weighted_loss(maps, tc, td)
+    oracle.backward(sc, cam, pose, td, dimg)
+    return time.perf_counter() - t0
+
+
+def oracle_tracking_seconds(sc, cam, pose, tc, td):
+    import oracle
+    t0 = time.perf_counter()
+    maps = oracle.render(sc, cam, pose)
+    _, dimg = oracle.tracking_loss(maps, tc, td)
+    oracle.backward(sc, cam, pose, None, dimg)
+    return time.perf_counter() - t0
+
+
+def perturbed_scene(np, sc, seed):
+    """The scene being optimised: the target scene with means moved by
+    N(0, 5 mm) and colours by N(0, 0.05)."""
+    rng = np.random.default_rng(seed)
+    out = dict(sc)
+    out["means"] = (sc["means"] + rng.normal(0.0, 0.005, sc["means"].shape)).astype(np.float32)
+    out["rgb"] = np.clip(sc["rgb"] + rng.normal(0.0, 0.05, sc["rgb"].shape), 0, 1).astype(np.float32)
+    return out
+
+
+def run_mapping(args, torch, R, synth, views: int):
+    import numpy as np
+    n = 500_000 if views == 1 else 1_000_000
+    seed = 3 if views == 1 else 4
+    log(f"building workload: {n} Gaussians, {views} view(s) of 1200x680")
+    sc_t = synth.room_scene(seed, n, (8.0, 6.0, 3.0))
+    sc = perturbed_scene(np, sc_t, seed + 1000)
+    cam = synth.MAPPING_CAMERA
+    pose_list = [synth.level_room_pose(seed)] if views == 1 else synth.random_walk_poses(seed + 1000, views)
+    P = torch.stack([R.pose_tensor(*p) for p in pose_list]).contiguous()
+    cams = [cam] * views
+    tst = R.State()
+    tgt = R.render(tst, {k: torch.from_numpy(v).cuda() for k, v in sc_t.items()}, P, cams, maps=("color", "depth"))
+    tcs = [t["color"].clone() for t in tgt]
+    tds = [t["depth"].clone() for t in tgt]
+    del tgt, tst
+    scd = {k: torch.from_numpy(v).cuda() for k, v in sc.items()}
+    modes = [("batched", True)] + ([("sequential", False)] if views > 1 else [])
+    res = {}
+    for name, batched in modes:
+        it = MappingIteration(torch, R, scd, P, cams, tcs, tds, batched)
+        it()
+        torch.cuda.synchronize()
+        it.freeze_capacity()
+        for _ in range(args.warmup):
+            it()
+        wall, ev = _sync_timed(torch, it, args.steps)
+        it.check()
+        res[name] = dict(ms_per_iter=wall * 1e3 / args.steps, event_ms_per_iter=ev / args.steps, stats=it.stats())
+        log(f"{name}: {res[name]['ms_per_iter']:.3f} ms/iteration ({views} view(s))")
+        del it
+    st = res["batched"]["stats"]
+    b = mapping_bytes(n, st["visible"], st["pairs"], views * cam["width"] * cam["height"])
+    ms = res["batched"]["ms_per_iter"]
+    out = {
+        "metric": ("mapping iters/s (fwd+full bwd) 1200x680 500k Gaussians" if views == 1 else
+                   "batched mapping views/s (fwd+full bwd) 8x1200x680 1M Gaussians"),
+        "value": round((1 if views == 1 else views) * 1e3 / ms, 3),
+        "unit": "it/s" if views == 1 else "views/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": (f"mapping: {n} Gaussians on an 8x6x3 m room, {views} view(s) 1200x680 f=600, "
+                                "render with sensor depth + uncertainty-weighted L1 + backward to all "
+                                "parameters and poses"), "gaussians": n, "views": views},
+        "hbm_roofline": {"algorithmic_bytes_per_iter": b, "achieved_GBs": round(b / (ms * 1e-3) / 1e9, 2),
+                         "peak_GBs": HBM_PEAK_GBS, "frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)},
+        "stats": st,
+    }
+    if views > 1:
+        out["sequential"] = {"ms_per_step": round(res["sequential"]["ms_per_iter"], 5),
+                             "value": round(views * 1e3 / res["sequential"]["ms_per_iter"], 3),
+                             "speedup_batched": round(res["sequential"]["ms_per_iter"] / ms, 3)}
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, one view)")
+        t = oracle_mapping_seconds(sc, cam, pose_list[0], tcs[0].cpu().numpy(), tds[0].cpu().numpy())
+        import oracle
+        out["cpu_baseline"] = {"value": round(1.0 / t, 5), "unit": out["unit"],
+                               "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": f"one view's full iteration (render + loss + backward) in {t:.1f} s"
+                                         + ("" if views == 1 else "; views/s extrapolated from one view")}
+    return out
+
+
+def run_batched_tracking(args, torch, R, synth, frames=32, iters=20):
+    import numpy as np
+    B = R.B
+    n = 1_000_000
+    seed = 5
+    log(f"building workload: {n} Gaussians, {frames} frames of uneven resolution")
+    sc = synth.room_scene(seed, n, (8.0, 6.0, 3.0))
+    scd = {k: torch.from_numpy(v).cuda() for k, v in sc.items()}
+    fr = synth.tracking_frames(seed + 1000, frames)
+    cams = [f[0] for f in fr]
+    Pt = torch.stack([R.pose_tensor(*f[1]) for f in fr]).contiguous()
+    tst = R.State()
+    tgt = R.render(tst, scd, Pt, cams, maps=("color", "depth"))
+    tcs = [t["color"].clone() for t in tgt]
+    tds = [t["depth"].clone() for t in tgt]
+    del tgt, tst
+    start = [synth.perturb_pose(*f[1], seed + 2000 + k) for k, f in enumerate(fr)]
+    P0 = torch.stack([R.pose_tensor(*p) for p in start]).contiguous()
+    params = R.adam_params()
+    g = R.gaussians_struct(scd)
+    cam_s = [R.camera_struct(c) for c in cams]
+    lam = R.TRACK_LAMBDA
+
+    def make(vs):
+        """Graph of `iters` fused tracking steps over frames vs (reset inside)."""
+        V = len(vs)
+        pose = torch.empty((V, 12), device="cuda")
+        pose0 = P0[vs].contiguous()
+        adam = torch.zeros((V, 16), device="cuda")
+        st = R.State(sync_capacity=True)
+        cs = [cam_s[v] for v in vs]
+        tc = [tcs[v].data_ptr() for v in vs]
+        td = [tds[v].data_ptr() for v in vs]
+
+        def step():
+            B.cgsr_tracking_step(st.handle, g, V, pose.data_ptr(), cs, tc, td, float(lam[0]), float(lam[1]),
+                                 None, adam.data_ptr(), params, None, R._stream())
+        pose.copy_(pose0)
+        step()
+        torch.cuda.synchronize()
+        st.reserve(pairs=int(st.stats().pairs * 1.5) + 4096)
+        graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(graph, stream=side):
+                torch.mul(pose0, 1.0, out=pose)
+                adam.zero_()
+                for _ in range(iters):
+                    step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        return graph, st, pose
+
+    res = {}
+    for name, groups in (("batched", [list(range(frames))]), ("sequential", [[v] for v in range(frames)])):
+        made = [make(vs) for vs in groups]
+
+        def solve():
+            for gr, _, _ in made:
+                gr.replay()
+        reps = max(1, args.steps // iters)
+        for _ in range(max(1, args.warmup // iters)):
+            solve()
+        wall, ev = _sync_timed(torch, solve, reps)
+        for _, st, _ in made:
+            st.check()
+        fi = frames * iters * reps
+        res[name] = dict(wall=wall, fi=fi, value=fi / wall, poses=torch.cat([p for _, _, p in made]).cpu())
+        log(f"{name}: {fi / wall:.1f} frame-iterations/s")
+        del made
+    d = float((res["batched"]["poses"] - res["sequential"]["poses"]).abs().max())
+    log(f"batched vs sequential final poses max diff {d:.2e}")
+    ms = res["batched"]["wall"] * 1e3 / (res["batched"]["fi"] / frames)
+    out = {
+        "metric": "batched tracking frame-iters/s (fwd+pose-bwd) 32 mixed-resolution frames 1M Gaussians",
+        "value": round(res["batched"]["value"], 2), "unit": "frame-it/s", "n_gpus": 1,
+        "steps": res["batched"]["fi"] // frames, "warmup": max(1, args.warmup // iters) * iters,
+        "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batched tracking: {n} Gaussians on an 8x6x3 m room, {frames} frames drawn from "
+                               "320x240/640x480/960x540/1200x680 (f = 525 W/640), 20-iteration Adam loops "
+                               "captured in one HIP graph", "gaussians": n, "frames": frames,
+                   "resolutions": [[c["width"], c["height"]] for c in cams], "solve_iters": iters},
+        "sequential": {"value": round(res["sequential"]["value"], 2),
+                       "speedup_batched": round(res["batched"]["value"] / res["sequential"]["value"], 3),
+                       "final_pose_max_diff": d},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, one frame per resolution)")
+        import oracle
+        per_res, tot = {}, 0.0
+        for v, c in enumerate(cams):
+            key = (c["width"], c["height"])
+            if key not in per_res:
+                per_res[key] = oracle_tracking_seconds(sc, c, start[v], tcs[v].cpu().numpy(), tds[v].cpu().numpy())
+            tot += per_res[key]
+        out["cpu_baseline"] = {"value": round(frames / tot, 5), "unit": "frame-it/s", "cores": oracle.num_threads(),
+                               "kind": "oracle",
+                               "sample": "one tracking iteration per distinct resolution ("
+                                         + ", ".join(f"{w}x{h}: {t:.1f} s" for (w, h), t in per_res.items())
+                                         + "), extrapolated to the 32-frame mix"}
+    return out
+
+
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="tracking",
+                    choices=("tracking", "mapping", "batched-mapping", "batched-tracking"))
     ap.add_argument("--steps", type=int, default=2000, help="timed tracking iterations")
     ap.add_argument("--warmup", type=int, default=200, help="untimed tracking iterations")
     ap.add_argument("--solve-iters", type=int, default=50, help="iterations per captured solve")
@@ -138,6 +461,13 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": n * 4, "copy_calibration_bytes_written": n * 4}))
+        return
+    if args.workload != "tracking":
+        if args.workload == "batched-tracking":
+            out = run_batched_tracking(args, torch, R, synth)
+        else:
+            out = run_mapping(args, torch, R, synth, 1 if args.workload == "mapping" else 8)
+        print(json.dumps(out), flush=True)
         return
     log("building workload: 100k Gaussians, 640x480")
     sc, prob, P0, true_pose = build_workload(torch, R, synth)

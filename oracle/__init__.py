@@ -77,6 +77,8 @@ def lib():
                                       C.c_int, C.POINTER(_ImageGrads), C.POINTER(_Grads)]
         _lib.orc_fd_linear.argtypes = [C.POINTER(_Gaussians), C.POINTER(_Camera), C.POINTER(_Pose), _dp,
                                        C.POINTER(_ImageGrads), C.c_int64, _ip, _lp, _ip, C.c_double, _dp]
+        _lib.orc_gaussian_uncertainty.argtypes = [C.POINTER(_Gaussians), C.POINTER(_Camera), C.POINTER(_Pose),
+                                                  _dp, C.c_int, _dp, _lp, _ip, _dp]
         _lib.orc_se3_exp.argtypes = [_dp, _dp, _dp]
         _lib.orc_se3_exp.restype = None
         _lib.orc_num_threads.restype = C.c_int
@@ -221,6 +223,55 @@ def fd_linear(scene, cam, pose, depth_obs, dimg: dict, coords, rel_step: float =
                                C.byref(ig), len(coords), _ptr(kinds, _ip), _ptr(idx, _lp),
                                _ptr(comp, _ip), float(rel_step), _ptr(out)), "fd_linear")
     return out
+
+
+#: Pruning threshold on the per-Gaussian uncertainty (Sec. 3.2).
+NU_TAU = 0.025
+#: Opacity a pruned Gaussian is lowered to (the paper says only "a low-opacity
+#: level"; reading: 0.01).
+NU_LOW_OPACITY = 0.01
+
+
+def gaussian_uncertainty(scene, cam, pose, depth_obs, nu_sum=None, nu_count=None, *, candidates: int = 1):
+    """One keyframe's contribution to Eq. 13 (see orc_gaussian_uncertainty).
+
+    nu_sum / nu_count: running float64 [n] / int64 [n] accumulators (new
+    zeros if None), updated in place.  Returns dict(sum, count, dominant
+    [H, W] int32, margin [H, W])."""
+    s = _Scene(scene)
+    n = s.n
+    nu_sum = np.zeros(n) if nu_sum is None else nu_sum
+    nu_count = np.zeros(n, np.int64) if nu_count is None else nu_count
+    assert nu_sum.dtype == np.float64 and nu_count.dtype == np.int64
+    H, W = int(cam["height"]), int(cam["width"])
+    dom = np.zeros((H, W), np.int32)
+    margin = np.zeros((H, W))
+    d = _f64(depth_obs)
+    _check(lib().orc_gaussian_uncertainty(C.byref(s.c), C.byref(_cam(cam)), C.byref(_pose(pose)), _ptr(d),
+                                          int(candidates), _ptr(nu_sum), _ptr(nu_count, _lp), _ptr(dom, _ip),
+                                          _ptr(margin)), "gaussian_uncertainty")
+    return dict(sum=nu_sum, count=nu_count, dominant=dom, margin=margin)
+
+
+def nu_from_sums(nu_sum, nu_count):
+    """Eq. 13: nu_i = (sum over dominated pixels of the window) / (M_1 + ... + M_k);
+    a Gaussian that dominates no pixel has no evidence and gets nu = 0."""
+    nu_sum = np.asarray(nu_sum, np.float64)
+    nu_count = np.asarray(nu_count)
+    out = np.zeros_like(nu_sum)
+    has = nu_count > 0
+    out[has] = nu_sum[has] / nu_count[has]
+    return out
+
+
+def prune_uncertain(opacity_logits, nu, tau=NU_TAU, level=NU_LOW_OPACITY):
+    """Sec. 3.2: Gaussians with nu > tau have their opacity lowered to `level`
+    (never raised).  Returns (new opacity logits, boolean mask of pruned)."""
+    o = np.asarray(opacity_logits, np.float64).copy()
+    mask = np.asarray(nu) > tau
+    cap = np.log(level / (1.0 - level))
+    o[mask] = np.minimum(o[mask], cap)
+    return o, mask
 
 
 def se3_exp(xi):

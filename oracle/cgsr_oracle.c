@@ -290,6 +290,10 @@ typedef struct {
     double color[3], depth, opacity, depth_median, uncertainty, t_final, margin, order_margin;
     int64_t median;      /* Gaussian id, -1 if T never fell below 0.5 */
     int n;               /* blended Gaussians */
+    /* Eq. 13: the blended Gaussian of largest weight alpha T, its weight and
+     * depth, and the largest weight among the others */
+    int64_t dominant;
+    double w_dominant, w_runner_up, d_dominant;
 } pixel_out;
 
 /* One blended Gaussian of a pixel, as recorded for the backward pass and
@@ -326,6 +330,7 @@ static void pixel_forward(const gproj *pr, const int64_t *cand, int64_t ncand, d
     double T = 1.0, prev_depth = -1.0;
     memset(po, 0, sizeof(*po));
     po->median = -1;
+    po->dominant = -1;
     po->margin = DBL_MAX;
     po->order_margin = DBL_MAX;
     for (int64_t k = 0; k < ncand; ++k) {
@@ -347,6 +352,14 @@ static void pixel_forward(const gproj *pr, const int64_t *cand, int64_t ncand, d
         po->depth += w * o->depth;
         po->opacity += w;
         if (has_dobs) po->uncertainty += w * (o->depth - dobs) * (o->depth - dobs);
+        if (w > po->w_dominant) {
+            po->w_runner_up = po->w_dominant;
+            po->w_dominant = w;
+            po->dominant = i;
+            po->d_dominant = o->depth;
+        } else if (w > po->w_runner_up) {
+            po->w_runner_up = w;
+        }
         if (po->median < 0) {
             po->margin = fmin(po->margin, rel_gap(Tn, ORC_T_MEDIAN));
             if (Tn < ORC_T_MEDIAN) {
@@ -436,6 +449,50 @@ int orc_render(const orc_gaussians *g, const orc_camera *cam, const orc_pose *po
         if (out->decision_margin) out->decision_margin[k] = po.margin;
         if (out->order_margin) out->order_margin[k] = po.order_margin;
     }
+    render_teardown(&rc);
+    return 0;
+}
+
+int orc_gaussian_uncertainty(const orc_gaussians *g, const orc_camera *cam, const orc_pose *pose,
+                             const double *depth_obs, int candidates, double *nu_sum,
+                             int64_t *nu_count, int32_t *dominant, double *dominant_margin)
+{
+    if (cam->width < 0 || cam->height < 0 || g->n < 0 || !depth_obs || !nu_sum || !nu_count) return -1;
+    render_ctx rc;
+    int st = render_setup(g, cam, pose, candidates, &rc);
+    if (st) { render_teardown(&rc); return st; }
+    const int64_t npx = (int64_t)cam->width * cam->height;
+    int64_t *dom = malloc(sizeof(int64_t) * (size_t)(npx ? npx : 1));
+    double *contrib = malloc(sizeof(double) * (size_t)(npx ? npx : 1));
+    if (!dom || !contrib) { free(dom); free(contrib); render_teardown(&rc); return -2; }
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t pix = 0; pix < npx; ++pix) {
+        const int64_t *cand;
+        int64_t nc;
+        pixel_candidates(&rc, pix, &cand, &nc);
+        pixel_out po;
+        pixel_forward(rc.pr, cand, nc, (double)(pix % cam->width), (double)(pix / cam->width),
+                      depth_obs[pix], 1, &po, NULL);
+        dom[pix] = -1;
+        contrib[pix] = 0.0;
+        if (po.dominant >= 0 && depth_obs[pix] > 0.0) {
+            const double e = depth_obs[pix] - po.d_dominant;
+            dom[pix] = po.dominant;
+            contrib[pix] = po.w_dominant * e * e;
+        }
+        if (dominant) dominant[pix] = (int32_t)po.dominant;
+        if (dominant_margin)
+            dominant_margin[pix] = po.dominant < 0 ? DBL_MAX
+                                                   : (po.w_dominant - po.w_runner_up) / po.w_dominant;
+    }
+    /* serial scatter: the sums do not depend on the thread count */
+    for (int64_t pix = 0; pix < npx; ++pix) {
+        if (dom[pix] < 0) continue;
+        nu_sum[dom[pix]] += contrib[pix];
+        nu_count[dom[pix]] += 1;
+    }
+    free(dom);
+    free(contrib);
     render_teardown(&rc);
     return 0;
 }

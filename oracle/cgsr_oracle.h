@@ -11,6 +11,7 @@
  *   Eq. 3-5 front-to-back alpha blending of colour
  *   Eq. 6   alpha-blended depth, Eq. 7-8 median depth, Eq. 9 opacity
  *   Eq. 10  uncertainty map  U = sum_i alpha_i T_i (d_i - D)^2
+ *   Eq. 13  per-Gaussian depth uncertainty from its dominated pixels
  * plus the analytic gradient of all of them with respect to every Gaussian
  * parameter and to the left se(3) perturbation of the world->camera pose
  * (Sec. 3.4 names these pose derivatives; their derivation is restated from
@@ -135,6 +136,22 @@ int orc_fd_linear(const orc_gaussians *g, const orc_camera *cam, const orc_pose 
                   const double *depth_obs, const orc_image_grads *dimg,
                   int64_t n_coords, const int32_t *kind, const int64_t *index,
                   const int32_t *comp, double rel_step, double *out);
+
+/* Per-Gaussian depth uncertainty of Eq. 13, the contribution of one keyframe.
+ * A pixel is "dominated" by the blended Gaussian of largest weight
+ * w = alpha T (the first of equal maxima in depth order).  For every pixel
+ * with at least one blended Gaussian and a positive sensor depth D (a
+ * non-positive depth is a missing measurement and does not count), the
+ * dominating Gaussian i receives w (D - d_i)^2 into nu_sum[i] and 1 into
+ * nu_count[i]; both are accumulated (+=), so calling this once per keyframe
+ * of a window gives the numerator and the denominator M_1 + ... + M_k of
+ * Eq. 13.  Optional per-pixel outputs: dominant[H][W] = the dominating
+ * Gaussian's index or -1, dominant_margin[H][W] = (w1 - w2) / w1 against the
+ * runner-up weight w2 (w2 = 0 if there is none; DBL_MAX if no Gaussian is
+ * blended).  Candidate mode as in orc_render. */
+int orc_gaussian_uncertainty(const orc_gaussians *g, const orc_camera *cam, const orc_pose *pose,
+                             const double *depth_obs, int candidates, double *nu_sum,
+                             int64_t *nu_count, int32_t *dominant, double *dominant_margin);
 
 /* SE(3) exponential of xi = (rho, phi): T = [exp(phi^), V(phi) rho]. */
 void orc_se3_exp(const double xi[6], double R[9], double t[3]);

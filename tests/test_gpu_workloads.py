@@ -5,7 +5,8 @@ and every parameter gradient of the uncertainty-weighted mapping loss.
 Batched mapping: 1M Gaussians, 8 keyframe views along a random walk, one
 launch sequence vs 8 single-view ones, sampled pixels vs the oracle.
 Batched tracking: 1M Gaussians, 32 frames of uneven resolution in one
-launch sequence, per-frame pose gradients vs the oracle, and a 20-step
+launch sequence, per-frame pose gradients vs the oracle's analytic
+backward and (one frame) its frozen-decision central differences, and a 20-step
 graph-captured Adam loop vs the same loop run eagerly.
 Tolerances and the decision-margin masking are those of test_gpu_parity.
 """
@@ -165,6 +166,15 @@ def test_batched_tracking_32_frames(R):
         e = np.abs(dposes[v].cpu().numpy() - rb["pose"]).max() / np.abs(rb["pose"]).max()
         say("frame", v, cam["width"], "x", cam["height"], "pose grad rel err", e)
         assert e <= 2e-3
+    # one frame against frozen-decision central differences of the oracle
+    v = next((k for k, c in enumerate(cams) if c["width"] == 320), 0)
+    cam = cams[v]
+    ref = oracle.render(sc, cam, start[v])
+    _, dimg = oracle.tracking_loss(ref, tc[v].cpu().numpy(), td[v].cpu().numpy())
+    fd = oracle.fd_linear(sc, cam, start[v], None, dimg, [("pose", 0, c) for c in range(6)])
+    e = np.abs(dposes[v].cpu().numpy() - fd).max() / np.abs(fd).max()
+    say("frame", v, cam["width"], "x", cam["height"], "pose grad vs frozen FD rel err", e)
+    assert e <= 2e-3
     # 20-step Adam loop captured in one graph vs the same loop eagerly
     params = R.adam_params()
     Pe, ae = P0.clone(), torch.zeros((32, 16), device="cuda")
