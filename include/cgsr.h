@@ -161,7 +161,44 @@ cgsr_status cgsr_render(cgsr_state *st, const cgsr_gaussians *g, int32_t n_views
                         const cgsr_images *outs, void *stream);
 
 /*
- * Backward of the last cgsr_render on this state: chain rule of Eq. 2-10 to
+ * cgsr_render plus the per-Gaussian depth uncertainty of Sec. 3.2, Eq. 13,
+ * taken in the same blend pass.  A pixel is "dominated" by its blended
+ * Gaussian of largest weight w = alpha T (the first of equal maxima in depth
+ * order).  For every pixel with a blended Gaussian and a sensor depth D > 0
+ * (D <= 0 marks a missing measurement), the dominating Gaussian i receives
+ * w (D - d_i)^2 into nu_sum[i] and 1 into nu_count[i], d_i being its camera
+ * depth in that view.  Rendering the k keyframes of a window, in one call or
+ * several, accumulates the numerator and the denominator M_1 + ... + M_k of
+ * Eq. 13; cgsr_nu_prune forms nu.
+ *   depth_obs  required: a sensor depth map for every view.
+ *   dominant   host array of n_views device int32[H][W] maps (each may be
+ *              NULL) receiving the dominating Gaussian's index or -1; or NULL.
+ *   nu_sum     device float[n] (+=), nu_count device uint32[n] (+=); both or
+ *              neither.  The caller clears them at the start of a window.
+ * Other arguments, the saved state and cgsr_backward as for cgsr_render.
+ * The sums use float atomics, so their rounding depends on the order.
+ */
+cgsr_status cgsr_render_nu(cgsr_state *st, const cgsr_gaussians *g, int32_t n_views, const float *poses,
+                           const cgsr_camera *cams, const float *const *depth_obs, const cgsr_images *outs,
+                           int32_t *const *dominant, float *nu_sum, uint32_t *nu_count, void *stream);
+
+/*
+ * Per-Gaussian uncertainty and pruning (Sec. 3.2, Eq. 13): for i < n,
+ * nu_i = nu_sum[i] / nu_count[i], or 0 when the Gaussian dominated no pixel
+ * (no evidence).  Gaussians with nu_i > tau (the paper uses 0.025) have their
+ * opacity lowered to low_opacity: opacity_logits[i] = min(opacity_logits[i],
+ * logit(low_opacity)), never raised, so they can still recover or be removed
+ * by later optimisation.  Optional outputs (device, may be NULL): nu [n]
+ * (overwritten), n_pruned (a uint32 counter, += number of Gaussians over tau).
+ * opacity_logits (device, in place) may be NULL to only evaluate nu.
+ * Errors: n < 0, missing accumulators, tau < 0, low_opacity outside (0, 1).
+ */
+cgsr_status cgsr_nu_prune(int64_t n, const float *nu_sum, const uint32_t *nu_count, float tau,
+                          float low_opacity, float *opacity_logits, float *nu, uint32_t *n_pruned,
+                          void *stream);
+
+/*
+ * Backward of the last cgsr_render (or cgsr_render_nu) on this state: chain rule of Eq. 2-10 to
  * every Gaussian parameter (accumulated over views) and to each view's pose.
  *   dimgs   host array of n_views upstream gradients (device maps; NULL fields
  *           are zero).  An uncertainty gradient needs that view's sensor depth.

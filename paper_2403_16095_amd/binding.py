@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "CGSR_OK", -1: "CGSR_ERR_INVALID_ARG", -2: "CGSR_ERR_OOM", -3
 
 EXPORTED = (
     "cgsr_default_settings", "cgsr_state_create", "cgsr_state_destroy", "cgsr_state_reserve",
-    "cgsr_render", "cgsr_backward", "cgsr_tracking_loss_grad", "cgsr_mapping_loss_grad", "cgsr_pose_adam_step",
+    "cgsr_render", "cgsr_render_nu", "cgsr_nu_prune", "cgsr_backward", "cgsr_tracking_loss_grad", "cgsr_mapping_loss_grad", "cgsr_pose_adam_step",
     "cgsr_tracking_step",
     "cgsr_autotune_tracking", "cgsr_state_check", "cgsr_get_stats", "cgsr_get_timings", "cgsr_debug_buffers",
     "cgsr_last_error",
@@ -105,6 +105,9 @@ def lib() -> C.CDLL:
     L.cgsr_state_reserve.argtypes = [vp, C.c_int64, C.c_int64, C.c_int64, C.c_int64]
     L.cgsr_render.argtypes = [vp, C.POINTER(cgsr_gaussians), C.c_int32, vp, C.POINTER(cgsr_camera),
                               C.POINTER(vp), C.POINTER(cgsr_images), vp]
+    L.cgsr_render_nu.argtypes = [vp, C.POINTER(cgsr_gaussians), C.c_int32, vp, C.POINTER(cgsr_camera),
+                                 C.POINTER(vp), C.POINTER(cgsr_images), C.POINTER(vp), vp, vp, vp]
+    L.cgsr_nu_prune.argtypes = [C.c_int64, vp, vp, C.c_float, C.c_float, vp, vp, vp, vp]
     L.cgsr_backward.argtypes = [vp, C.POINTER(cgsr_images), C.POINTER(cgsr_gaussian_grads), vp, vp]
     L.cgsr_tracking_loss_grad.argtypes = [C.c_int32, C.c_int32, vp, vp, vp, vp, C.c_float, C.c_float, vp, vp,
                                           vp, vp]
@@ -164,6 +167,22 @@ def cgsr_render(state: int, g: cgsr_gaussians, n_views: int, poses: int, cams, d
     out_arr = (cgsr_images * n_views)(*outs)
     dep = None if depth_obs is None else (C.c_void_p * n_views)(*[p or None for p in depth_obs])
     _check(lib().cgsr_render(state, C.byref(g), n_views, poses, cam_arr, dep, out_arr, stream))
+
+
+def cgsr_render_nu(state: int, g: cgsr_gaussians, n_views: int, poses: int, cams, depth_obs, outs, dominant,
+                   nu_sum, nu_count, stream: int) -> None:
+    """depth_obs: sequence of device pointers (required); dominant: sequence of
+    device pointers (0/None allowed) or None."""
+    cam_arr = (cgsr_camera * n_views)(*cams)
+    out_arr = (cgsr_images * n_views)(*outs)
+    dep = (C.c_void_p * n_views)(*depth_obs)
+    dom = None if dominant is None else (C.c_void_p * n_views)(*[p or None for p in dominant])
+    _check(lib().cgsr_render_nu(state, C.byref(g), n_views, poses, cam_arr, dep, out_arr, dom, nu_sum, nu_count,
+                                stream))
+
+
+def cgsr_nu_prune(n, nu_sum, nu_count, tau, low_opacity, opacity_logits, nu, n_pruned, stream) -> None:
+    _check(lib().cgsr_nu_prune(n, nu_sum, nu_count, tau, low_opacity, opacity_logits, nu, n_pruned, stream))
 
 
 def cgsr_backward(state: int, dimgs, dG: cgsr_gaussian_grads | None, dposes: int | None, stream: int) -> None:

@@ -5,6 +5,7 @@
 // -> segment sort (depth order per tile, tile ranges) -> blend.
 // Backward: blend backward -> projection backward (parameters, pose).
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -239,6 +240,9 @@ RasterBufs raster_bufs(cgsr_state* st, int slot) {
   rb.rec_grad = st->rec_grad;
   rb.lambda_color = rb.lambda_depth = 0.f;
   rb.loss = nullptr;
+  rb.nu_sum = nullptr;
+  rb.nu_count = nullptr;
+  rb.nu = false;
   rb.views = ViewTable{st->io[slot].dev, st->n_views, (int32_t)st->g.n};
   rb.total_tiles = st->total_tiles;
   return rb;
@@ -407,6 +411,9 @@ struct RenderArgs {
   bool track;
   float lambda_color, lambda_depth;
   float* loss;
+  bool nu;             // track dominated pixels (Eq. 13)
+  float* nu_sum;
+  uint32_t* nu_count;
 };
 
 // Projection -> tile-count scan -> emission -> segment sort -> blend.
@@ -482,6 +489,9 @@ cgsr_status render_impl(cgsr_state* st, const RenderArgs& a, hipStream_t stream)
   rb.lambda_color = a.lambda_color;
   rb.lambda_depth = a.lambda_depth;
   rb.loss = a.loss;
+  rb.nu = a.nu;
+  rb.nu_sum = a.nu_sum;
+  rb.nu_count = a.nu_count;
   launch_raster_forward(rb, a.track, st->settings.fwd_pixels_per_lane, stream);
   HIP_TRY(hipGetLastError());
   if ((s = mark(CGSR_STAGE_BLEND_FWD + 1))) return s;
@@ -519,10 +529,15 @@ bool bad_adam(const cgsr_adam_params* p) {
 
 extern "C" {
 
-cgsr_status cgsr_render(cgsr_state* st, const cgsr_gaussians* g, int32_t n_views, const float* poses,
-                        const cgsr_camera* cams, const float* const* depth_obs, const cgsr_images* outs,
-                        void* stream) {
-  if (!st || !outs) return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: NULL argument");
+}  // extern "C"
+
+namespace {
+
+cgsr_status render_entry(const char* name, cgsr_state* st, const cgsr_gaussians* g, int32_t n_views,
+                         const float* poses, const cgsr_camera* cams, const float* const* depth_obs,
+                         const cgsr_images* outs, bool nu, int32_t* const* dominant, float* nu_sum,
+                         uint32_t* nu_count, void* stream) {
+  if (!st || !outs) return fail(CGSR_ERR_INVALID_ARG, "%s: NULL argument", name);
   ViewIO io[CGSR_MAX_VIEWS];
   int64_t tiles = 0, pixels = 0;
   cgsr_status s = check_views(g, n_views, poses, cams, io, &tiles, &pixels);
@@ -535,10 +550,48 @@ cgsr_status cgsr_render(cgsr_state* st, const cgsr_gaussians* g, int32_t n_views
     io[v].depth_median = outs[v].depth_median;
     io[v].uncertainty = outs[v].uncertainty;
     if (io[v].uncertainty && !io[v].depth_obs)
-      return fail(CGSR_ERR_INVALID_ARG, "cgsr_render: view %d asks for uncertainty without sensor depth", v);
+      return fail(CGSR_ERR_INVALID_ARG, "%s: view %d asks for uncertainty without sensor depth", name, v);
+    if (nu) {
+      if (!io[v].depth_obs) return fail(CGSR_ERR_INVALID_ARG, "%s: view %d has no sensor depth", name, v);
+      io[v].dominant = dominant ? dominant[v] : nullptr;
+    }
   }
-  return render_impl(st, RenderArgs{g, n_views, poses, io, tiles, pixels, false, 0.f, 0.f, nullptr},
+  return render_impl(st, RenderArgs{g, n_views, poses, io, tiles, pixels, false, 0.f, 0.f, nullptr, nu, nu_sum,
+                                    nu_count},
                      (hipStream_t)stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+cgsr_status cgsr_render(cgsr_state* st, const cgsr_gaussians* g, int32_t n_views, const float* poses,
+                        const cgsr_camera* cams, const float* const* depth_obs, const cgsr_images* outs,
+                        void* stream) {
+  return render_entry("cgsr_render", st, g, n_views, poses, cams, depth_obs, outs, false, nullptr, nullptr, nullptr,
+                      stream);
+}
+
+cgsr_status cgsr_render_nu(cgsr_state* st, const cgsr_gaussians* g, int32_t n_views, const float* poses,
+                           const cgsr_camera* cams, const float* const* depth_obs, const cgsr_images* outs,
+                           int32_t* const* dominant, float* nu_sum, uint32_t* nu_count, void* stream) {
+  if (!depth_obs) return fail(CGSR_ERR_INVALID_ARG, "cgsr_render_nu: sensor depth is required");
+  if ((nu_sum == nullptr) != (nu_count == nullptr))
+    return fail(CGSR_ERR_INVALID_ARG, "cgsr_render_nu: give both nu_sum and nu_count, or neither");
+  return render_entry("cgsr_render_nu", st, g, n_views, poses, cams, depth_obs, outs, true, dominant, nu_sum,
+                      nu_count, stream);
+}
+
+cgsr_status cgsr_nu_prune(int64_t n, const float* nu_sum, const uint32_t* nu_count, float tau, float low_opacity,
+                          float* opacity_logits, float* nu, uint32_t* n_pruned, void* stream) {
+  if (n < 0) return fail(CGSR_ERR_INVALID_ARG, "cgsr_nu_prune: negative count");
+  if (n > 0 && (!nu_sum || !nu_count)) return fail(CGSR_ERR_INVALID_ARG, "cgsr_nu_prune: NULL accumulator");
+  if (!(tau >= 0.f) || !(low_opacity > 0.f && low_opacity < 1.f))
+    return fail(CGSR_ERR_INVALID_ARG, "cgsr_nu_prune: need tau >= 0 and 0 < low_opacity < 1");
+  const float low_logit = (float)std::log((double)low_opacity / (1.0 - (double)low_opacity));
+  launch_nu_prune(n, nu_sum, nu_count, tau, low_logit, opacity_logits, nu, n_pruned, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return CGSR_OK;
 }
 
 cgsr_status cgsr_backward(cgsr_state* st, const cgsr_image_grads* dimgs, const cgsr_gaussian_grads* dG,
@@ -590,7 +643,8 @@ cgsr_status cgsr_tracking_step(cgsr_state* st, const cgsr_gaussians* g, int32_t 
     io[v].t_color = target_color[v];
     io[v].t_depth = target_depth[v];
   }
-  s = render_impl(st, RenderArgs{g, n_views, poses, io, tiles, pixels, true, lambda_color, lambda_depth, loss},
+  s = render_impl(st, RenderArgs{g, n_views, poses, io, tiles, pixels, true, lambda_color, lambda_depth, loss, false,
+                                  nullptr, nullptr},
                   stream);
   if (s) return s;
   if (!dposes && !adam) return CGSR_OK;

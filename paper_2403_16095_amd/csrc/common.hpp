@@ -45,6 +45,7 @@ struct ViewIO {
   float* opacity;
   float* depth_median;
   float* uncertainty;
+  int32_t* dominant;        // [H][W] Gaussian of largest weight (Eq. 13) or -1, or null
   const float* g_color;     // upstream gradients (backward)
   const float* g_depth;
   const float* g_opacity;

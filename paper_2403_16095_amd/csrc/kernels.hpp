@@ -90,9 +90,19 @@ struct RasterBufs {
   int32_t total_tiles;
   float lambda_color, lambda_depth;  // tracking loss weights (Eq. 19)
   float* loss;              // [views] tracking loss (+=) or null
+  // Eq. 13 accumulation (mapping renders): per Gaussian, sum of w (D - d)^2
+  // over its dominated pixels and their number (+=); nu selects the kernel
+  // variant that tracks each pixel's largest-weight Gaussian.
+  float* nu_sum;
+  uint32_t* nu_count;
+  bool nu;
 };
 // ppl: pixels per lane, 1, 2 or 4 (256 / ppl lanes per 16x16 tile).
 void launch_raster_forward(const RasterBufs& b, bool track, int ppl, hipStream_t s);
+// nu_i = nu_sum_i / nu_count_i (0 without dominated pixels); Gaussians with
+// nu_i > tau get opacity_logit = min(opacity_logit, low_logit).
+void launch_nu_prune(int64_t n, const float* nu_sum, const uint32_t* nu_count, float tau, float low_logit,
+                     float* opacity_logits, float* nu, uint32_t* n_pruned, hipStream_t s);
 void launch_raster_backward(const RasterBufs& b, bool param_grads, bool track, int ppl, hipStream_t s);
 
 void launch_tracking_loss(int w, int h, const float* color, const float* depth, const float* tcolor,

@@ -9,6 +9,11 @@
 // uses it for all of its pixels.  A pair below the skip threshold costs one
 // base-2 exponent and a compare; only blended pairs evaluate exp2.
 //
+// kNu (mapping renders) also keeps, per pixel, the blended Gaussian of
+// largest weight alpha T -- the pixel is "dominated" by it (Sec. 3.2,
+// Eq. 13) -- and at the end adds w (D - d)^2 and 1 to that Gaussian's
+// uncertainty sum and count when the pixel has a sensor depth D > 0.
+//
 // Tracking mode (kTrack) forms the gradient images of the tracking loss
 // (Eq. 19: L1 colour, Eq. 14, and L1 depth, Eq. 16) at the end of the
 // forward, straight from the blended values in registers, and keeps them in
@@ -19,6 +24,7 @@ namespace cgsr {
 namespace {
 
 constexpr int kBatch = 256;
+constexpr uint32_t kNone = 0xffffffffu;
 
 struct PixelCoord {
   int px, py;
@@ -39,12 +45,13 @@ __device__ __forceinline__ PixelCoord pixel_of(const ViewInfo& cam, int gtile, i
 
 __device__ __forceinline__ float sgn(float x) { return (float)((x > 0.f) - (x < 0.f)); }
 
-template <int kPPL, bool kTrack>
+template <int kPPL, bool kTrack, bool kNu>
 __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(RasterBufs b) {
   constexpr int L = kTilePixels / kPPL;
   __shared__ float4 sA[kBatch];
   __shared__ float4 sB[kBatch];
   __shared__ float4 sC[kBatch];
+  __shared__ uint32_t sM[kNu ? kBatch : 1];
   const int gtile = blockIdx.x;
   const int v = view_of_tile(b.views, gtile);
   const ViewIO io = b.views.io[v];
@@ -57,6 +64,8 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(Rast
   int64_t pix[kPPL];
   int med[kPPL];
   uint32_t last[kPPL], evaluated[kPPL], blended[kPPL];
+  float wdom[kPPL], ddom[kPPL];   // kNu: largest weight so far and its depth
+  uint32_t dom[kPPL];             // kNu: its record id, kNone if none
   bool inside[kPPL], done[kPPL];
   bool lane_done = true;
 #pragma unroll
@@ -72,6 +81,8 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(Rast
     med[k] = -1;
     last[k] = 0;
     blended[k] = 0;
+    wdom[k] = ddom[k] = 0.f;
+    dom[k] = kNone;
     evaluated[k] = range.y - range.x;
     done[k] = !pc.inside;
     lane_done = lane_done && done[k];
@@ -81,6 +92,7 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(Rast
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += L) {
       const uint32_t m = b.vals[base + i];
+      if (kNu) sM[i] = m;
       stage_record(b.rec + (int64_t)kRecF4 * m, sA[i], sB[i], sC[i]);
     }
     __syncthreads();
@@ -116,6 +128,11 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(Rast
           if (med[k] < 0 && Tn < kTMedian) {
             med[k] = (int)(off + j);
             Dmed[k] = B.z;
+          }
+          if (kNu && wgt > wdom[k]) {   // strict: the first of equal maxima
+            wdom[k] = wgt;
+            ddom[k] = B.z;
+            dom[k] = sM[j];
           }
           T[k] = Tn;
           last[k] = off + j + 1;
@@ -166,6 +183,16 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(Rast
     if (io.uncertainty) io.uncertainty[p] = U[k];
     b.pixel_state[cam.pixel_base + p] = make_uint4(__float_as_uint(T[k]), last[k], (uint32_t)med[k], evaluated[k]);
     b.pixel_count[cam.pixel_base + p] = blended[k];
+    if (kNu) {
+      // record id m = view * N + Gaussian index
+      const int gi = dom[k] == kNone ? -1 : (int)(dom[k] - (uint32_t)v * (uint32_t)b.views.n_gauss);
+      if (io.dominant) io.dominant[p] = gi;
+      if (gi >= 0 && dobs[k] > 0.f && b.nu_sum) {
+        const float e = dobs[k] - ddom[k];
+        unsafeAtomicAdd(b.nu_sum + gi, wdom[k] * e * e);
+        atomicAdd(b.nu_count + gi, 1u);
+      }
+    }
   }
 }
 
@@ -340,8 +367,9 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
 template <int kPPL>
 void launch_fwd(const RasterBufs& b, bool track, hipStream_t s) {
   const dim3 grid(b.total_tiles), block(kTilePixels / kPPL);
-  if (track) hipLaunchKernelGGL((raster_forward_kernel<kPPL, true>), grid, block, 0, s, b);
-  else hipLaunchKernelGGL((raster_forward_kernel<kPPL, false>), grid, block, 0, s, b);
+  if (track) hipLaunchKernelGGL((raster_forward_kernel<kPPL, true, false>), grid, block, 0, s, b);
+  else if (b.nu) hipLaunchKernelGGL((raster_forward_kernel<kPPL, false, true>), grid, block, 0, s, b);
+  else hipLaunchKernelGGL((raster_forward_kernel<kPPL, false, false>), grid, block, 0, s, b);
 }
 
 template <int kPPL>

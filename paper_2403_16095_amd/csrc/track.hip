@@ -1,7 +1,8 @@
 // Sequential-tracking glue kept on the device so a whole tracking iteration
 // can be replayed from a HIP graph: gradient images of the tracking loss
 // (Eq. 19 from Eq. 14 and 16) and the Adam step plus retraction on the pose
-// (Eq. 20).  Also the counters behind cgsr_get_stats.
+// (Eq. 20).  Also the counters behind cgsr_get_stats, and the per-Gaussian
+// uncertainty finalisation and pruning of Sec. 3.2 (Eq. 13).
 #include "kernels.hpp"
 
 namespace cgsr {
@@ -86,6 +87,36 @@ __global__ void pose_adam_kernel(int n_views, float* poses, float* dposes, float
   adam_retract(poses + 12 * v, adam + 16 * v, g, ap);
 }
 
+// nu_i = nu_sum_i / (M_1 + ... + M_k) (Eq. 13), 0 for a Gaussian that
+// dominates no pixel; nu_i > tau lowers its opacity logit to low_logit (it is
+// never raised).  One block-reduced atomic counts the pruned Gaussians.
+__global__ __launch_bounds__(kThreads) void nu_prune_kernel(int64_t n, const float* __restrict__ nu_sum,
+                                                            const uint32_t* __restrict__ nu_count, float tau,
+                                                            float low_logit, float* __restrict__ opacity_logits,
+                                                            float* __restrict__ nu, uint32_t* n_pruned) {
+  __shared__ uint32_t s_part[kThreads / 64];
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  uint32_t pruned = 0;
+  if (i < n) {
+    const uint32_t c = nu_count[i];
+    const float v = c ? nu_sum[i] / (float)c : 0.f;
+    if (nu) nu[i] = v;
+    if (v > tau) {
+      pruned = 1;
+      if (opacity_logits) opacity_logits[i] = fminf(opacity_logits[i], low_logit);
+    }
+  }
+  if (!n_pruned) return;
+  const uint64_t mask = __ballot(pruned);
+  if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = (uint32_t)__popcll(mask);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int k = 0; k < kThreads / 64; ++k) t += s_part[k];
+    if (t) atomicAdd(n_pruned, t);
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void stats_kernel(const uint32_t* __restrict__ tiles, int64_t m,
                                                          const uint4* __restrict__ ps,
                                                          const uint32_t* __restrict__ count, int64_t pixels,
@@ -121,6 +152,13 @@ void launch_mapping_loss(int w, int h, const float* color, const float* depth, c
   const int64_t hw = (int64_t)w * h;
   hipLaunchKernelGGL(mapping_loss_kernel, dim3((unsigned)((hw + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
                      w, h, color, depth, unc, tcolor, tdepth, dcolor, ddepth, dunc, loss);
+}
+
+void launch_nu_prune(int64_t n, const float* nu_sum, const uint32_t* nu_count, float tau, float low_logit,
+                     float* opacity_logits, float* nu, uint32_t* n_pruned, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(nu_prune_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, n,
+                     nu_sum, nu_count, tau, low_logit, opacity_logits, nu, n_pruned);
 }
 
 void launch_pose_adam(int n_views, float* poses, float* dposes, float* adam, const AdamParams& ap, hipStream_t s) {

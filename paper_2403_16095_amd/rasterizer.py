@@ -137,6 +137,59 @@ def render(state: State, scene: dict, poses: torch.Tensor, cams, depth_obs=None,
     return outs
 
 
+#: Pruning threshold on the per-Gaussian uncertainty (Sec. 3.2).
+NU_TAU = 0.025
+#: Opacity a pruned Gaussian is lowered to (reading of "a low-opacity level").
+NU_LOW_OPACITY = 0.01
+
+
+def render_nu(state: State, scene: dict, poses: torch.Tensor, cams, depth_obs, nu_sum: torch.Tensor,
+              nu_count: torch.Tensor, maps=MAP_NAMES, dominant: bool = False):
+    """Render like ``render`` and accumulate the per-Gaussian uncertainty sums
+    of Eq. 13 into nu_sum (float32 [n]) and nu_count (int32 [n], read as
+    uint32 by the library).  Returns (list of map dicts, list of int32 [H, W]
+    dominant-Gaussian maps or None)."""
+    if isinstance(cams, dict):
+        cams = [cams]
+    V = len(cams)
+    poses = poses.reshape(V, 12)
+    _check_f32("poses", poses)
+    g = gaussians_struct(scene)
+    n = g.n
+    _check_f32("nu_sum", nu_sum, (n,))
+    if not (isinstance(nu_count, torch.Tensor) and nu_count.is_cuda and nu_count.dtype == torch.int32
+            and nu_count.is_contiguous() and tuple(nu_count.shape) == (n,)):
+        raise ValueError("nu_count must be a contiguous int32 CUDA tensor of shape [n]")
+    dev = poses.device
+    outs, structs, doms = [], [], []
+    for v, cam in enumerate(cams):
+        H, W = int(cam["height"]), int(cam["width"])
+        _check_f32(f"depth_obs[{v}]", depth_obs[v], (H, W))
+        o = {k: torch.empty((3, H, W) if k == "color" else (H, W), dtype=torch.float32, device=dev) for k in maps}
+        outs.append(o)
+        structs.append(B.cgsr_images(*[_ptr(o.get(k)) for k in MAP_NAMES]))
+        doms.append(torch.empty((H, W), dtype=torch.int32, device=dev) if dominant else None)
+    B.cgsr_render_nu(state.handle, g, V, poses.data_ptr(), [camera_struct(c) for c in cams],
+                     [d.data_ptr() for d in depth_obs], structs, [_ptr(d) for d in doms] if dominant else None,
+                     nu_sum.data_ptr(), nu_count.data_ptr(), _stream())
+    state.n_views, state.n = V, n
+    state.inputs = (scene, poses, depth_obs)
+    return outs, (doms if dominant else None)
+
+
+def nu_prune(nu_sum: torch.Tensor, nu_count: torch.Tensor, tau: float = NU_TAU, low_opacity: float = NU_LOW_OPACITY,
+             opacity_logits: torch.Tensor | None = None):
+    """nu of Eq. 13 from the window's sums and the tau rule of Sec. 3.2 applied
+    in place to opacity_logits (if given).  Returns (nu [n], pruned count
+    as a 1-element int32 device tensor)."""
+    n = nu_sum.shape[0]
+    nu = torch.empty_like(nu_sum)
+    cnt = torch.zeros(1, dtype=torch.int32, device=nu_sum.device)
+    B.cgsr_nu_prune(n, nu_sum.data_ptr(), nu_count.data_ptr(), float(tau), float(low_opacity), _ptr(opacity_logits),
+                    nu.data_ptr(), cnt.data_ptr(), _stream())
+    return nu, cnt
+
+
 def backward(state: State, dimgs, param_grads: bool = True, pose_grads: bool = True):
     """Backward of the last render on ``state``.
 

@@ -57,6 +57,17 @@ def test_host_side_argument_checks(lib):
     assert lib.cgsr_pose_adam_step(1, 8, 8, 8, None, None) == B.CGSR_ERR_INVALID_ARG
     assert lib.cgsr_tracking_step(None, None, 1, None, None, None, None, 1.0, 1.0, None, None, None, None,
                                   None) == B.CGSR_ERR_INVALID_ARG
+    assert lib.cgsr_render_nu(None, None, 1, None, None, None, None, None, None, None,
+                              None) == B.CGSR_ERR_INVALID_ARG
+    # sensor depth is required; nu_sum and nu_count come together
+    assert lib.cgsr_render_nu(8, None, 1, None, None, None, None, None, 8, 8, None) == B.CGSR_ERR_INVALID_ARG
+    dep = (C.c_void_p * 1)(8)
+    assert lib.cgsr_render_nu(8, None, 1, None, None, dep, None, None, 8, None, None) == B.CGSR_ERR_INVALID_ARG
+    assert lib.cgsr_nu_prune(-1, None, None, 0.025, 0.01, None, None, None, None) == B.CGSR_ERR_INVALID_ARG
+    assert lib.cgsr_nu_prune(4, None, None, 0.025, 0.01, None, None, None, None) == B.CGSR_ERR_INVALID_ARG
+    assert lib.cgsr_nu_prune(4, 8, 8, -1.0, 0.01, None, None, None, None) == B.CGSR_ERR_INVALID_ARG
+    assert lib.cgsr_nu_prune(4, 8, 8, 0.025, 1.0, None, None, None, None) == B.CGSR_ERR_INVALID_ARG
+    assert lib.cgsr_nu_prune(4, 8, 8, 0.025, 0.0, None, None, None, None) == B.CGSR_ERR_INVALID_ARG
     assert lib.cgsr_state_check(None, None) == B.CGSR_ERR_INVALID_ARG
     assert lib.cgsr_get_stats(None, None, None) == B.CGSR_ERR_INVALID_ARG
     assert lib.cgsr_state_reserve(None, 1, 1, 1, 1) == B.CGSR_ERR_INVALID_ARG
