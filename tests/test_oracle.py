@@ -411,6 +411,11 @@ def test_paper_constants():
     import inspect
     lam = inspect.signature(oracle.tracking_loss).parameters["lam"].default
     assert list(lam) == paper["tracking_lambda_replica"]["value"]
+    from oracle import mapping
+    assert list(mapping.OMEGA_REPLICA) == paper["mapping_omega_replica"]["value"]
+    assert list(mapping.OMEGA_REAL) == paper["mapping_omega_tum_scannet"]["value"]
+    assert mapping.ISO_EPS == paper["iso_epsilon"]["value"]
+    assert oracle.NU_TAU == paper["uncertainty_prune_tau"]["value"]
     # the median threshold is exercised by the two-Gaussian case above; check
     # a crossing exactly around 0.5 here
     cam = synth.SMALL_CAMERA
