@@ -182,6 +182,51 @@ cgsr_status cgsr_render_nu(cgsr_state *st, const cgsr_gaussians *g, int32_t n_vi
                            const cgsr_camera *cams, const float *const *depth_obs, const cgsr_images *outs,
                            int32_t *const *dominant, float *nu_sum, uint32_t *nu_count, void *stream);
 
+/* Weights of the mapping objective, Eq. 18 (omega_1 .. omega_6), and the
+ * anisotropy level epsilon of Eq. 17.  Sec. 4 uses {0.7, 0.1, 0.25, 0.25,
+ * 0.1, 0.15} on Replica and {1.0, 0.1, 0.8, 0.5, 0.1, 0.5} on TUM and
+ * ScanNet, epsilon = 1.0 (Sec. 3.3). */
+typedef struct {
+    float color, ssim, geo, align, iso, var;
+    float iso_epsilon;
+} cgsr_mapping_weights;
+
+/*
+ * Gradient images of the mapping objective, Eq. 18, for the views of the
+ * last cgsr_render / cgsr_render_nu on this state, and the gradient of its
+ * isotropy term with respect to the log-scales:
+ *   color  L_color = mean over pixels of the L1 over RGB          (Eq. 14)
+ *   ssim   L_ssim  = 1 - SSIM(I^, I): 11x11 Gaussian window of standard
+ *          deviation 1.5, zero padding, C1 = 0.01^2, C2 = 0.03^2, mean over
+ *          channels and pixels (the splatting conventions)         (Eq. 15)
+ *   geo    L_geo   = mean |D^ - D|                                 (Eq. 16)
+ *   align  L_align = mean |D^ - D^_median| over pixels that have a median
+ *          Gaussian (median depth > 0), divided by H W            (Eq. 12)
+ *   iso    L_iso   = mean over the view's visible Gaussians of
+ *          max(max s / min s, epsilon) - epsilon                  (Eq. 17)
+ *   var    L_var   = mean |U|                                      (Eq. 11)
+ * The objective of a window is the sum over its views.
+ *   maps          host array of n_views rendered maps (device; the render's
+ *                 outputs): colour for colour/SSIM, depth for geo/align,
+ *                 depth_median for align, uncertainty for var.
+ *   target_color  host array of n_views device [3][H][W] (or NULL if unused);
+ *   target_depth  host array of n_views device [H][W] (or NULL if unused).
+ *   dimgs         host array of n_views gradient outputs (device, overwritten,
+ *                 opacity unused): color, depth, depth_median, uncertainty.
+ *                 Each term with a non-zero weight needs its outputs; each
+ *                 given output needs the maps and targets of its terms.
+ *                 They are the upstream gradients cgsr_backward then takes.
+ *   dlog_scales   device float[n][3] (+=) gradient of the isotropy term, or
+ *                 NULL.
+ *   loss          device float[n_views] (+=) per-view objective, or NULL.
+ * The Gaussians are the ones the state's last render read.  The first call
+ * with SSIM allocates its scratch (9 floats per pixel of the largest view);
+ * under graph capture that allocation is an error (CGSR_ERR_STATE).
+ */
+cgsr_status cgsr_mapping_objective(cgsr_state *st, const cgsr_mapping_weights *w, const cgsr_images *maps,
+                                   const float *const *target_color, const float *const *target_depth,
+                                   const cgsr_images *dimgs, float *dlog_scales, float *loss, void *stream);
+
 /*
  * Per-Gaussian uncertainty and pruning (Sec. 3.2, Eq. 13): for i < n,
  * nu_i = nu_sum[i] / nu_count[i], or 0 when the Gaussian dominated no pixel

@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "CGSR_OK", -1: "CGSR_ERR_INVALID_ARG", -2: "CGSR_ERR_OOM", -3
 
 EXPORTED = (
     "cgsr_default_settings", "cgsr_state_create", "cgsr_state_destroy", "cgsr_state_reserve",
-    "cgsr_render", "cgsr_render_nu", "cgsr_nu_prune", "cgsr_backward", "cgsr_tracking_loss_grad", "cgsr_mapping_loss_grad", "cgsr_pose_adam_step",
+    "cgsr_render", "cgsr_render_nu", "cgsr_nu_prune", "cgsr_mapping_objective", "cgsr_backward", "cgsr_tracking_loss_grad", "cgsr_mapping_loss_grad", "cgsr_pose_adam_step",
     "cgsr_tracking_step",
     "cgsr_autotune_tracking", "cgsr_state_check", "cgsr_get_stats", "cgsr_get_timings", "cgsr_debug_buffers",
     "cgsr_last_error",
@@ -75,6 +75,11 @@ class cgsr_adam_params(C.Structure):
                 ("eps", C.c_float)]
 
 
+class cgsr_mapping_weights(C.Structure):
+    _fields_ = [("color", C.c_float), ("ssim", C.c_float), ("geo", C.c_float), ("align", C.c_float),
+                ("iso", C.c_float), ("var", C.c_float), ("iso_epsilon", C.c_float)]
+
+
 class cgsr_stats(C.Structure):
     _fields_ = [("visible", C.c_int64), ("pairs", C.c_int64), ("pair_capacity", C.c_int64),
                 ("overflow", C.c_int32), ("n_views", C.c_int32), ("processed", C.c_int64),
@@ -107,6 +112,8 @@ def lib() -> C.CDLL:
                               C.POINTER(vp), C.POINTER(cgsr_images), vp]
     L.cgsr_render_nu.argtypes = [vp, C.POINTER(cgsr_gaussians), C.c_int32, vp, C.POINTER(cgsr_camera),
                                  C.POINTER(vp), C.POINTER(cgsr_images), C.POINTER(vp), vp, vp, vp]
+    L.cgsr_mapping_objective.argtypes = [vp, C.POINTER(cgsr_mapping_weights), C.POINTER(cgsr_images), C.POINTER(vp),
+                                         C.POINTER(vp), C.POINTER(cgsr_images), vp, vp, vp]
     L.cgsr_nu_prune.argtypes = [C.c_int64, vp, vp, C.c_float, C.c_float, vp, vp, vp, vp]
     L.cgsr_backward.argtypes = [vp, C.POINTER(cgsr_images), C.POINTER(cgsr_gaussian_grads), vp, vp]
     L.cgsr_tracking_loss_grad.argtypes = [C.c_int32, C.c_int32, vp, vp, vp, vp, C.c_float, C.c_float, vp, vp,
@@ -179,6 +186,18 @@ def cgsr_render_nu(state: int, g: cgsr_gaussians, n_views: int, poses: int, cams
     dom = None if dominant is None else (C.c_void_p * n_views)(*[p or None for p in dominant])
     _check(lib().cgsr_render_nu(state, C.byref(g), n_views, poses, cam_arr, dep, out_arr, dom, nu_sum, nu_count,
                                 stream))
+
+
+def cgsr_mapping_objective(state: int, weights: cgsr_mapping_weights, maps, target_color, target_depth, dimgs,
+                           dlog_scales, loss, stream: int) -> None:
+    """maps, dimgs: sequences of cgsr_images; target_color/target_depth:
+    sequences of device pointers (0/None allowed) or None."""
+    n = len(maps)
+    m_arr = (cgsr_images * n)(*maps)
+    d_arr = (cgsr_images * n)(*dimgs)
+    tc = None if target_color is None else (C.c_void_p * n)(*[p or None for p in target_color])
+    td = None if target_depth is None else (C.c_void_p * n)(*[p or None for p in target_depth])
+    _check(lib().cgsr_mapping_objective(state, C.byref(weights), m_arr, tc, td, d_arr, dlog_scales, loss, stream))
 
 
 def cgsr_nu_prune(n, nu_sum, nu_count, tau, low_opacity, opacity_logits, nu, n_pruned, stream) -> None:

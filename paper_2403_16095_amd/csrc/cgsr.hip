@@ -82,6 +82,9 @@ struct cgsr_state {
   float4* pixel_grad = nullptr;
   // small buffers
   float* tune_dposes = nullptr;   // [64][6] scratch pose gradients of the autotuner
+  float* obj_part = nullptr;      // SSIM moment derivatives, 9 floats per pixel of one view
+  int64_t cap_obj_pixels = 0;
+  uint32_t* obj_counts = nullptr; // visible Gaussians per view (isotropy term)
   uint32_t* counters = nullptr;
   double* pose_acc = nullptr;
   unsigned long long* stats_dev = nullptr;
@@ -294,6 +297,7 @@ cgsr_status cgsr_state_create(const cgsr_settings* s, cgsr_state** out) {
   }
   if (!r) r = dev_alloc(&st->stats_dev, 4);
   if (!r) r = dev_alloc(&st->tune_dposes, 6 * CGSR_MAX_VIEWS);
+  if (!r) r = dev_alloc(&st->obj_counts, CGSR_MAX_VIEWS);
   for (auto& ev : st->ev_fwd)
     if (!r && hipEventCreate(&ev) != hipSuccess) r = fail(CGSR_ERR_HIP, "hipEventCreate failed");
   for (auto& ev : st->ev_bwd)
@@ -331,6 +335,8 @@ cgsr_status cgsr_state_destroy(cgsr_state* st) {
   dev_free(st->pose_acc);
   dev_free(st->stats_dev);
   dev_free(st->tune_dposes);
+  dev_free(st->obj_counts);
+  dev_free(st->obj_part);
   for (int k = 0; k < 2; ++k) {
     dev_free(st->io[k].dev);
     if (st->io[k].pinned) (void)hipHostFree(st->io[k].pinned);
@@ -735,6 +741,74 @@ cgsr_status cgsr_pose_adam_step(int32_t n_views, float* poses, float* dposes, fl
   launch_pose_adam(n_views, poses, dposes, adam, AdamParams{p->lr_rho, p->lr_phi, p->beta1, p->beta2, p->eps},
                    (hipStream_t)stream);
   HIP_TRY(hipGetLastError());
+  return CGSR_OK;
+}
+
+cgsr_status cgsr_mapping_objective(cgsr_state* st, const cgsr_mapping_weights* w, const cgsr_images* maps,
+                                   const float* const* target_color, const float* const* target_depth,
+                                   const cgsr_images* dimgs, float* dlog_scales, float* loss, void* stream_) {
+  hipStream_t stream = (hipStream_t)stream_;
+  if (!st || !w || !maps || !dimgs) return fail(CGSR_ERR_INVALID_ARG, "cgsr_mapping_objective: NULL argument");
+  if (!st->have_forward) return fail(CGSR_ERR_STATE, "cgsr_mapping_objective: no forward pass on this state");
+  if (st->tracked) return fail(CGSR_ERR_STATE, "cgsr_mapping_objective: the last forward was a tracking step");
+  const float ws[7] = {w->color, w->ssim, w->geo, w->align, w->iso, w->var, w->iso_epsilon};
+  for (float x : ws)
+    if (!std::isfinite(x)) return fail(CGSR_ERR_INVALID_ARG, "cgsr_mapping_objective: non-finite weight");
+  const int n_views = st->n_views;
+  int64_t max_px = 0;
+  for (int v = 0; v < n_views; ++v) {
+    const cgsr_images& m = maps[v];
+    const cgsr_images& d = dimgs[v];
+    const float* tc = target_color ? target_color[v] : nullptr;
+    const float* td = target_depth ? target_depth[v] : nullptr;
+    const bool bad = ((w->color != 0.f || w->ssim != 0.f) && !d.color) || (d.color && (!m.color || !tc)) ||
+                     ((w->geo != 0.f || w->align != 0.f) && !d.depth) || (d.depth && (!m.depth || !td)) ||
+                     ((w->align != 0.f || d.depth_median) && (!m.depth_median || !m.depth)) ||
+                     (w->var != 0.f && !d.uncertainty) || (d.uncertainty && !m.uncertainty);
+    if (bad)
+      return fail(CGSR_ERR_INVALID_ARG, "cgsr_mapping_objective: view %d lacks a map, target or gradient output "
+                  "that its weighted terms need", v);
+    max_px = std::max<int64_t>(max_px, (int64_t)st->io_fwd[v].info.width * st->io_fwd[v].info.height);
+  }
+  cgsr_status s = set_device(st);
+  if (s) return s;
+  if (w->ssim != 0.f && max_px > st->cap_obj_pixels) {
+    hipStreamCaptureStatus capturing = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(stream, &capturing));
+    if (capturing != hipStreamCaptureStatusNone)
+      return fail(CGSR_ERR_STATE, "cgsr_mapping_objective: SSIM scratch too small for graph capture; run once first");
+    HIP_TRY(hipDeviceSynchronize());
+    dev_free(st->obj_part);
+    st->cap_obj_pixels = 0;
+    if ((s = dev_alloc(&st->obj_part, 9 * max_px))) return s;
+    st->cap_obj_pixels = max_px;
+  }
+  const ObjectiveWeights ow{w->color, w->ssim, w->geo, w->align, w->iso, w->var};
+  for (int v = 0; v < n_views; ++v) {
+    const cgsr_images& m = maps[v];
+    const cgsr_images& d = dimgs[v];
+    ObjectiveView o;
+    o.width = st->io_fwd[v].info.width;
+    o.height = st->io_fwd[v].info.height;
+    o.color = m.color;
+    o.depth = m.depth;
+    o.median = (w->align != 0.f || d.depth_median) ? m.depth_median : nullptr;
+    o.unc = m.uncertainty;
+    o.tcolor = target_color ? target_color[v] : nullptr;
+    o.tdepth = target_depth ? target_depth[v] : nullptr;
+    o.dcolor = d.color;
+    o.ddepth = d.depth;
+    o.dmedian = d.depth_median;
+    o.dunc = d.uncertainty;
+    o.loss = loss ? loss + v : nullptr;
+    launch_objective_view(o, ow, st->obj_part, stream);
+    HIP_TRY(hipGetLastError());
+  }
+  if (w->iso != 0.f) {
+    launch_iso(st->g.n, n_views, st->tiles, st->obj_counts, st->g.log_scales, w->iso, w->iso_epsilon, dlog_scales,
+               loss, stream);
+    HIP_TRY(hipGetLastError());
+  }
   return CGSR_OK;
 }
 

@@ -99,6 +99,24 @@ struct RasterBufs {
 };
 // ppl: pixels per lane, 1, 2 or 4 (256 / ppl lanes per 16x16 tile).
 void launch_raster_forward(const RasterBufs& b, bool track, int ppl, hipStream_t s);
+// One view of the mapping objective (Eq. 18).  Inputs: rendered maps and
+// targets; outputs (null = not wanted): gradient images, overwritten, and the
+// view's loss (+=).  median != null enables the alignment term (it then
+// needs depth), dcolor the colour L1 and SSIM terms, ddepth the depth L1.
+struct ObjectiveView {
+  int width, height;
+  const float *color, *depth, *median, *unc, *tcolor, *tdepth;
+  float *dcolor, *ddepth, *dmedian, *dunc, *loss;
+};
+struct ObjectiveWeights {
+  float color, ssim, geo, align, iso, var;
+};
+// ssim_part: scratch of 9 floats per pixel of the view.
+void launch_objective_view(const ObjectiveView& o, const ObjectiveWeights& w, float* ssim_part, hipStream_t s);
+// Eq. 17 over each view's visible Gaussians (tiles[v * n + i] > 0): counts
+// (scratch, n_views words), dlog_scales (+=, may be null), loss[v] (+=).
+void launch_iso(int64_t n, int n_views, const uint32_t* tiles, uint32_t* counts, const float* log_scales, float w_iso,
+                float eps, float* dlog_scales, float* loss, hipStream_t s);
 // nu_i = nu_sum_i / nu_count_i (0 without dominated pixels); Gaussians with
 // nu_i > tau get opacity_logit = min(opacity_logit, low_logit).
 void launch_nu_prune(int64_t n, const float* nu_sum, const uint32_t* nu_count, float tau, float low_logit,

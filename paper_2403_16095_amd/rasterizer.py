@@ -190,6 +190,48 @@ def nu_prune(nu_sum: torch.Tensor, nu_count: torch.Tensor, tau: float = NU_TAU, 
     return nu, cnt
 
 
+#: Eq. 18 weights (colour, ssim, geo, align, iso, var), Sec. 4.
+MAPPING_OMEGA_REPLICA = (0.7, 0.1, 0.25, 0.25, 0.1, 0.15)
+MAPPING_OMEGA_TUM_SCANNET = (1.0, 0.1, 0.8, 0.5, 0.1, 0.5)
+#: Eq. 17 anisotropy level (Sec. 3.3).
+ISO_EPSILON = 1.0
+
+
+def mapping_objective(state: State, maps, target_colors, target_depths, omega=MAPPING_OMEGA_REPLICA,
+                      iso_epsilon: float = ISO_EPSILON, dlog_scales: torch.Tensor | None = None,
+                      loss: torch.Tensor | None = None):
+    """Gradient images of Eq. 18 for the views of the last render on ``state``.
+
+    maps: list (one per view) of dicts with the rendered colour, depth,
+    depth_median and uncertainty the weighted terms need.  Returns a list of
+    dicts of gradient images (colour, depth, depth_median, uncertainty, as
+    the weights need them) to hand to ``backward``; the isotropy gradient is
+    added into dlog_scales ([n, 3]) and the per-view objective into loss
+    ([V]) when given."""
+    w = B.cgsr_mapping_weights(*[float(x) for x in omega], float(iso_epsilon))
+    V = len(maps)
+    if V != state.n_views:
+        raise ValueError(f"expected {state.n_views} views of maps, got {V}")
+    outs, m_s, d_s = [], [], []
+    for m in maps:
+        d = {}
+        if omega[0] != 0 or omega[1] != 0:
+            d["color"] = torch.empty_like(m["color"])
+        if omega[2] != 0 or omega[3] != 0:
+            d["depth"] = torch.empty_like(m["depth"])
+        if omega[3] != 0:
+            d["depth_median"] = torch.empty_like(m["depth"])
+        if omega[5] != 0:
+            d["uncertainty"] = torch.empty_like(m["depth"])
+        outs.append(d)
+        m_s.append(B.cgsr_images(*[_ptr(m.get(k)) for k in MAP_NAMES]))
+        d_s.append(B.cgsr_images(*[_ptr(d.get(k)) for k in MAP_NAMES]))
+    B.cgsr_mapping_objective(state.handle, w, m_s, [_ptr(t) for t in target_colors] if target_colors else None,
+                             [_ptr(t) for t in target_depths] if target_depths else None, d_s, _ptr(dlog_scales),
+                             _ptr(loss), _stream())
+    return outs
+
+
 def backward(state: State, dimgs, param_grads: bool = True, pose_grads: bool = True):
     """Backward of the last render on ``state``.
 
