@@ -80,7 +80,8 @@ def test_objective_kernels_on_synthetic_maps(R, size):
     say("loss gpu", loss.item(), "oracle", L)
     assert abs(loss.item() - L) <= 2e-5 * abs(L)
     for k in ("depth", "depth_median", "uncertainty"):
-        np.testing.assert_array_equal(dimg[k].cpu().numpy(), ref[k].astype(np.float32), err_msg=k)
+        # sign-based terms: equal up to float rounding of the weights / (H W)
+        np.testing.assert_allclose(dimg[k].cpu().numpy(), ref[k], rtol=1e-6, atol=0, err_msg=k)
     gc = dimg["color"].cpu().numpy().astype(np.float64)
     err = np.abs(gc - ref["color"]).max() / np.abs(ref["color"]).max()
     say("colour gradient (L1 + SSIM) max rel err", err)
