@@ -355,10 +355,15 @@ def run_batched_tracking(args, torch, R, synth, frames=32, iters=20):
         def step():
             B.cgsr_tracking_step(st.handle, g, V, pose.data_ptr(), cs, tc, td, float(lam[0]), float(lam[1]),
                                  None, adam.data_ptr(), params, None, R._stream())
+        # Size the pair buffer from an eager run of the same loop (the pair
+        # count moves with the poses), then capture it.
         pose.copy_(pose0)
-        step()
-        torch.cuda.synchronize()
-        st.reserve(pairs=int(st.stats().pairs * 1.5) + 4096)
+        adam.zero_()
+        peak = 0
+        for _ in range(iters):
+            step()
+            peak = max(peak, int(st.stats().pairs))
+        st.reserve(pairs=int(peak * 1.25) + 4096)
         graph = torch.cuda.CUDAGraph()
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
@@ -512,7 +517,9 @@ def main():
     # launch stream, over eager iterations of the same workload.
     stages, stats = {}, None
     if not args.no_stage_timing:
-        tst = R.State(timing=True, fwd_ppl=fppl, bwd_ppl=bppl)
+        # no capacity readback: it would put a host round trip inside the
+        # projection stage's events
+        tst = R.State(sync_capacity=False, timing=True, fwd_ppl=fppl, bwd_ppl=bppl)
         tst.reserve(pairs=solver.state.stats().pairs * 2)
         pose = P0.clone().reshape(1, 12)
         acc = {}

@@ -62,9 +62,10 @@ struct ViewTable {
 };
 
 // Projected record, 3 x float4 per (view, Gaussian):
-//   a = (mu_x, mu_y, conic_a, conic_b)
+//   a = (mu_x, mu_y, conic_a, conic_b)      mu = float nearest the mean
 //   b = (conic_c, opacity, depth, r)
-//   c = (g, b, 0, 0)
+//   c = (g, b, mu_x lo, mu_y lo)             the mean is mu + lo
+// (the projection runs in double; the float pair keeps its mean to ~1e-11 px)
 constexpr int kRecF4 = 3;
 
 // Per-record gradient accumulator with respect to the projected quantities:
@@ -72,7 +73,8 @@ constexpr int kRecF4 = 3;
 constexpr int kGradStride = 12;  // floats per record (48 B, 16-B aligned)
 
 // A record as the blend kernels stage it in LDS, once per (tile, record):
-//   a = (mu_x, mu_y, qa, qb)       qa = -a/2 log2(e), qb = -b log2(e)
+//   a = (mu_x, mu_y, qa, qb)       mean relative to the tile origin (ox, oy),
+//                                  qa = -a/2 log2(e), qb = -b log2(e)
 //   b = (qc, opacity, depth, thr)  qc = -c/2 log2(e), thr = -log2(255 opacity)
 //   c = (r, g, b, -)
 // so that the exponent of Eq. 5 in base 2 is qa dx^2 + qb dx dy + qc dy^2 and
@@ -84,9 +86,16 @@ constexpr int kGradStride = 12;  // floats per record (48 B, 16-B aligned)
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kLn2 = 0.6931471805599453f;
 
-__device__ __forceinline__ void stage_record(const float4* __restrict__ rec, float4& A, float4& B, float4& C) {
+// Pixel coordinates inside the blend kernels are relative to the tile origin
+// too, so dx and dy carry no rounding from large absolute coordinates: the
+// float part minus the origin is exact when the mean lies within a factor of
+// two of the origin (and rounds by an ulp of the difference otherwise, where
+// only wide Gaussians, with small conics, reach the tile); the low part adds
+// the rest.
+__device__ __forceinline__ void stage_record(const float4* __restrict__ rec, float ox, float oy, float4& A, float4& B,
+                                             float4& C) {
   const float4 r0 = rec[0], r1 = rec[1], r2 = rec[2];
-  A = make_float4(r0.x, r0.y, (-0.5f * kLog2e) * r0.z, -kLog2e * r0.w);
+  A = make_float4((r0.x - ox) + r2.z, (r0.y - oy) + r2.w, (-0.5f * kLog2e) * r0.z, -kLog2e * r0.w);
   B = make_float4((-0.5f * kLog2e) * r1.x, r1.y, r1.z, -__log2f(255.0f * r1.y));
   C = make_float4(r1.w, r2.x, r2.y, 0.f);
 }

@@ -38,31 +38,35 @@ __device__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* total, uint32_t* 
 }
 
 // Rotation matrix (row-major) of the unit quaternion (w, x, y, z).
-__device__ __forceinline__ void quat_rot(float w, float x, float y, float z, float R[9]) {
-  R[0] = 1.f - 2.f * (y * y + z * z);
-  R[1] = 2.f * (x * y - w * z);
-  R[2] = 2.f * (x * z + w * y);
-  R[3] = 2.f * (x * y + w * z);
-  R[4] = 1.f - 2.f * (x * x + z * z);
-  R[5] = 2.f * (y * z - w * x);
-  R[6] = 2.f * (x * z - w * y);
-  R[7] = 2.f * (y * z + w * x);
-  R[8] = 1.f - 2.f * (x * x + y * y);
+__device__ __forceinline__ void quat_rot(double w, double x, double y, double z, double R[9]) {
+  R[0] = 1.0 - 2.0 * (y * y + z * z);
+  R[1] = 2.0 * (x * y - w * z);
+  R[2] = 2.0 * (x * z + w * y);
+  R[3] = 2.0 * (x * y + w * z);
+  R[4] = 1.0 - 2.0 * (x * x + z * z);
+  R[5] = 2.0 * (y * z - w * x);
+  R[6] = 2.0 * (x * z - w * y);
+  R[7] = 2.0 * (y * z + w * x);
+  R[8] = 1.0 - 2.0 * (x * x + y * y);
 }
 
-// Everything the forward and backward projection share.
+// Everything the forward and backward projection share.  The projection is
+// evaluated in double precision: it costs a few hundred operations per
+// Gaussian, and single precision would leave pixel-space means near
+// x = 1000 with ~1e-4 px of rounding, which the exponent of Eq. 5 amplifies
+// by the conic times the offset from the mean.
 struct Proj {
-  float qn[4], qinv;     // unit quaternion and 1/|q|
-  float R[9];            // rotation of the ellipsoid
-  float s[3];            // scales
-  float p[3];            // camera-space mean
-  float Sc[6];           // camera covariance W Sigma W^T: 00 01 02 11 12 22
-  float J00, J02, J11, J12;
+  double qn[4], qinv;    // unit quaternion and 1/|q|
+  double R[9];           // rotation of the ellipsoid
+  double s[3];           // scales
+  double p[3];           // camera-space mean
+  double Sc[6];          // camera covariance W Sigma W^T: 00 01 02 11 12 22
+  double J00, J02, J11, J12;
   int clampx, clampy;
-  float tx, ty;          // (possibly clamped) tangents used in J
-  float cov[3];          // Sigma2d xx, xy, yy (dilated)
-  float conic[3];
-  float opacity;
+  double tx, ty;         // (possibly clamped) tangents used in J
+  double cov[3];         // Sigma2d xx, xy, yy (dilated)
+  double conic[3];
+  double opacity;
 };
 
 // Eq. 1-2 for Gaussian i under pose P.  Returns false if the Gaussian is
@@ -71,59 +75,63 @@ struct Proj {
 __device__ bool project_core(const GaussianPtrs& g, int64_t i, const float* P, const ViewInfo& cam,
                              Proj& o) {
   const float4 q = reinterpret_cast<const float4*>(g.quats)[i];
-  const float qn2 = q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w;
-  if (!(qn2 > 0.f) || !(qn2 < 3.0e38f)) return false;
-  o.qinv = 1.0f / sqrtf(qn2);
-  o.qn[0] = q.x * o.qinv; o.qn[1] = q.y * o.qinv; o.qn[2] = q.z * o.qinv; o.qn[3] = q.w * o.qinv;
+  const double q0 = q.x, q1 = q.y, q2 = q.z, q3 = q.w;
+  const double qn2 = q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3;
+  if (!(qn2 > 0.0) || !(qn2 < 1.0e300)) return false;
+  o.qinv = 1.0 / sqrt(qn2);
+  o.qn[0] = q0 * o.qinv; o.qn[1] = q1 * o.qinv; o.qn[2] = q2 * o.qinv; o.qn[3] = q3 * o.qinv;
   quat_rot(o.qn[0], o.qn[1], o.qn[2], o.qn[3], o.R);
   const float* ls = g.log_scales + 3 * i;
-  o.s[0] = expf(ls[0]); o.s[1] = expf(ls[1]); o.s[2] = expf(ls[2]);
+  o.s[0] = exp((double)ls[0]); o.s[1] = exp((double)ls[1]); o.s[2] = exp((double)ls[2]);
   const float* X = g.means + 3 * i;
+  const double X0 = X[0], X1 = X[1], X2 = X[2];
+  double W[9];
 #pragma unroll
-  for (int r = 0; r < 3; ++r)
-    o.p[r] = __builtin_fmaf(P[3 * r + 0], X[0], __builtin_fmaf(P[3 * r + 1], X[1], __builtin_fmaf(P[3 * r + 2], X[2], P[9 + r])));
-  const float z = o.p[2];
-  if (!(z > kNearZ)) return false;
-  o.opacity = 1.0f / (1.0f + expf(-g.opacity_logits[i]));
-  if (!(o.opacity >= kAlphaMin)) return false;
+  for (int k = 0; k < 9; ++k) W[k] = P[k];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) o.p[r] = W[3 * r] * X0 + W[3 * r + 1] * X1 + W[3 * r + 2] * X2 + (double)P[9 + r];
+  const double z = o.p[2];
+  if (!(z > (double)kNearZ)) return false;
+  o.opacity = 1.0 / (1.0 + exp(-(double)g.opacity_logits[i]));
+  if (!(o.opacity >= (double)kAlphaMin)) return false;
   // Sigma = (R S)(R S)^T, then Sc = W Sigma W^T with W the camera rotation.
-  float M[9];
+  double M[9];
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
     for (int k = 0; k < 3; ++k) M[3 * r + k] = o.R[3 * r + k] * o.s[k];
-  float WM[9];
+  double WM[9];
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
-      WM[3 * r + k] = __builtin_fmaf(P[3 * r], M[k], __builtin_fmaf(P[3 * r + 1], M[3 + k], P[3 * r + 2] * M[6 + k]));
+    for (int k = 0; k < 3; ++k) WM[3 * r + k] = W[3 * r] * M[k] + W[3 * r + 1] * M[3 + k] + W[3 * r + 2] * M[6 + k];
   auto dot3 = [&](int r, int c) {
-    return __builtin_fmaf(WM[3 * r], WM[3 * c], __builtin_fmaf(WM[3 * r + 1], WM[3 * c + 1], WM[3 * r + 2] * WM[3 * c + 2]));
+    return WM[3 * r] * WM[3 * c] + WM[3 * r + 1] * WM[3 * c + 1] + WM[3 * r + 2] * WM[3 * c + 2];
   };
   o.Sc[0] = dot3(0, 0); o.Sc[1] = dot3(0, 1); o.Sc[2] = dot3(0, 2);
   o.Sc[3] = dot3(1, 1); o.Sc[4] = dot3(1, 2); o.Sc[5] = dot3(2, 2);
   // Affine projection Jacobian at p with the tangent clamp.
-  const float limx = kTanClamp * 0.5f * (float)cam.width / cam.fx;
-  const float limy = kTanClamp * 0.5f * (float)cam.height / cam.fy;
-  const float zinv = 1.0f / z;
-  float tx = o.p[0] * zinv, ty = o.p[1] * zinv;
+  const double fx = cam.fx, fy = cam.fy;
+  const double limx = (double)kTanClamp * 0.5 * (double)cam.width / fx;
+  const double limy = (double)kTanClamp * 0.5 * (double)cam.height / fy;
+  const double zinv = 1.0 / z;
+  double tx = o.p[0] * zinv, ty = o.p[1] * zinv;
   o.clampx = tx > limx ? 1 : (tx < -limx ? -1 : 0);
   o.clampy = ty > limy ? 1 : (ty < -limy ? -1 : 0);
   if (o.clampx) tx = o.clampx * limx;
   if (o.clampy) ty = o.clampy * limy;
   o.tx = tx; o.ty = ty;
-  o.J00 = cam.fx * zinv;
-  o.J02 = -cam.fx * tx * zinv;
-  o.J11 = cam.fy * zinv;
-  o.J12 = -cam.fy * ty * zinv;
-  const float* S = o.Sc;
-  o.cov[0] = o.J00 * o.J00 * S[0] + 2.f * o.J00 * o.J02 * S[2] + o.J02 * o.J02 * S[5] + kDilation;
+  o.J00 = fx * zinv;
+  o.J02 = -fx * tx * zinv;
+  o.J11 = fy * zinv;
+  o.J12 = -fy * ty * zinv;
+  const double* S = o.Sc;
+  o.cov[0] = o.J00 * o.J00 * S[0] + 2.0 * o.J00 * o.J02 * S[2] + o.J02 * o.J02 * S[5] + (double)kDilation;
   o.cov[1] = o.J00 * o.J11 * S[1] + o.J00 * o.J12 * S[2] + o.J02 * o.J11 * S[4] + o.J02 * o.J12 * S[5];
-  o.cov[2] = o.J11 * o.J11 * S[3] + 2.f * o.J11 * o.J12 * S[4] + o.J12 * o.J12 * S[5] + kDilation;
-  const float det = o.cov[0] * o.cov[2] - o.cov[1] * o.cov[1];
-  if (!(det > 0.f)) return false;
-  const float dinv = 1.0f / det;
+  o.cov[2] = o.J11 * o.J11 * S[3] + 2.0 * o.J11 * o.J12 * S[4] + o.J12 * o.J12 * S[5] + (double)kDilation;
+  const double det = o.cov[0] * o.cov[2] - o.cov[1] * o.cov[1];
+  if (!(det > 0.0)) return false;
+  const double dinv = 1.0 / det;
   o.conic[0] = o.cov[2] * dinv;
   o.conic[1] = -o.cov[1] * dinv;
   o.conic[2] = o.cov[0] * dinv;
@@ -142,22 +150,25 @@ __global__ __launch_bounds__(kThreads) void project_kernel(GaussianPtrs g, const
     uint32_t ntiles = 0;
     Proj o;
     if (project_core(g, i, P, cam, o)) {
-      const float mux = __builtin_fmaf(cam.fx, o.p[0] / o.p[2], cam.cx);
-      const float muy = __builtin_fmaf(cam.fy, o.p[1] / o.p[2], cam.cy);
+      const double mux = (double)cam.fx * (o.p[0] / o.p[2]) + (double)cam.cx;
+      const double muy = (double)cam.fy * (o.p[1] / o.p[2]) + (double)cam.cy;
       // Bounding box of the alpha >= 1/255 ellipse, widened by the margins.
-      const float r2 = __builtin_fmaf(2.0f * logf(255.0f * o.opacity), kBinR2Rel, kBinR2Abs);
-      const float ex = sqrtf(r2 * o.cov[0]), ey = sqrtf(r2 * o.cov[2]);
-      const float u0 = fmaxf(0.f, ceilf(mux - ex)), u1 = fminf((float)(cam.width - 1), floorf(mux + ex));
-      const float v0 = fmaxf(0.f, ceilf(muy - ey)), v1 = fminf((float)(cam.height - 1), floorf(muy + ey));
+      const double r2 = 2.0 * log(255.0 * o.opacity) * (double)kBinR2Rel + (double)kBinR2Abs;
+      const double ex = sqrt(r2 * o.cov[0]), ey = sqrt(r2 * o.cov[2]);
+      const double u0 = fmax(0.0, ceil(mux - ex)), u1 = fmin((double)(cam.width - 1), floor(mux + ex));
+      const double v0 = fmax(0.0, ceil(muy - ey)), v1 = fmin((double)(cam.height - 1), floor(muy + ey));
       if (u0 <= u1 && v0 <= v1) {
         const uint32_t tx0 = (uint32_t)u0 / kTile, tx1 = (uint32_t)u1 / kTile;
         const uint32_t ty0 = (uint32_t)v0 / kTile, ty1 = (uint32_t)v1 / kTile;
         ntiles = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
         const float* c = g.rgb + 3 * i;
         float4* rec = b.rec + kRecF4 * m;
-        rec[0] = make_float4(mux, muy, o.conic[0], o.conic[1]);
-        rec[1] = make_float4(o.conic[2], o.opacity, o.p[2], c[0]);
-        rec[2] = make_float4(c[1], c[2], 0.f, 0.f);
+        // The mean is kept as a float pair hi + lo; the blend kernels take it
+        // relative to their tile's origin, where hi - origin is exact.
+        const float hx = (float)mux, hy = (float)muy;
+        rec[0] = make_float4(hx, hy, (float)o.conic[0], (float)o.conic[1]);
+        rec[1] = make_float4((float)o.conic[2], (float)o.opacity, (float)o.p[2], c[0]);
+        rec[2] = make_float4(c[1], c[2], (float)(mux - (double)hx), (float)(muy - (double)hy));
         b.rect[m] = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
         for (uint32_t ty = ty0; ty <= ty1; ++ty)
           for (uint32_t tx = tx0; tx <= tx1; ++tx)
@@ -250,10 +261,10 @@ __global__ __launch_bounds__(kThreads) void project_backward_kernel(GaussianPtrs
     const float* P = poses + 12 * v;
     Proj o;
     if (project_core(g, i, P, cam, o)) {
-      const float x = o.p[0], y = o.p[1], z = o.p[2];
+      const float x = (float)o.p[0], y = (float)o.p[1], z = (float)o.p[2];
       const float zinv = 1.0f / z, zinv2 = zinv * zinv;
       // dL/dSigma2d = -Q dQ Q with the off-diagonal conic entry counted twice.
-      const float a = o.conic[0], b = o.conic[1], c = o.conic[2];
+      const float a = (float)o.conic[0], b = (float)o.conic[1], c = (float)o.conic[2];
       const float hb = 0.5f * db;
       const float QG00 = a * da + b * hb, QG01 = a * hb + b * dc;
       const float QG10 = b * da + c * hb, QG11 = b * hb + c * dc;
@@ -261,7 +272,7 @@ __global__ __launch_bounds__(kThreads) void project_backward_kernel(GaussianPtrs
       const float A01 = -(QG00 * b + QG01 * c);
       const float A11 = -(QG10 * b + QG11 * c);
       // Sigma2d = J Sc J^T: dSc = J^T A J, dJ = 2 A J Sc.
-      const float J00 = o.J00, J02 = o.J02, J11 = o.J11, J12 = o.J12;
+      const float J00 = (float)o.J00, J02 = (float)o.J02, J11 = (float)o.J11, J12 = (float)o.J12;
       float dS[6];
       dS[0] = J00 * J00 * A00;
       dS[1] = J00 * A01 * J11;
@@ -269,7 +280,9 @@ __global__ __launch_bounds__(kThreads) void project_backward_kernel(GaussianPtrs
       dS[3] = J11 * J11 * A11;
       dS[4] = J11 * (A01 * J02 + A11 * J12);
       dS[5] = J02 * J02 * A00 + 2.f * J02 * J12 * A01 + J12 * J12 * A11;
-      const float* S = o.Sc;
+      float S[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) S[k] = (float)o.Sc[k];
       // (J Sc) rows
       const float JS00 = J00 * S[0] + J02 * S[2], JS02 = J00 * S[2] + J02 * S[5];
       const float JS11 = J11 * S[3] + J12 * S[4], JS12 = J11 * S[4] + J12 * S[5];

@@ -27,7 +27,8 @@ constexpr int kBatch = 256;
 constexpr uint32_t kNone = 0xffffffffu;
 
 struct PixelCoord {
-  int px, py;
+  int px, py;   // absolute pixel
+  int ox, oy;   // tile origin
   bool inside;
 };
 
@@ -37,10 +38,17 @@ __device__ __forceinline__ PixelCoord pixel_of(const ViewInfo& cam, int gtile, i
   const int tx = lt % cam.tiles_x, ty = lt / cam.tiles_x;
   const int w = q >> 6, l = q & 63;
   PixelCoord c;
-  c.px = tx * kTile + (w & 1) * 8 + (l & 7);
-  c.py = ty * kTile + (w >> 1) * 8 + (l >> 3);
+  c.ox = tx * kTile;
+  c.oy = ty * kTile;
+  c.px = c.ox + (w & 1) * 8 + (l & 7);
+  c.py = c.oy + (w >> 1) * 8 + (l >> 3);
   c.inside = c.px < cam.width && c.py < cam.height;
   return c;
+}
+
+__device__ __forceinline__ float2 tile_origin(const ViewInfo& cam, int gtile) {
+  const int lt = gtile - cam.tile_base;
+  return make_float2((float)((lt % cam.tiles_x) * kTile), (float)((lt / cam.tiles_x) * kTile));
 }
 
 __device__ __forceinline__ float sgn(float x) { return (float)((x > 0.f) - (x < 0.f)); }
@@ -56,6 +64,7 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(Rast
   const int v = view_of_tile(b.views, gtile);
   const ViewIO io = b.views.io[v];
   const ViewInfo cam = io.info;
+  const float2 org = tile_origin(cam, gtile);
   const uint2 range = b.ranges[gtile];
   const int64_t hw = (int64_t)cam.width * cam.height;
 
@@ -71,8 +80,8 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(Rast
 #pragma unroll
   for (int k = 0; k < kPPL; ++k) {
     const PixelCoord pc = pixel_of(cam, gtile, k * L + threadIdx.x);
-    fx[k] = (float)pc.px;
-    fy[k] = (float)pc.py;
+    fx[k] = (float)(pc.px - pc.ox);
+    fy[k] = (float)(pc.py - pc.oy);
     inside[k] = pc.inside;
     pix[k] = (int64_t)pc.py * cam.width + pc.px;
     dobs[k] = (!kTrack && io.depth_obs && pc.inside) ? io.depth_obs[pix[k]] : 0.f;
@@ -93,7 +102,7 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(Rast
     for (int i = threadIdx.x; i < n; i += L) {
       const uint32_t m = b.vals[base + i];
       if (kNu) sM[i] = m;
-      stage_record(b.rec + (int64_t)kRecF4 * m, sA[i], sB[i], sC[i]);
+      stage_record(b.rec + (int64_t)kRecF4 * m, org.x, org.y, sA[i], sB[i], sC[i]);
     }
     __syncthreads();
     if (!lane_done) {
@@ -216,6 +225,7 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
   const int v = view_of_tile(b.views, gtile);
   const ViewIO io = b.views.io[v];
   const ViewInfo cam = io.info;
+  const float2 org = tile_origin(cam, gtile);
   const int64_t hw = (int64_t)cam.width * cam.height;
   const uint2 range = b.ranges[gtile];
   const int lane = threadIdx.x & 63;
@@ -229,8 +239,8 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
   for (int k = 0; k < kPPL; ++k) {
     const PixelCoord pc = pixel_of(cam, gtile, k * L + threadIdx.x);
     const int64_t pix = (int64_t)pc.py * cam.width + pc.px;
-    fx[k] = (float)pc.px;
-    fy[k] = (float)pc.py;
+    fx[k] = (float)(pc.px - pc.ox);
+    fy[k] = (float)(pc.py - pc.oy);
     T[k] = 1.f;
     walked[k] = 0;
     med[k] = -1;
@@ -275,7 +285,7 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
     for (int i = threadIdx.x; i < n; i += L) {
       const uint32_t m = b.vals[range.x + start + i];
       sM[i] = m;
-      stage_record(b.rec + (int64_t)kRecF4 * m, sA[i], sB[i], sC[i]);
+      stage_record(b.rec + (int64_t)kRecF4 * m, org.x, org.y, sA[i], sB[i], sC[i]);
     }
     __syncthreads();
     for (int j = n - 1; j >= 0; --j) {

@@ -4,9 +4,13 @@ the FP64 oracle.
 Which Gaussian dominates a pixel is decided by comparing float weights, so
 per-pixel dominant maps are compared where every decision of the pixel is
 clear (the render margins of test_gpu_parity plus a relative gap >= 1e-4
-between the two largest weights).  Per-Gaussian sums and counts are compared
-for every Gaussian that no ambiguous pixel names as dominant on either side;
-the excluded share is asserted small.
+between the two largest weights).  Per-Gaussian sums and counts are then
+checked for every Gaussian: an ambiguous pixel can move at most one count
+and one contribution between the Gaussians it names on either side, and a
+contribution w (D - d)^2 is one summand of the pixel's Eq. 10 uncertainty U,
+so |S_gpu - S_ref| may exceed the float tolerance by at most the summed U of
+the ambiguous pixels that name the Gaussian, and the counts by their number.
+Gaussians that no ambiguous pixel names must match to the float tolerance.
 """
 import sys
 
@@ -44,7 +48,7 @@ def sensor_depth(seed, cam, lo, hi, missing=0.05):
     return D
 
 
-def compare_window(R, sc, cams, poses, depths, max_excluded):
+def compare_window(R, sc, cams, poses, depths):
     """GPU window (one batched call) vs oracle per keyframe; returns GPU sums."""
     n = sc["means"].shape[0]
     scd = {k: t32(v) for k, v in sc.items()}
@@ -55,7 +59,7 @@ def compare_window(R, sc, cams, poses, depths, max_excluded):
     _, doms = R.render_nu(st, scd, P, cams, [t32(d) for d in depths], nu_sum, nu_cnt, maps=("depth",), dominant=True)
     gs, gc = nu_sum.cpu().numpy().astype(np.float64), nu_cnt.cpu().numpy().astype(np.int64)
     o_sum, o_cnt = np.zeros(n), np.zeros(n, np.int64)
-    excluded = set()
+    slack_sum, slack_cnt = np.zeros(n), np.zeros(n, np.int64)
     n_amb = n_px = 0
     for v, (cam, pose, D) in enumerate(zip(cams, poses, depths)):
         D64 = D.astype(np.float64)
@@ -64,21 +68,25 @@ def compare_window(R, sc, cams, poses, depths, max_excluded):
         gd = doms[v].cpu().numpy()
         clear = unambiguous(ref) & (r["margin"] >= DECISION_MARGIN)
         assert np.array_equal(gd[clear], r["dominant"][clear]), f"view {v}: dominant map differs"
-        amb = ~clear
-        excluded |= set(r["dominant"][amb][r["dominant"][amb] >= 0].tolist())
-        excluded |= set(gd[amb][gd[amb] >= 0].tolist())
+        amb = ~clear & (D > 0)
+        U = ref["uncertainty"][amb] * (1 + 1e-3) + 1e-9
+        for ids in (r["dominant"][amb], gd[amb]):
+            ok = ids >= 0
+            np.add.at(slack_sum, ids[ok], U[ok])
+            np.add.at(slack_cnt, ids[ok], 1)
         n_amb += int(amb.sum())
         n_px += amb.size
-    keep = np.ones(n, bool)
-    keep[list(excluded)] = False
     involved = (o_cnt > 0) | (gc > 0)
-    share = (~keep & involved).sum() / max(1, involved.sum())
+    touched = slack_cnt > 0
     say(f"ambiguous pixels {n_amb}/{n_px}; Gaussians with dominated pixels {int(involved.sum())}, "
-        f"excluded {share:.4f}")
-    assert share <= max_excluded
-    assert np.array_equal(gc[keep], o_cnt[keep])
-    err = np.abs(gs[keep] - o_sum[keep]) / np.maximum(np.abs(o_sum[keep]), 1e-3)
-    say("max rel err of nu sums", err.max(initial=0.0))
+        f"named by an ambiguous pixel {int((touched & involved).sum())}")
+    assert np.all(np.abs(gc - o_cnt) <= slack_cnt)
+    tol = 1e-4 * np.abs(o_sum) + 1e-7
+    assert np.all(np.abs(gs - o_sum) <= tol + slack_sum)
+    clean = ~touched
+    assert np.array_equal(gc[clean], o_cnt[clean])
+    err = np.abs(gs[clean] - o_sum[clean]) / np.maximum(np.abs(o_sum[clean]), 1e-3)
+    say("max rel err of clean nu sums", err.max(initial=0.0))
     assert err.max(initial=0.0) <= 1e-4
     return nu_sum, nu_cnt
 
@@ -89,7 +97,7 @@ def test_nu_parity_scene(R):
     cam = synth.SMALL_CAMERA
     poses = [(np.eye(3), np.zeros(3)), (synth.rot_about_axis([0, 1, 0], np.deg2rad(4.0)), np.array([0.05, 0.0, 0.0]))]
     depths = [sensor_depth(1000 + k, cam, 1.5, 4.0) for k in range(2)]
-    compare_window(R, sc, [cam, cam], poses, depths, max_excluded=0.05)
+    compare_window(R, sc, [cam, cam], poses, depths)
 
 
 def test_nu_mapping_size_keyframe_window(R):
@@ -98,7 +106,7 @@ def test_nu_mapping_size_keyframe_window(R):
     cam = synth.MAPPING_CAMERA
     poses = synth.random_walk_poses(7, 4)
     depths = [sensor_depth(2000 + k, cam, 0.5, 5.0) for k in range(4)]
-    nu_sum, nu_cnt = compare_window(R, sc, [cam] * 4, poses, depths, max_excluded=0.05)
+    nu_sum, nu_cnt = compare_window(R, sc, [cam] * 4, poses, depths)
     # one batched window == the keyframes one call at a time
     scd = {k: t32(v) for k, v in sc.items()}
     s2 = torch.zeros_like(nu_sum)

@@ -100,8 +100,10 @@ def test_projection_records_match_oracle(R, config1):
     rec = rec.cpu().numpy().astype(np.float64)
     proj = oracle.project(sc, cam, identity_pose())
     vis = proj["visible"] == 1
-    np.testing.assert_allclose(rec[vis, 0:2], proj["mu"][vis], rtol=0, atol=2e-4)
-    np.testing.assert_allclose(rec[vis, 2:5], proj["conic"][vis], rtol=2e-4, atol=1e-7)
+    # the mean is stored as a float pair (hi, lo) in slots 0-1 and 10-11
+    mu = rec[vis, 0:2].astype(np.float64) + rec[vis, 10:12]
+    np.testing.assert_allclose(mu, proj["mu"][vis], rtol=0, atol=1e-6)
+    np.testing.assert_allclose(rec[vis, 2:5], proj["conic"][vis], rtol=1e-6, atol=1e-9)
     np.testing.assert_allclose(rec[vis, 5], proj["opacity"][vis], rtol=1e-5)
     np.testing.assert_allclose(rec[vis, 6], proj["depth"][vis], rtol=1e-6)
     np.testing.assert_allclose(rec[vis, 7:10], sc["rgb"][vis], rtol=0, atol=0)
