@@ -364,17 +364,31 @@ def run_batched_tracking(args, torch, R, synth, frames=32, iters=20):
             step()
             peak = max(peak, int(st.stats().pairs))
         st.reserve(pairs=int(peak * 1.25) + 4096)
-        graph = torch.cuda.CUDAGraph()
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            with torch.cuda.graph(graph, stream=side):
-                torch.mul(pose0, 1.0, out=pose)
-                adam.zero_()
-                for _ in range(iters):
-                    step()
-        torch.cuda.current_stream().wait_stream(side)
-        torch.cuda.synchronize()
+        for attempt in range(3):
+            graph = torch.cuda.CUDAGraph()
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                with torch.cuda.graph(graph, stream=side):
+                    torch.mul(pose0, 1.0, out=pose)
+                    adam.zero_()
+                    for _ in range(iters):
+                        step()
+            torch.cuda.current_stream().wait_stream(side)
+            st.check()          # starts a clean overflow period
+            graph.replay()
+            torch.cuda.synchronize()
+            s = st.stats()
+            if not s.overflow:
+                break
+            # the replayed trajectory needed more pairs than the eager one:
+            # grow and capture again
+            log(f"frames {vs[0]}..{vs[-1]}: replay needed {s.peak_pairs} pairs (eager peak {peak}); recapturing")
+            try:
+                st.check()
+            except R.B.CgsrError:
+                pass
+            st.reserve(pairs=int(s.peak_pairs * 1.25) + 4096)
         return graph, st, pose
 
     res = {}

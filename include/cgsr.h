@@ -101,13 +101,16 @@ typedef struct {
     int64_t visible;         /* (view, Gaussian) records that reach the image   */
     int64_t pairs;           /* (tile, Gaussian) pairs of the last render       */
     int64_t pair_capacity;   /* pairs the state can hold                         */
-    int32_t overflow;        /* 1 if the last render needed more than capacity   */
+    int32_t overflow;        /* 1 if a render since the last cgsr_state_check
+                                needed more than the capacity                    */
     int32_t n_views;
     int64_t processed;       /* (pixel, list entry) alpha evaluations of the
                                 forward blend, summed over pixels                */
     int64_t blended;         /* (pixel, Gaussian) pairs actually blended          */
     int64_t walked;          /* (pixel, list entry) pairs up to each pixel's last
                                 blended Gaussian: what the backward revisits    */
+    int64_t peak_pairs;      /* most pairs a render needed since the last
+                                cgsr_state_check                                 */
 } cgsr_stats;
 
 /* Stages timed when cgsr_settings.timing is set. */
@@ -333,8 +336,10 @@ cgsr_status cgsr_autotune_tracking(cgsr_state *st, const cgsr_gaussians *g, int3
                                    const float *const *target_depth, int32_t repeats, cgsr_settings *out,
                                    void *stream);
 
-/* Synchronise the stream and report CGSR_ERR_CAPACITY if the last render on
- * this state overflowed its pair buffer. */
+/* Synchronise the stream and report CGSR_ERR_CAPACITY if any render on this
+ * state since the previous check (or since creation) overflowed its pair
+ * buffer; the message names the most pairs a render needed.  The check then
+ * starts a new period (clears the overflow flag and the peak). */
 cgsr_status cgsr_state_check(cgsr_state *st, void *stream);
 
 /* Synchronise the stream and read the counters of the last render. */
@@ -351,7 +356,10 @@ cgsr_status cgsr_get_timings(cgsr_state *st, float *ms_out);
  * | record id, grouped by tile segment (unsorted within it); sorted_values:
  * [pairs] record ids in (tile, depth, record id) order; ranges: [tiles][2]
  * start/end into sorted_values; records: [records][12] float32 projected
- * record (mu_x, mu_y, conic a, b, c, opacity, depth, r, g, b, 0, 0);
+ * record (mu_x, mu_y, a, k, c', opacity, depth, r, g, b, mu_x lo, mu_y lo):
+ * the mean is mu + lo, and the conic (a, b, c) of Eq. 5 is kept in the
+ * completed-square form a (dx + k dy)^2 + c' dy^2 with k = b / a and
+ * c' = c - b^2 / a;
  * pixel_state: [pixels][4] (final T as float bits, list entries up to the
  * last blended one, median position or -1, alpha evaluations). */
 cgsr_status cgsr_debug_buffers(cgsr_state *st, const uint64_t **keys, const uint32_t **sorted_values,

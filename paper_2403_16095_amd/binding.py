@@ -83,7 +83,7 @@ class cgsr_mapping_weights(C.Structure):
 class cgsr_stats(C.Structure):
     _fields_ = [("visible", C.c_int64), ("pairs", C.c_int64), ("pair_capacity", C.c_int64),
                 ("overflow", C.c_int32), ("n_views", C.c_int32), ("processed", C.c_int64),
-                ("blended", C.c_int64), ("walked", C.c_int64)]
+                ("blended", C.c_int64), ("walked", C.c_int64), ("peak_pairs", C.c_int64)]
 
 
 _lib = None

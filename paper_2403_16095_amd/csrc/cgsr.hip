@@ -5,6 +5,7 @@
 // -> segment sort (depth order per tile, tile ranges) -> blend.
 // Backward: blend backward -> projection backward (parameters, pose).
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -461,19 +462,21 @@ cgsr_status render_impl(cgsr_state* st, const RenderArgs& a, hipStream_t stream)
   if ((s = mark(CGSR_STAGE_PROJECT))) return s;
   st->tiles_dirty = true;
   ProjectBufs pb = project_bufs(st);
+  const bool grow = st->settings.sync_capacity && !in_capture;
+  // A render that grows the pair buffer itself must not raise the overflow
+  // flag at the projection's count: it compares against no limit there.
+  if (grow) pb.pair_cap = INT64_MAX;
   launch_project(st->g, a.poses, vt, pb, stream);
   HIP_TRY(hipGetLastError());
-  if (st->settings.sync_capacity && !in_capture) {
+  if (grow) {
     HIP_TRY(hipMemcpyAsync(st->counters_pinned, st->counters, sizeof(uint32_t) * 2, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
     const int64_t need = st->counters_pinned[kCntPairs];
     if (need > st->cap_pairs) {
       s = grow_pairs(st, std::max<int64_t>(need + need / 4, 1 << 16));
       if (s) return s;
-      // The projection flagged an overflow against the old capacity; clear it.
-      launch_clear_u32(st->counters + kCntOverflow, 1, stream);
-      pb = project_bufs(st);
     }
+    pb = project_bufs(st);
   }
   if ((s = mark(CGSR_STAGE_EMIT))) return s;
   launch_emit(vt, pb, stream);
@@ -816,12 +819,15 @@ cgsr_status cgsr_state_check(cgsr_state* st, void* stream) {
   if (!st) return fail(CGSR_ERR_INVALID_ARG, "state is NULL");
   cgsr_status s = set_device(st);
   if (s) return s;
-  HIP_TRY(hipMemcpyAsync(st->counters_pinned, st->counters, sizeof(uint32_t) * 2, hipMemcpyDeviceToHost,
+  HIP_TRY(hipMemcpyAsync(st->counters_pinned, st->counters, sizeof(uint32_t) * 3, hipMemcpyDeviceToHost,
                          (hipStream_t)stream));
   HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
-  if (st->counters_pinned[kCntOverflow])
-    return fail(CGSR_ERR_CAPACITY, "render needed %u pairs, capacity is %lld", st->counters_pinned[kCntPairs],
-                (long long)st->cap_pairs);
+  const uint32_t overflow = st->counters_pinned[kCntOverflow], peak = st->counters_pinned[kCntPeak];
+  // start the next checking period
+  launch_clear_u32(st->counters + kCntOverflow, 2, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  if (overflow)
+    return fail(CGSR_ERR_CAPACITY, "a render needed %u pairs, capacity is %lld", peak, (long long)st->cap_pairs);
   return CGSR_OK;
 }
 
@@ -837,11 +843,12 @@ cgsr_status cgsr_get_stats(cgsr_state* st, void* stream_, cgsr_stats* out) {
   unsigned long long host[4];
   launch_clear_u32(reinterpret_cast<uint32_t*>(st->stats_dev), 8, stream);
   launch_stats(st->tiles, st->records, st->pixel_state, st->pixel_count, st->total_pixels, st->stats_dev, stream);
-  HIP_TRY(hipMemcpyAsync(st->counters_pinned, st->counters, sizeof(uint32_t) * 2, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipMemcpyAsync(st->counters_pinned, st->counters, sizeof(uint32_t) * 3, hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipMemcpyAsync(host, st->stats_dev, sizeof(host), hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
   out->pairs = st->counters_pinned[kCntPairs];
   out->overflow = (int32_t)st->counters_pinned[kCntOverflow];
+  out->peak_pairs = st->counters_pinned[kCntPeak];
   out->visible = (int64_t)host[0];
   out->processed = (int64_t)host[1];
   out->blended = (int64_t)host[2];

@@ -62,10 +62,16 @@ struct ViewTable {
 };
 
 // Projected record, 3 x float4 per (view, Gaussian):
-//   a = (mu_x, mu_y, conic_a, conic_b)      mu = float nearest the mean
-//   b = (conic_c, opacity, depth, r)
+//   a = (mu_x, mu_y, a, k)                  mu = float nearest the mean
+//   b = (c', opacity, depth, r)
 //   c = (g, b, mu_x lo, mu_y lo)             the mean is mu + lo
-// (the projection runs in double; the float pair keeps its mean to ~1e-11 px)
+// The conic (a, b, c) enters as the completed square
+//   a dx^2 + 2 b dx dy + c dy^2 = a (dx + k dy)^2 + c' dy^2,
+//   k = b / a,  c' = c - b^2 / a = 1 / Sigma2d_yy,
+// whose two terms are non-negative: the expanded form cancels for thin,
+// tilted footprints (|2 b dx dy| ~ a dx^2 + c dy^2), and float rounding of its
+// large terms then reached 1e-4 of the exponent.  Both k and c' come from the
+// double-precision projection.
 constexpr int kRecF4 = 3;
 
 // Per-record gradient accumulator with respect to the projected quantities:
@@ -73,12 +79,12 @@ constexpr int kRecF4 = 3;
 constexpr int kGradStride = 12;  // floats per record (48 B, 16-B aligned)
 
 // A record as the blend kernels stage it in LDS, once per (tile, record):
-//   a = (mu_x, mu_y, qa, qb)       mean relative to the tile origin (ox, oy),
-//                                  qa = -a/2 log2(e), qb = -b log2(e)
-//   b = (qc, opacity, depth, thr)  qc = -c/2 log2(e), thr = -log2(255 opacity)
+//   a = (mu_x, mu_y, qa, k)        mean relative to the tile origin (ox, oy),
+//                                  qa = -a/2 log2(e)
+//   b = (qc, opacity, depth, thr)  qc = -c'/2 log2(e), thr = -log2(255 opacity)
 //   c = (r, g, b, -)
-// so that the exponent of Eq. 5 in base 2 is qa dx^2 + qb dx dy + qc dy^2 and
-// a pair is skipped (alpha < 1/255) exactly when that exponent is below thr.
+// so that the exponent of Eq. 5 in base 2 is qa (dx + k dy)^2 + qc dy^2 and a
+// pair is skipped (alpha < 1/255) exactly when that exponent is below thr.
 // The forward and the backward stage and evaluate with these same functions
 // (the library is built without floating-point contraction, every fused
 // multiply-add is explicit), so they take identical skip, cap and stop
@@ -95,17 +101,19 @@ constexpr float kLn2 = 0.6931471805599453f;
 __device__ __forceinline__ void stage_record(const float4* __restrict__ rec, float ox, float oy, float4& A, float4& B,
                                              float4& C) {
   const float4 r0 = rec[0], r1 = rec[1], r2 = rec[2];
-  A = make_float4((r0.x - ox) + r2.z, (r0.y - oy) + r2.w, (-0.5f * kLog2e) * r0.z, -kLog2e * r0.w);
+  A = make_float4((r0.x - ox) + r2.z, (r0.y - oy) + r2.w, (-0.5f * kLog2e) * r0.z, r0.w);
   B = make_float4((-0.5f * kLog2e) * r1.x, r1.y, r1.z, -__log2f(255.0f * r1.y));
   C = make_float4(r1.w, r2.x, r2.y, 0.f);
 }
 
-// Base-2 exponent of a staged record at pixel centre (px, py); dx, dy = mu - p.
+// Base-2 exponent of a staged record at pixel centre (px, py); dx, dy = mu - p
+// and t = dx + k dy.
 __device__ __forceinline__ float pair_exponent(const float4& A, const float4& B, float px, float py, float& dx,
-                                               float& dy) {
+                                               float& dy, float& t) {
   dx = A.x - px;
   dy = A.y - py;
-  return __builtin_fmaf(A.z, dx * dx, __builtin_fmaf(A.w, dx * dy, B.x * (dy * dy)));
+  t = __builtin_fmaf(A.w, dy, dx);
+  return __builtin_fmaf(A.z, t * t, B.x * (dy * dy));
 }
 
 template <int kCtrl, int kRowMask>
@@ -124,6 +132,73 @@ __device__ __forceinline__ float wave_sum(float v) {
   v += dpp_move<0x142, 0xA>(v);  // row_bcast:15
   v += dpp_move<0x143, 0xC>(v);  // row_bcast:31
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+
+// Sums K per-lane values (K <= NV, NV = 8 or 16) over the 64 lanes of a wave
+// at once, by halving the lanes per value while doubling the values per
+// register: a gfx950 permlane32 swap pairs the two wave halves, a permlane16
+// swap pairs rows, row_ror:8 pairs the halves of each row (and, for NV = 16,
+// row_half_mirror pairs the quarters), and the remaining DPP butterflies
+// finish each value inside a group of 64 / NV lanes.  About NV + 2 log2(64 /
+// NV) adds and swaps instead of K full six-step reductions.  Every lane must be
+// active.  Returns, in each lane, the total of value reduced_value_index<NV>
+// (lane), which is the same for the 64 / NV lanes of a group.
+template <int NV>
+__device__ __forceinline__ constexpr int reduced_value_index(int lane) {
+  const int r = lane >> 4;
+  const int qb = NV == 16 ? 2 * ((lane >> 2) & 1) + ((lane >> 3) & 1) : ((lane >> 3) & 1);
+  return 2 * (2 * qb + (r & 1)) + (r >> 1);
+}
+
+// The swaps are written as inline assembly: this compiler's optimiser folds
+// the two results of its permlane-swap builtins into one (the IR adds the
+// first result to itself), which would silently drop half of every sum.  The
+// s_nop pairs give the wait states a VALU write needs before a permlane reads
+// the register, and a permlane write before the next VALU reads it.
+__device__ __forceinline__ float swap_add32(float x, float y) {
+  asm volatile("s_nop 1\n\tv_permlane32_swap_b32 %0, %1\n\ts_nop 1" : "+v"(x), "+v"(y));
+  return x + y;
+}
+
+__device__ __forceinline__ float swap_add16(float x, float y) {
+  asm volatile("s_nop 1\n\tv_permlane16_swap_b32 %0, %1\n\ts_nop 1" : "+v"(x), "+v"(y));
+  return x + y;
+}
+
+template <int NV, int K>
+__device__ __forceinline__ float wave_sum_many(const float (&v)[K]) {
+  static_assert((NV == 8 || NV == 16) && K <= NV, "8 or 16 slots");
+  const int lane = __lane_id();
+  float a[NV / 2];
+#pragma unroll
+  for (int p = 0; p < NV / 2; ++p) {
+    if (2 * p >= K) a[p] = 0.f;                                   // both slots empty
+    else a[p] = swap_add32(v[2 * p], 2 * p + 1 < K ? v[2 * p + 1] : 0.f);
+  }
+  float b[NV / 4];
+#pragma unroll
+  for (int q = 0; q < NV / 4; ++q) b[q] = 4 * q >= K ? 0.f : swap_add16(a[2 * q], a[2 * q + 1]);
+  float c[NV / 8];
+  const bool hi8 = lane & 8;
+#pragma unroll
+  for (int t = 0; t < NV / 8; ++t) {
+    const float send = hi8 ? b[2 * t] : b[2 * t + 1];
+    const float keep = hi8 ? b[2 * t + 1] : b[2 * t];
+    c[t] = keep + dpp_move<0x128, 0xF>(send);                     // row_ror:8
+  }
+  float d;
+  if constexpr (NV == 16) {
+    const bool hi4 = lane & 4;
+    const float send = hi4 ? c[0] : c[1];
+    const float keep = hi4 ? c[1] : c[0];
+    d = keep + dpp_move<0x141, 0xF>(send);                        // row_half_mirror
+  } else {
+    d = c[0];
+    d += dpp_move<0x141, 0xF>(d);
+  }
+  d += dpp_move<0x4E, 0xF>(d);                                    // quad_perm [2,3,0,1]
+  d += dpp_move<0xB1, 0xF>(d);                                    // quad_perm [1,0,3,2]
+  return d;
 }
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }

@@ -11,7 +11,8 @@ namespace cgsr {
 // Counters kept in device memory, one block of them per state.
 enum Counter : int {
   kCntPairs = 0,        // (tile, Gaussian) pairs of the last render
-  kCntOverflow = 1,     // 1 if pairs exceeded the capacity
+  kCntOverflow = 1,     // 1 if a render since the last check exceeded the capacity
+  kCntPeak = 2,         // most pairs any render needed since the last check
 };
 constexpr int kCounterWords = 8;
 

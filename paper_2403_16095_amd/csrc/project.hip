@@ -138,16 +138,59 @@ __device__ bool project_core(const GaussianPtrs& g, int64_t i, const float* P, c
   return true;
 }
 
+// A wave's (Gaussian, tile) pairs, spread evenly over its 64 lanes.  Each
+// lane owns ntiles tiles of its Gaussian's rectangle (tx0, ty0, width w); a
+// single large Gaussian would otherwise keep one lane busy for hundreds of
+// tiles while the rest of the chip waits for that wave.  The lanes' exclusive
+// prefix offsets go to LDS; pair k of the wave belongs to the last lane whose
+// offset is <= k (lanes without tiles share the next lane's offset, so they
+// are never chosen).  Every lane of the wave must call this.
+struct WavePairs {
+  uint32_t* off;    // [64] exclusive prefix of ntiles
+  uint32_t* org;    // [64] tx0 | ty0 << 16
+  uint32_t* wid;    // [64] rectangle width in tiles
+  uint32_t total;
+};
+
+__device__ __forceinline__ WavePairs wave_pairs(uint32_t ntiles, uint32_t tx0, uint32_t ty0, uint32_t w,
+                                                uint32_t* lds_off, uint32_t* lds_org, uint32_t* lds_wid) {
+  const int lane = threadIdx.x & 63;
+  uint32_t incl = ntiles;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(incl, d);
+    if (lane >= d) incl += y;
+  }
+  lds_off[lane] = incl - ntiles;
+  lds_org[lane] = tx0 | (ty0 << 16);
+  lds_wid[lane] = w;
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the LDS writes have landed
+  return WavePairs{lds_off, lds_org, lds_wid, (uint32_t)__shfl(incl, 63)};
+}
+
+// Owner lane and tile (within the view, row-major) of pair k of the wave.
+__device__ __forceinline__ uint32_t pair_tile(const WavePairs& wp, uint32_t k, int tiles_x, int* owner) {
+  int j = 0;
+#pragma unroll
+  for (int step = 32; step >= 1; step >>= 1)
+    if (wp.off[j + step] <= k) j += step;
+  const uint32_t local = k - wp.off[j], w = wp.wid[j], org = wp.org[j];
+  *owner = j;
+  return ((org >> 16) + local / w) * (uint32_t)tiles_x + (org & 0xFFFF) + local % w;
+}
+
 __global__ __launch_bounds__(kThreads) void project_kernel(GaussianPtrs g, const float* __restrict__ poses,
                                                            ViewTable vt, ProjectBufs b) {
+  __shared__ uint32_t s_off[kThreads], s_org[kThreads], s_wid[kThreads];
   const int v = blockIdx.y;
   const int64_t N = g.n;
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const ViewInfo cam = vt.io[v].info;
+  uint32_t ntiles = 0, tx0 = 0, ty0 = 0, width = 1;
   if (i < N) {
-    const ViewInfo cam = vt.io[v].info;
     const float* P = poses + 12 * v;
     const int64_t m = (int64_t)v * N + i;
-    uint32_t ntiles = 0;
     Proj o;
     if (project_core(g, i, P, cam, o)) {
       const double mux = (double)cam.fx * (o.p[0] / o.p[2]) + (double)cam.cx;
@@ -158,24 +201,32 @@ __global__ __launch_bounds__(kThreads) void project_kernel(GaussianPtrs g, const
       const double u0 = fmax(0.0, ceil(mux - ex)), u1 = fmin((double)(cam.width - 1), floor(mux + ex));
       const double v0 = fmax(0.0, ceil(muy - ey)), v1 = fmin((double)(cam.height - 1), floor(muy + ey));
       if (u0 <= u1 && v0 <= v1) {
-        const uint32_t tx0 = (uint32_t)u0 / kTile, tx1 = (uint32_t)u1 / kTile;
-        const uint32_t ty0 = (uint32_t)v0 / kTile, ty1 = (uint32_t)v1 / kTile;
-        ntiles = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+        tx0 = (uint32_t)u0 / kTile;
+        ty0 = (uint32_t)v0 / kTile;
+        const uint32_t tx1 = (uint32_t)u1 / kTile, ty1 = (uint32_t)v1 / kTile;
+        width = tx1 - tx0 + 1;
+        ntiles = width * (ty1 - ty0 + 1);
         const float* c = g.rgb + 3 * i;
         float4* rec = b.rec + kRecF4 * m;
         // The mean is kept as a float pair hi + lo; the blend kernels take it
         // relative to their tile's origin, where hi - origin is exact.
         const float hx = (float)mux, hy = (float)muy;
-        rec[0] = make_float4(hx, hy, (float)o.conic[0], (float)o.conic[1]);
-        rec[1] = make_float4((float)o.conic[2], (float)o.opacity, (float)o.p[2], c[0]);
+        // completed-square conic: a, k = b / a, c' = c - b^2 / a = 1 / Sigma2d_yy
+        rec[0] = make_float4(hx, hy, (float)o.conic[0], (float)(o.conic[1] / o.conic[0]));
+        rec[1] = make_float4((float)(1.0 / o.cov[2]), (float)o.opacity, (float)o.p[2], c[0]);
         rec[2] = make_float4(c[1], c[2], (float)(mux - (double)hx), (float)(muy - (double)hy));
         b.rect[m] = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
-        for (uint32_t ty = ty0; ty <= ty1; ++ty)
-          for (uint32_t tx = tx0; tx <= tx1; ++tx)
-            atomicAdd(&b.tile_count[cam.tile_base + ty * cam.tiles_x + tx], 1u);
       }
     }
     b.tiles[m] = ntiles;
+  }
+  // per-tile pair counts, the wave's pairs spread over its lanes
+  const int wv = threadIdx.x >> 6;
+  const WavePairs wp = wave_pairs(ntiles, tx0, ty0, width, s_off + 64 * wv, s_org + 64 * wv, s_wid + 64 * wv);
+  for (uint32_t k = threadIdx.x & 63; k < wp.total; k += 64) {
+    int owner;
+    const uint32_t tile = pair_tile(wp, k, cam.tiles_x, &owner);
+    atomicAdd(&b.tile_count[cam.tile_base + tile], 1u);
   }
 }
 
@@ -197,8 +248,11 @@ __global__ __launch_bounds__(kThreads) void tile_scan_kernel(ProjectBufs b) {
   }
   if (threadIdx.x == 0) {
     b.tile_offset[T] = total;
+    // sticky until cgsr_state_check reads them, so a captured loop of
+    // renders reports any overflow, not only its last one
     b.counters[kCntPairs] = total;
-    b.counters[kCntOverflow] = (int64_t)total > b.pair_cap ? 1u : 0u;
+    if ((int64_t)total > b.pair_cap) b.counters[kCntOverflow] = 1u;
+    b.counters[kCntPeak] = max(b.counters[kCntPeak], total);
   }
 }
 
@@ -206,32 +260,49 @@ __global__ __launch_bounds__(kThreads) void tile_scan_kernel(ProjectBufs b) {
 // with an atomic: key = float bits of the camera depth (positive, so the bits
 // order like the values) << 32 | record id.
 __global__ __launch_bounds__(kThreads) void emit_kernel(ViewTable vt, ProjectBufs b, int64_t N) {
+  __shared__ uint32_t s_off[kThreads], s_org[kThreads], s_wid[kThreads];
+  __shared__ uint64_t s_key[kThreads];
   const int v = blockIdx.y;
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i >= N) return;
-  const int64_t m = (int64_t)v * N + i;
-  if (b.tiles[m] == 0u) return;
-  const uint2 r = b.rect[m];
-  const uint32_t tx0 = r.x & 0xFFFF, tx1 = r.x >> 16, ty0 = r.y & 0xFFFF, ty1 = r.y >> 16;
-  const uint64_t key = ((uint64_t)float_key(b.rec[kRecF4 * m + 1].z) << 32) | (uint64_t)m;
+  const int wv = threadIdx.x >> 6;
+  uint32_t ntiles = 0, tx0 = 0, ty0 = 0, width = 1;
+  uint64_t key = 0;
+  if (i < N) {
+    const int64_t m = (int64_t)v * N + i;
+    ntiles = b.tiles[m];
+    if (ntiles) {
+      const uint2 r = b.rect[m];
+      tx0 = r.x & 0xFFFF;
+      ty0 = r.y & 0xFFFF;
+      width = (r.x >> 16) - tx0 + 1;
+      key = ((uint64_t)float_key(b.rec[kRecF4 * m + 1].z) << 32) | (uint64_t)m;
+    }
+  }
+  s_key[threadIdx.x] = key;
+  const WavePairs wp = wave_pairs(ntiles, tx0, ty0, width, s_off + 64 * wv, s_org + 64 * wv, s_wid + 64 * wv);
   const int32_t tile_base = vt.io[v].info.tile_base, tiles_x = vt.io[v].info.tiles_x;
-  const uint32_t w = tx1 - tx0 + 1, n = w * (ty1 - ty0 + 1);
-  // Take the slots of up to 8 tiles before using any, so a lane waits for
-  // its returning atomics once per 8 tiles rather than once per tile.
-  constexpr uint32_t kBatchTiles = 8;
-  for (uint32_t k0 = 0; k0 < n; k0 += kBatchTiles) {
-    uint32_t tile[kBatchTiles], slot[kBatchTiles];
+  // Take the slots of up to 8 pairs before using any, so a lane waits for
+  // its returning atomics once per 8 pairs rather than once per pair.
+  constexpr uint32_t kBatchPairs = 8;
+  const uint32_t lane = threadIdx.x & 63;
+  for (uint32_t k0 = lane; k0 < wp.total; k0 += 64 * kBatchPairs) {
+    uint32_t tile[kBatchPairs], slot[kBatchPairs];
+    uint64_t kk[kBatchPairs];
 #pragma unroll
-    for (uint32_t j = 0; j < kBatchTiles; ++j) {
-      const uint32_t k = k0 + j;
-      tile[j] = tile_base + (ty0 + k / w) * tiles_x + tx0 + k % w;
-      if (k < n) slot[j] = atomicAdd(&b.tile_fill[tile[j]], 1u);
+    for (uint32_t j = 0; j < kBatchPairs; ++j) {
+      const uint32_t k = k0 + 64 * j;
+      if (k < wp.total) {
+        int owner;
+        tile[j] = tile_base + pair_tile(wp, k, tiles_x, &owner);
+        kk[j] = s_key[64 * wv + owner];
+        slot[j] = atomicAdd(&b.tile_fill[tile[j]], 1u);
+      }
     }
 #pragma unroll
-    for (uint32_t j = 0; j < kBatchTiles; ++j) {
-      if (k0 + j >= n) break;
+    for (uint32_t j = 0; j < kBatchPairs; ++j) {
+      if (k0 + 64 * j >= wp.total) break;
       const uint64_t pos = (uint64_t)b.tile_offset[tile[j]] + slot[j];
-      if (pos < (uint64_t)b.pair_cap) b.keys[pos] = key;
+      if (pos < (uint64_t)b.pair_cap) b.keys[pos] = kk[j];
     }
   }
 }

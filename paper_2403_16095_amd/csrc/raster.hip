@@ -113,8 +113,8 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(Rast
 #pragma unroll
         for (int k = 0; k < kPPL; ++k) {
           if (done[k]) continue;
-          float dx, dy;
-          const float e = pair_exponent(A, B, fx[k], fy[k], dx, dy);
+          float dx, dy, tq;
+          const float e = pair_exponent(A, B, fx[k], fy[k], dx, dy, tq);
           if (e < B.w) continue;
           const float alpha = fminf(kAlphaMax, B.y * __builtin_amdgcn_exp2f(e));
           const float Tn = T[k] * (1.f - alpha);
@@ -210,7 +210,8 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(Rast
 // and Bx <- alpha_j x_j + (1 - alpha_j) Bx moves the sums one Gaussian forward;
 // T_j = T_{j+1} / (1 - alpha_j) recovers the transmittance from the final one.
 // A lane first sums its pixels' contributions to a Gaussian, then the wave
-// reduces them (DPP) and issues one multi-lane atomic.  kParams adds the
+// reduces all of the Gaussian's gradient terms together (wave_sum_many) and
+// issues one atomic instruction.  kParams adds the
 // opacity and colour gradients (mapping); kTrack takes the upstream
 // gradients from the tracking forward (colour and depth only).
 template <int kPPL, bool kParams, bool kTrack>
@@ -297,8 +298,8 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
       bool any = false;
 #pragma unroll
       for (int k = 0; k < kPPL; ++k) {
-        float dx, dy;
-        const float e = pair_exponent(A, B, fx[k], fy[k], dx, dy);
+        float dx, dy, tq;
+        const float e = pair_exponent(A, B, fx[k], fy[k], dx, dy, tq);
         if (pos >= walked[k] || e < B.w) continue;
         any = true;
         const float4 Cc = sC[j];
@@ -326,10 +327,11 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
         T[k] = Tj;
         const bool capped = raw > kAlphaMax;
         const float dpower = capped ? 0.f : dalpha * raw;   // alpha = opacity * exp(power)
-        // power = -(a dx^2 + 2 b dx dy + c dy^2) / 2, with the staged
-        // qa = -a/2 log2 e etc.: d power/d mu = ln2 (2 qa dx + qb dy, qb dx + 2 qc dy)
-        gmx += dpower * kLn2 * __builtin_fmaf(2.f * A.z, dx, A.w * dy);
-        gmy += dpower * kLn2 * __builtin_fmaf(A.w, dx, 2.f * B.x * dy);
+        // power = -(a dx^2 + 2 b dx dy + c dy^2) / 2 = ln2 (qa t^2 + qc dy^2)
+        // with t = dx + k dy: d power/d mu = 2 ln2 (qa t, qa k t + qc dy)
+        const float qt = dpower * (2.f * kLn2) * A.z * tq;
+        gmx += qt;
+        gmy += __builtin_fmaf(qt, A.w, dpower * (2.f * kLn2) * B.x * dy);
         ga -= 0.5f * dpower * dx * dx;
         gb -= dpower * dx * dy;
         gcc -= 0.5f * dpower * dy * dy;
@@ -345,29 +347,17 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
       if (__ballot(any)) {
         const uint32_t m = sM[j];
         float* dst = b.rec_grad + (int64_t)kGradStride * m;
-        const float s0 = wave_sum(gmx), s1 = wave_sum(gmy), s2 = wave_sum(ga), s3 = wave_sum(gb);
-        const float s4 = wave_sum(gcc), s6 = wave_sum(gdd);
         if (kParams) {
-          const float s5 = wave_sum(gop), s7 = wave_sum(gr), s8 = wave_sum(gg), s9 = wave_sum(gbl);
-          float val = s0;
-          val = lane == 1 ? s1 : val;
-          val = lane == 2 ? s2 : val;
-          val = lane == 3 ? s3 : val;
-          val = lane == 4 ? s4 : val;
-          val = lane == 5 ? s5 : val;
-          val = lane == 6 ? s6 : val;
-          val = lane == 7 ? s7 : val;
-          val = lane == 8 ? s8 : val;
-          val = lane == 9 ? s9 : val;
-          if (lane < 10) unsafeAtomicAdd(dst + lane, val);
+          // slots 0-9: mu x, mu y, conic a, b, c, opacity, depth, colour
+          const float vals[10] = {gmx, gmy, ga, gb, gcc, gop, gdd, gr, gg, gbl};
+          const float t = wave_sum_many<16>(vals);
+          const int idx = reduced_value_index<16>(lane);
+          if ((lane & 3) == 0 && idx < 10) unsafeAtomicAdd(dst + idx, t);
         } else {
-          float val = s0;
-          val = lane == 1 ? s1 : val;
-          val = lane == 2 ? s2 : val;
-          val = lane == 3 ? s3 : val;
-          val = lane == 4 ? s4 : val;
-          val = lane == 5 ? s6 : val;
-          if (lane < 6) unsafeAtomicAdd(dst + (lane == 5 ? 6 : lane), val);
+          const float vals[6] = {gmx, gmy, ga, gb, gcc, gdd};
+          const float t = wave_sum_many<8>(vals);
+          const int idx = reduced_value_index<8>(lane);
+          if ((lane & 7) == 0 && idx < 6) unsafeAtomicAdd(dst + (idx == 5 ? 6 : idx), t);
         }
       }
     }

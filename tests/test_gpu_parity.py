@@ -103,7 +103,10 @@ def test_projection_records_match_oracle(R, config1):
     # the mean is stored as a float pair (hi, lo) in slots 0-1 and 10-11
     mu = rec[vis, 0:2].astype(np.float64) + rec[vis, 10:12]
     np.testing.assert_allclose(mu, proj["mu"][vis], rtol=0, atol=1e-6)
-    np.testing.assert_allclose(rec[vis, 2:5], proj["conic"][vis], rtol=1e-6, atol=1e-9)
+    # the conic is stored as (a, k, c') of a (dx + k dy)^2 + c' dy^2
+    a, k, cp = rec[vis, 2], rec[vis, 3], rec[vis, 4]
+    conic = np.stack([a, k * a, cp + k * k * a], 1)
+    np.testing.assert_allclose(conic, proj["conic"][vis], rtol=2e-6, atol=1e-9)
     np.testing.assert_allclose(rec[vis, 5], proj["opacity"][vis], rtol=1e-5)
     np.testing.assert_allclose(rec[vis, 6], proj["depth"][vis], rtol=1e-6)
     np.testing.assert_allclose(rec[vis, 7:10], sc["rgb"][vis], rtol=0, atol=0)
