@@ -51,6 +51,24 @@ __device__ __forceinline__ float2 tile_origin(const ViewInfo& cam, int gtile) {
   return make_float2((float)((lt % cam.tiles_x) * kTile), (float)((lt / cam.tiles_x) * kTile));
 }
 
+// The box of the pixels wave (threadIdx.x / 64) owns: pixel q of the tile
+// lies in quadrant q / 64, and the wave's lanes own q = k L + lane.
+template <int kPPL>
+__device__ __forceinline__ WaveBox wave_box() {
+  constexpr int L = kTilePixels / kPPL;
+  WaveBox w{16.f, -1.f, 16.f, -1.f};
+#pragma unroll
+  for (int k = 0; k < kPPL; ++k) {
+    const int quad = (k * L + (int)threadIdx.x) >> 6;
+    const float qx = (float)((quad & 1) * 8), qy = (float)((quad >> 1) * 8);
+    w.x0 = fminf(w.x0, qx);
+    w.x1 = fmaxf(w.x1, qx + 7.f);
+    w.y0 = fminf(w.y0, qy);
+    w.y1 = fmaxf(w.y1, qy + 7.f);
+  }
+  return w;
+}
+
 __device__ __forceinline__ float sgn(float x) { return (float)((x > 0.f) - (x < 0.f)); }
 
 template <int kPPL, bool kTrack, bool kNu>
@@ -59,6 +77,7 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(Rast
   __shared__ float4 sA[kBatch];
   __shared__ float4 sB[kBatch];
   __shared__ float4 sC[kBatch];
+  __shared__ float2 sE[kBatch];
   __shared__ uint32_t sM[kNu ? kBatch : 1];
   const int gtile = blockIdx.x;
   const int v = view_of_tile(b.views, gtile);
@@ -77,6 +96,7 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(Rast
   uint32_t dom[kPPL];             // kNu: its record id, kNone if none
   bool inside[kPPL], done[kPPL];
   bool lane_done = true;
+  const WaveBox box = wave_box<kPPL>();
 #pragma unroll
   for (int k = 0; k < kPPL; ++k) {
     const PixelCoord pc = pixel_of(cam, gtile, k * L + threadIdx.x);
@@ -102,7 +122,7 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(Rast
     for (int i = threadIdx.x; i < n; i += L) {
       const uint32_t m = b.vals[base + i];
       if (kNu) sM[i] = m;
-      stage_record(b.rec + (int64_t)kRecF4 * m, org.x, org.y, sA[i], sB[i], sC[i]);
+      stage_record(b.rec + (int64_t)kRecF4 * m, org.x, org.y, sA[i], sB[i], sC[i], sE[i]);
     }
     __syncthreads();
     if (!lane_done) {
@@ -110,9 +130,10 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(Rast
       for (int j = 0; j < n; ++j) {
         const float4 A = sA[j];
         const float4 B = sB[j];
+        const bool reach = wave_reaches(A, sE[j], box);
 #pragma unroll
         for (int k = 0; k < kPPL; ++k) {
-          if (done[k]) continue;
+          if (!reach || done[k]) continue;
           float dx, dy, tq;
           const float e = pair_exponent(A, B, fx[k], fy[k], dx, dy, tq);
           if (e < B.w) continue;
@@ -220,6 +241,7 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
   __shared__ float4 sA[kBatch];
   __shared__ float4 sB[kBatch];
   __shared__ float4 sC[kBatch];
+  __shared__ float2 sE[kBatch];
   __shared__ uint32_t sM[kBatch];
   __shared__ uint32_t s_max;
   const int gtile = blockIdx.x;
@@ -236,6 +258,7 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
   float Bc0[kPPL], Bc1[kPPL], Bc2[kPPL], Bd[kPPL], Bo[kPPL], Bu[kPPL];
   int walked[kPPL], med[kPPL];
   uint32_t lane_max = 0;
+  const WaveBox box = wave_box<kPPL>();
 #pragma unroll
   for (int k = 0; k < kPPL; ++k) {
     const PixelCoord pc = pixel_of(cam, gtile, k * L + threadIdx.x);
@@ -286,12 +309,13 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
     for (int i = threadIdx.x; i < n; i += L) {
       const uint32_t m = b.vals[range.x + start + i];
       sM[i] = m;
-      stage_record(b.rec + (int64_t)kRecF4 * m, org.x, org.y, sA[i], sB[i], sC[i]);
+      stage_record(b.rec + (int64_t)kRecF4 * m, org.x, org.y, sA[i], sB[i], sC[i], sE[i]);
     }
     __syncthreads();
     for (int j = n - 1; j >= 0; --j) {
       const int pos = start + j;
       const float4 A = sA[j];
+      if (!wave_reaches(A, sE[j], box)) continue;   // no pixel of this wave can blend it
       const float4 B = sB[j];
       float gmx = 0.f, gmy = 0.f, ga = 0.f, gb = 0.f, gcc = 0.f, gop = 0.f, gdd = 0.f;
       float gr = 0.f, gg = 0.f, gbl = 0.f;
