@@ -59,6 +59,35 @@ FLOP_BLEND = 12
 FLOP_BLEND_BWD = 44
 
 
+def kernel_source_digest() -> str:
+    """sha256 over the HIP sources the library is built from (sorted names)."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2403_16095_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".hpp")):
+            h.update(name.encode())
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter profile
+    (profiles/blend_traffic.json: FETCH_SIZE and WRITE_SIZE scaled by a copy
+    calibration), or None if the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "blend_traffic.json")
+    try:
+        with open(path) as f:
+            prof = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if prof.get("source_sha256") != kernel_source_digest():
+        return None
+    k = prof.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -581,9 +610,12 @@ def main():
         name = max(cand, key=lambda k: cand[k][0])
         ms, fl = cand[name]
         achieved = fl / (ms * 1e-3) / 1e12
-        result["roofline"] = {"bound": "alu", "kernel": name, "achieved": round(achieved, 4),
+        symbol = (f"raster_backward_kernel<{bppl}, false, true>" if name == "blend_bwd"
+                  else f"raster_forward_kernel<{fppl}, true, false>")
+        result["roofline"] = {"bound": "alu", "kernel": name, "symbol": symbol, "achieved": round(achieved, 4),
                               "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                              "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 5), "traffic": None,
+                              "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 5),
+                              "traffic": measured_traffic(symbol),
                               "avg_ms": round(ms, 5), "algorithmic_flops": fl}
         b = algorithmic_bytes(100_000, stats["visible"], stats["pairs"], 640 * 480)
         result["hbm_roofline"] = {"algorithmic_bytes_per_iter": b,
