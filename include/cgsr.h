@@ -301,6 +301,36 @@ typedef struct {
 cgsr_status cgsr_pose_adam_step(int32_t n_views, float *poses, float *dposes, float *adam,
                                 const cgsr_adam_params *params, void *stream);
 
+/* Learning rates and Adam constants of cgsr_gaussian_adam_step.  The paper
+ * defers the mapping learning rates to its supplementary material, so they
+ * are the caller's choice. */
+typedef struct {
+    float lr_means, lr_log_scales, lr_quats, lr_opacity_logits, lr_rgb;
+    float beta1, beta2, eps;
+} cgsr_gaussian_adam_params;
+
+/*
+ * One Adam step (with bias correction) on every Gaussian parameter: the
+ * parameter half of the sliding-window bundle adjustment of Eq. 21, whose
+ * pose half is cgsr_pose_adam_step.
+ *   n        number of Gaussians.
+ *   params   the parameter arrays (device, float, updated in place), in the
+ *            layouts of cgsr_gaussians.
+ *   grads    their gradients (device; read, then zeroed for the next
+ *            accumulation by cgsr_backward and cgsr_mapping_objective).
+ *   moments  device float[2][14 n]: first then second moments, each the
+ *            concatenation of the groups means (3n), log_scales (3n), quats
+ *            (4n), opacity_logits (n), rgb (3n); zero-initialise.
+ *   step     device uint32 step counter (zero-initialise); the call reads it
+ *            for the bias correction and then increments it, on the stream, so
+ *            a captured loop keeps counting.
+ * Errors: NULL arrays (n > 0), negative learning rates, betas outside [0, 1),
+ * eps <= 0.
+ */
+cgsr_status cgsr_gaussian_adam_step(int64_t n, const cgsr_gaussian_grads *params, const cgsr_gaussian_grads *grads,
+                                    float *moments, uint32_t *step, const cgsr_gaussian_adam_params *hp,
+                                    void *stream);
+
 /*
  * One sequential-tracking iteration (Sec. 3.4, Eq. 19-20) of n_views
  * independent frames in one launch sequence: render; the gradient images of

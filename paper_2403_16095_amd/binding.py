@@ -27,7 +27,8 @@ STATUS_NAMES = {0: "CGSR_OK", -1: "CGSR_ERR_INVALID_ARG", -2: "CGSR_ERR_OOM", -3
 
 EXPORTED = (
     "cgsr_default_settings", "cgsr_state_create", "cgsr_state_destroy", "cgsr_state_reserve",
-    "cgsr_render", "cgsr_render_nu", "cgsr_nu_prune", "cgsr_mapping_objective", "cgsr_backward", "cgsr_tracking_loss_grad", "cgsr_mapping_loss_grad", "cgsr_pose_adam_step",
+    "cgsr_render", "cgsr_render_nu", "cgsr_nu_prune", "cgsr_mapping_objective", "cgsr_gaussian_adam_step",
+    "cgsr_backward", "cgsr_tracking_loss_grad", "cgsr_mapping_loss_grad", "cgsr_pose_adam_step",
     "cgsr_tracking_step",
     "cgsr_autotune_tracking", "cgsr_state_check", "cgsr_get_stats", "cgsr_get_timings", "cgsr_debug_buffers",
     "cgsr_last_error",
@@ -80,6 +81,12 @@ class cgsr_mapping_weights(C.Structure):
                 ("iso", C.c_float), ("var", C.c_float), ("iso_epsilon", C.c_float)]
 
 
+class cgsr_gaussian_adam_params(C.Structure):
+    _fields_ = [("lr_means", C.c_float), ("lr_log_scales", C.c_float), ("lr_quats", C.c_float),
+                ("lr_opacity_logits", C.c_float), ("lr_rgb", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float)]
+
+
 class cgsr_stats(C.Structure):
     _fields_ = [("visible", C.c_int64), ("pairs", C.c_int64), ("pair_capacity", C.c_int64),
                 ("overflow", C.c_int32), ("n_views", C.c_int32), ("processed", C.c_int64),
@@ -114,6 +121,8 @@ def lib() -> C.CDLL:
                                  C.POINTER(vp), C.POINTER(cgsr_images), C.POINTER(vp), vp, vp, vp]
     L.cgsr_mapping_objective.argtypes = [vp, C.POINTER(cgsr_mapping_weights), C.POINTER(cgsr_images), C.POINTER(vp),
                                          C.POINTER(vp), C.POINTER(cgsr_images), vp, vp, vp]
+    L.cgsr_gaussian_adam_step.argtypes = [C.c_int64, C.POINTER(cgsr_gaussian_grads), C.POINTER(cgsr_gaussian_grads),
+                                          vp, vp, C.POINTER(cgsr_gaussian_adam_params), vp]
     L.cgsr_nu_prune.argtypes = [C.c_int64, vp, vp, C.c_float, C.c_float, vp, vp, vp, vp]
     L.cgsr_backward.argtypes = [vp, C.POINTER(cgsr_images), C.POINTER(cgsr_gaussian_grads), vp, vp]
     L.cgsr_tracking_loss_grad.argtypes = [C.c_int32, C.c_int32, vp, vp, vp, vp, C.c_float, C.c_float, vp, vp,
@@ -198,6 +207,11 @@ def cgsr_mapping_objective(state: int, weights: cgsr_mapping_weights, maps, targ
     tc = None if target_color is None else (C.c_void_p * n)(*[p or None for p in target_color])
     td = None if target_depth is None else (C.c_void_p * n)(*[p or None for p in target_depth])
     _check(lib().cgsr_mapping_objective(state, C.byref(weights), m_arr, tc, td, d_arr, dlog_scales, loss, stream))
+
+
+def cgsr_gaussian_adam_step(n, params: cgsr_gaussian_grads, grads: cgsr_gaussian_grads, moments, step,
+                            hp: cgsr_gaussian_adam_params, stream) -> None:
+    _check(lib().cgsr_gaussian_adam_step(n, C.byref(params), C.byref(grads), moments, step, C.byref(hp), stream))
 
 
 def cgsr_nu_prune(n, nu_sum, nu_count, tau, low_opacity, opacity_logits, nu, n_pruned, stream) -> None:

@@ -815,6 +815,33 @@ cgsr_status cgsr_mapping_objective(cgsr_state* st, const cgsr_mapping_weights* w
   return CGSR_OK;
 }
 
+cgsr_status cgsr_gaussian_adam_step(int64_t n, const cgsr_gaussian_grads* params, const cgsr_gaussian_grads* grads,
+                                    float* moments, uint32_t* step, const cgsr_gaussian_adam_params* hp,
+                                    void* stream) {
+  if (n < 0 || !params || !grads || !hp || !moments || !step)
+    return fail(CGSR_ERR_INVALID_ARG, "cgsr_gaussian_adam_step: NULL argument or negative count");
+  if (!(hp->beta1 >= 0.f && hp->beta1 < 1.f) || !(hp->beta2 >= 0.f && hp->beta2 < 1.f) || !(hp->eps > 0.f))
+    return fail(CGSR_ERR_INVALID_ARG, "cgsr_gaussian_adam_step: bad Adam parameters");
+  GaussianAdam a;
+  float* const ps[5] = {params->means, params->log_scales, params->quats, params->opacity_logits, params->rgb};
+  float* const gs[5] = {grads->means, grads->log_scales, grads->quats, grads->opacity_logits, grads->rgb};
+  const float lrs[5] = {hp->lr_means, hp->lr_log_scales, hp->lr_quats, hp->lr_opacity_logits, hp->lr_rgb};
+  for (int k = 0; k < 5; ++k) {
+    if (n > 0 && (!ps[k] || !gs[k]))
+      return fail(CGSR_ERR_INVALID_ARG, "cgsr_gaussian_adam_step: every parameter and gradient array is required");
+    if (!(lrs[k] >= 0.f)) return fail(CGSR_ERR_INVALID_ARG, "cgsr_gaussian_adam_step: negative learning rate");
+    a.param[k] = ps[k];
+    a.grad[k] = gs[k];
+    a.lr[k] = lrs[k];
+  }
+  a.beta1 = hp->beta1;
+  a.beta2 = hp->beta2;
+  a.eps = hp->eps;
+  launch_gaussian_adam(n, a, moments, step, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return CGSR_OK;
+}
+
 cgsr_status cgsr_state_check(cgsr_state* st, void* stream) {
   if (!st) return fail(CGSR_ERR_INVALID_ARG, "state is NULL");
   cgsr_status s = set_device(st);

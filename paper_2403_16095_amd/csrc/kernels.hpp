@@ -118,6 +118,16 @@ void launch_objective_view(const ObjectiveView& o, const ObjectiveWeights& w, fl
 // (scratch, n_views words), dlog_scales (+=, may be null), loss[v] (+=).
 void launch_iso(int64_t n, int n_views, const uint32_t* tiles, uint32_t* counts, const float* log_scales, float w_iso,
                 float eps, float* dlog_scales, float* loss, hipStream_t s);
+// Adam over the Gaussian parameter groups (element-wise; moments [2][14 n] in
+// group order), bias-corrected with the device step counter, which a second
+// one-lane launch then increments.  Gradients are zeroed after use.
+struct GaussianAdam {
+  float* param[5];       // means, log_scales, quats, opacity_logits, rgb
+  float* grad[5];
+  float lr[5];
+  float beta1, beta2, eps;
+};
+void launch_gaussian_adam(int64_t n, const GaussianAdam& a, float* moments, uint32_t* step, hipStream_t s);
 // nu_i = nu_sum_i / nu_count_i (0 without dominated pixels); Gaussians with
 // nu_i > tau get opacity_logit = min(opacity_logit, low_logit).
 void launch_nu_prune(int64_t n, const float* nu_sum, const uint32_t* nu_count, float tau, float low_logit,

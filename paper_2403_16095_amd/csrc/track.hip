@@ -117,6 +117,39 @@ __global__ __launch_bounds__(kThreads) void nu_prune_kernel(int64_t n, const flo
   }
 }
 
+// One Adam step (Kingma and Ba, with bias correction) on element e of the
+// concatenated parameter groups: widths 3, 3, 4, 1, 3 per Gaussian.
+__global__ __launch_bounds__(kThreads) void gaussian_adam_kernel(int64_t n, GaussianAdam a, float* moments,
+                                                                 const uint32_t* step) {
+  const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t total = 14 * n;
+  if (e >= total) return;
+  // group of e: boundaries 3n, 6n, 10n, 11n, 14n
+  int grp;
+  int64_t base;
+  if (e < 3 * n) { grp = 0; base = 0; }
+  else if (e < 6 * n) { grp = 1; base = 3 * n; }
+  else if (e < 10 * n) { grp = 2; base = 6 * n; }
+  else if (e < 11 * n) { grp = 3; base = 10 * n; }
+  else { grp = 4; base = 11 * n; }
+  float* p = a.param[grp];
+  float* gp = a.grad[grp];
+  const int64_t k = e - base;
+  const float t = (float)(*step + 1u);
+  const float g = gp[k];
+  gp[k] = 0.f;
+  float* m = moments + e;
+  float* v = moments + total + e;
+  const float mm = a.beta1 * *m + (1.f - a.beta1) * g;
+  const float vv = a.beta2 * *v + (1.f - a.beta2) * g * g;
+  *m = mm;
+  *v = vv;
+  const float c1 = 1.f - powf(a.beta1, t), c2 = 1.f - powf(a.beta2, t);
+  p[k] -= a.lr[grp] * (mm / c1) / (sqrtf(vv / c2) + a.eps);
+}
+
+__global__ void increment_kernel(uint32_t* step) { *step += 1u; }
+
 __global__ __launch_bounds__(kThreads) void stats_kernel(const uint32_t* __restrict__ tiles, int64_t m,
                                                          const uint4* __restrict__ ps,
                                                          const uint32_t* __restrict__ count, int64_t pixels,
@@ -159,6 +192,13 @@ void launch_nu_prune(int64_t n, const float* nu_sum, const uint32_t* nu_count, f
   if (n <= 0) return;
   hipLaunchKernelGGL(nu_prune_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, n,
                      nu_sum, nu_count, tau, low_logit, opacity_logits, nu, n_pruned);
+}
+
+void launch_gaussian_adam(int64_t n, const GaussianAdam& a, float* moments, uint32_t* step, hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(gaussian_adam_kernel, dim3((unsigned)((14 * n + kThreads - 1) / kThreads)), dim3(kThreads), 0,
+                       s, n, a, moments, (const uint32_t*)step);
+  hipLaunchKernelGGL(increment_kernel, dim3(1), dim3(1), 0, s, step);
 }
 
 void launch_pose_adam(int n_views, float* poses, float* dposes, float* adam, const AdamParams& ap, hipStream_t s) {

@@ -232,6 +232,100 @@ def mapping_objective(state: State, maps, target_colors, target_depths, omega=MA
     return outs
 
 
+#: Mapping learning rates (reading: the paper defers them to its supplementary
+#: material; these are the 3D Gaussian splatting defaults, the position rate
+#: scaled by a 5 m scene extent).
+MAPPING_LR = dict(means=1.6e-4 * 5.0, log_scales=5e-3, quats=1e-3, opacity_logits=5e-2, rgb=2.5e-3)
+
+
+def gaussian_adam_params(lr=None, betas=(0.9, 0.999), eps=1e-15) -> B.cgsr_gaussian_adam_params:
+    lr = dict(MAPPING_LR, **(lr or {}))
+    return B.cgsr_gaussian_adam_params(*[float(lr[k]) for k in PARAM_NAMES], float(betas[0]), float(betas[1]),
+                                       float(eps))
+
+
+def gaussian_grads_struct(tensors: dict) -> B.cgsr_gaussian_grads:
+    n = tensors["means"].shape[0]
+    for k in PARAM_NAMES:
+        w = PARAM_WIDTH[k]
+        _check_f32(k, tensors[k], (n,) if w == 1 else (n, w))
+    return B.cgsr_gaussian_grads(*[tensors[k].data_ptr() for k in PARAM_NAMES])
+
+
+def gaussian_adam_step(scene: dict, grads: dict, moments: torch.Tensor, step: torch.Tensor, lr=None,
+                       betas=(0.9, 0.999), eps=1e-15):
+    """In-place Adam step on every Gaussian parameter tensor of ``scene`` with
+    ``grads`` (zeroed afterwards).  moments: float32 [2, 14 n] zeros; step:
+    int32 [1] zeros (read as uint32 by the library)."""
+    n = scene["means"].shape[0]
+    _check_f32("moments", moments, (2, 14 * n))
+    B.cgsr_gaussian_adam_step(n, gaussian_grads_struct(scene), gaussian_grads_struct(grads), moments.data_ptr(),
+                              step.data_ptr(), gaussian_adam_params(lr, betas, eps), _stream())
+
+
+class BundleAdjuster:
+    """Sliding-window bundle adjustment (Sec. 3.4, Eq. 21) over k keyframes:
+    one iteration renders every keyframe in one launch sequence (with its
+    sensor depth, for the uncertainty terms), forms the gradient images of
+    the mapping objective (Eq. 18), back-propagates to the Gaussians and to
+    each keyframe pose, then takes an Adam step on the Gaussians and one on
+    the poses.  All buffers are allocated once, so ``step`` can be captured
+    into a HIP graph after one eager call has sized the workspace."""
+
+    def __init__(self, scene: dict, poses: torch.Tensor, cams, target_colors, target_depths,
+                 omega=MAPPING_OMEGA_REPLICA, lr=None, pose_lr=(TRACK_LR_RHO, TRACK_LR_PHI), optimize_poses=True):
+        self.scene, self.cams = scene, list(cams)
+        V = len(self.cams)
+        self.poses = poses.reshape(V, 12)
+        _check_f32("poses", self.poses)
+        self.tc, self.td = list(target_colors), list(target_depths)
+        self.omega = tuple(omega)
+        n = scene["means"].shape[0]
+        dev = self.poses.device
+        self.grads = {k: torch.zeros_like(scene[k]) for k in PARAM_NAMES}
+        self.moments = torch.zeros((2, 14 * n), dtype=torch.float32, device=dev)
+        self.step_count = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.dposes = torch.zeros((V, 6), dtype=torch.float32, device=dev)
+        self.pose_adam = torch.zeros((V, 16), dtype=torch.float32, device=dev)
+        self.loss = torch.zeros(V, dtype=torch.float32, device=dev)
+        self.state = State(sync_capacity=True)
+        self.g = gaussians_struct(scene)
+        self.cam_s = [camera_struct(c) for c in self.cams]
+        self.maps = []
+        for c in self.cams:
+            H, W = int(c["height"]), int(c["width"])
+            self.maps.append(dict(color=torch.empty((3, H, W), device=dev), depth=torch.empty((H, W), device=dev),
+                                  depth_median=torch.empty((H, W), device=dev),
+                                  uncertainty=torch.empty((H, W), device=dev)))
+        self.dimgs = [{k: torch.empty_like(m[k]) for k in m} for m in self.maps]
+        self.map_s = [B.cgsr_images(*[_ptr(m.get(k)) for k in MAP_NAMES]) for m in self.maps]
+        self.dimg_s = [B.cgsr_images(*[_ptr(d.get(k)) for k in MAP_NAMES]) for d in self.dimgs]
+        self.weights = B.cgsr_mapping_weights(*[float(x) for x in self.omega], float(ISO_EPSILON))
+        self.hp = gaussian_adam_params(lr)
+        self.pose_hp = adam_params(pose_lr[0], pose_lr[1])
+        self.param_s = gaussian_grads_struct(scene)
+        self.grad_s = gaussian_grads_struct(self.grads)
+        self.optimize_poses = optimize_poses
+
+    def step(self):
+        s = _stream()
+        V = len(self.cams)
+        st = self.state.handle
+        B.cgsr_render(st, self.g, V, self.poses.data_ptr(), self.cam_s, [t.data_ptr() for t in self.td], self.map_s, s)
+        B.cgsr_mapping_objective(st, self.weights, self.map_s, [t.data_ptr() for t in self.tc],
+                                 [t.data_ptr() for t in self.td], self.dimg_s, self.grads["log_scales"].data_ptr(),
+                                 self.loss.data_ptr(), s)
+        B.cgsr_backward(st, self.dimg_s, self.grad_s, self.dposes.data_ptr() if self.optimize_poses else None, s)
+        B.cgsr_gaussian_adam_step(self.scene["means"].shape[0], self.param_s, self.grad_s, self.moments.data_ptr(),
+                                  self.step_count.data_ptr(), self.hp, s)
+        if self.optimize_poses:
+            B.cgsr_pose_adam_step(V, self.poses.data_ptr(), self.dposes.data_ptr(), self.pose_adam.data_ptr(),
+                                  self.pose_hp, s)
+
+    def check(self):
+        self.state.check()
+
+
 def backward(state: State, dimgs, param_grads: bool = True, pose_grads: bool = True):
     """Backward of the last render on ``state``.
 

@@ -68,6 +68,16 @@ def test_host_side_argument_checks(lib):
     assert lib.cgsr_nu_prune(4, 8, 8, -1.0, 0.01, None, None, None, None) == B.CGSR_ERR_INVALID_ARG
     assert lib.cgsr_nu_prune(4, 8, 8, 0.025, 1.0, None, None, None, None) == B.CGSR_ERR_INVALID_ARG
     assert lib.cgsr_nu_prune(4, 8, 8, 0.025, 0.0, None, None, None, None) == B.CGSR_ERR_INVALID_ARG
+    hp = B.cgsr_gaussian_adam_params(1e-3, 1e-3, 1e-3, 1e-3, 1e-3, 0.9, 0.999, 1e-15)
+    gg = B.cgsr_gaussian_grads(8, 8, 8, 8, 8)
+    assert lib.cgsr_gaussian_adam_step(-1, C.byref(gg), C.byref(gg), 8, 8, C.byref(hp), None) == B.CGSR_ERR_INVALID_ARG
+    assert lib.cgsr_gaussian_adam_step(4, None, C.byref(gg), 8, 8, C.byref(hp), None) == B.CGSR_ERR_INVALID_ARG
+    bad_hp = B.cgsr_gaussian_adam_params(1e-3, 1e-3, 1e-3, 1e-3, 1e-3, 1.0, 0.999, 1e-15)
+    assert lib.cgsr_gaussian_adam_step(4, C.byref(gg), C.byref(gg), 8, 8, C.byref(bad_hp), None) == B.CGSR_ERR_INVALID_ARG
+    neg_lr = B.cgsr_gaussian_adam_params(-1e-3, 1e-3, 1e-3, 1e-3, 1e-3, 0.9, 0.999, 1e-15)
+    assert lib.cgsr_gaussian_adam_step(4, C.byref(gg), C.byref(gg), 8, 8, C.byref(neg_lr), None) == B.CGSR_ERR_INVALID_ARG
+    part = B.cgsr_gaussian_grads(8, None, 8, 8, 8)
+    assert lib.cgsr_gaussian_adam_step(4, C.byref(part), C.byref(gg), 8, 8, C.byref(hp), None) == B.CGSR_ERR_INVALID_ARG
     assert lib.cgsr_state_check(None, None) == B.CGSR_ERR_INVALID_ARG
     assert lib.cgsr_get_stats(None, None, None) == B.CGSR_ERR_INVALID_ARG
     assert lib.cgsr_state_reserve(None, 1, 1, 1, 1) == B.CGSR_ERR_INVALID_ARG
