@@ -388,7 +388,7 @@ def run_batched_tracking(args, torch, R, synth, frames=32, iters=20):
     cam_s = [R.camera_struct(c) for c in cams]
     lam = R.TRACK_LAMBDA
 
-    def make(vs):
+    def make(vs, margin):
         """Graph of `iters` fused tracking steps over frames vs (reset inside)."""
         V = len(vs)
         pose = torch.empty((V, 12), device="cuda")
@@ -410,7 +410,7 @@ def run_batched_tracking(args, torch, R, synth, frames=32, iters=20):
         for _ in range(iters):
             step()
             peak = max(peak, int(st.stats().pairs))
-        st.reserve(pairs=int(peak * 1.25) + 4096)
+        st.reserve(pairs=int(peak * margin) + 4096)
         for attempt in range(3):
             graph = torch.cuda.CUDAGraph()
             side = torch.cuda.Stream()
@@ -440,20 +440,36 @@ def run_batched_tracking(args, torch, R, synth, frames=32, iters=20):
 
     res = {}
     for name, groups in (("batched", [list(range(frames))]), ("sequential", [[v] for v in range(frames)])):
-        made = [make(vs) for vs in groups]
+        margin = 1.5
+        for attempt in range(3):
+            made = [make(vs, margin) for vs in groups]
 
-        def solve():
-            for gr, _, _ in made:
-                gr.replay()
-        reps = max(1, args.steps // iters)
-        for _ in range(max(1, args.warmup // iters)):
-            solve()
-        wall, ev = _sync_timed(torch, solve, reps)
-        for _, st, _ in made:
-            st.check()
+            def solve():
+                for gr, _, _ in made:
+                    gr.replay()
+            reps = max(1, args.steps // iters)
+            for _ in range(max(1, args.warmup // iters)):
+                solve()
+            wall, ev = _sync_timed(torch, solve, reps)
+            over = []
+            for k, (_, st, _) in enumerate(made):
+                s = st.stats()
+                if s.overflow:
+                    over.append((groups[k][0], int(s.peak_pairs), int(s.pair_capacity)))
+            if not over:
+                break
+            # Replays of some solve needed more pairs than its sizing run (the
+            # pose trajectory, and with it the visible set, differs from run
+            # to run through the order of float atomics): size up and time again.
+            log(f"{name}: pair capacity exceeded (first frame, peak, capacity): {over[:4]}; retiming")
+            margin *= 2.0
+            del made
         fi = frames * iters * reps
-        res[name] = dict(wall=wall, fi=fi, value=fi / wall, poses=torch.cat([p for _, _, p in made]).cpu())
-        log(f"{name}: {fi / wall:.1f} frame-iterations/s")
+        fin = torch.cat([p for _, _, p in made]).cpu()
+        res[name] = dict(wall=wall, fi=fi, value=fi / wall, poses=fin)
+        terr = [float((fin[k, 9:].double() - Pt[k, 9:].cpu().double()).abs().max()) for k in range(frames)]
+        log(f"{name}: {fi / wall:.1f} frame-iterations/s; final |t - t_true|_inf max {max(terr):.3e} "
+            f"median {sorted(terr)[frames // 2]:.3e}")
         del made
     d = float((res["batched"]["poses"] - res["sequential"]["poses"]).abs().max())
     log(f"batched vs sequential final poses max diff {d:.2e}")

@@ -51,22 +51,15 @@ __device__ __forceinline__ float2 tile_origin(const ViewInfo& cam, int gtile) {
   return make_float2((float)((lt % cam.tiles_x) * kTile), (float)((lt / cam.tiles_x) * kTile));
 }
 
-// The box of the pixels wave (threadIdx.x / 64) owns: pixel q of the tile
-// lies in quadrant q / 64, and the wave's lanes own q = k L + lane.
+// The quadrants whose pixels wave (threadIdx.x / 64) owns: pixel q of the
+// tile lies in quadrant q / 64, and the wave's lanes own q = k L + lane.
 template <int kPPL>
-__device__ __forceinline__ WaveBox wave_box() {
+__device__ __forceinline__ uint32_t wave_quads() {
   constexpr int L = kTilePixels / kPPL;
-  WaveBox w{16.f, -1.f, 16.f, -1.f};
+  uint32_t m = 0;
 #pragma unroll
-  for (int k = 0; k < kPPL; ++k) {
-    const int quad = (k * L + (int)threadIdx.x) >> 6;
-    const float qx = (float)((quad & 1) * 8), qy = (float)((quad >> 1) * 8);
-    w.x0 = fminf(w.x0, qx);
-    w.x1 = fmaxf(w.x1, qx + 7.f);
-    w.y0 = fminf(w.y0, qy);
-    w.y1 = fmaxf(w.y1, qy + 7.f);
-  }
-  return w;
+  for (int k = 0; k < kPPL; ++k) m |= 1u << ((k * L + (int)threadIdx.x) >> 6);
+  return m;
 }
 
 __device__ __forceinline__ float sgn(float x) { return (float)((x > 0.f) - (x < 0.f)); }
@@ -77,7 +70,6 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(Rast
   __shared__ float4 sA[kBatch];
   __shared__ float4 sB[kBatch];
   __shared__ float4 sC[kBatch];
-  __shared__ float2 sE[kBatch];
   __shared__ uint32_t sM[kNu ? kBatch : 1];
   const int gtile = blockIdx.x;
   const int v = view_of_tile(b.views, gtile);
@@ -96,7 +88,7 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(Rast
   uint32_t dom[kPPL];             // kNu: its record id, kNone if none
   bool inside[kPPL], done[kPPL];
   bool lane_done = true;
-  const WaveBox box = wave_box<kPPL>();
+  const uint32_t wq = wave_quads<kPPL>();
 #pragma unroll
   for (int k = 0; k < kPPL; ++k) {
     const PixelCoord pc = pixel_of(cam, gtile, k * L + threadIdx.x);
@@ -122,30 +114,34 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(Rast
     for (int i = threadIdx.x; i < n; i += L) {
       const uint32_t m = b.vals[base + i];
       if (kNu) sM[i] = m;
-      stage_record(b.rec + (int64_t)kRecF4 * m, org.x, org.y, sA[i], sB[i], sC[i], sE[i]);
+      stage_record(b.rec + (int64_t)kRecF4 * m, org.x, org.y, sA[i], sB[i], sC[i]);
     }
     __syncthreads();
-    if (!lane_done) {
+    // The wave walks the batch while any of its lanes still blends; lanes
+    // that are done ride along predicated off, and the wave leaves together
+    // (checked every 8 records), so the loop carries no per-lane exit masks.
+    if (__ballot(!lane_done) != 0ull) {
       const uint32_t off = base - range.x;
       for (int j = 0; j < n; ++j) {
+        if (staged_quads(&sC[j]) & wq) {
         const float4 A = sA[j];
         const float4 B = sB[j];
-        const bool reach = wave_reaches(A, sE[j], box);
+        const float4 Cc = sC[j];
+        // Straight-line, predicated per lane: a lane that skips (alpha below
+        // 1/255, or already done) adds exact zeros, so the results are those
+        // of the branching form, without exec-mask bookkeeping per record.
 #pragma unroll
         for (int k = 0; k < kPPL; ++k) {
-          if (!reach || done[k]) continue;
           float dx, dy, tq;
           const float e = pair_exponent(A, B, fx[k], fy[k], dx, dy, tq);
-          if (e < B.w) continue;
+          const bool hit = !done[k] && e >= B.w;
           const float alpha = fminf(kAlphaMax, B.y * __builtin_amdgcn_exp2f(e));
           const float Tn = T[k] * (1.f - alpha);
-          if (Tn < kTStop) {
-            done[k] = true;
-            evaluated[k] = off + j + 1;
-            continue;
-          }
-          const float wgt = alpha * T[k];
-          const float4 Cc = sC[j];
+          const bool stop = hit && Tn < kTStop;
+          const bool blend = hit && !stop;
+          done[k] = done[k] || stop;
+          evaluated[k] = stop ? off + j + 1 : evaluated[k];
+          const float wgt = blend ? alpha * T[k] : 0.f;
           C0[k] = __builtin_fmaf(wgt, Cc.x, C0[k]);
           C1[k] = __builtin_fmaf(wgt, Cc.y, C1[k]);
           C2[k] = __builtin_fmaf(wgt, Cc.z, C2[k]);
@@ -155,27 +151,31 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(Rast
             const float dz = B.z - dobs[k];
             U[k] = __builtin_fmaf(wgt * dz, dz, U[k]);
           }
-          if (med[k] < 0 && Tn < kTMedian) {
-            med[k] = (int)(off + j);
-            Dmed[k] = B.z;
+          const bool first_med = blend && med[k] < 0 && Tn < kTMedian;
+          med[k] = first_med ? (int)(off + j) : med[k];
+          Dmed[k] = first_med ? B.z : Dmed[k];
+          if (kNu) {
+            const bool more = blend && wgt > wdom[k];   // strict: the first of equal maxima
+            wdom[k] = more ? wgt : wdom[k];
+            ddom[k] = more ? B.z : ddom[k];
+            dom[k] = more ? sM[j] : dom[k];
           }
-          if (kNu && wgt > wdom[k]) {   // strict: the first of equal maxima
-            wdom[k] = wgt;
-            ddom[k] = B.z;
-            dom[k] = sM[j];
-          }
-          T[k] = Tn;
-          last[k] = off + j + 1;
-          ++blended[k];
+          T[k] = blend ? Tn : T[k];
+          last[k] = blend ? off + j + 1 : last[k];
+          blended[k] += blend ? 1u : 0u;
         }
-        bool all = true;
+        }
+        if ((j & 7) == 7) {
+          bool all = true;
 #pragma unroll
-        for (int k = 0; k < kPPL; ++k) all = all && done[k];
-        if (all) {
-          lane_done = true;
-          break;
+          for (int k = 0; k < kPPL; ++k) all = all && done[k];
+          if (__ballot(!all) == 0ull) break;
         }
       }
+      bool all = true;
+#pragma unroll
+      for (int k = 0; k < kPPL; ++k) all = all && done[k];
+      lane_done = all;
     }
     if (__syncthreads_count(lane_done) == L) break;
   }
@@ -241,7 +241,6 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
   __shared__ float4 sA[kBatch];
   __shared__ float4 sB[kBatch];
   __shared__ float4 sC[kBatch];
-  __shared__ float2 sE[kBatch];
   __shared__ uint32_t sM[kBatch];
   __shared__ uint32_t s_max;
   const int gtile = blockIdx.x;
@@ -258,7 +257,7 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
   float Bc0[kPPL], Bc1[kPPL], Bc2[kPPL], Bd[kPPL], Bo[kPPL], Bu[kPPL];
   int walked[kPPL], med[kPPL];
   uint32_t lane_max = 0;
-  const WaveBox box = wave_box<kPPL>();
+  const uint32_t wq = wave_quads<kPPL>();
 #pragma unroll
   for (int k = 0; k < kPPL; ++k) {
     const PixelCoord pc = pixel_of(cam, gtile, k * L + threadIdx.x);
@@ -309,27 +308,31 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
     for (int i = threadIdx.x; i < n; i += L) {
       const uint32_t m = b.vals[range.x + start + i];
       sM[i] = m;
-      stage_record(b.rec + (int64_t)kRecF4 * m, org.x, org.y, sA[i], sB[i], sC[i], sE[i]);
+      stage_record(b.rec + (int64_t)kRecF4 * m, org.x, org.y, sA[i], sB[i], sC[i]);
     }
     __syncthreads();
     for (int j = n - 1; j >= 0; --j) {
       const int pos = start + j;
+      if (!(staged_quads(&sC[j]) & wq)) continue;   // no pixel of this wave can blend it
       const float4 A = sA[j];
-      if (!wave_reaches(A, sE[j], box)) continue;   // no pixel of this wave can blend it
       const float4 B = sB[j];
       float gmx = 0.f, gmy = 0.f, ga = 0.f, gb = 0.f, gcc = 0.f, gop = 0.f, gdd = 0.f;
       float gr = 0.f, gg = 0.f, gbl = 0.f;
       bool any = false;
+      const float4 Cc = sC[j];
+      // Straight-line, predicated per lane: a lane that did not blend this
+      // record (past its last blended one, or alpha below 1/255) takes
+      // alpha = 0, which leaves T and the behind sums exactly unchanged and
+      // adds exact zeros to every gradient term.
 #pragma unroll
       for (int k = 0; k < kPPL; ++k) {
         float dx, dy, tq;
         const float e = pair_exponent(A, B, fx[k], fy[k], dx, dy, tq);
-        if (pos >= walked[k] || e < B.w) continue;
-        any = true;
-        const float4 Cc = sC[j];
+        const bool hit = pos < walked[k] && e >= B.w;
+        any = any || hit;
         const float g = __builtin_amdgcn_exp2f(e);
         const float raw = B.y * g;
-        const float alpha = fminf(kAlphaMax, raw);
+        const float alpha = hit ? fminf(kAlphaMax, raw) : 0.f;
         const float oma = 1.f - alpha;
         const float Tj = T[k] * __builtin_amdgcn_rcpf(oma);
         const float wgt = alpha * Tj;
@@ -349,8 +352,8 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
         }
         const float dalpha = Tj * dsum;
         T[k] = Tj;
-        const bool capped = raw > kAlphaMax;
-        const float dpower = capped ? 0.f : dalpha * raw;   // alpha = opacity * exp(power)
+        const bool live = hit && !(raw > kAlphaMax);   // a capped alpha has no gradient
+        const float dpower = live ? dalpha * raw : 0.f;   // alpha = opacity * exp(power)
         // power = -(a dx^2 + 2 b dx dy + c dy^2) / 2 = ln2 (qa t^2 + qc dy^2)
         // with t = dx + k dy: d power/d mu = 2 ln2 (qa t, qa k t + qc dy)
         const float qt = dpower * (2.f * kLn2) * A.z * tq;
@@ -360,9 +363,9 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
         gb -= dpower * dx * dy;
         gcc -= 0.5f * dpower * dy * dy;
         gdd += wgt * gd[k];
-        if (!kTrack) gdd += 2.f * wgt * dz * gu[k] + (pos == med[k] ? gm[k] : 0.f);
+        if (!kTrack) gdd += 2.f * wgt * dz * gu[k] + ((hit && pos == med[k]) ? gm[k] : 0.f);
         if (kParams) {
-          gop += capped ? 0.f : dalpha * g;
+          gop += live ? dalpha * g : 0.f;
           gr += wgt * gc0[k];
           gg += wgt * gc1[k];
           gbl += wgt * gc2[k];

@@ -65,17 +65,36 @@ def test_mapping_size_all_maps_and_gradients(R):
     mask = unambiguous(ref)
     say("unambiguous pixels", mask.mean())
     assert mask.mean() > 0.9
+    bad = {}
     for k in MAPS:
         g = gpu[k]
-        err = np.abs(g - ref[k])[np.broadcast_to(mask, g.shape)].max()
-        say(k, "max abs err", err)
-        assert err <= 1e-4, k
+        e = np.abs(g - ref[k]) * np.broadcast_to(mask, g.shape)
+        err = e.max()
+        say(k, "max abs err", err, "pixels over 1e-4:", int((e > 1e-4).sum()))
+        if err > 1e-4:
+            bad[k] = np.unravel_index(np.argmax(e), e.shape)
+    for k, idx in bad.items():
+        v, u = idx[-2], idx[-1]
+        px = [int(v) * cam["width"] + int(u)]
+        brute = oracle.render(sc, cam, pose, td, candidates=0, pixels=px)
+        say(f"{k} worst pixel (u={u}, v={v}): gpu {gpu[k][idx]:.7f} oracle {ref[k][idx]:.7f} "
+            f"brute {np.asarray(brute[k])[..., 0].ravel()[idx[0] if len(idx) == 3 else 0]:.7f} "
+            f"n_contrib {ref['n_contrib'][v, u]} (brute {brute['n_contrib'][0]}), gpu blended "
+            f"T_final {ref['t_final'][v, u]:.3e}, decision margin {ref['decision_margin'][v, u]:.3e}, "
+            f"order margin {ref['order_margin'][v, u]:.3e}")
+    assert not bad, f"maps over 1e-4: {sorted(bad)}"
     swap = order_only_ambiguous(ref)
     assert np.abs(gpu["opacity"] - ref["opacity"])[swap].max(initial=0.0) <= 1e-4
-    # device mapping-loss gradient images equal the oracle's on the same maps
+    # the device mapping-loss kernel against the oracle's loss on the same
+    # seeded synthetic maps
+    rng = np.random.default_rng(77)
+    H, W = cam["height"], cam["width"]
+    syn = dict(color=rng.random((3, H, W)).astype(np.float32), depth=rng.uniform(0.5, 5, (H, W)).astype(np.float32),
+               uncertainty=rng.uniform(0, 0.3, (H, W)).astype(np.float32))
     L = torch.zeros(1, device="cuda")
-    dimg_d = R.mapping_loss_grad(out["color"], out["depth"], out["uncertainty"], t32(tc), t32(td), loss=L)
-    Lr, dimg_r = oracle.uncertainty_weighted_loss({k: gpu[k] for k in MAPS}, tc, td)
+    dimg_d = R.mapping_loss_grad(t32(syn["color"]), t32(syn["depth"]), t32(syn["uncertainty"]), t32(tc), t32(td),
+                                 loss=L)
+    Lr, dimg_r = oracle.uncertainty_weighted_loss({k: v.astype(np.float64) for k, v in syn.items()}, tc, td)
     assert abs(L.item() - Lr) <= 1e-4 * abs(Lr)
     for k in ("color", "depth", "uncertainty"):
         np.testing.assert_allclose(dimg_d[k].cpu().numpy(), dimg_r[k], rtol=1e-5, atol=1e-12)
@@ -158,21 +177,26 @@ def test_batched_tracking_32_frames(R):
         R.tracking_step(s1, scd, P0[v].contiguous(), [cams[v]], [tc[v]], [td[v]], dposes=d1)
         e = ((d1[0] - dposes[v]).abs().max() / d1.abs().max()).item()
         assert e < 1e-4, (v, e)
+    # per-frame pose gradients against the oracle, both sides on the same
+    # seeded random target images
+    rt = [synth.random_targets(500 + k, cams[k], depth_range=(0.5, 5.0)) for k in range(32)]
+    dposes_r = torch.zeros((32, 6), device="cuda")
+    R.tracking_step(st, scd, P0, cams, [t32(c) for c, _ in rt], [t32(d) for _, d in rt], dposes=dposes_r)
     for v in (0, 7, 19):
         cam = cams[v]
         ref = oracle.render(sc, cam, start[v])
-        _, dimg = oracle.tracking_loss(ref, tc[v].cpu().numpy(), td[v].cpu().numpy())
+        _, dimg = oracle.tracking_loss(ref, rt[v][0], rt[v][1])
         rb = oracle.backward(sc, cam, start[v], None, dimg)
-        e = np.abs(dposes[v].cpu().numpy() - rb["pose"]).max() / np.abs(rb["pose"]).max()
+        e = np.abs(dposes_r[v].cpu().numpy() - rb["pose"]).max() / np.abs(rb["pose"]).max()
         say("frame", v, cam["width"], "x", cam["height"], "pose grad rel err", e)
         assert e <= 2e-3
     # one frame against frozen-decision central differences of the oracle
     v = next((k for k, c in enumerate(cams) if c["width"] == 320), 0)
     cam = cams[v]
     ref = oracle.render(sc, cam, start[v])
-    _, dimg = oracle.tracking_loss(ref, tc[v].cpu().numpy(), td[v].cpu().numpy())
+    _, dimg = oracle.tracking_loss(ref, rt[v][0], rt[v][1])
     fd = oracle.fd_linear(sc, cam, start[v], None, dimg, [("pose", 0, c) for c in range(6)])
-    e = np.abs(dposes[v].cpu().numpy() - fd).max() / np.abs(fd).max()
+    e = np.abs(dposes_r[v].cpu().numpy() - fd).max() / np.abs(fd).max()
     say("frame", v, cam["width"], "x", cam["height"], "pose grad vs frozen FD rel err", e)
     assert e <= 2e-3
     # 20-step Adam loop captured in one graph vs the same loop eagerly
