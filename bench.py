@@ -436,7 +436,8 @@ def run_batched_tracking(args, torch, R, synth, frames=32, iters=20):
             except R.B.CgsrError:
                 pass
             st.reserve(pairs=int(s.peak_pairs * 1.25) + 4096)
-        return graph, st, pose
+        # the graph reads and writes these tensors: keep them alive with it
+        return graph, st, pose, (pose0, adam)
 
     res = {}
     for name, groups in (("batched", [list(range(frames))]), ("sequential", [[v] for v in range(frames)])):
@@ -445,14 +446,14 @@ def run_batched_tracking(args, torch, R, synth, frames=32, iters=20):
             made = [make(vs, margin) for vs in groups]
 
             def solve():
-                for gr, _, _ in made:
+                for gr, _, _, _ in made:
                     gr.replay()
             reps = max(1, args.steps // iters)
             for _ in range(max(1, args.warmup // iters)):
                 solve()
             wall, ev = _sync_timed(torch, solve, reps)
             over = []
-            for k, (_, st, _) in enumerate(made):
+            for k, (_, st, _, _) in enumerate(made):
                 s = st.stats()
                 if s.overflow:
                     over.append((groups[k][0], int(s.peak_pairs), int(s.pair_capacity)))
@@ -465,7 +466,7 @@ def run_batched_tracking(args, torch, R, synth, frames=32, iters=20):
             margin *= 2.0
             del made
         fi = frames * iters * reps
-        fin = torch.cat([p for _, _, p in made]).cpu()
+        fin = torch.cat([p for _, _, p, _ in made]).cpu()
         res[name] = dict(wall=wall, fi=fi, value=fi / wall, poses=fin)
         terr = [float((fin[k, 9:].double() - Pt[k, 9:].cpu().double()).abs().max()) for k in range(frames)]
         log(f"{name}: {fi / wall:.1f} frame-iterations/s; final |t - t_true|_inf max {max(terr):.3e} "

@@ -49,7 +49,7 @@ class _Projection(C.Structure):
 class _Images(C.Structure):
     _fields_ = [("color", _dp), ("depth", _dp), ("opacity", _dp), ("depth_median", _dp),
                 ("uncertainty", _dp), ("n_contrib", _ip), ("t_final", _dp), ("median_id", _ip),
-                ("decision_margin", _dp), ("order_margin", _dp)]
+                ("decision_margin", _dp), ("order_margin", _dp), ("stop_order_margin", _dp)]
 
 
 class _ImageGrads(C.Structure):
@@ -160,10 +160,11 @@ def render(scene, cam, pose, depth_obs=None, *, candidates: int = 1, pixels=None
                depth_median=np.zeros(shape2), uncertainty=np.zeros(shape2),
                n_contrib=np.zeros(shape2, np.int32), t_final=np.zeros(shape2),
                median_id=np.zeros(shape2, np.int32), decision_margin=np.zeros(shape2),
-               order_margin=np.zeros(shape2))
+               order_margin=np.zeros(shape2), stop_order_margin=np.zeros(shape2))
     im = _Images(*[_ptr(out[k], _ip if out[k].dtype == np.int32 else _dp)
                    for k in ("color", "depth", "opacity", "depth_median", "uncertainty",
-                             "n_contrib", "t_final", "median_id", "decision_margin", "order_margin")])
+                             "n_contrib", "t_final", "median_id", "decision_margin", "order_margin",
+                             "stop_order_margin")])
     _check(lib().orc_render(C.byref(s.c), C.byref(_cam(cam)), C.byref(_pose(pose)), _ptr(d),
                             int(candidates), _ptr(px, _lp), int(npx), C.byref(im)), "render")
     if depth_obs is None:

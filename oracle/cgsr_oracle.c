@@ -287,7 +287,7 @@ static void free_candidates(cand_lists *cl)
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
-    double color[3], depth, opacity, depth_median, uncertainty, t_final, margin, order_margin;
+    double color[3], depth, opacity, depth_median, uncertainty, t_final, margin, order_margin, stop_order_margin;
     int64_t median;      /* Gaussian id, -1 if T never fell below 0.5 */
     int n;               /* blended Gaussians */
     /* Eq. 13: the blended Gaussian of largest weight alpha T, its weight and
@@ -333,6 +333,7 @@ static void pixel_forward(const gproj *pr, const int64_t *cand, int64_t ncand, d
     po->dominant = -1;
     po->margin = DBL_MAX;
     po->order_margin = DBL_MAX;
+    po->stop_order_margin = DBL_MAX;
     for (int64_t k = 0; k < ncand; ++k) {
         const int64_t i = cand[k];
         const gproj *o = &pr[i];
@@ -345,7 +346,21 @@ static void pixel_forward(const gproj *pr, const int64_t *cand, int64_t ncand, d
         const double alpha = clamped ? ORC_ALPHA_MAX : a_raw;
         const double Tn = T * (1.0 - alpha);
         po->margin = fmin(po->margin, rel_gap(Tn, ORC_T_STOP));
-        if (Tn < ORC_T_STOP) break;
+        if (Tn < ORC_T_STOP) {
+            /* The Gaussian that stops the walk, and the next one that would
+             * pass the skip test, take part in the result through their order
+             * too: were either swapped with its neighbour in depth, a
+             * different set of Gaussians would be blended. */
+            if (po->n > 0)
+                po->stop_order_margin = fmin(po->stop_order_margin, fabs(o->depth - prev_depth) / o->depth);
+            for (int64_t k2 = k + 1; k2 < ncand; ++k2) {
+                const gproj *o2 = &pr[cand[k2]];
+                if (o2->opacity * exp(gauss_power(o2, u, v)) < ORC_ALPHA_MIN) continue;
+                po->stop_order_margin = fmin(po->stop_order_margin, fabs(o2->depth - o->depth) / o2->depth);
+                break;
+            }
+            break;
+        }
         if (po->n > 0) po->order_margin = fmin(po->order_margin, fabs(o->depth - prev_depth) / o->depth);
         const double w = alpha * T;
         for (int c = 0; c < 3; ++c) po->color[c] += w * o->color[c];
@@ -448,6 +463,7 @@ int orc_render(const orc_gaussians *g, const orc_camera *cam, const orc_pose *po
         if (out->median_id) out->median_id[k] = (int32_t)po.median;
         if (out->decision_margin) out->decision_margin[k] = po.margin;
         if (out->order_margin) out->order_margin[k] = po.order_margin;
+        if (out->stop_order_margin) out->stop_order_margin[k] = po.stop_order_margin;
     }
     render_teardown(&rc);
     return 0;

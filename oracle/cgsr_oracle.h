@@ -89,7 +89,13 @@ typedef struct {
     double *decision_margin; /* [H][W] smallest relative distance of any alpha
                                 skip/cap, stop or median decision to its threshold */
     double *order_margin;    /* [H][W] smallest relative depth gap between two
-                                consecutively blended Gaussians */
+                                consecutively blended Gaussians (a swap keeps
+                                the blended set, so the opacity)           */
+    double *stop_order_margin; /* [H][W] smallest relative depth gap between
+                                the Gaussian that stops the walk and its two
+                                neighbours in the walk (the last blended one
+                                and the next one past the skip test): a swap
+                                there changes which Gaussians are blended  */
 } orc_images;
 
 /* Upstream gradient images (dL/d maps); NULL members are zero. */

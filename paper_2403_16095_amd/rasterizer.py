@@ -273,7 +273,8 @@ class BundleAdjuster:
     into a HIP graph after one eager call has sized the workspace."""
 
     def __init__(self, scene: dict, poses: torch.Tensor, cams, target_colors, target_depths,
-                 omega=MAPPING_OMEGA_REPLICA, lr=None, pose_lr=(TRACK_LR_RHO, TRACK_LR_PHI), optimize_poses=True):
+                 omega=MAPPING_OMEGA_REPLICA, lr=None, pose_lr=(TRACK_LR_RHO, TRACK_LR_PHI), optimize_poses=True,
+                 eps=1e-15):
         self.scene, self.cams = scene, list(cams)
         V = len(self.cams)
         self.poses = poses.reshape(V, 12)
@@ -301,7 +302,7 @@ class BundleAdjuster:
         self.map_s = [B.cgsr_images(*[_ptr(m.get(k)) for k in MAP_NAMES]) for m in self.maps]
         self.dimg_s = [B.cgsr_images(*[_ptr(d.get(k)) for k in MAP_NAMES]) for d in self.dimgs]
         self.weights = B.cgsr_mapping_weights(*[float(x) for x in self.omega], float(ISO_EPSILON))
-        self.hp = gaussian_adam_params(lr)
+        self.hp = gaussian_adam_params(lr, eps=eps)
         self.pose_hp = adam_params(pose_lr[0], pose_lr[1])
         self.param_s = gaussian_grads_struct(scene)
         self.grad_s = gaussian_grads_struct(self.grads)

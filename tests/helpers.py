@@ -11,14 +11,16 @@ ORDER_MARGIN = 1e-6
 
 def unambiguous(ref):
     """Pixels of an oracle render whose every discrete decision is clear."""
-    return (ref["decision_margin"] >= DECISION_MARGIN) & (ref["order_margin"] >= ORDER_MARGIN)
+    return ((ref["decision_margin"] >= DECISION_MARGIN) & (ref["order_margin"] >= ORDER_MARGIN)
+            & (ref["stop_order_margin"] >= ORDER_MARGIN))
 
 
 def order_only_ambiguous(ref):
     """Pixels whose thresholds are clear but whose blend order may swap two
     near-equal depths.  Accumulated opacity, 1 - prod(1 - alpha), does not
     depend on that order, so it must still match there."""
-    return (ref["decision_margin"] >= DECISION_MARGIN) & (ref["order_margin"] < ORDER_MARGIN)
+    return ((ref["decision_margin"] >= DECISION_MARGIN) & (ref["order_margin"] < ORDER_MARGIN)
+            & (ref["stop_order_margin"] >= ORDER_MARGIN))
 
 
 def rel_l2(a, b):

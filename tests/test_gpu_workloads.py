@@ -81,7 +81,7 @@ def test_mapping_size_all_maps_and_gradients(R):
             f"brute {np.asarray(brute[k])[..., 0].ravel()[idx[0] if len(idx) == 3 else 0]:.7f} "
             f"n_contrib {ref['n_contrib'][v, u]} (brute {brute['n_contrib'][0]}), gpu blended "
             f"T_final {ref['t_final'][v, u]:.3e}, decision margin {ref['decision_margin'][v, u]:.3e}, "
-            f"order margin {ref['order_margin'][v, u]:.3e}")
+            f"order margin {ref['order_margin'][v, u]:.3e}, stop order margin {ref['stop_order_margin'][v, u]:.3e}")
     assert not bad, f"maps over 1e-4: {sorted(bad)}"
     swap = order_only_ambiguous(ref)
     assert np.abs(gpu["opacity"] - ref["opacity"])[swap].max(initial=0.0) <= 1e-4
