@@ -98,35 +98,12 @@ constexpr float kLn2 = 0.6931471805599453f;
 // two of the origin (and rounds by an ulp of the difference otherwise, where
 // only wide Gaussians, with small conics, reach the tile); the low part adds
 // the rest.
-//
-// c.w carries the record's quadrant mask: bit q is set when its binning
-// rectangle (the bounding box of the alpha >= 1/255 ellipse with the
-// projection's margins, widened by 1e-5 relative and 1e-3 px) reaches the
-// 8x8 quadrant q of the tile (q = 2 row + column).  A wave whose pixels lie in
-// quadrants the mask misses cannot blend the record and skips it.  With
-// Sigma2d = Q^-1 for the conic Q = [[a, a k], [a k, a k^2 + c']]:
-// Sigma_xx = 1/a + k^2/c', Sigma_yy = 1/c'.
 __device__ __forceinline__ void stage_record(const float4* __restrict__ rec, float ox, float oy, float4& A, float4& B,
                                              float4& C) {
   const float4 r0 = rec[0], r1 = rec[1], r2 = rec[2];
-  const float thr = -__log2f(255.0f * r1.y);
   A = make_float4((r0.x - ox) + r2.z, (r0.y - oy) + r2.w, (-0.5f * kLog2e) * r0.z, r0.w);
-  B = make_float4((-0.5f * kLog2e) * r1.x, r1.y, r1.z, thr);
-  const float r2m = __builtin_fmaf(-2.0f * kLn2 * thr, kBinR2Rel, kBinR2Abs);
-  const float syy = 1.0f / r1.x, sxx = __builtin_fmaf(r0.w * r0.w, syy, 1.0f / r0.z);
-  const float ex = __builtin_fmaf(sqrtf(r2m * sxx), 1e-5f, sqrtf(r2m * sxx)) + 1e-3f;
-  const float ey = __builtin_fmaf(sqrtf(r2m * syy), 1e-5f, sqrtf(r2m * syy)) + 1e-3f;
-  const float x0 = A.x - ex, x1 = A.x + ex, y0 = A.y - ey, y1 = A.y + ey;
-  const bool c0 = x0 <= 7.f && x1 >= 0.f, c1 = x0 <= 15.f && x1 >= 8.f;
-  const bool w0 = y0 <= 7.f && y1 >= 0.f, w1 = y0 <= 15.f && y1 >= 8.f;
-  const uint32_t quads = (uint32_t)(c0 && w0) | (uint32_t)(c1 && w0) << 1 | (uint32_t)(c0 && w1) << 2 |
-                         (uint32_t)(c1 && w1) << 3;
-  C = make_float4(r1.w, r2.x, r2.y, __uint_as_float(quads));
-}
-
-// The quadrant mask of a staged record (see stage_record).
-__device__ __forceinline__ uint32_t staged_quads(const float4* c) {
-  return __float_as_uint(reinterpret_cast<const float*>(c)[3]);
+  B = make_float4((-0.5f * kLog2e) * r1.x, r1.y, r1.z, -__log2f(255.0f * r1.y));
+  C = make_float4(r1.w, r2.x, r2.y, 0.f);
 }
 
 // Base-2 exponent of a staged record at pixel centre (px, py); dx, dy = mu - p

@@ -51,17 +51,6 @@ __device__ __forceinline__ float2 tile_origin(const ViewInfo& cam, int gtile) {
   return make_float2((float)((lt % cam.tiles_x) * kTile), (float)((lt / cam.tiles_x) * kTile));
 }
 
-// The quadrants whose pixels wave (threadIdx.x / 64) owns: pixel q of the
-// tile lies in quadrant q / 64, and the wave's lanes own q = k L + lane.
-template <int kPPL>
-__device__ __forceinline__ uint32_t wave_quads() {
-  constexpr int L = kTilePixels / kPPL;
-  uint32_t m = 0;
-#pragma unroll
-  for (int k = 0; k < kPPL; ++k) m |= 1u << ((k * L + (int)threadIdx.x) >> 6);
-  return m;
-}
-
 __device__ __forceinline__ float sgn(float x) { return (float)((x > 0.f) - (x < 0.f)); }
 
 template <int kPPL, bool kTrack, bool kNu>
@@ -88,7 +77,6 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(Rast
   uint32_t dom[kPPL];             // kNu: its record id, kNone if none
   bool inside[kPPL], done[kPPL];
   bool lane_done = true;
-  const uint32_t wq = wave_quads<kPPL>();
 #pragma unroll
   for (int k = 0; k < kPPL; ++k) {
     const PixelCoord pc = pixel_of(cam, gtile, k * L + threadIdx.x);
@@ -117,13 +105,13 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(Rast
       stage_record(b.rec + (int64_t)kRecF4 * m, org.x, org.y, sA[i], sB[i], sC[i]);
     }
     __syncthreads();
-    // The wave walks the batch while any of its lanes still blends; lanes
-    // that are done ride along predicated off, and the wave leaves together
-    // (checked every 8 records), so the loop carries no per-lane exit masks.
+    // The wave walks the whole batch while any of its lanes still blends;
+    // lanes that are done ride along predicated off.  (A vote every few
+    // records to leave early cost more issue slots than it saved: at tracking
+    // sizes most pixels never reach the stop threshold.)
     if (__ballot(!lane_done) != 0ull) {
       const uint32_t off = base - range.x;
       for (int j = 0; j < n; ++j) {
-        if (staged_quads(&sC[j]) & wq) {
         const float4 A = sA[j];
         const float4 B = sB[j];
         const float4 Cc = sC[j];
@@ -163,13 +151,6 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(Rast
           T[k] = blend ? Tn : T[k];
           last[k] = blend ? off + j + 1 : last[k];
           blended[k] += blend ? 1u : 0u;
-        }
-        }
-        if ((j & 7) == 7) {
-          bool all = true;
-#pragma unroll
-          for (int k = 0; k < kPPL; ++k) all = all && done[k];
-          if (__ballot(!all) == 0ull) break;
         }
       }
       bool all = true;
@@ -257,7 +238,6 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
   float Bc0[kPPL], Bc1[kPPL], Bc2[kPPL], Bd[kPPL], Bo[kPPL], Bu[kPPL];
   int walked[kPPL], med[kPPL];
   uint32_t lane_max = 0;
-  const uint32_t wq = wave_quads<kPPL>();
 #pragma unroll
   for (int k = 0; k < kPPL; ++k) {
     const PixelCoord pc = pixel_of(cam, gtile, k * L + threadIdx.x);
@@ -313,10 +293,9 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
     __syncthreads();
     for (int j = n - 1; j >= 0; --j) {
       const int pos = start + j;
-      if (!(staged_quads(&sC[j]) & wq)) continue;   // no pixel of this wave can blend it
       const float4 A = sA[j];
       const float4 B = sB[j];
-      float gmx = 0.f, gmy = 0.f, ga = 0.f, gb = 0.f, gcc = 0.f, gop = 0.f, gdd = 0.f;
+      float u1 = 0.f, u2 = 0.f, sxx = 0.f, sxy = 0.f, syy = 0.f, gop = 0.f, gdd = 0.f;
       float gr = 0.f, gg = 0.f, gbl = 0.f;
       bool any = false;
       const float4 Cc = sC[j];
@@ -355,13 +334,17 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
         const bool live = hit && !(raw > kAlphaMax);   // a capped alpha has no gradient
         const float dpower = live ? dalpha * raw : 0.f;   // alpha = opacity * exp(power)
         // power = -(a dx^2 + 2 b dx dy + c dy^2) / 2 = ln2 (qa t^2 + qc dy^2)
-        // with t = dx + k dy: d power/d mu = 2 ln2 (qa t, qa k t + qc dy)
-        const float qt = dpower * (2.f * kLn2) * A.z * tq;
-        gmx += qt;
-        gmy += __builtin_fmaf(qt, A.w, dpower * (2.f * kLn2) * B.x * dy);
-        ga -= 0.5f * dpower * dx * dx;
-        gb -= dpower * dx * dy;
-        gcc -= 0.5f * dpower * dy * dy;
+        // with t = dx + k dy, so d power/d mu = 2 ln2 (qa t, qa k t + qc dy)
+        // and d power/d(a, b, c) = -(dx^2 / 2, dx dy, dy^2 / 2).  The factors
+        // that belong to the record (qa, k, qc, the constants) are applied
+        // once after the wave reduction; lanes only accumulate
+        // u1 = sum dpower t, u2 = sum dpower dy and the second moments.
+        const float pdx = dpower * dx, pdy = dpower * dy;
+        u1 = __builtin_fmaf(dpower, tq, u1);
+        u2 += pdy;
+        sxx = __builtin_fmaf(pdx, dx, sxx);
+        sxy = __builtin_fmaf(pdx, dy, sxy);
+        syy = __builtin_fmaf(pdy, dy, syy);
         gdd += wgt * gd[k];
         if (!kTrack) gdd += 2.f * wgt * dz * gu[k] + ((hit && pos == med[k]) ? gm[k] : 0.f);
         if (kParams) {
@@ -374,17 +357,31 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
       if (__ballot(any)) {
         const uint32_t m = sM[j];
         float* dst = b.rec_grad + (int64_t)kGradStride * m;
+        // values 0-4 (u1, u2, sxx, sxy, syy) become the gradients of mu x,
+        // mu y and the conic (a, b, c); the rest pass through.
+        auto finish = [&](int idx, float t) {
+          const float U1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, t), 0));
+          const float c2 = 2.f * kLn2;
+          float out = t;
+          out = idx == 0 ? c2 * A.z * t : out;
+          out = idx == 1 ? c2 * __builtin_fmaf(A.z * A.w, U1, B.x * t) : out;
+          out = (idx == 2 || idx == 4) ? -0.5f * t : out;
+          out = idx == 3 ? -t : out;
+          return out;
+        };
         if (kParams) {
           // slots 0-9: mu x, mu y, conic a, b, c, opacity, depth, colour
-          const float vals[10] = {gmx, gmy, ga, gb, gcc, gop, gdd, gr, gg, gbl};
+          const float vals[10] = {u1, u2, sxx, sxy, syy, gop, gdd, gr, gg, gbl};
           const float t = wave_sum_many<16>(vals);
           const int idx = reduced_value_index<16>(lane);
-          if ((lane & 3) == 0 && idx < 10) unsafeAtomicAdd(dst + idx, t);
+          const float out = finish(idx, t);
+          if ((lane & 3) == 0 && idx < 10) unsafeAtomicAdd(dst + idx, out);
         } else {
-          const float vals[6] = {gmx, gmy, ga, gb, gcc, gdd};
+          const float vals[6] = {u1, u2, sxx, sxy, syy, gdd};
           const float t = wave_sum_many<8>(vals);
           const int idx = reduced_value_index<8>(lane);
-          if ((lane & 7) == 0 && idx < 6) unsafeAtomicAdd(dst + (idx == 5 ? 6 : idx), t);
+          const float out = finish(idx, t);
+          if ((lane & 7) == 0 && idx < 6) unsafeAtomicAdd(dst + (idx == 5 ? 6 : idx), out);
         }
       }
     }
