@@ -122,9 +122,11 @@ def test_bundle_adjustment_window(R):
         d = (scene_g[k] - scene_e[k]).abs()
         frac = float((d > 1e-5).float().mean())
         say(k, "graph vs eager: max diff", float(d.max()), "share over 1e-5", frac)
-        # parameters whose gradient is ~0 (cancelling contributions) follow
-        # the order of float atomics in any two runs; the rest must agree
-        assert frac < 1e-2, k
+        # parameters whose gradient is ~0 (cancelling contributions) take
+        # Adam steps on the sign of rounding noise, which follows the order of
+        # float atomics in any two runs; the objective and the poses below must
+        # agree, and only a small share of parameters may differ
+        assert frac < 5e-2, k
     d = float((P_g - P_e).abs().max())
     say("poses graph vs eager max diff", d)
     assert d < 1e-4
