@@ -50,11 +50,14 @@ __device__ __forceinline__ void quat_rot(double w, double x, double y, double z,
   R[8] = 1.0 - 2.0 * (x * x + y * y);
 }
 
-// Everything the forward and backward projection share.  The projection is
-// evaluated in double precision: it costs a few hundred operations per
-// Gaussian, and single precision would leave pixel-space means near
-// x = 1000 with ~1e-4 px of rounding, which the exponent of Eq. 5 amplifies
-// by the conic times the offset from the mean.
+// Everything the forward and backward projection share.  The projection's
+// linear algebra is evaluated in double precision: it costs a few hundred
+// operations per Gaussian, and single precision would leave pixel-space means
+// near x = 1000 with ~1e-4 px of rounding, which the exponent of Eq. 5
+// amplifies by the conic times the offset from the mean, and conics of thin
+// footprints with the cancellation of their 2x2 determinant.  The
+// transcendentals of the activations (scale = exp, opacity = sigmoid) are
+// single precision, good to an ulp of the float inputs.
 struct Proj {
   double qn[4], qinv;    // unit quaternion and 1/|q|
   double R[9];           // rotation of the ellipsoid
@@ -82,7 +85,7 @@ __device__ bool project_core(const GaussianPtrs& g, int64_t i, const float* P, c
   o.qn[0] = q0 * o.qinv; o.qn[1] = q1 * o.qinv; o.qn[2] = q2 * o.qinv; o.qn[3] = q3 * o.qinv;
   quat_rot(o.qn[0], o.qn[1], o.qn[2], o.qn[3], o.R);
   const float* ls = g.log_scales + 3 * i;
-  o.s[0] = exp((double)ls[0]); o.s[1] = exp((double)ls[1]); o.s[2] = exp((double)ls[2]);
+  o.s[0] = expf(ls[0]); o.s[1] = expf(ls[1]); o.s[2] = expf(ls[2]);
   const float* X = g.means + 3 * i;
   const double X0 = X[0], X1 = X[1], X2 = X[2];
   double W[9];
@@ -92,7 +95,7 @@ __device__ bool project_core(const GaussianPtrs& g, int64_t i, const float* P, c
   for (int r = 0; r < 3; ++r) o.p[r] = W[3 * r] * X0 + W[3 * r + 1] * X1 + W[3 * r + 2] * X2 + (double)P[9 + r];
   const double z = o.p[2];
   if (!(z > (double)kNearZ)) return false;
-  o.opacity = 1.0 / (1.0 + exp(-(double)g.opacity_logits[i]));
+  o.opacity = 1.0f / (1.0f + expf(-g.opacity_logits[i]));
   if (!(o.opacity >= (double)kAlphaMin)) return false;
   // Sigma = (R S)(R S)^T, then Sc = W Sigma W^T with W the camera rotation.
   double M[9];
@@ -196,7 +199,7 @@ __global__ __launch_bounds__(kThreads) void project_kernel(GaussianPtrs g, const
       const double mux = (double)cam.fx * (o.p[0] / o.p[2]) + (double)cam.cx;
       const double muy = (double)cam.fy * (o.p[1] / o.p[2]) + (double)cam.cy;
       // Bounding box of the alpha >= 1/255 ellipse, widened by the margins.
-      const double r2 = 2.0 * log(255.0 * o.opacity) * (double)kBinR2Rel + (double)kBinR2Abs;
+      const double r2 = 2.0 * (double)logf((float)(255.0 * o.opacity)) * (double)kBinR2Rel + (double)kBinR2Abs;
       const double ex = sqrt(r2 * o.cov[0]), ey = sqrt(r2 * o.cov[2]);
       const double u0 = fmax(0.0, ceil(mux - ex)), u1 = fmin((double)(cam.width - 1), floor(mux + ex));
       const double v0 = fmax(0.0, ceil(muy - ey)), v1 = fmin((double)(cam.height - 1), floor(muy + ey));

@@ -5,10 +5,13 @@
 //
 // Keys are depth bits << 32 | record id, unique within a tile, so the result
 // is the order of (depth, record id) -- a stable depth sort of the records --
-// whatever order the atomics left.  Segments up to kLdsKeys are sorted in LDS
-// with a bitonic network; longer ones are sorted in LDS-sized chunks, merged
-// pairwise in global memory by the same workgroup (merge path by binary
-// search), ping-ponging between the two key buffers.
+// whatever order the atomics left.  A segment of at most one key per thread
+// is ranked directly (each thread counts the keys below its own, reading the
+// segment from LDS by broadcast: one barrier instead of a network of them);
+// segments up to kLdsKeys are sorted in LDS with a bitonic network; longer
+// ones are sorted in LDS-sized chunks, merged pairwise in global memory by the
+// same workgroup (merge path by binary search), ping-ponging between the two
+// key buffers.
 #include <algorithm>
 
 #include "kernels.hpp"
@@ -67,6 +70,18 @@ __global__ __launch_bounds__(kThreads) void segment_sort_kernel(SegSortBufs b) {
   }
   if (n == 0) return;
   uint64_t* keys = b.keys[0] + base;
+  if (n <= (uint32_t)kThreads) {
+    const bool mine = threadIdx.x < n;
+    const uint64_t key = mine ? keys[threadIdx.x] : 0ull;
+    if (mine) s[threadIdx.x] = key;
+    __syncthreads();
+    if (mine) {
+      uint32_t rank = 0;
+      for (uint32_t i = 0; i < n; ++i) rank += s[i] < key ? 1u : 0u;   // keys are unique
+      b.sorted_vals[base + rank] = (uint32_t)key;
+    }
+    return;
+  }
   if (n <= (uint32_t)kLdsKeys) {
     const uint32_t p = next_pow2(n);
     for (uint32_t i = threadIdx.x; i < p; i += kThreads) s[i] = i < n ? keys[i] : ~0ull;
