@@ -55,9 +55,10 @@ __device__ __forceinline__ void quat_rot(double w, double x, double y, double z,
 // operations per Gaussian, and single precision would leave pixel-space means
 // near x = 1000 with ~1e-4 px of rounding, which the exponent of Eq. 5
 // amplifies by the conic times the offset from the mean, and conics of thin
-// footprints with the cancellation of their 2x2 determinant.  The
-// transcendentals of the activations (scale = exp, opacity = sigmoid) are
-// single precision, good to an ulp of the float inputs.
+// footprints with the cancellation of their 2x2 determinant (which also
+// amplifies any rounding of the scales, so exp of the log-scales is double
+// too).  The opacity sigmoid and the rectangle's log are single precision:
+// they enter linearly or against a relative margin.
 struct Proj {
   double qn[4], qinv;    // unit quaternion and 1/|q|
   double R[9];           // rotation of the ellipsoid
@@ -85,7 +86,7 @@ __device__ bool project_core(const GaussianPtrs& g, int64_t i, const float* P, c
   o.qn[0] = q0 * o.qinv; o.qn[1] = q1 * o.qinv; o.qn[2] = q2 * o.qinv; o.qn[3] = q3 * o.qinv;
   quat_rot(o.qn[0], o.qn[1], o.qn[2], o.qn[3], o.R);
   const float* ls = g.log_scales + 3 * i;
-  o.s[0] = expf(ls[0]); o.s[1] = expf(ls[1]); o.s[2] = expf(ls[2]);
+  o.s[0] = exp((double)ls[0]); o.s[1] = exp((double)ls[1]); o.s[2] = exp((double)ls[2]);
   const float* X = g.means + 3 * i;
   const double X0 = X[0], X1 = X[1], X2 = X[2];
   double W[9];
