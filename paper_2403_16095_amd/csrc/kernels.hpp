@@ -133,6 +133,9 @@ void launch_gaussian_adam(int64_t n, const GaussianAdam& a, float* moments, uint
 void launch_nu_prune(int64_t n, const float* nu_sum, const uint32_t* nu_count, float tau, float low_logit,
                      float* opacity_logits, float* nu, uint32_t* n_pruned, hipStream_t s);
 void launch_raster_backward(const RasterBufs& b, bool param_grads, bool track, int ppl, hipStream_t s);
+// Forward, tracking-loss gradients and pose-only blend backward of each tile
+// in one launch (rec_grad +=); writes pixel_state / pixel_count for the stats.
+void launch_raster_track(const RasterBufs& b, int ppl, hipStream_t s);
 
 void launch_tracking_loss(int w, int h, const float* color, const float* depth, const float* tcolor,
                           const float* tdepth, float lc, float ld, float* dcolor, float* ddepth, float* loss,

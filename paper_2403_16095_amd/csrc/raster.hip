@@ -6,8 +6,7 @@
 // pixels are whole quadrants and leave together.  The tile's depth-ordered
 // records are staged through LDS 256 at a time (see stage_record); every lane
 // then reads the same LDS address, a broadcast free of bank conflicts, and
-// uses it for all of its pixels.  A pair below the skip threshold costs one
-// base-2 exponent and a compare; only blended pairs evaluate exp2.
+// uses it for all of its pixels.
 //
 // kNu (mapping renders) also keeps, per pixel, the blended Gaussian of
 // largest weight alpha T -- the pixel is "dominated" by it (Sec. 3.2,
@@ -16,8 +15,12 @@
 //
 // Tracking mode (kTrack) forms the gradient images of the tracking loss
 // (Eq. 19: L1 colour, Eq. 14, and L1 depth, Eq. 16) at the end of the
-// forward, straight from the blended values in registers, and keeps them in
-// a per-pixel buffer for the backward instead of writing maps.
+// forward, straight from the blended values in registers.  The loss is per
+// pixel, so a tile's backward needs nothing from other tiles:
+// raster_track_kernel runs the forward and the pose backward of a tile in one
+// workgroup, the per-pixel state never leaves registers, and the records
+// staged for the forward are reused by the backward when the tile's list fits
+// one batch.  The separate kernels serve rendering and the mapping backward.
 #include "kernels.hpp"
 
 namespace cgsr {
@@ -53,21 +56,27 @@ __device__ __forceinline__ float2 tile_origin(const ViewInfo& cam, int gtile) {
 
 __device__ __forceinline__ float sgn(float x) { return (float)((x > 0.f) - (x < 0.f)); }
 
-template <int kPPL, bool kTrack, bool kNu>
-__global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(RasterBufs b) {
-  constexpr int L = kTilePixels / kPPL;
-  __shared__ float4 sA[kBatch];
-  __shared__ float4 sB[kBatch];
-  __shared__ float4 sC[kBatch];
-  __shared__ uint32_t sM[kNu ? kBatch : 1];
-  const int gtile = blockIdx.x;
-  const int v = view_of_tile(b.views, gtile);
-  const ViewIO io = b.views.io[v];
-  const ViewInfo cam = io.info;
-  const float2 org = tile_origin(cam, gtile);
-  const uint2 range = b.ranges[gtile];
-  const int64_t hw = (int64_t)cam.width * cam.height;
+// The LDS batch of staged records (see stage_record) and their record ids.
+struct Stage {
+  float4 A[kBatch], B[kBatch], C[kBatch];
+  uint32_t M[kBatch];
+};
 
+// Stages list entries [first, first + n) of the tile; every thread calls it.
+template <int L>
+__device__ __forceinline__ void stage_batch(const RasterBufs& b, Stage& s, uint32_t first, int n, float2 org) {
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += L) {
+    const uint32_t m = b.vals[first + i];
+    s.M[i] = m;
+    stage_record(b.rec + (int64_t)kRecF4 * m, org.x, org.y, s.A[i], s.B[i], s.C[i]);
+  }
+  __syncthreads();
+}
+
+// Per-lane state of the forward walk.
+template <int kPPL>
+struct FwdPix {
   float fx[kPPL], fy[kPPL], dobs[kPPL], T[kPPL], C0[kPPL], C1[kPPL], C2[kPPL], D[kPPL], O[kPPL], U[kPPL],
       Dmed[kPPL];
   int64_t pix[kPPL];
@@ -76,35 +85,39 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(Rast
   float wdom[kPPL], ddom[kPPL];   // kNu: largest weight so far and its depth
   uint32_t dom[kPPL];             // kNu: its record id, kNone if none
   bool inside[kPPL], done[kPPL];
+};
+
+// Front-to-back walk of the tile's list (Eq. 3-9, Eq. 10 with kTrack off).
+// On return the stage holds the last batch walked; that is the whole list when
+// it fits one batch.
+template <int kPPL, bool kTrack, bool kNu>
+__device__ __forceinline__ void forward_tile(const RasterBufs& b, Stage& s, int gtile, const ViewIO& io,
+                                             float2 org, uint2 range, FwdPix<kPPL>& f) {
+  constexpr int L = kTilePixels / kPPL;
+  const ViewInfo& cam = io.info;
   bool lane_done = true;
 #pragma unroll
   for (int k = 0; k < kPPL; ++k) {
     const PixelCoord pc = pixel_of(cam, gtile, k * L + threadIdx.x);
-    fx[k] = (float)(pc.px - pc.ox);
-    fy[k] = (float)(pc.py - pc.oy);
-    inside[k] = pc.inside;
-    pix[k] = (int64_t)pc.py * cam.width + pc.px;
-    dobs[k] = (!kTrack && io.depth_obs && pc.inside) ? io.depth_obs[pix[k]] : 0.f;
-    T[k] = 1.f;
-    C0[k] = C1[k] = C2[k] = D[k] = O[k] = U[k] = Dmed[k] = 0.f;
-    med[k] = -1;
-    last[k] = 0;
-    blended[k] = 0;
-    wdom[k] = ddom[k] = 0.f;
-    dom[k] = kNone;
-    evaluated[k] = range.y - range.x;
-    done[k] = !pc.inside;
-    lane_done = lane_done && done[k];
+    f.fx[k] = (float)(pc.px - pc.ox);
+    f.fy[k] = (float)(pc.py - pc.oy);
+    f.inside[k] = pc.inside;
+    f.pix[k] = (int64_t)pc.py * cam.width + pc.px;
+    f.dobs[k] = (!kTrack && io.depth_obs && pc.inside) ? io.depth_obs[f.pix[k]] : 0.f;
+    f.T[k] = 1.f;
+    f.C0[k] = f.C1[k] = f.C2[k] = f.D[k] = f.O[k] = f.U[k] = f.Dmed[k] = 0.f;
+    f.med[k] = -1;
+    f.last[k] = 0;
+    f.blended[k] = 0;
+    f.wdom[k] = f.ddom[k] = 0.f;
+    f.dom[k] = kNone;
+    f.evaluated[k] = range.y - range.x;
+    f.done[k] = !pc.inside;
+    lane_done = lane_done && f.done[k];
   }
   for (uint32_t base = range.x; base < range.y; base += kBatch) {
     const int n = (int)min((uint32_t)kBatch, range.y - base);
-    __syncthreads();
-    for (int i = threadIdx.x; i < n; i += L) {
-      const uint32_t m = b.vals[base + i];
-      if (kNu) sM[i] = m;
-      stage_record(b.rec + (int64_t)kRecF4 * m, org.x, org.y, sA[i], sB[i], sC[i]);
-    }
-    __syncthreads();
+    stage_batch<L>(b, s, base, n, org);
     // The wave walks the whole batch while any of its lanes still blends;
     // lanes that are done ride along predicated off.  (A vote every few
     // records to leave early cost more issue slots than it saved: at tracking
@@ -112,54 +125,64 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(Rast
     if (__ballot(!lane_done) != 0ull) {
       const uint32_t off = base - range.x;
       for (int j = 0; j < n; ++j) {
-        const float4 A = sA[j];
-        const float4 B = sB[j];
-        const float4 Cc = sC[j];
+        const float4 A = s.A[j];
+        const float4 B = s.B[j];
+        const float4 Cc = s.C[j];
         // Straight-line, predicated per lane: a lane that skips (alpha below
         // 1/255, or already done) adds exact zeros, so the results are those
         // of the branching form, without exec-mask bookkeeping per record.
 #pragma unroll
         for (int k = 0; k < kPPL; ++k) {
           float dx, dy, tq;
-          const float e = pair_exponent(A, B, fx[k], fy[k], dx, dy, tq);
-          const bool hit = !done[k] && e >= B.w;
+          const float e = pair_exponent(A, B, f.fx[k], f.fy[k], dx, dy, tq);
+          const bool hit = !f.done[k] && e >= B.w;
           const float alpha = fminf(kAlphaMax, B.y * __builtin_amdgcn_exp2f(e));
-          const float Tn = T[k] * (1.f - alpha);
+          const float Tn = f.T[k] * (1.f - alpha);
           const bool stop = hit && Tn < kTStop;
           const bool blend = hit && !stop;
-          done[k] = done[k] || stop;
-          evaluated[k] = stop ? off + j + 1 : evaluated[k];
-          const float wgt = blend ? alpha * T[k] : 0.f;
-          C0[k] = __builtin_fmaf(wgt, Cc.x, C0[k]);
-          C1[k] = __builtin_fmaf(wgt, Cc.y, C1[k]);
-          C2[k] = __builtin_fmaf(wgt, Cc.z, C2[k]);
-          D[k] = __builtin_fmaf(wgt, B.z, D[k]);
-          O[k] += wgt;
+          f.done[k] = f.done[k] || stop;
+          f.evaluated[k] = stop ? off + j + 1 : f.evaluated[k];
+          const float wgt = blend ? alpha * f.T[k] : 0.f;
+          f.C0[k] = __builtin_fmaf(wgt, Cc.x, f.C0[k]);
+          f.C1[k] = __builtin_fmaf(wgt, Cc.y, f.C1[k]);
+          f.C2[k] = __builtin_fmaf(wgt, Cc.z, f.C2[k]);
+          f.D[k] = __builtin_fmaf(wgt, B.z, f.D[k]);
+          f.O[k] += wgt;
           if (!kTrack) {
-            const float dz = B.z - dobs[k];
-            U[k] = __builtin_fmaf(wgt * dz, dz, U[k]);
+            const float dz = B.z - f.dobs[k];
+            f.U[k] = __builtin_fmaf(wgt * dz, dz, f.U[k]);
           }
-          const bool first_med = blend && med[k] < 0 && Tn < kTMedian;
-          med[k] = first_med ? (int)(off + j) : med[k];
-          Dmed[k] = first_med ? B.z : Dmed[k];
+          const bool first_med = blend && f.med[k] < 0 && Tn < kTMedian;
+          f.med[k] = first_med ? (int)(off + j) : f.med[k];
+          f.Dmed[k] = first_med ? B.z : f.Dmed[k];
           if (kNu) {
-            const bool more = blend && wgt > wdom[k];   // strict: the first of equal maxima
-            wdom[k] = more ? wgt : wdom[k];
-            ddom[k] = more ? B.z : ddom[k];
-            dom[k] = more ? sM[j] : dom[k];
+            const bool more = blend && wgt > f.wdom[k];   // strict: the first of equal maxima
+            f.wdom[k] = more ? wgt : f.wdom[k];
+            f.ddom[k] = more ? B.z : f.ddom[k];
+            f.dom[k] = more ? s.M[j] : f.dom[k];
           }
-          T[k] = blend ? Tn : T[k];
-          last[k] = blend ? off + j + 1 : last[k];
-          blended[k] += blend ? 1u : 0u;
+          f.T[k] = blend ? Tn : f.T[k];
+          f.last[k] = blend ? off + j + 1 : f.last[k];
+          f.blended[k] += blend ? 1u : 0u;
         }
       }
       bool all = true;
 #pragma unroll
-      for (int k = 0; k < kPPL; ++k) all = all && done[k];
+      for (int k = 0; k < kPPL; ++k) all = all && f.done[k];
       lane_done = all;
     }
     if (__syncthreads_count(lane_done) == L) break;
   }
+}
+
+// Everything the forward leaves behind: maps, saved per-pixel state, the
+// tracking-loss gradients (returned in g; stored for a separate backward when
+// store_grad) and the Eq. 13 accumulation.
+template <int kPPL, bool kTrack, bool kNu>
+__device__ __forceinline__ void forward_outputs(const RasterBufs& b, int v, const ViewIO& io,
+                                                const FwdPix<kPPL>& f, float (&g)[kPPL][4], bool store_grad) {
+  const ViewInfo& cam = io.info;
+  const int64_t hw = (int64_t)cam.width * cam.height;
   if (kTrack) {
     // dL/dcolour and dL/ddepth of L = lc mean_n |I^ - I|_1 + ld mean_n |D^ - D|.
     float l = 0.f;
@@ -167,11 +190,17 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(Rast
     const float lc = b.lambda_color * inv, ld = b.lambda_depth * inv;
 #pragma unroll
     for (int k = 0; k < kPPL; ++k) {
-      if (!inside[k]) continue;
-      const int64_t p = pix[k];
-      const float e0 = C0[k] - io.t_color[p], e1 = C1[k] - io.t_color[hw + p], e2 = C2[k] - io.t_color[2 * hw + p];
-      const float ed = D[k] - io.t_depth[p];
-      b.pixel_grad[cam.pixel_base + p] = make_float4(lc * sgn(e0), lc * sgn(e1), lc * sgn(e2), ld * sgn(ed));
+      g[k][0] = g[k][1] = g[k][2] = g[k][3] = 0.f;
+      if (!f.inside[k]) continue;
+      const int64_t p = f.pix[k];
+      const float e0 = f.C0[k] - io.t_color[p], e1 = f.C1[k] - io.t_color[hw + p],
+                  e2 = f.C2[k] - io.t_color[2 * hw + p];
+      const float ed = f.D[k] - io.t_depth[p];
+      g[k][0] = lc * sgn(e0);
+      g[k][1] = lc * sgn(e1);
+      g[k][2] = lc * sgn(e2);
+      g[k][3] = ld * sgn(ed);
+      if (store_grad) b.pixel_grad[cam.pixel_base + p] = make_float4(g[k][0], g[k][1], g[k][2], g[k][3]);
       l += lc * (fabsf(e0) + fabsf(e1) + fabsf(e2)) + ld * fabsf(ed);
     }
     if (b.loss) {
@@ -181,30 +210,50 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(Rast
   }
 #pragma unroll
   for (int k = 0; k < kPPL; ++k) {
-    if (!inside[k]) continue;
-    const int64_t p = pix[k];
+    if (!f.inside[k]) continue;
+    const int64_t p = f.pix[k];
     if (io.color) {
-      io.color[p] = C0[k];
-      io.color[hw + p] = C1[k];
-      io.color[2 * hw + p] = C2[k];
+      io.color[p] = f.C0[k];
+      io.color[hw + p] = f.C1[k];
+      io.color[2 * hw + p] = f.C2[k];
     }
-    if (io.depth) io.depth[p] = D[k];
-    if (io.opacity) io.opacity[p] = O[k];
-    if (io.depth_median) io.depth_median[p] = Dmed[k];
-    if (io.uncertainty) io.uncertainty[p] = U[k];
-    b.pixel_state[cam.pixel_base + p] = make_uint4(__float_as_uint(T[k]), last[k], (uint32_t)med[k], evaluated[k]);
-    b.pixel_count[cam.pixel_base + p] = blended[k];
+    if (io.depth) io.depth[p] = f.D[k];
+    if (io.opacity) io.opacity[p] = f.O[k];
+    if (io.depth_median) io.depth_median[p] = f.Dmed[k];
+    if (io.uncertainty) io.uncertainty[p] = f.U[k];
+    b.pixel_state[cam.pixel_base + p] =
+        make_uint4(__float_as_uint(f.T[k]), f.last[k], (uint32_t)f.med[k], f.evaluated[k]);
+    b.pixel_count[cam.pixel_base + p] = f.blended[k];
     if (kNu) {
       // record id m = view * N + Gaussian index
-      const int gi = dom[k] == kNone ? -1 : (int)(dom[k] - (uint32_t)v * (uint32_t)b.views.n_gauss);
+      const int gi = f.dom[k] == kNone ? -1 : (int)(f.dom[k] - (uint32_t)v * (uint32_t)b.views.n_gauss);
       if (io.dominant) io.dominant[p] = gi;
-      if (gi >= 0 && dobs[k] > 0.f && b.nu_sum) {
-        const float e = dobs[k] - ddom[k];
-        unsafeAtomicAdd(b.nu_sum + gi, wdom[k] * e * e);
+      if (gi >= 0 && f.dobs[k] > 0.f && b.nu_sum) {
+        const float e = f.dobs[k] - f.ddom[k];
+        unsafeAtomicAdd(b.nu_sum + gi, f.wdom[k] * e * e);
         atomicAdd(b.nu_count + gi, 1u);
       }
     }
   }
+}
+
+// Per-lane state of the backward walk.
+template <int kPPL>
+struct BwdPix {
+  float fx[kPPL], fy[kPPL], T[kPPL], gc0[kPPL], gc1[kPPL], gc2[kPPL], gd[kPPL], go[kPPL], gm[kPPL], gu[kPPL],
+      dobs[kPPL];
+  float Bc0[kPPL], Bc1[kPPL], Bc2[kPPL], Bd[kPPL], Bo[kPPL], Bu[kPPL];
+  int walked[kPPL], med[kPPL];
+};
+
+// Largest walked length over the workgroup.
+__device__ __forceinline__ int block_max(uint32_t lane_max, uint32_t* s_max) {
+  __syncthreads();
+  if (threadIdx.x == 0) *s_max = 0u;
+  __syncthreads();
+  if (lane_max) atomicMax(s_max, lane_max);
+  __syncthreads();
+  return (int)*s_max;
 }
 
 // Back-to-front over each pixel's blended run.  With the normalised "behind"
@@ -213,92 +262,26 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(Rast
 // T_j = T_{j+1} / (1 - alpha_j) recovers the transmittance from the final one.
 // A lane first sums its pixels' contributions to a Gaussian, then the wave
 // reduces all of the Gaussian's gradient terms together (wave_sum_many) and
-// issues one atomic instruction.  kParams adds the
-// opacity and colour gradients (mapping); kTrack takes the upstream
-// gradients from the tracking forward (colour and depth only).
+// issues one atomic instruction.  kParams adds the opacity and colour
+// gradients (mapping); kTrack has colour and depth upstream gradients only.
+// staged_n > 0: the stage already holds list entries [0, staged_n).
 template <int kPPL, bool kParams, bool kTrack>
-__global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(RasterBufs b) {
+__device__ __forceinline__ void backward_tile(const RasterBufs& b, Stage& s, uint2 range, float2 org, int nmax,
+                                              int staged_n, BwdPix<kPPL>& p) {
   constexpr int L = kTilePixels / kPPL;
-  __shared__ float4 sA[kBatch];
-  __shared__ float4 sB[kBatch];
-  __shared__ float4 sC[kBatch];
-  __shared__ uint32_t sM[kBatch];
-  __shared__ uint32_t s_max;
-  const int gtile = blockIdx.x;
-  const int v = view_of_tile(b.views, gtile);
-  const ViewIO io = b.views.io[v];
-  const ViewInfo cam = io.info;
-  const float2 org = tile_origin(cam, gtile);
-  const int64_t hw = (int64_t)cam.width * cam.height;
-  const uint2 range = b.ranges[gtile];
   const int lane = threadIdx.x & 63;
-
-  float fx[kPPL], fy[kPPL], T[kPPL], gc0[kPPL], gc1[kPPL], gc2[kPPL], gd[kPPL], go[kPPL], gm[kPPL], gu[kPPL],
-      dobs[kPPL];
-  float Bc0[kPPL], Bc1[kPPL], Bc2[kPPL], Bd[kPPL], Bo[kPPL], Bu[kPPL];
-  int walked[kPPL], med[kPPL];
-  uint32_t lane_max = 0;
-#pragma unroll
-  for (int k = 0; k < kPPL; ++k) {
-    const PixelCoord pc = pixel_of(cam, gtile, k * L + threadIdx.x);
-    const int64_t pix = (int64_t)pc.py * cam.width + pc.px;
-    fx[k] = (float)(pc.px - pc.ox);
-    fy[k] = (float)(pc.py - pc.oy);
-    T[k] = 1.f;
-    walked[k] = 0;
-    med[k] = -1;
-    gc0[k] = gc1[k] = gc2[k] = gd[k] = go[k] = gm[k] = gu[k] = dobs[k] = 0.f;
-    Bc0[k] = Bc1[k] = Bc2[k] = Bd[k] = Bo[k] = Bu[k] = 0.f;
-    if (pc.inside) {
-      const uint4 ps = b.pixel_state[cam.pixel_base + pix];
-      T[k] = __uint_as_float(ps.x);
-      walked[k] = (int)ps.y;
-      med[k] = (int)ps.z;
-      if (kTrack) {
-        const float4 g4 = b.pixel_grad[cam.pixel_base + pix];
-        gc0[k] = g4.x;
-        gc1[k] = g4.y;
-        gc2[k] = g4.z;
-        gd[k] = g4.w;
-      } else {
-        if (io.g_color) {
-          gc0[k] = io.g_color[pix];
-          gc1[k] = io.g_color[hw + pix];
-          gc2[k] = io.g_color[2 * hw + pix];
-        }
-        if (io.g_depth) gd[k] = io.g_depth[pix];
-        if (io.g_opacity) go[k] = io.g_opacity[pix];
-        if (io.g_median) gm[k] = io.g_median[pix];
-        if (io.g_uncertainty) gu[k] = io.g_uncertainty[pix];
-        if (io.depth_obs) dobs[k] = io.depth_obs[pix];
-      }
-      lane_max = max(lane_max, (uint32_t)walked[k]);
-    }
-  }
-  if (threadIdx.x == 0) s_max = 0u;
-  __syncthreads();
-  if (lane_max) atomicMax(&s_max, lane_max);
-  __syncthreads();
-  const int nmax = (int)s_max;
-
   for (int end = nmax; end > 0; end -= kBatch) {
     const int start = max(0, end - kBatch);
     const int n = end - start;
-    __syncthreads();
-    for (int i = threadIdx.x; i < n; i += L) {
-      const uint32_t m = b.vals[range.x + start + i];
-      sM[i] = m;
-      stage_record(b.rec + (int64_t)kRecF4 * m, org.x, org.y, sA[i], sB[i], sC[i]);
-    }
-    __syncthreads();
+    if (!(start == 0 && end <= staged_n)) stage_batch<L>(b, s, range.x + start, n, org);
     for (int j = n - 1; j >= 0; --j) {
       const int pos = start + j;
-      const float4 A = sA[j];
-      const float4 B = sB[j];
+      const float4 A = s.A[j];
+      const float4 B = s.B[j];
       float u1 = 0.f, u2 = 0.f, sxx = 0.f, sxy = 0.f, syy = 0.f, gop = 0.f, gdd = 0.f;
       float gr = 0.f, gg = 0.f, gbl = 0.f;
       bool any = false;
-      const float4 Cc = sC[j];
+      const float4 Cc = s.C[j];
       // Straight-line, predicated per lane: a lane that did not blend this
       // record (past its last blended one, or alpha below 1/255) takes
       // alpha = 0, which leaves T and the behind sums exactly unchanged and
@@ -306,31 +289,31 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
 #pragma unroll
       for (int k = 0; k < kPPL; ++k) {
         float dx, dy, tq;
-        const float e = pair_exponent(A, B, fx[k], fy[k], dx, dy, tq);
-        const bool hit = pos < walked[k] && e >= B.w;
+        const float e = pair_exponent(A, B, p.fx[k], p.fy[k], dx, dy, tq);
+        const bool hit = pos < p.walked[k] && e >= B.w;
         any = any || hit;
         const float g = __builtin_amdgcn_exp2f(e);
         const float raw = B.y * g;
         const float alpha = hit ? fminf(kAlphaMax, raw) : 0.f;
         const float oma = 1.f - alpha;
-        const float Tj = T[k] * __builtin_amdgcn_rcpf(oma);
+        const float Tj = p.T[k] * __builtin_amdgcn_rcpf(oma);
         const float wgt = alpha * Tj;
-        float dsum = gc0[k] * (Cc.x - Bc0[k]) + gc1[k] * (Cc.y - Bc1[k]) + gc2[k] * (Cc.z - Bc2[k]) +
-                     gd[k] * (B.z - Bd[k]);
-        Bc0[k] = __builtin_fmaf(alpha, Cc.x, oma * Bc0[k]);
-        Bc1[k] = __builtin_fmaf(alpha, Cc.y, oma * Bc1[k]);
-        Bc2[k] = __builtin_fmaf(alpha, Cc.z, oma * Bc2[k]);
-        Bd[k] = __builtin_fmaf(alpha, B.z, oma * Bd[k]);
+        float dsum = p.gc0[k] * (Cc.x - p.Bc0[k]) + p.gc1[k] * (Cc.y - p.Bc1[k]) + p.gc2[k] * (Cc.z - p.Bc2[k]) +
+                     p.gd[k] * (B.z - p.Bd[k]);
+        p.Bc0[k] = __builtin_fmaf(alpha, Cc.x, oma * p.Bc0[k]);
+        p.Bc1[k] = __builtin_fmaf(alpha, Cc.y, oma * p.Bc1[k]);
+        p.Bc2[k] = __builtin_fmaf(alpha, Cc.z, oma * p.Bc2[k]);
+        p.Bd[k] = __builtin_fmaf(alpha, B.z, oma * p.Bd[k]);
         float dz = 0.f;
         if (!kTrack) {
-          dz = B.z - dobs[k];
+          dz = B.z - p.dobs[k];
           const float u = dz * dz;
-          dsum += go[k] * (1.f - Bo[k]) + gu[k] * (u - Bu[k]);
-          Bo[k] = __builtin_fmaf(alpha, 1.f, oma * Bo[k]);
-          Bu[k] = __builtin_fmaf(alpha, u, oma * Bu[k]);
+          dsum += p.go[k] * (1.f - p.Bo[k]) + p.gu[k] * (u - p.Bu[k]);
+          p.Bo[k] = __builtin_fmaf(alpha, 1.f, oma * p.Bo[k]);
+          p.Bu[k] = __builtin_fmaf(alpha, u, oma * p.Bu[k]);
         }
         const float dalpha = Tj * dsum;
-        T[k] = Tj;
+        p.T[k] = Tj;
         const bool live = hit && !(raw > kAlphaMax);   // a capped alpha has no gradient
         const float dpower = live ? dalpha * raw : 0.f;   // alpha = opacity * exp(power)
         // power = -(a dx^2 + 2 b dx dy + c dy^2) / 2 = ln2 (qa t^2 + qc dy^2)
@@ -345,17 +328,17 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
         sxx = __builtin_fmaf(pdx, dx, sxx);
         sxy = __builtin_fmaf(pdx, dy, sxy);
         syy = __builtin_fmaf(pdy, dy, syy);
-        gdd += wgt * gd[k];
-        if (!kTrack) gdd += 2.f * wgt * dz * gu[k] + ((hit && pos == med[k]) ? gm[k] : 0.f);
+        gdd += wgt * p.gd[k];
+        if (!kTrack) gdd += 2.f * wgt * dz * p.gu[k] + ((hit && pos == p.med[k]) ? p.gm[k] : 0.f);
         if (kParams) {
           gop += live ? dalpha * g : 0.f;
-          gr += wgt * gc0[k];
-          gg += wgt * gc1[k];
-          gbl += wgt * gc2[k];
+          gr += wgt * p.gc0[k];
+          gg += wgt * p.gc1[k];
+          gbl += wgt * p.gc2[k];
         }
       }
       if (__ballot(any)) {
-        const uint32_t m = sM[j];
+        const uint32_t m = s.M[j];
         float* dst = b.rec_grad + (int64_t)kGradStride * m;
         // values 0-4 (u1, u2, sxx, sxy, syy) become the gradients of mu x,
         // mu y and the conic (a, b, c); the rest pass through.
@@ -388,6 +371,110 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
   }
 }
 
+template <int kPPL, bool kTrack, bool kNu>
+__global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(RasterBufs b) {
+  __shared__ Stage s;
+  const int gtile = blockIdx.x;
+  const int v = view_of_tile(b.views, gtile);
+  const ViewIO io = b.views.io[v];
+  FwdPix<kPPL> f;
+  forward_tile<kPPL, kTrack, kNu>(b, s, gtile, io, tile_origin(io.info, gtile), b.ranges[gtile], f);
+  float g[kPPL][4];
+  forward_outputs<kPPL, kTrack, kNu>(b, v, io, f, g, true);
+}
+
+template <int kPPL, bool kParams, bool kTrack>
+__global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(RasterBufs b) {
+  constexpr int L = kTilePixels / kPPL;
+  __shared__ Stage s;
+  __shared__ uint32_t s_max;
+  const int gtile = blockIdx.x;
+  const int v = view_of_tile(b.views, gtile);
+  const ViewIO io = b.views.io[v];
+  const ViewInfo& cam = io.info;
+  const int64_t hw = (int64_t)cam.width * cam.height;
+  BwdPix<kPPL> p;
+  uint32_t lane_max = 0;
+#pragma unroll
+  for (int k = 0; k < kPPL; ++k) {
+    const PixelCoord pc = pixel_of(cam, gtile, k * L + threadIdx.x);
+    const int64_t pix = (int64_t)pc.py * cam.width + pc.px;
+    p.fx[k] = (float)(pc.px - pc.ox);
+    p.fy[k] = (float)(pc.py - pc.oy);
+    p.T[k] = 1.f;
+    p.walked[k] = 0;
+    p.med[k] = -1;
+    p.gc0[k] = p.gc1[k] = p.gc2[k] = p.gd[k] = p.go[k] = p.gm[k] = p.gu[k] = p.dobs[k] = 0.f;
+    p.Bc0[k] = p.Bc1[k] = p.Bc2[k] = p.Bd[k] = p.Bo[k] = p.Bu[k] = 0.f;
+    if (pc.inside) {
+      const uint4 ps = b.pixel_state[cam.pixel_base + pix];
+      p.T[k] = __uint_as_float(ps.x);
+      p.walked[k] = (int)ps.y;
+      p.med[k] = (int)ps.z;
+      if (kTrack) {
+        const float4 g4 = b.pixel_grad[cam.pixel_base + pix];
+        p.gc0[k] = g4.x;
+        p.gc1[k] = g4.y;
+        p.gc2[k] = g4.z;
+        p.gd[k] = g4.w;
+      } else {
+        if (io.g_color) {
+          p.gc0[k] = io.g_color[pix];
+          p.gc1[k] = io.g_color[hw + pix];
+          p.gc2[k] = io.g_color[2 * hw + pix];
+        }
+        if (io.g_depth) p.gd[k] = io.g_depth[pix];
+        if (io.g_opacity) p.go[k] = io.g_opacity[pix];
+        if (io.g_median) p.gm[k] = io.g_median[pix];
+        if (io.g_uncertainty) p.gu[k] = io.g_uncertainty[pix];
+        if (io.depth_obs) p.dobs[k] = io.depth_obs[pix];
+      }
+      lane_max = max(lane_max, (uint32_t)p.walked[k]);
+    }
+  }
+  const int nmax = block_max(lane_max, &s_max);
+  backward_tile<kPPL, kParams, kTrack>(b, s, b.ranges[gtile], tile_origin(cam, gtile), nmax, 0, p);
+}
+
+// Tracking iteration of one tile: forward, tracking-loss gradients in
+// registers, pose backward.
+template <int kPPL>
+__global__ __launch_bounds__(kTilePixels / kPPL) void raster_track_kernel(RasterBufs b) {
+  __shared__ Stage s;
+  __shared__ uint32_t s_max;
+  const int gtile = blockIdx.x;
+  const int v = view_of_tile(b.views, gtile);
+  const ViewIO io = b.views.io[v];
+  const float2 org = tile_origin(io.info, gtile);
+  const uint2 range = b.ranges[gtile];
+  BwdPix<kPPL> p;
+  uint32_t lane_max = 0;
+  {
+    FwdPix<kPPL> f;
+    forward_tile<kPPL, true, false>(b, s, gtile, io, org, range, f);
+    float g[kPPL][4];
+    forward_outputs<kPPL, true, false>(b, v, io, f, g, false);
+#pragma unroll
+    for (int k = 0; k < kPPL; ++k) {
+      p.fx[k] = f.fx[k];
+      p.fy[k] = f.fy[k];
+      p.T[k] = f.T[k];
+      p.walked[k] = f.inside[k] ? (int)f.last[k] : 0;
+      p.med[k] = -1;
+      p.gc0[k] = g[k][0];
+      p.gc1[k] = g[k][1];
+      p.gc2[k] = g[k][2];
+      p.gd[k] = g[k][3];
+      p.go[k] = p.gm[k] = p.gu[k] = p.dobs[k] = 0.f;
+      p.Bc0[k] = p.Bc1[k] = p.Bc2[k] = p.Bd[k] = p.Bo[k] = p.Bu[k] = 0.f;
+      lane_max = max(lane_max, (uint32_t)p.walked[k]);
+    }
+  }
+  const int nmax = block_max(lane_max, &s_max);
+  const int len = (int)(range.y - range.x);
+  backward_tile<kPPL, false, true>(b, s, range, org, nmax, len <= kBatch ? len : 0, p);
+}
+
 template <int kPPL>
 void launch_fwd(const RasterBufs& b, bool track, hipStream_t s) {
   const dim3 grid(b.total_tiles), block(kTilePixels / kPPL);
@@ -404,6 +491,11 @@ void launch_bwd(const RasterBufs& b, bool params, bool track, hipStream_t s) {
   else hipLaunchKernelGGL((raster_backward_kernel<kPPL, false, false>), grid, block, 0, s, b);
 }
 
+template <int kPPL>
+void launch_track(const RasterBufs& b, hipStream_t s) {
+  hipLaunchKernelGGL((raster_track_kernel<kPPL>), dim3(b.total_tiles), dim3(kTilePixels / kPPL), 0, s, b);
+}
+
 }  // namespace
 
 void launch_raster_forward(const RasterBufs& b, bool track, int ppl, hipStream_t s) {
@@ -418,6 +510,13 @@ void launch_raster_backward(const RasterBufs& b, bool param_grads, bool track, i
   if (ppl == 4) launch_bwd<4>(b, param_grads, track, s);
   else if (ppl == 2) launch_bwd<2>(b, param_grads, track, s);
   else launch_bwd<1>(b, param_grads, track, s);
+}
+
+void launch_raster_track(const RasterBufs& b, int ppl, hipStream_t s) {
+  if (b.total_tiles <= 0) return;
+  if (ppl == 4) launch_track<4>(b, s);
+  else if (ppl == 2) launch_track<2>(b, s);
+  else launch_track<1>(b, s);
 }
 
 }  // namespace cgsr
