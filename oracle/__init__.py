@@ -28,7 +28,7 @@ _lp = C.POINTER(C.c_int64)
 
 class _Gaussians(C.Structure):
     _fields_ = [("n", C.c_int64), ("means", _dp), ("log_scales", _dp), ("quats", _dp),
-                ("opacity_logits", _dp), ("rgb", _dp)]
+                ("opacity_logits", _dp), ("rgb", _dp), ("sh", _dp), ("sh_degree", C.c_int32)]
 
 
 class _Camera(C.Structure):
@@ -59,7 +59,7 @@ class _ImageGrads(C.Structure):
 
 class _Grads(C.Structure):
     _fields_ = [("means", _dp), ("log_scales", _dp), ("quats", _dp), ("opacity_logits", _dp),
-                ("rgb", _dp), ("pose", _dp), ("mu", _dp), ("conic", _dp), ("opacity", _dp),
+                ("rgb", _dp), ("pose", _dp), ("sh", _dp), ("mu", _dp), ("conic", _dp), ("opacity", _dp),
                 ("depth", _dp)]
 
 
@@ -79,6 +79,8 @@ def lib():
                                        C.POINTER(_ImageGrads), C.c_int64, _ip, _lp, _ip, C.c_double, _dp]
         _lib.orc_gaussian_uncertainty.argtypes = [C.POINTER(_Gaussians), C.POINTER(_Camera), C.POINTER(_Pose),
                                                   _dp, C.c_int, _dp, _lp, _ip, _dp]
+        _lib.orc_sh_basis.argtypes = [C.c_int32, _dp, _dp, _dp]
+        _lib.orc_sh_basis.restype = C.c_int
         _lib.orc_se3_exp.argtypes = [_dp, _dp, _dp]
         _lib.orc_se3_exp.restype = None
         _lib.orc_num_threads.restype = C.c_int
@@ -98,12 +100,24 @@ def _ptr(a, t=_dp):
 
 
 class _Scene:
-    """Keeps the double copies alive while C holds their pointers."""
+    """Keeps the double copies alive while C holds their pointers.  A scene
+    with an ``sh`` array [n, (degree + 1)^2, 3] takes its colour from it (the
+    degree follows from its shape) and may omit ``rgb``."""
 
     def __init__(self, scene):
-        self.arrays = [_f64(scene[k]) for k in ("means", "log_scales", "quats", "opacity_logits", "rgb")]
+        sh = scene.get("sh")
+        self.arrays = [_f64(scene[k]) for k in ("means", "log_scales", "quats", "opacity_logits")]
+        self.arrays.append(None if scene.get("rgb") is None else _f64(scene["rgb"]))
         n = self.arrays[0].shape[0]
-        self.c = _Gaussians(n, *[_ptr(a) for a in self.arrays])
+        self.degree = 0
+        if sh is not None:
+            sh = _f64(sh)
+            K = sh.shape[1]
+            self.degree = int(round(np.sqrt(K))) - 1
+            if sh.shape != (n, (self.degree + 1) ** 2, 3):
+                raise ValueError("sh must be [n, (degree + 1)^2, 3]")
+        self.sh = sh
+        self.c = _Gaussians(n, *[_ptr(a) for a in self.arrays], _ptr(sh), self.degree)
         self.n = n
 
 
@@ -194,17 +208,18 @@ def backward(scene, cam, pose, depth_obs, dimg: dict, *, candidates: int = 1) ->
     d = None if depth_obs is None else _f64(depth_obs)
     out = dict(means=np.zeros((n, 3)), log_scales=np.zeros((n, 3)), quats=np.zeros((n, 4)),
                opacity_logits=np.zeros(n), rgb=np.zeros((n, 3)), pose=np.zeros(6),
+               sh=None if s.sh is None else np.zeros(s.sh.shape),
                proj_mu=np.zeros((n, 2)), proj_conic=np.zeros((n, 3)), proj_opacity=np.zeros(n),
                proj_depth=np.zeros(n))
     gr = _Grads(*[_ptr(out[k]) for k in ("means", "log_scales", "quats", "opacity_logits", "rgb",
-                                          "pose", "proj_mu", "proj_conic", "proj_opacity",
+                                          "pose", "sh", "proj_mu", "proj_conic", "proj_opacity",
                                           "proj_depth")])
     _check(lib().orc_backward(C.byref(s.c), C.byref(_cam(cam)), C.byref(_pose(pose)), _ptr(d),
                               int(candidates), C.byref(ig), C.byref(gr)), "backward")
     return out
 
 
-PARAM_KINDS = {"means": 0, "log_scales": 1, "quats": 2, "opacity_logits": 3, "rgb": 4, "pose": 5}
+PARAM_KINDS = {"means": 0, "log_scales": 1, "quats": 2, "opacity_logits": 3, "rgb": 4, "pose": 5, "sh": 6}
 
 
 def fd_linear(scene, cam, pose, depth_obs, dimg: dict, coords, rel_step: float = 1e-6) -> np.ndarray:
@@ -212,7 +227,7 @@ def fd_linear(scene, cam, pose, depth_obs, dimg: dict, coords, rel_step: float =
 
     ``coords`` is a list of ``(kind, index, component)`` with kind one of
     ``PARAM_KINDS``; for ``"pose"`` the component is the xi coordinate
-    (rho then phi) and the index is ignored."""
+    (rho then phi) and the index is ignored; for ``"sh"`` it is 3 k + c."""
     s = _Scene(scene)
     keep, ig = _image_grads(dimg)
     d = None if depth_obs is None else _f64(depth_obs)
@@ -273,6 +288,17 @@ def prune_uncertain(opacity_logits, nu, tau=NU_TAU, level=NU_LOW_OPACITY):
     cap = np.log(level / (1.0 - level))
     o[mask] = np.minimum(o[mask], cap)
     return o, mask
+
+
+def sh_basis(degree: int, d):
+    """Real spherical harmonics of the colour reading (orc_sh_basis) at unit
+    direction d: returns (Y [K], dY [K, 3])."""
+    K = (int(degree) + 1) ** 2
+    Y, dY = np.zeros(K), np.zeros((K, 3))
+    dd = _f64(np.asarray(d).reshape(3))
+    if lib().orc_sh_basis(int(degree), _ptr(dd), _ptr(Y), _ptr(dY)) != K:
+        raise ValueError("degree must be 0 .. 3")
+    return Y, dY
 
 
 def se3_exp(xi):

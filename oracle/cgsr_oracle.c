@@ -38,6 +38,9 @@ typedef struct {
     double depth;      /* camera z                               */
     double opacity;    /* sigmoid of the logit                   */
     double color[3];
+    double dir[3];     /* unit viewing direction (SH colour)     */
+    double vlen;       /* distance from the camera centre        */
+    int col_clamped[3]; /* SH colour clamped at zero, per channel */
     int rect[4];       /* u0, u1, v0, v1 inclusive               */
     double edges[4];   /* mu_x - ext_x, mu_x + ext_x, mu_y - ext_y, mu_y + ext_y */
 } gproj;
@@ -73,12 +76,101 @@ static void quat_to_rot(const double *q, double *R)
     R[8] = 1.0 - 2.0 * (x * x + y * y);
 }
 
+/* ------------------------------------------------------------------------ */
+/* View-dependent colour (Sec. 3.1): real spherical harmonics               */
+/* ------------------------------------------------------------------------ */
+
+static double factorial(int k)
+{
+    double f = 1.0;
+    for (int i = 2; i <= k; ++i) f *= i;
+    return f;
+}
+
+/* Normalisation of the real harmonic (l, m):
+ * sqrt((2l + 1) / (4 pi) (l - |m|)! / (l + |m|)!), times sqrt 2 for m != 0. */
+static double sh_norm(int l, int m)
+{
+    const int a = m < 0 ? -m : m;
+    const double pi = acos(-1.0);
+    const double n = sqrt((2.0 * l + 1.0) / (4.0 * pi) * factorial(l - a) / factorial(l + a));
+    return m == 0 ? n : sqrt(2.0) * n;
+}
+
 /*
- * Project Gaussian i (Eq. 1-2).  frozen_clamp, when given, replays the
- * tangent-clamp decision recorded at another parameter point.
+ * Y_l^m = N_lm P_l^|m|(z) times cos(|m| phi) (m > 0) or sin(|m| phi) (m < 0),
+ * with P_l^a the associated Legendre function including the Condon-Shortley
+ * phase (-1)^a.  Writing P_l^a(z) = Q_la(z) sin^a(theta), the factor
+ * sin^a cos(a phi) = Re (x + i y)^a and sin^a sin(a phi) = Im (x + i y)^a,
+ * so each harmonic is the polynomial Q_la(z) T(x, y):
+ *   P_1 = z:               Q_10 = z,               Q_11 = -1
+ *   P_2 = (3z^2 - 1)/2:    Q_20 = (3z^2 - 1)/2,    Q_21 = -3z,  Q_22 = 3
+ *   P_3 = (5z^3 - 3z)/2:   Q_30 = (5z^3 - 3z)/2,   Q_31 = -3/2 (5z^2 - 1),
+ *                          Q_32 = 15z,             Q_33 = -15
+ * (the a-th derivative of P_l times (-1)^a).
+ */
+static void sh_q(int l, int a, double z, double *q, double *dq)
+{
+    switch (10 * l + a) {
+    case 0:  *q = 1.0;                          *dq = 0.0; break;
+    case 10: *q = z;                            *dq = 1.0; break;
+    case 11: *q = -1.0;                         *dq = 0.0; break;
+    case 20: *q = 0.5 * (3.0 * z * z - 1.0);    *dq = 3.0 * z; break;
+    case 21: *q = -3.0 * z;                     *dq = -3.0; break;
+    case 22: *q = 3.0;                          *dq = 0.0; break;
+    case 30: *q = 0.5 * (5.0 * z * z * z - 3.0 * z); *dq = 0.5 * (15.0 * z * z - 3.0); break;
+    case 31: *q = -1.5 * (5.0 * z * z - 1.0);   *dq = -15.0 * z; break;
+    case 32: *q = 15.0 * z;                     *dq = 15.0; break;
+    default: *q = -15.0;                        *dq = 0.0; break;   /* l = 3, a = 3 */
+    }
+}
+
+/* Re (m >= 0) or Im (m < 0) of (x + i y)^|m| and its gradient (x, y). */
+static void sh_t(int m, double x, double y, double *t, double g[2])
+{
+    const int a = m < 0 ? -m : m;
+    double re = 1.0, im = 0.0, dre[2] = {0.0, 0.0}, dim[2] = {0.0, 0.0};
+    for (int k = 0; k < a; ++k) {   /* (re + i im)(x + i y), product rule */
+        const double nre = re * x - im * y, nim = re * y + im * x;
+        const double ndre[2] = {dre[0] * x + re - dim[0] * y, dre[1] * x - dim[1] * y - im};
+        const double ndim[2] = {dre[0] * y + dim[0] * x + im, dre[1] * y + re + dim[1] * x};
+        re = nre; im = nim;
+        dre[0] = ndre[0]; dre[1] = ndre[1];
+        dim[0] = ndim[0]; dim[1] = ndim[1];
+    }
+    if (m >= 0) { *t = re; g[0] = dre[0]; g[1] = dre[1]; }
+    else        { *t = im; g[0] = dim[0]; g[1] = dim[1]; }
+}
+
+int orc_sh_basis(int32_t degree, const double d[3], double *Y, double *dY)
+{
+    if (degree < 0 || degree > ORC_SH_MAX_DEGREE) return -1;
+    int k = 0;
+    for (int l = 0; l <= degree; ++l)
+        for (int m = -l; m <= l; ++m, ++k) {
+            double q, dq, t, gt[2];
+            sh_q(l, m < 0 ? -m : m, d[2], &q, &dq);
+            sh_t(m, d[0], d[1], &t, gt);
+            const double n = sh_norm(l, m);
+            Y[k] = n * q * t;
+            if (dY) {
+                dY[3 * k + 0] = n * q * gt[0];
+                dY[3 * k + 1] = n * q * gt[1];
+                dY[3 * k + 2] = n * dq * t;
+            }
+        }
+    return k;
+}
+
+static int sh_count(const orc_gaussians *g) { return (g->sh_degree + 1) * (g->sh_degree + 1); }
+
+/*
+ * Project Gaussian i (Eq. 1-2).  frozen, when given, replays the tangent-clamp
+ * decisions (x, y) and the colour clamps (r, g, b) recorded at another
+ * parameter point.
  */
 static void project_one(const orc_gaussians *g, int64_t i, const orc_camera *cam,
-                        const orc_pose *P, const int *frozen_clamp, gproj *o)
+                        const orc_pose *P, const int *frozen, gproj *o)
 {
     memset(o, 0, sizeof(*o));
     o->rect[0] = o->rect[1] = o->rect[2] = o->rect[3] = -1;
@@ -98,7 +190,25 @@ static void project_one(const orc_gaussians *g, int64_t i, const orc_camera *cam
             o->Sigma[3 * r + c] = acc;
         }
     o->opacity = 1.0 / (1.0 + exp(-g->opacity_logits[i]));
-    for (int k = 0; k < 3; ++k) o->color[k] = g->rgb[3 * i + k];
+    if (g->sh) {
+        /* Colour seen along d = (X - C) / |X - C| from the camera centre
+         * C = -R^T t, from the SH coefficients (reading in the header). */
+        double v[3];
+        for (int k = 0; k < 3; ++k)
+            v[k] = X[k] + (P->R[k] * P->t[0] + P->R[3 + k] * P->t[1] + P->R[6 + k] * P->t[2]);
+        o->vlen = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        for (int k = 0; k < 3; ++k) o->dir[k] = o->vlen > 0.0 ? v[k] / o->vlen : (k == 2 ? 1.0 : 0.0);
+        double Y[ORC_SH_MAX_COEFFS];
+        const int K = orc_sh_basis(g->sh_degree, o->dir, Y, NULL);
+        for (int c = 0; c < 3; ++c) {
+            double sum = 0.5;
+            for (int k = 0; k < K; ++k) sum += g->sh[(K * i + k) * 3 + c] * Y[k];
+            o->col_clamped[c] = frozen ? frozen[2 + c] : sum < 0.0;
+            o->color[c] = o->col_clamped[c] ? 0.0 : sum;
+        }
+    } else {
+        for (int k = 0; k < 3; ++k) o->color[k] = g->rgb[3 * i + k];
+    }
 
     /* World to camera. */
     for (int r = 0; r < 3; ++r)
@@ -117,9 +227,9 @@ static void project_one(const orc_gaussians *g, int64_t i, const orc_camera *cam
     const double limx = ORC_TAN_CLAMP * 0.5 * cam->width / cam->fx;
     const double limy = ORC_TAN_CLAMP * 0.5 * cam->height / cam->fy;
     double tx = x / z, ty = y / z;
-    if (frozen_clamp) {
-        o->clamp[0] = frozen_clamp[0];
-        o->clamp[1] = frozen_clamp[1];
+    if (frozen) {
+        o->clamp[0] = frozen[0];
+        o->clamp[1] = frozen[1];
     } else {
         o->clamp[0] = tx > limx ? 1 : (tx < -limx ? -1 : 0);
         o->clamp[1] = ty > limy ? 1 : (ty < -limy ? -1 : 0);
@@ -177,20 +287,22 @@ static void project_one(const orc_gaussians *g, int64_t i, const orc_camera *cam
     o->visible = 1;
 }
 
+/* frozen: NULL or [n][5] decisions as in project_one. */
 static gproj *project_all(const orc_gaussians *g, const orc_camera *cam, const orc_pose *P,
-                          const int *frozen_clamp)
+                          const int *frozen)
 {
     gproj *pr = (gproj *)malloc(sizeof(gproj) * (size_t)(g->n > 0 ? g->n : 1));
     if (!pr) return NULL;
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < g->n; ++i)
-        project_one(g, i, cam, P, frozen_clamp ? frozen_clamp + 2 * i : NULL, &pr[i]);
+        project_one(g, i, cam, P, frozen ? frozen + 5 * i : NULL, &pr[i]);
     return pr;
 }
 
 int orc_project(const orc_gaussians *g, const orc_camera *cam, const orc_pose *pose,
                 orc_projection *out)
 {
+    if (g->sh && (g->sh_degree < 0 || g->sh_degree > ORC_SH_MAX_DEGREE)) return -1;
     gproj *pr = project_all(g, cam, pose, NULL);
     if (!pr) return -2;
     for (int64_t i = 0; i < g->n; ++i) {
@@ -417,6 +529,7 @@ static int render_setup(const orc_gaussians *g, const orc_camera *cam, const orc
 {
     memset(rc, 0, sizeof(*rc));
     rc->mode = mode;
+    if (g->sh && (g->sh_degree < 0 || g->sh_degree > ORC_SH_MAX_DEGREE)) return -1;
     rc->pr = project_all(g, cam, P, NULL);
     if (!rc->pr) return -2;
     rc->ord = depth_order(rc->pr, g->n, &rc->n_vis);
@@ -677,9 +790,30 @@ static void gaussian_backward(const orc_gaussians *g, int64_t i, const orc_camer
     }
     if (out->opacity_logits)
         out->opacity_logits[i] += d->opacity * o->opacity * (1.0 - o->opacity);
-    if (out->rgb)
+    if (g->sh) {
+        /* colour_c = max(0, sum_k sh_kc Y_k(d) + 1/2), d = v / |v|, v = X - C. */
+        double Y[ORC_SH_MAX_COEFFS], dY[3 * ORC_SH_MAX_COEFFS], gdir[3] = {0.0, 0.0, 0.0};
+        const int K = orc_sh_basis(g->sh_degree, o->dir, Y, dY);
+        for (int c = 0; c < 3; ++c) {
+            const double dc = o->col_clamped[c] ? 0.0 : d->color[c];
+            for (int k = 0; k < K; ++k) {
+                if (out->sh) out->sh[(K * i + k) * 3 + c] += dc * Y[k];
+                for (int j = 0; j < 3; ++j) gdir[j] += dc * g->sh[(K * i + k) * 3 + c] * dY[3 * k + j];
+            }
+        }
+        /* d = v / |v|: dL/dv = (I - d d^T) dL/dd / |v|. */
+        const double dot = gdir[0] * o->dir[0] + gdir[1] * o->dir[1] + gdir[2] * o->dir[2];
+        double dv[3];
+        for (int j = 0; j < 3; ++j) dv[j] = (gdir[j] - o->dir[j] * dot) / o->vlen;
+        if (out->means)
+            for (int j = 0; j < 3; ++j) out->means[3 * i + j] += dv[j];
+        /* The camera centre C = -R^T t moves to C - R^T rho under exp(xi^) T
+         * (rotation alone leaves it in place), so dL/drho += -R dL/dC = R dL/dv. */
+        for (int r = 0; r < 3; ++r)
+            pose_acc[r] += P->R[3 * r] * dv[0] + P->R[3 * r + 1] * dv[1] + P->R[3 * r + 2] * dv[2];
+    } else if (out->rgb) {
         for (int k = 0; k < 3; ++k) out->rgb[3 * i + k] += d->color[k];
-    (void)g;
+    }
     /* Pose: p' = exp(xi^) p gives dp'/drho = I, dp'/dphi = -[p]x; the camera
      * covariance Sc' = exp(phi^) Sc exp(phi^)^T contributes 2 vee-parts of
      * the skew part of M = Sc dSc. */
@@ -786,7 +920,7 @@ typedef struct {
     int64_t *start;      /* [npx + 1] */
     blend_entry *e;      /* blended Gaussians of every pixel, front to back */
     int64_t *median_pos; /* [npx] position of the median within the pixel's run, -1 */
-    int *clamp;          /* [n][2] tangent clamps */
+    int *clamp;          /* [n][5] tangent clamps (x, y), colour clamps (r, g, b) */
 } frozen_trace;
 
 /* Linear probe over the frozen branch: re-project with the recorded clamps,
@@ -839,9 +973,13 @@ int orc_fd_linear(const orc_gaussians *g, const orc_camera *cam, const orc_pose 
     frozen_trace ft;
     ft.start = (int64_t *)calloc((size_t)npx + 1, sizeof(int64_t));
     ft.median_pos = (int64_t *)malloc(sizeof(int64_t) * (size_t)(npx > 0 ? npx : 1));
-    ft.clamp = (int *)malloc(sizeof(int) * (size_t)(2 * (n > 0 ? n : 1)));
+    ft.clamp = (int *)malloc(sizeof(int) * (size_t)(5 * (n > 0 ? n : 1)));
     pixel_out *pos = (pixel_out *)malloc(sizeof(pixel_out) * (size_t)(npx > 0 ? npx : 1));
-    for (int64_t i = 0; i < n; ++i) { ft.clamp[2 * i] = rc.pr[i].clamp[0]; ft.clamp[2 * i + 1] = rc.pr[i].clamp[1]; }
+    for (int64_t i = 0; i < n; ++i) {
+        ft.clamp[5 * i] = rc.pr[i].clamp[0];
+        ft.clamp[5 * i + 1] = rc.pr[i].clamp[1];
+        for (int c = 0; c < 3; ++c) ft.clamp[5 * i + 2 + c] = rc.pr[i].col_clamped[c];
+    }
     for (int64_t pix = 0; pix < npx; ++pix) {
         const int64_t *cand;
         int64_t nc;
@@ -866,14 +1004,15 @@ int orc_fd_linear(const orc_gaussians *g, const orc_camera *cam, const orc_pose 
     render_teardown(&rc);
 
     /* Private copies of the parameters to perturb. */
-    double *buf[5];
-    const double *src[5] = {g->means, g->log_scales, g->quats, g->opacity_logits, g->rgb};
-    const int width[5] = {3, 3, 4, 1, 3};
-    for (int k = 0; k < 5; ++k) {
-        buf[k] = (double *)malloc(sizeof(double) * (size_t)(width[k] * (n > 0 ? n : 1)));
-        memcpy(buf[k], src[k], sizeof(double) * (size_t)(width[k] * n));
+    double *buf[7];
+    const double *src[7] = {g->means, g->log_scales, g->quats, g->opacity_logits, g->rgb, NULL, g->sh};
+    const int width[7] = {3, 3, 4, 1, 3, 0, g->sh ? 3 * sh_count(g) : 0};
+    for (int k = 0; k < 7; ++k) {
+        buf[k] = (double *)malloc(sizeof(double) * (size_t)(width[k] * (n > 0 ? n : 1) + 1));
+        if (src[k]) memcpy(buf[k], src[k], sizeof(double) * (size_t)(width[k] * n));
     }
-    orc_gaussians gp = {n, buf[0], buf[1], buf[2], buf[3], buf[4]};
+    orc_gaussians gp = {n, buf[0], buf[1], buf[2], buf[3], g->rgb ? buf[4] : NULL, g->sh ? buf[6] : NULL,
+                        g->sh_degree};
     for (int64_t c = 0; c < n_coords; ++c) {
         double vals[2];
         double h = rel_step;
@@ -899,7 +1038,7 @@ int orc_fd_linear(const orc_gaussians *g, const orc_camera *cam, const orc_pose 
         }
         out[c] = (vals[0] - vals[1]) / (2.0 * h);
     }
-    for (int k = 0; k < 5; ++k) free(buf[k]);
+    for (int k = 0; k < 7; ++k) free(buf[k]);
     free(ft.start);
     free(ft.e);
     free(ft.median_pos);

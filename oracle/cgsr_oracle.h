@@ -12,6 +12,7 @@
  *   Eq. 6   alpha-blended depth, Eq. 7-8 median depth, Eq. 9 opacity
  *   Eq. 10  uncertainty map  U = sum_i alpha_i T_i (d_i - D)^2
  *   Eq. 13  per-Gaussian depth uncertainty from its dominated pixels
+ *   Sec. 3.1 view-dependent colour from spherical-harmonic coefficients
  * plus the analytic gradient of all of them with respect to every Gaussian
  * parameter and to the left se(3) perturbation of the world->camera pose
  * (Sec. 3.4 names these pose derivatives; their derivation is restated from
@@ -20,7 +21,9 @@
  *
  * Layouts: every array is plain row-major double.  Gaussian i owns
  * means[3i..3i+2], log_scales[3i..], quats[4i..] (w,x,y,z), opacity_logits[i],
- * rgb[3i..].  Images are planar: colour [3][H][W], the others [H][W].
+ * rgb[3i..], and optionally sh[(K i + k) 3 + c] (K = (sh_degree + 1)^2
+ * coefficients k per colour channel c).  Images are planar: colour [3][H][W],
+ * the others [H][W].
  * pose = {R[9] row-major, t[3]} maps world to camera (OpenCV axes).
  * cam  = {fx, fy, cx, cy}; pixel (u, v) has its centre at (u, v).
  */
@@ -47,9 +50,23 @@ extern "C" {
 #define ORC_BIN_R2_REL  (1.0 + 1.0 / 128.0)
 #define ORC_BIN_R2_ABS  (1.0 / 256.0)
 
+/* View-dependent colour (Sec. 3.1 gives each Gaussian spherical-harmonic
+ * coefficients; the reading of their convention is that of the splatting
+ * rasterizer the paper builds on): with sh non-NULL, the colour of Gaussian i
+ * seen from camera centre C = -R^T t is, per channel c,
+ *     colour_c = max(0, sum_k sh[i][k][c] Y_k(d) + 1/2),  d = (X_i - C) / |X_i - C|,
+ * where Y_k are the real spherical harmonics of degree l <= sh_degree with
+ * the Condon-Shortley phase, ordered k = l^2 + l + m, m = -l .. l, at the
+ * unit direction d = (x, y, z) (z the polar axis, azimuth atan2(y, x)); rgb
+ * is then unused.  With sh NULL the colour is rgb. */
+#define ORC_SH_MAX_DEGREE 3
+#define ORC_SH_MAX_COEFFS 16
+
 typedef struct {
     int64_t n;
     const double *means, *log_scales, *quats, *opacity_logits, *rgb;
+    const double *sh;      /* NULL or [n][(sh_degree + 1)^2][3] */
+    int32_t sh_degree;     /* 0 .. ORC_SH_MAX_DEGREE */
 } orc_gaussians;
 
 typedef struct {
@@ -107,6 +124,7 @@ typedef struct {
 typedef struct {
     double *means, *log_scales, *quats, *opacity_logits, *rgb;
     double *pose;          /* [6] (rho, phi): left perturbation exp(xi^) T_cw */
+    double *sh;            /* [n][K][3] when the Gaussians carry sh */
     /* gradients with respect to the projected quantities, [n][k] */
     double *mu, *conic, *opacity, *depth;
 } orc_grads;
@@ -133,11 +151,11 @@ int orc_backward(const orc_gaussians *g, const orc_camera *cam, const orc_pose *
 /* Frozen-decision central differences of the linear probe
  *     L = sum over maps and pixels of dimg * map
  * at n_coords coordinates.  Every discontinuous decision (culling, tangent
- * clamp, skip, stop, alpha cap, median choice, blend order) is recorded at the
- * unperturbed point and replayed at the perturbed ones, so the result is the
- * derivative of one smooth branch.  kind: 0 means, 1 log_scales, 2 quats,
- * 3 opacity_logits, 4 rgb, 5 pose; index = Gaussian index (ignored for pose);
- * comp = component.  Step h = rel_step * max(1, |theta|) (pose: rel_step). */
+ * clamp, skip, stop, alpha cap, median choice, blend order, colour clamp at
+ * zero) is recorded at the unperturbed point and replayed at the perturbed
+ * ones, so the result is the derivative of one smooth branch.  kind: 0 means,
+ * 1 log_scales, 2 quats, 3 opacity_logits, 4 rgb, 5 pose, 6 sh (comp =
+ * 3 k + c); index = Gaussian index (ignored for pose); comp = component.  Step h = rel_step * max(1, |theta|) (pose: rel_step). */
 int orc_fd_linear(const orc_gaussians *g, const orc_camera *cam, const orc_pose *pose,
                   const double *depth_obs, const orc_image_grads *dimg,
                   int64_t n_coords, const int32_t *kind, const int64_t *index,
@@ -158,6 +176,13 @@ int orc_fd_linear(const orc_gaussians *g, const orc_camera *cam, const orc_pose 
 int orc_gaussian_uncertainty(const orc_gaussians *g, const orc_camera *cam, const orc_pose *pose,
                              const double *depth_obs, int candidates, double *nu_sum,
                              int64_t *nu_count, int32_t *dominant, double *dominant_margin);
+
+/* The real spherical harmonics Y_k(d), k < (degree + 1)^2, of the colour
+ * reading above at a unit direction d, and their gradients dY[k][3] with
+ * respect to d (of the homogeneous polynomial form; only the part tangent to
+ * the sphere is meaningful).  Returns the number of coefficients, -1 for a
+ * degree outside 0 .. ORC_SH_MAX_DEGREE. */
+int orc_sh_basis(int32_t degree, const double d[3], double *Y, double *dY);
 
 /* SE(3) exponential of xi = (rho, phi): T = [exp(phi^), V(phi) rho]. */
 void orc_se3_exp(const double xi[6], double R[9], double t[3]);

@@ -91,6 +91,21 @@ def uniform_box_scene(seed: int, n: int = 2000, *, xy=(-1.0, 1.0), z=(1.5, 4.0),
     return _pack(np.stack([x, y, zz], 1), ls, q, o, rgb)
 
 
+def sh_coefficients(seed: int, n: int, degree: int, *, dc=(-1.5, 1.5), rest_std: float = 0.3) -> np.ndarray:
+    """View-dependent colour coefficients [n, (degree + 1)^2, 3] float32.
+
+    Draw order (fixed): the degree-0 coefficients ~ U[dc], then the others ~
+    N(0, rest_std), each in [n, K, 3] order.  Inputs only: how they turn into
+    a colour is the library's business."""
+    rng = np.random.default_rng(seed)
+    K = (degree + 1) ** 2
+    out = np.empty((n, K, 3), np.float32)
+    out[:, 0, :] = rng.uniform(dc[0], dc[1], (n, 3))
+    if K > 1:
+        out[:, 1:, :] = rng.normal(0.0, rest_std, (n, K - 1, 3))
+    return out
+
+
 def room_scene(seed: int, n: int, dims=(5.0, 4.0, 3.0), *, jitter: float = 0.01,
                log_scale=(-4.0, 0.4), opacity=(1.0, 1.0)) -> dict:
     """Gaussians on the six walls of an axis-aligned room centred at the origin, z up.
