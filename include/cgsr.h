@@ -19,7 +19,9 @@
  * Conventions shared by every entry point:
  *  - Gaussians are SoA float32: means[n][3], log_scales[n][3] (scale = exp),
  *    quats[n][4] as (w, x, y, z), normalised inside the forward pass,
- *    opacity_logits[n] (opacity = sigmoid), rgb[n][3]  (Sec. 3.1, Eq. 1).
+ *    opacity_logits[n] (opacity = sigmoid), rgb[n][3]  (Sec. 3.1, Eq. 1), or,
+ *    for view-dependent colour, sh[n][K][3] spherical-harmonic coefficients
+ *    (K = (sh_degree + 1)^2, see cgsr_gaussians).
  *  - A pose is float32[12] in device memory: a row-major 3x3 rotation followed
  *    by a translation, mapping world points into the camera frame (x right,
  *    y down, z forward).
@@ -54,10 +56,23 @@ typedef struct {
     float fx, fy, cx, cy;
 } cgsr_camera;
 
-/* Gaussian parameters (device pointers, SoA float32, layouts above). */
+/* Gaussian parameters (device pointers, SoA float32, layouts above).
+ * Colour (Sec. 3.1 gives each Gaussian spherical-harmonic coefficients for a
+ * view-dependent radiance): with sh NULL the colour is rgb.  With sh
+ * non-NULL, sh_degree in 0 .. 3, rgb is unused (may be NULL) and the colour
+ * of Gaussian i in a view whose camera centre is C = -R^T t is, per channel c,
+ *     max(0, sum_k sh[i][k][c] Y_k(d) + 1/2),   d = (X_i - C) / |X_i - C|,
+ * Y_k the real spherical harmonics with the Condon-Shortley phase, ordered
+ * k = l^2 + l + m (l = 0 .. sh_degree, m = -l .. l), d = (x, y, z) with z as
+ * the polar axis -- the convention of the splatting rasterizer the paper
+ * builds on, so its coefficients load unchanged.  The colour then depends on
+ * the pose through C: pose gradients include that term. */
+#define CGSR_MAX_SH_DEGREE 3
 typedef struct {
     int64_t n;
     const float *means, *log_scales, *quats, *opacity_logits, *rgb;
+    const float *sh;       /* NULL or [n][(sh_degree + 1)^2][3] */
+    int32_t sh_degree;
 } cgsr_gaussians;
 
 /* Rendered maps of one view (device pointers; NULL = not written).
@@ -76,9 +91,12 @@ typedef struct {
 } cgsr_image_grads;
 
 /* Gradient outputs for the Gaussian parameters (device, +=).  All NULL (or
- * the struct pointer NULL) selects the pose-only backward used by tracking. */
+ * the struct pointer NULL) selects the pose-only backward used by tracking.
+ * sh receives the coefficient gradients (layout of cgsr_gaussians.sh) when
+ * the rendered Gaussians carry sh; rgb is then not written. */
 typedef struct {
     float *means, *log_scales, *quats, *opacity_logits, *rgb;
+    float *sh;
 } cgsr_gaussian_grads;
 
 /* Library settings; cgsr_default_settings() fills the defaults. */
@@ -307,6 +325,8 @@ cgsr_status cgsr_pose_adam_step(int32_t n_views, float *poses, float *dposes, fl
 typedef struct {
     float lr_means, lr_log_scales, lr_quats, lr_opacity_logits, lr_rgb;
     float beta1, beta2, eps;
+    float lr_sh_rest;      /* spherical-harmonic coefficients of degree >= 1 */
+    int32_t sh_degree;     /* degree of params->sh / grads->sh when they are set */
 } cgsr_gaussian_adam_params;
 
 /*
@@ -315,17 +335,21 @@ typedef struct {
  * pose half is cgsr_pose_adam_step.
  *   n        number of Gaussians.
  *   params   the parameter arrays (device, float, updated in place), in the
- *            layouts of cgsr_gaussians.
+ *            layouts of cgsr_gaussians.  With params->sh set (and grads->sh),
+ *            the colour group is sh, of hp->sh_degree, instead of rgb:
+ *            lr_rgb then applies to its degree-0 coefficients and
+ *            lr_sh_rest to the others.
  *   grads    their gradients (device; read, then zeroed for the next
  *            accumulation by cgsr_backward and cgsr_mapping_objective).
- *   moments  device float[2][14 n]: first then second moments, each the
+ *   moments  device float[2][(11 + W) n]: first then second moments, each the
  *            concatenation of the groups means (3n), log_scales (3n), quats
- *            (4n), opacity_logits (n), rgb (3n); zero-initialise.
+ *            (4n), opacity_logits (n) and colour (W n: W = 3 for rgb,
+ *            3 (sh_degree + 1)^2 for sh); zero-initialise.
  *   step     device uint32 step counter (zero-initialise); the call reads it
  *            for the bias correction and then increments it, on the stream, so
  *            a captured loop keeps counting.
  * Errors: NULL arrays (n > 0), negative learning rates, betas outside [0, 1),
- * eps <= 0.
+ * eps <= 0, sh on one side only, sh_degree outside 0 .. 3.
  */
 cgsr_status cgsr_gaussian_adam_step(int64_t n, const cgsr_gaussian_grads *params, const cgsr_gaussian_grads *grads,
                                     float *moments, uint32_t *step, const cgsr_gaussian_adam_params *hp,

@@ -50,7 +50,8 @@ class cgsr_camera(C.Structure):
 
 class cgsr_gaussians(C.Structure):
     _fields_ = [("n", C.c_int64), ("means", C.c_void_p), ("log_scales", C.c_void_p),
-                ("quats", C.c_void_p), ("opacity_logits", C.c_void_p), ("rgb", C.c_void_p)]
+                ("quats", C.c_void_p), ("opacity_logits", C.c_void_p), ("rgb", C.c_void_p),
+                ("sh", C.c_void_p), ("sh_degree", C.c_int32)]
 
 
 class cgsr_images(C.Structure):
@@ -63,7 +64,7 @@ cgsr_image_grads = cgsr_images  # same layout, const on the C side
 
 class cgsr_gaussian_grads(C.Structure):
     _fields_ = [("means", C.c_void_p), ("log_scales", C.c_void_p), ("quats", C.c_void_p),
-                ("opacity_logits", C.c_void_p), ("rgb", C.c_void_p)]
+                ("opacity_logits", C.c_void_p), ("rgb", C.c_void_p), ("sh", C.c_void_p)]
 
 
 class cgsr_settings(C.Structure):
@@ -84,7 +85,7 @@ class cgsr_mapping_weights(C.Structure):
 class cgsr_gaussian_adam_params(C.Structure):
     _fields_ = [("lr_means", C.c_float), ("lr_log_scales", C.c_float), ("lr_quats", C.c_float),
                 ("lr_opacity_logits", C.c_float), ("lr_rgb", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
-                ("eps", C.c_float)]
+                ("eps", C.c_float), ("lr_sh_rest", C.c_float), ("sh_degree", C.c_int32)]
 
 
 class cgsr_stats(C.Structure):

@@ -247,6 +247,7 @@ RasterBufs raster_bufs(cgsr_state* st, int slot) {
   rb.nu_sum = nullptr;
   rb.nu_count = nullptr;
   rb.nu = false;
+  rb.color_grads = st->g.sh != nullptr;
   rb.views = ViewTable{st->io[slot].dev, st->n_views, (int32_t)st->g.n};
   rb.total_tiles = st->total_tiles;
   return rb;
@@ -377,8 +378,10 @@ cgsr_status check_views(const cgsr_gaussians* g, int32_t n_views, const float* p
     return fail(CGSR_ERR_INVALID_ARG, "render: n_views must be in [1, %d]", CGSR_MAX_VIEWS);
   if (g->n < 0) return fail(CGSR_ERR_INVALID_ARG, "render: negative Gaussian count");
   if (g->n > INT32_MAX) return fail(CGSR_ERR_INVALID_ARG, "render: more than 2^31 Gaussians");
-  if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->rgb))
+  if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !(g->rgb || g->sh)))
     return fail(CGSR_ERR_INVALID_ARG, "render: NULL Gaussian parameter pointer");
+  if (g->sh && (g->sh_degree < 0 || g->sh_degree > CGSR_MAX_SH_DEGREE))
+    return fail(CGSR_ERR_INVALID_ARG, "render: sh_degree must be in [0, %d]", CGSR_MAX_SH_DEGREE);
   if ((int64_t)g->n * n_views >= (1ll << 32))
     return fail(CGSR_ERR_INVALID_ARG, "render: more than 2^32 (view, Gaussian) records");
   if (g->n > 0 && ((uintptr_t)g->quats & 15))
@@ -439,7 +442,8 @@ cgsr_status render_impl(cgsr_state* st, const RenderArgs& a, hipStream_t stream)
   st->have_forward = false;
   st->tracked = false;
   st->n_views = a.n_views;
-  st->g = GaussianPtrs{a.g->means, a.g->log_scales, a.g->quats, a.g->opacity_logits, a.g->rgb, a.g->n};
+  st->g = GaussianPtrs{a.g->means, a.g->log_scales, a.g->quats, a.g->opacity_logits, a.g->rgb, a.g->n,
+                       a.g->sh, a.g->sh ? a.g->sh_degree : 0};
   st->poses = a.poses;
   st->total_pixels = a.pixels;
   st->total_tiles = (int32_t)a.tiles;
@@ -612,7 +616,7 @@ cgsr_status cgsr_backward(cgsr_state* st, const cgsr_image_grads* dimgs, const c
   if (!st->have_forward) return fail(CGSR_ERR_STATE, "cgsr_backward: no forward pass on this state");
   if (st->tracked) return fail(CGSR_ERR_STATE, "cgsr_backward: the last forward was a tracking step");
   const int n_views = st->n_views;
-  const bool params = dG && (dG->means || dG->log_scales || dG->quats || dG->opacity_logits || dG->rgb);
+  const bool params = dG && (dG->means || dG->log_scales || dG->quats || dG->opacity_logits || dG->rgb || dG->sh);
   if (!params && !dposes) return CGSR_OK;
   ViewIO io[CGSR_MAX_VIEWS];
   for (int v = 0; v < n_views; ++v) {
@@ -630,7 +634,7 @@ cgsr_status cgsr_backward(cgsr_state* st, const cgsr_image_grads* dimgs, const c
   s = upload_io(st, 1, io, n_views, stream);
   if (s) return s;
   GradPtrs gp{};
-  if (params) gp = GradPtrs{dG->means, dG->log_scales, dG->quats, dG->opacity_logits, dG->rgb};
+  if (params) gp = GradPtrs{dG->means, dG->log_scales, dG->quats, dG->opacity_logits, dG->rgb, dG->sh};
   return backward_impl(st, 1, params, false, gp, dposes, nullptr, stream);
 }
 
@@ -827,9 +831,18 @@ cgsr_status cgsr_gaussian_adam_step(int64_t n, const cgsr_gaussian_grads* params
     return fail(CGSR_ERR_INVALID_ARG, "cgsr_gaussian_adam_step: NULL argument or negative count");
   if (!(hp->beta1 >= 0.f && hp->beta1 < 1.f) || !(hp->beta2 >= 0.f && hp->beta2 < 1.f) || !(hp->eps > 0.f))
     return fail(CGSR_ERR_INVALID_ARG, "cgsr_gaussian_adam_step: bad Adam parameters");
+  const bool sh = params->sh || grads->sh;
+  if (sh && !(params->sh && grads->sh))
+    return fail(CGSR_ERR_INVALID_ARG, "cgsr_gaussian_adam_step: sh needs both the parameters and their gradients");
+  if (sh && (hp->sh_degree < 0 || hp->sh_degree > CGSR_MAX_SH_DEGREE))
+    return fail(CGSR_ERR_INVALID_ARG, "cgsr_gaussian_adam_step: sh_degree must be 0 .. %d", CGSR_MAX_SH_DEGREE);
+  if (sh && !(hp->lr_sh_rest >= 0.f))
+    return fail(CGSR_ERR_INVALID_ARG, "cgsr_gaussian_adam_step: negative learning rate");
   GaussianAdam a;
-  float* const ps[5] = {params->means, params->log_scales, params->quats, params->opacity_logits, params->rgb};
-  float* const gs[5] = {grads->means, grads->log_scales, grads->quats, grads->opacity_logits, grads->rgb};
+  float* const ps[5] = {params->means, params->log_scales, params->quats, params->opacity_logits,
+                        sh ? params->sh : params->rgb};
+  float* const gs[5] = {grads->means, grads->log_scales, grads->quats, grads->opacity_logits,
+                        sh ? grads->sh : grads->rgb};
   const float lrs[5] = {hp->lr_means, hp->lr_log_scales, hp->lr_quats, hp->lr_opacity_logits, hp->lr_rgb};
   for (int k = 0; k < 5; ++k) {
     if (n > 0 && (!ps[k] || !gs[k]))
@@ -842,6 +855,8 @@ cgsr_status cgsr_gaussian_adam_step(int64_t n, const cgsr_gaussian_grads* params
   a.beta1 = hp->beta1;
   a.beta2 = hp->beta2;
   a.eps = hp->eps;
+  a.colour_width = sh ? 3 * (hp->sh_degree + 1) * (hp->sh_degree + 1) : 3;
+  a.lr_sh_rest = sh ? hp->lr_sh_rest : 0.f;
   launch_gaussian_adam(n, a, moments, step, (hipStream_t)stream);
   HIP_TRY(hipGetLastError());
   return CGSR_OK;

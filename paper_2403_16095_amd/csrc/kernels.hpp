@@ -36,6 +36,8 @@ struct GaussianPtrs {
   const float* opacity_logits;
   const float* rgb;
   int64_t n;
+  const float* sh;     // null, or [n][(sh_degree + 1)^2][3]: view-dependent colour
+  int32_t sh_degree;
 };
 
 struct GradPtrs {
@@ -44,6 +46,7 @@ struct GradPtrs {
   float* quats;
   float* opacity_logits;
   float* rgb;
+  float* sh;
 };
 
 // Projection (one lane per (view, Gaussian)) followed by the tile-count scan.
@@ -97,6 +100,9 @@ struct RasterBufs {
   float* nu_sum;
   uint32_t* nu_count;
   bool nu;
+  // The backward also reduces the colour gradients when the pose gradient
+  // needs them (view-dependent colour) even without parameter gradients.
+  bool color_grads;
 };
 // ppl: pixels per lane, 1, 2 or 4 (256 / ppl lanes per 16x16 tile).
 void launch_raster_forward(const RasterBufs& b, bool track, int ppl, hipStream_t s);
@@ -118,14 +124,18 @@ void launch_objective_view(const ObjectiveView& o, const ObjectiveWeights& w, fl
 // (scratch, n_views words), dlog_scales (+=, may be null), loss[v] (+=).
 void launch_iso(int64_t n, int n_views, const uint32_t* tiles, uint32_t* counts, const float* log_scales, float w_iso,
                 float eps, float* dlog_scales, float* loss, hipStream_t s);
-// Adam over the Gaussian parameter groups (element-wise; moments [2][14 n] in
-// group order), bias-corrected with the device step counter, which a second
-// one-lane launch then increments.  Gradients are zeroed after use.
+// Adam over the Gaussian parameter groups (element-wise; moments
+// [2][(11 + colour_width) n] in group order), bias-corrected with the device
+// step counter, which a second one-lane launch then increments.  Gradients
+// are zeroed after use.  The colour group is rgb (width 3) or the SH
+// coefficients (width 3 K), whose degree >= 1 entries take lr_sh_rest.
 struct GaussianAdam {
-  float* param[5];       // means, log_scales, quats, opacity_logits, rgb
+  float* param[5];       // means, log_scales, quats, opacity_logits, colour
   float* grad[5];
   float lr[5];
   float beta1, beta2, eps;
+  int32_t colour_width;  // 3 (rgb) or 3 (sh_degree + 1)^2
+  float lr_sh_rest;
 };
 void launch_gaussian_adam(int64_t n, const GaussianAdam& a, float* moments, uint32_t* step, hipStream_t s);
 // nu_i = nu_sum_i / nu_count_i (0 without dominated pixels); Gaussians with

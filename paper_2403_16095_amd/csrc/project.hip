@@ -184,6 +184,117 @@ __device__ __forceinline__ uint32_t pair_tile(const WavePairs& wp, uint32_t k, i
   return ((org >> 16) + local / w) * (uint32_t)tiles_x + (org & 0xFFFF) + local % w;
 }
 
+// View-dependent colour (Sec. 3.1): real spherical harmonics with the
+// Condon-Shortley phase, k = l^2 + l + m, at the unit direction (x, y, z).
+// Each constant is the normalisation sqrt((2l + 1) / (4 pi) (l - |m|)! /
+// (l + |m|)!) (times sqrt 2 for m != 0) times the leading coefficient of the
+// harmonic's polynomial.
+constexpr float kSh00 = 0.28209479177387814f;   // sqrt(1 / (4 pi))
+constexpr float kSh1 = 0.4886025119029199f;     // sqrt(3 / (4 pi))
+constexpr float kSh2a = 1.0925484305920792f;    // sqrt(15 / (4 pi))
+constexpr float kSh20 = 0.31539156525252005f;   // sqrt(5 / (16 pi))
+constexpr float kSh22 = 0.5462742152960396f;    // sqrt(15 / (16 pi))
+constexpr float kSh33 = 0.5900435899266435f;    // sqrt(35 / (32 pi))
+constexpr float kSh32 = 2.890611442640554f;     // sqrt(105 / (4 pi))
+constexpr float kSh31 = 0.4570457994644658f;    // sqrt(21 / (32 pi))
+constexpr float kSh30 = 0.3731763325901154f;    // sqrt(7 / (16 pi))
+constexpr float kSh32b = 1.445305721320277f;    // sqrt(105 / (16 pi))
+
+__device__ __forceinline__ void sh_basis(int degree, float x, float y, float z, float (&Y)[16]) {
+  Y[0] = kSh00;
+  if (degree < 1) return;
+  Y[1] = -kSh1 * y;
+  Y[2] = kSh1 * z;
+  Y[3] = -kSh1 * x;
+  if (degree < 2) return;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  Y[4] = kSh2a * x * y;
+  Y[5] = -kSh2a * y * z;
+  Y[6] = kSh20 * (3.f * zz - 1.f);
+  Y[7] = -kSh2a * x * z;
+  Y[8] = kSh22 * (xx - yy);
+  if (degree < 3) return;
+  Y[9] = -kSh33 * y * (3.f * xx - yy);
+  Y[10] = kSh32 * x * y * z;
+  Y[11] = -kSh31 * y * (5.f * zz - 1.f);
+  Y[12] = kSh30 * z * (5.f * zz - 3.f);
+  Y[13] = -kSh31 * x * (5.f * zz - 1.f);
+  Y[14] = kSh32b * z * (xx - yy);
+  Y[15] = -kSh33 * x * (xx - 3.f * yy);
+}
+
+// sum_k w_k grad Y_k at (x, y, z), k < (degree + 1)^2.
+__device__ __forceinline__ float3 sh_grad(int degree, float x, float y, float z, const float (&w)[16]) {
+  float gx = 0.f, gy = 0.f, gz = 0.f;
+  if (degree >= 1) {
+    gy -= kSh1 * w[1];
+    gz += kSh1 * w[2];
+    gx -= kSh1 * w[3];
+  }
+  if (degree >= 2) {
+    gx += kSh2a * y * w[4];
+    gy += kSh2a * x * w[4];
+    gy -= kSh2a * z * w[5];
+    gz -= kSh2a * y * w[5];
+    gz += 6.f * kSh20 * z * w[6];
+    gx -= kSh2a * z * w[7];
+    gz -= kSh2a * x * w[7];
+    gx += 2.f * kSh22 * x * w[8];
+    gy -= 2.f * kSh22 * y * w[8];
+  }
+  if (degree >= 3) {
+    const float xx = x * x, yy = y * y, zz = z * z;
+    gx -= kSh33 * 6.f * x * y * w[9];
+    gy -= kSh33 * 3.f * (xx - yy) * w[9];
+    gx += kSh32 * y * z * w[10];
+    gy += kSh32 * x * z * w[10];
+    gz += kSh32 * x * y * w[10];
+    gy -= kSh31 * (5.f * zz - 1.f) * w[11];
+    gz -= kSh31 * 10.f * y * z * w[11];
+    gz += kSh30 * (15.f * zz - 3.f) * w[12];
+    gx -= kSh31 * (5.f * zz - 1.f) * w[13];
+    gz -= kSh31 * 10.f * x * z * w[13];
+    gx += kSh32b * 2.f * x * z * w[14];
+    gy -= kSh32b * 2.f * y * z * w[14];
+    gz += kSh32b * (xx - yy) * w[14];
+    gx -= kSh33 * 3.f * (xx - yy) * w[15];
+    gy += kSh33 * 6.f * x * y * w[15];
+  }
+  return make_float3(gx, gy, gz);
+}
+
+// Viewing direction of Gaussian i from the camera centre C = -R^T t of pose
+// P, its inverse distance, the harmonics there and the colour
+// max(0, sum_k sh_k Y_k + 1/2) per channel (clamped[c]: below zero).
+struct ShColour {
+  float d[3], inv_len;
+  float Y[16];
+  float col[3];
+  bool clamped[3];
+};
+
+__device__ __forceinline__ void sh_colour(const GaussianPtrs& g, int64_t i, const float* P, ShColour& o) {
+  const float* X = g.means + 3 * i;
+  float v[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) v[k] = X[k] + (P[k] * P[9] + P[3 + k] * P[10] + P[6 + k] * P[11]);
+  const float len2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  o.inv_len = len2 > 0.f ? 1.0f / sqrtf(len2) : 0.f;
+  o.d[0] = v[0] * o.inv_len;
+  o.d[1] = v[1] * o.inv_len;
+  o.d[2] = len2 > 0.f ? v[2] * o.inv_len : 1.f;
+  sh_basis(g.sh_degree, o.d[0], o.d[1], o.d[2], o.Y);
+  const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
+  const float* c = g.sh + (int64_t)3 * K * i;
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    float sum = 0.5f;
+    for (int k = 0; k < K; ++k) sum = __builtin_fmaf(c[3 * k + ch], o.Y[k], sum);
+    o.clamped[ch] = sum < 0.f;
+    o.col[ch] = o.clamped[ch] ? 0.f : sum;
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void project_kernel(GaussianPtrs g, const float* __restrict__ poses,
                                                            ViewTable vt, ProjectBufs b) {
   __shared__ uint32_t s_off[kThreads], s_org[kThreads], s_wid[kThreads];
@@ -210,7 +321,18 @@ __global__ __launch_bounds__(kThreads) void project_kernel(GaussianPtrs g, const
         const uint32_t tx1 = (uint32_t)u1 / kTile, ty1 = (uint32_t)v1 / kTile;
         width = tx1 - tx0 + 1;
         ntiles = width * (ty1 - ty0 + 1);
-        const float* c = g.rgb + 3 * i;
+        float c[3];
+        if (g.sh) {
+          ShColour sc;
+          sh_colour(g, i, P, sc);
+          c[0] = sc.col[0];
+          c[1] = sc.col[1];
+          c[2] = sc.col[2];
+        } else {
+          c[0] = g.rgb[3 * i];
+          c[1] = g.rgb[3 * i + 1];
+          c[2] = g.rgb[3 * i + 2];
+        }
         float4* rec = b.rec + kRecF4 * m;
         // The mean is kept as a float pair hi + lo; the blend kernels take it
         // relative to their tile's origin, where hi - origin is exact.
@@ -383,6 +505,39 @@ __global__ __launch_bounds__(kThreads) void project_backward_kernel(GaussianPtrs
       } else {
         dp2 += dJ12 * cam.fy * o.ty * zinv2;
       }
+      // View-dependent colour: colour_c = max(0, sum_k sh_kc Y_k(d) + 1/2),
+      // d = v / |v|, v = X - C, C = -R^T t.  dL/dv = (I - d d^T) dL/dd / |v|
+      // reaches the mean (+dL/dv) and the camera centre (-dL/dv); C moves to
+      // C - R^T rho under exp(xi^) T, so dL/drho gains R dL/dv.
+      float dv[3] = {0.f, 0.f, 0.f};
+      if (g.sh) {
+        ShColour sc;
+        sh_colour(g, i, P, sc);
+        const float gcol[3] = {g1.w, g2.x, g2.y};
+        float dc[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) dc[ch] = sc.clamped[ch] ? 0.f : gcol[ch];
+        const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
+        const float* c = g.sh + (int64_t)3 * K * i;
+        float w[16];
+        for (int k = 0; k < 16; ++k) w[k] = 0.f;
+        for (int k = 0; k < K; ++k) w[k] = dc[0] * c[3 * k] + dc[1] * c[3 * k + 1] + dc[2] * c[3 * k + 2];
+        const float3 gd = sh_grad(g.sh_degree, sc.d[0], sc.d[1], sc.d[2], w);
+        const float dot = gd.x * sc.d[0] + gd.y * sc.d[1] + gd.z * sc.d[2];
+        dv[0] = (gd.x - sc.d[0] * dot) * sc.inv_len;
+        dv[1] = (gd.y - sc.d[1] * dot) * sc.inv_len;
+        dv[2] = (gd.z - sc.d[2] * dot) * sc.inv_len;
+        if (param_grads && dg.sh) {
+          float* out = dg.sh + (int64_t)3 * K * i;
+          for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+              const float val = dc[ch] * sc.Y[k];
+              if (atomic_params) unsafeAtomicAdd(out + 3 * k + ch, val);
+              else out[3 * k + ch] += val;
+            }
+        }
+      }
       if (param_grads) {
         // Means: p = W X + t.
         float dX[3];
@@ -430,27 +585,30 @@ __global__ __launch_bounds__(kThreads) void project_backward_kernel(GaussianPtrs
         const float dotq = o.qn[0] * dq[0] + o.qn[1] * dq[1] + o.qn[2] * dq[2] + o.qn[3] * dq[3];
         const float dlogit = dop * o.opacity * (1.f - o.opacity);
         float* outs[5] = {dg.means, dg.log_scales, dg.quats, dg.opacity_logits, dg.rgb};
-        const float vals_mean[3] = {dX[0], dX[1], dX[2]};
+        float vals_mean[3] = {dX[0], dX[1], dX[2]};
         auto put = [&](float* base, int64_t idx, float val) {
           if (!base) return;
           if (atomic_params) unsafeAtomicAdd(base + idx, val);
           else base[idx] += val;
         };
+        for (int k = 0; k < 3; ++k) vals_mean[k] += dv[k];
         for (int k = 0; k < 3; ++k) put(outs[0], 3 * i + k, vals_mean[k]);
         for (int k = 0; k < 3; ++k) put(outs[1], 3 * i + k, dls[k]);
         for (int k = 0; k < 4; ++k) put(outs[2], 4 * i + k, (dq[k] - o.qn[k] * dotq) * o.qinv);
         put(outs[3], i, dlogit);
-        put(outs[4], 3 * i + 0, g1.w);
-        put(outs[4], 3 * i + 1, g2.x);
-        put(outs[4], 3 * i + 2, g2.y);
+        if (!g.sh) {
+          put(outs[4], 3 * i + 0, g1.w);
+          put(outs[4], 3 * i + 1, g2.x);
+          put(outs[4], 3 * i + 2, g2.y);
+        }
       }
       // Pose, left perturbation: drho = dp; dphi = p x dp + 2 vee(skew(Sc dSc)).
       const float Sf[9] = {S[0], S[1], S[2], S[1], S[3], S[4], S[2], S[4], S[5]};
       const float dSf[9] = {dS[0], dS[1], dS[2], dS[1], dS[3], dS[4], dS[2], dS[4], dS[5]};
       auto Mrc = [&](int r, int cc) { return Sf[3 * r] * dSf[cc] + Sf[3 * r + 1] * dSf[3 + cc] + Sf[3 * r + 2] * dSf[6 + cc]; };
-      gp[0] = dp0;
-      gp[1] = dp1;
-      gp[2] = dp2;
+      gp[0] = dp0 + P[0] * dv[0] + P[1] * dv[1] + P[2] * dv[2];
+      gp[1] = dp1 + P[3] * dv[0] + P[4] * dv[1] + P[5] * dv[2];
+      gp[2] = dp2 + P[6] * dv[0] + P[7] * dv[1] + P[8] * dv[2];
       gp[3] = y * dp2 - z * dp1 + 2.f * (Mrc(1, 2) - Mrc(2, 1));
       gp[4] = z * dp0 - x * dp2 + 2.f * (Mrc(2, 0) - Mrc(0, 2));
       gp[5] = x * dp1 - y * dp0 + 2.f * (Mrc(0, 1) - Mrc(1, 0));

@@ -263,9 +263,11 @@ __device__ __forceinline__ int block_max(uint32_t lane_max, uint32_t* s_max) {
 // A lane first sums its pixels' contributions to a Gaussian, then the wave
 // reduces all of the Gaussian's gradient terms together (wave_sum_many) and
 // issues one atomic instruction.  kParams adds the opacity and colour
-// gradients (mapping); kTrack has colour and depth upstream gradients only.
+// gradients (mapping); kColor alone adds the colour gradients (the pose
+// gradient needs them when the colour depends on the viewpoint); kTrack has
+// colour and depth upstream gradients only.
 // staged_n > 0: the stage already holds list entries [0, staged_n).
-template <int kPPL, bool kParams, bool kTrack>
+template <int kPPL, bool kParams, bool kTrack, bool kColor = false>
 __device__ __forceinline__ void backward_tile(const RasterBufs& b, Stage& s, uint2 range, float2 org, int nmax,
                                               int staged_n, BwdPix<kPPL>& p) {
   constexpr int L = kTilePixels / kPPL;
@@ -330,8 +332,8 @@ __device__ __forceinline__ void backward_tile(const RasterBufs& b, Stage& s, uin
         syy = __builtin_fmaf(pdy, dy, syy);
         gdd += wgt * p.gd[k];
         if (!kTrack) gdd += 2.f * wgt * dz * p.gu[k] + ((hit && pos == p.med[k]) ? p.gm[k] : 0.f);
-        if (kParams) {
-          gop += live ? dalpha * g : 0.f;
+        if (kParams) gop += live ? dalpha * g : 0.f;
+        if (kParams || kColor) {
           gr += wgt * p.gc0[k];
           gg += wgt * p.gc1[k];
           gbl += wgt * p.gc2[k];
@@ -359,6 +361,13 @@ __device__ __forceinline__ void backward_tile(const RasterBufs& b, Stage& s, uin
           const int idx = reduced_value_index<16>(lane);
           const float out = finish(idx, t);
           if ((lane & 3) == 0 && idx < 10) unsafeAtomicAdd(dst + idx, out);
+        } else if (kColor) {
+          // slots 0-4, depth in 6, colour in 7-9
+          const float vals[9] = {u1, u2, sxx, sxy, syy, gdd, gr, gg, gbl};
+          const float t = wave_sum_many<16>(vals);
+          const int idx = reduced_value_index<16>(lane);
+          const float out = finish(idx, t);
+          if ((lane & 3) == 0 && idx < 9) unsafeAtomicAdd(dst + (idx < 5 ? idx : idx + 1), out);
         } else {
           const float vals[6] = {u1, u2, sxx, sxy, syy, gdd};
           const float t = wave_sum_many<8>(vals);
@@ -383,7 +392,7 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(Rast
   forward_outputs<kPPL, kTrack, kNu>(b, v, io, f, g, true);
 }
 
-template <int kPPL, bool kParams, bool kTrack>
+template <int kPPL, bool kParams, bool kTrack, bool kColor>
 __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(RasterBufs b) {
   constexpr int L = kTilePixels / kPPL;
   __shared__ Stage s;
@@ -433,12 +442,13 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
     }
   }
   const int nmax = block_max(lane_max, &s_max);
-  backward_tile<kPPL, kParams, kTrack>(b, s, b.ranges[gtile], tile_origin(cam, gtile), nmax, 0, p);
+  backward_tile<kPPL, kParams, kTrack, kColor>(b, s, b.ranges[gtile], tile_origin(cam, gtile), nmax, 0, p);
 }
 
 // Tracking iteration of one tile: forward, tracking-loss gradients in
-// registers, pose backward.
-template <int kPPL>
+// registers, pose backward (kColor: with the colour gradients that the pose
+// gradient of a view-dependent colour needs).
+template <int kPPL, bool kColor>
 __global__ __launch_bounds__(kTilePixels / kPPL) void raster_track_kernel(RasterBufs b) {
   __shared__ Stage s;
   __shared__ uint32_t s_max;
@@ -472,7 +482,7 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_track_kernel(Raster
   }
   const int nmax = block_max(lane_max, &s_max);
   const int len = (int)(range.y - range.x);
-  backward_tile<kPPL, false, true>(b, s, range, org, nmax, len <= kBatch ? len : 0, p);
+  backward_tile<kPPL, false, true, kColor>(b, s, range, org, nmax, len <= kBatch ? len : 0, p);
 }
 
 template <int kPPL>
@@ -486,14 +496,19 @@ void launch_fwd(const RasterBufs& b, bool track, hipStream_t s) {
 template <int kPPL>
 void launch_bwd(const RasterBufs& b, bool params, bool track, hipStream_t s) {
   const dim3 grid(b.total_tiles), block(kTilePixels / kPPL);
-  if (track) hipLaunchKernelGGL((raster_backward_kernel<kPPL, false, true>), grid, block, 0, s, b);
-  else if (params) hipLaunchKernelGGL((raster_backward_kernel<kPPL, true, false>), grid, block, 0, s, b);
-  else hipLaunchKernelGGL((raster_backward_kernel<kPPL, false, false>), grid, block, 0, s, b);
+  if (track && b.color_grads)
+    hipLaunchKernelGGL((raster_backward_kernel<kPPL, false, true, true>), grid, block, 0, s, b);
+  else if (track) hipLaunchKernelGGL((raster_backward_kernel<kPPL, false, true, false>), grid, block, 0, s, b);
+  else if (params || b.color_grads)
+    hipLaunchKernelGGL((raster_backward_kernel<kPPL, true, false, false>), grid, block, 0, s, b);
+  else hipLaunchKernelGGL((raster_backward_kernel<kPPL, false, false, false>), grid, block, 0, s, b);
 }
 
 template <int kPPL>
 void launch_track(const RasterBufs& b, hipStream_t s) {
-  hipLaunchKernelGGL((raster_track_kernel<kPPL>), dim3(b.total_tiles), dim3(kTilePixels / kPPL), 0, s, b);
+  const dim3 grid(b.total_tiles), block(kTilePixels / kPPL);
+  if (b.color_grads) hipLaunchKernelGGL((raster_track_kernel<kPPL, true>), grid, block, 0, s, b);
+  else hipLaunchKernelGGL((raster_track_kernel<kPPL, false>), grid, block, 0, s, b);
 }
 
 }  // namespace

@@ -118,13 +118,14 @@ __global__ __launch_bounds__(kThreads) void nu_prune_kernel(int64_t n, const flo
 }
 
 // One Adam step (Kingma and Ba, with bias correction) on element e of the
-// concatenated parameter groups: widths 3, 3, 4, 1, 3 per Gaussian.
+// concatenated parameter groups: widths 3, 3, 4, 1 and the colour width per
+// Gaussian.
 __global__ __launch_bounds__(kThreads) void gaussian_adam_kernel(int64_t n, GaussianAdam a, float* moments,
                                                                  const uint32_t* step) {
   const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  const int64_t total = 14 * n;
+  const int64_t total = (11 + (int64_t)a.colour_width) * n;
   if (e >= total) return;
-  // group of e: boundaries 3n, 6n, 10n, 11n, 14n
+  // group of e: boundaries 3n, 6n, 10n, 11n, total
   int grp;
   int64_t base;
   if (e < 3 * n) { grp = 0; base = 0; }
@@ -135,6 +136,8 @@ __global__ __launch_bounds__(kThreads) void gaussian_adam_kernel(int64_t n, Gaus
   float* p = a.param[grp];
   float* gp = a.grad[grp];
   const int64_t k = e - base;
+  // SH coefficients past the three of degree 0 take their own rate
+  const float lr = grp == 4 && k % a.colour_width >= 3 ? a.lr_sh_rest : a.lr[grp];
   const float t = (float)(*step + 1u);
   const float g = gp[k];
   gp[k] = 0.f;
@@ -145,7 +148,7 @@ __global__ __launch_bounds__(kThreads) void gaussian_adam_kernel(int64_t n, Gaus
   *m = mm;
   *v = vv;
   const float c1 = 1.f - powf(a.beta1, t), c2 = 1.f - powf(a.beta2, t);
-  p[k] -= a.lr[grp] * (mm / c1) / (sqrtf(vv / c2) + a.eps);
+  p[k] -= lr * (mm / c1) / (sqrtf(vv / c2) + a.eps);
 }
 
 __global__ void increment_kernel(uint32_t* step) { *step += 1u; }
@@ -196,8 +199,9 @@ void launch_nu_prune(int64_t n, const float* nu_sum, const uint32_t* nu_count, f
 
 void launch_gaussian_adam(int64_t n, const GaussianAdam& a, float* moments, uint32_t* step, hipStream_t s) {
   if (n > 0)
-    hipLaunchKernelGGL(gaussian_adam_kernel, dim3((unsigned)((14 * n + kThreads - 1) / kThreads)), dim3(kThreads), 0,
-                       s, n, a, moments, (const uint32_t*)step);
+    hipLaunchKernelGGL(gaussian_adam_kernel,
+                       dim3((unsigned)(((11 + (int64_t)a.colour_width) * n + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, s, n, a, moments, (const uint32_t*)step);
   hipLaunchKernelGGL(increment_kernel, dim3(1), dim3(1), 0, s, step);
 }
 

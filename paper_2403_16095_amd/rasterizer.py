@@ -40,12 +40,30 @@ def _check_f32(name, t, shape=None):
         raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
 
 
+def sh_degree_of(sh: torch.Tensor) -> int:
+    """Degree of an SH coefficient tensor [n, (degree + 1)^2, 3]."""
+    K = sh.shape[1] if sh.dim() == 3 else -1
+    for d in range(4):
+        if K == (d + 1) ** 2 and sh.shape[2] == 3:
+            return d
+    raise ValueError("sh must be [n, (degree + 1)^2, 3] with degree 0 .. 3")
+
+
 def gaussians_struct(scene: dict) -> B.cgsr_gaussians:
+    """Parameters of ``scene``; with an ``sh`` tensor [n, (degree + 1)^2, 3]
+    the colour is view-dependent and ``rgb`` may be absent."""
     n = scene["means"].shape[0]
+    sh = scene.get("sh")
     for k in PARAM_NAMES:
+        if k == "rgb" and sh is not None and scene.get("rgb") is None:
+            continue
         w = PARAM_WIDTH[k]
         _check_f32(k, scene[k], (n,) if w == 1 else (n, w))
-    return B.cgsr_gaussians(n, *[scene[k].data_ptr() for k in PARAM_NAMES])
+    deg = 0
+    if sh is not None:
+        deg = sh_degree_of(sh)
+        _check_f32("sh", sh, (n, (deg + 1) ** 2, 3))
+    return B.cgsr_gaussians(n, *[_ptr(scene.get(k)) for k in PARAM_NAMES], _ptr(sh), deg)
 
 
 def camera_struct(cam: dict) -> B.cgsr_camera:
@@ -132,6 +150,7 @@ def render(state: State, scene: dict, poses: torch.Tensor, cams, depth_obs=None,
     B.cgsr_render(state.handle, g, V, poses.data_ptr(), [camera_struct(c) for c in cams],
                   None if depth_obs is None else deps, structs, _stream())
     state.n_views, state.n = V, g.n
+    state.sh_shape = None if scene.get("sh") is None else tuple(scene["sh"].shape)
     # The backward reads these through the pointers the state recorded.
     state.inputs = (scene, poses, depth_obs)
     return outs
@@ -173,6 +192,7 @@ def render_nu(state: State, scene: dict, poses: torch.Tensor, cams, depth_obs, n
                      [d.data_ptr() for d in depth_obs], structs, [_ptr(d) for d in doms] if dominant else None,
                      nu_sum.data_ptr(), nu_count.data_ptr(), _stream())
     state.n_views, state.n = V, n
+    state.sh_shape = None if scene.get("sh") is None else tuple(scene["sh"].shape)
     state.inputs = (scene, poses, depth_obs)
     return outs, (doms if dominant else None)
 
@@ -235,32 +255,52 @@ def mapping_objective(state: State, maps, target_colors, target_depths, omega=MA
 #: Mapping learning rates (reading: the paper defers them to its supplementary
 #: material; these are the 3D Gaussian splatting defaults, the position rate
 #: scaled by a 5 m scene extent).
-MAPPING_LR = dict(means=1.6e-4 * 5.0, log_scales=5e-3, quats=1e-3, opacity_logits=5e-2, rgb=2.5e-3)
+MAPPING_LR = dict(means=1.6e-4 * 5.0, log_scales=5e-3, quats=1e-3, opacity_logits=5e-2, rgb=2.5e-3,
+                  sh_rest=2.5e-3 / 20.0)
 
 
-def gaussian_adam_params(lr=None, betas=(0.9, 0.999), eps=1e-15) -> B.cgsr_gaussian_adam_params:
+def gaussian_adam_params(lr=None, betas=(0.9, 0.999), eps=1e-15, sh_degree: int = 0) -> B.cgsr_gaussian_adam_params:
+    """Adam constants; with SH colour, lr["rgb"] is the rate of the degree-0
+    coefficients and lr["sh_rest"] that of the others."""
     lr = dict(MAPPING_LR, **(lr or {}))
     return B.cgsr_gaussian_adam_params(*[float(lr[k]) for k in PARAM_NAMES], float(betas[0]), float(betas[1]),
-                                       float(eps))
+                                       float(eps), float(lr["sh_rest"]), int(sh_degree))
 
 
 def gaussian_grads_struct(tensors: dict) -> B.cgsr_gaussian_grads:
+    """Pointers of a parameter or gradient dict; ``sh`` replaces ``rgb`` for
+    view-dependent colour."""
     n = tensors["means"].shape[0]
+    sh = tensors.get("sh")
     for k in PARAM_NAMES:
+        if k == "rgb" and sh is not None and tensors.get("rgb") is None:
+            continue
         w = PARAM_WIDTH[k]
         _check_f32(k, tensors[k], (n,) if w == 1 else (n, w))
-    return B.cgsr_gaussian_grads(*[tensors[k].data_ptr() for k in PARAM_NAMES])
+    if sh is not None:
+        _check_f32("sh", sh, (n, sh.shape[1], 3))
+    return B.cgsr_gaussian_grads(*[_ptr(tensors.get(k)) for k in PARAM_NAMES], _ptr(sh))
 
 
 def gaussian_adam_step(scene: dict, grads: dict, moments: torch.Tensor, step: torch.Tensor, lr=None,
                        betas=(0.9, 0.999), eps=1e-15):
     """In-place Adam step on every Gaussian parameter tensor of ``scene`` with
-    ``grads`` (zeroed afterwards).  moments: float32 [2, 14 n] zeros; step:
-    int32 [1] zeros (read as uint32 by the library)."""
+    ``grads`` (zeroed afterwards).  moments: float32 [2, (11 + W) n] zeros,
+    W = 3 for rgb or 3 (degree + 1)^2 for SH colour; step: int32 [1] zeros
+    (read as uint32 by the library)."""
     n = scene["means"].shape[0]
-    _check_f32("moments", moments, (2, 14 * n))
-    B.cgsr_gaussian_adam_step(n, gaussian_grads_struct(scene), gaussian_grads_struct(grads), moments.data_ptr(),
-                              step.data_ptr(), gaussian_adam_params(lr, betas, eps), _stream())
+    sh = scene.get("sh")
+    deg = 0 if sh is None else sh_degree_of(sh)
+    W = 3 if sh is None else 3 * (deg + 1) ** 2
+    _check_f32("moments", moments, (2, (11 + W) * n))
+    g_struct = gaussian_grads_struct(scene)
+    if sh is not None:
+        g_struct.rgb = None
+    d_struct = gaussian_grads_struct(grads)
+    if sh is not None:
+        d_struct.rgb = None
+    B.cgsr_gaussian_adam_step(n, g_struct, d_struct, moments.data_ptr(), step.data_ptr(),
+                              gaussian_adam_params(lr, betas, eps, deg), _stream())
 
 
 class BundleAdjuster:
@@ -283,8 +323,12 @@ class BundleAdjuster:
         self.omega = tuple(omega)
         n = scene["means"].shape[0]
         dev = self.poses.device
-        self.grads = {k: torch.zeros_like(scene[k]) for k in PARAM_NAMES}
-        self.moments = torch.zeros((2, 14 * n), dtype=torch.float32, device=dev)
+        sh = scene.get("sh")
+        self.sh_degree = 0 if sh is None else sh_degree_of(sh)
+        names = [k for k in PARAM_NAMES if not (k == "rgb" and sh is not None)] + (["sh"] if sh is not None else [])
+        self.grads = {k: torch.zeros_like(scene[k]) for k in names}
+        W = 3 if sh is None else 3 * (self.sh_degree + 1) ** 2
+        self.moments = torch.zeros((2, (11 + W) * n), dtype=torch.float32, device=dev)
         self.step_count = torch.zeros(1, dtype=torch.int32, device=dev)
         self.dposes = torch.zeros((V, 6), dtype=torch.float32, device=dev)
         self.pose_adam = torch.zeros((V, 16), dtype=torch.float32, device=dev)
@@ -302,7 +346,7 @@ class BundleAdjuster:
         self.map_s = [B.cgsr_images(*[_ptr(m.get(k)) for k in MAP_NAMES]) for m in self.maps]
         self.dimg_s = [B.cgsr_images(*[_ptr(d.get(k)) for k in MAP_NAMES]) for d in self.dimgs]
         self.weights = B.cgsr_mapping_weights(*[float(x) for x in self.omega], float(ISO_EPSILON))
-        self.hp = gaussian_adam_params(lr, eps=eps)
+        self.hp = gaussian_adam_params(lr, eps=eps, sh_degree=self.sh_degree)
         self.pose_hp = adam_params(pose_lr[0], pose_lr[1])
         self.param_s = gaussian_grads_struct(scene)
         self.grad_s = gaussian_grads_struct(self.grads)
@@ -344,9 +388,13 @@ def backward(state: State, dimgs, param_grads: bool = True, pose_grads: bool = T
     grads = None
     dG = None
     if param_grads:
+        sh_shape = getattr(state, "sh_shape", None)
+        names = [k for k in PARAM_NAMES if not (k == "rgb" and sh_shape is not None)]
         grads = {k: torch.zeros((n,) if PARAM_WIDTH[k] == 1 else (n, PARAM_WIDTH[k]), dtype=torch.float32,
-                                device=dev) for k in PARAM_NAMES}
-        dG = B.cgsr_gaussian_grads(*[grads[k].data_ptr() for k in PARAM_NAMES])
+                                device=dev) for k in names}
+        if sh_shape is not None:
+            grads["sh"] = torch.zeros(sh_shape, dtype=torch.float32, device=dev)
+        dG = gaussian_grads_struct(grads)
     dposes = torch.zeros((V, 6), dtype=torch.float32, device=dev) if pose_grads else None
     B.cgsr_backward(state.handle, structs, dG, _ptr(dposes), _stream())
     return grads, dposes

@@ -1,0 +1,170 @@
+"""View-dependent colour (spherical-harmonic coefficients, Sec. 3.1) on the
+HIP path vs the FP64 oracle, through the C ABI: renders within 1e-4, the
+gradients of the coefficients, the means (through the viewing direction) and
+the pose (through the camera centre) within 1e-3 relative, in the separate
+backward and in the fused tracking step, and the SH Adam groups."""
+import sys
+
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+
+import oracle
+from paper_2403_16095_amd import synth
+from helpers import rel_l2, unambiguous
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+POSE = (Rotation.from_rotvec([0.03, -0.05, 0.02]).as_matrix(), np.array([0.12, -0.07, 0.2]))
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_16095_amd import rasterizer
+    return rasterizer
+
+
+def t32(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+
+
+def sh_scene(seed, n, degree):
+    # strongly view-dependent, so the pose term through the camera centre is
+    # well above the tolerance
+    sc = synth.uniform_box_scene(seed, n)
+    sc["sh"] = synth.sh_coefficients(seed + 1, n, degree, rest_std=1.0)
+    del sc["rgb"]
+    return sc
+
+
+def render(R, st, sc, cam, pose, dobs=None):
+    out = R.render(st, {k: t32(v) for k, v in sc.items()}, R.pose_tensor(*pose), [cam],
+                   None if dobs is None else [t32(dobs)])[0]
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
+
+
+@pytest.mark.parametrize("degree", [1, 3])
+def test_sh_render_matches_oracle(R, degree):
+    say(f"case: SH degree {degree} render, 2000 Gaussians 64x48")
+    sc = sh_scene(0, 2000, degree)
+    cam = synth.SMALL_CAMERA
+    gpu = render(R, R.State(), sc, cam, POSE)
+    ref = oracle.render(sc, cam, POSE)
+    mask = unambiguous(ref)
+    assert mask.mean() > 0.99
+    for k in ("color", "depth", "opacity", "depth_median"):
+        err = np.abs(gpu[k] - ref[k])[np.broadcast_to(mask, gpu[k].shape)].max()
+        say(k, err)
+        assert err <= 1e-4, (k, err)
+    # the colour really varies with the viewpoint
+    ref2 = oracle.render(sc, cam, (POSE[0], POSE[1] + np.array([0.3, 0.0, 0.0])))
+    assert np.abs(ref2["color"] - ref["color"]).max() > 1e-2
+
+
+def test_sh_degree_zero_equals_rgb(R):
+    say("case: SH degree 0 against rgb")
+    sc = synth.uniform_box_scene(4, 1500)
+    cam = synth.SMALL_CAMERA
+    sh = dict(sc)
+    sh["sh"] = ((sc["rgb"].astype(np.float64) - 0.5) * np.sqrt(4 * np.pi))[:, None, :].astype(np.float32)
+    del sh["rgb"]
+    a = render(R, R.State(), sc, cam, POSE)
+    b = render(R, R.State(), sh, cam, POSE)
+    for k in ("color", "depth", "opacity"):
+        np.testing.assert_allclose(b[k], a[k], atol=2e-6, err_msg=k)
+
+
+def test_sh_backward_matches_oracle(R):
+    say("case: SH degree 3 full backward, 2000 Gaussians 64x48")
+    sc = sh_scene(1, 2000, 3)
+    cam = synth.SMALL_CAMERA
+    rng = np.random.default_rng(8)
+    H, W = cam["height"], cam["width"]
+    dimg = dict(color=rng.standard_normal((3, H, W)), depth=rng.standard_normal((H, W)),
+                opacity=rng.standard_normal((H, W)))
+    st = R.State()
+    render(R, st, sc, cam, POSE)
+    grads, dposes = R.backward(st, [{k: t32(v) for k, v in dimg.items()}])
+    torch.cuda.synchronize()
+    ref = oracle.backward(sc, cam, POSE, None, dimg)
+    assert "rgb" not in grads
+    for k in ("sh", "means", "log_scales", "quats", "opacity_logits"):
+        e = rel_l2(grads[k].cpu().numpy(), ref[k])
+        say(k, "rel err", e)
+        assert e <= 1e-3, (k, e)
+    dp = dposes[0].cpu().numpy()
+    e = np.abs(dp - ref["pose"]).max() / np.abs(ref["pose"]).max()
+    say("pose", dp, ref["pose"], e)
+    assert e <= 1e-3
+    # the pose-only backward reaches the same pose gradient
+    _, dp2 = R.backward(st, [{k: t32(v) for k, v in dimg.items()}], param_grads=False)
+    e2 = np.abs(dp2[0].cpu().numpy() - ref["pose"]).max() / np.abs(ref["pose"]).max()
+    say("pose only", e2)
+    assert e2 <= 1e-3
+
+
+def test_sh_tracking_step_pose_gradient(R):
+    say("case: SH degree 3 fused tracking step pose gradient, 2000 Gaussians 64x48")
+    sc = sh_scene(3, 2000, 3)
+    cam = synth.SMALL_CAMERA
+    tc, td = synth.random_targets(77, cam)
+    st = R.State()
+    dp = torch.zeros((1, 6), device="cuda")
+    R.tracking_step(st, {k: t32(v) for k, v in sc.items()}, R.pose_tensor(*POSE), [cam], [t32(tc)], [t32(td)],
+                    lam=(1.0, 1.0), dposes=dp)
+    torch.cuda.synchronize()
+    m = oracle.render(sc, cam, POSE)
+    _, dimg = oracle.tracking_loss(m, tc, td, lam=(1.0, 1.0))
+    ref = oracle.backward(sc, cam, POSE, None, dimg)
+    got = dp[0].cpu().numpy()
+    e = np.abs(got - ref["pose"]).max() / np.abs(ref["pose"]).max()
+    say("pose", got, ref["pose"], e)
+    assert e <= 1e-3
+
+
+def test_sh_adam_groups_match_oracle(R):
+    say("case: Gaussian Adam with SH degree 2, 5001 Gaussians, 2 steps")
+    rng = np.random.default_rng(2)
+    n, deg = 5001, 2
+    K = (deg + 1) ** 2
+    shapes = dict(means=(n, 3), log_scales=(n, 3), quats=(n, 4), opacity_logits=(n,), sh=(n, K, 3))
+    params = {k: rng.normal(0, 1, s).astype(np.float32) for k, s in shapes.items()}
+    scene = {k: t32(v) for k, v in params.items()}
+    moments = torch.zeros((2, (11 + 3 * K) * n), device="cuda")
+    step = torch.zeros(1, dtype=torch.int32, device="cuda")
+    lr = dict(means=1e-3, log_scales=5e-3, quats=2e-3, opacity_logits=5e-2, rgb=2.5e-3, sh_rest=1.25e-4)
+    ref = {k: v.astype(np.float64) for k, v in params.items()}
+    m = {k: np.zeros_like(v) for k, v in ref.items()}
+    v2 = {k: np.zeros_like(v) for k, v in ref.items()}
+    for it in range(2):
+        gr = {k: rng.normal(0, 1e-2, shapes[k]).astype(np.float32) for k in shapes}
+        R.gaussian_adam_step(scene, {k: t32(v) for k, v in gr.items()}, moments, step, lr=lr, eps=1e-8)
+        for k in ref:
+            if k == "sh":
+                rates = np.full((n, K, 3), lr["sh_rest"])
+                rates[:, 0, :] = lr["rgb"]
+            else:
+                rates = lr[k]
+            ref[k], m[k], v2[k] = oracle.adam_step(ref[k], gr[k].astype(np.float64), m[k], v2[k], it + 1, rates,
+                                                   eps=1e-8)
+    for k in ref:
+        np.testing.assert_allclose(scene[k].cpu().numpy(), ref[k], rtol=1e-5, atol=1e-6, err_msg=k)
+
+
+def test_sh_arguments_are_checked(R):
+    from paper_2403_16095_amd import binding as B
+    sc = sh_scene(5, 10, 1)
+    d = {k: t32(v) for k, v in sc.items()}
+    g = R.gaussians_struct(d)
+    g.sh_degree = 4
+    with pytest.raises(RuntimeError):
+        B.cgsr_render(R.State().handle, g, 1, R.pose_tensor(*POSE).data_ptr(), [R.camera_struct(synth.SMALL_CAMERA)],
+                      None, [B.cgsr_images()], 0)

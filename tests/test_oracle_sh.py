@@ -125,9 +125,9 @@ def test_negative_colour_is_clamped_to_zero_with_zero_gradient():
     assert g["sh"][0, 0, 0] == 0.0 and g["sh"][0, 0, 1] > 0
 
 
-def sh_scene(seed, n, degree, **kw):
+def sh_scene(seed, n, degree, rest_std=0.3, **kw):
     sc = {k: v.astype(np.float64) for k, v in synth.uniform_box_scene(seed, n, **kw).items()}
-    sc["sh"] = synth.sh_coefficients(seed + 1, n, degree).astype(np.float64)
+    sc["sh"] = synth.sh_coefficients(seed + 1, n, degree, rest_std=rest_std).astype(np.float64)
     del sc["rgb"]
     return sc
 
@@ -174,3 +174,33 @@ def test_camera_translation_equals_moving_every_gaussian():
     g = oracle.backward(sc, cam, IDENTITY, None, dimg)
     np.testing.assert_allclose(g["pose"][:3], g["means"].sum(0), rtol=1e-10,
                                atol=1e-12 * np.abs(g["means"]).sum())
+
+
+def test_direction_term_is_material_at_parity_sizes():
+    """On the GPU parity scene (strongly view-dependent coefficients) the pose
+    gradient through the camera centre is well above the 1e-3 parity
+    tolerance, so a GPU path without it fails: freezing
+    every Gaussian's colour at its value for this pose (an rgb scene) changes
+    the translation gradient by much more than that."""
+    cam = synth.SMALL_CAMERA
+    sc = sh_scene(1, 2000, 3, rest_std=1.0)
+    pose = (Rotation.from_rotvec([0.03, -0.05, 0.02]).as_matrix(), np.array([0.12, -0.07, 0.2]))
+    rng = np.random.default_rng(8)
+    dimg = dict(color=rng.standard_normal((3, 48, 64)))
+    g = oracle.backward(sc, cam, pose, None, dimg)
+    R, t = pose
+    C = -R.T @ t
+    rgb = np.zeros((2000, 3))
+    for i in range(2000):
+        v = sc["means"][i] - C
+        Y, _ = oracle.sh_basis(3, v / np.linalg.norm(v))
+        rgb[i] = np.maximum(0.0, Y @ sc["sh"][i] + 0.5)
+    frozen = {k: v for k, v in sc.items() if k != "sh"}
+    frozen["rgb"] = rgb
+    a = oracle.render(sc, cam, pose)
+    b = oracle.render(frozen, cam, pose)
+    np.testing.assert_allclose(b["color"], a["color"], atol=1e-12)   # same colours at this pose
+    gf = oracle.backward(frozen, cam, pose, None, dimg)
+    diff = np.abs(g["pose"][:3] - gf["pose"][:3]).max() / np.abs(g["pose"]).max()
+    assert diff > 5e-3, diff
+    np.testing.assert_allclose(g["pose"][3:], gf["pose"][3:], rtol=1e-10, atol=1e-12)
