@@ -110,8 +110,23 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def build_workload(torch, R, synth, n=100_000, seed=0):
-    sc = synth.room_scene(seed, n, (5.0, 4.0, 3.0))
+def with_sh(synth, sc, seed, degree):
+    """The scene with view-dependent colour of the given degree instead of rgb
+    (degree 0 keeps rgb)."""
+    if degree <= 0:
+        return sc
+    out = {k: v for k, v in sc.items() if k != "rgb"}
+    out["sh"] = synth.sh_coefficients(seed, sc["means"].shape[0], degree)
+    return out
+
+
+def param_floats(degree):
+    """float32 parameters per Gaussian: 11 + 3 for rgb, 11 + 3 (degree + 1)^2 with SH."""
+    return 14 if degree <= 0 else 11 + 3 * (degree + 1) ** 2
+
+
+def build_workload(torch, R, synth, n=100_000, seed=0, sh_degree=0):
+    sc = with_sh(synth, synth.room_scene(seed, n, (5.0, 4.0, 3.0)), seed + 7, sh_degree)
     scd = {k: torch.from_numpy(v).cuda() for k, v in sc.items()}
     cam = synth.TRACKING_CAMERA
     Rt, tt = synth.level_room_pose(seed)
@@ -123,16 +138,18 @@ def build_workload(torch, R, synth, n=100_000, seed=0):
     return sc, prob, P0, (Rt, tt)
 
 
-def algorithmic_bytes(n, visible, pairs, pixels):
+def algorithmic_bytes(n, visible, pairs, pixels, sh_degree=0):
     """HBM bytes one tracking iteration must move: parameters read (56 B per
-    Gaussian), projected records written (40 B per visible one), pairs written
+    Gaussian with rgb, 4 (11 + 3 K) B with K SH coefficients per channel; read
+    again by the backward for the visible ones), projected records written (40 B per visible one), pairs written
     and read back after the sort (24 B) and record gathers per pair (40 B),
     per-pixel sensor depth, 28 B of maps and 8 B of saved state (40 B); the
     backward reads gradient images, saved state and depth (32 B per pixel),
     record ids and records per pair (44 B) and writes and re-reads projected
     gradients plus parameters per visible Gaussian (88 B)."""
-    fwd = 56 * n + 40 * visible + 24 * pairs + 40 * pairs + 40 * pixels
-    bwd = 32 * pixels + 44 * pairs + 88 * visible
+    pb = 4 * param_floats(sh_degree)
+    fwd = pb * n + 40 * visible + 24 * pairs + 40 * pairs + 40 * pixels
+    bwd = 32 * pixels + 44 * pairs + 88 * visible + (pb - 56) * visible
     return fwd + bwd
 
 
@@ -200,12 +217,17 @@ class MappingIteration:
         self.poses = poses
         self.cams = [R.camera_struct(c) for c in cams]
         self.tc, self.td = target_colors, target_depths
-        self.flat = torch.zeros(n * 14, dtype=torch.float32, device=dev)
-        off, views = 0, []
-        for name, w in PARAM_WIDTHS:
-            views.append(self.flat[off:off + n * w].data_ptr())
+        sh = scene.get("sh")
+        widths = [(k, w) for k, w in PARAM_WIDTHS if not (k == "rgb" and sh is not None)]
+        if sh is not None:
+            widths.append(("sh", sh.shape[1] * 3))
+        self.flat = torch.zeros(n * sum(w for _, w in widths), dtype=torch.float32, device=dev)
+        off, views = 0, {}
+        for name, w in widths:
+            views[name] = self.flat[off:off + n * w].data_ptr()
             off += n * w
-        self.dG = B.cgsr_gaussian_grads(*views)
+        self.dG = B.cgsr_gaussian_grads(views["means"], views["log_scales"], views["quats"], views["opacity_logits"],
+                                        views.get("rgb"), views.get("sh"))
         self.dposes = torch.zeros((self.V, 6), dtype=torch.float32, device=dev)
         self.maps, self.grads, self.out_s, self.grad_s = [], [], [], []
         for c in cams:
@@ -266,12 +288,13 @@ class MappingIteration:
         return tot
 
 
-def mapping_bytes(n, visible, pairs, pixels):
+def mapping_bytes(n, visible, pairs, pixels, sh_degree=0):
     """HBM bytes one mapping iteration must move: the tracking figures plus,
     per pixel, the uncertainty map and its gradient (8 B) and the loss
     gradient pass (read 3 maps + 4 targets, write 3 gradients: 40 B), and per
-    visible Gaussian the 14 parameter gradients written (56 B)."""
-    return algorithmic_bytes(n, visible, pairs, pixels) + 48 * pixels + 56 * visible
+    visible Gaussian its parameter gradients written (56 B with rgb)."""
+    return (algorithmic_bytes(n, visible, pairs, pixels, sh_degree) + 48 * pixels
+            + 4 * param_floats(sh_degree) * visible)
 
 
 def oracle_mapping_seconds(sc, cam, pose, tc, td):
@@ -298,7 +321,10 @@ def perturbed_scene(np, sc, seed):
     rng = np.random.default_rng(seed)
     out = dict(sc)
     out["means"] = (sc["means"] + rng.normal(0.0, 0.005, sc["means"].shape)).astype(np.float32)
-    out["rgb"] = np.clip(sc["rgb"] + rng.normal(0.0, 0.05, sc["rgb"].shape), 0, 1).astype(np.float32)
+    if "sh" in sc:
+        out["sh"] = (sc["sh"] + rng.normal(0.0, 0.2, sc["sh"].shape)).astype(np.float32)
+    else:
+        out["rgb"] = np.clip(sc["rgb"] + rng.normal(0.0, 0.05, sc["rgb"].shape), 0, 1).astype(np.float32)
     return out
 
 
@@ -307,7 +333,8 @@ def run_mapping(args, torch, R, synth, views: int):
     n = 500_000 if views == 1 else 1_000_000
     seed = 3 if views == 1 else 4
     log(f"building workload: {n} Gaussians, {views} view(s) of 1200x680")
-    sc_t = synth.room_scene(seed, n, (8.0, 6.0, 3.0))
+    deg = args.sh_degree
+    sc_t = with_sh(synth, synth.room_scene(seed, n, (8.0, 6.0, 3.0)), seed + 7, deg)
     sc = perturbed_scene(np, sc_t, seed + 1000)
     cam = synth.MAPPING_CAMERA
     pose_list = [synth.level_room_pose(seed)] if views == 1 else synth.random_walk_poses(seed + 1000, views)
@@ -334,18 +361,19 @@ def run_mapping(args, torch, R, synth, views: int):
         log(f"{name}: {res[name]['ms_per_iter']:.3f} ms/iteration ({views} view(s))")
         del it
     st = res["batched"]["stats"]
-    b = mapping_bytes(n, st["visible"], st["pairs"], views * cam["width"] * cam["height"])
+    b = mapping_bytes(n, st["visible"], st["pairs"], views * cam["width"] * cam["height"], deg)
     ms = res["batched"]["ms_per_iter"]
     out = {
         "metric": ("mapping iters/s (fwd+full bwd) 1200x680 500k Gaussians" if views == 1 else
-                   "batched mapping views/s (fwd+full bwd) 8x1200x680 1M Gaussians"),
+                   "batched mapping views/s (fwd+full bwd) 8x1200x680 1M Gaussians")
+                  + (f", SH degree {deg}" if deg > 0 else ""),
         "value": round((1 if views == 1 else views) * 1e3 / ms, 3),
         "unit": "it/s" if views == 1 else "views/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": (f"mapping: {n} Gaussians on an 8x6x3 m room, {views} view(s) 1200x680 f=600, "
                                 "render with sensor depth + uncertainty-weighted L1 + backward to all "
-                                "parameters and poses"), "gaussians": n, "views": views},
+                                "parameters and poses"), "gaussians": n, "views": views, "sh_degree": deg},
         "hbm_roofline": {"algorithmic_bytes_per_iter": b, "achieved_GBs": round(b / (ms * 1e-3) / 1e9, 2),
                          "peak_GBs": HBM_PEAK_GBS, "frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)},
         "stats": st,
@@ -520,6 +548,8 @@ def main():
     ap.add_argument("--no-stage-timing", action="store_true")
     ap.add_argument("--eager", action="store_true",
                     help="run the solves without graph capture (same kernels; for counter collection)")
+    ap.add_argument("--sh-degree", type=int, default=0, choices=(0, 1, 2, 3),
+                    help="view-dependent colour of this SH degree instead of rgb (tracking and mapping workloads)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device copy of this many MB, 10 times (profiler byte-counter scale)")
     args = ap.parse_args()
@@ -552,8 +582,9 @@ def main():
             out = run_mapping(args, torch, R, synth, 1 if args.workload == "mapping" else 8)
         print(json.dumps(out), flush=True)
         return
-    log("building workload: 100k Gaussians, 640x480")
-    sc, prob, P0, true_pose = build_workload(torch, R, synth)
+    deg = args.sh_degree
+    log("building workload: 100k Gaussians, 640x480" + (f", SH degree {deg}" if deg else ""))
+    sc, prob, P0, true_pose = build_workload(torch, R, synth, sh_degree=deg)
     iters = args.solve_iters
     tune_state = R.State()
     fppl, bppl = R.autotune_tracking(tune_state, prob.scene, P0, [prob.cam], [prob.target_color],
@@ -617,7 +648,7 @@ def main():
         log("stage ms:", {k: round(v, 4) for k, v in stages.items()}, "stats:", stats)
 
     result = {
-        "metric": METRIC,
+        "metric": METRIC + (f", SH degree {deg}" if deg else ""),
         "value": round(value, 2),
         "unit": "it/s",
         "n_gpus": 1,
@@ -636,7 +667,7 @@ def main():
                                "render + L1 colour/depth loss + pose-only backward + Adam, 50-iteration "
                                "solves replayed from one HIP graph",
                    "gaussians": 100_000, "width": 640, "height": 480, "solve_iters": iters,
-                   "pixels_per_lane": fppl,
+                   "pixels_per_lane": fppl, "sh_degree": deg,
                    "loss_lambda": list(R.TRACK_LAMBDA)},
     }
     if stages:
@@ -648,13 +679,13 @@ def main():
         name = "blend_track"
         ms, fl = stages["blend_fwd"], flops_fwd + flops_bwd
         achieved = fl / (ms * 1e-3) / 1e12
-        symbol = f"raster_track_kernel<{fppl}>"
+        symbol = f"raster_track_kernel<{fppl}, {'true' if deg else 'false'}>"
         result["roofline"] = {"bound": "alu", "kernel": name, "symbol": symbol, "achieved": round(achieved, 4),
                               "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                               "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 5),
                               "traffic": measured_traffic(symbol),
                               "avg_ms": round(ms, 5), "algorithmic_flops": fl}
-        b = algorithmic_bytes(100_000, stats["visible"], stats["pairs"], 640 * 480)
+        b = algorithmic_bytes(100_000, stats["visible"], stats["pairs"], 640 * 480, deg)
         copy_gbs = copy_bandwidth(torch)
         result["hbm_roofline"] = {"algorithmic_bytes_per_iter": b,
                                   "achieved_GBs": round(b / (ms_per_step * 1e-3) / 1e9, 2),
