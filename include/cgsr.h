@@ -390,6 +390,88 @@ cgsr_status cgsr_autotune_tracking(cgsr_state *st, const cgsr_gaussians *g, int3
                                    const float *const *target_depth, int32_t repeats, cgsr_settings *out,
                                    void *stream);
 
+/*
+ * Gaussian management (Sec. 3.3).  The set is grown by spawning and
+ * densification and shrunk by compaction; each call writes a new set (or
+ * appends to one) in caller-owned arrays and returns the new count on the
+ * host, so it synchronises the stream.  Orders are deterministic.
+ *
+ * Writable parameter arrays of a set (device float, layouts of
+ * cgsr_gaussians): colour in rgb, or in sh (then rgb unused) with
+ * sh_degree as in cgsr_gaussians.
+ */
+typedef struct {
+    float *means, *log_scales, *quats, *opacity_logits, *rgb, *sh;
+    int32_t sh_degree;
+} cgsr_gaussian_arrays;
+
+/* Rendered-opacity threshold below which a pixel is unobserved (Sec. 3.3). */
+#define CGSR_SPAWN_PSI 0.5f
+
+/*
+ * Spawning (Sec. 3.3): new Gaussians from the pixels of one RGB-D view whose
+ * rendered opacity (Eq. 9) is below psi and whose sensor depth D is
+ * positive, appended at indices n, n + 1, ... in row-major pixel order.
+ * With opacity NULL every pixel with a depth spawns (the dense
+ * initialisation from the first frame).  stride >= 1 takes the pixels with
+ * u and v multiples of stride only.  A new Gaussian (readings where the
+ * paper is silent): mean = the back-projection of the pixel centre at depth
+ * D through the pose, T^-1 (D K^-1 (u, v, 1)); isotropic scale
+ * D / ((fx + fy) / 2) (one pixel at that depth); identity rotation;
+ * opacity logit init_logit; colour = the pixel's colour (with sh: the
+ * degree-0 coefficient (c - 1/2) sqrt(4 pi), the others zero).
+ *   dst       the set's arrays, holding n Gaussians and room for capacity.
+ *   cam       host camera of the view; pose device float[12] (world -> camera).
+ *   color     device [3][H][W]; depth device [H][W]; opacity device [H][W] or NULL.
+ *   n_out     host: n + the number spawned.  If that exceeds capacity, only
+ *             the first capacity - n are written and CGSR_ERR_CAPACITY is
+ *             returned with n_out still the full count.
+ */
+cgsr_status cgsr_spawn_gaussians(const cgsr_gaussian_arrays *dst, int64_t n, int64_t capacity,
+                                 const cgsr_camera *cam, const float *pose, const float *color,
+                                 const float *depth, const float *opacity, float psi, int32_t stride,
+                                 float init_logit, int64_t *n_out, void *stream);
+
+/*
+ * Removal: writes the Gaussians i < n with keep[i] != 0 (device uint8[n]),
+ * in order, to dst (which must not overlap src), and *n_out (host) = their
+ * number.  n_extra (<= 12) further per-Gaussian float arrays extra_src[e]
+ * of extra_width[e] floats per Gaussian (say Adam moments or uncertainty
+ * sums; host arrays of device pointers and widths) are compacted the same
+ * way into extra_dst[e].
+ */
+cgsr_status cgsr_compact_gaussians(int64_t n, const uint8_t *keep, const cgsr_gaussian_arrays *src,
+                                   const cgsr_gaussian_arrays *dst, int32_t n_extra,
+                                   const float *const *extra_src, float *const *extra_dst,
+                                   const int32_t *extra_width, int64_t *n_out, void *stream);
+
+/*
+ * Densification statistic (Sec. 3.3 keeps the densification of splatting):
+ * from now on every cgsr_backward on this state adds, for each (view,
+ * Gaussian) record that reaches the image, |dL/dmu| (the gradient of the
+ * loss with respect to the Gaussian's projected mean, in pixels) to
+ * grad_accum[i] and 1 to count[i] (device float[n] and uint32[n], caller
+ * cleared).  NULL pointers stop the accumulation.
+ */
+cgsr_status cgsr_set_densify_stats(cgsr_state *st, float *grad_accum, uint32_t *count);
+
+/*
+ * Densification: with stat_i = grad_accum[i] / count[i] (0 if count is 0),
+ * Gaussian i with stat_i >= grad_threshold is cloned when its largest scale
+ * is at most dense_scale and split otherwise.  A clone is an exact copy; a
+ * split replaces the Gaussian by two at mu + R diag(s) z_k (k = 0, 1; z the
+ * caller's standard normal draws normals[i][k][3], device float[n][2][3])
+ * with scales s / 1.6 and the other parameters copied.  dst (not
+ * overlapping src) receives the Gaussians that were not split, in order,
+ * then the clones in index order, then the split halves in index order (k
+ * = 0 first); *n_out (host) = their number.  If it exceeds capacity only the
+ * first capacity are written and CGSR_ERR_CAPACITY is returned.
+ */
+cgsr_status cgsr_densify_gaussians(int64_t n, const float *grad_accum, const uint32_t *count,
+                                   float grad_threshold, float dense_scale, const float *normals,
+                                   const cgsr_gaussian_arrays *src, const cgsr_gaussian_arrays *dst,
+                                   int64_t capacity, int64_t *n_out, void *stream);
+
 /* Synchronise the stream and report CGSR_ERR_CAPACITY if any render on this
  * state since the previous check (or since creation) overflowed its pair
  * buffer; the message names the most pairs a render needed.  The check then

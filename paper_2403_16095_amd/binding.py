@@ -30,7 +30,8 @@ EXPORTED = (
     "cgsr_render", "cgsr_render_nu", "cgsr_nu_prune", "cgsr_mapping_objective", "cgsr_gaussian_adam_step",
     "cgsr_backward", "cgsr_tracking_loss_grad", "cgsr_mapping_loss_grad", "cgsr_pose_adam_step",
     "cgsr_tracking_step",
-    "cgsr_autotune_tracking", "cgsr_state_check", "cgsr_get_stats", "cgsr_get_timings", "cgsr_debug_buffers",
+    "cgsr_autotune_tracking", "cgsr_spawn_gaussians", "cgsr_compact_gaussians", "cgsr_set_densify_stats",
+    "cgsr_densify_gaussians", "cgsr_state_check", "cgsr_get_stats", "cgsr_get_timings", "cgsr_debug_buffers",
     "cgsr_last_error",
     "cgsr_version",
 )
@@ -52,6 +53,11 @@ class cgsr_gaussians(C.Structure):
     _fields_ = [("n", C.c_int64), ("means", C.c_void_p), ("log_scales", C.c_void_p),
                 ("quats", C.c_void_p), ("opacity_logits", C.c_void_p), ("rgb", C.c_void_p),
                 ("sh", C.c_void_p), ("sh_degree", C.c_int32)]
+
+
+class cgsr_gaussian_arrays(C.Structure):
+    _fields_ = [("means", C.c_void_p), ("log_scales", C.c_void_p), ("quats", C.c_void_p),
+                ("opacity_logits", C.c_void_p), ("rgb", C.c_void_p), ("sh", C.c_void_p), ("sh_degree", C.c_int32)]
 
 
 class cgsr_images(C.Structure):
@@ -135,6 +141,15 @@ def lib() -> C.CDLL:
                                      C.POINTER(cgsr_adam_params), vp, vp]
     L.cgsr_autotune_tracking.argtypes = [vp, C.POINTER(cgsr_gaussians), C.c_int32, vp, C.POINTER(cgsr_camera),
                                          C.POINTER(vp), C.POINTER(vp), C.c_int32, C.POINTER(cgsr_settings), vp]
+    L.cgsr_spawn_gaussians.argtypes = [C.POINTER(cgsr_gaussian_arrays), C.c_int64, C.c_int64, C.POINTER(cgsr_camera),
+                                       vp, vp, vp, vp, C.c_float, C.c_int32, C.c_float, C.POINTER(C.c_int64), vp]
+    L.cgsr_compact_gaussians.argtypes = [C.c_int64, vp, C.POINTER(cgsr_gaussian_arrays),
+                                         C.POINTER(cgsr_gaussian_arrays), C.c_int32, C.POINTER(vp), C.POINTER(vp),
+                                         C.POINTER(C.c_int32), C.POINTER(C.c_int64), vp]
+    L.cgsr_set_densify_stats.argtypes = [vp, vp, vp]
+    L.cgsr_densify_gaussians.argtypes = [C.c_int64, vp, vp, C.c_float, C.c_float, vp,
+                                         C.POINTER(cgsr_gaussian_arrays), C.POINTER(cgsr_gaussian_arrays), C.c_int64,
+                                         C.POINTER(C.c_int64), vp]
     L.cgsr_state_check.argtypes = [vp, vp]
     L.cgsr_get_stats.argtypes = [vp, vp, C.POINTER(cgsr_stats)]
     L.cgsr_get_timings.argtypes = [vp, C.POINTER(C.c_float)]
@@ -213,6 +228,39 @@ def cgsr_mapping_objective(state: int, weights: cgsr_mapping_weights, maps, targ
 def cgsr_gaussian_adam_step(n, params: cgsr_gaussian_grads, grads: cgsr_gaussian_grads, moments, step,
                             hp: cgsr_gaussian_adam_params, stream) -> None:
     _check(lib().cgsr_gaussian_adam_step(n, C.byref(params), C.byref(grads), moments, step, C.byref(hp), stream))
+
+
+def cgsr_spawn_gaussians(dst: cgsr_gaussian_arrays, n, capacity, cam: cgsr_camera, pose, color, depth, opacity, psi,
+                         stride, init_logit, stream) -> int:
+    """Returns n plus the number spawned."""
+    out = C.c_int64(0)
+    _check(lib().cgsr_spawn_gaussians(C.byref(dst), n, capacity, C.byref(cam), pose, color, depth, opacity, psi,
+                                      stride, init_logit, C.byref(out), stream))
+    return out.value
+
+
+def cgsr_compact_gaussians(n, keep, src: cgsr_gaussian_arrays, dst: cgsr_gaussian_arrays, extra_src, extra_dst,
+                           extra_width, stream) -> int:
+    """extra_*: sequences of device pointers and widths (may be empty)."""
+    k = len(extra_src)
+    es = (C.c_void_p * max(k, 1))(*extra_src)
+    ed = (C.c_void_p * max(k, 1))(*extra_dst)
+    ew = (C.c_int32 * max(k, 1))(*extra_width)
+    out = C.c_int64(0)
+    _check(lib().cgsr_compact_gaussians(n, keep, C.byref(src), C.byref(dst), k, es, ed, ew, C.byref(out), stream))
+    return out.value
+
+
+def cgsr_set_densify_stats(state: int, grad_accum, count) -> None:
+    _check(lib().cgsr_set_densify_stats(state, grad_accum, count))
+
+
+def cgsr_densify_gaussians(n, grad_accum, count, grad_threshold, dense_scale, normals, src: cgsr_gaussian_arrays,
+                           dst: cgsr_gaussian_arrays, capacity, stream) -> int:
+    out = C.c_int64(0)
+    _check(lib().cgsr_densify_gaussians(n, grad_accum, count, grad_threshold, dense_scale, normals, C.byref(src),
+                                        C.byref(dst), capacity, C.byref(out), stream))
+    return out.value
 
 
 def cgsr_nu_prune(n, nu_sum, nu_count, tau, low_opacity, opacity_logits, nu, n_pruned, stream) -> None:

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcgsr.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["project.hip", "sort.hip", "raster.hip", "track.hip", "objective.hip", "cgsr.hip"]
+SOURCES = ["project.hip", "sort.hip", "raster.hip", "track.hip", "objective.hip", "management.hip", "cgsr.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # No floating-point contraction: the forward and backward blend evaluate alpha

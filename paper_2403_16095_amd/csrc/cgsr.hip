@@ -87,6 +87,8 @@ struct cgsr_state {
   int64_t cap_obj_pixels = 0;
   uint32_t* obj_counts = nullptr; // visible Gaussians per view (isotropy term)
   uint32_t* counters = nullptr;
+  float* dens_grad = nullptr;      // densification statistic (cgsr_set_densify_stats)
+  uint32_t* dens_count = nullptr;
   double* pose_acc = nullptr;
   unsigned long long* stats_dev = nullptr;
   uint32_t* counters_pinned = nullptr;
@@ -528,7 +530,7 @@ cgsr_status backward_impl(cgsr_state* st, int slot, bool params, bool track, con
   if (!blend_done) launch_raster_backward(rb, params, track, st->settings.bwd_pixels_per_lane, stream);
   if (timed) HIP_TRY(hipEventRecord(st->ev_bwd[1], stream));
   launch_project_backward(st->g, st->poses, rb.views, st->rec_grad, st->tiles, gp, params, st->pose_acc, dposes, step,
-                          stream);
+                          st->dens_grad, st->dens_count, stream);
   HIP_TRY(hipGetLastError());
   if (timed) HIP_TRY(hipEventRecord(st->ev_bwd[2], stream));
   st->bwd_timed = timed;
@@ -859,6 +861,131 @@ cgsr_status cgsr_gaussian_adam_step(int64_t n, const cgsr_gaussian_grads* params
   a.lr_sh_rest = sh ? hp->lr_sh_rest : 0.f;
   launch_gaussian_adam(n, a, moments, step, (hipStream_t)stream);
   HIP_TRY(hipGetLastError());
+  return CGSR_OK;
+}
+
+namespace {
+
+// Checks a writable set; colour_w receives the colour floats per Gaussian.
+cgsr_status check_arrays(const cgsr_gaussian_arrays* a, const char* what, int* colour_w) {
+  if (!a) return fail(CGSR_ERR_INVALID_ARG, "%s: NULL arrays", what);
+  if (!a->means || !a->log_scales || !a->quats || !a->opacity_logits || !(a->sh || a->rgb))
+    return fail(CGSR_ERR_INVALID_ARG, "%s: NULL parameter array", what);
+  if (a->sh && (a->sh_degree < 0 || a->sh_degree > CGSR_MAX_SH_DEGREE))
+    return fail(CGSR_ERR_INVALID_ARG, "%s: sh_degree must be in [0, %d]", what, CGSR_MAX_SH_DEGREE);
+  *colour_w = a->sh ? 3 * (a->sh_degree + 1) * (a->sh_degree + 1) : 3;
+  return CGSR_OK;
+}
+
+GaussArrays gauss_arrays(const cgsr_gaussian_arrays* a) {
+  return GaussArrays{a->means, a->log_scales, a->quats, a->opacity_logits, a->sh ? nullptr : a->rgb, a->sh};
+}
+
+// src and dst of an out-of-place pass: same colour layout, no shared array.
+cgsr_status check_src_dst(const cgsr_gaussian_arrays* src, const cgsr_gaussian_arrays* dst, const char* what,
+                          int* colour_w) {
+  int wd = 0;
+  cgsr_status s = check_arrays(src, what, colour_w);
+  if (!s) s = check_arrays(dst, what, &wd);
+  if (s) return s;
+  if ((src->sh != nullptr) != (dst->sh != nullptr) || wd != *colour_w)
+    return fail(CGSR_ERR_INVALID_ARG, "%s: src and dst differ in their colour layout", what);
+  const void* sp[6] = {src->means, src->log_scales, src->quats, src->opacity_logits, src->rgb, src->sh};
+  const void* dp[6] = {dst->means, dst->log_scales, dst->quats, dst->opacity_logits, dst->rgb, dst->sh};
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j)
+      if (sp[i] && sp[i] == dp[j]) return fail(CGSR_ERR_INVALID_ARG, "%s: dst shares an array with src", what);
+  return CGSR_OK;
+}
+
+}  // namespace
+
+cgsr_status cgsr_spawn_gaussians(const cgsr_gaussian_arrays* dst, int64_t n, int64_t capacity, const cgsr_camera* cam,
+                                 const float* pose, const float* color, const float* depth, const float* opacity,
+                                 float psi, int32_t stride, float init_logit, int64_t* n_out, void* stream) {
+  int cw = 0;
+  cgsr_status s = check_arrays(dst, "cgsr_spawn_gaussians", &cw);
+  if (s) return s;
+  if (!cam || !pose || !color || !depth || !n_out)
+    return fail(CGSR_ERR_INVALID_ARG, "cgsr_spawn_gaussians: NULL argument");
+  if (bad_camera(*cam)) return fail(CGSR_ERR_INVALID_ARG, "cgsr_spawn_gaussians: invalid camera");
+  if (n < 0 || capacity < n || capacity > INT32_MAX)
+    return fail(CGSR_ERR_INVALID_ARG, "cgsr_spawn_gaussians: need 0 <= n <= capacity <= 2^31 - 1");
+  if (stride < 1 || !(psi == psi) || !(init_logit == init_logit))
+    return fail(CGSR_ERR_INVALID_ARG, "cgsr_spawn_gaussians: stride must be >= 1, psi and init_logit finite");
+  ViewInfo vi{};
+  vi.width = cam->width;
+  vi.height = cam->height;
+  vi.fx = cam->fx;
+  vi.fy = cam->fy;
+  vi.cx = cam->cx;
+  vi.cy = cam->cy;
+  uint32_t total = 0;
+  HIP_TRY(run_spawn(gauss_arrays(dst), n, capacity, vi, pose, color, depth, opacity, psi, stride, init_logit,
+                    dst->sh ? (dst->sh_degree + 1) * (dst->sh_degree + 1) : 0, &total, (hipStream_t)stream));
+  *n_out = n + (int64_t)total;
+  if (*n_out > capacity)
+    return fail(CGSR_ERR_CAPACITY, "cgsr_spawn_gaussians: %lld Gaussians needed, capacity %lld",
+                (long long)*n_out, (long long)capacity);
+  return CGSR_OK;
+}
+
+cgsr_status cgsr_compact_gaussians(int64_t n, const uint8_t* keep, const cgsr_gaussian_arrays* src,
+                                   const cgsr_gaussian_arrays* dst, int32_t n_extra, const float* const* extra_src,
+                                   float* const* extra_dst, const int32_t* extra_width, int64_t* n_out,
+                                   void* stream) {
+  int cw = 0;
+  cgsr_status s = check_src_dst(src, dst, "cgsr_compact_gaussians", &cw);
+  if (s) return s;
+  if (!n_out || (n > 0 && !keep)) return fail(CGSR_ERR_INVALID_ARG, "cgsr_compact_gaussians: NULL argument");
+  if (n < 0 || n > INT32_MAX) return fail(CGSR_ERR_INVALID_ARG, "cgsr_compact_gaussians: need 0 <= n < 2^31");
+  if (n_extra < 0 || n_extra > kMaxExtraArrays || (n_extra > 0 && (!extra_src || !extra_dst || !extra_width)))
+    return fail(CGSR_ERR_INVALID_ARG, "cgsr_compact_gaussians: 0 .. %d extra arrays with their pointers and widths",
+                kMaxExtraArrays);
+  ExtraArrays ex{};
+  ex.n = n_extra;
+  for (int e = 0; e < n_extra; ++e) {
+    if (!extra_src[e] || !extra_dst[e] || extra_width[e] < 1 || extra_src[e] == extra_dst[e])
+      return fail(CGSR_ERR_INVALID_ARG, "cgsr_compact_gaussians: bad extra array %d", e);
+    ex.src[e] = extra_src[e];
+    ex.dst[e] = extra_dst[e];
+    ex.width[e] = extra_width[e];
+  }
+  uint32_t total = 0;
+  HIP_TRY(run_compact(n, keep, gauss_arrays(src), gauss_arrays(dst), cw, ex, &total, (hipStream_t)stream));
+  *n_out = total;
+  return CGSR_OK;
+}
+
+cgsr_status cgsr_set_densify_stats(cgsr_state* st, float* grad_accum, uint32_t* count) {
+  if (!st) return fail(CGSR_ERR_INVALID_ARG, "state is NULL");
+  if ((grad_accum == nullptr) != (count == nullptr))
+    return fail(CGSR_ERR_INVALID_ARG, "cgsr_set_densify_stats: both arrays or neither");
+  st->dens_grad = grad_accum;
+  st->dens_count = count;
+  return CGSR_OK;
+}
+
+cgsr_status cgsr_densify_gaussians(int64_t n, const float* grad_accum, const uint32_t* count, float grad_threshold,
+                                   float dense_scale, const float* normals, const cgsr_gaussian_arrays* src,
+                                   const cgsr_gaussian_arrays* dst, int64_t capacity, int64_t* n_out,
+                                   void* stream) {
+  int cw = 0;
+  cgsr_status s = check_src_dst(src, dst, "cgsr_densify_gaussians", &cw);
+  if (s) return s;
+  if (!n_out || (n > 0 && (!grad_accum || !count || !normals)))
+    return fail(CGSR_ERR_INVALID_ARG, "cgsr_densify_gaussians: NULL argument");
+  if (n < 0 || n > INT32_MAX / 3 || capacity < 0 || capacity > INT32_MAX)
+    return fail(CGSR_ERR_INVALID_ARG, "cgsr_densify_gaussians: need 0 <= n < 2^31 / 3 and 0 <= capacity < 2^31");
+  if (!(grad_threshold == grad_threshold) || !(dense_scale == dense_scale))
+    return fail(CGSR_ERR_INVALID_ARG, "cgsr_densify_gaussians: thresholds must not be NaN");
+  uint32_t t[kRankKinds] = {0, 0, 0};
+  HIP_TRY(run_densify(n, grad_accum, count, grad_threshold, dense_scale, normals, gauss_arrays(src), gauss_arrays(dst),
+                      cw, capacity, t, (hipStream_t)stream));
+  *n_out = (int64_t)t[0] + t[1] + 2 * (int64_t)t[2];
+  if (*n_out > capacity)
+    return fail(CGSR_ERR_CAPACITY, "cgsr_densify_gaussians: %lld Gaussians needed, capacity %lld",
+                (long long)*n_out, (long long)capacity);
   return CGSR_OK;
 }
 

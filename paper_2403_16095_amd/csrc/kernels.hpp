@@ -62,9 +62,37 @@ struct PoseStep {
   float* adam;    // [views][16]
   AdamParams params;
 };
+// dens_grad / dens_count (may be null): per Gaussian, += |dL/dmu| of every
+// record that reaches the image and += 1 (the densification statistic).
 void launch_project_backward(const GaussianPtrs& g, const float* poses, const ViewTable& vt, float* rec_grad,
                              const uint32_t* tiles, const GradPtrs& dg, bool param_grads, double* pose_acc,
-                             float* dposes, const PoseStep* step, hipStream_t s);
+                             float* dposes, const PoseStep* step, float* dens_grad, uint32_t* dens_count,
+                             hipStream_t s);
+
+// Gaussian management (management.hip).  Writable parameter arrays of a set
+// (colour in rgb, or sh with K coefficients per channel).
+struct GaussArrays {
+  float *means, *log_scales, *quats, *opacity_logits, *rgb, *sh;
+};
+constexpr int kMaxExtraArrays = 12;
+// Additional per-Gaussian float arrays compacted along with a set.
+struct ExtraArrays {
+  int n;
+  const float* src[kMaxExtraArrays];
+  float* dst[kMaxExtraArrays];
+  int width[kMaxExtraArrays];
+};
+constexpr int kRankKinds = 3;
+// Each runs a ranked selection and synchronises the stream to return the
+// totals: spawned pixels; kept Gaussians; (not split, cloned, split).
+hipError_t run_spawn(const GaussArrays& dst, int64_t n, int64_t capacity, const ViewInfo& cam, const float* pose,
+                     const float* color, const float* depth, const float* opacity, float psi, int stride,
+                     float init_logit, int K, uint32_t* total, hipStream_t s);
+hipError_t run_compact(int64_t n, const uint8_t* keep, const GaussArrays& src, const GaussArrays& dst, int colour_w,
+                       const ExtraArrays& extra, uint32_t* total, hipStream_t s);
+hipError_t run_densify(int64_t n, const float* grad_accum, const uint32_t* count, float threshold, float dense_scale,
+                       const float* normals, const GaussArrays& src, const GaussArrays& dst, int colour_w,
+                       int64_t capacity, uint32_t* totals, hipStream_t s);
 
 // Segmented sort: one workgroup per tile orders its segment of keys and
 // writes the record ids in depth order plus the tile's range.

@@ -440,7 +440,8 @@ __global__ __launch_bounds__(kThreads) void project_backward_kernel(GaussianPtrs
                                                                     ViewTable vt, float* rec_grad,
                                                                     const uint32_t* __restrict__ tiles,
                                                                     GradPtrs dg, int param_grads, int atomic_params,
-                                                                    double* pose_acc) {
+                                                                    double* pose_acc, float* dens_grad,
+                                                                    uint32_t* dens_count) {
   __shared__ float s_pose[4][6];
   const int v = blockIdx.y;
   const int64_t N = g.n;
@@ -454,6 +455,10 @@ __global__ __launch_bounds__(kThreads) void project_backward_kernel(GaussianPtrs
     gr[1] = make_float4(0.f, 0.f, 0.f, 0.f);
     gr[2] = make_float4(0.f, 0.f, 0.f, 0.f);
     const float dmux = g0.x, dmuy = g0.y, da = g0.z, db = g0.w, dc = g1.x, dop = g1.y, dd = g1.z;
+    if (dens_grad) {
+      atomicAdd(dens_grad + i, sqrtf(dmux * dmux + dmuy * dmuy));
+      atomicAdd(dens_count + i, 1u);
+    }
     const ViewInfo cam = vt.io[v].info;
     const float* P = poses + 12 * v;
     Proj o;
@@ -662,11 +667,12 @@ void launch_emit(const ViewTable& vt, const ProjectBufs& b, hipStream_t s) {
 
 void launch_project_backward(const GaussianPtrs& g, const float* poses, const ViewTable& vt, float* rec_grad,
                              const uint32_t* tiles, const GradPtrs& dg, bool param_grads, double* pose_acc,
-                             float* dposes, const PoseStep* step, hipStream_t s) {
+                             float* dposes, const PoseStep* step, float* dens_grad, uint32_t* dens_count,
+                             hipStream_t s) {
   const dim3 grid((unsigned)std::max<int64_t>(1, (g.n + kThreads - 1) / kThreads), (unsigned)vt.n);
   const bool pose = dposes || step;
   hipLaunchKernelGGL(project_backward_kernel, grid, dim3(kThreads), 0, s, g, poses, vt, rec_grad, tiles, dg,
-                     param_grads ? 1 : 0, vt.n > 1 ? 1 : 0, pose ? pose_acc : nullptr);
+                     param_grads ? 1 : 0, vt.n > 1 ? 1 : 0, pose ? pose_acc : nullptr, dens_grad, dens_count);
   if (pose)
     hipLaunchKernelGGL(pose_finalize_kernel, dim3(1), dim3(64), 0, s, pose_acc, dposes, vt.n,
                        step ? step->poses : nullptr, step ? step->adam : nullptr,

@@ -197,6 +197,80 @@ def render_nu(state: State, scene: dict, poses: torch.Tensor, cams, depth_obs, n
     return outs, (doms if dominant else None)
 
 
+#: Rendered-opacity threshold of Gaussian spawning (Sec. 3.3).
+SPAWN_PSI = 0.5
+GAUSSIAN_ARRAYS = ("means", "log_scales", "quats", "opacity_logits", "rgb", "sh")
+
+
+def arrays_struct(params: dict) -> B.cgsr_gaussian_arrays:
+    """Writable arrays of a Gaussian set (rows beyond the count are spare
+    capacity); ``sh`` [rows, K, 3] replaces ``rgb`` for view-dependent colour."""
+    for k in GAUSSIAN_ARRAYS:
+        if params.get(k) is not None:
+            _check_f32(k, params[k])
+    sh = params.get("sh")
+    return B.cgsr_gaussian_arrays(*[_ptr(params.get(k)) for k in GAUSSIAN_ARRAYS],
+                                  0 if sh is None else sh_degree_of(sh))
+
+
+def empty_like_set(params: dict, rows: int) -> dict:
+    """Uninitialised arrays of the same layout with ``rows`` Gaussians."""
+    return {k: torch.empty((rows,) + tuple(v.shape[1:]), dtype=torch.float32, device=v.device)
+            for k, v in params.items() if k in GAUSSIAN_ARRAYS and v is not None}
+
+
+def spawn_gaussians(params: dict, n: int, cam: dict, pose: torch.Tensor, color: torch.Tensor, depth: torch.Tensor,
+                    opacity: torch.Tensor | None = None, psi: float = SPAWN_PSI, stride: int = 1,
+                    init_logit: float = 0.0) -> int:
+    """Sec. 3.3 spawning into ``params`` (arrays with spare rows, n in use)
+    from the pixels of one RGB-D view whose rendered opacity is below psi (all
+    pixels with a depth when ``opacity`` is None).  Returns the new count."""
+    capacity = params["means"].shape[0]
+    H, W = int(cam["height"]), int(cam["width"])
+    _check_f32("color", color, (3, H, W))
+    _check_f32("depth", depth, (H, W))
+    if opacity is not None:
+        _check_f32("opacity", opacity, (H, W))
+    return B.cgsr_spawn_gaussians(arrays_struct(params), int(n), int(capacity), camera_struct(cam),
+                                  pose.reshape(12).data_ptr(), color.data_ptr(), depth.data_ptr(), _ptr(opacity),
+                                  float(psi), int(stride), float(init_logit), _stream())
+
+
+def compact_gaussians(params: dict, keep: torch.Tensor, extra=()):
+    """The Gaussians with keep != 0 (uint8 [n]) in order: returns (new arrays
+    trimmed to the kept count, list of compacted extra tensors).  ``extra``:
+    per-Gaussian float32 tensors [n, ...] compacted alike."""
+    n = params["means"].shape[0]
+    if not (keep.is_cuda and keep.dtype == torch.uint8 and keep.numel() == n and keep.is_contiguous()):
+        raise ValueError("keep must be a contiguous uint8 CUDA tensor of n entries")
+    dst = empty_like_set(params, n)
+    ex_dst = [torch.empty_like(e) for e in extra]
+    widths = [int(e.numel() // max(n, 1)) for e in extra]
+    m = B.cgsr_compact_gaussians(n, keep.data_ptr(), arrays_struct(params), arrays_struct(dst),
+                                 [e.data_ptr() for e in extra], [e.data_ptr() for e in ex_dst], widths, _stream())
+    return {k: v[:m] for k, v in dst.items()}, [e[:m] for e in ex_dst]
+
+
+def set_densify_stats(state: State, grad_accum: torch.Tensor | None, count: torch.Tensor | None):
+    """Accumulate |dL/dmu| and visibility counts of every later backward on
+    ``state`` (float32 [n], int32 [n] read as uint32); None stops."""
+    B.cgsr_set_densify_stats(state.handle, _ptr(grad_accum), _ptr(count))
+
+
+def densify_gaussians(params: dict, grad_accum: torch.Tensor, count: torch.Tensor, grad_threshold: float,
+                      dense_scale: float, normals: torch.Tensor):
+    """Clone / split densification (Sec. 3.3, kept from splatting); normals:
+    float32 [n, 2, 3] standard normal draws.  Returns the new arrays."""
+    n = params["means"].shape[0]
+    _check_f32("grad_accum", grad_accum, (n,))
+    _check_f32("normals", normals, (n, 2, 3))
+    dst = empty_like_set(params, max(2 * n, 1))
+    m = B.cgsr_densify_gaussians(n, grad_accum.data_ptr(), count.data_ptr(), float(grad_threshold),
+                                 float(dense_scale), normals.data_ptr(), arrays_struct(params), arrays_struct(dst),
+                                 max(2 * n, 1), _stream())
+    return {k: v[:m] for k, v in dst.items()}
+
+
 def nu_prune(nu_sum: torch.Tensor, nu_count: torch.Tensor, tau: float = NU_TAU, low_opacity: float = NU_LOW_OPACITY,
              opacity_logits: torch.Tensor | None = None):
     """nu of Eq. 13 from the window's sums and the tau rule of Sec. 3.2 applied

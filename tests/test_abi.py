@@ -94,3 +94,45 @@ def test_binding_raises_with_message(lib):
     with pytest.raises(B.CgsrError) as e:
         B.cgsr_tracking_loss_grad(0, 0, 0, 0, 0, 0, 1.0, 1.0, 0, 0, None, None)
     assert e.value.status == B.CGSR_ERR_INVALID_ARG
+
+
+def test_management_and_sh_argument_checks(lib):
+    ga = B.cgsr_gaussian_arrays(8, 16, 24, 32, 40, None, 0)
+    cam = B.cgsr_camera(64, 48, 60.0, 60.0, 32.0, 24.0)
+    n_out = C.c_int64(-7)
+    spawn = lambda arr, n, cap, stride=1, c=C.byref(cam): lib.cgsr_spawn_gaussians(
+        arr, n, cap, c, 8, 8, 8, None, 0.5, stride, 0.0, C.byref(n_out), None)
+    assert spawn(None, 0, 10) == B.CGSR_ERR_INVALID_ARG
+    assert spawn(C.byref(ga), 11, 10) == B.CGSR_ERR_INVALID_ARG          # n > capacity
+    assert spawn(C.byref(ga), 0, 10, stride=0) == B.CGSR_ERR_INVALID_ARG
+    assert spawn(C.byref(ga), 0, 10, c=None) == B.CGSR_ERR_INVALID_ARG
+    no_colour = B.cgsr_gaussian_arrays(8, 16, 24, 32, None, None, 0)
+    assert spawn(C.byref(no_colour), 0, 10) == B.CGSR_ERR_INVALID_ARG
+    bad_deg = B.cgsr_gaussian_arrays(8, 16, 24, 32, None, 48, 4)
+    assert spawn(C.byref(bad_deg), 0, 10) == B.CGSR_ERR_INVALID_ARG
+    assert n_out.value == -7, "a rejected call writes nothing"
+    other = B.cgsr_gaussian_arrays(108, 116, 124, 132, 140, None, 0)
+    sh_set = B.cgsr_gaussian_arrays(208, 216, 224, 232, None, 248, 1)
+    shared = B.cgsr_gaussian_arrays(108, 16, 124, 132, 140, None, 0)     # log_scales shared with ga
+    z = (C.c_void_p * 1)()
+    w = (C.c_int32 * 1)()
+    compact = lambda src, dst, n=4, keep=8, k=0: lib.cgsr_compact_gaussians(
+        n, keep, C.byref(src), C.byref(dst), k, z, z, w, C.byref(n_out), None)
+    assert compact(ga, shared) == B.CGSR_ERR_INVALID_ARG
+    assert compact(ga, sh_set) == B.CGSR_ERR_INVALID_ARG                 # colour layouts differ
+    assert compact(ga, other, keep=None) == B.CGSR_ERR_INVALID_ARG
+    assert compact(ga, other, k=13) == B.CGSR_ERR_INVALID_ARG
+    assert compact(ga, other, n=-1) == B.CGSR_ERR_INVALID_ARG
+    dens = lambda src, dst, n=4, normals=8: lib.cgsr_densify_gaussians(
+        n, 8, 8, 1e-4, 0.01, normals, C.byref(src), C.byref(dst), 10, C.byref(n_out), None)
+    assert dens(ga, other, normals=None) == B.CGSR_ERR_INVALID_ARG
+    assert dens(ga, ga) == B.CGSR_ERR_INVALID_ARG
+    assert lib.cgsr_set_densify_stats(None, 8, 8) == B.CGSR_ERR_INVALID_ARG
+    # view-dependent colour: Adam needs both sh arrays and a valid degree
+    hp = B.cgsr_gaussian_adam_params(1e-3, 1e-3, 1e-3, 1e-3, 1e-3, 0.9, 0.999, 1e-15, 1e-4, 4)
+    with_sh = B.cgsr_gaussian_grads(8, 8, 8, 8, None, 8)
+    without = B.cgsr_gaussian_grads(8, 8, 8, 8, 8, None)
+    assert lib.cgsr_gaussian_adam_step(4, C.byref(with_sh), C.byref(without), 8, 8, C.byref(hp),
+                                       None) == B.CGSR_ERR_INVALID_ARG
+    assert lib.cgsr_gaussian_adam_step(4, C.byref(with_sh), C.byref(with_sh), 8, 8, C.byref(hp),
+                                       None) == B.CGSR_ERR_INVALID_ARG   # degree 4

@@ -1,0 +1,182 @@
+"""Gaussian management (Sec. 3.3) on the HIP path vs the FP64 oracle, through
+the C ABI: spawning from an RGB-D view's unobserved pixels, order-preserving
+compaction, the densification statistic accumulated by the backward, and
+clone / split densification.  Counts and orders bit-exact, copies exact,
+computed positions within float rounding."""
+import sys
+
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+
+import oracle
+from oracle import management as M
+from paper_2403_16095_amd import synth
+from helpers import rel_l2
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+POSE = (Rotation.from_rotvec([0.1, -0.2, 0.05]).as_matrix(), np.array([0.3, -0.1, 0.5]))
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_16095_amd import rasterizer
+    return rasterizer
+
+
+def t32(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+
+
+def rgbd_view(seed, cam):
+    rng = np.random.default_rng(seed)
+    H, W = cam["height"], cam["width"]
+    color = rng.random((3, H, W)).astype(np.float32)
+    depth = rng.uniform(0.5, 4.0, (H, W)).astype(np.float32)
+    depth[rng.random((H, W)) < 0.1] = 0.0
+    opacity = rng.random((H, W)).astype(np.float32)
+    return color, depth, opacity
+
+
+def set_arrays(n_rows, sh_K=None):
+    d = dict(means=torch.zeros((n_rows, 3), device="cuda"), log_scales=torch.zeros((n_rows, 3), device="cuda"),
+             quats=torch.zeros((n_rows, 4), device="cuda"), opacity_logits=torch.zeros(n_rows, device="cuda"))
+    if sh_K is None:
+        d["rgb"] = torch.zeros((n_rows, 3), device="cuda")
+    else:
+        d["sh"] = torch.zeros((n_rows, sh_K, 3), device="cuda")
+    return d
+
+
+@pytest.mark.parametrize("cam_kind,stride,deg", [("small", 1, None), ("small", 3, 2), ("mapping", 1, None)])
+def test_spawn_matches_oracle(R, cam_kind, stride, deg):
+    cam = synth.SMALL_CAMERA if cam_kind == "small" else synth.MAPPING_CAMERA
+    say(f"case: spawn {cam['width']}x{cam['height']} stride {stride} sh {deg}")
+    color, depth, opacity = rgbd_view(1, cam)
+    ref, idx = M.spawn(color.astype(np.float64), depth.astype(np.float64), cam, POSE, opacity.astype(np.float64),
+                       init_logit=-1.5, stride=stride, sh_degree=deg)
+    n0 = 5
+    cap = n0 + len(idx) + 10
+    arr = set_arrays(cap, None if deg is None else (deg + 1) ** 2)
+    marker = arr["means"][:n0].clone().fill_(7.0)
+    arr["means"][:n0] = marker
+    n = R.spawn_gaussians(arr, n0, cam, R.pose_tensor(*POSE), t32(color), t32(depth), t32(opacity), stride=stride,
+                          init_logit=-1.5)
+    torch.cuda.synchronize()
+    assert n == n0 + len(idx)
+    assert torch.equal(arr["means"][:n0], marker), "existing Gaussians untouched"
+    got = {k: v[n0:n].cpu().numpy().astype(np.float64) for k, v in arr.items()}
+    np.testing.assert_allclose(got["means"], ref["means"], rtol=2e-6, atol=2e-6)
+    np.testing.assert_allclose(got["log_scales"], ref["log_scales"], atol=2e-6)
+    np.testing.assert_array_equal(got["quats"], ref["quats"])
+    np.testing.assert_array_equal(got["opacity_logits"], np.float32(-1.5))
+    if deg is None:
+        np.testing.assert_array_equal(got["rgb"], color.reshape(3, -1)[:, idx].T)
+    else:
+        np.testing.assert_allclose(got["sh"], ref["sh"], atol=2e-6)
+
+
+def test_spawn_first_frame_and_capacity(R):
+    cam = synth.SMALL_CAMERA
+    say("case: spawn without opacity (dense), then over capacity")
+    color, depth, _ = rgbd_view(2, cam)
+    ref, idx = M.spawn(color.astype(np.float64), depth.astype(np.float64), cam, POSE, None)
+    arr = set_arrays(len(idx))
+    assert R.spawn_gaussians(arr, 0, cam, R.pose_tensor(*POSE), t32(color), t32(depth)) == len(idx)
+    small = set_arrays(100)
+    from paper_2403_16095_amd import binding as B
+    with pytest.raises(B.CgsrError) as e:
+        R.spawn_gaussians(small, 0, cam, R.pose_tensor(*POSE), t32(color), t32(depth))
+    assert e.value.status == B.CGSR_ERR_CAPACITY
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(small["means"].cpu().numpy(), ref["means"][:100], rtol=2e-6, atol=2e-6)
+
+
+@pytest.mark.parametrize("n,sh", [(1, False), (1000, False), (100_003, True)])
+def test_compaction_matches_oracle(R, n, sh):
+    say(f"case: compaction of {n} Gaussians, sh {sh}")
+    rng = np.random.default_rng(n)
+    sc = synth.uniform_box_scene(3, n)
+    if sh:
+        sc["sh"] = synth.sh_coefficients(4, n, 3)
+        del sc["rgb"]
+    keep = (rng.random(n) < 0.6).astype(np.uint8)
+    extra = [rng.standard_normal((n, 3)).astype(np.float32), rng.standard_normal(n).astype(np.float32)]
+    out, ex = R.compact_gaussians({k: t32(v) for k, v in sc.items()}, torch.from_numpy(keep).cuda(),
+                                  [t32(e) for e in extra])
+    ref = M.compact(sc, keep)
+    for k in sc:
+        np.testing.assert_array_equal(out[k].cpu().numpy(), ref[k], err_msg=k)
+    for e, g in zip(extra, ex):
+        np.testing.assert_array_equal(g.cpu().numpy(), e[keep.astype(bool)])
+
+
+def test_densify_statistic_from_the_backward(R):
+    say("case: densification statistic, 2000 Gaussians 64x48, two backwards")
+    sc = synth.uniform_box_scene(0, 2000)
+    cam = synth.SMALL_CAMERA
+    rng = np.random.default_rng(4)
+    dimg = dict(color=rng.standard_normal((3, 48, 64)), depth=rng.standard_normal((48, 64)))
+    st = R.State()
+    n = 2000
+    acc = torch.zeros(n, device="cuda")
+    cnt = torch.zeros(n, dtype=torch.int32, device="cuda")
+    R.set_densify_stats(st, acc, cnt)
+    scd = {k: t32(v) for k, v in sc.items()}
+    for _ in range(2):
+        R.render(st, scd, R.pose_tensor(*POSE), [cam])
+        R.backward(st, [{k: t32(v) for k, v in dimg.items()}], param_grads=False)
+    R.set_densify_stats(st, None, None)
+    R.render(st, scd, R.pose_tensor(*POSE), [cam])
+    R.backward(st, [{k: t32(v) for k, v in dimg.items()}], param_grads=False)   # not counted
+    torch.cuda.synchronize()
+    ref = oracle.backward(sc, cam, POSE, None, dimg)
+    vis = oracle.project(sc, cam, POSE)["visible"] == 1
+    np.testing.assert_array_equal(cnt.cpu().numpy(), 2 * vis.astype(np.int32))
+    expect = 2 * np.linalg.norm(ref["proj_mu"], axis=1) * vis
+    e = rel_l2(acc.cpu().numpy(), expect)
+    say("statistic rel err", e)
+    assert e <= 1e-3
+
+
+@pytest.mark.parametrize("sh", [False, True])
+def test_densify_matches_oracle(R, sh):
+    say(f"case: densify 20000 Gaussians, sh {sh}")
+    n = 20_000
+    rng = np.random.default_rng(6)
+    sc = synth.uniform_box_scene(8, n)
+    if sh:
+        sc["sh"] = synth.sh_coefficients(9, n, 1)
+        del sc["rgb"]
+    grad = rng.uniform(0, 4e-3, n).astype(np.float32)
+    cnt = rng.integers(0, 6, n).astype(np.int32)
+    z = rng.standard_normal((n, 2, 3)).astype(np.float32)
+    thr, dense = 2e-4, 0.05
+    # keep the decisions clear of float rounding at their thresholds
+    stat = np.where(cnt > 0, grad / np.maximum(cnt, 1), 0)
+    smax = np.exp(sc["log_scales"].astype(np.float64)).max(1)
+    assert np.abs(stat - thr).min() > 1e-9 and np.abs(np.log(smax / dense)).min() > 1e-6
+    out = R.densify_gaussians({k: t32(v) for k, v in sc.items()}, t32(grad), torch.from_numpy(cnt).cuda(), thr,
+                              dense, t32(z))
+    ref, clone, split = M.densify({k: v.astype(np.float64) for k, v in sc.items()}, grad.astype(np.float64), cnt,
+                                  thr, dense, z.astype(np.float64))
+    say("clones", int(clone.sum()), "splits", int(split.sum()))
+    assert clone.sum() > 100 and split.sum() > 100
+    m = out["means"].shape[0]
+    assert m == ref["means"].shape[0]
+    nk, nc = int((~split).sum()), int(clone.sum())
+    for k in sc:
+        g = out[k].cpu().numpy()
+        if k in ("means", "log_scales"):
+            np.testing.assert_array_equal(g[:nk + nc], ref[k][:nk + nc].astype(np.float32), err_msg=k)
+            np.testing.assert_allclose(g[nk + nc:], ref[k][nk + nc:], rtol=1e-5, atol=2e-6, err_msg=k)
+        else:
+            np.testing.assert_array_equal(g, ref[k].astype(np.float32), err_msg=k)
