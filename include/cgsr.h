@@ -123,7 +123,9 @@ typedef struct {
                                 needed more than the capacity                    */
     int32_t n_views;
     int64_t processed;       /* (pixel, list entry) alpha evaluations of the
-                                forward blend, summed over pixels                */
+                                forward blend, summed over pixels; a pixel's list
+                                holds the Gaussians whose binning rectangle
+                                reaches its 8x8 pixel cell                       */
     int64_t blended;         /* (pixel, Gaussian) pairs actually blended          */
     int64_t walked;          /* (pixel, list entry) pairs up to each pixel's last
                                 blended Gaussian: what the backward revisits    */

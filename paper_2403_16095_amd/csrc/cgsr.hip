@@ -79,7 +79,7 @@ struct cgsr_state {
   uint32_t* sorted_vals = nullptr;
   // per pixel
   uint4* pixel_state = nullptr;
-  uint32_t* pixel_count = nullptr;
+  uint2* pixel_count = nullptr;
   float4* pixel_grad = nullptr;
   // small buffers
   float* tune_dposes = nullptr;   // [64][6] scratch pose gradients of the autotuner
@@ -191,7 +191,8 @@ cgsr_status reserve(cgsr_state* st, int64_t records, int64_t pixels, int64_t til
 }
 
 bool bad_camera(const cgsr_camera& c) {
-  return c.width < 1 || c.height < 1 || c.width > 65535 * kTile || c.height > 65535 * kTile || !(c.fx > 0.f) ||
+  // the binning rectangle is kept in 8-pixel cells of 16 bits
+  return c.width < 1 || c.height < 1 || c.width > 65535 * 8 || c.height > 65535 * 8 || !(c.fx > 0.f) ||
          !(c.fy > 0.f) || !(c.cx == c.cx) || !(c.cy == c.cy);
 }
 
@@ -242,6 +243,7 @@ RasterBufs raster_bufs(cgsr_state* st, int slot) {
   rb.ranges = st->ranges;
   rb.pixel_state = st->pixel_state;
   rb.pixel_count = st->pixel_count;
+  rb.rect = st->rect;
   rb.pixel_grad = st->pixel_grad;
   rb.rec_grad = st->rec_grad;
   rb.lambda_color = rb.lambda_depth = 0.f;

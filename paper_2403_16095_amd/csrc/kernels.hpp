@@ -19,7 +19,7 @@ constexpr int kCounterWords = 8;
 struct ProjectBufs {
   float4* rec;              // [M][3]
   uint32_t* tiles;          // [M] tiles touched (0 = culled)
-  uint2* rect;              // [M] tile rect: x = tx0 | tx1 << 16, y = ty0 | ty1 << 16
+  uint2* rect;              // [M] binning rect in 8-pixel cells: x = cx0 | cx1 << 16, y = cy0 | cy1 << 16
   uint32_t* tile_count;     // [T] pairs per tile (zero on entry; reset by the segment sort)
   uint32_t* tile_fill;      // [T] emission slots taken (zero on entry; reset by the segment sort)
   uint32_t* tile_offset;    // [T + 1] exclusive offsets of the tile segments
@@ -115,7 +115,9 @@ struct RasterBufs {
   const uint2* ranges;
   uint4* pixel_state;       // [total pixels]: final T bits, entries up to the last blended one,
                             // median position or -1, alpha evaluations
-  uint32_t* pixel_count;    // [total pixels]: Gaussians blended
+  uint2* pixel_count;       // [total pixels]: Gaussians blended, entries of the wave's list up to the
+                            // last blended one
+  const uint2* rect;        // [M] binning rect in 8-pixel cells (see ProjectBufs)
   float4* pixel_grad;       // [total pixels]: tracking-loss gradient (colour, depth)
   float* rec_grad;          // [M][kGradStride]
   ViewTable views;          // device table of the pass (forward or backward pointers)
@@ -184,7 +186,7 @@ void launch_mapping_loss(int w, int h, const float* color, const float* depth, c
 void launch_pose_adam(int n_views, float* poses, float* dposes, float* adam, const AdamParams& ap, hipStream_t s);
 
 // Statistics: visible records, alpha evaluations, blended pairs, walked entries.
-void launch_stats(const uint32_t* tiles, int64_t m, const uint4* pixel_state, const uint32_t* pixel_count,
+void launch_stats(const uint32_t* tiles, int64_t m, const uint4* pixel_state, const uint2* pixel_count,
                   int64_t pixels, unsigned long long* out4, hipStream_t s);
 
 }  // namespace cgsr

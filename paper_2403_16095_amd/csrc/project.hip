@@ -341,7 +341,9 @@ __global__ __launch_bounds__(kThreads) void project_kernel(GaussianPtrs g, const
         rec[0] = make_float4(hx, hy, (float)o.conic[0], (float)(o.conic[1] / o.conic[0]));
         rec[1] = make_float4((float)(1.0 / o.cov[2]), (float)o.opacity, (float)o.p[2], c[0]);
         rec[2] = make_float4(c[1], c[2], (float)(mux - (double)hx), (float)(muy - (double)hy));
-        b.rect[m] = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
+        const uint32_t cx0 = (uint32_t)u0 / 8u, cx1 = (uint32_t)u1 / 8u, cy0 = (uint32_t)v0 / 8u,
+                       cy1 = (uint32_t)v1 / 8u;
+        b.rect[m] = make_uint2(cx0 | (cx1 << 16), cy0 | (cy1 << 16));
       }
     }
     b.tiles[m] = ntiles;
@@ -397,10 +399,10 @@ __global__ __launch_bounds__(kThreads) void emit_kernel(ViewTable vt, ProjectBuf
     const int64_t m = (int64_t)v * N + i;
     ntiles = b.tiles[m];
     if (ntiles) {
-      const uint2 r = b.rect[m];
-      tx0 = r.x & 0xFFFF;
-      ty0 = r.y & 0xFFFF;
-      width = (r.x >> 16) - tx0 + 1;
+      const uint2 r = b.rect[m];   // 8-pixel cells, two per tile
+      tx0 = (r.x & 0xFFFF) >> 1;
+      ty0 = (r.y & 0xFFFF) >> 1;
+      width = (r.x >> 17) - tx0 + 1;
       key = ((uint64_t)float_key(b.rec[kRecF4 * m + 1].z) << 32) | (uint64_t)m;
     }
   }

@@ -8,6 +8,14 @@
 // then reads the same LDS address, a broadcast free of bank conflicts, and
 // uses it for all of its pixels.
 //
+// Each wave stages its own copy of the batch holding only the records whose
+// binning rectangle reaches one of its 8x8 quadrants (the projection keeps
+// the rectangle in 8-pixel cells), so a wave walks the list of 8x8 binning --
+// a third shorter at tracking sizes -- while the sort and the pair buffer
+// stay at 16x16.  A record left out of a wave's copy has alpha below 1/255 at
+// every one of its pixels (the rectangle bounds the support), so the results
+// are exactly those of walking the whole tile list.
+//
 // kNu (mapping renders) also keeps, per pixel, the blended Gaussian of
 // largest weight alpha T -- the pixel is "dominated" by it (Sec. 3.2,
 // Eq. 13) -- and at the end adds w (D - d)^2 and 1 to that Gaussian's
@@ -26,7 +34,7 @@
 namespace cgsr {
 namespace {
 
-constexpr int kBatch = 256;
+constexpr int kBatch = 128;   // tile-list entries staged at a time
 constexpr uint32_t kNone = 0xffffffffu;
 
 struct PixelCoord {
@@ -56,20 +64,91 @@ __device__ __forceinline__ float2 tile_origin(const ViewInfo& cam, int gtile) {
 
 __device__ __forceinline__ float sgn(float x) { return (float)((x > 0.f) - (x < 0.f)); }
 
-// The LDS batch of staged records (see stage_record) and their record ids.
+// The LDS batch of staged records (see stage_record) and their record ids,
+// one compacted copy per wave (W waves per tile), and each copy's length.
+// C.w of a staged record holds its position in the batch (as int bits).
+template <int W>
 struct Stage {
-  float4 A[kBatch], B[kBatch], C[kBatch];
-  uint32_t M[kBatch];
+  float4 A[W][kBatch], B[W][kBatch], C[W][kBatch];
+  uint32_t M[W][kBatch];
+  uint32_t cnt[W];
+  uint32_t scan[4];
 };
 
-// Stages list entries [first, first + n) of the tile; every thread calls it.
-template <int L>
-__device__ __forceinline__ void stage_batch(const RasterBufs& b, Stage& s, uint32_t first, int n, float2 org) {
+// Quadrants (q / 64 of pixel q, see pixel_of) of the tile that wave w of W
+// covers: w, w + W, ... (kPPL = 4 / W of them).
+template <int W>
+__device__ __forceinline__ bool wave_reaches(int w, uint32_t cx0, uint32_t cx1, uint32_t cy0, uint32_t cy1,
+                                             uint32_t tcx, uint32_t tcy) {
+  bool any = false;
+#pragma unroll
+  for (int k = 0; k < 4 / W; ++k) {
+    const int qd = w + k * W;
+    const uint32_t cx = tcx + (qd & 1), cy = tcy + (qd >> 1);
+    any = any || (cx0 <= cx && cx <= cx1 && cy0 <= cy && cy <= cy1);
+  }
+  return any;
+}
+
+// Stages list entries [first, first + n) of the tile, n <= kBatch, into each
+// wave's copy; every thread calls it.  (tcx, tcy): the tile's first 8-pixel
+// cell.  With one wave per tile every record reaches it.
+template <int L, int W>
+__device__ __forceinline__ void stage_batch(const RasterBufs& b, Stage<W>& s, uint32_t first, int n, float2 org,
+                                            uint32_t tcx, uint32_t tcy) {
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += L) {
-    const uint32_t m = b.vals[first + i];
-    s.M[i] = m;
-    stage_record(b.rec + (int64_t)kRecF4 * m, org.x, org.y, s.A[i], s.B[i], s.C[i]);
+  if constexpr (W == 1) {
+    for (int i = threadIdx.x; i < n; i += L) {
+      const uint32_t m = b.vals[first + i];
+      s.M[0][i] = m;
+      float4 C;
+      stage_record(b.rec + (int64_t)kRecF4 * m, org.x, org.y, s.A[0][i], s.B[0][i], C);
+      C.w = __int_as_float(i);
+      s.C[0][i] = C;
+    }
+    if (threadIdx.x == 0) s.cnt[0] = (uint32_t)n;
+  } else {
+    // L >= kBatch: one record per thread.  A byte per wave counts the
+    // records it takes; their exclusive prefix over the threads is the
+    // record's slot in that wave's copy (no byte exceeds kBatch < 256).
+    static_assert(L >= kBatch && W <= 4, "one record per thread");
+    const int i = threadIdx.x;
+    uint32_t take = 0, m = 0;
+    float4 A, B, C;
+    if (i < n) {
+      m = b.vals[first + i];
+      stage_record(b.rec + (int64_t)kRecF4 * m, org.x, org.y, A, B, C);
+      C.w = __int_as_float(i);
+      const uint2 r = b.rect[m];
+      const uint32_t cx0 = r.x & 0xFFFFu, cx1 = r.x >> 16, cy0 = r.y & 0xFFFFu, cy1 = r.y >> 16;
+#pragma unroll
+      for (int w = 0; w < W; ++w) take |= wave_reaches<W>(w, cx0, cx1, cy0, cy1, tcx, tcy) ? 1u << (8 * w) : 0u;
+    }
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    uint32_t inc = take;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const uint32_t y = __shfl_up(inc, d);
+      if (lane >= d) inc += y;
+    }
+    if (lane == kWave - 1) s.scan[wv] = inc;
+    __syncthreads();
+    uint32_t pre = inc - take, total = 0;
+#pragma unroll
+    for (int q = 0; q < L / kWave; ++q) {
+      pre += q < wv ? s.scan[q] : 0u;
+      total += s.scan[q];
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+      if ((take >> (8 * w)) & 1u) {
+        const uint32_t d = (pre >> (8 * w)) & 0xFFu;
+        s.A[w][d] = A;
+        s.B[w][d] = B;
+        s.C[w][d] = C;
+        s.M[w][d] = m;
+      }
+    if (threadIdx.x < W) s.cnt[threadIdx.x] = (total >> (8 * threadIdx.x)) & 0xFFu;
   }
   __syncthreads();
 }
@@ -81,7 +160,7 @@ struct FwdPix {
       Dmed[kPPL];
   int64_t pix[kPPL];
   int med[kPPL];
-  uint32_t last[kPPL], evaluated[kPPL], blended[kPPL];
+  uint32_t last[kPPL], evaluated[kPPL], blended[kPPL], wlast[kPPL];
   float wdom[kPPL], ddom[kPPL];   // kNu: largest weight so far and its depth
   uint32_t dom[kPPL];             // kNu: its record id, kNone if none
   bool inside[kPPL], done[kPPL];
@@ -89,11 +168,16 @@ struct FwdPix {
 
 // Front-to-back walk of the tile's list (Eq. 3-9, Eq. 10 with kTrack off).
 // On return the stage holds the last batch walked; that is the whole list when
-// it fits one batch.
+// it fits one batch.  evaluated, wlast and blended count entries of the
+// wave's own (8x8) list; last and med are positions in the tile's list.
 template <int kPPL, bool kTrack, bool kNu>
-__device__ __forceinline__ void forward_tile(const RasterBufs& b, Stage& s, int gtile, const ViewIO& io,
-                                             float2 org, uint2 range, FwdPix<kPPL>& f) {
+__device__ __forceinline__ void forward_tile(const RasterBufs& b, Stage<kTilePixels / kPPL / kWave>& s, int gtile,
+                                             const ViewIO& io, float2 org, uint2 range, FwdPix<kPPL>& f) {
   constexpr int L = kTilePixels / kPPL;
+  constexpr int W = L / kWave;
+  const int wv = threadIdx.x / kWave;
+  const uint32_t tcx = (uint32_t)org.x / 8u, tcy = (uint32_t)org.y / 8u;
+  uint32_t loc = 0;   // entries of the wave's list before this batch
   const ViewInfo& cam = io.info;
   bool lane_done = true;
 #pragma unroll
@@ -111,23 +195,26 @@ __device__ __forceinline__ void forward_tile(const RasterBufs& b, Stage& s, int 
     f.blended[k] = 0;
     f.wdom[k] = f.ddom[k] = 0.f;
     f.dom[k] = kNone;
-    f.evaluated[k] = range.y - range.x;
+    f.evaluated[k] = 0;
+    f.wlast[k] = 0;
     f.done[k] = !pc.inside;
     lane_done = lane_done && f.done[k];
   }
   for (uint32_t base = range.x; base < range.y; base += kBatch) {
     const int n = (int)min((uint32_t)kBatch, range.y - base);
-    stage_batch<L>(b, s, base, n, org);
+    stage_batch<L, W>(b, s, base, n, org, tcx, tcy);
+    const int nw = (int)s.cnt[wv];
     // The wave walks the whole batch while any of its lanes still blends;
     // lanes that are done ride along predicated off.  (A vote every few
     // records to leave early cost more issue slots than it saved: at tracking
     // sizes most pixels never reach the stop threshold.)
     if (__ballot(!lane_done) != 0ull) {
       const uint32_t off = base - range.x;
-      for (int j = 0; j < n; ++j) {
-        const float4 A = s.A[j];
-        const float4 B = s.B[j];
-        const float4 Cc = s.C[j];
+      for (int j = 0; j < nw; ++j) {
+        const float4 A = s.A[wv][j];
+        const float4 B = s.B[wv][j];
+        const float4 Cc = s.C[wv][j];
+        const uint32_t pos = off + (uint32_t)__float_as_int(Cc.w);   // position in the tile's list
         // Straight-line, predicated per lane: a lane that skips (alpha below
         // 1/255, or already done) adds exact zeros, so the results are those
         // of the branching form, without exec-mask bookkeeping per record.
@@ -141,7 +228,7 @@ __device__ __forceinline__ void forward_tile(const RasterBufs& b, Stage& s, int 
           const bool stop = hit && Tn < kTStop;
           const bool blend = hit && !stop;
           f.done[k] = f.done[k] || stop;
-          f.evaluated[k] = stop ? off + j + 1 : f.evaluated[k];
+          f.evaluated[k] = stop ? loc + j + 1 : f.evaluated[k];
           const float wgt = blend ? alpha * f.T[k] : 0.f;
           f.C0[k] = __builtin_fmaf(wgt, Cc.x, f.C0[k]);
           f.C1[k] = __builtin_fmaf(wgt, Cc.y, f.C1[k]);
@@ -153,16 +240,17 @@ __device__ __forceinline__ void forward_tile(const RasterBufs& b, Stage& s, int 
             f.U[k] = __builtin_fmaf(wgt * dz, dz, f.U[k]);
           }
           const bool first_med = blend && f.med[k] < 0 && Tn < kTMedian;
-          f.med[k] = first_med ? (int)(off + j) : f.med[k];
+          f.med[k] = first_med ? (int)pos : f.med[k];
           f.Dmed[k] = first_med ? B.z : f.Dmed[k];
           if (kNu) {
             const bool more = blend && wgt > f.wdom[k];   // strict: the first of equal maxima
             f.wdom[k] = more ? wgt : f.wdom[k];
             f.ddom[k] = more ? B.z : f.ddom[k];
-            f.dom[k] = more ? s.M[j] : f.dom[k];
+            f.dom[k] = more ? s.M[wv][j] : f.dom[k];
           }
           f.T[k] = blend ? Tn : f.T[k];
-          f.last[k] = blend ? off + j + 1 : f.last[k];
+          f.last[k] = blend ? pos + 1 : f.last[k];
+          f.wlast[k] = blend ? loc + j + 1 : f.wlast[k];
           f.blended[k] += blend ? 1u : 0u;
         }
       }
@@ -171,8 +259,12 @@ __device__ __forceinline__ void forward_tile(const RasterBufs& b, Stage& s, int 
       for (int k = 0; k < kPPL; ++k) all = all && f.done[k];
       lane_done = all;
     }
+    loc += (uint32_t)nw;
     if (__syncthreads_count(lane_done) == L) break;
   }
+  // a pixel that never stopped evaluated every entry of its wave's list
+#pragma unroll
+  for (int k = 0; k < kPPL; ++k) f.evaluated[k] = f.evaluated[k] ? f.evaluated[k] : loc;
 }
 
 // Everything the forward leaves behind: maps, saved per-pixel state, the
@@ -223,7 +315,7 @@ __device__ __forceinline__ void forward_outputs(const RasterBufs& b, int v, cons
     if (io.uncertainty) io.uncertainty[p] = f.U[k];
     b.pixel_state[cam.pixel_base + p] =
         make_uint4(__float_as_uint(f.T[k]), f.last[k], (uint32_t)f.med[k], f.evaluated[k]);
-    b.pixel_count[cam.pixel_base + p] = f.blended[k];
+    b.pixel_count[cam.pixel_base + p] = make_uint2(f.blended[k], f.wlast[k]);
     if (kNu) {
       // record id m = view * N + Gaussian index
       const int gi = f.dom[k] == kNone ? -1 : (int)(f.dom[k] - (uint32_t)v * (uint32_t)b.views.n_gauss);
@@ -268,22 +360,25 @@ __device__ __forceinline__ int block_max(uint32_t lane_max, uint32_t* s_max) {
 // colour and depth upstream gradients only.
 // staged_n > 0: the stage already holds list entries [0, staged_n).
 template <int kPPL, bool kParams, bool kTrack, bool kColor = false>
-__device__ __forceinline__ void backward_tile(const RasterBufs& b, Stage& s, uint2 range, float2 org, int nmax,
-                                              int staged_n, BwdPix<kPPL>& p) {
+__device__ __forceinline__ void backward_tile(const RasterBufs& b, Stage<kTilePixels / kPPL / kWave>& s, uint2 range,
+                                              float2 org, int nmax, int staged_n, BwdPix<kPPL>& p) {
   constexpr int L = kTilePixels / kPPL;
+  constexpr int W = L / kWave;
   const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x / kWave;
+  const uint32_t tcx = (uint32_t)org.x / 8u, tcy = (uint32_t)org.y / 8u;
   for (int end = nmax; end > 0; end -= kBatch) {
     const int start = max(0, end - kBatch);
     const int n = end - start;
-    if (!(start == 0 && end <= staged_n)) stage_batch<L>(b, s, range.x + start, n, org);
-    for (int j = n - 1; j >= 0; --j) {
-      const int pos = start + j;
-      const float4 A = s.A[j];
-      const float4 B = s.B[j];
+    if (!(start == 0 && end <= staged_n)) stage_batch<L, W>(b, s, range.x + start, n, org, tcx, tcy);
+    for (int j = (int)s.cnt[wv] - 1; j >= 0; --j) {
+      const float4 A = s.A[wv][j];
+      const float4 B = s.B[wv][j];
       float u1 = 0.f, u2 = 0.f, sxx = 0.f, sxy = 0.f, syy = 0.f, gop = 0.f, gdd = 0.f;
       float gr = 0.f, gg = 0.f, gbl = 0.f;
       bool any = false;
-      const float4 Cc = s.C[j];
+      const float4 Cc = s.C[wv][j];
+      const int pos = start + __float_as_int(Cc.w);
       // Straight-line, predicated per lane: a lane that did not blend this
       // record (past its last blended one, or alpha below 1/255) takes
       // alpha = 0, which leaves T and the behind sums exactly unchanged and
@@ -340,7 +435,7 @@ __device__ __forceinline__ void backward_tile(const RasterBufs& b, Stage& s, uin
         }
       }
       if (__ballot(any)) {
-        const uint32_t m = s.M[j];
+        const uint32_t m = s.M[wv][j];
         float* dst = b.rec_grad + (int64_t)kGradStride * m;
         // values 0-4 (u1, u2, sxx, sxy, syy) become the gradients of mu x,
         // mu y and the conic (a, b, c); the rest pass through.
@@ -382,7 +477,7 @@ __device__ __forceinline__ void backward_tile(const RasterBufs& b, Stage& s, uin
 
 template <int kPPL, bool kTrack, bool kNu>
 __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(RasterBufs b) {
-  __shared__ Stage s;
+  __shared__ Stage<kTilePixels / kPPL / kWave> s;
   const int gtile = blockIdx.x;
   const int v = view_of_tile(b.views, gtile);
   const ViewIO io = b.views.io[v];
@@ -395,7 +490,7 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(Rast
 template <int kPPL, bool kParams, bool kTrack, bool kColor>
 __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(RasterBufs b) {
   constexpr int L = kTilePixels / kPPL;
-  __shared__ Stage s;
+  __shared__ Stage<kTilePixels / kPPL / kWave> s;
   __shared__ uint32_t s_max;
   const int gtile = blockIdx.x;
   const int v = view_of_tile(b.views, gtile);
@@ -450,7 +545,7 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
 // gradient of a view-dependent colour needs).
 template <int kPPL, bool kColor>
 __global__ __launch_bounds__(kTilePixels / kPPL) void raster_track_kernel(RasterBufs b) {
-  __shared__ Stage s;
+  __shared__ Stage<kTilePixels / kPPL / kWave> s;
   __shared__ uint32_t s_max;
   const int gtile = blockIdx.x;
   const int v = view_of_tile(b.views, gtile);

@@ -155,15 +155,15 @@ __global__ void increment_kernel(uint32_t* step) { *step += 1u; }
 
 __global__ __launch_bounds__(kThreads) void stats_kernel(const uint32_t* __restrict__ tiles, int64_t m,
                                                          const uint4* __restrict__ ps,
-                                                         const uint32_t* __restrict__ count, int64_t pixels,
+                                                         const uint2* __restrict__ count, int64_t pixels,
                                                          unsigned long long* out) {
   unsigned long long vis = 0, ev = 0, bl = 0, wk = 0;
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < m; i += (int64_t)gridDim.x * kThreads)
     vis += tiles[i] != 0u;
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < pixels; i += (int64_t)gridDim.x * kThreads) {
     ev += ps[i].w;
-    wk += ps[i].y;
-    bl += count[i];
+    wk += count[i].y;
+    bl += count[i].x;
   }
   // These counters are read rarely; one atomic per lane keeps the code short.
   if (vis) atomicAdd(out, vis);
@@ -209,7 +209,7 @@ void launch_pose_adam(int n_views, float* poses, float* dposes, float* adam, con
   hipLaunchKernelGGL(pose_adam_kernel, dim3(1), dim3(64), 0, s, n_views, poses, dposes, adam, ap);
 }
 
-void launch_stats(const uint32_t* tiles, int64_t m, const uint4* pixel_state, const uint32_t* pixel_count,
+void launch_stats(const uint32_t* tiles, int64_t m, const uint4* pixel_state, const uint2* pixel_count,
                   int64_t pixels, unsigned long long* out4, hipStream_t s) {
   hipLaunchKernelGGL(stats_kernel, dim3(256), dim3(kThreads), 0, s, tiles, m, pixel_state, pixel_count, pixels,
                      out4);
