@@ -869,8 +869,13 @@ cgsr_status cgsr_gaussian_adam_step(int64_t n, const cgsr_gaussian_grads* params
 namespace {
 
 // Checks a writable set; colour_w receives the colour floats per Gaussian.
-cgsr_status check_arrays(const cgsr_gaussian_arrays* a, const char* what, int* colour_w) {
+// A set of no rows (empty) may have every array NULL; then *colour_w = 0.
+cgsr_status check_arrays(const cgsr_gaussian_arrays* a, const char* what, int* colour_w, bool empty = false) {
   if (!a) return fail(CGSR_ERR_INVALID_ARG, "%s: NULL arrays", what);
+  if (empty && !a->means && !a->log_scales && !a->quats && !a->opacity_logits && !a->rgb && !a->sh) {
+    *colour_w = 0;
+    return CGSR_OK;
+  }
   if (!a->means || !a->log_scales || !a->quats || !a->opacity_logits || !(a->sh || a->rgb))
     return fail(CGSR_ERR_INVALID_ARG, "%s: NULL parameter array", what);
   if (a->sh && (a->sh_degree < 0 || a->sh_degree > CGSR_MAX_SH_DEGREE))
@@ -884,14 +889,17 @@ GaussArrays gauss_arrays(const cgsr_gaussian_arrays* a) {
 }
 
 // src and dst of an out-of-place pass: same colour layout, no shared array.
+// src_empty / dst_empty: that side has no rows and may be all NULL.
 cgsr_status check_src_dst(const cgsr_gaussian_arrays* src, const cgsr_gaussian_arrays* dst, const char* what,
-                          int* colour_w) {
+                          int* colour_w, bool src_empty = false, bool dst_empty = false) {
   int wd = 0;
-  cgsr_status s = check_arrays(src, what, colour_w);
-  if (!s) s = check_arrays(dst, what, &wd);
+  cgsr_status s = check_arrays(src, what, colour_w, src_empty);
+  if (!s) s = check_arrays(dst, what, &wd, dst_empty);
   if (s) return s;
-  if ((src->sh != nullptr) != (dst->sh != nullptr) || wd != *colour_w)
+  const bool both = src->means && dst->means;   // neither side empty
+  if (both && ((src->sh != nullptr) != (dst->sh != nullptr) || wd != *colour_w))
     return fail(CGSR_ERR_INVALID_ARG, "%s: src and dst differ in their colour layout", what);
+  if (*colour_w == 0) *colour_w = wd;   // an empty src takes dst's layout
   const void* sp[6] = {src->means, src->log_scales, src->quats, src->opacity_logits, src->rgb, src->sh};
   const void* dp[6] = {dst->means, dst->log_scales, dst->quats, dst->opacity_logits, dst->rgb, dst->sh};
   for (int i = 0; i < 6; ++i)
@@ -906,7 +914,7 @@ cgsr_status cgsr_spawn_gaussians(const cgsr_gaussian_arrays* dst, int64_t n, int
                                  const float* pose, const float* color, const float* depth, const float* opacity,
                                  float psi, int32_t stride, float init_logit, int64_t* n_out, void* stream) {
   int cw = 0;
-  cgsr_status s = check_arrays(dst, "cgsr_spawn_gaussians", &cw);
+  cgsr_status s = check_arrays(dst, "cgsr_spawn_gaussians", &cw, capacity == 0);
   if (s) return s;
   if (!cam || !pose || !color || !depth || !n_out)
     return fail(CGSR_ERR_INVALID_ARG, "cgsr_spawn_gaussians: NULL argument");
@@ -937,7 +945,7 @@ cgsr_status cgsr_compact_gaussians(int64_t n, const uint8_t* keep, const cgsr_ga
                                    float* const* extra_dst, const int32_t* extra_width, int64_t* n_out,
                                    void* stream) {
   int cw = 0;
-  cgsr_status s = check_src_dst(src, dst, "cgsr_compact_gaussians", &cw);
+  cgsr_status s = check_src_dst(src, dst, "cgsr_compact_gaussians", &cw, n == 0, n == 0);
   if (s) return s;
   if (!n_out || (n > 0 && !keep)) return fail(CGSR_ERR_INVALID_ARG, "cgsr_compact_gaussians: NULL argument");
   if (n < 0 || n > INT32_MAX) return fail(CGSR_ERR_INVALID_ARG, "cgsr_compact_gaussians: need 0 <= n < 2^31");
@@ -973,7 +981,7 @@ cgsr_status cgsr_densify_gaussians(int64_t n, const float* grad_accum, const uin
                                    const cgsr_gaussian_arrays* dst, int64_t capacity, int64_t* n_out,
                                    void* stream) {
   int cw = 0;
-  cgsr_status s = check_src_dst(src, dst, "cgsr_densify_gaussians", &cw);
+  cgsr_status s = check_src_dst(src, dst, "cgsr_densify_gaussians", &cw, n == 0, capacity == 0);
   if (s) return s;
   if (!n_out || (n > 0 && (!grad_accum || !count || !normals)))
     return fail(CGSR_ERR_INVALID_ARG, "cgsr_densify_gaussians: NULL argument");

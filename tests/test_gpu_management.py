@@ -180,3 +180,36 @@ def test_densify_matches_oracle(R, sh):
             np.testing.assert_allclose(g[nk + nc:], ref[k][nk + nc:], rtol=1e-5, atol=2e-6, err_msg=k)
         else:
             np.testing.assert_array_equal(g, ref[k].astype(np.float32), err_msg=k)
+
+
+def test_management_edge_cases(R):
+    say("case: management edge cases")
+    cam = synth.SMALL_CAMERA
+    color, depth, opacity = rgbd_view(7, cam)
+    from paper_2403_16095_amd import binding as B
+    # nothing to spawn: every pixel observed
+    arr = set_arrays(10)
+    assert R.spawn_gaussians(arr, 4, cam, R.pose_tensor(*POSE), t32(color), t32(depth),
+                             torch.ones((48, 64), device="cuda")) == 4
+    # a full set: spawning must fail with the count needed
+    with pytest.raises(B.CgsrError) as e:
+        R.spawn_gaussians(arr, 10, cam, R.pose_tensor(*POSE), t32(color), t32(depth), t32(opacity))
+    assert e.value.status == B.CGSR_ERR_CAPACITY
+    sc = synth.uniform_box_scene(1, 500)
+    d = {k: t32(v) for k, v in sc.items()}
+    out, _ = R.compact_gaussians(d, torch.zeros(500, dtype=torch.uint8, device="cuda"))
+    assert out["means"].shape[0] == 0
+    out, _ = R.compact_gaussians(d, torch.ones(500, dtype=torch.uint8, device="cuda"))
+    for k in d:
+        assert torch.equal(out[k], d[k])
+    # no Gaussian reaches the threshold: densification is a copy
+    cnt = torch.ones(500, dtype=torch.int32, device="cuda")
+    out = R.densify_gaussians(d, torch.zeros(500, device="cuda"), cnt, 1e-4, 0.05,
+                              torch.zeros((500, 2, 3), device="cuda"))
+    for k in d:
+        assert torch.equal(out[k], d[k])
+    # an empty set
+    e0 = {k: v[:0].contiguous() for k, v in d.items()}
+    out = R.densify_gaussians(e0, torch.zeros(0, device="cuda"), cnt[:0], 1e-4, 0.05,
+                              torch.zeros((0, 2, 3), device="cuda"))
+    assert out["means"].shape[0] == 0

@@ -168,3 +168,34 @@ def test_sh_arguments_are_checked(R):
     with pytest.raises(RuntimeError):
         B.cgsr_render(R.State().handle, g, 1, R.pose_tensor(*POSE).data_ptr(), [R.camera_struct(synth.SMALL_CAMERA)],
                       None, [B.cgsr_images()], 0)
+
+
+def test_sh_batched_views_equal_sequential(R):
+    """Each (view, Gaussian) record gets the colour seen from its own camera:
+    a batched render of three views equals three single-view renders bit for
+    bit, and the batched backward equals the sum of the single-view ones."""
+    say("case: SH degree 3, three views batched vs sequential")
+    sc = sh_scene(6, 2000, 3)
+    cam = synth.SMALL_CAMERA
+    poses = [POSE, (POSE[0], POSE[1] + np.array([0.2, 0.0, 0.0])),
+             (Rotation.from_rotvec([-0.04, 0.06, 0.0]).as_matrix(), np.array([-0.1, 0.05, 0.1]))]
+    scd = {k: t32(v) for k, v in sc.items()}
+    P = torch.stack([R.pose_tensor(*p) for p in poses]).contiguous()
+    st = R.State()
+    outs = R.render(st, scd, P, [cam] * 3)
+    rng = np.random.default_rng(3)
+    dimgs = [dict(color=t32(rng.standard_normal((3, 48, 64)))) for _ in range(3)]
+    gb, dpb = R.backward(st, dimgs)
+    torch.cuda.synchronize()
+    gs = None
+    for v in range(3):
+        s1 = R.State()
+        o = R.render(s1, scd, P[v], [cam])[0]
+        for k in ("color", "depth", "opacity"):
+            assert torch.equal(o[k], outs[v][k]), (v, k)
+        g, dp = R.backward(s1, [dimgs[v]])
+        assert torch.allclose(dp[0], dpb[v], rtol=1e-4, atol=1e-6 * float(dpb[v].abs().max()))
+        gs = g if gs is None else {k: gs[k] + g[k] for k in g}
+    for k in gs:
+        e = rel_l2(gb[k].cpu().numpy(), gs[k].cpu().numpy())
+        assert e <= 1e-5, (k, e)
