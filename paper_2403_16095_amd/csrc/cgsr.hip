@@ -178,12 +178,12 @@ cgsr_status reserve(cgsr_state* st, int64_t records, int64_t pixels, int64_t til
     dev_free(st->tile_offset);
     st->cap_tiles = 0;
     if ((s = dev_alloc(&st->ranges, tiles))) return s;
-    if ((s = dev_alloc(&st->tile_count, tiles))) return s;
-    if ((s = dev_alloc(&st->tile_fill, tiles))) return s;
+    if ((s = dev_alloc(&st->tile_count, tiles * kTileCounterStride))) return s;
+    if ((s = dev_alloc(&st->tile_fill, tiles * kTileCounterStride))) return s;
     if ((s = dev_alloc(&st->tile_offset, tiles + 1))) return s;
     HIP_TRY(hipMemset(st->ranges, 0, sizeof(uint2) * (size_t)tiles));
-    HIP_TRY(hipMemset(st->tile_count, 0, sizeof(uint32_t) * (size_t)tiles));
-    HIP_TRY(hipMemset(st->tile_fill, 0, sizeof(uint32_t) * (size_t)tiles));
+    HIP_TRY(hipMemset(st->tile_count, 0, sizeof(uint32_t) * kTileCounterStride * (size_t)tiles));
+    HIP_TRY(hipMemset(st->tile_fill, 0, sizeof(uint32_t) * kTileCounterStride * (size_t)tiles));
     st->tiles_dirty = false;
     st->cap_tiles = tiles;
   }
@@ -457,8 +457,8 @@ cgsr_status render_impl(cgsr_state* st, const RenderArgs& a, hipStream_t stream)
   if (s) return s;
   if (st->tiles_dirty) {
     // A previous render stopped before its sort reset the per-tile counters.
-    launch_clear_u32(st->tile_count, st->cap_tiles, stream);
-    launch_clear_u32(st->tile_fill, st->cap_tiles, stream);
+    launch_clear_u32(st->tile_count, st->cap_tiles * kTileCounterStride, stream);
+    launch_clear_u32(st->tile_fill, st->cap_tiles * kTileCounterStride, stream);
   }
 
   const ViewTable vt{st->io[0].dev, a.n_views, (int32_t)a.g->n};

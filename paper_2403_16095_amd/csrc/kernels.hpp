@@ -16,12 +16,17 @@ enum Counter : int {
 };
 constexpr int kCounterWords = 8;
 
+// Every workgroup takes the per-tile counters by atomics; each counter sits on
+// a 128-byte line of its own so that atomics on neighbouring tiles do not queue
+// behind one another.
+constexpr int kTileCounterStride = 32;
+
 struct ProjectBufs {
   float4* rec;              // [M][3]
   uint32_t* tiles;          // [M] tiles touched (0 = culled)
   uint2* rect;              // [M] binning rect in 8-pixel cells: x = cx0 | cx1 << 16, y = cy0 | cy1 << 16
-  uint32_t* tile_count;     // [T] pairs per tile (zero on entry; reset by the segment sort)
-  uint32_t* tile_fill;      // [T] emission slots taken (zero on entry; reset by the segment sort)
+  uint32_t* tile_count;     // [T * kTileCounterStride] pairs per tile (zero on entry; reset by the segment sort)
+  uint32_t* tile_fill;      // [T * kTileCounterStride] emission slots taken (zero on entry; reset by the sort)
   uint32_t* tile_offset;    // [T + 1] exclusive offsets of the tile segments
   uint32_t* counters;       // Counter enum above
   int32_t total_tiles;

@@ -354,7 +354,7 @@ __global__ __launch_bounds__(kThreads) void project_kernel(GaussianPtrs g, const
   for (uint32_t k = threadIdx.x & 63; k < wp.total; k += 64) {
     int owner;
     const uint32_t tile = pair_tile(wp, k, cam.tiles_x, &owner);
-    atomicAdd(&b.tile_count[cam.tile_base + tile], 1u);
+    atomicAdd(&b.tile_count[(size_t)(cam.tile_base + tile) * kTileCounterStride], 1u);
   }
 }
 
@@ -367,12 +367,12 @@ __global__ __launch_bounds__(kThreads) void tile_scan_kernel(ProjectBufs b) {
   const uint32_t per = (T + kThreads - 1) / kThreads;
   const uint32_t t0 = min(T, threadIdx.x * per), t1 = min(T, t0 + per);
   uint32_t run = 0;
-  for (uint32_t t = t0; t < t1; ++t) run += b.tile_count[t];
+  for (uint32_t t = t0; t < t1; ++t) run += b.tile_count[(size_t)t * kTileCounterStride];
   uint32_t total;
   uint32_t acc = block_exclusive_scan(run, &total, s_scan);
   for (uint32_t t = t0; t < t1; ++t) {
     b.tile_offset[t] = acc;
-    acc += b.tile_count[t];
+    acc += b.tile_count[(size_t)t * kTileCounterStride];
   }
   if (threadIdx.x == 0) {
     b.tile_offset[T] = total;
@@ -423,7 +423,7 @@ __global__ __launch_bounds__(kThreads) void emit_kernel(ViewTable vt, ProjectBuf
         int owner;
         tile[j] = tile_base + pair_tile(wp, k, tiles_x, &owner);
         kk[j] = s_key[64 * wv + owner];
-        slot[j] = atomicAdd(&b.tile_fill[tile[j]], 1u);
+        slot[j] = atomicAdd(&b.tile_fill[(size_t)tile[j] * kTileCounterStride], 1u);
       }
     }
 #pragma unroll

@@ -65,8 +65,8 @@ __global__ __launch_bounds__(kThreads) void segment_sort_kernel(SegSortBufs b) {
   const uint32_t n = (uint32_t)(end - base);
   if (threadIdx.x == 0) {
     b.ranges[t] = make_uint2((uint32_t)base, (uint32_t)end);
-    b.tile_count[t] = 0u;   // reset the counters for the next render
-    b.tile_fill[t] = 0u;
+    b.tile_count[(size_t)t * kTileCounterStride] = 0u;   // reset the counters for the next render
+    b.tile_fill[(size_t)t * kTileCounterStride] = 0u;
   }
   if (n == 0) return;
   uint64_t* keys = b.keys[0] + base;
