@@ -268,9 +268,9 @@ class MappingIteration:
     def freeze_capacity(self, margin=1.25):
         """After a sizing call: fixed pair capacity, no per-call readback."""
         for k, st in enumerate(self.states):
-            pairs = st.stats().pairs
+            peak = st.stats().peak_pairs
             new = self.R.State(sync_capacity=False)
-            new.reserve(pairs=int(pairs * margin) + 4096)
+            new.reserve(tile_pairs=int(peak * margin) + 64)
             self.states[k] = new
             st.close()
 
@@ -529,8 +529,8 @@ def run_batched_tracking(args, torch, R, synth, frames=32, iters=20):
         peak = 0
         for _ in range(iters):
             step()
-            peak = max(peak, int(st.stats().pairs))
-        st.reserve(pairs=int(peak * margin) + 4096)
+            peak = max(peak, int(st.stats().peak_pairs))
+        st.reserve(tile_pairs=int(peak * margin) + 64)
         for attempt in range(3):
             graph = torch.cuda.CUDAGraph()
             side = torch.cuda.Stream()
@@ -555,7 +555,7 @@ def run_batched_tracking(args, torch, R, synth, frames=32, iters=20):
                 st.check()
             except R.B.CgsrError:
                 pass
-            st.reserve(pairs=int(s.peak_pairs * 1.25) + 4096)
+            st.reserve(tile_pairs=int(s.peak_pairs * 1.25) + 64)
         # the graph reads and writes these tensors: keep them alive with it
         return graph, st, pose, (pose0, adam)
 
@@ -723,7 +723,7 @@ def main():
         # no capacity readback: it would put a host round trip inside the
         # projection stage's events
         tst = R.State(sync_capacity=False, timing=True, fwd_ppl=fppl, bwd_ppl=bppl)
-        tst.reserve(pairs=solver.state.stats().pairs * 2)
+        tst.reserve(tile_pairs=solver.state.stats().peak_pairs * 2)
         pose = P0.clone().reshape(1, 12)
         acc = {}
         reps = 20

@@ -101,11 +101,12 @@ typedef struct {
 
 /* Library settings; cgsr_default_settings() fills the defaults. */
 typedef struct {
-    int32_t sync_capacity;   /* 1: render reads the pair count back and grows the
-                                pair buffer as needed (one host sync per render),
-                                except while its stream is being captured into a
-                                graph.  0: never syncs; the pair buffer must be
-                                large enough, see cgsr_state_reserve().          */
+    int32_t sync_capacity;   /* 1: render reads its fullest tile back and grows
+                                the per-tile pair buckets as needed (one host
+                                sync per render), except while its stream is
+                                being captured into a graph.  0: never syncs; the
+                                buckets must be large enough, see
+                                cgsr_state_reserve().                            */
     int32_t timing;          /* 1: time every stage with HIP events on the call's
                                 stream (not while it is being captured); read
                                 the durations with cgsr_get_timings()            */
@@ -118,9 +119,9 @@ typedef struct {
 typedef struct {
     int64_t visible;         /* (view, Gaussian) records that reach the image   */
     int64_t pairs;           /* (tile, Gaussian) pairs of the last render       */
-    int64_t pair_capacity;   /* pairs the state can hold                         */
+    int64_t pair_capacity;   /* pairs one tile's bucket holds                    */
     int32_t overflow;        /* 1 if a render since the last cgsr_state_check
-                                needed more than the capacity                    */
+                                had a tile needing more than its bucket          */
     int32_t n_views;
     int64_t processed;       /* (pixel, list entry) alpha evaluations of the
                                 forward blend, summed over pixels; a pixel's list
@@ -129,14 +130,16 @@ typedef struct {
     int64_t blended;         /* (pixel, Gaussian) pairs actually blended          */
     int64_t walked;          /* (pixel, list entry) pairs up to each pixel's last
                                 blended Gaussian: what the backward revisits    */
-    int64_t peak_pairs;      /* most pairs a render needed since the last
-                                cgsr_state_check                                 */
+    int64_t peak_pairs;      /* pairs of the last render's fullest tile, or, if a
+                                render since the last cgsr_state_check
+                                overflowed, the most any tile needed there      */
 } cgsr_stats;
 
 /* Stages timed when cgsr_settings.timing is set. */
 typedef enum {
-    CGSR_STAGE_PROJECT = 0,     /* EWA projection and per-tile pair counts    */
-    CGSR_STAGE_EMIT = 1,        /* (depth, record) keys into tile segments    */
+    CGSR_STAGE_PROJECT = 0,     /* EWA projection and the (depth, record) keys
+                                   into the tile buckets                      */
+    CGSR_STAGE_EMIT = 1,        /* empty: the projection emits the keys       */
     CGSR_STAGE_SORT = 2,        /* per-tile depth sort and tile ranges        */
     CGSR_STAGE_BLEND_FWD = 3,   /* front-to-back blend                        */
     CGSR_STAGE_BLEND_BWD = 4,   /* back-to-front blend backward               */
@@ -157,11 +160,13 @@ cgsr_status cgsr_state_create(const cgsr_settings *s /* NULL = defaults */, cgsr
 cgsr_status cgsr_state_destroy(cgsr_state *st);
 
 /* Grow the workspace for up to max_records (views x Gaussians), max_pixels
- * (summed over views), max_tiles (summed over views) and max_pairs; never
+ * (summed over views), max_tiles (summed over views) and max_tile_pairs
+ * (the (tile, Gaussian) pairs of one tile: every tile gets a bucket of that
+ * many, so max_tiles x max_tile_pairs must stay below 2^32); never
  * shrinks.  Allocation happens here, so a render whose sizes fit does not
  * allocate and can be captured into a HIP graph. */
 cgsr_status cgsr_state_reserve(cgsr_state *st, int64_t max_records, int64_t max_pixels,
-                               int64_t max_tiles, int64_t max_pairs);
+                               int64_t max_tiles, int64_t max_tile_pairs);
 
 /*
  * Forward render of n_views views of one Gaussian set (Sec. 3.1: EWA projection,
@@ -490,16 +495,18 @@ cgsr_status cgsr_get_stats(cgsr_state *st, void *stream, cgsr_stats *out);
 cgsr_status cgsr_get_timings(cgsr_state *st, float *ms_out);
 
 /* Debug views of the last render (device buffers owned by the state; valid
- * until the next render on it).  keys: [pairs] emitted keys, depth bits << 32
- * | record id, grouped by tile segment (unsorted within it); sorted_values:
- * [pairs] record ids in (tile, depth, record id) order; ranges: [tiles][2]
+ * until the next render on it).  keys: [tiles][pair_capacity] each tile's
+ * bucket of emitted keys, depth bits << 32 | record id (overwritten by the
+ * sort for buckets longer than 4096); sorted_values: [tiles][pair_capacity]
+ * record ids of each tile in (depth, record id) order; ranges: [tiles][2]
  * start/end into sorted_values; records: [records][12] float32 projected
  * record (mu_x, mu_y, a, k, c', opacity, depth, r, g, b, mu_x lo, mu_y lo):
  * the mean is mu + lo, and the conic (a, b, c) of Eq. 5 is kept in the
  * completed-square form a (dx + k dy)^2 + c' dy^2 with k = b / a and
  * c' = c - b^2 / a;
- * pixel_state: [pixels][4] (final T as float bits, list entries up to the
- * last blended one, median position or -1, alpha evaluations). */
+ * pixel_state: [pixels][4] (final T as float bits, tile-list entries up to
+ * the last blended one, median position in the tile list or -1, alpha
+ * evaluations: entries of the pixel's 8x8-cell list walked). */
 cgsr_status cgsr_debug_buffers(cgsr_state *st, const uint64_t **keys, const uint32_t **sorted_values,
                                const uint32_t **ranges, const float **records, const uint32_t **pixel_state);
 

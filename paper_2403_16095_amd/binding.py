@@ -187,8 +187,8 @@ def cgsr_state_destroy(state: int) -> None:
     _check(lib().cgsr_state_destroy(state))
 
 
-def cgsr_state_reserve(state: int, max_records: int, max_pixels: int, max_tiles: int, max_pairs: int) -> None:
-    _check(lib().cgsr_state_reserve(state, max_records, max_pixels, max_tiles, max_pairs))
+def cgsr_state_reserve(state: int, max_records: int, max_pixels: int, max_tiles: int, max_tile_pairs: int) -> None:
+    _check(lib().cgsr_state_reserve(state, max_records, max_pixels, max_tiles, max_tile_pairs))
 
 
 def cgsr_render(state: int, g: cgsr_gaussians, n_views: int, poses: int, cams, depth_obs, outs,

@@ -62,7 +62,9 @@ struct cgsr_state {
   int device = 0;
   cgsr_settings settings{};
   // capacities
-  int64_t cap_records = 0, cap_pixels = 0, cap_tiles = 0, cap_pairs = 0;
+  int64_t cap_records = 0, cap_pixels = 0, cap_tiles = 0;
+  int64_t cap_tile_pairs = 0;   // pairs one tile's bucket holds
+  int64_t bucket_tiles = 0;     // tiles the bucket buffers are sized for
   // per (view, Gaussian) record
   float4* rec = nullptr;
   uint32_t* tiles = nullptr;
@@ -70,11 +72,9 @@ struct cgsr_state {
   float* rec_grad = nullptr;
   // per tile
   uint32_t* tile_count = nullptr;
-  uint32_t* tile_fill = nullptr;
-  uint32_t* tile_offset = nullptr;
   uint2* ranges = nullptr;
   bool tiles_dirty = false;   // a render stopped between projection and sort
-  // per pair
+  // per-tile buckets of pairs, [bucket_tiles][cap_tile_pairs]
   uint64_t* keys[2] = {nullptr, nullptr};
   uint32_t* sorted_vals = nullptr;
   // per pixel
@@ -128,23 +128,31 @@ cgsr_status set_device(cgsr_state* st) {
   return CGSR_OK;
 }
 
-cgsr_status grow_pairs(cgsr_state* st, int64_t pairs) {
-  if (pairs <= st->cap_pairs) return CGSR_OK;
+// Buckets for cap_tiles tiles of at least tile_pairs pairs each.  Sizes are
+// kept in 32 bits on the device (tile ranges), so tiles x pairs < 2^32.
+cgsr_status grow_buckets(cgsr_state* st, int64_t tile_pairs) {
+  const int64_t cap = std::max<int64_t>(std::max<int64_t>(tile_pairs, st->cap_tile_pairs), 64);
+  if (cap == st->cap_tile_pairs && st->bucket_tiles >= st->cap_tiles) return CGSR_OK;
+  const int64_t tiles = std::max<int64_t>(st->cap_tiles, 1);
+  if (tiles * cap >= (1ll << 32))
+    return fail(CGSR_ERR_CAPACITY, "%lld tiles of %lld pairs exceed 2^32 bucket slots", (long long)tiles,
+                (long long)cap);
   HIP_TRY(hipDeviceSynchronize());
   dev_free(st->keys[0]);
   dev_free(st->keys[1]);
   dev_free(st->sorted_vals);
-  st->cap_pairs = 0;
-  const int64_t cap = std::max<int64_t>(pairs, 1);
+  st->cap_tile_pairs = 0;
+  st->bucket_tiles = 0;
   cgsr_status s;
-  if ((s = dev_alloc(&st->keys[0], cap))) return s;
-  if ((s = dev_alloc(&st->keys[1], cap))) return s;
-  if ((s = dev_alloc(&st->sorted_vals, cap))) return s;
-  st->cap_pairs = cap;
+  if ((s = dev_alloc(&st->keys[0], tiles * cap))) return s;
+  if ((s = dev_alloc(&st->keys[1], tiles * cap))) return s;
+  if ((s = dev_alloc(&st->sorted_vals, tiles * cap))) return s;
+  st->cap_tile_pairs = cap;
+  st->bucket_tiles = tiles;
   return CGSR_OK;
 }
 
-cgsr_status reserve(cgsr_state* st, int64_t records, int64_t pixels, int64_t tiles, int64_t pairs) {
+cgsr_status reserve(cgsr_state* st, int64_t records, int64_t pixels, int64_t tiles, int64_t tile_pairs) {
   if (records > st->cap_records || pixels > st->cap_pixels || tiles > st->cap_tiles)
     HIP_TRY(hipDeviceSynchronize());
   cgsr_status s;
@@ -174,20 +182,15 @@ cgsr_status reserve(cgsr_state* st, int64_t records, int64_t pixels, int64_t til
   if (tiles > st->cap_tiles) {
     dev_free(st->ranges);
     dev_free(st->tile_count);
-    dev_free(st->tile_fill);
-    dev_free(st->tile_offset);
     st->cap_tiles = 0;
     if ((s = dev_alloc(&st->ranges, tiles))) return s;
     if ((s = dev_alloc(&st->tile_count, tiles * kTileCounterStride))) return s;
-    if ((s = dev_alloc(&st->tile_fill, tiles * kTileCounterStride))) return s;
-    if ((s = dev_alloc(&st->tile_offset, tiles + 1))) return s;
     HIP_TRY(hipMemset(st->ranges, 0, sizeof(uint2) * (size_t)tiles));
     HIP_TRY(hipMemset(st->tile_count, 0, sizeof(uint32_t) * kTileCounterStride * (size_t)tiles));
-    HIP_TRY(hipMemset(st->tile_fill, 0, sizeof(uint32_t) * kTileCounterStride * (size_t)tiles));
     st->tiles_dirty = false;
     st->cap_tiles = tiles;
   }
-  return grow_pairs(st, pairs);
+  return grow_buckets(st, tile_pairs);
 }
 
 bool bad_camera(const cgsr_camera& c) {
@@ -227,12 +230,11 @@ ProjectBufs project_bufs(cgsr_state* st) {
   b.tiles = st->tiles;
   b.rect = st->rect;
   b.tile_count = st->tile_count;
-  b.tile_fill = st->tile_fill;
-  b.tile_offset = st->tile_offset;
   b.counters = st->counters;
   b.total_tiles = st->total_tiles;
   b.keys = st->keys[0];
-  b.pair_cap = st->cap_pairs;
+  b.tile_cap = (uint32_t)st->cap_tile_pairs;
+  b.flag_cap = b.tile_cap;
   return b;
 }
 
@@ -301,14 +303,15 @@ cgsr_status cgsr_state_create(const cgsr_settings* s, cgsr_state** out) {
     if (!r && hipEventCreateWithFlags(&st->io[k].event, hipEventDisableTiming) != hipSuccess)
       r = fail(CGSR_ERR_HIP, "hipEventCreate failed");
   }
-  if (!r) r = dev_alloc(&st->stats_dev, 4);
+  if (!r) r = dev_alloc(&st->stats_dev, 6);
   if (!r) r = dev_alloc(&st->tune_dposes, 6 * CGSR_MAX_VIEWS);
   if (!r) r = dev_alloc(&st->obj_counts, CGSR_MAX_VIEWS);
   for (auto& ev : st->ev_fwd)
     if (!r && hipEventCreate(&ev) != hipSuccess) r = fail(CGSR_ERR_HIP, "hipEventCreate failed");
   for (auto& ev : st->ev_bwd)
     if (!r && hipEventCreate(&ev) != hipSuccess) r = fail(CGSR_ERR_HIP, "hipEventCreate failed");
-  if (!r && hipHostMalloc((void**)&st->counters_pinned, sizeof(uint32_t) * 4, hipHostMallocDefault) != hipSuccess)
+  if (!r && hipHostMalloc((void**)&st->counters_pinned, sizeof(uint32_t) * kCounterWords,
+                                 hipHostMallocDefault) != hipSuccess)
     r = fail(CGSR_ERR_OOM, "pinned allocation failed");
   if (r) {
     cgsr_state_destroy(st);
@@ -328,8 +331,7 @@ cgsr_status cgsr_state_destroy(cgsr_state* st) {
   dev_free(st->rect);
   dev_free(st->rec_grad);
   dev_free(st->tile_count);
-  dev_free(st->tile_fill);
-  dev_free(st->tile_offset);
+
   dev_free(st->ranges);
   dev_free(st->keys[0]);
   dev_free(st->keys[1]);
@@ -359,14 +361,14 @@ cgsr_status cgsr_state_destroy(cgsr_state* st) {
 }
 
 cgsr_status cgsr_state_reserve(cgsr_state* st, int64_t max_records, int64_t max_pixels, int64_t max_tiles,
-                               int64_t max_pairs) {
+                               int64_t max_tile_pairs) {
   if (!st) return fail(CGSR_ERR_INVALID_ARG, "state is NULL");
-  if (max_records < 0 || max_pixels < 0 || max_tiles < 0 || max_pairs < 0 || max_records >= (1ll << 32) ||
-      max_pairs >= (1ll << 32) || max_tiles >= INT32_MAX || max_pixels >= INT32_MAX)
+  if (max_records < 0 || max_pixels < 0 || max_tiles < 0 || max_tile_pairs < 0 || max_records >= (1ll << 32) ||
+      max_tile_pairs >= (1ll << 32) || max_tiles >= INT32_MAX || max_pixels >= INT32_MAX)
     return fail(CGSR_ERR_INVALID_ARG, "reserve: sizes out of range");
   cgsr_status s = set_device(st);
   if (s) return s;
-  return reserve(st, max_records, max_pixels, max_tiles, max_pairs);
+  return reserve(st, max_records, max_pixels, max_tiles, max_tile_pairs);
 }
 
 }  // extern "C"
@@ -431,7 +433,7 @@ struct RenderArgs {
   bool fused = false;  // tracking: run the pose-only blend backward in the same launch
 };
 
-// Projection -> tile-count scan -> emission -> segment sort -> blend.
+// Projection with emission into tile buckets -> segment sort -> blend.
 cgsr_status render_impl(cgsr_state* st, const RenderArgs& a, hipStream_t stream) {
   cgsr_status s = set_device(st);
   if (s) return s;
@@ -458,7 +460,7 @@ cgsr_status render_impl(cgsr_state* st, const RenderArgs& a, hipStream_t stream)
   if (st->tiles_dirty) {
     // A previous render stopped before its sort reset the per-tile counters.
     launch_clear_u32(st->tile_count, st->cap_tiles * kTileCounterStride, stream);
-    launch_clear_u32(st->tile_fill, st->cap_tiles * kTileCounterStride, stream);
+    launch_clear_u32(st->counters + kCntRenderPeak, 1, stream);
   }
 
   const ViewTable vt{st->io[0].dev, a.n_views, (int32_t)a.g->n};
@@ -472,33 +474,39 @@ cgsr_status render_impl(cgsr_state* st, const RenderArgs& a, hipStream_t stream)
   st->tiles_dirty = true;
   ProjectBufs pb = project_bufs(st);
   const bool grow = st->settings.sync_capacity && !in_capture;
-  // A render that grows the pair buffer itself must not raise the overflow
-  // flag at the projection's count: it compares against no limit there.
-  if (grow) pb.pair_cap = INT64_MAX;
+  // A render that grows the buckets itself raises no overflow flag: it reads
+  // the render's fullest tile back and, if that did not fit, grows the
+  // buckets and projects again.
+  if (grow) pb.flag_cap = UINT32_MAX;
   launch_project(st->g, a.poses, vt, pb, stream);
   HIP_TRY(hipGetLastError());
   if (grow) {
-    HIP_TRY(hipMemcpyAsync(st->counters_pinned, st->counters, sizeof(uint32_t) * 2, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(st->counters_pinned, st->counters, sizeof(uint32_t) * kCounterWords,
+                           hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
-    const int64_t need = st->counters_pinned[kCntPairs];
-    if (need > st->cap_pairs) {
-      s = grow_pairs(st, std::max<int64_t>(need + need / 4, 1 << 16));
+    const int64_t need = st->counters_pinned[kCntRenderPeak];
+    if (need > st->cap_tile_pairs) {
+      s = grow_buckets(st, need + need / 4);
       if (s) return s;
+      launch_clear_u32(st->tile_count, (int64_t)st->total_tiles * kTileCounterStride, stream);
+      launch_clear_u32(st->counters + kCntRenderPeak, 1, stream);
+      pb = project_bufs(st);
+      pb.flag_cap = UINT32_MAX;
+      launch_project(st->g, a.poses, vt, pb, stream);
+      HIP_TRY(hipGetLastError());
     }
-    pb = project_bufs(st);
   }
+  // the emission is part of the projection: its stage is empty
   if ((s = mark(CGSR_STAGE_EMIT))) return s;
-  launch_emit(vt, pb, stream);
   if ((s = mark(CGSR_STAGE_SORT))) return s;
   SegSortBufs sb;
   sb.keys[0] = st->keys[0];
   sb.keys[1] = st->keys[1];
   sb.sorted_vals = st->sorted_vals;
-  sb.tile_offset = st->tile_offset;
   sb.tile_count = st->tile_count;
-  sb.tile_fill = st->tile_fill;
   sb.ranges = st->ranges;
-  sb.cap = st->cap_pairs;
+  sb.counters = st->counters;
+  sb.cap = (uint32_t)st->cap_tile_pairs;
   launch_segment_sort(sb, st->total_tiles, stream);
   HIP_TRY(hipGetLastError());
   st->tiles_dirty = false;
@@ -1011,7 +1019,8 @@ cgsr_status cgsr_state_check(cgsr_state* st, void* stream) {
   launch_clear_u32(st->counters + kCntOverflow, 2, (hipStream_t)stream);
   HIP_TRY(hipGetLastError());
   if (overflow)
-    return fail(CGSR_ERR_CAPACITY, "a render needed %u pairs, capacity is %lld", peak, (long long)st->cap_pairs);
+    return fail(CGSR_ERR_CAPACITY, "a tile needed %u pairs, the buckets hold %lld", peak,
+                (long long)st->cap_tile_pairs);
   return CGSR_OK;
 }
 
@@ -1021,18 +1030,22 @@ cgsr_status cgsr_get_stats(cgsr_state* st, void* stream_, cgsr_stats* out) {
   cgsr_status s = set_device(st);
   if (s) return s;
   std::memset(out, 0, sizeof(*out));
-  out->pair_capacity = st->cap_pairs;
+  out->pair_capacity = st->cap_tile_pairs;
   out->n_views = st->n_views;
   if (!st->have_forward) return CGSR_OK;
-  unsigned long long host[4];
-  launch_clear_u32(reinterpret_cast<uint32_t*>(st->stats_dev), 8, stream);
-  launch_stats(st->tiles, st->records, st->pixel_state, st->pixel_count, st->total_pixels, st->stats_dev, stream);
-  HIP_TRY(hipMemcpyAsync(st->counters_pinned, st->counters, sizeof(uint32_t) * 3, hipMemcpyDeviceToHost, stream));
+  unsigned long long host[6];
+  launch_clear_u32(reinterpret_cast<uint32_t*>(st->stats_dev), 12, stream);
+  launch_stats(st->tiles, st->records, st->pixel_state, st->pixel_count, st->total_pixels, st->ranges,
+               st->total_tiles, st->stats_dev, stream);
+  HIP_TRY(hipMemcpyAsync(st->counters_pinned, st->counters, sizeof(uint32_t) * kCounterWords,
+                         hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipMemcpyAsync(host, st->stats_dev, sizeof(host), hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
-  out->pairs = st->counters_pinned[kCntPairs];
+  out->pairs = (int64_t)host[4];
   out->overflow = (int32_t)st->counters_pinned[kCntOverflow];
-  out->peak_pairs = st->counters_pinned[kCntPeak];
+  // the last render's fullest tile, or the most any tile needed since the
+  // last check if that overflowed
+  out->peak_pairs = std::max<int64_t>((int64_t)host[5], st->counters_pinned[kCntPeak]);
   out->visible = (int64_t)host[0];
   out->processed = (int64_t)host[1];
   out->blended = (int64_t)host[2];

@@ -10,9 +10,9 @@ namespace cgsr {
 
 // Counters kept in device memory, one block of them per state.
 enum Counter : int {
-  kCntPairs = 0,        // (tile, Gaussian) pairs of the last render
-  kCntOverflow = 1,     // 1 if a render since the last check exceeded the capacity
-  kCntPeak = 2,         // most pairs any render needed since the last check
+  kCntOverflow = 1,     // 1 if a render since the last check had a tile over its bucket
+  kCntPeak = 2,         // most pairs an overflowing tile needed since the last check
+  kCntRenderPeak = 4,   // most pairs an overflowing tile needs in the render in flight (reset by the sort)
 };
 constexpr int kCounterWords = 8;
 
@@ -26,12 +26,11 @@ struct ProjectBufs {
   uint32_t* tiles;          // [M] tiles touched (0 = culled)
   uint2* rect;              // [M] binning rect in 8-pixel cells: x = cx0 | cx1 << 16, y = cy0 | cy1 << 16
   uint32_t* tile_count;     // [T * kTileCounterStride] pairs per tile (zero on entry; reset by the segment sort)
-  uint32_t* tile_fill;      // [T * kTileCounterStride] emission slots taken (zero on entry; reset by the sort)
-  uint32_t* tile_offset;    // [T + 1] exclusive offsets of the tile segments
   uint32_t* counters;       // Counter enum above
   int32_t total_tiles;
-  uint64_t* keys;           // [cap] emitted pair keys: depth bits << 32 | record id
-  int64_t pair_cap;
+  uint64_t* keys;           // [T][tile_cap] each tile's bucket of pair keys: depth bits << 32 | record id
+  uint32_t tile_cap;        // pairs a bucket holds (later ones are dropped)
+  uint32_t flag_cap;        // a tile needing more raises the overflow flag
 };
 
 struct GaussianPtrs {
@@ -54,10 +53,10 @@ struct GradPtrs {
   float* sh;
 };
 
-// Projection (one lane per (view, Gaussian)) followed by the tile-count scan.
+// Projection (one lane per (view, Gaussian)) with the emission of every
+// (tile, Gaussian) pair into its tile's bucket.
 void launch_project(const GaussianPtrs& g, const float* poses, const ViewTable& vt, const ProjectBufs& b,
                     hipStream_t s);
-void launch_emit(const ViewTable& vt, const ProjectBufs& b, hipStream_t s);
 // Chain rule from the per-record projected gradients to the parameters and
 // the poses.  pose_acc: device double[views][6] scratch, zero on entry and
 // left zero on exit; dposes (+=) may be null.
@@ -99,16 +98,15 @@ hipError_t run_densify(int64_t n, const float* grad_accum, const uint32_t* count
                        const float* normals, const GaussArrays& src, const GaussArrays& dst, int colour_w,
                        int64_t capacity, uint32_t* totals, hipStream_t s);
 
-// Segmented sort: one workgroup per tile orders its segment of keys and
+// Segmented sort: one workgroup per tile orders its bucket of keys and
 // writes the record ids in depth order plus the tile's range.
 struct SegSortBufs {
-  uint64_t* keys[2];        // [cap] emitted keys, and scratch for long segments
-  uint32_t* sorted_vals;    // [cap] record ids in (tile, depth, id) order
-  const uint32_t* tile_offset;  // [T + 1]
-  uint32_t* tile_count;     // [T] reset to zero here
-  uint32_t* tile_fill;      // [T] reset to zero here
+  uint64_t* keys[2];        // [T][cap] the buckets, and scratch for long segments
+  uint32_t* sorted_vals;    // [T][cap] record ids in (depth, id) order
+  uint32_t* tile_count;     // [T * kTileCounterStride] read, then reset to zero here
   uint2* ranges;            // [T]
-  int64_t cap;
+  uint32_t* counters;       // resets kCntRenderPeak
+  uint32_t cap;
 };
 void launch_segment_sort(const SegSortBufs& b, int32_t total_tiles, hipStream_t s);
 // Fill n uint32 with zero (a kernel, so it can sit in a captured graph).
@@ -190,8 +188,9 @@ void launch_mapping_loss(int w, int h, const float* color, const float* depth, c
                          float* loss, hipStream_t s);
 void launch_pose_adam(int n_views, float* poses, float* dposes, float* adam, const AdamParams& ap, hipStream_t s);
 
-// Statistics: visible records, alpha evaluations, blended pairs, walked entries.
+// Statistics: visible records, alpha evaluations, blended pairs, walked
+// entries, (tile, record) pairs and the fullest tile's pairs, added into out6.
 void launch_stats(const uint32_t* tiles, int64_t m, const uint4* pixel_state, const uint2* pixel_count,
-                  int64_t pixels, unsigned long long* out4, hipStream_t s);
+                  int64_t pixels, const uint2* ranges, int64_t n_tiles, unsigned long long* out6, hipStream_t s);
 
 }  // namespace cgsr

@@ -1,6 +1,7 @@
-// Per-(view, Gaussian) projection (Sec. 3.1, Eq. 1-2), pair emission for the
-// tile sort, and the chain rule back from the projected quantities to the
-// Gaussian parameters and the camera pose.
+// Per-(view, Gaussian) projection (Sec. 3.1, Eq. 1-2), pair emission into
+// fixed-size per-tile buckets for the tile sort (no global scan: a returning
+// atomic on the tile's count is the pair's slot), and the chain rule back from
+// the projected quantities to the Gaussian parameters and the camera pose.
 //
 // Grid layout: blockIdx.y = view, blockIdx.x covers the Gaussians, so every
 // workgroup sees one view and reads its camera from the view table with
@@ -13,29 +14,6 @@ namespace cgsr {
 namespace {
 
 constexpr int kThreads = 256;
-
-// Exclusive prefix sum over the 256 threads of a workgroup; *total gets the sum.
-__device__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* total, uint32_t* lds4) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  uint32_t inc = x;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t y = __shfl_up(inc, d);
-    if (lane >= d) inc += y;
-  }
-  if (lane == 63) lds4[w] = inc;
-  __syncthreads();
-  uint32_t base = 0, tot = 0;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const uint32_t t = lds4[k];
-    base += (k < w) ? t : 0u;
-    tot += t;
-  }
-  __syncthreads();
-  *total = tot;
-  return base + inc - x;
-}
 
 // Rotation matrix (row-major) of the unit quaternion (w, x, y, z).
 __device__ __forceinline__ void quat_rot(double w, double x, double y, double z, double R[9]) {
@@ -298,11 +276,13 @@ __device__ __forceinline__ void sh_colour(const GaussianPtrs& g, int64_t i, cons
 __global__ __launch_bounds__(kThreads) void project_kernel(GaussianPtrs g, const float* __restrict__ poses,
                                                            ViewTable vt, ProjectBufs b) {
   __shared__ uint32_t s_off[kThreads], s_org[kThreads], s_wid[kThreads];
+  __shared__ uint64_t s_key[kThreads];
   const int v = blockIdx.y;
   const int64_t N = g.n;
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const ViewInfo cam = vt.io[v].info;
   uint32_t ntiles = 0, tx0 = 0, ty0 = 0, width = 1;
+  uint64_t key = 0;
   if (i < N) {
     const float* P = poses + 12 * v;
     const int64_t m = (int64_t)v * N + i;
@@ -344,75 +324,22 @@ __global__ __launch_bounds__(kThreads) void project_kernel(GaussianPtrs g, const
         const uint32_t cx0 = (uint32_t)u0 / 8u, cx1 = (uint32_t)u1 / 8u, cy0 = (uint32_t)v0 / 8u,
                        cy1 = (uint32_t)v1 / 8u;
         b.rect[m] = make_uint2(cx0 | (cx1 << 16), cy0 | (cy1 << 16));
+        // key = float bits of the camera depth (positive, so the bits order
+        // like the values) << 32 | record id
+        key = ((uint64_t)float_key((float)o.p[2]) << 32) | (uint64_t)m;
       }
     }
     b.tiles[m] = ntiles;
   }
-  // per-tile pair counts, the wave's pairs spread over its lanes
+  // Emission: the wave's pairs spread over its lanes, each taking a slot in
+  // its tile's bucket with a returning atomic -- up to kBatchPairs before
+  // using any, so a lane waits once per batch -- and writing its key there.
   const int wv = threadIdx.x >> 6;
-  const WavePairs wp = wave_pairs(ntiles, tx0, ty0, width, s_off + 64 * wv, s_org + 64 * wv, s_wid + 64 * wv);
-  for (uint32_t k = threadIdx.x & 63; k < wp.total; k += 64) {
-    int owner;
-    const uint32_t tile = pair_tile(wp, k, cam.tiles_x, &owner);
-    atomicAdd(&b.tile_count[(size_t)(cam.tile_base + tile) * kTileCounterStride], 1u);
-  }
-}
-
-// Exclusive scan of the per-tile pair counts into segment offsets, one
-// workgroup, each lane taking a contiguous run of tiles; also records the
-// pair total and whether it overflows the pair buffer.
-__global__ __launch_bounds__(kThreads) void tile_scan_kernel(ProjectBufs b) {
-  __shared__ uint32_t s_scan[4];
-  const uint32_t T = (uint32_t)b.total_tiles;
-  const uint32_t per = (T + kThreads - 1) / kThreads;
-  const uint32_t t0 = min(T, threadIdx.x * per), t1 = min(T, t0 + per);
-  uint32_t run = 0;
-  for (uint32_t t = t0; t < t1; ++t) run += b.tile_count[(size_t)t * kTileCounterStride];
-  uint32_t total;
-  uint32_t acc = block_exclusive_scan(run, &total, s_scan);
-  for (uint32_t t = t0; t < t1; ++t) {
-    b.tile_offset[t] = acc;
-    acc += b.tile_count[(size_t)t * kTileCounterStride];
-  }
-  if (threadIdx.x == 0) {
-    b.tile_offset[T] = total;
-    // sticky until cgsr_state_check reads them, so a captured loop of
-    // renders reports any overflow, not only its last one
-    b.counters[kCntPairs] = total;
-    if ((int64_t)total > b.pair_cap) b.counters[kCntOverflow] = 1u;
-    b.counters[kCntPeak] = max(b.counters[kCntPeak], total);
-  }
-}
-
-// Drops every (tile, record) pair into its tile's segment at a slot taken
-// with an atomic: key = float bits of the camera depth (positive, so the bits
-// order like the values) << 32 | record id.
-__global__ __launch_bounds__(kThreads) void emit_kernel(ViewTable vt, ProjectBufs b, int64_t N) {
-  __shared__ uint32_t s_off[kThreads], s_org[kThreads], s_wid[kThreads];
-  __shared__ uint64_t s_key[kThreads];
-  const int v = blockIdx.y;
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  const int wv = threadIdx.x >> 6;
-  uint32_t ntiles = 0, tx0 = 0, ty0 = 0, width = 1;
-  uint64_t key = 0;
-  if (i < N) {
-    const int64_t m = (int64_t)v * N + i;
-    ntiles = b.tiles[m];
-    if (ntiles) {
-      const uint2 r = b.rect[m];   // 8-pixel cells, two per tile
-      tx0 = (r.x & 0xFFFF) >> 1;
-      ty0 = (r.y & 0xFFFF) >> 1;
-      width = (r.x >> 17) - tx0 + 1;
-      key = ((uint64_t)float_key(b.rec[kRecF4 * m + 1].z) << 32) | (uint64_t)m;
-    }
-  }
+  const uint32_t lane = threadIdx.x & 63;
   s_key[threadIdx.x] = key;
   const WavePairs wp = wave_pairs(ntiles, tx0, ty0, width, s_off + 64 * wv, s_org + 64 * wv, s_wid + 64 * wv);
-  const int32_t tile_base = vt.io[v].info.tile_base, tiles_x = vt.io[v].info.tiles_x;
-  // Take the slots of up to 8 pairs before using any, so a lane waits for
-  // its returning atomics once per 8 pairs rather than once per pair.
   constexpr uint32_t kBatchPairs = 8;
-  const uint32_t lane = threadIdx.x & 63;
+  uint32_t lost = 0;   // one past the fullest slot of a pair that found its bucket full
   for (uint32_t k0 = lane; k0 < wp.total; k0 += 64 * kBatchPairs) {
     uint32_t tile[kBatchPairs], slot[kBatchPairs];
     uint64_t kk[kBatchPairs];
@@ -421,16 +348,27 @@ __global__ __launch_bounds__(kThreads) void emit_kernel(ViewTable vt, ProjectBuf
       const uint32_t k = k0 + 64 * j;
       if (k < wp.total) {
         int owner;
-        tile[j] = tile_base + pair_tile(wp, k, tiles_x, &owner);
+        tile[j] = cam.tile_base + pair_tile(wp, k, cam.tiles_x, &owner);
         kk[j] = s_key[64 * wv + owner];
-        slot[j] = atomicAdd(&b.tile_fill[(size_t)tile[j] * kTileCounterStride], 1u);
+        slot[j] = atomicAdd(&b.tile_count[(size_t)tile[j] * kTileCounterStride], 1u);
       }
     }
 #pragma unroll
     for (uint32_t j = 0; j < kBatchPairs; ++j) {
       if (k0 + 64 * j >= wp.total) break;
-      const uint64_t pos = (uint64_t)b.tile_offset[tile[j]] + slot[j];
-      if (pos < (uint64_t)b.pair_cap) b.keys[pos] = kk[j];
+      if (slot[j] < b.tile_cap) b.keys[(uint64_t)tile[j] * b.tile_cap + slot[j]] = kk[j];
+      else lost = max(lost, slot[j] + 1u);
+    }
+  }
+  // Only a pair that found its bucket full reports, so the counters see no
+  // atomics in a render that fits: the largest such slot is the count the
+  // fullest bucket needs, for this render and (above flag_cap) sticky until
+  // the next check, with the overflow flag.
+  if (lost) {
+    atomicMax(&b.counters[kCntRenderPeak], lost);
+    if (lost > b.flag_cap) {
+      atomicMax(&b.counters[kCntPeak], lost);
+      b.counters[kCntOverflow] = 1u;
     }
   }
 }
@@ -658,13 +596,6 @@ void launch_project(const GaussianPtrs& g, const float* poses, const ViewTable& 
                     hipStream_t s) {
   const dim3 grid((unsigned)std::max<int64_t>(1, (g.n + kThreads - 1) / kThreads), (unsigned)vt.n);
   hipLaunchKernelGGL(project_kernel, grid, dim3(kThreads), 0, s, g, poses, vt, b);
-  hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(kThreads), 0, s, b);
-}
-
-void launch_emit(const ViewTable& vt, const ProjectBufs& b, hipStream_t s) {
-  const int64_t n = vt.n_gauss;
-  const dim3 grid((unsigned)std::max<int64_t>(1, (n + kThreads - 1) / kThreads), (unsigned)vt.n);
-  hipLaunchKernelGGL(emit_kernel, grid, dim3(kThreads), 0, s, vt, b, n);
 }
 
 void launch_project_backward(const GaussianPtrs& g, const float* poses, const ViewTable& vt, float* rec_grad,

@@ -1,7 +1,7 @@
 // Depth order within each 16x16 tile -- the pre-sort of Sec. 3.1 -- as a
-// segmented sort: the projection counted each tile's pairs and the emission
-// dropped every (depth | record) key into its tile's segment at an atomic
-// slot, so one workgroup per tile now sorts its own segment.
+// segmented sort: the projection dropped every (depth | record) key into its
+// tile's fixed-size bucket at an atomic slot, so one workgroup per tile now
+// sorts its own bucket.
 //
 // Keys are depth bits << 32 | record id, unique within a tile, so the result
 // is the order of (depth, record id) -- a stable depth sort of the records --
@@ -56,18 +56,19 @@ __device__ __forceinline__ uint32_t count_less(const uint64_t* r, uint32_t n, ui
 
 __global__ __launch_bounds__(kThreads) void segment_sort_kernel(SegSortBufs b) {
   __shared__ uint64_t s[kLdsKeys];
+  __shared__ uint32_t s_n;
   const uint32_t t = blockIdx.x;
-  const uint64_t cap = (uint64_t)b.cap;
-  uint64_t base = b.tile_offset[t];
-  uint64_t end = b.tile_offset[t + 1];
-  if (base > cap) base = cap;
-  if (end > cap) end = cap;   // only after an overflow, which is reported
-  const uint32_t n = (uint32_t)(end - base);
+  const uint64_t base = (uint64_t)t * b.cap;
   if (threadIdx.x == 0) {
-    b.ranges[t] = make_uint2((uint32_t)base, (uint32_t)end);
-    b.tile_count[(size_t)t * kTileCounterStride] = 0u;   // reset the counters for the next render
-    b.tile_fill[(size_t)t * kTileCounterStride] = 0u;
+    const uint32_t cnt = b.tile_count[(size_t)t * kTileCounterStride];
+    const uint32_t n = min(cnt, b.cap);   // beyond the bucket only after an overflow, which is reported
+    s_n = n;
+    b.ranges[t] = make_uint2((uint32_t)base, (uint32_t)(base + n));
+    b.tile_count[(size_t)t * kTileCounterStride] = 0u;   // reset the count for the next render
+    if (t == 0) b.counters[kCntRenderPeak] = 0u;
   }
+  __syncthreads();
+  const uint32_t n = s_n;
   if (n == 0) return;
   uint64_t* keys = b.keys[0] + base;
   if (n <= (uint32_t)kThreads) {

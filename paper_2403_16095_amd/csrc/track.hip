@@ -156,8 +156,9 @@ __global__ void increment_kernel(uint32_t* step) { *step += 1u; }
 __global__ __launch_bounds__(kThreads) void stats_kernel(const uint32_t* __restrict__ tiles, int64_t m,
                                                          const uint4* __restrict__ ps,
                                                          const uint2* __restrict__ count, int64_t pixels,
+                                                         const uint2* __restrict__ ranges, int64_t n_tiles,
                                                          unsigned long long* out) {
-  unsigned long long vis = 0, ev = 0, bl = 0, wk = 0;
+  unsigned long long vis = 0, ev = 0, bl = 0, wk = 0, pairs = 0, peak = 0;
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < m; i += (int64_t)gridDim.x * kThreads)
     vis += tiles[i] != 0u;
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < pixels; i += (int64_t)gridDim.x * kThreads) {
@@ -165,11 +166,18 @@ __global__ __launch_bounds__(kThreads) void stats_kernel(const uint32_t* __restr
     wk += count[i].y;
     bl += count[i].x;
   }
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n_tiles; i += (int64_t)gridDim.x * kThreads) {
+    const unsigned long long n = ranges[i].y - ranges[i].x;
+    pairs += n;
+    peak = n > peak ? n : peak;
+  }
   // These counters are read rarely; one atomic per lane keeps the code short.
   if (vis) atomicAdd(out, vis);
   if (ev) atomicAdd(out + 1, ev);
   if (bl) atomicAdd(out + 2, bl);
   if (wk) atomicAdd(out + 3, wk);
+  if (pairs) atomicAdd(out + 4, pairs);
+  if (peak) atomicMax(out + 5, peak);
 }
 
 }  // namespace
@@ -210,9 +218,9 @@ void launch_pose_adam(int n_views, float* poses, float* dposes, float* adam, con
 }
 
 void launch_stats(const uint32_t* tiles, int64_t m, const uint4* pixel_state, const uint2* pixel_count,
-                  int64_t pixels, unsigned long long* out4, hipStream_t s) {
+                  int64_t pixels, const uint2* ranges, int64_t n_tiles, unsigned long long* out6, hipStream_t s) {
   hipLaunchKernelGGL(stats_kernel, dim3(256), dim3(kThreads), 0, s, tiles, m, pixel_state, pixel_count, pixels,
-                     out4);
+                     ranges, n_tiles, out6);
 }
 
 }  // namespace cgsr

@@ -95,8 +95,10 @@ class State:
         self.n_views = 0
         self.n = 0
 
-    def reserve(self, records=0, pixels=0, tiles=0, pairs=0):
-        B.cgsr_state_reserve(self.handle, int(records), int(pixels), int(tiles), int(pairs))
+    def reserve(self, records=0, pixels=0, tiles=0, tile_pairs=0):
+        """Grow the workspace; tile_pairs: (tile, Gaussian) pairs one tile's
+        bucket holds (size it from ``stats().peak_pairs``)."""
+        B.cgsr_state_reserve(self.handle, int(records), int(pixels), int(tiles), int(tile_pairs))
 
     def stats(self) -> B.cgsr_stats:
         return B.cgsr_get_stats(self.handle, _stream())
@@ -680,7 +682,7 @@ class TrackingSolver:
         self._iteration()                       # eager, grows the pair buffer
         torch.cuda.synchronize()
         st = self.state.stats()
-        self.state.reserve(pairs=int(st.pairs * self.pair_margin) + 4096)
+        self.state.reserve(tile_pairs=int(st.peak_pairs * self.pair_margin) + 64)
         self.reset(pose0)
         if self.use_graph:
             self.graph = torch.cuda.CUDAGraph()

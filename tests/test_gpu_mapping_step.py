@@ -103,7 +103,7 @@ def test_bundle_adjustment_window(R):
     scene_g, P_g, ba_g = make()
     ba_g.step()                 # sizes the workspace (eager)
     ba_e.step()
-    ba_g.state.reserve(pairs=int(ba_g.state.stats().pairs * 1.5) + 4096)
+    ba_g.state.reserve(tile_pairs=int(ba_g.state.stats().peak_pairs * 1.5) + 64)
     ba_g.state.check()
     graph = torch.cuda.CUDAGraph()
     side = torch.cuda.Stream()

@@ -117,13 +117,16 @@ def tile_lists_from_gpu(R, st, n_tiles):
     keys, vals, ranges, recs, pst = B.cgsr_debug_buffers(st.handle)
     s = st.stats()
     K = int(s.pairs)
-    v = torch.empty(max(K, 1), dtype=torch.int32, device="cuda")
+    slots = n_tiles * int(s.pair_capacity)   # one bucket per tile
+    v = torch.empty(slots, dtype=torch.int32, device="cuda")
     rg = torch.empty((n_tiles, 2), dtype=torch.int32, device="cuda")
-    copy_device(v, vals, K * 4)
+    copy_device(v, vals, slots * 4)
     copy_device(rg, ranges, n_tiles * 8)
-    v = v.cpu().numpy()[:K].astype(np.int64)
+    v = v.cpu().numpy().astype(np.int64)
     rg = rg.cpu().numpy()
-    return {t: v[rg[t, 0]:rg[t, 1]] for t in range(n_tiles) if rg[t, 1] > rg[t, 0]}, K
+    lists = {t: v[rg[t, 0]:rg[t, 1]] for t in range(n_tiles) if rg[t, 1] > rg[t, 0]}
+    assert sum(len(x) for x in lists.values()) == K
+    return lists, K
 
 
 def check_tiles(R, sc, cam, pose):
@@ -451,14 +454,14 @@ def test_error_paths(R, config1):
     assert e.value.status == B.CGSR_ERR_INVALID_ARG
     # capacity overflow without the host sync: flagged, reported by check()
     st2 = R.State(sync_capacity=False)
-    st2.reserve(records=2000, pixels=64 * 48, tiles=12, pairs=100)
+    st2.reserve(records=2000, pixels=64 * 48, tiles=12, tile_pairs=100)
     R.render(st2, scd, p, [cam])
     with pytest.raises(B.CgsrError) as e:
         st2.check()
     assert e.value.status == B.CGSR_ERR_CAPACITY
     # and with the default sync the same state sizes itself
     st3 = R.State()
-    st3.reserve(pairs=100)
+    st3.reserve(tile_pairs=100)
     out = R.render(st3, scd, p, [cam])
     st3.check()
 

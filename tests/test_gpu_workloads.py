@@ -208,7 +208,7 @@ def test_batched_tracking_32_frames(R):
     Pg, ag = P0.clone(), torch.zeros((32, 16), device="cuda")
     gst = R.State()
     R.tracking_step(gst, scd, Pg, cams, tc, td, adam=ag, params=params)   # sizes the workspace
-    gst.reserve(pairs=int(gst.stats().pairs * 1.5))
+    gst.reserve(tile_pairs=int(gst.stats().peak_pairs * 1.5))
     graph = torch.cuda.CUDAGraph()
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
