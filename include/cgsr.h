@@ -114,6 +114,11 @@ typedef struct {
                                 a 16x16 tile then takes 256 / that many lanes   */
     int32_t bwd_pixels_per_lane; /* same for the backward blend; each lane sums its
                                 pixels before the per-Gaussian wave reduction   */
+    int32_t count_work;      /* 1: a tracking step keeps the per-pixel work
+                                counts that cgsr_get_stats reports (processed,
+                                blended, walked).  0: it skips that bookkeeping
+                                and cgsr_get_stats reports -1 for them after
+                                it; renders and backward passes always count  */
 } cgsr_settings;
 
 typedef struct {
@@ -129,7 +134,9 @@ typedef struct {
                                 reaches its 8x8 pixel cell                       */
     int64_t blended;         /* (pixel, Gaussian) pairs actually blended          */
     int64_t walked;          /* (pixel, list entry) pairs up to each pixel's last
-                                blended Gaussian: what the backward revisits    */
+                                blended Gaussian: what the backward revisits.
+                                processed, blended and walked are -1 after a
+                                tracking step with count_work 0               */
     int64_t peak_pairs;      /* pairs of the last render's fullest tile, or, if a
                                 render since the last cgsr_state_check
                                 overflowed, the most any tile needed there      */

@@ -75,7 +75,7 @@ class cgsr_gaussian_grads(C.Structure):
 
 class cgsr_settings(C.Structure):
     _fields_ = [("sync_capacity", C.c_int32), ("timing", C.c_int32), ("fwd_pixels_per_lane", C.c_int32),
-                ("bwd_pixels_per_lane", C.c_int32)]
+                ("bwd_pixels_per_lane", C.c_int32), ("count_work", C.c_int32)]
 
 
 class cgsr_adam_params(C.Structure):

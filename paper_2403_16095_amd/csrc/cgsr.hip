@@ -110,6 +110,7 @@ struct cgsr_state {
   // last render
   bool have_forward = false;
   bool tracked = false;   // the last forward was a tracking step
+  bool counted = false;   // the last forward kept the per-pixel work counts
   int32_t n_views = 0;
   GaussianPtrs g{};
   const float* poses = nullptr;
@@ -254,6 +255,7 @@ RasterBufs raster_bufs(cgsr_state* st, int slot) {
   rb.nu_count = nullptr;
   rb.nu = false;
   rb.color_grads = st->g.sh != nullptr;
+  rb.count_work = st->settings.count_work != 0;
   rb.views = ViewTable{st->io[slot].dev, st->n_views, (int32_t)st->g.n};
   rb.total_tiles = st->total_tiles;
   return rb;
@@ -269,6 +271,7 @@ void cgsr_default_settings(cgsr_settings* s) {
   s->timing = 0;
   s->fwd_pixels_per_lane = 1;
   s->bwd_pixels_per_lane = 1;
+  s->count_work = 1;
 }
 
 cgsr_status cgsr_state_create(const cgsr_settings* s, cgsr_state** out) {
@@ -281,10 +284,10 @@ cgsr_status cgsr_state_create(const cgsr_settings* s, cgsr_state** out) {
   auto ppl_ok = [](int32_t p) { return p == 1 || p == 2 || p == 4; };
   if (st->settings.sync_capacity < 0 || st->settings.sync_capacity > 1 || st->settings.timing < 0 ||
       st->settings.timing > 1 || !ppl_ok(st->settings.fwd_pixels_per_lane) ||
-      !ppl_ok(st->settings.bwd_pixels_per_lane)) {
+      !ppl_ok(st->settings.bwd_pixels_per_lane) || st->settings.count_work < 0 || st->settings.count_work > 1) {
     delete st;
     return fail(CGSR_ERR_INVALID_ARG,
-                "settings: sync_capacity and timing must be 0 or 1, pixels per lane 1, 2 or 4");
+                "settings: sync_capacity, timing and count_work must be 0 or 1, pixels per lane 1, 2 or 4");
   }
   cgsr_status r = CGSR_OK;
   hipError_t e = hipGetDevice(&st->device);
@@ -524,6 +527,7 @@ cgsr_status render_impl(cgsr_state* st, const RenderArgs& a, hipStream_t stream)
   if ((s = mark(CGSR_STAGE_BLEND_FWD + 1))) return s;
   st->fwd_timed = timed;
   st->tracked = a.track;
+  st->counted = !(a.track && a.fused && !st->settings.count_work);
   st->have_forward = true;
   return CGSR_OK;
 }
@@ -1047,9 +1051,9 @@ cgsr_status cgsr_get_stats(cgsr_state* st, void* stream_, cgsr_stats* out) {
   // last check if that overflowed
   out->peak_pairs = std::max<int64_t>((int64_t)host[5], st->counters_pinned[kCntPeak]);
   out->visible = (int64_t)host[0];
-  out->processed = (int64_t)host[1];
-  out->blended = (int64_t)host[2];
-  out->walked = (int64_t)host[3];
+  out->processed = st->counted ? (int64_t)host[1] : -1;
+  out->blended = st->counted ? (int64_t)host[2] : -1;
+  out->walked = st->counted ? (int64_t)host[3] : -1;
   return CGSR_OK;
 }
 

@@ -136,6 +136,8 @@ struct RasterBufs {
   // The backward also reduces the colour gradients when the pose gradient
   // needs them (view-dependent colour) even without parameter gradients.
   bool color_grads;
+  // The fused tracking kernel keeps the per-pixel state and work counts.
+  bool count_work;
 };
 // ppl: pixels per lane, 1, 2 or 4 (256 / ppl lanes per 16x16 tile).
 void launch_raster_forward(const RasterBufs& b, bool track, int ppl, hipStream_t s);

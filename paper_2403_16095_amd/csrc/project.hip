@@ -373,9 +373,11 @@ __global__ __launch_bounds__(kThreads) void project_kernel(GaussianPtrs g, const
   }
 }
 
-// Backward of project_kernel for one record.  rec_grad holds dL/d(mu, conic,
-// opacity, depth, colour) accumulated by the blend backward; it is read and
-// cleared here so the next backward starts from zero.
+// Backward of project_kernel for one record.  rec_grad holds what the blend
+// backward accumulated over the record's pixels: the sums u1, u2, sxx, sxy,
+// syy of dL/dpower times (t, dy, dx^2, dx dy, dy^2), dL/dopacity, dL/ddepth
+// and dL/dcolour; it is read and cleared here so the next backward starts
+// from zero.
 __global__ __launch_bounds__(kThreads) void project_backward_kernel(GaussianPtrs g, const float* __restrict__ poses,
                                                                     ViewTable vt, float* rec_grad,
                                                                     const uint32_t* __restrict__ tiles,
@@ -394,15 +396,24 @@ __global__ __launch_bounds__(kThreads) void project_backward_kernel(GaussianPtrs
     gr[0] = make_float4(0.f, 0.f, 0.f, 0.f);
     gr[1] = make_float4(0.f, 0.f, 0.f, 0.f);
     gr[2] = make_float4(0.f, 0.f, 0.f, 0.f);
-    const float dmux = g0.x, dmuy = g0.y, da = g0.z, db = g0.w, dc = g1.x, dop = g1.y, dd = g1.z;
-    if (dens_grad) {
-      atomicAdd(dens_grad + i, sqrtf(dmux * dmux + dmuy * dmuy));
-      atomicAdd(dens_count + i, 1u);
-    }
+    const float dop = g1.y, dd = g1.z;
     const ViewInfo cam = vt.io[v].info;
     const float* P = poses + 12 * v;
     Proj o;
+    // the record was visible in the forward at this pose, so this holds
     if (project_core(g, i, P, cam, o)) {
+      // power = -(a t^2 + c' dy^2) / 2 with t = dx + k dy, k = b / a and
+      // c' = c - b^2 / a = 1 / Sigma2d_yy (dx, dy = mu - pixel), so
+      // dpower/dmu = -(a t, a k t + c' dy) and dpower/d(a, b, c) =
+      // -(dx^2 / 2, dx dy, dy^2 / 2).
+      const double qa = o.conic[0], qk = o.conic[1] / o.conic[0], qc = 1.0 / o.cov[2];
+      const float dmux = (float)(-qa * (double)g0.x);
+      const float dmuy = (float)(-(qa * qk * (double)g0.x + qc * (double)g0.y));
+      const float da = -0.5f * g0.z, db = -g0.w, dc = -0.5f * g1.x;
+      if (dens_grad) {
+        atomicAdd(dens_grad + i, sqrtf(dmux * dmux + dmuy * dmuy));
+        atomicAdd(dens_count + i, 1u);
+      }
       const float x = (float)o.p[0], y = (float)o.p[1], z = (float)o.p[2];
       const float zinv = 1.0f / z, zinv2 = zinv * zinv;
       // dL/dSigma2d = -Q dQ Q with the off-diagonal conic entry counted twice.

@@ -66,7 +66,8 @@ __device__ __forceinline__ float sgn(float x) { return (float)((x > 0.f) - (x < 
 
 // The LDS batch of staged records (see stage_record) and their record ids,
 // one compacted copy per wave (W waves per tile), and each copy's length.
-// C.w of a staged record holds its position in the batch (as int bits).
+// C.w of a staged record holds one past its position in the tile's list (as
+// int bits), so a walk compares it with its pixel's bounds without arithmetic.
 template <int W>
 struct Stage {
   float4 A[W][kBatch], B[W][kBatch], C[W][kBatch];
@@ -91,11 +92,12 @@ __device__ __forceinline__ bool wave_reaches(int w, uint32_t cx0, uint32_t cx1, 
 }
 
 // Stages list entries [first, first + n) of the tile, n <= kBatch, into each
-// wave's copy; every thread calls it.  (tcx, tcy): the tile's first 8-pixel
-// cell.  With one wave per tile every record reaches it.
+// wave's copy; every thread calls it.  pos0: the position of entry first in
+// the tile's list.  (tcx, tcy): the tile's first 8-pixel cell.  With one wave
+// per tile every record reaches it.
 template <int L, int W>
-__device__ __forceinline__ void stage_batch(const RasterBufs& b, Stage<W>& s, uint32_t first, int n, float2 org,
-                                            uint32_t tcx, uint32_t tcy) {
+__device__ __forceinline__ void stage_batch(const RasterBufs& b, Stage<W>& s, uint32_t first, uint32_t pos0, int n,
+                                            float2 org, uint32_t tcx, uint32_t tcy) {
   __syncthreads();
   if constexpr (W == 1) {
     for (int i = threadIdx.x; i < n; i += L) {
@@ -103,7 +105,7 @@ __device__ __forceinline__ void stage_batch(const RasterBufs& b, Stage<W>& s, ui
       s.M[0][i] = m;
       float4 C;
       stage_record(b.rec + (int64_t)kRecF4 * m, org.x, org.y, s.A[0][i], s.B[0][i], C);
-      C.w = __int_as_float(i);
+      C.w = __int_as_float((int)(pos0 + i + 1));
       s.C[0][i] = C;
     }
     if (threadIdx.x == 0) s.cnt[0] = (uint32_t)n;
@@ -118,7 +120,7 @@ __device__ __forceinline__ void stage_batch(const RasterBufs& b, Stage<W>& s, ui
     if (i < n) {
       m = b.vals[first + i];
       stage_record(b.rec + (int64_t)kRecF4 * m, org.x, org.y, A, B, C);
-      C.w = __int_as_float(i);
+      C.w = __int_as_float((int)(pos0 + i + 1));
       const uint2 r = b.rect[m];
       const uint32_t cx0 = r.x & 0xFFFFu, cx1 = r.x >> 16, cy0 = r.y & 0xFFFFu, cy1 = r.y >> 16;
 #pragma unroll
@@ -159,7 +161,7 @@ struct FwdPix {
   float fx[kPPL], fy[kPPL], dobs[kPPL], T[kPPL], C0[kPPL], C1[kPPL], C2[kPPL], D[kPPL], O[kPPL], U[kPPL],
       Dmed[kPPL];
   int64_t pix[kPPL];
-  int med[kPPL];
+  uint32_t med1[kPPL];            // one past the median's position in the tile's list, 0 if none
   uint32_t last[kPPL], evaluated[kPPL], blended[kPPL], wlast[kPPL];
   float wdom[kPPL], ddom[kPPL];   // kNu: largest weight so far and its depth
   uint32_t dom[kPPL];             // kNu: its record id, kNone if none
@@ -169,8 +171,11 @@ struct FwdPix {
 // Front-to-back walk of the tile's list (Eq. 3-9, Eq. 10 with kTrack off).
 // On return the stage holds the last batch walked; that is the whole list when
 // it fits one batch.  evaluated, wlast and blended count entries of the
-// wave's own (8x8) list; last and med are positions in the tile's list.
-template <int kPPL, bool kTrack, bool kNu>
+// wave's own (8x8) list; last and med1 are one past positions in the tile's
+// list.  With kFull off (a tracking step that keeps no statistics) the walk
+// keeps only what the tracking loss and the pose backward read: colour,
+// depth, transmittance and the last blended entry.
+template <int kPPL, bool kTrack, bool kNu, bool kFull = true>
 __device__ __forceinline__ void forward_tile(const RasterBufs& b, Stage<kTilePixels / kPPL / kWave>& s, int gtile,
                                              const ViewIO& io, float2 org, uint2 range, FwdPix<kPPL>& f) {
   constexpr int L = kTilePixels / kPPL;
@@ -190,7 +195,7 @@ __device__ __forceinline__ void forward_tile(const RasterBufs& b, Stage<kTilePix
     f.dobs[k] = (!kTrack && io.depth_obs && pc.inside) ? io.depth_obs[f.pix[k]] : 0.f;
     f.T[k] = 1.f;
     f.C0[k] = f.C1[k] = f.C2[k] = f.D[k] = f.O[k] = f.U[k] = f.Dmed[k] = 0.f;
-    f.med[k] = -1;
+    f.med1[k] = 0;
     f.last[k] = 0;
     f.blended[k] = 0;
     f.wdom[k] = f.ddom[k] = 0.f;
@@ -202,19 +207,19 @@ __device__ __forceinline__ void forward_tile(const RasterBufs& b, Stage<kTilePix
   }
   for (uint32_t base = range.x; base < range.y; base += kBatch) {
     const int n = (int)min((uint32_t)kBatch, range.y - base);
-    stage_batch<L, W>(b, s, base, n, org, tcx, tcy);
-    const int nw = (int)s.cnt[wv];
+    stage_batch<L, W>(b, s, base, base - range.x, n, org, tcx, tcy);
+    // the copy's length is the same for the whole wave
+    const int nw = (int)__builtin_amdgcn_readfirstlane(s.cnt[wv]);
     // The wave walks the whole batch while any of its lanes still blends;
     // lanes that are done ride along predicated off.  (A vote every few
     // records to leave early cost more issue slots than it saved: at tracking
     // sizes most pixels never reach the stop threshold.)
     if (__ballot(!lane_done) != 0ull) {
-      const uint32_t off = base - range.x;
       for (int j = 0; j < nw; ++j) {
         const float4 A = s.A[wv][j];
         const float4 B = s.B[wv][j];
         const float4 Cc = s.C[wv][j];
-        const uint32_t pos = off + (uint32_t)__float_as_int(Cc.w);   // position in the tile's list
+        const uint32_t pos1 = (uint32_t)__float_as_int(Cc.w);   // one past its position in the tile's list
         // Straight-line, predicated per lane: a lane that skips (alpha below
         // 1/255, or already done) adds exact zeros, so the results are those
         // of the branching form, without exec-mask bookkeeping per record.
@@ -228,20 +233,22 @@ __device__ __forceinline__ void forward_tile(const RasterBufs& b, Stage<kTilePix
           const bool stop = hit && Tn < kTStop;
           const bool blend = hit && !stop;
           f.done[k] = f.done[k] || stop;
-          f.evaluated[k] = stop ? loc + j + 1 : f.evaluated[k];
+          if (kFull) f.evaluated[k] = stop ? loc + j + 1 : f.evaluated[k];
           const float wgt = blend ? alpha * f.T[k] : 0.f;
           f.C0[k] = __builtin_fmaf(wgt, Cc.x, f.C0[k]);
           f.C1[k] = __builtin_fmaf(wgt, Cc.y, f.C1[k]);
           f.C2[k] = __builtin_fmaf(wgt, Cc.z, f.C2[k]);
           f.D[k] = __builtin_fmaf(wgt, B.z, f.D[k]);
-          f.O[k] += wgt;
+          if (kFull) f.O[k] += wgt;
           if (!kTrack) {
             const float dz = B.z - f.dobs[k];
             f.U[k] = __builtin_fmaf(wgt * dz, dz, f.U[k]);
           }
-          const bool first_med = blend && f.med[k] < 0 && Tn < kTMedian;
-          f.med[k] = first_med ? (int)pos : f.med[k];
-          f.Dmed[k] = first_med ? B.z : f.Dmed[k];
+          if (kFull) {
+            const bool first_med = blend && f.med1[k] == 0u && Tn < kTMedian;
+            f.med1[k] = first_med ? pos1 : f.med1[k];
+            f.Dmed[k] = first_med ? B.z : f.Dmed[k];
+          }
           if (kNu) {
             const bool more = blend && wgt > f.wdom[k];   // strict: the first of equal maxima
             f.wdom[k] = more ? wgt : f.wdom[k];
@@ -249,9 +256,11 @@ __device__ __forceinline__ void forward_tile(const RasterBufs& b, Stage<kTilePix
             f.dom[k] = more ? s.M[wv][j] : f.dom[k];
           }
           f.T[k] = blend ? Tn : f.T[k];
-          f.last[k] = blend ? pos + 1 : f.last[k];
-          f.wlast[k] = blend ? loc + j + 1 : f.wlast[k];
-          f.blended[k] += blend ? 1u : 0u;
+          f.last[k] = blend ? pos1 : f.last[k];
+          if (kFull) {
+            f.wlast[k] = blend ? loc + j + 1 : f.wlast[k];
+            f.blended[k] += blend ? 1u : 0u;
+          }
         }
       }
       bool all = true;
@@ -270,7 +279,9 @@ __device__ __forceinline__ void forward_tile(const RasterBufs& b, Stage<kTilePix
 // Everything the forward leaves behind: maps, saved per-pixel state, the
 // tracking-loss gradients (returned in g; stored for a separate backward when
 // store_grad) and the Eq. 13 accumulation.
-template <int kPPL, bool kTrack, bool kNu>
+// Without kFull only the colour and depth maps are written (the tracking
+// step requests none) and no per-pixel state is saved.
+template <int kPPL, bool kTrack, bool kNu, bool kFull = true>
 __device__ __forceinline__ void forward_outputs(const RasterBufs& b, int v, const ViewIO& io,
                                                 const FwdPix<kPPL>& f, float (&g)[kPPL][4], bool store_grad) {
   const ViewInfo& cam = io.info;
@@ -310,11 +321,12 @@ __device__ __forceinline__ void forward_outputs(const RasterBufs& b, int v, cons
       io.color[2 * hw + p] = f.C2[k];
     }
     if (io.depth) io.depth[p] = f.D[k];
+    if (!kFull) continue;
     if (io.opacity) io.opacity[p] = f.O[k];
     if (io.depth_median) io.depth_median[p] = f.Dmed[k];
     if (io.uncertainty) io.uncertainty[p] = f.U[k];
-    b.pixel_state[cam.pixel_base + p] =
-        make_uint4(__float_as_uint(f.T[k]), f.last[k], (uint32_t)f.med[k], f.evaluated[k]);
+    // the median's position, or ~0u if it has none
+    b.pixel_state[cam.pixel_base + p] = make_uint4(__float_as_uint(f.T[k]), f.last[k], f.med1[k] - 1u, f.evaluated[k]);
     b.pixel_count[cam.pixel_base + p] = make_uint2(f.blended[k], f.wlast[k]);
     if (kNu) {
       // record id m = view * N + Gaussian index
@@ -335,7 +347,7 @@ struct BwdPix {
   float fx[kPPL], fy[kPPL], T[kPPL], gc0[kPPL], gc1[kPPL], gc2[kPPL], gd[kPPL], go[kPPL], gm[kPPL], gu[kPPL],
       dobs[kPPL];
   float Bc0[kPPL], Bc1[kPPL], Bc2[kPPL], Bd[kPPL], Bo[kPPL], Bu[kPPL];
-  int walked[kPPL], med[kPPL];
+  int walked[kPPL], med1[kPPL];   // one past the last blended entry's / the median's position (0: none)
 };
 
 // Largest walked length over the workgroup.
@@ -370,15 +382,19 @@ __device__ __forceinline__ void backward_tile(const RasterBufs& b, Stage<kTilePi
   for (int end = nmax; end > 0; end -= kBatch) {
     const int start = max(0, end - kBatch);
     const int n = end - start;
-    if (!(start == 0 && end <= staged_n)) stage_batch<L, W>(b, s, range.x + start, n, org, tcx, tcy);
-    for (int j = (int)s.cnt[wv] - 1; j >= 0; --j) {
+    if (!(start == 0 && end <= staged_n)) stage_batch<L, W>(b, s, range.x + start, start, n, org, tcx, tcy);
+    for (int j = (int)__builtin_amdgcn_readfirstlane(s.cnt[wv]) - 1; j >= 0; --j) {
       const float4 A = s.A[wv][j];
       const float4 B = s.B[wv][j];
       float u1 = 0.f, u2 = 0.f, sxx = 0.f, sxy = 0.f, syy = 0.f, gop = 0.f, gdd = 0.f;
       float gr = 0.f, gg = 0.f, gbl = 0.f;
       bool any = false;
       const float4 Cc = s.C[wv][j];
-      const int pos = start + __float_as_int(Cc.w);
+      const int pos1 = __float_as_int(Cc.w);   // one past its position in the tile's list
+      const uint32_t m = s.M[wv][j];
+      // Keep this read beside the record's: left to the compiler it moves
+      // into the branch below and the next record's reads wait for it.
+      asm volatile("" : : "v"(m));
       // Straight-line, predicated per lane: a lane that did not blend this
       // record (past its last blended one, or alpha below 1/255) takes
       // alpha = 0, which leaves T and the behind sums exactly unchanged and
@@ -387,7 +403,7 @@ __device__ __forceinline__ void backward_tile(const RasterBufs& b, Stage<kTilePi
       for (int k = 0; k < kPPL; ++k) {
         float dx, dy, tq;
         const float e = pair_exponent(A, B, p.fx[k], p.fy[k], dx, dy, tq);
-        const bool hit = pos < p.walked[k] && e >= B.w;
+        const bool hit = pos1 <= p.walked[k] && e >= B.w;
         any = any || hit;
         const float g = __builtin_amdgcn_exp2f(e);
         const float raw = B.y * g;
@@ -415,60 +431,47 @@ __device__ __forceinline__ void backward_tile(const RasterBufs& b, Stage<kTilePi
         const float dpower = live ? dalpha * raw : 0.f;   // alpha = opacity * exp(power)
         // power = -(a dx^2 + 2 b dx dy + c dy^2) / 2 = ln2 (qa t^2 + qc dy^2)
         // with t = dx + k dy, so d power/d mu = 2 ln2 (qa t, qa k t + qc dy)
-        // and d power/d(a, b, c) = -(dx^2 / 2, dx dy, dy^2 / 2).  The factors
-        // that belong to the record (qa, k, qc, the constants) are applied
-        // once after the wave reduction; lanes only accumulate
-        // u1 = sum dpower t, u2 = sum dpower dy and the second moments.
+        // and d power/d(a, b, c) = -(dx^2 / 2, dx dy, dy^2 / 2).  These are
+        // linear in the sums u1 = sum dpower t, u2 = sum dpower dy and the
+        // second moments, so lanes, waves and tiles only add those up; the
+        // factors that belong to the record (qa, k, qc, the constants) are
+        // applied once per record by the projection backward.
         const float pdx = dpower * dx, pdy = dpower * dy;
-        u1 = __builtin_fmaf(dpower, tq, u1);
-        u2 += pdy;
-        sxx = __builtin_fmaf(pdx, dx, sxx);
-        sxy = __builtin_fmaf(pdx, dy, sxy);
-        syy = __builtin_fmaf(pdy, dy, syy);
-        gdd += wgt * p.gd[k];
-        if (!kTrack) gdd += 2.f * wgt * dz * p.gu[k] + ((hit && pos == p.med[k]) ? p.gm[k] : 0.f);
-        if (kParams) gop += live ? dalpha * g : 0.f;
+        // the first pixel's terms start the sums, so nothing adds a zero
+        auto acc = [&](float& sum, float x) { sum = k == 0 ? x : sum + x; };
+        auto acc_fma = [&](float& sum, float x, float y) { sum = k == 0 ? x * y : __builtin_fmaf(x, y, sum); };
+        acc_fma(u1, dpower, tq);
+        acc(u2, pdy);
+        acc_fma(sxx, pdx, dx);
+        acc_fma(sxy, pdx, dy);
+        acc_fma(syy, pdy, dy);
+        acc_fma(gdd, wgt, p.gd[k]);
+        if (!kTrack) gdd += 2.f * wgt * dz * p.gu[k] + ((hit && pos1 == p.med1[k]) ? p.gm[k] : 0.f);
+        if (kParams) acc(gop, live ? dalpha * g : 0.f);
         if (kParams || kColor) {
-          gr += wgt * p.gc0[k];
-          gg += wgt * p.gc1[k];
-          gbl += wgt * p.gc2[k];
+          acc_fma(gr, wgt, p.gc0[k]);
+          acc_fma(gg, wgt, p.gc1[k]);
+          acc_fma(gbl, wgt, p.gc2[k]);
         }
       }
       if (__ballot(any)) {
-        const uint32_t m = s.M[wv][j];
         float* dst = b.rec_grad + (int64_t)kGradStride * m;
-        // values 0-4 (u1, u2, sxx, sxy, syy) become the gradients of mu x,
-        // mu y and the conic (a, b, c); the rest pass through.
-        auto finish = [&](int idx, float t) {
-          const float U1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, t), 0));
-          const float c2 = 2.f * kLn2;
-          float out = t;
-          out = idx == 0 ? c2 * A.z * t : out;
-          out = idx == 1 ? c2 * __builtin_fmaf(A.z * A.w, U1, B.x * t) : out;
-          out = (idx == 2 || idx == 4) ? -0.5f * t : out;
-          out = idx == 3 ? -t : out;
-          return out;
-        };
+        // slots 0-4: the sums u1, u2, sxx, sxy, syy; 5 opacity, 6 depth, 7-9 colour
         if (kParams) {
-          // slots 0-9: mu x, mu y, conic a, b, c, opacity, depth, colour
           const float vals[10] = {u1, u2, sxx, sxy, syy, gop, gdd, gr, gg, gbl};
           const float t = wave_sum_many<16>(vals);
           const int idx = reduced_value_index<16>(lane);
-          const float out = finish(idx, t);
-          if ((lane & 3) == 0 && idx < 10) unsafeAtomicAdd(dst + idx, out);
+          if ((lane & 3) == 0 && idx < 10) unsafeAtomicAdd(dst + idx, t);
         } else if (kColor) {
-          // slots 0-4, depth in 6, colour in 7-9
           const float vals[9] = {u1, u2, sxx, sxy, syy, gdd, gr, gg, gbl};
           const float t = wave_sum_many<16>(vals);
           const int idx = reduced_value_index<16>(lane);
-          const float out = finish(idx, t);
-          if ((lane & 3) == 0 && idx < 9) unsafeAtomicAdd(dst + (idx < 5 ? idx : idx + 1), out);
+          if ((lane & 3) == 0 && idx < 9) unsafeAtomicAdd(dst + (idx < 5 ? idx : idx + 1), t);
         } else {
           const float vals[6] = {u1, u2, sxx, sxy, syy, gdd};
           const float t = wave_sum_many<8>(vals);
           const int idx = reduced_value_index<8>(lane);
-          const float out = finish(idx, t);
-          if ((lane & 7) == 0 && idx < 6) unsafeAtomicAdd(dst + (idx == 5 ? 6 : idx), out);
+          if ((lane & 7) == 0 && idx < 6) unsafeAtomicAdd(dst + (idx == 5 ? 6 : idx), t);
         }
       }
     }
@@ -507,14 +510,14 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
     p.fy[k] = (float)(pc.py - pc.oy);
     p.T[k] = 1.f;
     p.walked[k] = 0;
-    p.med[k] = -1;
+    p.med1[k] = 0;
     p.gc0[k] = p.gc1[k] = p.gc2[k] = p.gd[k] = p.go[k] = p.gm[k] = p.gu[k] = p.dobs[k] = 0.f;
     p.Bc0[k] = p.Bc1[k] = p.Bc2[k] = p.Bd[k] = p.Bo[k] = p.Bu[k] = 0.f;
     if (pc.inside) {
       const uint4 ps = b.pixel_state[cam.pixel_base + pix];
       p.T[k] = __uint_as_float(ps.x);
       p.walked[k] = (int)ps.y;
-      p.med[k] = (int)ps.z;
+      p.med1[k] = (int)(ps.z + 1u);
       if (kTrack) {
         const float4 g4 = b.pixel_grad[cam.pixel_base + pix];
         p.gc0[k] = g4.x;
@@ -542,8 +545,9 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
 
 // Tracking iteration of one tile: forward, tracking-loss gradients in
 // registers, pose backward (kColor: with the colour gradients that the pose
-// gradient of a view-dependent colour needs).
-template <int kPPL, bool kColor>
+// gradient of a view-dependent colour needs; kFull: also the per-pixel state
+// and work counts that the statistics read).
+template <int kPPL, bool kColor, bool kFull>
 __global__ __launch_bounds__(kTilePixels / kPPL) void raster_track_kernel(RasterBufs b) {
   __shared__ Stage<kTilePixels / kPPL / kWave> s;
   __shared__ uint32_t s_max;
@@ -556,16 +560,16 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_track_kernel(Raster
   uint32_t lane_max = 0;
   {
     FwdPix<kPPL> f;
-    forward_tile<kPPL, true, false>(b, s, gtile, io, org, range, f);
+    forward_tile<kPPL, true, false, kFull>(b, s, gtile, io, org, range, f);
     float g[kPPL][4];
-    forward_outputs<kPPL, true, false>(b, v, io, f, g, false);
+    forward_outputs<kPPL, true, false, kFull>(b, v, io, f, g, false);
 #pragma unroll
     for (int k = 0; k < kPPL; ++k) {
       p.fx[k] = f.fx[k];
       p.fy[k] = f.fy[k];
       p.T[k] = f.T[k];
       p.walked[k] = f.inside[k] ? (int)f.last[k] : 0;
-      p.med[k] = -1;
+      p.med1[k] = 0;
       p.gc0[k] = g[k][0];
       p.gc1[k] = g[k][1];
       p.gc2[k] = g[k][2];
@@ -602,8 +606,10 @@ void launch_bwd(const RasterBufs& b, bool params, bool track, hipStream_t s) {
 template <int kPPL>
 void launch_track(const RasterBufs& b, hipStream_t s) {
   const dim3 grid(b.total_tiles), block(kTilePixels / kPPL);
-  if (b.color_grads) hipLaunchKernelGGL((raster_track_kernel<kPPL, true>), grid, block, 0, s, b);
-  else hipLaunchKernelGGL((raster_track_kernel<kPPL, false>), grid, block, 0, s, b);
+  if (b.color_grads && b.count_work) hipLaunchKernelGGL((raster_track_kernel<kPPL, true, true>), grid, block, 0, s, b);
+  else if (b.color_grads) hipLaunchKernelGGL((raster_track_kernel<kPPL, true, false>), grid, block, 0, s, b);
+  else if (b.count_work) hipLaunchKernelGGL((raster_track_kernel<kPPL, false, true>), grid, block, 0, s, b);
+  else hipLaunchKernelGGL((raster_track_kernel<kPPL, false, false>), grid, block, 0, s, b);
 }
 
 }  // namespace

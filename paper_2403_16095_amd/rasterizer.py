@@ -82,10 +82,11 @@ class State:
     """Owns one cgsr_state (the workspace of a render and its backward)."""
 
     def __init__(self, sync_capacity: bool = True, timing: bool = False, fwd_ppl: int | None = None,
-                 bwd_ppl: int | None = None):
+                 bwd_ppl: int | None = None, count_work: bool = True):
         s = B.cgsr_default_settings()
         s.sync_capacity = int(sync_capacity)
         s.timing = int(timing)
+        s.count_work = int(count_work)
         if fwd_ppl is not None:
             s.fwd_pixels_per_lane = int(fwd_ppl)
         if bwd_ppl is not None:
@@ -620,9 +621,11 @@ class TrackingSolver:
 
     def __init__(self, prob: TrackingProblem, iters: int = 50, pair_margin: float = 1.5, use_graph: bool = True,
                  reset_pose: torch.Tensor | None = None, fused: bool = True, fwd_ppl: int | None = None,
-                 bwd_ppl: int | None = None):
+                 bwd_ppl: int | None = None, count_work: bool = False):
         """reset_pose: if given, every solve (and every graph replay) starts
-        from this pose with fresh Adam moments; the reset is part of the graph."""
+        from this pose with fresh Adam moments; the reset is part of the graph.
+        count_work: keep the per-pixel work counts of ``state.stats()`` (off:
+        the fused step skips that bookkeeping)."""
         self.prob = prob
         self.iters = int(iters)
         cam = prob.cam
@@ -635,7 +638,7 @@ class TrackingSolver:
         self.ddepth = torch.empty((H, W), dtype=torch.float32, device=dev)
         self.color = torch.empty((3, H, W), dtype=torch.float32, device=dev)
         self.depth = torch.empty((H, W), dtype=torch.float32, device=dev)
-        self.state = State(sync_capacity=True, fwd_ppl=fwd_ppl, bwd_ppl=bwd_ppl)
+        self.state = State(sync_capacity=True, fwd_ppl=fwd_ppl, bwd_ppl=bwd_ppl, count_work=count_work)
         self.g = gaussians_struct(prob.scene)
         self.cam_s = camera_struct(cam)
         self.out_s = B.cgsr_images(self.color.data_ptr(), self.depth.data_ptr(), None, None, None)

@@ -88,6 +88,9 @@ def test_host_side_argument_checks(lib):
     assert out.value is None
     bad_ppl = B.cgsr_settings(1, 0, 3, 1)
     assert lib.cgsr_state_create(C.byref(bad_ppl), C.byref(out)) == B.CGSR_ERR_INVALID_ARG
+    bad_count = B.cgsr_settings(1, 0, 1, 1, 2)
+    assert lib.cgsr_state_create(C.byref(bad_count), C.byref(out)) == B.CGSR_ERR_INVALID_ARG
+    assert B.cgsr_default_settings().count_work == 1
 
 
 def test_binding_raises_with_message(lib):

@@ -533,6 +533,45 @@ def test_fused_tracking_step_matches_separate_calls(R):
     assert e < 1e-4
 
 
+def test_tracking_step_without_work_counts(R):
+    """count_work = 0 (the fused step keeps only colour, depth, transmittance
+    and the last blended entry per pixel) gives the same losses, poses and
+    pose gradients as the counting kernel; its statistics report the work
+    counts as unknown (-1)."""
+    say("case: tracking step with and without work counts, 2 frames")
+    sc = synth.room_scene(5, 30_000, (5.0, 4.0, 3.0))
+    cams = [synth.camera(320, 240, 262.5, 262.5, 160, 120), synth.camera(160, 128, 131.25, 131.25, 80, 64)]
+    scd = dev(sc)
+    tgt_poses = [synth.level_room_pose(s) for s in (23, 24)]
+    ref = R.State()
+    P_t = torch.stack([R.pose_tensor(*p) for p in tgt_poses])
+    tg = R.render(ref, scd, P_t, cams)
+    tc = [t["color"].clone() for t in tg]
+    td = [t["depth"].clone() for t in tg]
+    P0 = torch.stack([R.pose_tensor(*synth.perturb_pose(*p, 40 + k)) for k, p in enumerate(tgt_poses)])
+    out = {}
+    for count in (True, False):
+        st = R.State(count_work=count)
+        P, adam = P0.clone(), torch.zeros((2, 16), device="cuda")
+        losses = []
+        for it in range(3):
+            L = torch.zeros(2, device="cuda")
+            R.tracking_step(st, scd, P, cams, tc, td, adam=adam, loss=L)
+            losses.append(L.cpu().tolist())
+        dposes = torch.zeros((2, 6), device="cuda")
+        R.tracking_step(st, scd, P0, cams, tc, td, dposes=dposes)
+        out[count] = (np.array(losses), P.cpu(), dposes.cpu(), st.stats())
+    (l1, p1, d1, s1), (l0, p0, d0, s0) = out[True], out[False]
+    np.testing.assert_allclose(l0, l1, rtol=1e-6)
+    assert (p0 - p1).abs().max().item() < 1e-6
+    e = ((d0 - d1).abs().max() / d1.abs().max()).item()
+    say("pose gradient, without vs with counts", e)
+    assert e < 1e-5
+    assert s1.processed > 0 and s1.blended > 0 and s1.walked > 0
+    assert s0.processed == -1 and s0.blended == -1 and s0.walked == -1
+    assert s0.visible == s1.visible and s0.pairs == s1.pairs and s0.peak_pairs == s1.peak_pairs
+
+
 def test_graph_tracking_replays_match_eager(R):
     """The captured 50-iteration tracking solve replayed several times, with
     eager work in between, matches the same loop run eagerly."""
