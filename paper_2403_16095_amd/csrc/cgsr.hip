@@ -256,6 +256,11 @@ RasterBufs raster_bufs(cgsr_state* st, int slot) {
   rb.nu = false;
   rb.color_grads = st->g.sh != nullptr;
   rb.count_work = st->settings.count_work != 0;
+  rb.sort_here = false;
+  rb.bucket_keys = st->keys[0];
+  rb.tile_count = st->tile_count;
+  rb.counters = st->counters;
+  rb.tile_cap = (uint32_t)st->cap_tile_pairs;
   rb.views = ViewTable{st->io[slot].dev, st->n_views, (int32_t)st->g.n};
   rb.total_tiles = st->total_tiles;
   return rb;
@@ -510,9 +515,13 @@ cgsr_status render_impl(cgsr_state* st, const RenderArgs& a, hipStream_t stream)
   sb.ranges = st->ranges;
   sb.counters = st->counters;
   sb.cap = (uint32_t)st->cap_tile_pairs;
-  launch_segment_sort(sb, st->total_tiles, stream);
-  HIP_TRY(hipGetLastError());
-  st->tiles_dirty = false;
+  // A fused tracking step whose buckets hold at most one key per thread of
+  // its blend sorts each bucket inside the blend: one launch fewer.
+  const bool sort_here = a.track && a.fused && st->cap_tile_pairs <= kTilePixels / st->settings.fwd_pixels_per_lane;
+  if (!sort_here) {
+    launch_segment_sort(sb, st->total_tiles, stream);
+    HIP_TRY(hipGetLastError());
+  }
   if ((s = mark(CGSR_STAGE_BLEND_FWD))) return s;
   RasterBufs rb = raster_bufs(st, 0);
   rb.lambda_color = a.lambda_color;
@@ -521,9 +530,11 @@ cgsr_status render_impl(cgsr_state* st, const RenderArgs& a, hipStream_t stream)
   rb.nu = a.nu;
   rb.nu_sum = a.nu_sum;
   rb.nu_count = a.nu_count;
+  rb.sort_here = sort_here;
   if (a.track && a.fused) launch_raster_track(rb, st->settings.fwd_pixels_per_lane, stream);
   else launch_raster_forward(rb, a.track, st->settings.fwd_pixels_per_lane, stream);
   HIP_TRY(hipGetLastError());
+  st->tiles_dirty = false;
   if ((s = mark(CGSR_STAGE_BLEND_FWD + 1))) return s;
   st->fwd_timed = timed;
   st->tracked = a.track;

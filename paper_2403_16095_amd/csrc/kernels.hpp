@@ -114,8 +114,8 @@ void launch_clear_u32(uint32_t* p, int64_t n, hipStream_t s);
 
 struct RasterBufs {
   const float4* rec;
-  const uint32_t* vals;     // sorted record ids
-  const uint2* ranges;
+  uint32_t* vals;           // sorted record ids
+  uint2* ranges;
   uint4* pixel_state;       // [total pixels]: final T bits, entries up to the last blended one,
                             // median position or -1, alpha evaluations
   uint2* pixel_count;       // [total pixels]: Gaussians blended, entries of the wave's list up to the
@@ -138,6 +138,15 @@ struct RasterBufs {
   bool color_grads;
   // The fused tracking kernel keeps the per-pixel state and work counts.
   bool count_work;
+  // The fused tracking kernel sorts its tile's bucket itself (no separate
+  // segmented sort): every bucket holds at most one key per thread.  It then
+  // reads the buckets and pair counters and writes vals and ranges as that
+  // sort would.
+  bool sort_here;
+  const uint64_t* bucket_keys;   // [T][tile_cap]
+  uint32_t* tile_count;          // [T * kTileCounterStride], reset to zero here
+  uint32_t* counters;            // kCntRenderPeak reset here
+  uint32_t tile_cap;
 };
 // ppl: pixels per lane, 1, 2 or 4 (256 / ppl lanes per 16x16 tile).
 void launch_raster_forward(const RasterBufs& b, bool track, int ppl, hipStream_t s);

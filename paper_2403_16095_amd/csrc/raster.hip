@@ -91,17 +91,17 @@ __device__ __forceinline__ bool wave_reaches(int w, uint32_t cx0, uint32_t cx1, 
   return any;
 }
 
-// Stages list entries [first, first + n) of the tile, n <= kBatch, into each
-// wave's copy; every thread calls it.  pos0: the position of entry first in
+// Stages n <= kBatch entries of the tile's list, record ids ids[0, n), into
+// each wave's copy; every thread calls it.  pos0: the position of ids[0] in
 // the tile's list.  (tcx, tcy): the tile's first 8-pixel cell.  With one wave
 // per tile every record reaches it.
 template <int L, int W>
-__device__ __forceinline__ void stage_batch(const RasterBufs& b, Stage<W>& s, uint32_t first, uint32_t pos0, int n,
-                                            float2 org, uint32_t tcx, uint32_t tcy) {
+__device__ __forceinline__ void stage_batch(const RasterBufs& b, Stage<W>& s, const uint32_t* ids, uint32_t pos0,
+                                            int n, float2 org, uint32_t tcx, uint32_t tcy) {
   __syncthreads();
   if constexpr (W == 1) {
     for (int i = threadIdx.x; i < n; i += L) {
-      const uint32_t m = b.vals[first + i];
+      const uint32_t m = ids[i];
       s.M[0][i] = m;
       float4 C;
       stage_record(b.rec + (int64_t)kRecF4 * m, org.x, org.y, s.A[0][i], s.B[0][i], C);
@@ -118,7 +118,7 @@ __device__ __forceinline__ void stage_batch(const RasterBufs& b, Stage<W>& s, ui
     uint32_t take = 0, m = 0;
     float4 A, B, C;
     if (i < n) {
-      m = b.vals[first + i];
+      m = ids[i];
       stage_record(b.rec + (int64_t)kRecF4 * m, org.x, org.y, A, B, C);
       C.w = __int_as_float((int)(pos0 + i + 1));
       const uint2 r = b.rect[m];
@@ -175,9 +175,11 @@ struct FwdPix {
 // list.  With kFull off (a tracking step that keeps no statistics) the walk
 // keeps only what the tracking loss and the pose backward read: colour,
 // depth, transmittance and the last blended entry.
+// ids: the tile's record ids in list order.
 template <int kPPL, bool kTrack, bool kNu, bool kFull = true>
 __device__ __forceinline__ void forward_tile(const RasterBufs& b, Stage<kTilePixels / kPPL / kWave>& s, int gtile,
-                                             const ViewIO& io, float2 org, uint2 range, FwdPix<kPPL>& f) {
+                                             const ViewIO& io, float2 org, uint2 range, const uint32_t* ids,
+                                             FwdPix<kPPL>& f) {
   constexpr int L = kTilePixels / kPPL;
   constexpr int W = L / kWave;
   const int wv = threadIdx.x / kWave;
@@ -207,7 +209,7 @@ __device__ __forceinline__ void forward_tile(const RasterBufs& b, Stage<kTilePix
   }
   for (uint32_t base = range.x; base < range.y; base += kBatch) {
     const int n = (int)min((uint32_t)kBatch, range.y - base);
-    stage_batch<L, W>(b, s, base, base - range.x, n, org, tcx, tcy);
+    stage_batch<L, W>(b, s, ids + (base - range.x), base - range.x, n, org, tcx, tcy);
     // the copy's length is the same for the whole wave
     const int nw = (int)__builtin_amdgcn_readfirstlane(s.cnt[wv]);
     // The wave walks the whole batch while any of its lanes still blends;
@@ -382,7 +384,8 @@ __device__ __forceinline__ void backward_tile(const RasterBufs& b, Stage<kTilePi
   for (int end = nmax; end > 0; end -= kBatch) {
     const int start = max(0, end - kBatch);
     const int n = end - start;
-    if (!(start == 0 && end <= staged_n)) stage_batch<L, W>(b, s, range.x + start, start, n, org, tcx, tcy);
+    if (!(start == 0 && end <= staged_n))
+      stage_batch<L, W>(b, s, b.vals + range.x + start, start, n, org, tcx, tcy);
     for (int j = (int)__builtin_amdgcn_readfirstlane(s.cnt[wv]) - 1; j >= 0; --j) {
       const float4 A = s.A[wv][j];
       const float4 B = s.B[wv][j];
@@ -485,7 +488,8 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(Rast
   const int v = view_of_tile(b.views, gtile);
   const ViewIO io = b.views.io[v];
   FwdPix<kPPL> f;
-  forward_tile<kPPL, kTrack, kNu>(b, s, gtile, io, tile_origin(io.info, gtile), b.ranges[gtile], f);
+  const uint2 range = b.ranges[gtile];
+  forward_tile<kPPL, kTrack, kNu>(b, s, gtile, io, tile_origin(io.info, gtile), range, b.vals + range.x, f);
   float g[kPPL][4];
   forward_outputs<kPPL, kTrack, kNu>(b, v, io, f, g, true);
 }
@@ -543,24 +547,60 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
   backward_tile<kPPL, kParams, kTrack, kColor>(b, s, b.ranges[gtile], tile_origin(cam, gtile), nmax, 0, p);
 }
 
+// The tile's bucket, at most L keys, sorted by the workgroup itself: a
+// key's rank is the number of keys below it (keys are unique), so the ids
+// come out in (depth, id) order as the segmented sort leaves them.  The
+// bucket is read whole while its count is still in flight, so the ranking
+// waits for one memory round trip, not two.  Leaves the ids in ids (LDS) and
+// in the sorted list, writes the tile's range and resets its counter, as the
+// segmented sort does.
+template <int L>
+__device__ __forceinline__ uint2 sort_own_bucket(const RasterBufs& b, int gtile, uint64_t* s_key, uint32_t* ids,
+                                                 uint32_t* s_n) {
+  const uint64_t base = (uint64_t)gtile * b.tile_cap;
+  uint32_t* counter = b.tile_count + (size_t)gtile * kTileCounterStride;
+  const uint64_t key = threadIdx.x < b.tile_cap ? b.bucket_keys[base + threadIdx.x] : 0ull;
+  if (threadIdx.x == 0) {
+    const uint32_t n = min(*counter, b.tile_cap);   // beyond the bucket only after an overflow, which is reported
+    *counter = 0u;
+    *s_n = n;
+    b.ranges[gtile] = make_uint2((uint32_t)base, (uint32_t)(base + n));
+    if (gtile == 0) b.counters[kCntRenderPeak] = 0u;
+  }
+  s_key[threadIdx.x] = key;
+  __syncthreads();
+  const uint32_t n = *s_n;
+  if (threadIdx.x < n) {
+    uint32_t rank = 0;
+    for (uint32_t i = 0; i < n; ++i) rank += s_key[i] < key ? 1u : 0u;
+    ids[rank] = (uint32_t)key;
+    b.vals[base + rank] = (uint32_t)key;
+  }
+  __syncthreads();
+  return make_uint2((uint32_t)base, (uint32_t)(base + n));
+}
+
 // Tracking iteration of one tile: forward, tracking-loss gradients in
 // registers, pose backward (kColor: with the colour gradients that the pose
 // gradient of a view-dependent colour needs; kFull: also the per-pixel state
 // and work counts that the statistics read).
 template <int kPPL, bool kColor, bool kFull>
 __global__ __launch_bounds__(kTilePixels / kPPL) void raster_track_kernel(RasterBufs b) {
+  constexpr int L = kTilePixels / kPPL;
   __shared__ Stage<kTilePixels / kPPL / kWave> s;
   __shared__ uint32_t s_max;
+  __shared__ uint64_t s_key[L];
+  __shared__ uint32_t s_ids[L];
   const int gtile = blockIdx.x;
   const int v = view_of_tile(b.views, gtile);
   const ViewIO io = b.views.io[v];
   const float2 org = tile_origin(io.info, gtile);
-  const uint2 range = b.ranges[gtile];
+  const uint2 range = b.sort_here ? sort_own_bucket<L>(b, gtile, s_key, s_ids, &s_max) : b.ranges[gtile];
   BwdPix<kPPL> p;
   uint32_t lane_max = 0;
   {
     FwdPix<kPPL> f;
-    forward_tile<kPPL, true, false, kFull>(b, s, gtile, io, org, range, f);
+    forward_tile<kPPL, true, false, kFull>(b, s, gtile, io, org, range, b.sort_here ? s_ids : b.vals + range.x, f);
     float g[kPPL][4];
     forward_outputs<kPPL, true, false, kFull>(b, v, io, f, g, false);
 #pragma unroll

@@ -537,7 +537,9 @@ def test_tracking_step_without_work_counts(R):
     """count_work = 0 (the fused step keeps only colour, depth, transmittance
     and the last blended entry per pixel) gives the same losses, poses and
     pose gradients as the counting kernel; its statistics report the work
-    counts as unknown (-1)."""
+    counts as unknown (-1).  Buckets of at most one key per thread are sorted
+    inside the fused kernel, larger ones by the segmented sort: both give the
+    same steps."""
     say("case: tracking step with and without work counts, 2 frames")
     sc = synth.room_scene(5, 30_000, (5.0, 4.0, 3.0))
     cams = [synth.camera(320, 240, 262.5, 262.5, 160, 120), synth.camera(160, 128, 131.25, 131.25, 80, 64)]
@@ -550,8 +552,10 @@ def test_tracking_step_without_work_counts(R):
     td = [t["depth"].clone() for t in tg]
     P0 = torch.stack([R.pose_tensor(*synth.perturb_pose(*p, 40 + k)) for k, p in enumerate(tgt_poses)])
     out = {}
-    for count in (True, False):
+    for count, big in ((True, False), (False, False), (False, True)):
         st = R.State(count_work=count)
+        if big:
+            st.reserve(tile_pairs=600)   # more than the 256 threads of a tile's workgroup
         P, adam = P0.clone(), torch.zeros((2, 16), device="cuda")
         losses = []
         for it in range(3):
@@ -560,8 +564,15 @@ def test_tracking_step_without_work_counts(R):
             losses.append(L.cpu().tolist())
         dposes = torch.zeros((2, 6), device="cuda")
         R.tracking_step(st, scd, P0, cams, tc, td, dposes=dposes)
-        out[count] = (np.array(losses), P.cpu(), dposes.cpu(), st.stats())
-    (l1, p1, d1, s1), (l0, p0, d0, s0) = out[True], out[False]
+        stats = st.stats()
+        assert (stats.pair_capacity > 256) == big
+        out[(count, big)] = (np.array(losses), P.cpu(), dposes.cpu(), stats)
+    (l1, p1, d1, s1), (l0, p0, d0, s0) = out[(True, False)], out[(False, False)]
+    lb, pb, db, sb = out[(False, True)]
+    np.testing.assert_allclose(lb, l1, rtol=1e-6)
+    assert (pb - p1).abs().max().item() < 1e-6
+    assert ((db - d1).abs().max() / d1.abs().max()).item() < 1e-5
+    assert sb.pairs == s1.pairs
     np.testing.assert_allclose(l0, l1, rtol=1e-6)
     assert (p0 - p1).abs().max().item() < 1e-6
     e = ((d0 - d1).abs().max() / d1.abs().max()).item()
