@@ -327,8 +327,9 @@ typedef struct {
  * retraction T <- exp(delta^) T (Sec. 3.4, Eq. 20; Adam with bias correction).
  *   poses      device float[n_views][12], updated in place.
  *   dposes     device float[n_views][6], read then zeroed.
- *   adam       device float[n_views][16]: m[6], v[6], step count, 3 unused;
- *              zero-initialise before the first step.
+ *   adam       device float[n_views][16]: m[6], v[6], step count,
+ *              1 - beta1^step, 1 - beta2^step, 1 unused; zero-initialise
+ *              before the first step.
  */
 cgsr_status cgsr_pose_adam_step(int32_t n_views, float *poses, float *dposes, float *adam,
                                 const cgsr_adam_params *params, void *stream);

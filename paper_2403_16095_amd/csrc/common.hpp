@@ -223,52 +223,67 @@ struct AdamParams {
 // One Adam step (bias-corrected) on a pose's tangent vector xi = (rho, phi),
 // whose value is zero at the current pose, so the step is
 // delta = -lr m_hat / (sqrt(v_hat) + eps); then the left retraction
-// T <- exp(delta^) T with the closed-form SE(3) exponential.
-// P: pose[12] (row-major R, t); st: m[6], v[6], step count; g: gradient.
-__device__ inline void adam_retract(float* P, float* st, const float g[6], const AdamParams& ap) {
+// T <- exp(delta^) T with the closed-form SE(3) exponential.  One wave per
+// pose: lane k < 6 holds gradient component g and updates its own moments;
+// lane 0 writes the pose.  P: pose[12] (row-major R, t); st: m[6], v[6], step
+// count, 1 - beta1^step, 1 - beta2^step (all zero before the first step: the
+// bias corrections are kept as running values, c <- beta c + 1 - beta).
+__device__ inline void adam_retract_wave(float* P, float* st, float g, const AdamParams& ap) {
+  const int k = __lane_id();
   const float step = st[12] + 1.f;
-  st[12] = step;
-  const float c1 = 1.f - powf(ap.beta1, step), c2 = 1.f - powf(ap.beta2, step);
-  float d[6];
-  for (int k = 0; k < 6; ++k) {
-    const float m = ap.beta1 * st[k] + (1.f - ap.beta1) * g[k];
-    const float s = ap.beta2 * st[6 + k] + (1.f - ap.beta2) * g[k] * g[k];
+  const float c1 = __builtin_fmaf(ap.beta1, st[13], 1.f - ap.beta1);
+  const float c2 = __builtin_fmaf(ap.beta2, st[14], 1.f - ap.beta2);
+  float d = 0.f;
+  if (k < 6) {
+    const float m = ap.beta1 * st[k] + (1.f - ap.beta1) * g;
+    const float s = ap.beta2 * st[6 + k] + (1.f - ap.beta2) * g * g;
     st[k] = m;
     st[6 + k] = s;
     const float lr = k < 3 ? ap.lr_rho : ap.lr_phi;
-    d[k] = -lr * (m / c1) / (sqrtf(s / c2) + ap.eps);
+    d = -lr * (m / c1) / (sqrtf(s / c2) + ap.eps);
   }
+  float dl[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) dl[j] = __shfl(d, j);
+  if (k != 0) return;
+  st[12] = step;
+  st[13] = c1;
+  st[14] = c2;
   // exp of (rho, phi): R = I + A K + B K^2, V = I + B K + C K^2, K = [phi]x.
-  const float p0 = d[3], p1 = d[4], p2 = d[5];
+  const float p0 = dl[3], p1 = dl[4], p2 = dl[5];
   const float th2 = p0 * p0 + p1 * p1 + p2 * p2;
+  // Below 0.1 rad (every step of a converging solve) the series, whose next
+  // terms are under 1e-9; the closed forms there lose digits to cancellation.
   float A, Bc, Cc;
-  if (th2 < 1e-8f) {
-    A = 1.f - th2 / 6.f;
-    Bc = 0.5f - th2 / 24.f;
-    Cc = 1.f / 6.f - th2 / 120.f;
+  if (th2 < 1e-2f) {
+    A = 1.f - th2 / 6.f * (1.f - th2 / 20.f);
+    Bc = 0.5f - th2 / 24.f * (1.f - th2 / 30.f);
+    Cc = 1.f / 6.f - th2 / 120.f * (1.f - th2 / 42.f);
   } else {
     const float th = sqrtf(th2);
-    A = sinf(th) / th;
-    Bc = (1.f - cosf(th)) / th2;
-    Cc = (th - sinf(th)) / (th2 * th);
+    float sn, cs;
+    sincosf(th, &sn, &cs);
+    A = sn / th;
+    Bc = (1.f - cs) / th2;
+    Cc = (th - sn) / (th2 * th);
   }
   const float K[9] = {0.f, -p2, p1, p2, 0.f, -p0, -p1, p0, 0.f};
   float K2[9], R[9], V[9];
   for (int r = 0; r < 3; ++r)
     for (int c = 0; c < 3; ++c) K2[3 * r + c] = K[3 * r] * K[c] + K[3 * r + 1] * K[3 + c] + K[3 * r + 2] * K[6 + c];
-  for (int k = 0; k < 9; ++k) {
-    const float I = (k % 4 == 0) ? 1.f : 0.f;
-    R[k] = I + A * K[k] + Bc * K2[k];
-    V[k] = I + Bc * K[k] + Cc * K2[k];
+  for (int q = 0; q < 9; ++q) {
+    const float I = (q % 4 == 0) ? 1.f : 0.f;
+    R[q] = I + A * K[q] + Bc * K2[q];
+    V[q] = I + Bc * K[q] + Cc * K2[q];
   }
   float Rn[9], tn[3];
   for (int r = 0; r < 3; ++r) {
     for (int c = 0; c < 3; ++c) Rn[3 * r + c] = R[3 * r] * P[c] + R[3 * r + 1] * P[3 + c] + R[3 * r + 2] * P[6 + c];
-    tn[r] = R[3 * r] * P[9] + R[3 * r + 1] * P[10] + R[3 * r + 2] * P[11] + V[3 * r] * d[0] + V[3 * r + 1] * d[1] +
-            V[3 * r + 2] * d[2];
+    tn[r] = R[3 * r] * P[9] + R[3 * r + 1] * P[10] + R[3 * r + 2] * P[11] + V[3 * r] * dl[0] + V[3 * r + 1] * dl[1] +
+            V[3 * r + 2] * dl[2];
   }
-  for (int k = 0; k < 9; ++k) P[k] = Rn[k];
-  for (int k = 0; k < 3; ++k) P[9 + k] = tn[k];
+  for (int q = 0; q < 9; ++q) P[q] = Rn[q];
+  for (int q = 0; q < 3; ++q) P[9 + q] = tn[q];
 }
 
 }  // namespace cgsr

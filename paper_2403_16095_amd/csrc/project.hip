@@ -586,19 +586,19 @@ __global__ __launch_bounds__(kThreads) void project_backward_kernel(GaussianPtrs
   }
 }
 
-// One lane per view: hands the summed pose gradient to the caller (dposes
-// +=) and/or to an Adam step with retraction, and clears the accumulator.
-__global__ void pose_finalize_kernel(double* pose_acc, float* dposes, int n_views, float* poses, float* adam,
-                                     AdamParams ap) {
-  const int v = threadIdx.x;
-  if (v >= n_views) return;
-  float g[6];
-  for (int k = 0; k < 6; ++k) {
-    g[k] = (float)pose_acc[6 * v + k];
+// One wave per view, lane k on component k: hands the summed pose gradient
+// to the caller (dposes +=) and/or to an Adam step with retraction, and
+// clears the accumulator.
+__global__ __launch_bounds__(64) void pose_finalize_kernel(double* pose_acc, float* dposes, float* poses, float* adam,
+                                                           AdamParams ap) {
+  const int v = blockIdx.x, k = threadIdx.x;
+  float g = 0.f;
+  if (k < 6) {
+    g = (float)pose_acc[6 * v + k];
     pose_acc[6 * v + k] = 0.0;
-    if (dposes) dposes[6 * v + k] += g[k];
+    if (dposes) dposes[6 * v + k] += g;
   }
-  if (adam) adam_retract(poses + 12 * v, adam + 16 * v, g, ap);
+  if (adam) adam_retract_wave(poses + 12 * v, adam + 16 * v, g, ap);
 }
 
 }  // namespace
@@ -618,7 +618,7 @@ void launch_project_backward(const GaussianPtrs& g, const float* poses, const Vi
   hipLaunchKernelGGL(project_backward_kernel, grid, dim3(kThreads), 0, s, g, poses, vt, rec_grad, tiles, dg,
                      param_grads ? 1 : 0, vt.n > 1 ? 1 : 0, pose ? pose_acc : nullptr, dens_grad, dens_count);
   if (pose)
-    hipLaunchKernelGGL(pose_finalize_kernel, dim3(1), dim3(64), 0, s, pose_acc, dposes, vt.n,
+    hipLaunchKernelGGL(pose_finalize_kernel, dim3((unsigned)vt.n), dim3(64), 0, s, pose_acc, dposes,
                        step ? step->poses : nullptr, step ? step->adam : nullptr,
                        step ? step->params : AdamParams{0.f, 0.f, 0.f, 0.f, 1.f});
 }

@@ -74,17 +74,17 @@ __global__ __launch_bounds__(kThreads) void mapping_loss_kernel(int w, int h, co
   if (threadIdx.x == 0) atomicAdd(loss, s_part[0] + s_part[1] + s_part[2] + s_part[3]);
 }
 
-// One lane per view: Adam step and retraction (adam_retract), then the
-// gradient buffer is cleared for the next iteration.
-__global__ void pose_adam_kernel(int n_views, float* poses, float* dposes, float* adam, AdamParams ap) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n_views) return;
-  float g[6];
-  for (int k = 0; k < 6; ++k) {
-    g[k] = dposes[6 * v + k];
+// One wave per view, lane k on component k: Adam step and retraction
+// (adam_retract_wave), then the gradient buffer is cleared for the next
+// iteration.
+__global__ __launch_bounds__(64) void pose_adam_kernel(float* poses, float* dposes, float* adam, AdamParams ap) {
+  const int v = blockIdx.x, k = threadIdx.x;
+  float g = 0.f;
+  if (k < 6) {
+    g = dposes[6 * v + k];
     dposes[6 * v + k] = 0.f;
   }
-  adam_retract(poses + 12 * v, adam + 16 * v, g, ap);
+  adam_retract_wave(poses + 12 * v, adam + 16 * v, g, ap);
 }
 
 // nu_i = nu_sum_i / (M_1 + ... + M_k) (Eq. 13), 0 for a Gaussian that
@@ -214,7 +214,7 @@ void launch_gaussian_adam(int64_t n, const GaussianAdam& a, float* moments, uint
 }
 
 void launch_pose_adam(int n_views, float* poses, float* dposes, float* adam, const AdamParams& ap, hipStream_t s) {
-  hipLaunchKernelGGL(pose_adam_kernel, dim3(1), dim3(64), 0, s, n_views, poses, dposes, adam, ap);
+  hipLaunchKernelGGL(pose_adam_kernel, dim3((unsigned)n_views), dim3(64), 0, s, poses, dposes, adam, ap);
 }
 
 void launch_stats(const uint32_t* tiles, int64_t m, const uint4* pixel_state, const uint2* pixel_count,
