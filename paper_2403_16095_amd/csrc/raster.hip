@@ -348,7 +348,7 @@ template <int kPPL>
 struct BwdPix {
   float fx[kPPL], fy[kPPL], T[kPPL], gc0[kPPL], gc1[kPPL], gc2[kPPL], gd[kPPL], go[kPPL], gm[kPPL], gu[kPPL],
       dobs[kPPL];
-  float Bc0[kPPL], Bc1[kPPL], Bc2[kPPL], Bd[kPPL], Bo[kPPL], Bu[kPPL];
+  float Bg[kPPL];   // sum_x g_x Bx, the behind sums weighted by the pixel's upstream gradients
   int walked[kPPL], med1[kPPL];   // one past the last blended entry's / the median's position (0: none)
 };
 
@@ -363,9 +363,13 @@ __device__ __forceinline__ int block_max(uint32_t lane_max, uint32_t* s_max) {
 }
 
 // Back-to-front over each pixel's blended run.  With the normalised "behind"
-// sums Bx = sum_{k>j} w_k x_k / T_{j+1}, dL/dalpha_j = T_j sum_x g_x (x_j - Bx),
-// and Bx <- alpha_j x_j + (1 - alpha_j) Bx moves the sums one Gaussian forward;
-// T_j = T_{j+1} / (1 - alpha_j) recovers the transmittance from the final one.
+// sums Bx = sum_{k>j} w_k x_k / T_{j+1}, dL/dalpha_j = T_j sum_x g_x (x_j - Bx)
+// = T_j (G_j - Bg) with G_j = sum_x g_x x_j and Bg = sum_x g_x Bx; since every
+// Bx moves one Gaussian forward as Bx <- alpha_j x_j + (1 - alpha_j) Bx and
+// the g_x are fixed per pixel, so does Bg <- alpha_j G_j + (1 - alpha_j) Bg,
+// one running sum for all the quantities x (colour, depth, opacity,
+// uncertainty).  T_j = T_{j+1} / (1 - alpha_j) recovers the transmittance
+// from the final one.
 // A lane first sums its pixels' contributions to a Gaussian, then the wave
 // reduces all of the Gaussian's gradient terms together (wave_sum_many) and
 // issues one atomic instruction.  kParams adds the opacity and colour
@@ -414,20 +418,15 @@ __device__ __forceinline__ void backward_tile(const RasterBufs& b, Stage<kTilePi
         const float oma = 1.f - alpha;
         const float Tj = p.T[k] * __builtin_amdgcn_rcpf(oma);
         const float wgt = alpha * Tj;
-        float dsum = p.gc0[k] * (Cc.x - p.Bc0[k]) + p.gc1[k] * (Cc.y - p.Bc1[k]) + p.gc2[k] * (Cc.z - p.Bc2[k]) +
-                     p.gd[k] * (B.z - p.Bd[k]);
-        p.Bc0[k] = __builtin_fmaf(alpha, Cc.x, oma * p.Bc0[k]);
-        p.Bc1[k] = __builtin_fmaf(alpha, Cc.y, oma * p.Bc1[k]);
-        p.Bc2[k] = __builtin_fmaf(alpha, Cc.z, oma * p.Bc2[k]);
-        p.Bd[k] = __builtin_fmaf(alpha, B.z, oma * p.Bd[k]);
+        float G = __builtin_fmaf(p.gc0[k], Cc.x,
+                                 __builtin_fmaf(p.gc1[k], Cc.y, __builtin_fmaf(p.gc2[k], Cc.z, p.gd[k] * B.z)));
         float dz = 0.f;
         if (!kTrack) {
           dz = B.z - p.dobs[k];
-          const float u = dz * dz;
-          dsum += p.go[k] * (1.f - p.Bo[k]) + p.gu[k] * (u - p.Bu[k]);
-          p.Bo[k] = __builtin_fmaf(alpha, 1.f, oma * p.Bo[k]);
-          p.Bu[k] = __builtin_fmaf(alpha, u, oma * p.Bu[k]);
+          G = __builtin_fmaf(p.gu[k], dz * dz, G + p.go[k]);
         }
+        const float dsum = G - p.Bg[k];
+        p.Bg[k] = __builtin_fmaf(alpha, G, oma * p.Bg[k]);
         const float dalpha = Tj * dsum;
         p.T[k] = Tj;
         const bool live = hit && !(raw > kAlphaMax);   // a capped alpha has no gradient
@@ -516,7 +515,7 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
     p.walked[k] = 0;
     p.med1[k] = 0;
     p.gc0[k] = p.gc1[k] = p.gc2[k] = p.gd[k] = p.go[k] = p.gm[k] = p.gu[k] = p.dobs[k] = 0.f;
-    p.Bc0[k] = p.Bc1[k] = p.Bc2[k] = p.Bd[k] = p.Bo[k] = p.Bu[k] = 0.f;
+    p.Bg[k] = 0.f;
     if (pc.inside) {
       const uint4 ps = b.pixel_state[cam.pixel_base + pix];
       p.T[k] = __uint_as_float(ps.x);
@@ -615,7 +614,7 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_track_kernel(Raster
       p.gc2[k] = g[k][2];
       p.gd[k] = g[k][3];
       p.go[k] = p.gm[k] = p.gu[k] = p.dobs[k] = 0.f;
-      p.Bc0[k] = p.Bc1[k] = p.Bc2[k] = p.Bd[k] = p.Bo[k] = p.Bu[k] = 0.f;
+      p.Bg[k] = 0.f;
       lane_max = max(lane_max, (uint32_t)p.walked[k]);
     }
   }
