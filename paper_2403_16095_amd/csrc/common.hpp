@@ -81,12 +81,12 @@ constexpr int kGradStride = 12;  // floats per record (48 B, 16-B aligned)
 // A record as the blend kernels stage it in LDS, once per (tile, record):
 //   a = (mu_x, mu_y, qa, k)        mean relative to the tile origin (ox, oy),
 //                                  qa = -a/2 log2(e)
-//   b = (qc, opacity, depth, thr)  qc = -c'/2 log2(e), thr = -log2(255 opacity)
-//   c = (r, g, b, -)
-// so that the exponent of Eq. 5 in base 2 is qa (dx + k dy)^2 + qc dy^2 and a
-// pair is skipped (alpha < 1/255) exactly when that exponent is below thr.
-// The forward and the backward stage and evaluate with these same functions
-// (the library is built without floating-point contraction, every fused
+//   b = (qc, opacity, depth, pos)  qc = -c'/2 log2(e); pos: the staging's
+//   c = (r, g, b, id)              list position and record id (int bits)
+// so that the exponent of Eq. 5 in base 2 is qa (dx + k dy)^2 + qc dy^2, and
+// alpha = opacity 2^exponent (skipped below 1/255, capped at 0.99).  The
+// forward and the backward stage and evaluate with these same functions (the
+// library is built without floating-point contraction, every fused
 // multiply-add is explicit), so they take identical skip, cap and stop
 // decisions.
 constexpr float kLog2e = 1.4426950408889634f;
@@ -102,7 +102,7 @@ __device__ __forceinline__ void stage_record(const float4* __restrict__ rec, flo
                                              float4& C) {
   const float4 r0 = rec[0], r1 = rec[1], r2 = rec[2];
   A = make_float4((r0.x - ox) + r2.z, (r0.y - oy) + r2.w, (-0.5f * kLog2e) * r0.z, r0.w);
-  B = make_float4((-0.5f * kLog2e) * r1.x, r1.y, r1.z, -__log2f(255.0f * r1.y));
+  B = make_float4((-0.5f * kLog2e) * r1.x, r1.y, r1.z, 0.f);
   C = make_float4(r1.w, r2.x, r2.y, 0.f);
 }
 

@@ -66,12 +66,12 @@ __device__ __forceinline__ float sgn(float x) { return (float)((x > 0.f) - (x < 
 
 // The LDS batch of staged records (see stage_record) and their record ids,
 // one compacted copy per wave (W waves per tile), and each copy's length.
-// C.w of a staged record holds one past its position in the tile's list (as
-// int bits), so a walk compares it with its pixel's bounds without arithmetic.
+// B.w of a staged record holds one past its position in the tile's list and
+// C.w its record id (as int bits), so a walk compares the position with its
+// pixel's bounds without arithmetic and reads the id with the record.
 template <int W>
 struct Stage {
   float4 A[W][kBatch], B[W][kBatch], C[W][kBatch];
-  uint32_t M[W][kBatch];
   uint32_t cnt[W];
   uint32_t scan[4];
 };
@@ -102,10 +102,11 @@ __device__ __forceinline__ void stage_batch(const RasterBufs& b, Stage<W>& s, co
   if constexpr (W == 1) {
     for (int i = threadIdx.x; i < n; i += L) {
       const uint32_t m = ids[i];
-      s.M[0][i] = m;
-      float4 C;
-      stage_record(b.rec + (int64_t)kRecF4 * m, org.x, org.y, s.A[0][i], s.B[0][i], C);
-      C.w = __int_as_float((int)(pos0 + i + 1));
+      float4 B, C;
+      stage_record(b.rec + (int64_t)kRecF4 * m, org.x, org.y, s.A[0][i], B, C);
+      B.w = __int_as_float((int)(pos0 + i + 1));
+      C.w = __uint_as_float(m);
+      s.B[0][i] = B;
       s.C[0][i] = C;
     }
     if (threadIdx.x == 0) s.cnt[0] = (uint32_t)n;
@@ -120,7 +121,8 @@ __device__ __forceinline__ void stage_batch(const RasterBufs& b, Stage<W>& s, co
     if (i < n) {
       m = ids[i];
       stage_record(b.rec + (int64_t)kRecF4 * m, org.x, org.y, A, B, C);
-      C.w = __int_as_float((int)(pos0 + i + 1));
+      B.w = __int_as_float((int)(pos0 + i + 1));
+      C.w = __uint_as_float(m);
       const uint2 r = b.rect[m];
       const uint32_t cx0 = r.x & 0xFFFFu, cx1 = r.x >> 16, cy0 = r.y & 0xFFFFu, cy1 = r.y >> 16;
 #pragma unroll
@@ -148,7 +150,6 @@ __device__ __forceinline__ void stage_batch(const RasterBufs& b, Stage<W>& s, co
         s.A[w][d] = A;
         s.B[w][d] = B;
         s.C[w][d] = C;
-        s.M[w][d] = m;
       }
     if (threadIdx.x < W) s.cnt[threadIdx.x] = (total >> (8 * threadIdx.x)) & 0xFFu;
   }
@@ -221,7 +222,7 @@ __device__ __forceinline__ void forward_tile(const RasterBufs& b, Stage<kTilePix
         const float4 A = s.A[wv][j];
         const float4 B = s.B[wv][j];
         const float4 Cc = s.C[wv][j];
-        const uint32_t pos1 = (uint32_t)__float_as_int(Cc.w);   // one past its position in the tile's list
+        const uint32_t pos1 = (uint32_t)__float_as_int(B.w);   // one past its position in the tile's list
         // Straight-line, predicated per lane: a lane that skips (alpha below
         // 1/255, or already done) adds exact zeros, so the results are those
         // of the branching form, without exec-mask bookkeeping per record.
@@ -229,8 +230,9 @@ __device__ __forceinline__ void forward_tile(const RasterBufs& b, Stage<kTilePix
         for (int k = 0; k < kPPL; ++k) {
           float dx, dy, tq;
           const float e = pair_exponent(A, B, f.fx[k], f.fy[k], dx, dy, tq);
-          const bool hit = !f.done[k] && e >= B.w;
-          const float alpha = fminf(kAlphaMax, B.y * __builtin_amdgcn_exp2f(e));
+          const float raw = B.y * __builtin_amdgcn_exp2f(e);
+          const bool hit = !f.done[k] && raw >= kAlphaMin;
+          const float alpha = fminf(kAlphaMax, raw);
           const float Tn = f.T[k] * (1.f - alpha);
           const bool stop = hit && Tn < kTStop;
           const bool blend = hit && !stop;
@@ -255,7 +257,7 @@ __device__ __forceinline__ void forward_tile(const RasterBufs& b, Stage<kTilePix
             const bool more = blend && wgt > f.wdom[k];   // strict: the first of equal maxima
             f.wdom[k] = more ? wgt : f.wdom[k];
             f.ddom[k] = more ? B.z : f.ddom[k];
-            f.dom[k] = more ? s.M[wv][j] : f.dom[k];
+            f.dom[k] = more ? __float_as_uint(Cc.w) : f.dom[k];
           }
           f.T[k] = blend ? Tn : f.T[k];
           f.last[k] = blend ? pos1 : f.last[k];
@@ -397,11 +399,8 @@ __device__ __forceinline__ void backward_tile(const RasterBufs& b, Stage<kTilePi
       float gr = 0.f, gg = 0.f, gbl = 0.f;
       bool any = false;
       const float4 Cc = s.C[wv][j];
-      const int pos1 = __float_as_int(Cc.w);   // one past its position in the tile's list
-      const uint32_t m = s.M[wv][j];
-      // Keep this read beside the record's: left to the compiler it moves
-      // into the branch below and the next record's reads wait for it.
-      asm volatile("" : : "v"(m));
+      const int pos1 = __float_as_int(B.w);   // one past its position in the tile's list
+      const uint32_t m = __float_as_uint(Cc.w);
       // Straight-line, predicated per lane: a lane that did not blend this
       // record (past its last blended one, or alpha below 1/255) takes
       // alpha = 0, which leaves T and the behind sums exactly unchanged and
@@ -410,10 +409,10 @@ __device__ __forceinline__ void backward_tile(const RasterBufs& b, Stage<kTilePi
       for (int k = 0; k < kPPL; ++k) {
         float dx, dy, tq;
         const float e = pair_exponent(A, B, p.fx[k], p.fy[k], dx, dy, tq);
-        const bool hit = pos1 <= p.walked[k] && e >= B.w;
-        any = any || hit;
         const float g = __builtin_amdgcn_exp2f(e);
         const float raw = B.y * g;
+        const bool hit = pos1 <= p.walked[k] && raw >= kAlphaMin;
+        any = any || hit;
         const float alpha = hit ? fminf(kAlphaMax, raw) : 0.f;
         const float oma = 1.f - alpha;
         const float Tj = p.T[k] * __builtin_amdgcn_rcpf(oma);
