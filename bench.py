@@ -638,6 +638,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stage-timing", action="store_true")
+    ap.add_argument("--ppl", type=int, default=0, choices=(0, 1, 2, 4),
+                    help="pixels per lane of the tracking blend (0: autotune)")
     ap.add_argument("--eager", action="store_true",
                     help="run the solves without graph capture (same kernels; for counter collection)")
     ap.add_argument("--sh-degree", type=int, default=0, choices=(0, 1, 2, 3),
@@ -680,11 +682,15 @@ def main():
     log("building workload: 100k Gaussians, 640x480" + (f", SH degree {deg}" if deg else ""))
     sc, prob, P0, true_pose = build_workload(torch, R, synth, sh_degree=deg)
     iters = args.solve_iters
-    tune_state = R.State()
-    fppl, bppl = R.autotune_tracking(tune_state, prob.scene, P0, [prob.cam], [prob.target_color],
-                                     [prob.target_depth])
-    del tune_state
-    log(f"autotuned pixels per lane: forward {fppl}, backward {bppl}")
+    if args.ppl:
+        fppl = bppl = args.ppl
+        log(f"pixels per lane: {fppl} (fixed)")
+    else:
+        tune_state = R.State()
+        fppl, bppl = R.autotune_tracking(tune_state, prob.scene, P0, [prob.cam], [prob.target_color],
+                                         [prob.target_depth])
+        del tune_state
+        log(f"autotuned pixels per lane: forward {fppl}, backward {bppl}")
     solver = R.TrackingSolver(prob, iters=iters, use_graph=not args.eager, reset_pose=P0, fwd_ppl=fppl,
                               bwd_ppl=bppl)
     solver.prepare(P0)
