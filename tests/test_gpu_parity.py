@@ -583,6 +583,52 @@ def test_tracking_step_without_work_counts(R):
     assert s0.visible == s1.visible and s0.pairs == s1.pairs and s0.peak_pairs == s1.peak_pairs
 
 
+def test_tracking_step_bucket_capacity(R):
+    """The fused tracking step (which sorts its own tile buckets when they
+    hold at most one key per thread) with buckets exactly as large as the
+    fullest tile gives the gradient it gives with roomy ones; with smaller
+    buckets the dropped pairs are reported: the statistics give the count
+    the fullest tile needed and the next check raises the capacity error."""
+    from paper_2403_16095_amd import binding as B
+    say("case: tracking step bucket capacity, 30k Gaussians 320x240")
+    sc = synth.room_scene(6, 30_000, (5.0, 4.0, 3.0))
+    cam = synth.camera(320, 240, 262.5, 262.5, 160, 120)
+    scd = dev(sc)
+    tgt = synth.level_room_pose(25)
+    ref_st = R.State()
+    tg = R.render(ref_st, scd, R.pose_tensor(*tgt).reshape(1, 12), [cam])[0]
+    tc, td = tg["color"].clone(), tg["depth"].clone()
+    P0 = R.pose_tensor(*synth.perturb_pose(*tgt, 50)).reshape(1, 12)
+
+    def step(st):
+        d = torch.zeros((1, 6), device="cuda")
+        R.tracking_step(st, scd, P0, [cam], [tc], [td], dposes=d)
+        torch.cuda.synchronize()
+        return d
+
+    roomy = R.State(sync_capacity=False)
+    roomy.reserve(tile_pairs=256)
+    d_ref = step(roomy)
+    peak = roomy.stats().peak_pairs
+    roomy.check()
+    say("fullest tile", peak)
+    assert 64 < peak <= 256, "the case needs a fullest tile between the smallest bucket and 256 pairs"
+    exact = R.State(sync_capacity=False)
+    exact.reserve(tile_pairs=peak)
+    d_ex = step(exact)
+    assert exact.stats().pair_capacity == peak
+    exact.check()
+    assert ((d_ex - d_ref).abs().max() / d_ref.abs().max()).item() < 1e-5
+    small = R.State(sync_capacity=False)
+    small.reserve(tile_pairs=max(64, peak // 2))
+    step(small)
+    s = small.stats()
+    assert s.overflow == 1 and s.peak_pairs == peak
+    with pytest.raises(B.CgsrError) as e:
+        small.check()
+    assert e.value.status == B.CGSR_ERR_CAPACITY
+
+
 def test_graph_tracking_replays_match_eager(R):
     """The captured 50-iteration tracking solve replayed several times, with
     eager work in between, matches the same loop run eagerly."""
