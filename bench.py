@@ -514,7 +514,8 @@ def run_batched_tracking(args, torch, R, synth, frames=32, iters=20):
         pose = torch.empty((V, 12), device="cuda")
         pose0 = P0[vs].contiguous()
         adam = torch.zeros((V, 16), device="cuda")
-        st = R.State(sync_capacity=True)
+        # the solve reads no work counts (only pair peaks and overflow)
+        st = R.State(sync_capacity=True, count_work=False)
         cs = [cam_s[v] for v in vs]
         tc = [tcs[v].data_ptr() for v in vs]
         td = [tds[v].data_ptr() for v in vs]
