@@ -587,8 +587,12 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_track_kernel(Raster
   constexpr int L = kTilePixels / kPPL;
   __shared__ Stage<kTilePixels / kPPL / kWave> s;
   __shared__ uint32_t s_max;
-  __shared__ uint64_t s_key[L];
   __shared__ uint32_t s_ids[L];
+  // The bucket's keys are ranked before the first batch is staged, so they
+  // share the stage's storage (keeping the workgroup's LDS at 25.6 KB, six
+  // workgroups per CU at one pixel per lane).
+  static_assert(sizeof(s.A) >= sizeof(uint64_t) * L, "sort keys fit the stage");
+  uint64_t* s_key = reinterpret_cast<uint64_t*>(&s.A[0][0]);
   const int gtile = blockIdx.x;
   const int v = view_of_tile(b.views, gtile);
   const ViewIO io = b.views.io[v];
