@@ -242,7 +242,8 @@ class MappingIteration:
                                             m["uncertainty"].data_ptr()))
             self.grad_s.append(B.cgsr_images(d["color"].data_ptr(), d["depth"].data_ptr(), None, None,
                                              d["uncertainty"].data_ptr()))
-        self.states = [R.State(sync_capacity=True) for _ in range(1 if batched else self.V)]
+        # the iteration reads no work counts (only pair peaks)
+        self.states = [R.State(sync_capacity=True, count_work=False) for _ in range(1 if batched else self.V)]
 
     def _views(self, st, vs):
         B, s = self.B, self.R._stream()
@@ -269,7 +270,7 @@ class MappingIteration:
         """After a sizing call: fixed pair capacity, no per-call readback."""
         for k, st in enumerate(self.states):
             peak = st.stats().peak_pairs
-            new = self.R.State(sync_capacity=False)
+            new = self.R.State(sync_capacity=False, count_work=False)
             new.reserve(tile_pairs=int(peak * margin) + 64)
             self.states[k] = new
             st.close()

@@ -114,11 +114,12 @@ typedef struct {
                                 a 16x16 tile then takes 256 / that many lanes   */
     int32_t bwd_pixels_per_lane; /* same for the backward blend; each lane sums its
                                 pixels before the per-Gaussian wave reduction   */
-    int32_t count_work;      /* 1: a tracking step keeps the per-pixel work
-                                counts that cgsr_get_stats reports (processed,
-                                blended, walked).  0: it skips that bookkeeping
-                                and cgsr_get_stats reports -1 for them after
-                                it; renders and backward passes always count  */
+    int32_t count_work;      /* 1: tracking steps and renders keep the
+                                per-pixel work counts that cgsr_get_stats
+                                reports (processed, blended, walked).  0: they
+                                skip that bookkeeping and cgsr_get_stats reports
+                                -1 for them (renders with nu and tracking steps
+                                without a pose update or gradient count anyway) */
 } cgsr_settings;
 
 typedef struct {
@@ -136,7 +137,7 @@ typedef struct {
     int64_t walked;          /* (pixel, list entry) pairs up to each pixel's last
                                 blended Gaussian: what the backward revisits.
                                 processed, blended and walked are -1 after a
-                                tracking step with count_work 0               */
+                                render or tracking step with count_work 0     */
     int64_t peak_pairs;      /* pairs of the last render's fullest tile, or, if a
                                 render since the last cgsr_state_check
                                 overflowed, the most any tile needed there      */

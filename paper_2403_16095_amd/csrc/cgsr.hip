@@ -538,7 +538,8 @@ cgsr_status render_impl(cgsr_state* st, const RenderArgs& a, hipStream_t stream)
   if ((s = mark(CGSR_STAGE_BLEND_FWD + 1))) return s;
   st->fwd_timed = timed;
   st->tracked = a.track;
-  st->counted = !(a.track && a.fused && !st->settings.count_work);
+  // renders of nu and split tracking steps always count
+  st->counted = st->settings.count_work || a.nu || (a.track && !a.fused);
   st->have_forward = true;
   return CGSR_OK;
 }

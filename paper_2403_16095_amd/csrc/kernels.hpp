@@ -136,7 +136,8 @@ struct RasterBufs {
   // The backward also reduces the colour gradients when the pose gradient
   // needs them (view-dependent colour) even without parameter gradients.
   bool color_grads;
-  // The fused tracking kernel keeps the per-pixel state and work counts.
+  // The fused tracking kernel keeps the per-pixel state and work counts; the
+  // forward blend of a render (no tracking, no nu) keeps the work counts.
   bool count_work;
   // The fused tracking kernel sorts its tile's bucket itself (no separate
   // segmented sort): every bucket holds at most one key per thread.  It then

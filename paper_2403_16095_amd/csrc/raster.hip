@@ -175,9 +175,10 @@ struct FwdPix {
 // wave's own (8x8) list; last and med1 are one past positions in the tile's
 // list.  With kFull off (a tracking step that keeps no statistics) the walk
 // keeps only what the tracking loss and the pose backward read: colour,
-// depth, transmittance and the last blended entry.
+// depth, transmittance and the last blended entry; kStats off (no work
+// counts) drops evaluated, wlast and blended alone.
 // ids: the tile's record ids in list order.
-template <int kPPL, bool kTrack, bool kNu, bool kFull = true>
+template <int kPPL, bool kTrack, bool kNu, bool kFull = true, bool kStats = kFull>
 __device__ __forceinline__ void forward_tile(const RasterBufs& b, Stage<kTilePixels / kPPL / kWave>& s, int gtile,
                                              const ViewIO& io, float2 org, uint2 range, const uint32_t* ids,
                                              FwdPix<kPPL>& f) {
@@ -237,7 +238,7 @@ __device__ __forceinline__ void forward_tile(const RasterBufs& b, Stage<kTilePix
           const bool stop = hit && Tn < kTStop;
           const bool blend = hit && !stop;
           f.done[k] = f.done[k] || stop;
-          if (kFull) f.evaluated[k] = stop ? loc + j + 1 : f.evaluated[k];
+          if (kStats) f.evaluated[k] = stop ? loc + j + 1 : f.evaluated[k];
           const float wgt = blend ? alpha * f.T[k] : 0.f;
           f.C0[k] = __builtin_fmaf(wgt, Cc.x, f.C0[k]);
           f.C1[k] = __builtin_fmaf(wgt, Cc.y, f.C1[k]);
@@ -261,7 +262,7 @@ __device__ __forceinline__ void forward_tile(const RasterBufs& b, Stage<kTilePix
           }
           f.T[k] = blend ? Tn : f.T[k];
           f.last[k] = blend ? pos1 : f.last[k];
-          if (kFull) {
+          if (kStats) {
             f.wlast[k] = blend ? loc + j + 1 : f.wlast[k];
             f.blended[k] += blend ? 1u : 0u;
           }
@@ -284,8 +285,9 @@ __device__ __forceinline__ void forward_tile(const RasterBufs& b, Stage<kTilePix
 // tracking-loss gradients (returned in g; stored for a separate backward when
 // store_grad) and the Eq. 13 accumulation.
 // Without kFull only the colour and depth maps are written (the tracking
-// step requests none) and no per-pixel state is saved.
-template <int kPPL, bool kTrack, bool kNu, bool kFull = true>
+// step requests none) and no per-pixel state is saved; without kStats the
+// saved state holds no work counts.
+template <int kPPL, bool kTrack, bool kNu, bool kFull = true, bool kStats = kFull>
 __device__ __forceinline__ void forward_outputs(const RasterBufs& b, int v, const ViewIO& io,
                                                 const FwdPix<kPPL>& f, float (&g)[kPPL][4], bool store_grad) {
   const ViewInfo& cam = io.info;
@@ -330,8 +332,9 @@ __device__ __forceinline__ void forward_outputs(const RasterBufs& b, int v, cons
     if (io.depth_median) io.depth_median[p] = f.Dmed[k];
     if (io.uncertainty) io.uncertainty[p] = f.U[k];
     // the median's position, or ~0u if it has none
-    b.pixel_state[cam.pixel_base + p] = make_uint4(__float_as_uint(f.T[k]), f.last[k], f.med1[k] - 1u, f.evaluated[k]);
-    b.pixel_count[cam.pixel_base + p] = make_uint2(f.blended[k], f.wlast[k]);
+    b.pixel_state[cam.pixel_base + p] =
+        make_uint4(__float_as_uint(f.T[k]), f.last[k], f.med1[k] - 1u, kStats ? f.evaluated[k] : 0u);
+    if (kStats) b.pixel_count[cam.pixel_base + p] = make_uint2(f.blended[k], f.wlast[k]);
     if (kNu) {
       // record id m = view * N + Gaussian index
       const int gi = f.dom[k] == kNone ? -1 : (int)(f.dom[k] - (uint32_t)v * (uint32_t)b.views.n_gauss);
@@ -479,7 +482,8 @@ __device__ __forceinline__ void backward_tile(const RasterBufs& b, Stage<kTilePi
   }
 }
 
-template <int kPPL, bool kTrack, bool kNu>
+// kStats: keep the work counts of the statistics.
+template <int kPPL, bool kTrack, bool kNu, bool kStats = true>
 __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(RasterBufs b) {
   __shared__ Stage<kTilePixels / kPPL / kWave> s;
   const int gtile = blockIdx.x;
@@ -487,9 +491,10 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(Rast
   const ViewIO io = b.views.io[v];
   FwdPix<kPPL> f;
   const uint2 range = b.ranges[gtile];
-  forward_tile<kPPL, kTrack, kNu>(b, s, gtile, io, tile_origin(io.info, gtile), range, b.vals + range.x, f);
+  forward_tile<kPPL, kTrack, kNu, true, kStats>(b, s, gtile, io, tile_origin(io.info, gtile), range, b.vals + range.x,
+                                                f);
   float g[kPPL][4];
-  forward_outputs<kPPL, kTrack, kNu>(b, v, io, f, g, true);
+  forward_outputs<kPPL, kTrack, kNu, true, kStats>(b, v, io, f, g, true);
 }
 
 template <int kPPL, bool kParams, bool kTrack, bool kColor>
@@ -631,7 +636,8 @@ void launch_fwd(const RasterBufs& b, bool track, hipStream_t s) {
   const dim3 grid(b.total_tiles), block(kTilePixels / kPPL);
   if (track) hipLaunchKernelGGL((raster_forward_kernel<kPPL, true, false>), grid, block, 0, s, b);
   else if (b.nu) hipLaunchKernelGGL((raster_forward_kernel<kPPL, false, true>), grid, block, 0, s, b);
-  else hipLaunchKernelGGL((raster_forward_kernel<kPPL, false, false>), grid, block, 0, s, b);
+  else if (b.count_work) hipLaunchKernelGGL((raster_forward_kernel<kPPL, false, false>), grid, block, 0, s, b);
+  else hipLaunchKernelGGL((raster_forward_kernel<kPPL, false, false, false>), grid, block, 0, s, b);
 }
 
 template <int kPPL>

@@ -583,6 +583,33 @@ def test_tracking_step_without_work_counts(R):
     assert s0.visible == s1.visible and s0.pairs == s1.pairs and s0.peak_pairs == s1.peak_pairs
 
 
+def test_render_without_work_counts(R, config1):
+    """A render with count_work = 0 writes the same maps and leaves the same
+    backward as one with the counts; its statistics report them as -1."""
+    sc, cam, tc, td = config1
+    say("case: config1 render and backward without work counts")
+    scd = dev(sc)
+    outs, grads = {}, {}
+    rng = np.random.default_rng(31)
+    H, W = cam["height"], cam["width"]
+    dimg = dict(color=rng.standard_normal((3, H, W)), depth=rng.standard_normal((H, W)),
+                opacity=rng.standard_normal((H, W)), depth_median=rng.standard_normal((H, W)),
+                uncertainty=rng.standard_normal((H, W)))
+    for count in (True, False):
+        st = R.State(count_work=count)
+        outs[count], _ = gpu_render(R, st, scd, identity_pose(), cam, td)
+        s = st.stats()
+        assert (s.processed > 0) == count and (s.processed == -1) == (not count)
+        grads[count] = R.backward(st, [{k: t32(v) for k, v in dimg.items()}])
+    for k in MAPS:
+        assert np.array_equal(outs[True][k], outs[False][k]), k
+    for k in PARAMS:
+        a, b = grads[True][0][k].cpu().numpy(), grads[False][0][k].cpu().numpy()
+        assert rel_l2(b, a) <= 1e-6, k
+    d1, d0 = grads[True][1][0].cpu().numpy(), grads[False][1][0].cpu().numpy()
+    assert np.abs(d0 - d1).max() <= 1e-5 * np.abs(d1).max()
+
+
 def test_tracking_step_bucket_capacity(R):
     """The fused tracking step (which sorts its own tile buckets when they
     hold at most one key per thread) with buckets exactly as large as the
