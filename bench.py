@@ -362,6 +362,13 @@ def run_mapping(args, torch, R, synth, views: int):
         log(f"{name}: {res[name]['ms_per_iter']:.3f} ms/iteration ({views} view(s))")
         del it
     st = res["batched"]["stats"]
+    # the timed states keep no work counts: one counting render of the same
+    # views gives them (they depend only on the workload)
+    cst = R.State()
+    R.render(cst, scd, P, cams, tds)
+    s = cst.stats()
+    st.update(evaluations=int(s.processed), blended=int(s.blended), walked=int(s.walked))
+    del cst
     b = mapping_bytes(n, st["visible"], st["pairs"], views * cam["width"] * cam["height"], deg)
     ms = res["batched"]["ms_per_iter"]
     out = {
