@@ -531,7 +531,7 @@ def run_batched_tracking(args, torch, R, synth, frames=32, iters=20):
         def step():
             B.cgsr_tracking_step(st.handle, g, V, pose.data_ptr(), cs, tc, td, float(lam[0]), float(lam[1]),
                                  None, adam.data_ptr(), params, None, R._stream())
-        # Size the pair buffer from an eager run of the same loop (the pair
+        # Size the tile buckets from an eager run of the same loop (the pair
         # count moves with the poses), then capture it.
         pose.copy_(pose0)
         adam.zero_()

@@ -13,8 +13,8 @@
  * Errors: every call returns a cgsr_status and never aborts; cgsr_last_error()
  * returns a message for the calling thread's last failure.  Argument checks are
  * done on the host before any work is enqueued, so a failed call enqueues
- * nothing.  Device-side capacity overflow of the pair buffer is reported by
- * cgsr_state_check() (which synchronises the stream).
+ * nothing.  Device-side capacity overflow of the per-tile pair buckets is
+ * reported by cgsr_state_check() (which synchronises the stream).
  *
  * Conventions shared by every entry point:
  *  - Gaussians are SoA float32: means[n][3], log_scales[n][3] (scale = exp),

@@ -4,14 +4,14 @@
 // tile takes 256 / kPPL lanes; pixel q of the tile lies in the 8x8 quadrant
 // q / 64, and lane t owns pixels t, t + L, t + 2L, ... (L lanes), so a wave's
 // pixels are whole quadrants and leave together.  The tile's depth-ordered
-// records are staged through LDS 256 at a time (see stage_record); every lane
+// records are staged through LDS kBatch at a time (see stage_record); every lane
 // then reads the same LDS address, a broadcast free of bank conflicts, and
 // uses it for all of its pixels.
 //
 // Each wave stages its own copy of the batch holding only the records whose
 // binning rectangle reaches one of its 8x8 quadrants (the projection keeps
 // the rectangle in 8-pixel cells), so a wave walks the list of 8x8 binning --
-// a third shorter at tracking sizes -- while the sort and the pair buffer
+// a third shorter at tracking sizes -- while the sort and the tile buckets
 // stay at 16x16.  A record left out of a wave's copy has alpha below 1/255 at
 // every one of its pixels (the rectangle bounds the support), so the results
 // are exactly those of walking the whole tile list.
@@ -28,7 +28,9 @@
 // raster_track_kernel runs the forward and the pose backward of a tile in one
 // workgroup, the per-pixel state never leaves registers, and the records
 // staged for the forward are reused by the backward when the tile's list fits
-// one batch.  The separate kernels serve rendering and the mapping backward.
+// one batch; when every bucket holds at most one key per thread it also sorts
+// its own bucket first (no separate sort launch).  The separate kernels serve
+// rendering and the mapping backward.
 #include "kernels.hpp"
 
 namespace cgsr {

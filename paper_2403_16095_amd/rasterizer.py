@@ -680,9 +680,9 @@ class TrackingSolver:
         self.adam.zero_()
 
     def prepare(self, pose0: torch.Tensor):
-        """Size the pair buffer from an eager render at pose0 and capture the graph."""
+        """Size the tile buckets from an eager step at pose0 and capture the graph."""
         self.reset(pose0)
-        self._iteration()                       # eager, grows the pair buffer
+        self._iteration()                       # eager, grows the tile buckets
         torch.cuda.synchronize()
         st = self.state.stats()
         self.state.reserve(tile_pairs=int(st.peak_pairs * self.pair_margin) + 64)
