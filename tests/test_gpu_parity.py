@@ -569,11 +569,13 @@ def test_tracking_step_without_work_counts(R):
         out[(count, big)] = (np.array(losses), P.cpu(), dposes.cpu(), stats)
     (l1, p1, d1, s1), (l0, p0, d0, s0) = out[(True, False)], out[(False, False)]
     lb, pb, db, sb = out[(False, True)]
-    np.testing.assert_allclose(lb, l1, rtol=1e-6)
+    # the per-record gradient sums are float atomics (order-dependent rounding),
+    # so later iterations' poses and losses differ from run to run at rounding level
+    np.testing.assert_allclose(lb, l1, rtol=1e-5)
     assert (pb - p1).abs().max().item() < 1e-6
     assert ((db - d1).abs().max() / d1.abs().max()).item() < 1e-5
     assert sb.pairs == s1.pairs
-    np.testing.assert_allclose(l0, l1, rtol=1e-6)
+    np.testing.assert_allclose(l0, l1, rtol=1e-5)
     assert (p0 - p1).abs().max().item() < 1e-6
     e = ((d0 - d1).abs().max() / d1.abs().max()).item()
     say("pose gradient, without vs with counts", e)
