@@ -705,11 +705,14 @@ def test_graph_tracking_replays_match_eager(R):
     assert l1 < 0.5 * l0 and e1 < e0
 
 
-def test_wave_lists_equal_8x8_binning(R):
+def test_wave_lists_within_8x8_binning(R):
     """Each wave walks the Gaussians whose binning rectangle reaches its 8x8
-    cell: on a scene where no pixel reaches the stop threshold, every pixel's
-    alpha evaluations equal the length of its cell's list under 8x8 binning
-    by enumeration (the oracle's tile lists with tile = 8), and the forward
+    cell, less those that cannot reach alpha >= 1/255 on the cell: on a scene
+    where no pixel reaches the stop threshold, every pixel's alpha evaluations
+    lie between the number of its cell's Gaussians that reach alpha >= 1/255
+    at some pixel of the cell (FP64, from the oracle's projection) and the
+    length of its cell's list under 8x8 binning by enumeration (the oracle's
+    tile lists with tile = 8); some cells are shortened, and the forward
     still matches the oracle."""
     say("case: per-wave 8x8 lists, 3000 faint Gaussians 64x48 and 200x120")
     from paper_2403_16095_amd import binding as B
@@ -722,16 +725,29 @@ def test_wave_lists_equal_8x8_binning(R):
         mask = unambiguous(ref)
         compare_maps(gpu, ref, mask)
         H, W = cam["height"], cam["width"]
-        lists = oracle.tile_lists(oracle.project(sc, cam, identity_pose()), cam, tile=8)
+        proj = oracle.project(sc, cam, identity_pose())
+        lists = oracle.tile_lists(proj, cam, tile=8)
         cells_x = (W + 7) // 8
         expect = np.zeros((H, W), np.int64)
-        for v in range(H):
-            for u in range(W):
-                expect[v, u] = len(lists.get((v // 8) * cells_x + u // 8, ()))
+        needed = np.zeros((H, W), np.int64)
+        for cell, ids in lists.items():
+            cy, cx = divmod(cell, cells_x)
+            ys, xs = np.arange(8 * cy, min(8 * cy + 8, H)), np.arange(8 * cx, min(8 * cx + 8, W))
+            X, Y = np.meshgrid(xs, ys)
+            n_need = 0
+            for i in ids:
+                a, b, c = proj["conic"][i]
+                dx, dy = X - proj["mu"][i][0], Y - proj["mu"][i][1]
+                alpha = proj["opacity"][i] * np.exp(-0.5 * (a * dx * dx + 2 * b * dx * dy + c * dy * dy))
+                n_need += bool((alpha >= 1.0 / 255.0).any())
+            expect[np.ix_(ys, xs)] = len(ids)
+            needed[np.ix_(ys, xs)] = n_need
         keys, vals, ranges, recs, pst = B.cgsr_debug_buffers(st.handle)
         ps = torch.empty((H * W, 4), dtype=torch.int32, device="cuda")
         torch.cuda.synchronize()
         copy_device(ps, pst, H * W * 16)
         got = ps[:, 3].cpu().numpy().reshape(H, W)
-        np.testing.assert_array_equal(got, expect)
+        say("entries walked", int(got.sum()), "8x8 binning", int(expect.sum()), "needed", int(needed.sum()))
+        assert (got <= expect).all() and (got >= needed).all()
+        assert got.sum() < expect.sum()
         assert expect.max() > 10
