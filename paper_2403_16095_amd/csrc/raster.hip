@@ -126,8 +126,9 @@ __device__ __forceinline__ bool wave_takes(int w, uint32_t cx0, uint32_t cx1, ui
 // Stages n <= kBatch entries of the tile's list, record ids ids[0, n), into
 // each wave's copy; every thread calls it.  pos0: the position of ids[0] in
 // the tile's list.  (tcx, tcy): the tile's first 8-pixel cell.  With one wave
-// per tile every record reaches it.
-template <int L, int W>
+// per tile every record reaches it.  kPerWave: each wave stages its copy on
+// its own (tracking), else the block shares the loads and tests (mapping).
+template <int L, int W, bool kPerWave>
 __device__ __forceinline__ void stage_batch(const RasterBufs& b, Stage<W>& s, const uint32_t* ids, uint32_t pos0,
                                             int n, float2 org, uint32_t tcx, uint32_t tcy) {
   __syncthreads();
@@ -142,10 +143,46 @@ __device__ __forceinline__ void stage_batch(const RasterBufs& b, Stage<W>& s, co
       s.C[0][i] = C;
     }
     if (threadIdx.x == 0) s.cnt[0] = (uint32_t)n;
+  } else if constexpr (kPerWave) {
+    // Each wave builds its own copy: lane l takes entries l, l + 64 of the
+    // batch, tests them against the wave's own quadrants, and the entries it
+    // keeps go to consecutive slots in list order (ballot rank).  Every wave
+    // loads and tests the whole batch, but none waits on a block scan or on
+    // one thread testing all quadrants: the shorter path for latency-bound
+    // tracking tiles.
+    static_assert(kBatch <= 2 * kWave, "two entries per lane");
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int r0 = 0; r0 < kBatch; r0 += kWave) {
+      if (r0 >= n) break;
+      const int i = r0 + lane;
+      bool take = false;
+      float4 A, B, C;
+      if (i < n) {
+        const uint32_t m = ids[i];
+        stage_record(b.rec + (int64_t)kRecF4 * m, org.x, org.y, A, B, C);
+        B.w = __int_as_float((int)(pos0 + i + 1));
+        C.w = __uint_as_float(m);
+        const uint2 r = b.rect[m];
+        take = wave_takes<W>(wv, r.x & 0xFFFFu, r.x >> 16, r.y & 0xFFFFu, r.y >> 16, tcx, tcy, A, B);
+      }
+      const uint64_t bal = __ballot(take);
+      if (take) {
+        const uint32_t d =
+            cnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+        s.A[wv][d] = A;
+        s.B[wv][d] = B;
+        s.C[wv][d] = C;
+      }
+      cnt += (uint32_t)__popcll(bal);
+    }
+    if (lane == 0) s.cnt[wv] = cnt;
   } else {
-    // L >= kBatch: one record per thread.  A byte per wave counts the
-    // records it takes; their exclusive prefix over the threads is the
-    // record's slot in that wave's copy (no byte exceeds kBatch < 256).
+    // L >= kBatch: one record per thread, tested against every wave's
+    // quadrants.  A byte per wave counts the records it takes; their
+    // exclusive prefix over the threads is the record's slot in that wave's
+    // copy (no byte exceeds kBatch < 256).
     static_assert(L >= kBatch && W <= 4, "one record per thread");
     const int i = threadIdx.x;
     uint32_t take = 0, m = 0;
@@ -243,7 +280,7 @@ __device__ __forceinline__ void forward_tile(const RasterBufs& b, Stage<kTilePix
   }
   for (uint32_t base = range.x; base < range.y; base += kBatch) {
     const int n = (int)min((uint32_t)kBatch, range.y - base);
-    stage_batch<L, W>(b, s, ids + (base - range.x), base - range.x, n, org, tcx, tcy);
+    stage_batch<L, W, kTrack>(b, s, ids + (base - range.x), base - range.x, n, org, tcx, tcy);
     // the copy's length is the same for the whole wave
     const int nw = (int)__builtin_amdgcn_readfirstlane(s.cnt[wv]);
     // The wave walks the whole batch while any of its lanes still blends;
@@ -426,7 +463,7 @@ __device__ __forceinline__ void backward_tile(const RasterBufs& b, Stage<kTilePi
     const int start = max(0, end - kBatch);
     const int n = end - start;
     if (!(start == 0 && end <= staged_n))
-      stage_batch<L, W>(b, s, b.vals + range.x + start, start, n, org, tcx, tcy);
+      stage_batch<L, W, kTrack>(b, s, b.vals + range.x + start, start, n, org, tcx, tcy);
     for (int j = (int)__builtin_amdgcn_readfirstlane(s.cnt[wv]) - 1; j >= 0; --j) {
       const float4 A = s.A[wv][j];
       const float4 B = s.B[wv][j];
