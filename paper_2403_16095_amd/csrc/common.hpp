@@ -106,6 +106,34 @@ __device__ __forceinline__ void stage_record(const float4* __restrict__ rec, flo
   C = make_float4(r1.w, r2.x, r2.y, 0.f);
 }
 
+// Whether a staged record (A, B) can reach alpha >= 1/255 anywhere on the
+// square of pixel centres [x0, x0 + span] x [y0, y0 + span], tile-relative.
+// The base-2 exponent of Eq. 5 is a concave quadratic in the pixel position,
+// so its maximum over the square (taken continuous, which bounds every
+// pixel's) is 0 at the mean when the square holds it and otherwise lies on an
+// edge, where it is a one-dimensional maximum clamped to the edge.  A record
+// is kept unless it falls short by kCellMargin (base-2 units: alpha a factor
+// 1.007 below the threshold), far more than the rounding of the per-pixel
+// evaluation, so a dropped record is one every pixel of the square would skip
+// and the blends give the same results without it.
+constexpr float kCellMargin = 0.01f;
+__device__ __forceinline__ bool box_reached(const float4& A, const float4& B, float x0, float y0, float span) {
+  const float dx0 = A.x - (x0 + span), dx1 = A.x - x0, dy0 = A.y - (y0 + span), dy1 = A.y - y0;
+  if (dx0 <= 0.f && dx1 >= 0.f && dy0 <= 0.f && dy1 >= 0.f) return true;
+  const float qa = A.z, k = A.w, qc = B.x;   // exponent qa t^2 + qc dy^2, t = dx + k dy
+  auto expo = [&](float dx, float dy) {
+    const float t = __builtin_fmaf(k, dy, dx);
+    return __builtin_fmaf(qa, t * t, qc * (dy * dy));
+  };
+  // edges dy = dy0, dy1: t = 0 at dx = -k dy
+  float best = fmaxf(expo(fminf(fmaxf(-k * dy0, dx0), dx1), dy0), expo(fminf(fmaxf(-k * dy1, dx0), dx1), dy1));
+  // edges dx = dx0, dx1: the exponent is largest at dy = sl dx
+  const float sl = -(qa * k) / __builtin_fmaf(qa * k, k, qc);
+  best = fmaxf(best, expo(dx0, fminf(fmaxf(sl * dx0, dy0), dy1)));
+  best = fmaxf(best, expo(dx1, fminf(fmaxf(sl * dx1, dy0), dy1)));
+  return B.y * __builtin_amdgcn_exp2f(best + kCellMargin) >= kAlphaMin;
+}
+
 // Base-2 exponent of a staged record at pixel centre (px, py); dx, dy = mu - p
 // and t = dx + k dy.
 __device__ __forceinline__ float pair_exponent(const float4& A, const float4& B, float px, float py, float& dx,

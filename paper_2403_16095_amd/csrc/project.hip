@@ -277,6 +277,7 @@ __global__ __launch_bounds__(kThreads) void project_kernel(GaussianPtrs g, const
                                                            ViewTable vt, ProjectBufs b) {
   __shared__ uint32_t s_off[kThreads], s_org[kThreads], s_wid[kThreads];
   __shared__ uint64_t s_key[kThreads];
+  __shared__ float4 s_r0[kThreads], s_r1[kThreads];   // record fields the pair test reads
   const int v = blockIdx.y;
   const int64_t N = g.n;
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -321,6 +322,9 @@ __global__ __launch_bounds__(kThreads) void project_kernel(GaussianPtrs g, const
         rec[0] = make_float4(hx, hy, (float)o.conic[0], (float)(o.conic[1] / o.conic[0]));
         rec[1] = make_float4((float)(1.0 / o.cov[2]), (float)o.opacity, (float)o.p[2], c[0]);
         rec[2] = make_float4(c[1], c[2], (float)(mux - (double)hx), (float)(muy - (double)hy));
+        s_r0[threadIdx.x] = make_float4(hx, hy, (float)o.conic[0], (float)(o.conic[1] / o.conic[0]));
+        s_r1[threadIdx.x] = make_float4((float)(1.0 / o.cov[2]), (float)o.opacity, (float)(mux - (double)hx),
+                                        (float)(muy - (double)hy));
         const uint32_t cx0 = (uint32_t)u0 / 8u, cx1 = (uint32_t)u1 / 8u, cy0 = (uint32_t)v0 / 8u,
                        cy1 = (uint32_t)v1 / 8u;
         b.rect[m] = make_uint2(cx0 | (cx1 << 16), cy0 | (cy1 << 16));
@@ -334,11 +338,15 @@ __global__ __launch_bounds__(kThreads) void project_kernel(GaussianPtrs g, const
   // Emission: the wave's pairs spread over its lanes, each taking a slot in
   // its tile's bucket with a returning atomic -- up to kBatchPairs before
   // using any, so a lane waits once per batch -- and writing its key there.
+  // A pair whose Gaussian cannot reach alpha >= 1/255 on any pixel of the
+  // tile (box_reached on the tile's 16x16 square, with the record fields the
+  // blends stage) is not emitted: the blends would skip it at every pixel.
   const int wv = threadIdx.x >> 6;
   const uint32_t lane = threadIdx.x & 63;
   s_key[threadIdx.x] = key;
   const WavePairs wp = wave_pairs(ntiles, tx0, ty0, width, s_off + 64 * wv, s_org + 64 * wv, s_wid + 64 * wv);
   constexpr uint32_t kBatchPairs = 8;
+  constexpr uint32_t kSkip = 0xFFFFFFFFu;
   uint32_t lost = 0;   // one past the fullest slot of a pair that found its bucket full
   for (uint32_t k0 = lane; k0 < wp.total; k0 += 64 * kBatchPairs) {
     uint32_t tile[kBatchPairs], slot[kBatchPairs];
@@ -346,16 +354,24 @@ __global__ __launch_bounds__(kThreads) void project_kernel(GaussianPtrs g, const
 #pragma unroll
     for (uint32_t j = 0; j < kBatchPairs; ++j) {
       const uint32_t k = k0 + 64 * j;
+      slot[j] = kSkip;
       if (k < wp.total) {
         int owner;
-        tile[j] = cam.tile_base + pair_tile(wp, k, cam.tiles_x, &owner);
+        const uint32_t local = pair_tile(wp, k, cam.tiles_x, &owner);
+        const float4 r0 = s_r0[64 * wv + owner], r1 = s_r1[64 * wv + owner];
+        const float ox = (float)((local % (uint32_t)cam.tiles_x) * kTile), oy = (float)((local / (uint32_t)cam.tiles_x) * kTile);
+        const float4 A = make_float4((r0.x - ox) + r1.z, (r0.y - oy) + r1.w, (-0.5f * kLog2e) * r0.z, r0.w);
+        const float4 B = make_float4((-0.5f * kLog2e) * r1.x, r1.y, 0.f, 0.f);
+        tile[j] = cam.tile_base + local;
         kk[j] = s_key[64 * wv + owner];
-        slot[j] = atomicAdd(&b.tile_count[(size_t)tile[j] * kTileCounterStride], 1u);
+        if (box_reached(A, B, 0.f, 0.f, (float)(kTile - 1)))
+          slot[j] = atomicAdd(&b.tile_count[(size_t)tile[j] * kTileCounterStride], 1u);
       }
     }
 #pragma unroll
     for (uint32_t j = 0; j < kBatchPairs; ++j) {
       if (k0 + 64 * j >= wp.total) break;
+      if (slot[j] == kSkip) continue;
       if (slot[j] < b.tile_cap) b.keys[(uint64_t)tile[j] * b.tile_cap + slot[j]] = kk[j];
       else lost = max(lost, slot[j] + 1u);
     }

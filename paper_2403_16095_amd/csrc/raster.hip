@@ -78,37 +78,9 @@ struct Stage {
   uint32_t scan[4];
 };
 
-// Whether a staged record (A, B) can reach alpha >= 1/255 anywhere on the
-// 8x8 pixel box whose first pixel centre is (x0, y0), tile-relative.  The
-// base-2 exponent of Eq. 5 is a concave quadratic in the pixel position, so
-// its maximum over the box (taken continuous, which bounds every pixel's) is
-// 0 at the mean when the box holds it and otherwise lies on an edge, where it
-// is a one-dimensional maximum clamped to the edge.  A record is kept unless
-// it falls short by kCellMargin (base-2 units: alpha a factor 1.007 below the
-// threshold), far more than the rounding of the per-pixel evaluation, so a
-// dropped record is one every pixel of the box would skip: the walks give the
-// same results with fewer entries.
-constexpr float kCellMargin = 0.01f;
-__device__ __forceinline__ bool cell_reached(const float4& A, const float4& B, float x0, float y0) {
-  const float dx0 = A.x - (x0 + 7.f), dx1 = A.x - x0, dy0 = A.y - (y0 + 7.f), dy1 = A.y - y0;
-  if (dx0 <= 0.f && dx1 >= 0.f && dy0 <= 0.f && dy1 >= 0.f) return true;
-  const float qa = A.z, k = A.w, qc = B.x;   // exponent qa t^2 + qc dy^2, t = dx + k dy
-  auto expo = [&](float dx, float dy) {
-    const float t = __builtin_fmaf(k, dy, dx);
-    return __builtin_fmaf(qa, t * t, qc * (dy * dy));
-  };
-  // edges dy = dy0, dy1: t = 0 at dx = -k dy
-  float best = fmaxf(expo(fminf(fmaxf(-k * dy0, dx0), dx1), dy0), expo(fminf(fmaxf(-k * dy1, dx0), dx1), dy1));
-  // edges dx = dx0, dx1: the exponent is largest at dy = sl dx
-  const float sl = -(qa * k) / __builtin_fmaf(qa * k, k, qc);
-  best = fmaxf(best, expo(dx0, fminf(fmaxf(sl * dx0, dy0), dy1)));
-  best = fmaxf(best, expo(dx1, fminf(fmaxf(sl * dx1, dy0), dy1)));
-  return B.y * __builtin_amdgcn_exp2f(best + kCellMargin) >= kAlphaMin;
-}
-
 // Whether wave w of W takes a staged record: one of its quadrants (q / 64 of
 // pixel q, see pixel_of: w, w + W, ..., kPPL = 4 / W of them) lies in the
-// record's binning rectangle (8-pixel cells) and passes cell_reached.
+// record's binning rectangle (8-pixel cells) and box_reached passes for it.
 template <int W>
 __device__ __forceinline__ bool wave_takes(int w, uint32_t cx0, uint32_t cx1, uint32_t cy0, uint32_t cy1,
                                            uint32_t tcx, uint32_t tcy, const float4& A, const float4& B) {
@@ -118,7 +90,7 @@ __device__ __forceinline__ bool wave_takes(int w, uint32_t cx0, uint32_t cx1, ui
     const int qd = w + k * W;
     const uint32_t cx = tcx + (qd & 1), cy = tcy + (qd >> 1);
     if (cx0 <= cx && cx <= cx1 && cy0 <= cy && cy <= cy1)
-      any = any || cell_reached(A, B, (float)(8 * (qd & 1)), (float)(8 * (qd >> 1)));
+      any = any || box_reached(A, B, (float)(8 * (qd & 1)), (float)(8 * (qd >> 1)), 7.f);
   }
   return any;
 }

@@ -129,7 +129,25 @@ def tile_lists_from_gpu(R, st, n_tiles):
     return lists, K
 
 
+def reaches_tile(proj, i, cam, t):
+    """Whether Gaussian i reaches alpha >= 1/255 (Eq. 5, FP64) at a pixel of
+    16x16 tile t."""
+    tiles_x = (cam["width"] + 15) // 16
+    ty, tx = divmod(t, tiles_x)
+    xs = np.arange(16 * tx, min(16 * tx + 16, cam["width"]))
+    ys = np.arange(16 * ty, min(16 * ty + 16, cam["height"]))
+    X, Y = np.meshgrid(xs, ys)
+    a, b, c = proj["conic"][i]
+    dx, dy = X - proj["mu"][i][0], Y - proj["mu"][i][1]
+    return bool((proj["opacity"][i] * np.exp(-0.5 * (a * dx * dx + 2 * b * dx * dy + c * dy * dy))
+                 >= 1.0 / 255.0).any())
+
+
 def check_tiles(R, sc, cam, pose):
+    """Each tile's list is the oracle's list under 16x16 binning, in the same
+    (depth, id) order, less Gaussians that reach alpha >= 1/255 at no pixel of
+    the tile (the projection drops those pairs); every Gaussian that reaches
+    one is kept."""
     st = R.State()
     gpu_render(R, st, dev(sc), pose, cam)
     tiles_x, tiles_y = (cam["width"] + 15) // 16, (cam["height"] + 15) // 16
@@ -142,10 +160,17 @@ def check_tiles(R, sc, cam, pose):
     near_edge = (np.abs(edges - np.round(edges)) < 1e-3).any(1) & (proj["visible"] == 1)
     amb = set(np.nonzero(near_edge)[0].tolist())
     d = proj["depth"]
-    n_checked = 0
+    n_checked = n_dropped = 0
     for t in set(gl) | set(ol):
         a = [i for i in gl.get(t, []) if i not in amb]
-        b = [i for i in ol.get(t, []) if i not in amb]
+        full = [i for i in ol.get(t, []) if i not in amb]
+        kept = set(a)
+        assert kept <= set(full), ("not in the tile's binned list", t)
+        for i in full:
+            if i not in kept:
+                assert not reaches_tile(proj, i, cam, t), ("dropped a Gaussian that reaches the tile", t, i)
+                n_dropped += 1
+        b = [i for i in full if i in kept]
         if a != b:
             # allow swaps of depth near-ties only
             assert sorted(a) == sorted(b), ("tile membership differs", t)
@@ -153,7 +178,7 @@ def check_tiles(R, sc, cam, pose):
                 if x != y:
                     assert abs(d[x] - d[y]) <= 1e-6 * d[x], ("order differs", t, x, y)
         n_checked += len(a)
-    say("pairs", K, "checked", n_checked, "ambiguous gaussians", len(amb))
+    say("pairs", K, "checked", n_checked, "dropped", n_dropped, "ambiguous gaussians", len(amb))
     assert len(amb) <= 0.01 * max(1, int(proj["visible"].sum())) + 5
     return K
 
@@ -619,8 +644,8 @@ def test_tracking_step_bucket_capacity(R):
     buckets the dropped pairs are reported: the statistics give the count
     the fullest tile needed and the next check raises the capacity error."""
     from paper_2403_16095_amd import binding as B
-    say("case: tracking step bucket capacity, 30k Gaussians 320x240")
-    sc = synth.room_scene(6, 30_000, (5.0, 4.0, 3.0))
+    say("case: tracking step bucket capacity, 40k Gaussians 320x240")
+    sc = synth.room_scene(6, 40_000, (5.0, 4.0, 3.0))
     cam = synth.camera(320, 240, 262.5, 262.5, 160, 120)
     scd = dev(sc)
     tgt = synth.level_room_pose(25)
