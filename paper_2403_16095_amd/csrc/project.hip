@@ -1,6 +1,7 @@
 // Per-(view, Gaussian) projection (Sec. 3.1, Eq. 1-2), pair emission into
 // fixed-size per-tile buckets for the tile sort (no global scan: a returning
-// atomic on the tile's count is the pair's slot), and the chain rule back from
+// atomic on the tile's count is the pair's slot; pairs whose Gaussian reaches
+// alpha >= 1/255 on no pixel of the tile are not emitted), and the chain rule back from
 // the projected quantities to the Gaussian parameters and the camera pose.
 //
 // Grid layout: blockIdx.y = view, blockIdx.x covers the Gaussians, so every

@@ -10,11 +10,11 @@
 //
 // Each wave stages its own copy of the batch holding only the records whose
 // binning rectangle reaches one of its 8x8 quadrants (the projection keeps
-// the rectangle in 8-pixel cells), so a wave walks the list of 8x8 binning --
-// a third shorter at tracking sizes -- while the sort and the tile buckets
-// stay at 16x16.  A record left out of a wave's copy has alpha below 1/255 at
-// every one of its pixels (the rectangle bounds the support), so the results
-// are exactly those of walking the whole tile list.
+// the rectangle in 8-pixel cells) and whose alpha >= 1/255 region does by the
+// closed-form test box_reached, so a wave walks a list shorter than 8x8
+// binning's while the sort and the tile buckets stay at 16x16.  A record left
+// out of a wave's copy has alpha below 1/255 at every one of its pixels, so
+// the results are exactly those of walking the whole tile list.
 //
 // kNu (mapping renders) also keeps, per pixel, the blended Gaussian of
 // largest weight alpha T -- the pixel is "dominated" by it (Sec. 3.2,

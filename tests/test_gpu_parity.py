@@ -197,6 +197,23 @@ def test_tile_assignment_bit_exact_tracking_size(R):
     assert K > 10_000
 
 
+def test_reach_tests_keep_every_contributor_of_thin_gaussians(R):
+    """Needle-like, rotated Gaussians (per-axis log-scales with a wide spread)
+    are where a binning rectangle overlaps most cells and tiles the ellipse
+    misses, and where the closed-form reach test is most exposed to rounding:
+    the tile lists keep every Gaussian that reaches its tile (FP64), and the
+    maps still match the oracle at every unambiguous pixel."""
+    for cam in (synth.SMALL_CAMERA, synth.camera(200, 120, 150.0, 150.0, 100.0, 60.0)):
+        say(f"case: 1500 thin Gaussians {cam['width']}x{cam['height']}")
+        sc = synth.uniform_box_scene(11, 1500, log_scale=(-3.0, 1.6), opacity=(0.0, 1.5))
+        check_tiles(R, sc, cam, identity_pose())
+        st = R.State()
+        gpu, _ = gpu_render(R, st, dev(sc), identity_pose(), cam)
+        ref = oracle.render(sc, cam, identity_pose())
+        mask = unambiguous(ref)
+        compare_maps(gpu, ref, mask)
+
+
 @pytest.mark.parametrize("ppl", [2, 4])
 def test_pixels_per_lane_variants(R, config1, ppl):
     """Blend kernels with 2 or 4 pixels per lane: forward maps bitwise equal to
