@@ -124,7 +124,10 @@ typedef struct {
 
 typedef struct {
     int64_t visible;         /* (view, Gaussian) records that reach the image   */
-    int64_t pairs;           /* (tile, Gaussian) pairs of the last render       */
+    int64_t pairs;           /* (tile, Gaussian) pairs of the last render: the
+                                tiles a Gaussian's binning rectangle overlaps,
+                                less those where its alpha stays below 1/255
+                                at every pixel (not emitted)                     */
     int64_t pair_capacity;   /* pairs one tile's bucket holds                    */
     int32_t overflow;        /* 1 if a render since the last cgsr_state_check
                                 had a tile needing more than its bucket          */
@@ -132,7 +135,8 @@ typedef struct {
     int64_t processed;       /* (pixel, list entry) alpha evaluations of the
                                 forward blend, summed over pixels; a pixel's list
                                 holds the Gaussians whose binning rectangle
-                                reaches its 8x8 pixel cell                       */
+                                reaches its 8x8 pixel cell and whose alpha can
+                                reach 1/255 there                                */
     int64_t blended;         /* (pixel, Gaussian) pairs actually blended          */
     int64_t walked;          /* (pixel, list entry) pairs up to each pixel's last
                                 blended Gaussian: what the backward revisits.
