@@ -73,6 +73,9 @@ def lib():
                                      C.POINTER(_Projection)]
         _lib.orc_render.argtypes = [C.POINTER(_Gaussians), C.POINTER(_Camera), C.POINTER(_Pose), _dp,
                                     C.c_int, _lp, C.c_int64, C.POINTER(_Images)]
+        _lib.orc_render_alternatives.argtypes = [C.POINTER(_Gaussians), C.POINTER(_Camera), C.POINTER(_Pose),
+                                                 _dp, C.c_int, _lp, C.c_int64, C.c_double, C.c_double, C.c_int32,
+                                                 _dp, _ip]
         _lib.orc_backward.argtypes = [C.POINTER(_Gaussians), C.POINTER(_Camera), C.POINTER(_Pose), _dp,
                                       C.c_int, C.POINTER(_ImageGrads), C.POINTER(_Grads)]
         _lib.orc_fd_linear.argtypes = [C.POINTER(_Gaussians), C.POINTER(_Camera), C.POINTER(_Pose), _dp,
@@ -184,6 +187,30 @@ def render(scene, cam, pose, depth_obs=None, *, candidates: int = 1, pixels=None
     if depth_obs is None:
         out["uncertainty"] = None
     return out
+
+
+#: Values of one alternative result of render_alternatives, in order.
+ALT_VALUES = ("color_r", "color_g", "color_b", "depth", "opacity", "depth_median", "uncertainty", "t_final")
+
+
+def render_alternatives(scene, cam, pose, depth_obs, pixels, decision_margin, order_margin, *,
+                        max_alts: int = 64, candidates: int = 1):
+    """Every admissible result of the listed pixels (flat indices v*W+u) when
+    the decisions of Eq. 3-5 and 7-8 that sit within ``decision_margin``
+    (relative) of their thresholds, and the order of Gaussians whose depths
+    differ by less than ``order_margin`` (relative), may go either way (see
+    orc_render_alternatives).  Returns (alts [n, max_alts, 8] in the order of
+    ALT_VALUES, count [n]); count > max_alts means more than max_alts."""
+    s = _Scene(scene)
+    px = np.ascontiguousarray(np.asarray(pixels, dtype=np.int64).reshape(-1))
+    d = None if depth_obs is None else _f64(depth_obs)
+    alts = np.zeros((px.size, int(max_alts), len(ALT_VALUES)))
+    count = np.zeros(px.size, np.int32)
+    _check(lib().orc_render_alternatives(C.byref(s.c), C.byref(_cam(cam)), C.byref(_pose(pose)), _ptr(d),
+                                         int(candidates), _ptr(px, _lp), int(px.size), float(decision_margin),
+                                         float(order_margin), int(max_alts), _ptr(alts), _ptr(count, _ip)),
+           "render_alternatives")
+    return alts, count
 
 
 def _image_grads(dimg):

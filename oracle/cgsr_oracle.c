@@ -582,6 +582,180 @@ int orc_render(const orc_gaussians *g, const orc_camera *cam, const orc_pose *po
     return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Admissible results where decisions sit within rounding of a threshold    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    const gproj *pr;
+    double u, v, dobs;
+    int has_dobs;
+    double dm, om;          /* decision and order margins (relative)          */
+    int max_alts, count;    /* count exceeds max_alts: too many to list       */
+    double *out;            /* [max_alts][ORC_ALT_VALUES]                     */
+    int64_t *order;         /* the pixel's candidates, reordered by the swaps */
+    int64_t n;
+} alt_ctx;
+
+typedef struct {
+    double T, color[3], depth, opacity, uncertainty, depth_median;
+    int has_median;
+} alt_state;
+
+static void alt_emit(alt_ctx *a, const alt_state *s)
+{
+    if (a->count < a->max_alts) {
+        double *o = a->out + (size_t)a->count * ORC_ALT_VALUES;
+        for (int c = 0; c < 3; ++c) o[c] = s->color[c];
+        o[3] = s->depth;
+        o[4] = s->opacity;
+        o[5] = s->has_median ? s->depth_median : 0.0;
+        o[6] = a->has_dobs ? s->uncertainty : 0.0;
+        o[7] = s->T;
+    }
+    a->count++;
+}
+
+static double alt_alpha_raw(const alt_ctx *a, int64_t k)
+{
+    const gproj *o = &a->pr[a->order[k]];
+    return o->opacity * exp(gauss_power(o, a->u, a->v));
+}
+
+/* Whether a raw alpha is blended under one of the admissible outcomes. */
+static int alt_may_blend(const alt_ctx *a, double a_raw)
+{
+    return a_raw >= ORC_ALPHA_MIN || rel_gap(a_raw, ORC_ALPHA_MIN) < a->dm;
+}
+
+/*
+ * The walk of pixel_forward (Eq. 3-10) from candidate position k with state s.
+ * At a decision inside the margins it follows one outcome by recursion and
+ * the other in place.  no_swap: the position whose pair was just exchanged
+ * (so the exchange is not undone there).  Each recursion ends in at least one
+ * alternative, so the nesting stays below max_alts + 2.
+ */
+static void alt_walk(alt_ctx *a, int64_t k, alt_state s, int64_t no_swap)
+{
+    for (; k < a->n; ++k) {
+        if (a->count > a->max_alts) return;
+        const double a_raw = alt_alpha_raw(a, k);
+        if (!alt_may_blend(a, a_raw)) continue;
+        /* Order: the next Gaussian that may be blended here, if its depth is
+         * within the order margin, may come first (Gaussians skipped at this
+         * pixel in between add nothing, wherever they stand). */
+        if (k != no_swap) {
+            const double d0 = a->pr[a->order[k]].depth;
+            for (int64_t k2 = k + 1; k2 < a->n; ++k2) {
+                const double d1 = a->pr[a->order[k2]].depth;
+                if (!(fabs(d1 - d0) < 2.0 * a->om * fabs(d1))) break;   /* past any near tie */
+                if (!alt_may_blend(a, alt_alpha_raw(a, k2))) continue;
+                if (fabs(d1 - d0) < a->om * fabs(d1)) {
+                    int64_t t = a->order[k];
+                    a->order[k] = a->order[k2];
+                    a->order[k2] = t;
+                    alt_walk(a, k, s, k);
+                    t = a->order[k];
+                    a->order[k] = a->order[k2];
+                    a->order[k2] = t;
+                }
+                break;
+            }
+        }
+        const gproj *o = &a->pr[a->order[k]];
+        if (rel_gap(a_raw, ORC_ALPHA_MIN) < a->dm)
+            alt_walk(a, k + 1, s, -1);           /* skipped; below: blended */
+        const double alpha = a_raw > ORC_ALPHA_MAX ? ORC_ALPHA_MAX : a_raw;
+        const double Tn = s.T * (1.0 - alpha);
+        if (rel_gap(Tn, ORC_T_STOP) < a->dm) {
+            alt_emit(a, &s);                     /* stopped; below: blended */
+        } else if (Tn < ORC_T_STOP) {
+            alt_emit(a, &s);
+            return;
+        }
+        const double w = alpha * s.T;
+        for (int c = 0; c < 3; ++c) s.color[c] += w * o->color[c];
+        s.depth += w * o->depth;
+        s.opacity += w;
+        if (a->has_dobs) s.uncertainty += w * (o->depth - a->dobs) * (o->depth - a->dobs);
+        if (!s.has_median) {
+            if (rel_gap(Tn, ORC_T_MEDIAN) < a->dm) {
+                alt_state m = s;                 /* the median; below: not yet */
+                m.has_median = 1;
+                m.depth_median = o->depth;
+                m.T = Tn;
+                alt_walk(a, k + 1, m, -1);
+            } else if (Tn < ORC_T_MEDIAN) {
+                s.has_median = 1;
+                s.depth_median = o->depth;
+            }
+        }
+        s.T = Tn;
+    }
+    alt_emit(a, &s);
+}
+
+int orc_render_alternatives(const orc_gaussians *g, const orc_camera *cam, const orc_pose *pose,
+                            const double *depth_obs, int candidates, const int64_t *pixels,
+                            int64_t n_pixels, double decision_margin, double order_margin,
+                            int32_t max_alts, double *alts, int32_t *n_alts)
+{
+    if (cam->width < 0 || cam->height < 0 || g->n < 0 || n_pixels < 0 || max_alts < 1) return -1;
+    if (!(decision_margin >= 0.0) || !(order_margin >= 0.0)) return -1;
+    const int64_t npx = (int64_t)cam->width * cam->height;
+    for (int64_t k = 0; k < n_pixels; ++k)
+        if (pixels[k] < 0 || pixels[k] >= npx) return -1;
+    render_ctx rc;
+    int st = render_setup(g, cam, pose, candidates, &rc);
+    if (st) { render_teardown(&rc); return st; }
+    int failed = 0;
+#pragma omp parallel
+    {
+        int64_t cap = 0;
+        int64_t *order = NULL;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t k = 0; k < n_pixels; ++k) {
+            const int64_t pix = pixels[k];
+            const int64_t *cand;
+            int64_t nc;
+            pixel_candidates(&rc, pix, &cand, &nc);
+            if (nc > cap) {
+                free(order);
+                cap = nc;
+                order = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+                if (!order) {
+#pragma omp atomic write
+                    failed = 1;
+                    cap = 0;
+                    continue;
+                }
+            }
+            if (nc > 0) memcpy(order, cand, sizeof(int64_t) * (size_t)nc);
+            alt_ctx a;
+            a.pr = rc.pr;
+            a.u = (double)(pix % cam->width);
+            a.v = (double)(pix / cam->width);
+            a.has_dobs = depth_obs != NULL;
+            a.dobs = depth_obs ? depth_obs[pix] : 0.0;
+            a.dm = decision_margin;
+            a.om = order_margin;
+            a.max_alts = max_alts;
+            a.count = 0;
+            a.out = alts + (size_t)k * (size_t)max_alts * ORC_ALT_VALUES;
+            a.order = order;
+            a.n = nc;
+            alt_state s;
+            memset(&s, 0, sizeof(s));
+            s.T = 1.0;
+            alt_walk(&a, 0, s, -1);
+            n_alts[k] = a.count > max_alts ? max_alts + 1 : a.count;
+        }
+        free(order);
+    }
+    render_teardown(&rc);
+    return failed ? -2 : 0;
+}
+
 int orc_gaussian_uncertainty(const orc_gaussians *g, const orc_camera *cam, const orc_pose *pose,
                              const double *depth_obs, int candidates, double *nu_sum,
                              int64_t *nu_count, int32_t *dominant, double *dominant_margin)

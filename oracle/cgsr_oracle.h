@@ -143,6 +143,32 @@ int orc_render(const orc_gaussians *g, const orc_camera *cam, const orc_pose *po
                const double *depth_obs, int candidates, const int64_t *pixels,
                int64_t n_pixels, orc_images *out);
 
+/* Every admissible result of listed pixels whose discrete decisions sit within
+ * rounding of their thresholds (Eq. 3-5 skip and stop, Eq. 7-8 median, and
+ * the blend order of Gaussians whose depths nearly tie).  A float32
+ * implementation evaluating alpha, T and the depth order may take either
+ * outcome of such a decision, so each one is a branch point here:
+ *   - alpha skip: |alpha_raw - 1/255| < decision_margin * (1/255);
+ *   - stop:       |T (1 - alpha) - 1e-4| < decision_margin * 1e-4;
+ *   - median:     |T (1 - alpha) - 0.5| < decision_margin * 0.5 while no
+ *                 median has been found;
+ *   - order:      two Gaussians adjacent in the pixel's walk whose depths
+ *                 differ by less than order_margin * depth may come in either
+ *                 order.
+ * Each branch continues the walk of orc_render with its outcome, and every
+ * walk's end is one alternative.  Per pixel k (flat index pixels[k]) the
+ * alternatives go to alts[k][a][ORC_ALT_VALUES] as (colour r, g, b, depth,
+ * opacity, median depth, uncertainty (0 without depth_obs), final T), and
+ * n_alts[k] = their number, or max_alts + 1 if the pixel has more (only the
+ * first max_alts are written).  A pixel with no decision inside the margins
+ * has exactly one alternative, orc_render's result.  Duplicates are kept.
+ * Candidate mode as in orc_render. */
+#define ORC_ALT_VALUES 8
+int orc_render_alternatives(const orc_gaussians *g, const orc_camera *cam, const orc_pose *pose,
+                            const double *depth_obs, int candidates, const int64_t *pixels,
+                            int64_t n_pixels, double decision_margin, double order_margin,
+                            int32_t max_alts, double *alts, int32_t *n_alts);
+
 /* Analytic backward of orc_render over the whole image. */
 int orc_backward(const orc_gaussians *g, const orc_camera *cam, const orc_pose *pose,
                  const double *depth_obs, int candidates, const orc_image_grads *dimg,
