@@ -15,7 +15,7 @@ import pytest
 import oracle
 from oracle import mapping as OM
 from paper_2403_16095_amd import synth
-from helpers import rel_l2
+from helpers import grad_parity, rel_l2
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -131,9 +131,7 @@ def test_render_objective_backward_end_to_end(R):
     rb = oracle.backward(sc, cam, pose, td, rdimg)
     rb["log_scales"] = rb["log_scales"] + rls
     for k in ("means", "log_scales", "quats", "opacity_logits", "rgb"):
-        e = rel_l2(grads[k].cpu().numpy(), rb[k])
-        say(k, "rel err", e)
-        assert e <= 1e-3, k
+        grad_parity(k, grads[k].cpu().numpy(), rb[k], label="Eq. 18 end to end")
     e = np.abs(dposes[0].cpu().numpy() - rb["pose"]).max() / np.abs(rb["pose"]).max()
     say("pose rel err", e)
     assert e <= 1e-3

@@ -1,10 +1,12 @@
 """HIP path vs the FP64 oracle, through the C ABI.
 
 Renders must match within 1e-4 absolute on every map, gradients within 1e-3
-relative (L2 per tensor), tile and sort assignment exactly.  Where float32
-and float64 can legitimately take a different discrete decision (a pixel
-whose alpha, stop, median or depth order sits within DECISION_MARGIN of its
-threshold), that pixel is left out of the element-wise comparison and counted.
+relative (L2 per tensor).  Where float32 and float64 can legitimately take a
+different discrete decision (a pixel whose alpha, stop, median or depth order
+sits within the rounding margins of its threshold), the pixel must match one
+of the results the oracle gives with that decision taken either way
+(helpers.check_maps); no pixel is left out.  Tile lists hold the oracle's
+binning lists in its order, less pairs shown unreachable (check_tiles).
 """
 import sys
 
@@ -13,7 +15,7 @@ import pytest
 
 import oracle
 from paper_2403_16095_amd import synth
-from helpers import copy_device, identity_pose, order_only_ambiguous, pose12, rel_l2, unambiguous
+from helpers import ORDER_MARGIN, check_maps, copy_device, grad_parity, identity_pose, pose12, rel_l2
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -49,19 +51,6 @@ def gpu_render(R, state, scene_d, pose, cam, dobs=None):
     return {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}, p
 
 
-def compare_maps(gpu, ref, mask, tol=1e-4):
-    worst = {}
-    for k in MAPS:
-        if k not in gpu or ref.get(k) is None:
-            continue
-        g, r = gpu[k], ref[k]
-        m = np.broadcast_to(mask, g.shape)
-        err = np.abs(g - r)[m].max() if m.any() else 0.0
-        worst[k] = err
-        assert err <= tol, (k, err)
-    return worst
-
-
 @pytest.fixture(scope="module")
 def config1():
     sc = synth.uniform_box_scene(0, 2000)
@@ -75,13 +64,7 @@ def test_render_config1_matches_oracle(R, config1):
     say("case: config1 forward, 2000 Gaussians 64x48")
     st = R.State()
     gpu, _ = gpu_render(R, st, dev(sc), identity_pose(), cam, td)
-    ref = oracle.render(sc, cam, identity_pose(), td)
-    mask = unambiguous(ref)
-    assert mask.mean() > 0.99, mask.mean()
-    worst = compare_maps(gpu, ref, mask)
-    swap = order_only_ambiguous(ref)
-    assert np.abs(gpu["opacity"] - ref["opacity"])[swap].max(initial=0.0) <= 1e-4
-    say("max abs err", worst, "excluded px", int((~mask).sum()))
+    check_maps(gpu, sc, cam, identity_pose(), td, max_ambiguous=0.01, label="config1")
     s = st.stats()
     assert s.overflow == 0 and s.pairs > 0
 
@@ -176,20 +159,20 @@ def check_tiles(R, sc, cam, pose):
             assert sorted(a) == sorted(b), ("tile membership differs", t)
             for x, y in zip(a, b):
                 if x != y:
-                    assert abs(d[x] - d[y]) <= 1e-6 * d[x], ("order differs", t, x, y)
+                    assert abs(d[x] - d[y]) <= ORDER_MARGIN * d[x], ("order differs", t, x, y)
         n_checked += len(a)
     say("pairs", K, "checked", n_checked, "dropped", n_dropped, "ambiguous gaussians", len(amb))
     assert len(amb) <= 0.01 * max(1, int(proj["visible"].sum())) + 5
     return K
 
 
-def test_tile_assignment_bit_exact_config1(R, config1):
+def test_tile_lists_match_oracle_binning_config1(R, config1):
     sc, cam, tc, td = config1
     say("case: config1 tile lists")
     check_tiles(R, sc, cam, identity_pose())
 
 
-def test_tile_assignment_bit_exact_tracking_size(R):
+def test_tile_lists_match_oracle_binning_tracking_size(R):
     say("case: 100k room, 640x480 tile lists")
     sc = synth.room_scene(0, 100_000, (5.0, 4.0, 3.0))
     pose = synth.level_room_pose(0)
@@ -202,16 +185,15 @@ def test_reach_tests_keep_every_contributor_of_thin_gaussians(R):
     are where a binning rectangle overlaps most cells and tiles the ellipse
     misses, and where the closed-form reach test is most exposed to rounding:
     the tile lists keep every Gaussian that reaches its tile (FP64), and the
-    maps still match the oracle at every unambiguous pixel."""
+    maps still match the oracle (or, at pixels with a near-threshold
+    decision, one of its admissible results)."""
     for cam in (synth.SMALL_CAMERA, synth.camera(200, 120, 150.0, 150.0, 100.0, 60.0)):
         say(f"case: 1500 thin Gaussians {cam['width']}x{cam['height']}")
         sc = synth.uniform_box_scene(11, 1500, log_scale=(-3.0, 1.6), opacity=(0.0, 1.5))
         check_tiles(R, sc, cam, identity_pose())
         st = R.State()
         gpu, _ = gpu_render(R, st, dev(sc), identity_pose(), cam)
-        ref = oracle.render(sc, cam, identity_pose())
-        mask = unambiguous(ref)
-        compare_maps(gpu, ref, mask)
+        check_maps(gpu, sc, cam, identity_pose(), max_ambiguous=0.01, label=f"thin {cam['width']}x{cam['height']}")
 
 
 @pytest.mark.parametrize("ppl", [2, 4])
@@ -283,10 +265,7 @@ def test_long_tile_segments_take_the_merge_path(R):
         assert np.all((np.diff(key) > 0) | ((np.diff(key) == 0) & (np.diff(ids) > 0)) |
                       (np.abs(np.diff(key)) <= 1e-6 * key[1:])), t
     check_tiles(R, sc, cam, identity_pose())
-    ref = oracle.render(sc, cam, identity_pose(), None)
-    mask = unambiguous(ref)
-    worst = compare_maps(gpu, ref, mask)
-    say("max abs err", worst, "excluded px", int((~mask).sum()))
+    check_maps(gpu, sc, cam, identity_pose(), max_ambiguous=0.05, label="crowded tiles")
 
 
 def test_backward_config1_all_params(R, config1):
@@ -303,9 +282,7 @@ def test_backward_config1_all_params(R, config1):
     torch.cuda.synchronize()
     ref = oracle.backward(sc, cam, identity_pose(), td, dimg)
     for k in PARAMS:
-        e = rel_l2(grads[k].cpu().numpy(), ref[k])
-        say(k, "rel err", e)
-        assert e <= 1e-3, (k, e)
+        grad_parity(k, grads[k].cpu().numpy(), ref[k], label="config1")
     dp = dposes[0].cpu().numpy()
     e = np.abs(dp - ref["pose"]).max() / np.abs(ref["pose"]).max()
     say("pose", dp, ref["pose"], e)
@@ -423,16 +400,7 @@ def test_sampled_pixels_tracking_size(R):
     rng = np.random.default_rng(9)
     px = rng.choice(cam["width"] * cam["height"], 3000, replace=False)
     ref = oracle.render(sc, cam, pose, td, candidates=0, pixels=px)
-    mask = unambiguous(ref)
-    flat = {k: (v.reshape(3, -1)[:, px] if k == "color" else v.reshape(-1)[px]) for k, v in gpu.items()}
-    worst = compare_maps(flat, ref, mask)
-    say("max abs err", worst, "excluded", int((~mask).sum()))
-    assert mask.mean() > 0.97
-    swap = order_only_ambiguous(ref)
-    if swap.any():
-        err = np.abs(flat["opacity"] - ref["opacity"])[swap].max()
-        say("order-ambiguous pixels", int(swap.sum()), "opacity err", err)
-        assert err <= 1e-4
+    check_maps(gpu, sc, cam, pose, td, px=px, ref=ref, max_ambiguous=0.03, label="tracking 640x480 sampled")
 
 
 def test_pose_gradient_tracking_size(R):
@@ -764,8 +732,7 @@ def test_wave_lists_within_8x8_binning(R):
         gpu, _ = gpu_render(R, st, dev(sc), identity_pose(), cam)
         ref = oracle.render(sc, cam, identity_pose())
         assert ref["t_final"].min() > 1e-3, "no pixel may stop"
-        mask = unambiguous(ref)
-        compare_maps(gpu, ref, mask)
+        check_maps(gpu, sc, cam, identity_pose(), ref=ref, max_ambiguous=0.01, label="faint")
         H, W = cam["height"], cam["width"]
         proj = oracle.project(sc, cam, identity_pose())
         lists = oracle.tile_lists(proj, cam, tile=8)

@@ -8,7 +8,8 @@ Batched tracking: 1M Gaussians, 32 frames of uneven resolution in one
 launch sequence, per-frame pose gradients vs the oracle's analytic
 backward and (one frame) its frozen-decision central differences, and a 20-step
 graph-captured Adam loop vs the same loop run eagerly.
-Tolerances and the decision-margin masking are those of test_gpu_parity.
+Tolerances, and the admissible results of near-threshold pixels, are those
+of test_gpu_parity.
 """
 import sys
 
@@ -17,7 +18,7 @@ import pytest
 
 import oracle
 from paper_2403_16095_amd import synth
-from helpers import order_only_ambiguous, rel_l2, unambiguous
+from helpers import check_maps, grad_parity, rel_l2
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -62,29 +63,7 @@ def test_mapping_size_all_maps_and_gradients(R):
     out = R.render(st, scd, P, [cam], [t32(td)])[0]
     gpu = to_np(out)
     ref = oracle.render(sc, cam, pose, td)
-    mask = unambiguous(ref)
-    say("unambiguous pixels", mask.mean())
-    assert mask.mean() > 0.9
-    bad = {}
-    for k in MAPS:
-        g = gpu[k]
-        e = np.abs(g - ref[k]) * np.broadcast_to(mask, g.shape)
-        err = e.max()
-        say(k, "max abs err", err, "pixels over 1e-4:", int((e > 1e-4).sum()))
-        if err > 1e-4:
-            bad[k] = np.unravel_index(np.argmax(e), e.shape)
-    for k, idx in bad.items():
-        v, u = idx[-2], idx[-1]
-        px = [int(v) * cam["width"] + int(u)]
-        brute = oracle.render(sc, cam, pose, td, candidates=0, pixels=px)
-        say(f"{k} worst pixel (u={u}, v={v}): gpu {gpu[k][idx]:.7f} oracle {ref[k][idx]:.7f} "
-            f"brute {np.asarray(brute[k])[..., 0].ravel()[idx[0] if len(idx) == 3 else 0]:.7f} "
-            f"n_contrib {ref['n_contrib'][v, u]} (brute {brute['n_contrib'][0]}), gpu blended "
-            f"T_final {ref['t_final'][v, u]:.3e}, decision margin {ref['decision_margin'][v, u]:.3e}, "
-            f"order margin {ref['order_margin'][v, u]:.3e}, stop order margin {ref['stop_order_margin'][v, u]:.3e}")
-    assert not bad, f"maps over 1e-4: {sorted(bad)}"
-    swap = order_only_ambiguous(ref)
-    assert np.abs(gpu["opacity"] - ref["opacity"])[swap].max(initial=0.0) <= 1e-4
+    check_maps(gpu, sc, cam, pose, td, ref=ref, max_ambiguous=0.06, label="mapping 1200x680")
     # the device mapping-loss kernel against the oracle's loss on the same
     # seeded synthetic maps
     rng = np.random.default_rng(77)
@@ -103,9 +82,7 @@ def test_mapping_size_all_maps_and_gradients(R):
     grads, dposes = R.backward(st, [{k: t32(v) for k, v in dimg.items()}])
     rb = oracle.backward(sc, cam, pose, td, dimg)
     for k in PARAMS:
-        e = rel_l2(grads[k].cpu().numpy(), rb[k])
-        say(k, "rel err", e)
-        assert e <= 1e-3, k
+        grad_parity(k, grads[k].cpu().numpy(), rb[k], label="mapping 1200x680")
     e = np.abs(dposes[0].cpu().numpy() - rb["pose"]).max() / np.abs(rb["pose"]).max()
     say("pose rel err", e)
     assert e <= 1e-3
@@ -143,14 +120,8 @@ def test_batched_mapping_8_views_full_size(R):
     # sampled pixels of two views against the oracle
     for v in (0, 5):
         px = rng.choice(cam["width"] * cam["height"], 1500, replace=False)
-        ref = oracle.render(sc, cam, poses[v], None, pixels=px)
-        mask = unambiguous(ref)
-        for k in ("color", "depth", "opacity", "depth_median"):
-            g = outs[v][k].cpu().numpy().astype(np.float64)
-            g = g.reshape(3, -1)[:, px] if k == "color" else g.reshape(-1)[px]
-            err = np.abs(g - ref[k])[np.broadcast_to(mask, g.shape)].max()
-            assert err <= 1e-4, (v, k, err)
-        say("view", v, "sampled parity ok, excluded", int((~mask).sum()))
+        gpu = {k: outs[v][k].cpu().numpy().astype(np.float64) for k in ("color", "depth", "opacity", "depth_median")}
+        check_maps(gpu, sc, cam, poses[v], None, px=px, max_ambiguous=0.15, label=f"batched mapping view {v}")
 
 
 def test_batched_tracking_32_frames(R):
@@ -189,7 +160,7 @@ def test_batched_tracking_32_frames(R):
         rb = oracle.backward(sc, cam, start[v], None, dimg)
         e = np.abs(dposes_r[v].cpu().numpy() - rb["pose"]).max() / np.abs(rb["pose"]).max()
         say("frame", v, cam["width"], "x", cam["height"], "pose grad rel err", e)
-        assert e <= 2e-3
+        assert e <= 1e-3
     # one frame against frozen-decision central differences of the oracle
     v = next((k for k, c in enumerate(cams) if c["width"] == 320), 0)
     cam = cams[v]
@@ -198,7 +169,7 @@ def test_batched_tracking_32_frames(R):
     fd = oracle.fd_linear(sc, cam, start[v], None, dimg, [("pose", 0, c) for c in range(6)])
     e = np.abs(dposes_r[v].cpu().numpy() - fd).max() / np.abs(fd).max()
     say("frame", v, cam["width"], "x", cam["height"], "pose grad vs frozen FD rel err", e)
-    assert e <= 2e-3
+    assert e <= 1e-3
     # 20-step Adam loop captured in one graph vs the same loop eagerly
     params = R.adam_params()
     Pe, ae = P0.clone(), torch.zeros((32, 16), device="cuda")

@@ -168,3 +168,41 @@ def test_too_many_alternatives_are_reported():
     sc = on_axis([2.0] * 12, [0.2] * 12, [[k / 12, 0.5, 1 - k / 12] for k in range(12)])
     alts, count = oracle.render_alternatives(sc, CAM, IDENTITY, None, [CENTRE], DM, OM, max_alts=8)
     assert count[0] == 9
+
+
+def test_map_checker_takes_admissible_results_and_catches_planted_errors(config1):
+    """helpers.check_maps (the GPU parity checker) on oracle maps: the
+    oracle's own render passes; so does the other order of an exact depth
+    tie (an admissible result); a clear pixel off by 2e-4 and an ambiguous
+    pixel matching none of its alternatives fail."""
+    from helpers import check_maps, grad_parity
+    sc, td = config1
+    ref = oracle.render(sc, CAM, IDENTITY, td)
+    res = check_maps(ref, sc, CAM, IDENTITY, td, label="oracle vs itself")
+    assert res["worst_clear"] == 0.0 and res["worst_alt"] == 0.0
+    clear = np.nonzero(((ref["decision_margin"] >= 1e-4) & (ref["order_margin"] >= 1.2e-7)
+                        & (ref["stop_order_margin"] >= 1.2e-7)).ravel())[0]
+    bad = {k: (None if v is None else v.copy()) for k, v in ref.items()}
+    bad["depth"].reshape(-1)[clear[7]] += 2e-4
+    with pytest.raises(AssertionError):
+        check_maps(bad, sc, CAM, IDENTITY, td, label="planted clear-pixel error")
+    # an exact depth tie: the second order is admissible, a value off both is not
+    c1, c2 = [1.0, 0.0, 0.0], [0.0, 0.0, 1.0]
+    tie = on_axis([2.0, 2.0], [0.6, 0.3], [c1, c2])
+    r2 = oracle.render(tie, CAM, IDENTITY)
+    other = blend([(0.3, c2, 2.0), (0.6, c1, 2.0)])
+    swapped = {k: (None if v is None else v.copy()) for k, v in r2.items()}
+    for c in range(3):
+        swapped["color"][c].reshape(-1)[CENTRE] = other[0][c]
+    assert not np.allclose(swapped["color"], r2["color"], atol=1e-4)
+    check_maps(swapped, tie, CAM, IDENTITY, label="other order of a tie")
+    swapped["color"][0].reshape(-1)[CENTRE] += 1e-2
+    with pytest.raises(AssertionError):
+        check_maps(swapped, tie, CAM, IDENTITY, label="planted ambiguous-pixel error")
+    # the gradient report: the binding relative L2 bar and the element-wise count
+    g = np.random.default_rng(3).standard_normal(1000)
+    assert grad_parity("g", g, g) == 0.0
+    assert grad_parity("g", g * (1 + 5e-4), g) == 0.0
+    assert 0.0 < grad_parity("g", g + 1e-2 * (np.arange(1000) == 3), g) <= 1e-3
+    with pytest.raises(AssertionError):
+        grad_parity("g", g * 1.01, g)
