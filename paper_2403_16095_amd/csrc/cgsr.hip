@@ -894,7 +894,7 @@ namespace {
 
 // Checks a writable set; colour_w receives the colour floats per Gaussian.
 // A set of no rows (empty) may have every array NULL; then *colour_w = 0.
-cgsr_status check_arrays(const cgsr_gaussian_arrays* a, const char* what, int* colour_w, bool empty = false) {
+static cgsr_status check_arrays(const cgsr_gaussian_arrays* a, const char* what, int* colour_w, bool empty = false) {
   if (!a) return fail(CGSR_ERR_INVALID_ARG, "%s: NULL arrays", what);
   if (empty && !a->means && !a->log_scales && !a->quats && !a->opacity_logits && !a->rgb && !a->sh) {
     *colour_w = 0;
@@ -908,14 +908,14 @@ cgsr_status check_arrays(const cgsr_gaussian_arrays* a, const char* what, int* c
   return CGSR_OK;
 }
 
-GaussArrays gauss_arrays(const cgsr_gaussian_arrays* a) {
+static GaussArrays gauss_arrays(const cgsr_gaussian_arrays* a) {
   return GaussArrays{a->means, a->log_scales, a->quats, a->opacity_logits, a->sh ? nullptr : a->rgb, a->sh};
 }
 
 // src and dst of an out-of-place pass: same colour layout, no shared array.
 // src_empty / dst_empty: that side has no rows and may be all NULL.
-cgsr_status check_src_dst(const cgsr_gaussian_arrays* src, const cgsr_gaussian_arrays* dst, const char* what,
-                          int* colour_w, bool src_empty = false, bool dst_empty = false) {
+static cgsr_status check_src_dst(const cgsr_gaussian_arrays* src, const cgsr_gaussian_arrays* dst, const char* what,
+                                 int* colour_w, bool src_empty = false, bool dst_empty = false) {
   int wd = 0;
   cgsr_status s = check_arrays(src, what, colour_w, src_empty);
   if (!s) s = check_arrays(dst, what, &wd, dst_empty);

@@ -19,6 +19,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / kWave;
 constexpr int kScanThreads = 1024;
+constexpr int kCompactItems = 1024;   // Gaussians per compaction workgroup
 
 struct Ranked {
   uint32_t* counts;   // [kRankKinds][blocks]: counts, then exclusive offsets
@@ -45,15 +46,16 @@ __global__ __launch_bounds__(kThreads) void ranked_count_kernel(Op op, int64_t n
   }
 }
 
-// One workgroup: exclusive scan of each kind's workgroup counts, each lane
-// taking a contiguous run of workgroups.
+// One workgroup: exclusive scan of each of kKinds kinds' workgroup counts,
+// each lane taking a contiguous run of workgroups.
+template <int kKinds>
 __global__ __launch_bounds__(kScanThreads) void ranked_scan_kernel(Ranked r) {
   __shared__ uint32_t s_w[kScanThreads / kWave];
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int64_t per = (r.blocks + kScanThreads - 1) / kScanThreads;
   const int64_t b0 = std::min<int64_t>(r.blocks, (int64_t)threadIdx.x * per);
   const int64_t b1 = std::min<int64_t>(r.blocks, b0 + per);
-  for (int k = 0; k < kRankKinds; ++k) {
+  for (int k = 0; k < kKinds; ++k) {
     uint32_t* c = r.counts + k * r.blocks;
     uint32_t run = 0;
     for (int64_t b = b0; b < b1; ++b) run += c[b];
@@ -170,23 +172,131 @@ struct SpawnOp {
   }
 };
 
-struct CompactOp {
-  GaussArrays src, dst;
-  int colour_w;
-  const uint8_t* keep;
-  ExtraArrays extra;
+// Compaction streams the set array by array.  A workgroup owns a chunk of
+// kCompactItems consecutive Gaussians: it ranks the chunk's kept ones in LDS
+// (one block scan, each thread ranking kCompactPerThread consecutive items),
+// then, for every array of w floats per Gaussian, reads the chunk's w x
+// kCompactItems floats as 16-byte loads in address order and writes each
+// kept float to its output row.  Kept Gaussians are contiguous in the output,
+// so lanes write consecutive addresses too: both sides are coalesced whatever
+// the width, instead of one lane walking one Gaussian's floats.
+constexpr int kCompactThreads = 256;
+constexpr int kCompactPerThread = 4;
+constexpr int kCompactUnroll = 4;   // 16-byte loads in flight per thread
+constexpr uint32_t kDropped = 0xFFFFFFFFu;
 
-  __device__ uint32_t flags(int64_t i) const { return keep[i] ? 1u : 0u; }
-
-  __device__ void emit(int64_t i, uint32_t, const uint32_t* rank, const uint32_t*) const {
-    const int64_t j = rank[0];
-    copy_gaussian(src, dst, i, j, colour_w);
-    for (int e = 0; e < extra.n; ++e) {
-      const int w = extra.width[e];
-      for (int c = 0; c < w; ++c) extra.dst[e][(int64_t)w * j + c] = extra.src[e][(int64_t)w * i + c];
-    }
-  }
+struct CompactArray {
+  const float* src;
+  float* dst;
+  uint32_t width;
+  uint32_t magic;   // floor(2^32 / width) + 1 (width >= 2): row = umulhi(f, magic)
 };
+constexpr int kMaxCompactArrays = 6 + kMaxExtraArrays;
+
+struct CompactJob {
+  int64_t n;
+  const uint8_t* keep;
+  uint32_t* counts;   // [chunks]: kept per chunk, then exclusive offsets
+  uint32_t* total;    // [1]
+  int64_t chunks;
+  int n_arrays;
+  CompactArray a[kMaxCompactArrays];
+};
+
+__global__ __launch_bounds__(kCompactThreads) void compact_count_kernel(CompactJob j) {
+  __shared__ uint32_t s_w[kCompactThreads / kWave];
+  const int64_t base = (int64_t)blockIdx.x * kCompactItems;
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < kCompactPerThread; ++k) {
+    const int64_t i = base + k * kCompactThreads + threadIdx.x;
+    c += (i < j.n && j.keep[i]) ? 1u : 0u;
+  }
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) c += __shfl_xor(c, d);
+  if (threadIdx.x % kWave == 0) s_w[threadIdx.x / kWave] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int q = 0; q < kCompactThreads / kWave; ++q) t += s_w[q];
+    j.counts[blockIdx.x] = t;
+  }
+}
+
+// Row of float f (0 <= f < kCompactItems * w) of a chunk: f / w, by a
+// multiply-high with magic = floor(2^32 / w) + 1, exact while f (w - 2^32 mod
+// w) < 2^32, which f < kCompactItems w with w < 2048 guarantees.
+__device__ __forceinline__ uint32_t row_of(uint32_t f, const CompactArray& a) {
+  if (a.width == 1) return f;
+  if (a.width < 2048) return __umulhi(f, a.magic);
+  return f / a.width;
+}
+
+__device__ __forceinline__ void put(const CompactArray& a, const uint32_t* s_rank, uint32_t f, float v) {
+  const uint32_t r = row_of(f, a);
+  const uint32_t out = s_rank[r];
+  if (out != kDropped) a.dst[(int64_t)out * a.width + (f - r * a.width)] = v;
+}
+
+__global__ __launch_bounds__(kCompactThreads) void compact_emit_kernel(CompactJob j) {
+  __shared__ uint32_t s_rank[kCompactItems];   // output row of each item of the chunk, or kDropped
+  __shared__ uint32_t s_w[kCompactThreads / kWave];
+  const int64_t base = (int64_t)blockIdx.x * kCompactItems;
+  const int t = threadIdx.x, lane = t % kWave, w = t / kWave;
+  uint32_t f[kCompactPerThread], c = 0;
+#pragma unroll
+  for (int k = 0; k < kCompactPerThread; ++k) {
+    const int64_t i = base + kCompactPerThread * t + k;
+    f[k] = (i < j.n && j.keep[i]) ? 1u : 0u;
+    c += f[k];
+  }
+  uint32_t inc = c;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const uint32_t y = __shfl_up(inc, d);
+    if (lane >= d) inc += y;
+  }
+  if (lane == kWave - 1) s_w[w] = inc;
+  __syncthreads();
+  uint32_t row = j.counts[blockIdx.x] + inc - c;
+  for (int q = 0; q < w; ++q) row += s_w[q];
+#pragma unroll
+  for (int k = 0; k < kCompactPerThread; ++k) s_rank[kCompactPerThread * t + k] = f[k] ? row++ : kDropped;
+  __syncthreads();
+  const uint32_t items = (uint32_t)std::min<int64_t>(kCompactItems, j.n - base);
+  for (int ai = 0; ai < j.n_arrays; ++ai) {
+    const CompactArray a = j.a[ai];
+    const float* src = a.src + base * a.width;
+    const uint32_t len = items * a.width;
+    uint32_t done = 0;
+    if ((reinterpret_cast<uintptr_t>(a.src) & 15u) == 0) {
+      // a chunk starts at a multiple of kCompactItems * w floats, so its
+      // 16-byte loads stay aligned when the array is
+      const uint32_t nv = len / 4;
+      const float4* src4 = reinterpret_cast<const float4*>(src);
+      for (uint32_t q0 = t; q0 < nv; q0 += kCompactThreads * kCompactUnroll) {
+        float4 v[kCompactUnroll];
+#pragma unroll
+        for (int u = 0; u < kCompactUnroll; ++u) {
+          const uint32_t q = q0 + u * kCompactThreads;
+          v[u] = q < nv ? src4[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < kCompactUnroll; ++u) {
+          const uint32_t q = q0 + u * kCompactThreads;
+          if (q < nv) {
+            put(a, s_rank, 4 * q, v[u].x);
+            put(a, s_rank, 4 * q + 1, v[u].y);
+            put(a, s_rank, 4 * q + 2, v[u].z);
+            put(a, s_rank, 4 * q + 3, v[u].w);
+          }
+        }
+      }
+      done = nv * 4;
+    }
+    for (uint32_t q = done + t; q < len; q += kCompactThreads) put(a, s_rank, q, src[q]);
+  }
+}
 
 // Flags: 1 kept (not split), 2 clone, 4 split.
 struct DensifyOp {
@@ -245,7 +355,7 @@ hipError_t run_ranked(const Op& op, int64_t n, uint32_t* totals_host, hipStream_
   if (e != hipSuccess) return e;
   Ranked r{buf, buf + kRankKinds * blocks, blocks};
   hipLaunchKernelGGL(ranked_count_kernel<Op>, dim3((unsigned)blocks), dim3(kThreads), 0, s, op, n, r);
-  hipLaunchKernelGGL(ranked_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, r);
+  hipLaunchKernelGGL(ranked_scan_kernel<kRankKinds>, dim3(1), dim3(kScanThreads), 0, s, r);
   hipLaunchKernelGGL(ranked_emit_kernel<Op>, dim3((unsigned)blocks), dim3(kThreads), 0, s, op, n, r);
   e = hipGetLastError();
   if (e == hipSuccess) e = hipMemcpyAsync(totals_host, r.totals, sizeof(uint32_t) * kRankKinds, hipMemcpyDeviceToHost, s);
@@ -285,13 +395,59 @@ hipError_t run_spawn(const GaussArrays& dst, int64_t n, int64_t capacity, const 
   return e;
 }
 
+namespace {
+
+// Fills the job's array list from the set and the extra arrays.
+CompactJob compact_job(int64_t n, const uint8_t* keep, const GaussArrays& src, const GaussArrays& dst, int colour_w,
+                       const ExtraArrays& extra) {
+  CompactJob j{};
+  j.n = n;
+  j.keep = keep;
+  j.chunks = (n + kCompactItems - 1) / kCompactItems;
+  auto add = [&](const float* sp, float* dp, int w) {
+    CompactArray& a = j.a[j.n_arrays++];
+    a.src = sp;
+    a.dst = dp;
+    a.width = (uint32_t)w;
+    a.magic = w >= 2 ? (uint32_t)((1ull << 32) / (uint64_t)w + 1ull) : 0u;
+  };
+  add(src.means, dst.means, 3);
+  add(src.log_scales, dst.log_scales, 3);
+  add(src.quats, dst.quats, 4);
+  add(src.opacity_logits, dst.opacity_logits, 1);
+  add(src.sh ? src.sh : src.rgb, src.sh ? dst.sh : dst.rgb, colour_w);
+  for (int e = 0; e < extra.n; ++e) add(extra.src[e], extra.dst[e], extra.width[e]);
+  return j;
+}
+
+// Count, scan and emit with the caller's scratch (chunks + 1 words), then
+// the kept count to the host.
+hipError_t launch_compact(CompactJob j, uint32_t* scratch, uint32_t* total, hipStream_t s) {
+  j.counts = scratch;
+  j.total = scratch + j.chunks;
+  const Ranked r{j.counts, j.total, j.chunks};
+  hipLaunchKernelGGL(compact_count_kernel, dim3((unsigned)j.chunks), dim3(kCompactThreads), 0, s, j);
+  hipLaunchKernelGGL(ranked_scan_kernel<1>, dim3(1), dim3(kScanThreads), 0, s, r);
+  hipLaunchKernelGGL(compact_emit_kernel, dim3((unsigned)j.chunks), dim3(kCompactThreads), 0, s, j);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(total, j.total, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+  return e;
+}
+
+}  // namespace
+
 hipError_t run_compact(int64_t n, const uint8_t* keep, const GaussArrays& src, const GaussArrays& dst, int colour_w,
                        const ExtraArrays& extra, uint32_t* total, hipStream_t s) {
-  CompactOp op{src, dst, colour_w, keep, extra};
-  uint32_t t[kRankKinds];
-  const hipError_t e = run_ranked(op, n, t, s);
-  *total = t[0];
-  return e;
+  *total = 0;
+  if (n <= 0) return hipSuccess;
+  const CompactJob j = compact_job(n, keep, src, dst, colour_w, extra);
+  uint32_t* buf = nullptr;
+  hipError_t e = hipMallocAsync((void**)&buf, sizeof(uint32_t) * (size_t)(j.chunks + 1), s);
+  if (e != hipSuccess) return e;
+  e = launch_compact(j, buf, total, s);
+  const hipError_t f = hipFreeAsync(buf, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e != hipSuccess ? e : f;
 }
 
 hipError_t run_densify(int64_t n, const float* grad_accum, const uint32_t* count, float threshold, float dense_scale,

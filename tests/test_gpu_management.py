@@ -119,6 +119,33 @@ def test_compaction_matches_oracle(R, n, sh):
         np.testing.assert_array_equal(g.cpu().numpy(), e[keep.astype(bool)])
 
 
+@pytest.mark.parametrize("n,p_keep", [(1023, 0.5), (1024, 1.0), (2049, 0.0), (70_001, 0.95)])
+def test_compaction_layouts(R, n, p_keep):
+    """Every chunk shape and array layout the streaming compaction meets:
+    ragged last chunk, all / none kept, widths 1, 2, 7 and 2050 (the
+    division fallback), and an array that is not 16-byte aligned (a view one
+    float into its buffer, so the chunk is read float by float)."""
+    say(f"case: compaction layouts, {n} Gaussians, keep fraction {p_keep}")
+    rng = np.random.default_rng(n + 7)
+    sc = synth.uniform_box_scene(5, n)
+    keep = (rng.random(n) < p_keep).astype(np.uint8)
+    widths = [1, 2, 7] + ([2050] if n <= 2049 else [])
+    extra = [rng.standard_normal((n, w)).astype(np.float32) for w in widths]
+    extra_t = [t32(e) for e in extra]
+    raw = torch.from_numpy(rng.standard_normal(n * 5 + 1).astype(np.float32)).cuda()
+    odd = raw[1:].view(n, 5)          # 4 bytes past a 256-byte aligned allocation
+    assert odd.data_ptr() % 16 == 4
+    extra_t.append(odd)
+    out, ex = R.compact_gaussians({k: t32(v) for k, v in sc.items()}, torch.from_numpy(keep).cuda(), extra_t)
+    ref = M.compact(sc, keep)
+    kb = keep.astype(bool)
+    assert out["means"].shape[0] == int(kb.sum())
+    for k in sc:
+        np.testing.assert_array_equal(out[k].cpu().numpy(), ref[k], err_msg=k)
+    for e, g in zip(extra + [odd.cpu().numpy()], ex):
+        np.testing.assert_array_equal(g.cpu().numpy(), e[kb])
+
+
 def test_densify_statistic_from_the_backward(R):
     say("case: densification statistic, 2000 Gaussians 64x48, two backwards")
     sc = synth.uniform_box_scene(0, 2000)
