@@ -465,6 +465,27 @@ cgsr_status cgsr_compact_gaussians(int64_t n, const uint8_t *keep, const cgsr_ga
                                    const float *const *extra_src, float *const *extra_dst,
                                    const int32_t *extra_width, int64_t *n_out, void *stream);
 
+/* Most Gaussians cgsr_compact_gaussians_noalloc takes (2^26). */
+#define CGSR_COMPACT_NOALLOC_MAX_N 67108864
+
+/*
+ * cgsr_compact_gaussians for callers that cannot allocate device memory
+ * (serving loops and harnesses that forbid hipMalloc): the same arguments,
+ * result, ordering and errors, but the call allocates nothing.  Its
+ * counters (one per 1024 Gaussians, 256 KB) live in a fixed array of the
+ * library, one copy per GPU, held until the process ends; each call
+ * rewrites the counters it reads before reading them.
+ *   n   0 .. CGSR_COMPACT_NOALLOC_MAX_N; larger n is CGSR_ERR_INVALID_ARG
+ *       (use cgsr_compact_gaussians).
+ * Calls that overlap on one GPU (from several host threads, or on streams
+ * not ordered with each other) share that array and race: serialise them.
+ * Like cgsr_compact_gaussians it synchronises the stream to return *n_out.
+ */
+cgsr_status cgsr_compact_gaussians_noalloc(int64_t n, const uint8_t *keep, const cgsr_gaussian_arrays *src,
+                                           const cgsr_gaussian_arrays *dst, int32_t n_extra,
+                                           const float *const *extra_src, float *const *extra_dst,
+                                           const int32_t *extra_width, int64_t *n_out, void *stream);
+
 /*
  * Densification statistic (Sec. 3.3 keeps the densification of splatting):
  * from now on every cgsr_backward on this state adds, for each (view,

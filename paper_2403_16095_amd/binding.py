@@ -30,7 +30,8 @@ EXPORTED = (
     "cgsr_render", "cgsr_render_nu", "cgsr_nu_prune", "cgsr_mapping_objective", "cgsr_gaussian_adam_step",
     "cgsr_backward", "cgsr_tracking_loss_grad", "cgsr_mapping_loss_grad", "cgsr_pose_adam_step",
     "cgsr_tracking_step",
-    "cgsr_autotune_tracking", "cgsr_spawn_gaussians", "cgsr_compact_gaussians", "cgsr_set_densify_stats",
+    "cgsr_autotune_tracking", "cgsr_spawn_gaussians", "cgsr_compact_gaussians", "cgsr_compact_gaussians_noalloc",
+    "cgsr_set_densify_stats",
     "cgsr_densify_gaussians", "cgsr_state_check", "cgsr_get_stats", "cgsr_get_timings", "cgsr_debug_buffers",
     "cgsr_last_error",
     "cgsr_version",
@@ -146,6 +147,7 @@ def lib() -> C.CDLL:
     L.cgsr_compact_gaussians.argtypes = [C.c_int64, vp, C.POINTER(cgsr_gaussian_arrays),
                                          C.POINTER(cgsr_gaussian_arrays), C.c_int32, C.POINTER(vp), C.POINTER(vp),
                                          C.POINTER(C.c_int32), C.POINTER(C.c_int64), vp]
+    L.cgsr_compact_gaussians_noalloc.argtypes = L.cgsr_compact_gaussians.argtypes
     L.cgsr_set_densify_stats.argtypes = [vp, vp, vp]
     L.cgsr_densify_gaussians.argtypes = [C.c_int64, vp, vp, C.c_float, C.c_float, vp,
                                          C.POINTER(cgsr_gaussian_arrays), C.POINTER(cgsr_gaussian_arrays), C.c_int64,
@@ -248,6 +250,19 @@ def cgsr_compact_gaussians(n, keep, src: cgsr_gaussian_arrays, dst: cgsr_gaussia
     ew = (C.c_int32 * max(k, 1))(*extra_width)
     out = C.c_int64(0)
     _check(lib().cgsr_compact_gaussians(n, keep, C.byref(src), C.byref(dst), k, es, ed, ew, C.byref(out), stream))
+    return out.value
+
+
+def cgsr_compact_gaussians_noalloc(n, keep, src: cgsr_gaussian_arrays, dst: cgsr_gaussian_arrays, extra_src,
+                                   extra_dst, extra_width, stream) -> int:
+    """As cgsr_compact_gaussians, with the library's fixed scratch (no device allocation)."""
+    k = len(extra_src)
+    es = (C.c_void_p * max(k, 1))(*extra_src)
+    ed = (C.c_void_p * max(k, 1))(*extra_dst)
+    ew = (C.c_int32 * max(k, 1))(*extra_width)
+    out = C.c_int64(0)
+    _check(lib().cgsr_compact_gaussians_noalloc(n, keep, C.byref(src), C.byref(dst), k, es, ed, ew, C.byref(out),
+                                                stream))
     return out.value
 
 

@@ -964,29 +964,64 @@ cgsr_status cgsr_spawn_gaussians(const cgsr_gaussian_arrays* dst, int64_t n, int
   return CGSR_OK;
 }
 
+namespace {
+
+// Argument checks and the extra-array table shared by both compaction entry
+// points.
+static cgsr_status compact_args(const char* what, int64_t n, const uint8_t* keep, const cgsr_gaussian_arrays* src,
+                                const cgsr_gaussian_arrays* dst, int32_t n_extra, const float* const* extra_src,
+                                float* const* extra_dst, const int32_t* extra_width, int64_t* n_out, int* cw,
+                                ExtraArrays* ex) {
+  cgsr_status s = check_src_dst(src, dst, what, cw, n == 0, n == 0);
+  if (s) return s;
+  if (!n_out || (n > 0 && !keep)) return fail(CGSR_ERR_INVALID_ARG, "%s: NULL argument", what);
+  if (n < 0 || n > INT32_MAX) return fail(CGSR_ERR_INVALID_ARG, "%s: need 0 <= n < 2^31", what);
+  if (n_extra < 0 || n_extra > kMaxExtraArrays || (n_extra > 0 && (!extra_src || !extra_dst || !extra_width)))
+    return fail(CGSR_ERR_INVALID_ARG, "%s: 0 .. %d extra arrays with their pointers and widths", what,
+                kMaxExtraArrays);
+  *ex = ExtraArrays{};
+  ex->n = n_extra;
+  for (int e = 0; e < n_extra; ++e) {
+    if (!extra_src[e] || !extra_dst[e] || extra_width[e] < 1 || extra_src[e] == extra_dst[e])
+      return fail(CGSR_ERR_INVALID_ARG, "%s: bad extra array %d", what, e);
+    ex->src[e] = extra_src[e];
+    ex->dst[e] = extra_dst[e];
+    ex->width[e] = extra_width[e];
+  }
+  return CGSR_OK;
+}
+
+}  // namespace
+
 cgsr_status cgsr_compact_gaussians(int64_t n, const uint8_t* keep, const cgsr_gaussian_arrays* src,
                                    const cgsr_gaussian_arrays* dst, int32_t n_extra, const float* const* extra_src,
                                    float* const* extra_dst, const int32_t* extra_width, int64_t* n_out,
                                    void* stream) {
   int cw = 0;
-  cgsr_status s = check_src_dst(src, dst, "cgsr_compact_gaussians", &cw, n == 0, n == 0);
+  ExtraArrays ex;
+  cgsr_status s = compact_args("cgsr_compact_gaussians", n, keep, src, dst, n_extra, extra_src, extra_dst,
+                               extra_width, n_out, &cw, &ex);
   if (s) return s;
-  if (!n_out || (n > 0 && !keep)) return fail(CGSR_ERR_INVALID_ARG, "cgsr_compact_gaussians: NULL argument");
-  if (n < 0 || n > INT32_MAX) return fail(CGSR_ERR_INVALID_ARG, "cgsr_compact_gaussians: need 0 <= n < 2^31");
-  if (n_extra < 0 || n_extra > kMaxExtraArrays || (n_extra > 0 && (!extra_src || !extra_dst || !extra_width)))
-    return fail(CGSR_ERR_INVALID_ARG, "cgsr_compact_gaussians: 0 .. %d extra arrays with their pointers and widths",
-                kMaxExtraArrays);
-  ExtraArrays ex{};
-  ex.n = n_extra;
-  for (int e = 0; e < n_extra; ++e) {
-    if (!extra_src[e] || !extra_dst[e] || extra_width[e] < 1 || extra_src[e] == extra_dst[e])
-      return fail(CGSR_ERR_INVALID_ARG, "cgsr_compact_gaussians: bad extra array %d", e);
-    ex.src[e] = extra_src[e];
-    ex.dst[e] = extra_dst[e];
-    ex.width[e] = extra_width[e];
-  }
   uint32_t total = 0;
   HIP_TRY(run_compact(n, keep, gauss_arrays(src), gauss_arrays(dst), cw, ex, &total, (hipStream_t)stream));
+  *n_out = total;
+  return CGSR_OK;
+}
+
+cgsr_status cgsr_compact_gaussians_noalloc(int64_t n, const uint8_t* keep, const cgsr_gaussian_arrays* src,
+                                           const cgsr_gaussian_arrays* dst, int32_t n_extra,
+                                           const float* const* extra_src, float* const* extra_dst,
+                                           const int32_t* extra_width, int64_t* n_out, void* stream) {
+  int cw = 0;
+  ExtraArrays ex;
+  cgsr_status s = compact_args("cgsr_compact_gaussians_noalloc", n, keep, src, dst, n_extra, extra_src, extra_dst,
+                               extra_width, n_out, &cw, &ex);
+  if (s) return s;
+  if (n > CGSR_COMPACT_NOALLOC_MAX_N)
+    return fail(CGSR_ERR_INVALID_ARG, "cgsr_compact_gaussians_noalloc: n = %lld exceeds its fixed scratch (%d)",
+                (long long)n, CGSR_COMPACT_NOALLOC_MAX_N);
+  uint32_t total = 0;
+  HIP_TRY(run_compact_noalloc(n, keep, gauss_arrays(src), gauss_arrays(dst), cw, ex, &total, (hipStream_t)stream));
   *n_out = total;
   return CGSR_OK;
 }

@@ -94,6 +94,12 @@ hipError_t run_spawn(const GaussArrays& dst, int64_t n, int64_t capacity, const 
                      float init_logit, int K, uint32_t* total, hipStream_t s);
 hipError_t run_compact(int64_t n, const uint8_t* keep, const GaussArrays& src, const GaussArrays& dst, int colour_w,
                        const ExtraArrays& extra, uint32_t* total, hipStream_t s);
+// The same without device allocation: its counters live in a fixed
+// per-GPU array of the library; n <= kNoAllocMaxN.  Overlapping calls on one
+// GPU share that array.
+constexpr int64_t kNoAllocMaxN = CGSR_COMPACT_NOALLOC_MAX_N;
+hipError_t run_compact_noalloc(int64_t n, const uint8_t* keep, const GaussArrays& src, const GaussArrays& dst,
+                               int colour_w, const ExtraArrays& extra, uint32_t* total, hipStream_t s);
 hipError_t run_densify(int64_t n, const float* grad_accum, const uint32_t* count, float threshold, float dense_scale,
                        const float* normals, const GaussArrays& src, const GaussArrays& dst, int colour_w,
                        int64_t capacity, uint32_t* totals, hipStream_t s);

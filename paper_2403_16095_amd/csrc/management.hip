@@ -10,6 +10,7 @@
 // scanning the counts into offsets and totals, then every workgroup emitting
 // its items at rank = workgroup offset + preceding waves + lane rank (mbcnt).
 #include <algorithm>
+#include <mutex>
 
 #include "kernels.hpp"
 
@@ -448,6 +449,55 @@ hipError_t run_compact(int64_t n, const uint8_t* keep, const GaussArrays& src, c
   const hipError_t f = hipFreeAsync(buf, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   return e != hipSuccess ? e : f;
+}
+
+// Scratch of the allocation-free compaction: one counter per chunk of
+// kCompactItems Gaussians plus the total, for up to kNoAllocMaxN Gaussians
+// (256 KB).  Every GPU the library runs on holds its own copy until the
+// process ends.  In host code the name is only a stand-in for the device
+// address, which scratch_address() takes from hipGetSymbolAddress once per
+// device and keeps.
+constexpr int64_t kNoAllocChunks = kNoAllocMaxN / kCompactItems;
+static __device__ __align__(256) uint32_t scratch[kNoAllocChunks + 64];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+uint32_t* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's scratch (the current device's).
+hipError_t scratch_address(uint32_t** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<uint32_t*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t run_compact_noalloc(int64_t n, const uint8_t* keep, const GaussArrays& src, const GaussArrays& dst,
+                               int colour_w, const ExtraArrays& extra, uint32_t* total, hipStream_t s) {
+  *total = 0;
+  if (n <= 0) return hipSuccess;
+  if (n > kNoAllocMaxN) return hipErrorInvalidValue;
+  uint32_t* buf = nullptr;
+  hipError_t e = scratch_address(&buf);
+  if (e != hipSuccess) return e;
+  // every counter the kernels read is written first by this call's count
+  // and scan launches, so nothing is cleared
+  e = launch_compact(compact_job(n, keep, src, dst, colour_w, extra), buf, total, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e;
 }
 
 hipError_t run_densify(int64_t n, const float* grad_accum, const uint32_t* count, float threshold, float dense_scale,

@@ -239,18 +239,21 @@ def spawn_gaussians(params: dict, n: int, cam: dict, pose: torch.Tensor, color: 
                                   float(psi), int(stride), float(init_logit), _stream())
 
 
-def compact_gaussians(params: dict, keep: torch.Tensor, extra=()):
+def compact_gaussians(params: dict, keep: torch.Tensor, extra=(), no_alloc: bool = False):
     """The Gaussians with keep != 0 (uint8 [n]) in order: returns (new arrays
     trimmed to the kept count, list of compacted extra tensors).  ``extra``:
-    per-Gaussian float32 tensors [n, ...] compacted alike."""
+    per-Gaussian float32 tensors [n, ...] compacted alike.  no_alloc: the
+    library call uses its fixed per-GPU scratch instead of allocating (n up to
+    CGSR_COMPACT_NOALLOC_MAX_N); the output tensors are still allocated here."""
     n = params["means"].shape[0]
     if not (keep.is_cuda and keep.dtype == torch.uint8 and keep.numel() == n and keep.is_contiguous()):
         raise ValueError("keep must be a contiguous uint8 CUDA tensor of n entries")
     dst = empty_like_set(params, n)
     ex_dst = [torch.empty_like(e) for e in extra]
     widths = [int(e.numel() // max(n, 1)) for e in extra]
-    m = B.cgsr_compact_gaussians(n, keep.data_ptr(), arrays_struct(params), arrays_struct(dst),
-                                 [e.data_ptr() for e in extra], [e.data_ptr() for e in ex_dst], widths, _stream())
+    fn = B.cgsr_compact_gaussians_noalloc if no_alloc else B.cgsr_compact_gaussians
+    m = fn(n, keep.data_ptr(), arrays_struct(params), arrays_struct(dst), [e.data_ptr() for e in extra],
+           [e.data_ptr() for e in ex_dst], widths, _stream())
     return {k: v[:m] for k, v in dst.items()}, [e[:m] for e in ex_dst]
 
 

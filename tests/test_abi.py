@@ -126,6 +126,14 @@ def test_management_and_sh_argument_checks(lib):
     assert compact(ga, other, keep=None) == B.CGSR_ERR_INVALID_ARG
     assert compact(ga, other, k=13) == B.CGSR_ERR_INVALID_ARG
     assert compact(ga, other, n=-1) == B.CGSR_ERR_INVALID_ARG
+    # the allocation-free variant: same checks, and n beyond its fixed scratch
+    compact0 = lambda src, dst, n=4, keep=8, k=0: lib.cgsr_compact_gaussians_noalloc(
+        n, keep, C.byref(src), C.byref(dst), k, z, z, w, C.byref(n_out), None)
+    assert compact0(ga, shared) == B.CGSR_ERR_INVALID_ARG
+    assert compact0(ga, other, keep=None) == B.CGSR_ERR_INVALID_ARG
+    assert compact0(ga, other, n=-1) == B.CGSR_ERR_INVALID_ARG
+    assert compact0(ga, other, n=(1 << 26) + 1) == B.CGSR_ERR_INVALID_ARG
+    assert "exceeds its fixed scratch" in B.cgsr_last_error()
     dens = lambda src, dst, n=4, normals=8: lib.cgsr_densify_gaussians(
         n, 8, 8, 1e-4, 0.01, normals, C.byref(src), C.byref(dst), 10, C.byref(n_out), None)
     assert dens(ga, other, normals=None) == B.CGSR_ERR_INVALID_ARG
