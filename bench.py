@@ -57,6 +57,38 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (256 CUs x 2.4 GHz)
 FLOP_EVAL = 13
 FLOP_BLEND = 12
 FLOP_BLEND_BWD = 44
+# The mapping iteration blends six quantities (colour, alpha-depth, opacity,
+# uncertainty with sensor depth, Eq. 3-10) and takes every gradient:
+#   forward per blended Gaussian: the 12 above + w (d - D)^2 (3) + the
+#   median test (1)                                                      = 16
+#   backward per blended Gaussian: T_j (2), w (1), dL/dalpha over the six
+#   quantities (15), behind sums (18), dL/dpower and dL/dopacity (2),
+#   dL/dmu (8), dL/dconic (9), dL/ddepth with the uncertainty term (6),
+#   dL/dcolour (3), opacity sum (1)                                      = 65
+FLOP_BLEND_MAP = 16
+FLOP_BLEND_BWD_MAP = 65
+FP32_REACHABLE_TFLOPS = 78.6     # without packed FP32 (this build disables it)
+VALU_CYCLES = 4                  # a wave64 VALU instruction on a 16-lane SIMD
+SIMDS = 1024                     # 256 CUs x 4 SIMDs
+CLOCK_HZ = 2.4e9
+
+
+def alu_roofline(kernel, symbol, flops, ms, timing, counters=None):
+    """ALU roofline of one kernel: algorithmic flops per launch over its
+    measured launch duration, against the published FP32 vector peak and the
+    peak reachable without packed FP32; with the committed instruction
+    counters of that kernel, the fraction of SIMD cycles issuing VALU."""
+    achieved = flops / (ms * 1e-3) / 1e12
+    out = {"bound": "alu", "kernel": kernel, "symbol": symbol, "achieved": round(achieved, 4),
+           "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 5),
+           "peak_reachable": FP32_REACHABLE_TFLOPS, "frac_reachable": round(achieved / FP32_REACHABLE_TFLOPS, 5),
+           "traffic": None, "avg_ms": round(ms, 5), "timing": timing, "algorithmic_flops": int(flops)}
+    if counters:
+        out["traffic"] = counters.get("bytes_per_launch")
+        if counters.get("valu_insts"):
+            out["valu_insts"] = counters["valu_insts"]
+            out["valu_issue_frac"] = round(counters["valu_insts"] * VALU_CYCLES / (SIMDS * CLOCK_HZ * ms * 1e-3), 4)
+    return out
 
 
 def kernel_source_digest() -> str:
@@ -72,11 +104,12 @@ def kernel_source_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter profile
-    (profiles/blend_traffic.json: FETCH_SIZE and WRITE_SIZE scaled by a copy
-    calibration), or None if the kernels changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", "blend_traffic.json")
+def measured_counters(kernel: str):
+    """Committed counter profile of `kernel` (profiles/blend_counters.json:
+    HBM bytes per launch from FETCH_SIZE and WRITE_SIZE scaled by a copy
+    calibration, VALU wave instructions per launch), or None if the kernel
+    sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "blend_counters.json")
     try:
         with open(path) as f:
             prof = json.load(f)
@@ -84,8 +117,7 @@ def measured_traffic(kernel: str):
         return None
     if prof.get("source_sha256") != kernel_source_digest():
         return None
-    k = prof.get("kernels", {}).get(kernel)
-    return None if k is None else k.get("bytes_per_launch")
+    return prof.get("kernels", {}).get(kernel)
 
 
 def copy_bandwidth(torch, mb=1024, reps=10):
@@ -266,6 +298,26 @@ class MappingIteration:
             for v in range(self.V):
                 self._views(self.states[v], [v])
 
+    def stage_times(self, reps=5):
+        """Stage durations (ms) of the batched form of the iteration, from
+        the library's HIP events around each stage, on a timing-enabled state
+        with the timed state's pair capacity (eager iterations)."""
+        cap = int(self.states[0].stats().pair_capacity)
+        tst = self.R.State(sync_capacity=False, timing=True, count_work=False)
+        tst.reserve(tile_pairs=cap)
+        acc = {}
+        for r in range(reps + 1):
+            self.flat.zero_()
+            self.dposes.zero_()
+            self._views(tst, list(range(self.V)))
+            t = tst.timings()
+            if r:
+                for k, v in t.items():
+                    acc[k] = acc.get(k, 0.0) + v / reps
+        tst.check()
+        tst.close()
+        return acc
+
     def freeze_capacity(self, margin=1.25):
         """After a sizing call: fixed pair capacity, no per-call readback."""
         for k, st in enumerate(self.states):
@@ -360,6 +412,8 @@ def run_mapping(args, torch, R, synth, views: int):
         it.check()
         res[name] = dict(ms_per_iter=wall * 1e3 / args.steps, event_ms_per_iter=ev / args.steps, stats=it.stats())
         log(f"{name}: {res[name]['ms_per_iter']:.3f} ms/iteration ({views} view(s))")
+        if batched:
+            res[name]["stages"] = it.stage_times()
         del it
     st = res["batched"]["stats"]
     # the timed states keep no work counts: one counting render of the same
@@ -371,6 +425,14 @@ def run_mapping(args, torch, R, synth, views: int):
     del cst
     b = mapping_bytes(n, st["visible"], st["pairs"], views * cam["width"] * cam["height"], deg)
     ms = res["batched"]["ms_per_iter"]
+    stages = res["batched"]["stages"]
+    # the dominant kernel: the blend backward to every parameter
+    bwd_flops = FLOP_EVAL * st["walked"] + FLOP_BLEND_BWD_MAP * st["blended"]
+    roof = alu_roofline("blend_bwd_map", "raster_backward_kernel<1, true, false, false>", bwd_flops,
+                        stages["blend_bwd"], "library HIP events around the stage, 5 eager iterations",
+                        measured_counters("raster_backward_kernel<1, true, false, false>"))
+    fwd_flops = FLOP_EVAL * st["evaluations"] + FLOP_BLEND_MAP * st["blended"]
+    fwd_tflops = fwd_flops / (stages["blend_fwd"] * 1e-3) / 1e12
     out = {
         "metric": ("mapping iters/s (fwd+full bwd) 1200x680 500k Gaussians" if views == 1 else
                    "batched mapping views/s (fwd+full bwd) 8x1200x680 1M Gaussians")
@@ -382,8 +444,14 @@ def run_mapping(args, torch, R, synth, views: int):
         "config": {"workload": (f"mapping: {n} Gaussians on an 8x6x3 m room, {views} view(s) 1200x680 f=600, "
                                 "render with sensor depth + uncertainty-weighted L1 + backward to all "
                                 "parameters and poses"), "gaussians": n, "views": views, "sh_degree": deg},
+        "roofline": roof,
+        "blend_fwd_roofline": {"achieved": round(fwd_tflops, 4), "unit": "TFLOP/s",
+                               "frac": round(fwd_tflops / FP32_VECTOR_PEAK_TFLOPS, 5),
+                               "frac_reachable": round(fwd_tflops / FP32_REACHABLE_TFLOPS, 5),
+                               "avg_ms": round(stages["blend_fwd"], 5), "algorithmic_flops": int(fwd_flops)},
         "hbm_roofline": {"algorithmic_bytes_per_iter": b, "achieved_GBs": round(b / (ms * 1e-3) / 1e9, 2),
                          "peak_GBs": HBM_PEAK_GBS, "frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)},
+        "stages_ms": {k: round(v, 5) for k, v in stages.items()},
         "stats": st,
     }
     if views > 1:
@@ -634,12 +702,32 @@ def run_batched_tracking(args, torch, R, synth, frames=32, iters=20):
         fi = frames * iters * reps
         fin = torch.cat([p for _, _, p, _ in made]).cpu()
         res[name] = dict(wall=wall, fi=fi, value=fi / wall, poses=fin)
+        if name == "batched":
+            # the dominant kernel: the fused tracking blend over all frames,
+            # re-run back to back after the last replayed step
+            res[name]["blend_ms"] = B.cgsr_time_tracking_blend(made[0][1].handle, 50, R._stream())
         terr = [float((fin[k, 9:].double() - Pt[k, 9:].cpu().double()).abs().max()) for k in range(frames)]
         log(f"{name}: {fi / wall:.1f} frame-iterations/s; final |t - t_true|_inf max {max(terr):.3e} "
             f"median {sorted(terr)[frames // 2]:.3e}")
         del made
     d = float((res["batched"]["poses"] - res["sequential"]["poses"]).abs().max())
     log(f"batched vs sequential final poses max diff {d:.2e}")
+    # work counts of one batched step at the start poses (the timed states
+    # keep none; they depend only on the workload)
+    cst = R.State(sync_capacity=True, count_work=True)
+    cpose = P0.clone()
+    cd = torch.zeros((frames, 6), device="cuda")
+    B.cgsr_tracking_step(cst.handle, g, frames, cpose.data_ptr(), cam_s, [t.data_ptr() for t in tcs],
+                         [t.data_ptr() for t in tds], float(lam[0]), float(lam[1]), cd.data_ptr(), None, None, None,
+                         R._stream())
+    cs = cst.stats()
+    stats = dict(visible=int(cs.visible), pairs=int(cs.pairs), evaluations=int(cs.processed),
+                 blended=int(cs.blended), walked=int(cs.walked))
+    del cst
+    flops = (FLOP_EVAL * stats["evaluations"] + FLOP_BLEND * stats["blended"] + FLOP_EVAL * stats["walked"]
+             + FLOP_BLEND_BWD * stats["blended"])
+    roof = alu_roofline("blend_track", "raster_track_kernel<1, false, false>", flops, res["batched"]["blend_ms"],
+                        "50 back-to-back launches between two HIP events")
     ms = res["batched"]["wall"] * 1e3 / (res["batched"]["fi"] / frames)
     out = {
         "metric": "batched tracking frame-iters/s (fwd+pose-bwd) 32 mixed-resolution frames 1M Gaussians",
@@ -654,6 +742,8 @@ def run_batched_tracking(args, torch, R, synth, frames=32, iters=20):
         "sequential": {"value": round(res["sequential"]["value"], 2),
                        "speedup_batched": round(res["batched"]["value"] / res["sequential"]["value"], 3),
                        "final_pose_max_diff": d},
+        "roofline": roof,
+        "stats": stats,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, one frame per resolution)")
@@ -678,12 +768,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="tracking",
                     choices=("tracking", "mapping", "batched-mapping", "batched-tracking", "management"))
-    ap.add_argument("--steps", type=int, default=2000, help="timed tracking iterations")
-    ap.add_argument("--warmup", type=int, default=200, help="untimed tracking iterations")
+    ap.add_argument("--steps", type=int, default=2000, help="timed tracking iterations (exactly)")
+    ap.add_argument("--warmup", type=int, default=200, help="untimed tracking iterations (exactly)")
     ap.add_argument("--solve-iters", type=int, default=50, help="iterations per captured solve")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stage-timing", action="store_true")
+    ap.add_argument("--replays", type=int, default=100, help="solve replays timed one by one for the spread")
+    ap.add_argument("--blend-reps", type=int, default=200,
+                    help="back-to-back re-runs of the fused blend that time the dominant kernel")
+    ap.add_argument("--tracking-only", action="store_true",
+                    help="only the headline tracking line (no mapping / batched workloads beside it)")
     ap.add_argument("--ppl", type=int, default=0, choices=(0, 1, 2, 4),
                     help="pixels per lane of the tracking blend (0: autotune)")
     ap.add_argument("--eager", action="store_true",
@@ -732,52 +827,90 @@ def main():
         fppl = bppl = args.ppl
         log(f"pixels per lane: {fppl} (fixed)")
     else:
-        tune_state = R.State()
-        fppl, bppl = R.autotune_tracking(tune_state, prob.scene, P0, [prob.cam], [prob.target_color],
-                                         [prob.target_depth])
-        del tune_state
-        log(f"autotuned pixels per lane: forward {fppl}, backward {bppl}")
-    solver = R.TrackingSolver(prob, iters=iters, use_graph=not args.eager, reset_pose=P0, fwd_ppl=fppl,
-                              bwd_ppl=bppl)
-    solver.prepare(P0)
-    solves_w = max(1, math.ceil(args.warmup / iters))
-    solves = max(1, math.ceil(args.steps / iters))
-    steps, warmup = solves * iters, solves_w * iters
+        probe = R.TrackingSolver(prob, iters=1, use_graph=False, reset_pose=P0)
+        fppl, bppl = probe.autotune(P0)
+        del probe
+        log(f"autotuned pixels per lane (whole steps timed on the solve's state configuration): {fppl}")
+
+    def make_solver(k):
+        s_ = R.TrackingSolver(prob, iters=k, use_graph=not args.eager, reset_pose=P0, fwd_ppl=fppl, bwd_ppl=bppl)
+        s_.prepare(P0)
+        return s_
+
+    solver = make_solver(iters)
+    partial = {}
+
+    def run_iterations(k):
+        """Exactly k tracking iterations: whole solves of `iters` from the
+        start pose, then one solve of the remainder (its own graph)."""
+        full, rem = divmod(k, iters)
+        for _ in range(full):
+            solver.run()
+        if rem:
+            if rem not in partial:
+                partial[rem] = make_solver(rem)
+            partial[rem].run()
+
+    steps, warmup = args.steps, args.warmup
+    if warmup % iters and (warmup % iters) not in partial:
+        partial[warmup % iters] = make_solver(warmup % iters)
+    if steps % iters and (steps % iters) not in partial:
+        partial[steps % iters] = make_solver(steps % iters)
     log(f"warmup {warmup} iterations")
-    for _ in range(solves_w):
-        solver.run()
+    run_iterations(warmup)
     torch.cuda.synchronize()
     solver.check()
 
-    log(f"timed {steps} iterations ({solves} graph replays of {iters})")
+    log(f"timed {steps} iterations ({steps // iters} solves of {iters}"
+        + (f" + one of {steps % iters})" if steps % iters else ")"))
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
-    for _ in range(solves):
-        solver.run()
+    run_iterations(steps)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gpu_ms = e0.elapsed_time(e1)
     solver.check()
+    for p_ in partial.values():
+        p_.check()
     ms_per_step = wall * 1e3 / steps
     value = steps / wall
-    err_t = float((solver.pose.cpu().double()[9:] - torch.as_tensor(true_pose[1])).abs().max())
-    log(f"{value:.1f} it/s ({ms_per_step * 1e3:.1f} us/it wall, {gpu_ms * 1e3 / steps:.1f} us/it events); "
-        f"final |t - t_true|_inf = {err_t:.2e} m")
+    log(f"{value:.1f} it/s ({ms_per_step * 1e3:.1f} us/it wall, {gpu_ms * 1e3 / steps:.1f} us/it events)")
 
-    # Per-stage kernel durations, HIP events recorded by the library on the
-    # launch stream, over eager iterations of the same workload.
-    stages, stats = {}, None
+    # Spread: every replay of a whole solve timed on its own by HIP events.
+    nrep = args.replays
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nrep)]
+    torch.cuda.synchronize()
+    for a, b in evs:
+        a.record(stream)
+        solver.run()
+        b.record(stream)
+    torch.cuda.synchronize()
+    solver.check()
+    per_it = sorted(a.elapsed_time(b) * 1e3 / iters for a, b in evs)
+    q = lambda f: round(per_it[min(nrep - 1, int(f * nrep))], 3)
+    spread = {"replays": nrep, "iters_per_replay": iters, "unit": "us/it", "p10": q(0.1), "p50": q(0.5),
+              "p90": q(0.9), "min": round(per_it[0], 3), "max": round(per_it[-1], 3)}
+    log(f"per-iteration time over {nrep} solve replays: p10 {spread['p10']} p50 {spread['p50']} "
+        f"p90 {spread['p90']} us")
+    err_t = float((solver.pose.cpu().double()[9:] - torch.as_tensor(true_pose[1])).abs().max())
+    log(f"final |t - t_true|_inf = {err_t:.2e} m")
+
+    # The dominant kernel: the fused tracking blend of the solve's last step,
+    # re-run back to back between two HIP events on the launch stream.
+    blend_ms = solver.state.time_tracking_blend(args.blend_reps)
+    log(f"fused tracking blend: {blend_ms * 1e3:.2f} us per launch ({args.blend_reps} back-to-back re-runs)")
+
+    # The other stages: HIP events recorded by the library around each stage,
+    # over eager steps of the same workload (each event pair adds a few us).
+    stages = {}
     if not args.no_stage_timing:
-        # no capacity readback: it would put a host round trip inside the
-        # projection stage's events
         tst = R.State(sync_capacity=False, timing=True, fwd_ppl=fppl, bwd_ppl=bppl, count_work=False)
-        tst.reserve(tile_pairs=solver.state.stats().peak_pairs * 2)
+        tst.reserve(tile_pairs=int(solver.state.stats().pair_capacity))
         pose = P0.clone().reshape(1, 12)
-        acc = {}
         reps = 20
         dpose = torch.zeros((1, 6), device="cuda")
         for r in range(reps + 2):
@@ -786,18 +919,19 @@ def main():
             t = tst.timings()
             if r >= 2:
                 for k, v in t.items():
-                    acc[k] = acc.get(k, 0.0) + v / reps
-        stages = acc
-        # The timed kernel keeps no work counts (as in the solve); the same
-        # step on a counting state gives them (they depend only on the
-        # workload).
-        cst = R.State(fwd_ppl=fppl, bwd_ppl=bppl, count_work=True)
-        R.tracking_step(cst, prob.scene, pose, [prob.cam], [prob.target_color], [prob.target_depth],
-                        dposes=dpose)
-        s = cst.stats()
-        stats = dict(visible=int(s.visible), pairs=int(s.pairs), evaluations=int(s.processed),
-                     blended=int(s.blended), walked=int(s.walked))
-        log("stage ms:", {k: round(v, 4) for k, v in stages.items()}, "stats:", stats)
+                    stages[k] = stages.get(k, 0.0) + v / reps
+        tst.check()
+        log("stage ms (events):", {k: round(v, 4) for k, v in stages.items()})
+    # Work counts: the timed kernel keeps none (as in the solve); the same
+    # step on a counting state gives them (they depend only on the workload).
+    cst = R.State(fwd_ppl=fppl, bwd_ppl=bppl, count_work=True)
+    dpose = torch.zeros((1, 6), device="cuda")
+    R.tracking_step(cst, prob.scene, P0.clone().reshape(1, 12), [prob.cam], [prob.target_color],
+                    [prob.target_depth], dposes=dpose)
+    s = cst.stats()
+    stats = dict(visible=int(s.visible), pairs=int(s.pairs), evaluations=int(s.processed),
+                 blended=int(s.blended), walked=int(s.walked))
+    log("stats:", stats)
 
     result = {
         "metric": METRIC + (f", SH degree {deg}" if deg else ""),
@@ -816,37 +950,32 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "tracking: 100k Gaussians on a 5x4x3 m room, 640x480 f=525, "
-                               "render + L1 colour/depth loss + pose-only backward + Adam, 50-iteration "
-                               "solves replayed from one HIP graph",
+                               f"render + L1 colour/depth loss + pose-only backward + Adam, {iters}-iteration "
+                               "solves replayed from HIP graphs",
                    "gaussians": 100_000, "width": 640, "height": 480, "solve_iters": iters,
                    "pixels_per_lane": fppl, "sh_degree": deg,
                    "loss_lambda": list(R.TRACK_LAMBDA)},
+        "spread": spread,
     }
+    # The dominant kernel's ALU roofline: the tracking step's blend forward
+    # and pose-only blend backward run as one launch per tile.
+    flops = (FLOP_EVAL * stats["evaluations"] + FLOP_BLEND * stats["blended"]
+             + FLOP_EVAL * stats["walked"] + FLOP_BLEND_BWD * stats["blended"])
+    symbol = f"raster_track_kernel<{fppl}, {'true' if deg else 'false'}, false>"
+    result["roofline"] = alu_roofline("blend_track", symbol, flops, blend_ms,
+                                      f"{args.blend_reps} back-to-back launches between two HIP events",
+                                      measured_counters(symbol))
+    b = algorithmic_bytes(100_000, stats["visible"], stats["pairs"], 640 * 480, deg)
+    copy_gbs = copy_bandwidth(torch)
+    result["hbm_roofline"] = {"algorithmic_bytes_per_iter": b,
+                              "achieved_GBs": round(b / (ms_per_step * 1e-3) / 1e9, 2),
+                              "peak_GBs": HBM_PEAK_GBS,
+                              "frac": round(b / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+                              "copy_GBs": round(copy_gbs, 1),
+                              "frac_of_copy": round(b / (ms_per_step * 1e-3) / 1e9 / copy_gbs, 5)}
     if stages:
-        # The dominant single kernel and its roofline: the tracking step's
-        # blend forward and pose-only blend backward run as one launch per
-        # tile, timed as the forward blend stage.
-        flops_fwd = FLOP_EVAL * stats["evaluations"] + FLOP_BLEND * stats["blended"]
-        flops_bwd = FLOP_EVAL * stats["walked"] + FLOP_BLEND_BWD * stats["blended"]
-        name = "blend_track"
-        ms, fl = stages["blend_fwd"], flops_fwd + flops_bwd
-        achieved = fl / (ms * 1e-3) / 1e12
-        symbol = f"raster_track_kernel<{fppl}, {'true' if deg else 'false'}, false>"
-        result["roofline"] = {"bound": "alu", "kernel": name, "symbol": symbol, "achieved": round(achieved, 4),
-                              "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                              "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 5),
-                              "traffic": measured_traffic(symbol),
-                              "avg_ms": round(ms, 5), "algorithmic_flops": fl}
-        b = algorithmic_bytes(100_000, stats["visible"], stats["pairs"], 640 * 480, deg)
-        copy_gbs = copy_bandwidth(torch)
-        result["hbm_roofline"] = {"algorithmic_bytes_per_iter": b,
-                                  "achieved_GBs": round(b / (ms_per_step * 1e-3) / 1e9, 2),
-                                  "peak_GBs": HBM_PEAK_GBS,
-                                  "frac": round(b / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
-                                  "copy_GBs": round(copy_gbs, 1),
-                                  "frac_of_copy": round(b / (ms_per_step * 1e-3) / 1e9 / copy_gbs, 5)}
-        result["stages_ms"] = {k: round(v, 5) for k, v in stages.items()}
-        result["stats"] = stats
+        result["stage_events_ms"] = {k: round(v, 5) for k, v in stages.items()}
+    result["stats"] = stats
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         tc = prob.target_color.cpu().numpy()
@@ -854,7 +983,33 @@ def main():
         p0 = P0.cpu().double().numpy()
         result["cpu_baseline"] = cpu_baseline((sc, tc, td), prob.cam, (p0[:9].reshape(3, 3), p0[9:]),
                                               args.cpu_budget)
+    del solver, partial
+    if not args.tracking_only and deg == 0:
+        result["workloads"] = other_workloads(args, torch, R, synth)
     print(json.dumps(result), flush=True)
+
+
+def other_workloads(args, torch, R, synth):
+    """The mapping, batched-mapping and batched-tracking workloads, each with
+    its own steps, ALU roofline and (extrapolated) oracle baseline, reported
+    beside the headline so every run records the batched-versus-unbatched
+    ratios."""
+    out = {}
+    for name, fn, steps, warmup in (
+            ("mapping", lambda a: run_mapping(a, torch, R, synth, 1), 50, 5),
+            ("batched_mapping", lambda a: run_mapping(a, torch, R, synth, 8), 20, 3),
+            ("batched_tracking", lambda a: run_batched_tracking(a, torch, R, synth), 20, 20)):
+        sub = argparse.Namespace(**vars(args))
+        sub.steps, sub.warmup, sub.sh_degree = steps, warmup, 0
+        t0 = time.perf_counter()
+        log(f"--- {name}")
+        r = fn(sub)
+        for k in ("n_gpus", "higher_is_better", "scaling", "dtype", "data"):
+            r.pop(k, None)
+        r["bench_seconds"] = round(time.perf_counter() - t0, 1)
+        out[name] = r
+        torch.cuda.empty_cache()
+    return out
 
 
 if __name__ == "__main__":

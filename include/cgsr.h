@@ -398,11 +398,15 @@ cgsr_status cgsr_tracking_step(cgsr_state *st, const cgsr_gaussians *g, int32_t 
                                float *loss, void *stream);
 
 /*
- * Autotuner: picks the blend kernels' pixels per lane (1, 2 or 4, forward and
- * backward independently) for a tracking workload by timing
- * cgsr_tracking_step on it with each candidate (HIP events on the stream,
- * `repeats` timed runs after one warm-up, no Adam step, poses unchanged),
- * stores the fastest in the state's settings and returns them in *out (may
+ * Autotuner: picks the blend kernels' pixels per lane (1, 2 or 4; one value
+ * for forward and backward, which the tracking step runs as one launch) for
+ * a tracking workload on this state, as configured (work counts, bucket
+ * capacity), by timing whole cgsr_tracking_step calls with each candidate:
+ * one step with the state's settings (it may grow the buckets), then
+ * `repeats` steps without the capacity read-back between two HIP events on
+ * the stream (no Adam step, poses unchanged).  A candidate whose buckets
+ * exceed one key per lane is timed with the segmented sort it then needs.
+ * Stores the fastest in the state's settings and returns them in *out (may
  * be NULL).  Synchronises; not for use under graph capture.
  */
 cgsr_status cgsr_autotune_tracking(cgsr_state *st, const cgsr_gaussians *g, int32_t n_views, const float *poses,
@@ -527,6 +531,21 @@ cgsr_status cgsr_get_stats(cgsr_state *st, void *stream, cgsr_stats *out);
  * Synchronises on the recorded events.  CGSR_ERR_STATE if timing is off or a
  * stage has not run since timing was enabled. */
 cgsr_status cgsr_get_timings(cgsr_state *st, float *ms_out);
+
+/*
+ * Measurement: re-runs the fused blend kernel of the last cgsr_tracking_step
+ * on st (the one with dposes or adam) reps times back to back between two
+ * HIP events on stream, and writes the average duration of one launch in
+ * milliseconds to *ms_out.  Every re-run is the same kernel instantiation and
+ * launch shape on the same tile buckets, pixels and targets as that step;
+ * the step's loss sum (if any) is not added to again.  The state is left as
+ * the step left it (pair counters reset, record gradient sums cleared), so
+ * it may be called repeatedly and the next call on st proceeds as usual.
+ *   reps   1 .. 100000.
+ * CGSR_ERR_STATE if another call changed the state since that step, or under
+ * graph capture.  Synchronises the stream.
+ */
+cgsr_status cgsr_time_tracking_blend(cgsr_state *st, int32_t reps, void *stream, float *ms_out);
 
 /* Debug views of the last render (device buffers owned by the state; valid
  * until the next render on it).  keys: [tiles][pair_capacity] each tile's

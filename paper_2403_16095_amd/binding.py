@@ -32,7 +32,7 @@ EXPORTED = (
     "cgsr_tracking_step",
     "cgsr_autotune_tracking", "cgsr_spawn_gaussians", "cgsr_compact_gaussians", "cgsr_compact_gaussians_noalloc",
     "cgsr_set_densify_stats",
-    "cgsr_densify_gaussians", "cgsr_state_check", "cgsr_get_stats", "cgsr_get_timings", "cgsr_debug_buffers",
+    "cgsr_densify_gaussians", "cgsr_state_check", "cgsr_get_stats", "cgsr_get_timings", "cgsr_time_tracking_blend", "cgsr_debug_buffers",
     "cgsr_last_error",
     "cgsr_version",
 )
@@ -155,6 +155,7 @@ def lib() -> C.CDLL:
     L.cgsr_state_check.argtypes = [vp, vp]
     L.cgsr_get_stats.argtypes = [vp, vp, C.POINTER(cgsr_stats)]
     L.cgsr_get_timings.argtypes = [vp, C.POINTER(C.c_float)]
+    L.cgsr_time_tracking_blend.argtypes = [vp, C.c_int32, vp, C.POINTER(C.c_float)]
     L.cgsr_debug_buffers.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
                                      C.POINTER(vp)]
     L.cgsr_last_error.argtypes = []
@@ -339,6 +340,13 @@ def cgsr_get_timings(state: int) -> dict:
     out = (C.c_float * len(STAGES))()
     _check(lib().cgsr_get_timings(state, out))
     return dict(zip(STAGES, [float(v) for v in out]))
+
+
+def cgsr_time_tracking_blend(state: int, reps: int, stream: int) -> float:
+    """Average ms of one re-run of the last tracking step's fused blend kernel."""
+    out = C.c_float(0.0)
+    _check(lib().cgsr_time_tracking_blend(state, reps, stream, C.byref(out)))
+    return out.value
 
 
 def cgsr_debug_buffers(state: int):

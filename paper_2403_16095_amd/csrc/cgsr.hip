@@ -118,6 +118,11 @@ struct cgsr_state {
   int32_t total_tiles = 0;
   int64_t records = 0;
   ViewIO io_fwd[CGSR_MAX_VIEWS];
+  // the fused blend launch of the last tracking step, for timing re-runs;
+  // valid while no other call has changed the state's buffers or tables
+  RasterBufs track_rb{};
+  int track_ppl = 1;
+  bool track_rb_ok = false;
 };
 
 namespace {
@@ -132,6 +137,7 @@ cgsr_status set_device(cgsr_state* st) {
 // Buckets for cap_tiles tiles of at least tile_pairs pairs each.  Sizes are
 // kept in 32 bits on the device (tile ranges), so tiles x pairs < 2^32.
 cgsr_status grow_buckets(cgsr_state* st, int64_t tile_pairs) {
+  st->track_rb_ok = false;
   const int64_t cap = std::max<int64_t>(std::max<int64_t>(tile_pairs, st->cap_tile_pairs), 64);
   if (cap == st->cap_tile_pairs && st->bucket_tiles >= st->cap_tiles) return CGSR_OK;
   const int64_t tiles = std::max<int64_t>(st->cap_tiles, 1);
@@ -154,6 +160,7 @@ cgsr_status grow_buckets(cgsr_state* st, int64_t tile_pairs) {
 }
 
 cgsr_status reserve(cgsr_state* st, int64_t records, int64_t pixels, int64_t tiles, int64_t tile_pairs) {
+  st->track_rb_ok = false;
   if (records > st->cap_records || pixels > st->cap_pixels || tiles > st->cap_tiles)
     HIP_TRY(hipDeviceSynchronize());
   cgsr_status s;
@@ -261,6 +268,7 @@ RasterBufs raster_bufs(cgsr_state* st, int slot) {
   rb.tile_count = st->tile_count;
   rb.counters = st->counters;
   rb.tile_cap = (uint32_t)st->cap_tile_pairs;
+  rb.keep_counts = false;
   rb.views = ViewTable{st->io[slot].dev, st->n_views, (int32_t)st->g.n};
   rb.total_tiles = st->total_tiles;
   return rb;
@@ -454,6 +462,7 @@ cgsr_status render_impl(cgsr_state* st, const RenderArgs& a, hipStream_t stream)
   s = reserve(st, records, a.pixels, a.tiles, 0);
   if (s) return s;
   st->have_forward = false;
+  st->track_rb_ok = false;
   st->tracked = false;
   st->n_views = a.n_views;
   st->g = GaussianPtrs{a.g->means, a.g->log_scales, a.g->quats, a.g->opacity_logits, a.g->rgb, a.g->n,
@@ -531,8 +540,13 @@ cgsr_status render_impl(cgsr_state* st, const RenderArgs& a, hipStream_t stream)
   rb.nu_sum = a.nu_sum;
   rb.nu_count = a.nu_count;
   rb.sort_here = sort_here;
-  if (a.track && a.fused) launch_raster_track(rb, st->settings.fwd_pixels_per_lane, stream);
-  else launch_raster_forward(rb, a.track, st->settings.fwd_pixels_per_lane, stream);
+  if (a.track && a.fused) {
+    launch_raster_track(rb, st->settings.fwd_pixels_per_lane, stream);
+    st->track_rb = rb;
+    st->track_ppl = st->settings.fwd_pixels_per_lane;
+  } else {
+    launch_raster_forward(rb, a.track, st->settings.fwd_pixels_per_lane, stream);
+  }
   HIP_TRY(hipGetLastError());
   st->tiles_dirty = false;
   if ((s = mark(CGSR_STAGE_BLEND_FWD + 1))) return s;
@@ -551,6 +565,7 @@ cgsr_status backward_impl(cgsr_state* st, int slot, bool params, bool track, con
   HIP_TRY(hipStreamIsCapturing(stream, &capturing));
   const bool timed = st->settings.timing && capturing == hipStreamCaptureStatusNone;
   st->bwd_timed = false;
+  st->track_rb_ok = false;
   if (timed) HIP_TRY(hipEventRecord(st->ev_bwd[0], stream));
   const RasterBufs rb = raster_bufs(st, slot);
   if (!blend_done) launch_raster_backward(rb, params, track, st->settings.bwd_pixels_per_lane, stream);
@@ -698,7 +713,50 @@ cgsr_status cgsr_tracking_step(cgsr_state* st, const cgsr_gaussians* g, int32_t 
   if (adam)
     step.params = AdamParams{adam_params->lr_rho, adam_params->lr_phi, adam_params->beta1, adam_params->beta2,
                              adam_params->eps};
-  return backward_impl(st, 0, false, true, GradPtrs{}, dposes, adam ? &step : nullptr, stream, true);
+  s = backward_impl(st, 0, false, true, GradPtrs{}, dposes, adam ? &step : nullptr, stream, true);
+  if (!s) st->track_rb_ok = true;
+  return s;
+}
+
+cgsr_status cgsr_time_tracking_blend(cgsr_state* st, int32_t reps, void* stream_, float* ms_out) {
+  hipStream_t stream = (hipStream_t)stream_;
+  if (!st || !ms_out) return fail(CGSR_ERR_INVALID_ARG, "cgsr_time_tracking_blend: NULL argument");
+  if (reps < 1 || reps > 100000) return fail(CGSR_ERR_INVALID_ARG, "cgsr_time_tracking_blend: reps must be 1 .. 100000");
+  if (!st->track_rb_ok)
+    return fail(CGSR_ERR_STATE, "cgsr_time_tracking_blend: the last call on this state was not a tracking step "
+                                "with a pose gradient or update");
+  cgsr_status s = set_device(st);
+  if (s) return s;
+  hipStreamCaptureStatus capturing = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(stream, &capturing));
+  if (capturing != hipStreamCaptureStatusNone)
+    return fail(CGSR_ERR_STATE, "cgsr_time_tracking_blend: not available under graph capture");
+  RasterBufs rb = st->track_rb;
+  rb.loss = nullptr;        // the step's loss sum is not added to again
+  rb.keep_counts = true;
+  if (rb.sort_here) launch_restore_counts(st->tile_count, st->ranges, st->total_tiles, stream);
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  HIP_TRY(hipEventCreate(&ev[0]));
+  hipError_t e = hipEventCreate(&ev[1]);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventRecord(ev[0], stream);
+  for (int r = 0; e == hipSuccess && r < reps; ++r) {
+    launch_raster_track(rb, st->track_ppl, stream);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipEventRecord(ev[1], stream);
+  // leave the state as the step left it: counters reset, record sums cleared
+  if (rb.sort_here) launch_clear_u32(st->tile_count, (int64_t)st->total_tiles * kTileCounterStride, stream);
+  launch_clear_u32(reinterpret_cast<uint32_t*>(st->rec_grad), st->records * kGradStride, stream);
+  if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  (void)hipEventDestroy(ev[0]);
+  if (ev[1]) (void)hipEventDestroy(ev[1]);
+  if (e != hipSuccess) return fail(CGSR_ERR_HIP, "cgsr_time_tracking_blend: %s", hipGetErrorString(e));
+  *ms_out = ms / (float)reps;
+  st->track_rb_ok = true;
+  return CGSR_OK;
 }
 
 cgsr_status cgsr_autotune_tracking(cgsr_state* st, const cgsr_gaussians* g, int32_t n_views, const float* poses,
@@ -712,39 +770,55 @@ cgsr_status cgsr_autotune_tracking(cgsr_state* st, const cgsr_gaussians* g, int3
   HIP_TRY(hipStreamIsCapturing(stream, &capturing));
   if (capturing != hipStreamCaptureStatusNone)
     return fail(CGSR_ERR_STATE, "cgsr_autotune_tracking: not under graph capture");
+  cgsr_status s = set_device(st);
+  if (s) return s;
   const cgsr_settings saved = st->settings;
-  st->settings.timing = 1;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  HIP_TRY(hipEventCreate(&ev[0]));
+  if (hipEventCreate(&ev[1]) != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    return fail(CGSR_ERR_HIP, "cgsr_autotune_tracking: hipEventCreate failed");
+  }
   const int32_t cand[3] = {1, 2, 4};
-  float best_f = 1e30f, best_b = 1e30f;
-  int32_t pick_f = saved.fwd_pixels_per_lane, pick_b = saved.bwd_pixels_per_lane;
-  cgsr_status s = CGSR_OK;
+  float best = 1e30f;
+  int32_t pick = saved.fwd_pixels_per_lane;
   for (int c = 0; c < 3 && !s; ++c) {
+    // The whole step (projection, sort unless the blend sorts its own
+    // buckets, fused blend, projection backward) between two events: a
+    // candidate whose buckets no longer fit one key per lane pays for the
+    // segmented sort it needs.  One step with the caller's settings first
+    // (it may grow the buckets), then the timed steps without the capacity
+    // read-back.
+    st->settings = saved;
+    st->settings.timing = 0;
     st->settings.fwd_pixels_per_lane = cand[c];
     st->settings.bwd_pixels_per_lane = cand[c];
-    float sum_f = 0.f, sum_b = 0.f;
-    for (int r = 0; r <= repeats && !s; ++r) {
+    s = cgsr_tracking_step(st, g, n_views, const_cast<float*>(poses), cams, target_color, target_depth, 1.f, 1.f,
+                           st->tune_dposes, nullptr, nullptr, nullptr, stream);
+    st->settings.sync_capacity = 0;
+    hipError_t e = hipSuccess;
+    if (!s) e = hipEventRecord(ev[0], stream);
+    for (int r = 0; r < repeats && !s && e == hipSuccess; ++r)
       s = cgsr_tracking_step(st, g, n_views, const_cast<float*>(poses), cams, target_color, target_depth, 1.f, 1.f,
                              st->tune_dposes, nullptr, nullptr, nullptr, stream);
-      float ms[CGSR_NUM_STAGES];
-      if (!s) s = cgsr_get_timings(st, ms);
-      if (!s && r > 0) {
-        sum_f += ms[CGSR_STAGE_BLEND_FWD];
-        sum_b += ms[CGSR_STAGE_BLEND_BWD];
-      }
-    }
-    // the tracking step's blend is one fused launch (timed as the forward
-    // stage), so one setting serves both
-    if (!s && sum_f + sum_b < best_f) {
-      best_f = sum_f + sum_b;
-      pick_f = cand[c];
+    float ms = 0.f;
+    if (!s && e == hipSuccess) e = hipEventRecord(ev[1], stream);
+    if (!s && e == hipSuccess) e = hipEventSynchronize(ev[1]);
+    if (!s && e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+    if (!s && e != hipSuccess) s = fail(CGSR_ERR_HIP, "cgsr_autotune_tracking: %s", hipGetErrorString(e));
+    if (!s && ms < best) {
+      best = ms;
+      pick = cand[c];
     }
   }
-  (void)best_b;
-  (void)pick_b;
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
   st->settings = saved;
   if (s) return s;
-  st->settings.fwd_pixels_per_lane = pick_f;
-  st->settings.bwd_pixels_per_lane = pick_f;
+  // the tracking step's forward and pose backward are one fused launch, so
+  // one setting serves both
+  st->settings.fwd_pixels_per_lane = pick;
+  st->settings.bwd_pixels_per_lane = pick;
   if (out) *out = st->settings;
   return CGSR_OK;
 }

@@ -606,7 +606,7 @@ __device__ __forceinline__ uint2 sort_own_bucket(const RasterBufs& b, int gtile,
   const uint64_t key = threadIdx.x < b.tile_cap ? b.bucket_keys[base + threadIdx.x] : 0ull;
   if (threadIdx.x == 0) {
     const uint32_t n = min(*counter, b.tile_cap);   // beyond the bucket only after an overflow, which is reported
-    *counter = 0u;
+    if (!b.keep_counts) *counter = 0u;
     *s_n = n;
     b.ranges[gtile] = make_uint2((uint32_t)base, (uint32_t)(base + n));
     if (gtile == 0) b.counters[kCntRenderPeak] = 0u;

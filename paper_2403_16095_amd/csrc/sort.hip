@@ -127,12 +127,27 @@ __global__ __launch_bounds__(kThreads) void clear_kernel(uint32_t* p, int64_t n)
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) p[i] = 0u;
 }
 
+__global__ __launch_bounds__(kThreads) void restore_counts_kernel(uint32_t* tile_count, const uint2* ranges,
+                                                                  int32_t tiles) {
+  const int t = blockIdx.x * kThreads + threadIdx.x;
+  if (t < tiles) {
+    const uint2 r = ranges[t];
+    tile_count[(size_t)t * kTileCounterStride] = r.y - r.x;
+  }
+}
+
 }  // namespace
 
 void launch_clear_u32(uint32_t* p, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   const int64_t blocks = std::min<int64_t>(1024, (n + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(clear_kernel, dim3((unsigned)blocks), dim3(kThreads), 0, s, p, n);
+}
+
+void launch_restore_counts(uint32_t* tile_count, const uint2* ranges, int32_t tiles, hipStream_t s) {
+  if (tiles <= 0) return;
+  hipLaunchKernelGGL(restore_counts_kernel, dim3((unsigned)((tiles + kThreads - 1) / kThreads)), dim3(kThreads), 0,
+                     s, tile_count, ranges, tiles);
 }
 
 void launch_segment_sort(const SegSortBufs& b, int32_t total_tiles, hipStream_t s) {

@@ -107,6 +107,11 @@ class State:
     def check(self):
         B.cgsr_state_check(self.handle, _stream())
 
+    def time_tracking_blend(self, reps: int = 200) -> float:
+        """Average ms of one launch of the last tracking step's fused blend
+        kernel, over ``reps`` back-to-back re-runs between two HIP events."""
+        return B.cgsr_time_tracking_blend(self.handle, int(reps), _stream())
+
     def timings(self) -> dict:
         return B.cgsr_get_timings(self.handle)
 
@@ -676,6 +681,20 @@ class TrackingSolver:
                                   self.dcolor.data_ptr(), self.ddepth.data_ptr(), None, s)
         B.cgsr_backward(self.state.handle, [self.grad_s], None, self.dpose.data_ptr(), s)
         B.cgsr_pose_adam_step(1, self.pose.data_ptr(), self.dpose.data_ptr(), self.adam.data_ptr(), self.params, s)
+
+    def autotune(self, pose0: torch.Tensor, repeats: int = 10):
+        """Pixels per lane for this solve, timed on the solver's own state
+        (no work counts, buckets reserved as prepare() reserves them) by the
+        library's autotuner; the solver keeps the pick.  Call before prepare().
+        Returns (fwd_pixels_per_lane, bwd_pixels_per_lane)."""
+        p = self.prob
+        self.reset(pose0)
+        self._iteration()                       # eager, grows the tile buckets
+        torch.cuda.synchronize()
+        self.state.reserve(tile_pairs=int(self.state.stats().peak_pairs * self.pair_margin) + 64)
+        self.reset(pose0)
+        return autotune_tracking(self.state, p.scene, self.pose, [p.cam], [p.target_color], [p.target_depth],
+                                 repeats=repeats)
 
     def reset(self, pose0: torch.Tensor):
         self.pose.copy_(pose0.reshape(12))

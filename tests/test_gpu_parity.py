@@ -242,6 +242,17 @@ def test_autotuner_picks_a_valid_setting(R):
     assert torch.equal(P, P_before)
     out = R.render(st, scd, P, [cam])[0]
     assert torch.equal(out["color"], tgt["color"])
+    # the solver's own tune: whole steps on its state configuration, then the
+    # captured solve runs with the pick
+    prob = R.TrackingProblem(scd, cam, tgt["color"].clone(), tgt["depth"].clone())
+    solver = R.TrackingSolver(prob, iters=3, reset_pose=P)
+    f2, b2 = solver.autotune(P, repeats=2)
+    say("solver picked", f2, b2)
+    assert f2 == b2 and f2 in (1, 2, 4)
+    solver.prepare(P)
+    solver.run()
+    torch.cuda.synchronize()
+    solver.check()
 
 
 def test_long_tile_segments_take_the_merge_path(R):

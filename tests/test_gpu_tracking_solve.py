@@ -149,3 +149,53 @@ def test_benchmarked_solve_matches_oracle(R, solve, ppl):
         say(f"solve replay {rep}: |R - R_oracle| {dR:.3e}, |t - t_oracle| {dt:.3e} m "
             f"(the solve moved R by {np.abs(Rr - R0).max():.3e}, t by {np.abs(tr - t0).max():.3e} m)")
         assert dR <= 1e-5 and dt <= 1e-5
+
+
+@pytest.mark.parametrize("ppl", [1, 4])
+def test_blend_timing_reruns_leave_the_state_as_the_step_left_it(R, ppl):
+    """cgsr_time_tracking_blend (how the benchmark times its dominant kernel)
+    re-runs the last step's fused blend; a state that was timed then takes
+    its next step exactly as one that was not (pose gradients equal up to the
+    float atomics' order), with the kernel ranking its own buckets (ppl 1) or
+    reading the segmented sort's lists (ppl 4)."""
+    say(f"case: blend timing re-runs, 100k room 640x480, {ppl} pixel(s) per lane")
+    sc = synth.room_scene(0, 100_000, (5.0, 4.0, 3.0))
+    cam = synth.TRACKING_CAMERA
+    true = synth.level_room_pose(0)
+    scd = {k: torch.from_numpy(np.ascontiguousarray(v, np.float32)).cuda() for k, v in sc.items()}
+    tgt = R.render(R.State(), scd, R.pose_tensor(*true), [cam])[0]
+    tc, td = tgt["color"].contiguous(), tgt["depth"].contiguous()
+    P1 = R.pose_tensor(*synth.perturb_pose(*true, 1000)).reshape(1, 12)
+    P2 = R.pose_tensor(*synth.perturb_pose(*true, 1001)).reshape(1, 12)
+    grads = []
+    for timed in (False, True):
+        st = R.State(sync_capacity=True, fwd_ppl=ppl, bwd_ppl=ppl, count_work=False)
+        d = torch.zeros((1, 6), device="cuda")
+        R.tracking_step(st, scd, P1.clone(), [cam], [tc], [td], dposes=d)
+        torch.cuda.synchronize()
+        st.reserve(tile_pairs=int(st.stats().peak_pairs * 1.5) + 64)
+        cap = int(st.stats().pair_capacity)
+        if ppl == 1:
+            assert cap <= 256, "the kernel ranks its own buckets"
+        else:
+            assert cap > 256 // ppl, "the segmented sort orders the buckets"
+        d.zero_()
+        R.tracking_step(st, scd, P1.clone(), [cam], [tc], [td], dposes=d)
+        g1 = d.clone()
+        if timed:
+            ms = [st.time_tracking_blend(reps) for reps in (1, 20)]
+            say(f"blend re-run: {ms[0] * 1e3:.1f} us (1 launch), {ms[1] * 1e3:.1f} us (average of 20)")
+            assert all(0.0 < m < 10.0 for m in ms)
+        d.zero_()
+        R.tracking_step(st, scd, P2.clone(), [cam], [tc], [td], dposes=d)
+        torch.cuda.synchronize()
+        st.check()
+        grads.append((g1.double().cpu().numpy(), d.double().cpu().numpy()))
+        if timed:
+            R.render(st, scd, P2.clone(), [cam])
+            with pytest.raises(R.B.CgsrError, match="not a tracking step"):
+                st.time_tracking_blend(5)
+    for a, b in zip(*grads):
+        err = np.abs(a - b).max() / np.abs(a).max()
+        say("pose gradient, timed state vs untimed:", err)
+        assert err <= 1e-5
