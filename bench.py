@@ -238,7 +238,7 @@ class MappingIteration:
     each view's pose, on preallocated buffers; gradients are cleared once per
     iteration and summed over the views by the library."""
 
-    def __init__(self, torch, R, scene, poses, cams, target_colors, target_depths, batched: bool):
+    def __init__(self, torch, R, scene, poses, cams, target_colors, target_depths, batched: bool, ppl=(1, 1)):
         B = R.B
         self.torch, self.R, self.B = torch, R, B
         self.batched = batched
@@ -275,7 +275,9 @@ class MappingIteration:
             self.grad_s.append(B.cgsr_images(d["color"].data_ptr(), d["depth"].data_ptr(), None, None,
                                              d["uncertainty"].data_ptr()))
         # the iteration reads no work counts (only pair peaks)
-        self.states = [R.State(sync_capacity=True, count_work=False) for _ in range(1 if batched else self.V)]
+        self.ppl = ppl
+        self.states = [R.State(sync_capacity=True, count_work=False, fwd_ppl=ppl[0], bwd_ppl=ppl[1])
+                       for _ in range(1 if batched else self.V)]
 
     def _views(self, st, vs):
         B, s = self.B, self.R._stream()
@@ -298,12 +300,27 @@ class MappingIteration:
             for v in range(self.V):
                 self._views(self.states[v], [v])
 
+    def autotune(self, repeats=3):
+        """The library's render autotuner on this iteration's first state and
+        views (after a sizing call, so the gradient images hold real
+        gradients); the states made by freeze_capacity then use its pick."""
+        B = self.B
+        vs = list(range(self.V)) if self.batched else [0]
+        out = B.cgsr_autotune_render(self.states[0].handle, self.g, len(vs), self.poses[vs[0]].data_ptr(),
+                                     [self.cams[v] for v in vs], [self.td[v].data_ptr() for v in vs],
+                                     [self.out_s[v] for v in vs], [self.grad_s[v] for v in vs], self.dG,
+                                     self.dposes[vs[0]].data_ptr(), repeats, self.R._stream())
+        self.ppl = (int(out.fwd_pixels_per_lane), int(out.bwd_pixels_per_lane))
+        self.flat.zero_()
+        self.dposes.zero_()
+        return self.ppl
+
     def stage_times(self, reps=5):
         """Stage durations (ms) of the batched form of the iteration, from
         the library's HIP events around each stage, on a timing-enabled state
         with the timed state's pair capacity (eager iterations)."""
         cap = int(self.states[0].stats().pair_capacity)
-        tst = self.R.State(sync_capacity=False, timing=True, count_work=False)
+        tst = self.R.State(sync_capacity=False, timing=True, count_work=False, fwd_ppl=self.ppl[0], bwd_ppl=self.ppl[1])
         tst.reserve(tile_pairs=cap)
         acc = {}
         for r in range(reps + 1):
@@ -322,7 +339,7 @@ class MappingIteration:
         """After a sizing call: fixed pair capacity, no per-call readback."""
         for k, st in enumerate(self.states):
             peak = st.stats().peak_pairs
-            new = self.R.State(sync_capacity=False, count_work=False)
+            new = self.R.State(sync_capacity=False, count_work=False, fwd_ppl=self.ppl[0], bwd_ppl=self.ppl[1])
             new.reserve(tile_pairs=int(peak * margin) + 64)
             self.states[k] = new
             st.close()
@@ -400,17 +417,22 @@ def run_mapping(args, torch, R, synth, views: int):
     del tgt, tst
     scd = {k: torch.from_numpy(v).cuda() for k, v in sc.items()}
     modes = [("batched", True)] + ([("sequential", False)] if views > 1 else [])
+    ppl = tuple(int(x) for x in args.mapping_ppl.split(",")) if args.mapping_ppl != "auto" else (1, 1)
     res = {}
     for name, batched in modes:
-        it = MappingIteration(torch, R, scd, P, cams, tcs, tds, batched)
+        it = MappingIteration(torch, R, scd, P, cams, tcs, tds, batched, ppl)
         it()
         torch.cuda.synchronize()
+        if args.mapping_ppl == "auto":
+            tuned = it.autotune()
+            log(f"{name}: autotuned pixels per lane (forward, backward): {tuned}")
         it.freeze_capacity()
         for _ in range(args.warmup):
             it()
         wall, ev = _sync_timed(torch, it, args.steps)
         it.check()
-        res[name] = dict(ms_per_iter=wall * 1e3 / args.steps, event_ms_per_iter=ev / args.steps, stats=it.stats())
+        res[name] = dict(ms_per_iter=wall * 1e3 / args.steps, event_ms_per_iter=ev / args.steps, stats=it.stats(),
+                         ppl=list(it.ppl))
         log(f"{name}: {res[name]['ms_per_iter']:.3f} ms/iteration ({views} view(s))")
         if batched:
             res[name]["stages"] = it.stage_times()
@@ -443,7 +465,8 @@ def run_mapping(args, torch, R, synth, views: int):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": (f"mapping: {n} Gaussians on an 8x6x3 m room, {views} view(s) 1200x680 f=600, "
                                 "render with sensor depth + uncertainty-weighted L1 + backward to all "
-                                "parameters and poses"), "gaussians": n, "views": views, "sh_degree": deg},
+                                "parameters and poses"), "gaussians": n, "views": views, "sh_degree": deg,
+                   "pixels_per_lane": res["batched"]["ppl"], "autotuned": args.mapping_ppl == "auto"},
         "roofline": roof,
         "blend_fwd_roofline": {"achieved": round(fwd_tflops, 4), "unit": "TFLOP/s",
                                "frac": round(fwd_tflops / FP32_VECTOR_PEAK_TFLOPS, 5),
@@ -456,6 +479,7 @@ def run_mapping(args, torch, R, synth, views: int):
     }
     if views > 1:
         out["sequential"] = {"ms_per_step": round(res["sequential"]["ms_per_iter"], 5),
+                             "pixels_per_lane": res["sequential"]["ppl"],
                              "value": round(views * 1e3 / res["sequential"]["ms_per_iter"], 3),
                              "speedup_batched": round(res["sequential"]["ms_per_iter"] / ms, 3)}
     if not args.no_cpu_baseline:
@@ -777,6 +801,8 @@ def main():
     ap.add_argument("--replays", type=int, default=100, help="solve replays timed one by one for the spread")
     ap.add_argument("--blend-reps", type=int, default=200,
                     help="back-to-back re-runs of the fused blend that time the dominant kernel")
+    ap.add_argument("--mapping-ppl", default="auto", metavar="FWD,BWD",
+                    help="pixels per lane of the mapping blends (forward, backward), or auto")
     ap.add_argument("--tracking-only", action="store_true",
                     help="only the headline tracking line (no mapping / batched workloads beside it)")
     ap.add_argument("--ppl", type=int, default=0, choices=(0, 1, 2, 4),

@@ -415,6 +415,29 @@ cgsr_status cgsr_autotune_tracking(cgsr_state *st, const cgsr_gaussians *g, int3
                                    void *stream);
 
 /*
+ * Autotuner of the mapping iteration's blends (Eq. 3-10 and their backward,
+ * the batched window of Eq. 21): picks the forward and the backward blend's
+ * pixels per lane (1, 2 or 4 each) for a render + backward workload on this
+ * state by timing, for each of the nine pairs, one cgsr_render + cgsr_backward
+ * with the state's settings (it may grow the buckets), then `repeats` more
+ * between two HIP events on the stream without the capacity read-back.  The
+ * arguments are those of cgsr_render and cgsr_backward.  The tuning runs
+ * write the maps and add their gradients to dG and dposes 9 (repeats + 1)
+ * times: the caller clears those after.
+ *
+ * Both autotuners keep their picks in the state, keyed by the workload's
+ * shape (Gaussian count, SH degree, view count and sizes, and which outputs
+ * and gradients are asked for; for tracking also the bucket size and work
+ * counts): a later call with the same shape applies the kept pick without
+ * timing.  The pick is stored in the state's settings and returned in *out
+ * (may be NULL).  Synchronises; not for use under graph capture.
+ */
+cgsr_status cgsr_autotune_render(cgsr_state *st, const cgsr_gaussians *g, int32_t n_views, const float *poses,
+                                 const cgsr_camera *cams, const float *const *depth_obs, const cgsr_images *outs,
+                                 const cgsr_image_grads *dimgs, const cgsr_gaussian_grads *dG, float *dposes,
+                                 int32_t repeats, cgsr_settings *out, void *stream);
+
+/*
  * Gaussian management (Sec. 3.3).  The set is grown by spawning and
  * densification and shrunk by compaction; each call writes a new set (or
  * appends to one) in caller-owned arrays and returns the new count on the

@@ -29,12 +29,10 @@ EXPORTED = (
     "cgsr_default_settings", "cgsr_state_create", "cgsr_state_destroy", "cgsr_state_reserve",
     "cgsr_render", "cgsr_render_nu", "cgsr_nu_prune", "cgsr_mapping_objective", "cgsr_gaussian_adam_step",
     "cgsr_backward", "cgsr_tracking_loss_grad", "cgsr_mapping_loss_grad", "cgsr_pose_adam_step",
-    "cgsr_tracking_step",
-    "cgsr_autotune_tracking", "cgsr_spawn_gaussians", "cgsr_compact_gaussians", "cgsr_compact_gaussians_noalloc",
-    "cgsr_set_densify_stats",
-    "cgsr_densify_gaussians", "cgsr_state_check", "cgsr_get_stats", "cgsr_get_timings", "cgsr_time_tracking_blend", "cgsr_debug_buffers",
-    "cgsr_last_error",
-    "cgsr_version",
+    "cgsr_tracking_step", "cgsr_autotune_tracking", "cgsr_autotune_render", "cgsr_spawn_gaussians",
+    "cgsr_compact_gaussians", "cgsr_compact_gaussians_noalloc", "cgsr_set_densify_stats", "cgsr_densify_gaussians",
+    "cgsr_state_check", "cgsr_get_stats", "cgsr_get_timings", "cgsr_time_tracking_blend", "cgsr_debug_buffers",
+    "cgsr_last_error", "cgsr_version",
 )
 STAGES = ("project", "emit", "sort", "blend_fwd", "blend_bwd", "project_bwd")
 
@@ -142,6 +140,9 @@ def lib() -> C.CDLL:
                                      C.POINTER(cgsr_adam_params), vp, vp]
     L.cgsr_autotune_tracking.argtypes = [vp, C.POINTER(cgsr_gaussians), C.c_int32, vp, C.POINTER(cgsr_camera),
                                          C.POINTER(vp), C.POINTER(vp), C.c_int32, C.POINTER(cgsr_settings), vp]
+    L.cgsr_autotune_render.argtypes = [vp, C.POINTER(cgsr_gaussians), C.c_int32, vp, C.POINTER(cgsr_camera),
+                                       C.POINTER(vp), C.POINTER(cgsr_images), C.POINTER(cgsr_images),
+                                       C.POINTER(cgsr_gaussian_grads), vp, C.c_int32, C.POINTER(cgsr_settings), vp]
     L.cgsr_spawn_gaussians.argtypes = [C.POINTER(cgsr_gaussian_arrays), C.c_int64, C.c_int64, C.POINTER(cgsr_camera),
                                        vp, vp, vp, vp, C.c_float, C.c_int32, C.c_float, C.POINTER(C.c_int64), vp]
     L.cgsr_compact_gaussians.argtypes = [C.c_int64, vp, C.POINTER(cgsr_gaussian_arrays),
@@ -322,6 +323,20 @@ def cgsr_autotune_tracking(state: int, g: cgsr_gaussians, n_views: int, poses: i
     out = cgsr_settings()
     _check(lib().cgsr_autotune_tracking(state, C.byref(g), n_views, poses, cam_arr, tc, td, repeats, C.byref(out),
                                         stream))
+    return out
+
+
+def cgsr_autotune_render(state: int, g: cgsr_gaussians, n_views: int, poses: int, cams, depth_obs, outs, dimgs,
+                         dG: cgsr_gaussian_grads | None, dposes: int | None, repeats: int,
+                         stream: int) -> cgsr_settings:
+    """depth_obs: sequence of device pointers (0/None allowed) or None; outs, dimgs: sequences of cgsr_images."""
+    cam_arr = (cgsr_camera * n_views)(*cams)
+    out_arr = (cgsr_images * n_views)(*outs)
+    grad_arr = (cgsr_images * n_views)(*dimgs)
+    dep = None if depth_obs is None else (C.c_void_p * n_views)(*[p or None for p in depth_obs])
+    out = cgsr_settings()
+    _check(lib().cgsr_autotune_render(state, C.byref(g), n_views, poses, cam_arr, dep, out_arr, grad_arr,
+                                      C.byref(dG) if dG is not None else None, dposes, repeats, C.byref(out), stream))
     return out
 
 

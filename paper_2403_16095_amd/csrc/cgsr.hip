@@ -58,6 +58,14 @@ void dev_free(T*& p) {
 
 }  // namespace
 
+// Fewest tiles for which a fused tracking step orders its tiles longest
+// first: about the workgroups the chip holds at once (256 CUs x 6).  No
+// launch orders more than kOrderMaxTiles: the one-workgroup order kernel then
+// costs about what it saves (32 frames of mixed resolution, 54k tiles: 0.5 %
+// slower with the order; eight 1200x680 views, 25.8k tiles: 1.5 % faster).
+constexpr int32_t kOrderMinTiles = 1536;
+constexpr int32_t kOrderMaxTiles = 32768;
+
 struct cgsr_state {
   int device = 0;
   cgsr_settings settings{};
@@ -73,6 +81,8 @@ struct cgsr_state {
   // per tile
   uint32_t* tile_count = nullptr;
   uint2* ranges = nullptr;
+  uint32_t* tile_order = nullptr;   // tiles by descending list length, for the blends
+  bool order_ok = false;            // tile_order holds the last render's order
   bool tiles_dirty = false;   // a render stopped between projection and sort
   // per-tile buckets of pairs, [bucket_tiles][cap_tile_pairs]
   uint64_t* keys[2] = {nullptr, nullptr};
@@ -118,6 +128,12 @@ struct cgsr_state {
   int32_t total_tiles = 0;
   int64_t records = 0;
   ViewIO io_fwd[CGSR_MAX_VIEWS];
+  // autotuner picks per workload shape (see tune_key)
+  struct TunePick {
+    uint64_t key;
+    int32_t fwd, bwd;
+  } tune_cache[16];
+  int tune_n = 0;
   // the fused blend launch of the last tracking step, for timing re-runs;
   // valid while no other call has changed the state's buffers or tables
   RasterBufs track_rb{};
@@ -190,8 +206,11 @@ cgsr_status reserve(cgsr_state* st, int64_t records, int64_t pixels, int64_t til
   if (tiles > st->cap_tiles) {
     dev_free(st->ranges);
     dev_free(st->tile_count);
+    dev_free(st->tile_order);
     st->cap_tiles = 0;
+    st->order_ok = false;
     if ((s = dev_alloc(&st->ranges, tiles))) return s;
+    if ((s = dev_alloc(&st->tile_order, tiles))) return s;
     if ((s = dev_alloc(&st->tile_count, tiles * kTileCounterStride))) return s;
     HIP_TRY(hipMemset(st->ranges, 0, sizeof(uint2) * (size_t)tiles));
     HIP_TRY(hipMemset(st->tile_count, 0, sizeof(uint32_t) * kTileCounterStride * (size_t)tiles));
@@ -269,6 +288,7 @@ RasterBufs raster_bufs(cgsr_state* st, int slot) {
   rb.counters = st->counters;
   rb.tile_cap = (uint32_t)st->cap_tile_pairs;
   rb.keep_counts = false;
+  rb.order = st->order_ok ? st->tile_order : nullptr;
   rb.views = ViewTable{st->io[slot].dev, st->n_views, (int32_t)st->g.n};
   rb.total_tiles = st->total_tiles;
   return rb;
@@ -347,7 +367,7 @@ cgsr_status cgsr_state_destroy(cgsr_state* st) {
   dev_free(st->rect);
   dev_free(st->rec_grad);
   dev_free(st->tile_count);
-
+  dev_free(st->tile_order);
   dev_free(st->ranges);
   dev_free(st->keys[0]);
   dev_free(st->keys[1]);
@@ -527,9 +547,21 @@ cgsr_status render_impl(cgsr_state* st, const RenderArgs& a, hipStream_t stream)
   // A fused tracking step whose buckets hold at most one key per thread of
   // its blend sorts each bucket inside the blend: one launch fewer.
   const bool sort_here = a.track && a.fused && st->cap_tile_pairs <= kTilePixels / st->settings.fwd_pixels_per_lane;
+  // The blends take the tiles longest list first.  A fused tracking step
+  // orders them from the pair counters only when its launch holds more tiles
+  // than fit the chip at once (a frame of 640x480 fits: its order would only
+  // add a launch).
+  st->order_ok = false;
+  const bool order = st->total_tiles < kOrderMaxTiles;
   if (!sort_here) {
     launch_segment_sort(sb, st->total_tiles, stream);
+    if (order) launch_tile_order(st->ranges, nullptr, st->total_tiles, st->tile_order, stream);
     HIP_TRY(hipGetLastError());
+    st->order_ok = order;
+  } else if (order && st->total_tiles >= kOrderMinTiles) {
+    launch_tile_order(nullptr, st->tile_count, st->total_tiles, st->tile_order, stream);
+    HIP_TRY(hipGetLastError());
+    st->order_ok = true;
   }
   if ((s = mark(CGSR_STAGE_BLEND_FWD))) return s;
   RasterBufs rb = raster_bufs(st, 0);
@@ -576,6 +608,39 @@ cgsr_status backward_impl(cgsr_state* st, int slot, bool params, bool track, con
   if (timed) HIP_TRY(hipEventRecord(st->ev_bwd[2], stream));
   st->bwd_timed = timed;
   return CGSR_OK;
+}
+
+// FNV-1a over the workload's shape: what the tuned kernels' speed depends on.
+uint64_t tune_key(int kind, const cgsr_gaussians* g, int32_t n_views, const cgsr_camera* cams, int32_t extra) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](int64_t v) {
+    for (int i = 0; i < 8; ++i) {
+      h ^= (uint64_t)((v >> (8 * i)) & 0xff);
+      h *= 1099511628211ull;
+    }
+  };
+  mix(kind);
+  mix(g ? g->n : 0);
+  mix(g && g->sh ? g->sh_degree + 1 : 0);
+  mix(n_views);
+  for (int v = 0; v < n_views; ++v) {
+    mix(cams[v].width);
+    mix(cams[v].height);
+  }
+  mix(extra);
+  return h;
+}
+
+const cgsr_state::TunePick* tune_lookup(const cgsr_state* st, uint64_t key) {
+  for (int i = 0; i < st->tune_n; ++i)
+    if (st->tune_cache[i].key == key) return &st->tune_cache[i];
+  return nullptr;
+}
+
+void tune_store(cgsr_state* st, uint64_t key, int32_t fwd, int32_t bwd) {
+  const int cap = (int)(sizeof(st->tune_cache) / sizeof(st->tune_cache[0]));
+  const int i = st->tune_n < cap ? st->tune_n++ : (int)(key % (uint64_t)cap);   // full: replace one
+  st->tune_cache[i] = cgsr_state::TunePick{key, fwd, bwd};
 }
 
 bool bad_adam(const cgsr_adam_params* p) {
@@ -721,7 +786,8 @@ cgsr_status cgsr_tracking_step(cgsr_state* st, const cgsr_gaussians* g, int32_t 
 cgsr_status cgsr_time_tracking_blend(cgsr_state* st, int32_t reps, void* stream_, float* ms_out) {
   hipStream_t stream = (hipStream_t)stream_;
   if (!st || !ms_out) return fail(CGSR_ERR_INVALID_ARG, "cgsr_time_tracking_blend: NULL argument");
-  if (reps < 1 || reps > 100000) return fail(CGSR_ERR_INVALID_ARG, "cgsr_time_tracking_blend: reps must be 1 .. 100000");
+  if (reps < 1 || reps > 100000)
+    return fail(CGSR_ERR_INVALID_ARG, "cgsr_time_tracking_blend: reps must be 1 .. 100000");
   if (!st->track_rb_ok)
     return fail(CGSR_ERR_STATE, "cgsr_time_tracking_blend: the last call on this state was not a tracking step "
                                 "with a pose gradient or update");
@@ -770,8 +836,19 @@ cgsr_status cgsr_autotune_tracking(cgsr_state* st, const cgsr_gaussians* g, int3
   HIP_TRY(hipStreamIsCapturing(stream, &capturing));
   if (capturing != hipStreamCaptureStatusNone)
     return fail(CGSR_ERR_STATE, "cgsr_autotune_tracking: not under graph capture");
+  if (!g || !cams || n_views < 1 || n_views > CGSR_MAX_VIEWS)
+    return fail(CGSR_ERR_INVALID_ARG, "cgsr_autotune_tracking: need the Gaussians and 1 .. %d cameras", CGSR_MAX_VIEWS);
   cgsr_status s = set_device(st);
   if (s) return s;
+  // the pick depends on the bucket size too: whether the blend sorts its own
+  const uint64_t key = tune_key(1, g, n_views, cams, (int32_t)std::min<int64_t>(st->cap_tile_pairs, 1 << 20) * 2 +
+                                                         st->settings.count_work);
+  if (const cgsr_state::TunePick* hit = tune_lookup(st, key)) {
+    st->settings.fwd_pixels_per_lane = hit->fwd;
+    st->settings.bwd_pixels_per_lane = hit->bwd;
+    if (out) *out = st->settings;
+    return CGSR_OK;
+  }
   const cgsr_settings saved = st->settings;
   hipEvent_t ev[2] = {nullptr, nullptr};
   HIP_TRY(hipEventCreate(&ev[0]));
@@ -819,6 +896,84 @@ cgsr_status cgsr_autotune_tracking(cgsr_state* st, const cgsr_gaussians* g, int3
   // one setting serves both
   st->settings.fwd_pixels_per_lane = pick;
   st->settings.bwd_pixels_per_lane = pick;
+  tune_store(st, key, pick, pick);
+  if (out) *out = st->settings;
+  return CGSR_OK;
+}
+
+cgsr_status cgsr_autotune_render(cgsr_state* st, const cgsr_gaussians* g, int32_t n_views, const float* poses,
+                                 const cgsr_camera* cams, const float* const* depth_obs, const cgsr_images* outs,
+                                 const cgsr_image_grads* dimgs, const cgsr_gaussian_grads* dG, float* dposes,
+                                 int32_t repeats, cgsr_settings* out, void* stream_) {
+  hipStream_t stream = (hipStream_t)stream_;
+  if (!st || !g || !cams || !outs || !dimgs)
+    return fail(CGSR_ERR_INVALID_ARG, "cgsr_autotune_render: NULL argument");
+  if (n_views < 1 || n_views > CGSR_MAX_VIEWS)
+    return fail(CGSR_ERR_INVALID_ARG, "cgsr_autotune_render: n_views in [1, %d]", CGSR_MAX_VIEWS);
+  if (repeats < 1 || repeats > 1000) return fail(CGSR_ERR_INVALID_ARG, "cgsr_autotune_render: repeats in [1, 1000]");
+  hipStreamCaptureStatus capturing = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(stream, &capturing));
+  if (capturing != hipStreamCaptureStatusNone)
+    return fail(CGSR_ERR_STATE, "cgsr_autotune_render: not under graph capture");
+  cgsr_status s = set_device(st);
+  if (s) return s;
+  const bool params = dG && (dG->means || dG->log_scales || dG->quats || dG->opacity_logits || dG->rgb || dG->sh);
+  int32_t what = (params ? 1 : 0) | (dposes ? 2 : 0);
+  for (int v = 0; v < n_views; ++v)
+    what |= (depth_obs && depth_obs[v] ? 4 : 0) | (outs[v].uncertainty ? 8 : 0) | (dimgs[v].opacity ? 16 : 0) |
+            (dimgs[v].depth_median ? 32 : 0);
+  const uint64_t key = tune_key(2, g, n_views, cams, what);
+  if (const cgsr_state::TunePick* hit = tune_lookup(st, key)) {
+    st->settings.fwd_pixels_per_lane = hit->fwd;
+    st->settings.bwd_pixels_per_lane = hit->bwd;
+    if (out) *out = st->settings;
+    return CGSR_OK;
+  }
+  const cgsr_settings saved = st->settings;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  HIP_TRY(hipEventCreate(&ev[0]));
+  if (hipEventCreate(&ev[1]) != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    return fail(CGSR_ERR_HIP, "cgsr_autotune_render: hipEventCreate failed");
+  }
+  const int32_t cand[3] = {1, 2, 4};
+  float best = 1e30f;
+  int32_t pick_f = saved.fwd_pixels_per_lane, pick_b = saved.bwd_pixels_per_lane;
+  for (int c = 0; c < 9 && !s; ++c) {
+    // One render + backward with the caller's settings (it may grow the
+    // buckets), then the timed ones without the capacity read-back.
+    st->settings = saved;
+    st->settings.timing = 0;
+    st->settings.fwd_pixels_per_lane = cand[c / 3];
+    st->settings.bwd_pixels_per_lane = cand[c % 3];
+    hipError_t e = hipSuccess;
+    for (int r = 0; r <= repeats && !s && e == hipSuccess; ++r) {
+      if (r == 1) {
+        st->settings.sync_capacity = 0;
+        e = hipEventRecord(ev[0], stream);
+        if (e != hipSuccess) break;
+      }
+      s = cgsr_render(st, g, n_views, poses, cams, depth_obs, outs, stream);
+      if (!s) s = cgsr_backward(st, dimgs, dG, dposes, stream);
+    }
+    float ms = 0.f;
+    if (!s && e == hipSuccess) e = hipEventRecord(ev[1], stream);
+    if (!s && e == hipSuccess) e = hipEventSynchronize(ev[1]);
+    if (!s && e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+    if (!s && e != hipSuccess) s = fail(CGSR_ERR_HIP, "cgsr_autotune_render: %s", hipGetErrorString(e));
+    if (!s && ms < best) {
+      best = ms;
+      pick_f = cand[c / 3];
+      pick_b = cand[c % 3];
+    }
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  st->settings = saved;
+  if (s) return s;
+  st->settings.fwd_pixels_per_lane = pick_f;
+  st->settings.bwd_pixels_per_lane = pick_b;
+  tune_store(st, key, pick_f, pick_b);
   if (out) *out = st->settings;
   return CGSR_OK;
 }

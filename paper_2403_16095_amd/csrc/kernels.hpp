@@ -117,6 +117,10 @@ struct SegSortBufs {
 void launch_segment_sort(const SegSortBufs& b, int32_t total_tiles, hipStream_t s);
 // Fill n uint32 with zero (a kernel, so it can sit in a captured graph).
 void launch_clear_u32(uint32_t* p, int64_t n, hipStream_t s);
+// Tiles by descending list length, in order[tiles]: lengths from the ranges
+// after the sort, or with ranges null from the pair counters (stride
+// kTileCounterStride) before a blend that sorts its own buckets.
+void launch_tile_order(const uint2* ranges, const uint32_t* counts, int32_t tiles, uint32_t* order, hipStream_t s);
 // Pair counter of each tile = the length of its range (undoes the reset of
 // a tracking kernel that sorted its own buckets).
 void launch_restore_counts(uint32_t* tile_count, const uint2* ranges, int32_t tiles, hipStream_t s);
@@ -160,6 +164,9 @@ struct RasterBufs {
   // Timing re-runs of a tracking step's kernel leave the pair counters as
   // they are, so every re-run sorts and walks the same buckets.
   bool keep_counts;
+  // Tile of each workgroup, longest list first (launch_tile_order), or null
+  // for workgroup b on tile b.
+  const uint32_t* order;
 };
 // ppl: pixels per lane, 1, 2 or 4 (256 / ppl lanes per 16x16 tile).
 void launch_raster_forward(const RasterBufs& b, bool track, int ppl, hipStream_t s);

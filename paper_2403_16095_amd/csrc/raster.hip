@@ -548,7 +548,7 @@ __device__ __forceinline__ void backward_tile(const RasterBufs& b, Stage<kTilePi
 template <int kPPL, bool kTrack, bool kNu, bool kStats = true>
 __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(RasterBufs b) {
   __shared__ Stage<kTilePixels / kPPL / kWave> s;
-  const int gtile = blockIdx.x;
+  const int gtile = b.order ? (int)b.order[blockIdx.x] : (int)blockIdx.x;
   const int v = view_of_tile(b.views, gtile);
   const ViewIO io = b.views.io[v];
   FwdPix<kPPL> f;
@@ -565,7 +565,7 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
   constexpr int L = kTilePixels / kPPL;
   __shared__ Stage<kTilePixels / kPPL / kWave> s;
   __shared__ uint32_t s_max;
-  const int gtile = blockIdx.x;
+  const int gtile = b.order ? (int)b.order[blockIdx.x] : (int)blockIdx.x;
   const int v = view_of_tile(b.views, gtile);
   const ViewIO io = b.views.io[v];
   const ViewInfo& cam = io.info;
@@ -665,7 +665,7 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_track_kernel(Raster
   // workgroups per CU at one pixel per lane).
   static_assert(sizeof(s.A) >= sizeof(uint64_t) * L, "sort keys fit the stage");
   uint64_t* s_key = reinterpret_cast<uint64_t*>(&s.A[0][0]);
-  const int gtile = blockIdx.x;
+  const int gtile = b.order ? (int)b.order[blockIdx.x] : (int)blockIdx.x;
   const int v = view_of_tile(b.views, gtile);
   const ViewIO io = b.views.io[v];
   const float2 org = tile_origin(io.info, gtile);

@@ -24,7 +24,18 @@ constexpr int kLdsKeys = 4096;   // 32 KB of 64-bit keys
 
 __device__ __forceinline__ uint32_t next_pow2(uint32_t x) { return x <= 1 ? 1u : 1u << (32 - __builtin_clz(x - 1)); }
 
-// Bitonic sort of s[0, p) ascending, p a power of two; all threads call it.
+// LDS slot of key x in the bitonic sort: its low five bits XORed with the
+// next five.  A compare-exchange stage of distance j has lane i read keys
+// lo = 2j (i / j) + i % j and lo + j, which for j < 32 land a wave's lanes on
+// the same banks several times over (SQ_LDS_BANK_CONFLICT counted 0.66
+// conflict cycles per LDS instruction at the mapping size).  The swizzle is a
+// permutation of every aligned block of 64 keys that puts each stage's 64
+// lanes on distinct bank pairs (enumerated for 32 and 64 banks of 4 bytes and
+// 512 to 4096 keys) and keeps the array dense.
+__device__ __forceinline__ uint32_t swz(uint32_t x) { return x ^ ((x >> 1) & 31u); }
+
+// Bitonic sort of s[0, p) ascending (slots swizzled by swz), p a power of
+// two; all threads call it.
 __device__ void bitonic_lds(uint64_t* s, uint32_t p) {
   for (uint32_t k = 2; k <= p; k <<= 1) {
     for (uint32_t j = k >> 1; j > 0; j >>= 1) {
@@ -32,10 +43,10 @@ __device__ void bitonic_lds(uint64_t* s, uint32_t p) {
         const uint32_t lo = 2 * j * (i / j) + (i % j);
         const uint32_t hi = lo + j;
         const bool up = (lo & k) == 0;
-        const uint64_t a = s[lo], b = s[hi];
+        const uint64_t a = s[swz(lo)], b = s[swz(hi)];
         if ((a > b) == up) {
-          s[lo] = b;
-          s[hi] = a;
+          s[swz(lo)] = b;
+          s[swz(hi)] = a;
         }
       }
       __syncthreads();
@@ -85,10 +96,10 @@ __global__ __launch_bounds__(kThreads) void segment_sort_kernel(SegSortBufs b) {
   }
   if (n <= (uint32_t)kLdsKeys) {
     const uint32_t p = next_pow2(n);
-    for (uint32_t i = threadIdx.x; i < p; i += kThreads) s[i] = i < n ? keys[i] : ~0ull;
+    for (uint32_t i = threadIdx.x; i < p; i += kThreads) s[swz(i)] = i < n ? keys[i] : ~0ull;
     __syncthreads();
     bitonic_lds(s, p);
-    for (uint32_t i = threadIdx.x; i < n; i += kThreads) b.sorted_vals[base + i] = (uint32_t)s[i];
+    for (uint32_t i = threadIdx.x; i < n; i += kThreads) b.sorted_vals[base + i] = (uint32_t)s[swz(i)];
     return;
   }
   // Long segment: sort chunks in LDS, write them back, then merge runs.
@@ -96,10 +107,10 @@ __global__ __launch_bounds__(kThreads) void segment_sort_kernel(SegSortBufs b) {
     const uint32_t cn = min((uint32_t)kLdsKeys, n - c0);
     const uint32_t p = next_pow2(cn);
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < p; i += kThreads) s[i] = i < cn ? keys[c0 + i] : ~0ull;
+    for (uint32_t i = threadIdx.x; i < p; i += kThreads) s[swz(i)] = i < cn ? keys[c0 + i] : ~0ull;
     __syncthreads();
     bitonic_lds(s, p);
-    for (uint32_t i = threadIdx.x; i < cn; i += kThreads) keys[c0 + i] = s[i];
+    for (uint32_t i = threadIdx.x; i < cn; i += kThreads) keys[c0 + i] = s[swz(i)];
   }
   __syncthreads();
   uint64_t* src = keys;
@@ -127,6 +138,64 @@ __global__ __launch_bounds__(kThreads) void clear_kernel(uint32_t* p, int64_t n)
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) p[i] = 0u;
 }
 
+// Longest-first order of the tiles for the blends: a launch with more tiles
+// than fit the chip at once then starts the long ones in its first round and
+// ends on short ones, instead of ending on whichever long tiles come last in
+// raster order.  One workgroup, a counting sort on bins of the list length:
+// 16 bins per octave (the leading bit and the next four), scanned from the
+// longest bin; tiles inside a bin keep the order their atomics left, which
+// changes no tile's result.
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderBins = 16 * 33;
+
+__device__ __forceinline__ uint32_t order_bin(uint32_t n) {
+  if (n == 0) return 0;
+  const uint32_t lz = __builtin_clz(n);                  // leading bit at 31 - lz
+  const uint32_t frac = lz <= 27 ? (n >> (27 - lz)) & 15u : (n << (lz - 27)) & 15u;   // the next four bits
+  return 1u + 16u * (31u - lz) + frac;
+}
+
+// A tile's list length: from its range after the sort, or (ranges null) from
+// its pair counter before a blend that sorts its own bucket.
+__device__ __forceinline__ uint32_t tile_length(const uint2* ranges, const uint32_t* counts, int t) {
+  if (ranges) {
+    const uint2 r = ranges[t];
+    return r.y - r.x;
+  }
+  return counts[(size_t)t * kTileCounterStride];
+}
+
+__global__ __launch_bounds__(kOrderThreads) void tile_order_kernel(const uint2* __restrict__ ranges,
+                                                                   const uint32_t* __restrict__ counts, int32_t tiles,
+                                                                   uint32_t* __restrict__ order) {
+  __shared__ uint32_t s_bin[kOrderBins];
+  __shared__ uint32_t s_wave[kOrderThreads / kWave];
+  for (int i = threadIdx.x; i < kOrderBins; i += kOrderThreads) s_bin[i] = 0u;
+  __syncthreads();
+  for (int t = threadIdx.x; t < tiles; t += kOrderThreads)
+    atomicAdd(&s_bin[order_bin(tile_length(ranges, counts, t))], 1u);
+  __syncthreads();
+  // exclusive offsets, the longest bin first: thread k takes bin
+  // kOrderBins - 1 - k (kOrderBins <= kOrderThreads)
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  const int bin = kOrderBins - 1 - (int)threadIdx.x;
+  const uint32_t c = bin >= 0 ? s_bin[bin] : 0u;
+  uint32_t inc = c;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const uint32_t y = __shfl_up(inc, d);
+    if (lane >= d) inc += y;
+  }
+  if (lane == kWave - 1) s_wave[wv] = inc;
+  __syncthreads();
+  uint32_t base = 0;
+  for (int q = 0; q < wv; ++q) base += s_wave[q];
+  if (bin >= 0) s_bin[bin] = base + inc - c;
+  __syncthreads();
+  for (int t = threadIdx.x; t < tiles; t += kOrderThreads)
+    order[atomicAdd(&s_bin[order_bin(tile_length(ranges, counts, t))], 1u)] = (uint32_t)t;
+}
+
 __global__ __launch_bounds__(kThreads) void restore_counts_kernel(uint32_t* tile_count, const uint2* ranges,
                                                                   int32_t tiles) {
   const int t = blockIdx.x * kThreads + threadIdx.x;
@@ -142,6 +211,12 @@ void launch_clear_u32(uint32_t* p, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   const int64_t blocks = std::min<int64_t>(1024, (n + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(clear_kernel, dim3((unsigned)blocks), dim3(kThreads), 0, s, p, n);
+}
+
+void launch_tile_order(const uint2* ranges, const uint32_t* counts, int32_t tiles, uint32_t* order, hipStream_t s) {
+  if (tiles <= 0) return;
+  static_assert(kOrderBins <= kOrderThreads, "one bin per thread in the scan");
+  hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderThreads), 0, s, ranges, counts, tiles, order);
 }
 
 void launch_restore_counts(uint32_t* tile_count, const uint2* ranges, int32_t tiles, hipStream_t s) {

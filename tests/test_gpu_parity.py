@@ -255,6 +255,47 @@ def test_autotuner_picks_a_valid_setting(R):
     solver.check()
 
 
+def test_render_autotuner_picks_and_keeps_a_setting(R):
+    """cgsr_autotune_render times render + backward for the nine (forward,
+    backward) pixels-per-lane pairs, keeps the pick per workload shape, and a
+    render with the pick writes the same maps as the default setting."""
+    from paper_2403_16095_amd import binding as B
+    say("case: render autotuner on a 20k-Gaussian 320x240 mapping workload")
+    sc = synth.room_scene(5, 20_000, (5.0, 4.0, 3.0))
+    cam = synth.camera(320, 240, 262.5, 262.5, 160, 120)
+    scd = dev(sc)
+    P = R.pose_tensor(*synth.level_room_pose(3))
+    H, W = cam["height"], cam["width"]
+    rng = np.random.default_rng(5)
+    td = t32(rng.uniform(0.5, 5.0, (H, W)))
+    maps = {k: torch.empty(sh, device="cuda") for k, sh in (("color", (3, H, W)), ("depth", (H, W)),
+                                                            ("uncertainty", (H, W)))}
+    dimgs = {k: t32(rng.standard_normal(v.shape) * 1e-3) for k, v in maps.items()}
+    grads = {k: torch.zeros_like(v) for k, v in scd.items()}
+    dposes = torch.zeros((1, 6), device="cuda")
+    out_s = B.cgsr_images(maps["color"].data_ptr(), maps["depth"].data_ptr(), None, None,
+                          maps["uncertainty"].data_ptr())
+    grad_s = B.cgsr_images(dimgs["color"].data_ptr(), dimgs["depth"].data_ptr(), None, None,
+                           dimgs["uncertainty"].data_ptr())
+    dG = B.cgsr_gaussian_grads(grads["means"].data_ptr(), grads["log_scales"].data_ptr(), grads["quats"].data_ptr(),
+                               grads["opacity_logits"].data_ptr(), grads["rgb"].data_ptr(), None)
+    st = R.State()
+    g = R.gaussians_struct(scd)
+    cs = [R.camera_struct(cam)]
+    picks = []
+    for _ in range(2):
+        o = B.cgsr_autotune_render(st.handle, g, 1, P.data_ptr(), cs, [td.data_ptr()], [out_s], [grad_s], dG,
+                                   dposes.data_ptr(), 2, torch.cuda.current_stream().cuda_stream)
+        picks.append((int(o.fwd_pixels_per_lane), int(o.bwd_pixels_per_lane)))
+    say("picked", picks)
+    assert picks[0] == picks[1] and all(x in (1, 2, 4) for x in picks[0])
+    tuned = R.render(st, scd, P, [cam], [td])[0]
+    ref = R.render(R.State(), scd, P, [cam], [td])[0]
+    torch.cuda.synchronize()
+    for k in ("color", "depth", "opacity", "depth_median", "uncertainty"):
+        assert torch.equal(tuned[k], ref[k]), k
+
+
 def test_long_tile_segments_take_the_merge_path(R):
     """More than 4096 Gaussians in one tile: the segment sort goes through its
     chunked LDS sort plus in-workgroup merges; lists and maps must still match."""
