@@ -450,9 +450,9 @@ def run_mapping(args, torch, R, synth, views: int):
     stages = res["batched"]["stages"]
     # the dominant kernel: the blend backward to every parameter
     bwd_flops = FLOP_EVAL * st["walked"] + FLOP_BLEND_BWD_MAP * st["blended"]
-    roof = alu_roofline("blend_bwd_map", "raster_backward_kernel<1, true, false, false>", bwd_flops,
-                        stages["blend_bwd"], "library HIP events around the stage, 5 eager iterations",
-                        measured_counters("raster_backward_kernel<1, true, false, false>"))
+    bsym = f"raster_backward_kernel<{res['batched']['ppl'][1]}, true, false, false>"
+    roof = alu_roofline("blend_bwd_map", bsym, bwd_flops, stages["blend_bwd"],
+                        "library HIP events around the stage, 5 eager iterations", measured_counters(bsym))
     fwd_flops = FLOP_EVAL * st["evaluations"] + FLOP_BLEND_MAP * st["blended"]
     fwd_tflops = fwd_flops / (stages["blend_fwd"] * 1e-3) / 1e12
     out = {
