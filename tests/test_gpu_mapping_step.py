@@ -98,11 +98,19 @@ def test_bundle_adjustment_window(R):
     e1 = np.mean([float((a["color"] - t).abs().mean()) for a, t in zip(after, tc)])
     say("mean keyframe colour L1 before/after", e0, e1)
     assert e1 < e0
-    # the same 10 iterations eagerly and from one captured graph
+    # The same 10 iterations from one captured graph, and twice eagerly.  The
+    # per-Gaussian gradient sums are float atomics taken in scheduling order,
+    # so no two runs agree bit for bit and Adam turns the rounding noise of a
+    # near-zero gradient into steps of up to its learning rate: the graph run
+    # must differ from an eager run no more than two eager runs differ from
+    # each other (the run-to-run spread, measured here, with a factor 3 for
+    # the randomness of both: measured ratios 1-1.8).
     scene_e, P_e, ba_e = make()
+    scene_e2, P_e2, ba_e2 = make()
     scene_g, P_g, ba_g = make()
     ba_g.step()                 # sizes the workspace (eager)
     ba_e.step()
+    ba_e2.step()
     ba_g.state.reserve(tile_pairs=int(ba_g.state.stats().peak_pairs * 1.5) + 64)
     ba_g.state.check()
     graph = torch.cuda.CUDAGraph()
@@ -115,18 +123,18 @@ def test_bundle_adjustment_window(R):
     torch.cuda.current_stream().wait_stream(side)
     for _ in range(9):
         ba_e.step()
+        ba_e2.step()
     graph.replay()
     torch.cuda.synchronize()
     ba_g.check()
     for k in ("means", "rgb", "log_scales", "quats", "opacity_logits"):
-        d = (scene_g[k] - scene_e[k]).abs()
-        frac = float((d > 1e-5).float().mean())
-        say(k, "graph vs eager: max diff", float(d.max()), "share over 1e-5", frac)
-        # parameters whose gradient is ~0 (cancelling contributions) take
-        # Adam steps on the sign of rounding noise, which follows the order of
-        # float atomics in any two runs; the objective and the poses below must
-        # agree, and only a small share of parameters may differ
-        assert frac < 5e-2, k
+        d_ge = (scene_g[k] - scene_e[k]).abs()
+        d_ee = (scene_e2[k] - scene_e[k]).abs()
+        share_ge, share_ee = float((d_ge > 1e-5).float().mean()), float((d_ee > 1e-5).float().mean())
+        say(k, f"graph vs eager: max diff {float(d_ge.max()):.3e}, share over 1e-5 {share_ge:.4f}; "
+               f"eager vs eager: max diff {float(d_ee.max()):.3e}, share over 1e-5 {share_ee:.4f}")
+        assert float(d_ge.max()) <= 3.0 * float(d_ee.max()) + 1e-6, k
+        assert share_ge <= 3.0 * share_ee + 1e-3, k
     d = float((P_g - P_e).abs().max())
     say("poses graph vs eager max diff", d)
     assert d < 1e-4
