@@ -268,7 +268,11 @@ __device__ __forceinline__ void sh_colour(const GaussianPtrs& g, int64_t i, cons
 #pragma unroll
   for (int ch = 0; ch < 3; ++ch) {
     float sum = 0.5f;
-    for (int k = 0; k < K; ++k) sum = __builtin_fmaf(c[3 * k + ch], o.Y[k], sum);
+    // a constant trip count keeps Y in registers (a bound of K would index
+    // it at run time, which puts the array in scratch memory)
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+      if (k < K) sum = __builtin_fmaf(c[3 * k + ch], o.Y[k], sum);
     o.clamped[ch] = sum < 0.f;
     o.col[ch] = o.clamped[ch] ? 0.f : sum;
   }
@@ -493,8 +497,9 @@ __global__ __launch_bounds__(kThreads) void project_backward_kernel(GaussianPtrs
         const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
         const float* c = g.sh + (int64_t)3 * K * i;
         float w[16];
-        for (int k = 0; k < 16; ++k) w[k] = 0.f;
-        for (int k = 0; k < K; ++k) w[k] = dc[0] * c[3 * k] + dc[1] * c[3 * k + 1] + dc[2] * c[3 * k + 2];
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+          w[k] = k < K ? dc[0] * c[3 * k] + dc[1] * c[3 * k + 1] + dc[2] * c[3 * k + 2] : 0.f;
         const float3 gd = sh_grad(g.sh_degree, sc.d[0], sc.d[1], sc.d[2], w);
         const float dot = gd.x * sc.d[0] + gd.y * sc.d[1] + gd.z * sc.d[2];
         dv[0] = (gd.x - sc.d[0] * dot) * sc.inv_len;
@@ -502,13 +507,17 @@ __global__ __launch_bounds__(kThreads) void project_backward_kernel(GaussianPtrs
         dv[2] = (gd.z - sc.d[2] * dot) * sc.inv_len;
         if (param_grads && dg.sh) {
           float* out = dg.sh + (int64_t)3 * K * i;
-          for (int k = 0; k < K; ++k)
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-              const float val = dc[ch] * sc.Y[k];
-              if (atomic_params) unsafeAtomicAdd(out + 3 * k + ch, val);
-              else out[3 * k + ch] += val;
+          for (int k = 0; k < 16; ++k) {
+            if (k < K) {
+#pragma unroll
+              for (int ch = 0; ch < 3; ++ch) {
+                const float val = dc[ch] * sc.Y[k];
+                if (atomic_params) unsafeAtomicAdd(out + 3 * k + ch, val);
+                else out[3 * k + ch] += val;
+              }
             }
+          }
         }
       }
       if (param_grads) {

@@ -101,10 +101,13 @@ def test_bundle_adjustment_window(R):
     # The same 10 iterations from one captured graph, and twice eagerly.  The
     # per-Gaussian gradient sums are float atomics taken in scheduling order,
     # so no two runs agree bit for bit and Adam turns the rounding noise of a
-    # near-zero gradient into steps of up to its learning rate: the graph run
-    # must differ from an eager run no more than two eager runs differ from
-    # each other (the run-to-run spread, measured here, with a factor 3 for
-    # the randomness of both: measured ratios 1-1.8).
+    # near-zero gradient into steps of up to its learning rate: the share of
+    # parameters on which the graph run and an eager run differ (by more than
+    # 1e-5) must be no larger than the share on which two eager runs differ
+    # (measured here, with a factor 3 for the randomness of both: ratios 1-2
+    # seen), and no parameter may differ by more than a few Adam steps (4 lr;
+    # up to 0.5 lr seen).  The largest difference itself is too noisy a
+    # statistic to compare between runs (its eager-to-eager value moved 4x).
     scene_e, P_e, ba_e = make()
     scene_e2, P_e2, ba_e2 = make()
     scene_g, P_g, ba_g = make()
@@ -133,8 +136,8 @@ def test_bundle_adjustment_window(R):
         share_ge, share_ee = float((d_ge > 1e-5).float().mean()), float((d_ee > 1e-5).float().mean())
         say(k, f"graph vs eager: max diff {float(d_ge.max()):.3e}, share over 1e-5 {share_ge:.4f}; "
                f"eager vs eager: max diff {float(d_ee.max()):.3e}, share over 1e-5 {share_ee:.4f}")
-        assert float(d_ge.max()) <= 3.0 * float(d_ee.max()) + 1e-6, k
         assert share_ge <= 3.0 * share_ee + 1e-3, k
+        assert float(d_ge.max()) <= 4.0 * R.MAPPING_LR[k], k
     d = float((P_g - P_e).abs().max())
     say("poses graph vs eager max diff", d)
     assert d < 1e-4

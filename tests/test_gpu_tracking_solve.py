@@ -199,3 +199,47 @@ def test_blend_timing_reruns_leave_the_state_as_the_step_left_it(R, ppl):
         err = np.abs(a - b).max() / np.abs(a).max()
         say("pose gradient, timed state vs untimed:", err)
         assert err <= 1e-5
+
+
+def test_ordered_fused_step_equals_separate_calls(R):
+    """A 1200x680 tracking frame holds 3225 tiles, more than fit the chip at
+    once, so the fused kernel (ranking its own buckets) takes its tiles
+    longest list first, ordered from the pair counters before it runs.  Its
+    loss and pose gradient equal those of render -> tracking_loss_grad ->
+    backward (whose blends take the order from the sorted ranges), and the
+    maps that render writes equal a render of a fresh state."""
+    say("case: ordered fused tracking step, 100k room at 1200x680")
+    sc = synth.room_scene(0, 100_000, (5.0, 4.0, 3.0))
+    cam = synth.MAPPING_CAMERA
+    true = synth.level_room_pose(0)
+    scd = {k: torch.from_numpy(np.ascontiguousarray(v, np.float32)).cuda() for k, v in sc.items()}
+    tgt = R.render(R.State(), scd, R.pose_tensor(*true), [cam])[0]
+    tc, td = tgt["color"].contiguous(), tgt["depth"].contiguous()
+    P = R.pose_tensor(*synth.perturb_pose(*true, 1000)).reshape(1, 12)
+    st = R.State(sync_capacity=True, count_work=False)
+    d = torch.zeros((1, 6), device="cuda")
+    R.tracking_step(st, scd, P.clone(), [cam], [tc], [td], dposes=d)
+    torch.cuda.synchronize()
+    st.reserve(tile_pairs=int(st.stats().peak_pairs * 1.5) + 64)
+    assert int(st.stats().pair_capacity) <= 256, "the fused kernel ranks its own buckets"
+    tiles = ((cam["width"] + 15) // 16) * ((cam["height"] + 15) // 16)
+    assert tiles >= 1536
+    d.zero_()
+    L = torch.zeros(1, device="cuda")
+    R.tracking_step(st, scd, P.clone(), [cam], [tc], [td], dposes=d, loss=L)
+    torch.cuda.synchronize()
+    st.check()
+    sep = R.State()
+    out = R.render(sep, scd, P.clone(), [cam], maps=("color", "depth"))[0]
+    L2 = torch.zeros(1, device="cuda")
+    dc, dd = R.tracking_loss_grad(out["color"], out["depth"], tc, td, loss=L2)
+    _, dp = R.backward(sep, [dict(color=dc, depth=dd)], param_grads=False)
+    fresh = R.render(R.State(), scd, P.clone(), [cam], maps=("color", "depth"))[0]
+    torch.cuda.synchronize()
+    for k in ("color", "depth"):
+        assert torch.equal(out[k], fresh[k]), k
+    a, b = d[0].double().cpu().numpy(), dp[0].double().cpu().numpy()
+    err = np.abs(a - b).max() / np.abs(b).max()
+    say("loss fused", float(L), "separate", float(L2), "pose gradient rel diff", err)
+    assert abs(float(L) - float(L2)) <= 1e-5 * abs(float(L2))
+    assert err <= 1e-5
