@@ -621,6 +621,23 @@ class TrackingProblem:
     lr_phi: float = TRACK_LR_PHI
 
 
+_hip_runtime = None
+
+
+def upload_graph(graph: torch.cuda.CUDAGraph):
+    """Uploads a captured graph's executable to the device without running
+    it (hipGraphUpload on the current stream), so that its first replay starts
+    as fast as later ones."""
+    global _hip_runtime
+    if _hip_runtime is None:
+        import ctypes
+        _hip_runtime = ctypes.CDLL("libamdhip64.so.7")   # the HIP runtime torch has loaded
+        _hip_runtime.hipGraphUpload.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    rc = _hip_runtime.hipGraphUpload(graph.raw_cuda_graph_exec(), _stream())
+    if rc != 0:
+        raise RuntimeError(f"hipGraphUpload failed with error {rc}")
+
+
 class TrackingSolver:
     """Sequential tracking (Eq. 20) of one frame: ``iters`` iterations of
     render -> tracking-loss gradient images -> pose-only backward -> Adam +
@@ -720,6 +737,7 @@ class TrackingSolver:
                     for _ in range(self.iters):
                         self._iteration()
             torch.cuda.current_stream().wait_stream(side)
+            upload_graph(self.graph)
             torch.cuda.synchronize()
 
     def run(self):
