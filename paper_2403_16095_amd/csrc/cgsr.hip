@@ -800,12 +800,17 @@ cgsr_status cgsr_time_tracking_blend(cgsr_state* st, int32_t reps, void* stream_
   RasterBufs rb = st->track_rb;
   rb.loss = nullptr;        // the step's loss sum is not added to again
   rb.keep_counts = true;
-  if (rb.sort_here) launch_restore_counts(st->tile_count, st->ranges, st->total_tiles, stream);
   hipEvent_t ev[2] = {nullptr, nullptr};
   HIP_TRY(hipEventCreate(&ev[0]));
   hipError_t e = hipEventCreate(&ev[1]);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    return fail(CGSR_ERR_HIP, "cgsr_time_tracking_blend: %s", hipGetErrorString(e));
+  }
+  // From here on the counters are restored and always reset again below.
+  if (rb.sort_here) launch_restore_counts(st->tile_count, st->ranges, st->total_tiles, stream);
   float ms = 0.f;
-  if (e == hipSuccess) e = hipEventRecord(ev[0], stream);
+  e = hipEventRecord(ev[0], stream);
   for (int r = 0; e == hipSuccess && r < reps; ++r) {
     launch_raster_track(rb, st->track_ppl, stream);
     e = hipGetLastError();
@@ -818,7 +823,7 @@ cgsr_status cgsr_time_tracking_blend(cgsr_state* st, int32_t reps, void* stream_
   if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   (void)hipEventDestroy(ev[0]);
-  if (ev[1]) (void)hipEventDestroy(ev[1]);
+  (void)hipEventDestroy(ev[1]);
   if (e != hipSuccess) return fail(CGSR_ERR_HIP, "cgsr_time_tracking_blend: %s", hipGetErrorString(e));
   *ms_out = ms / (float)reps;
   st->track_rb_ok = true;
