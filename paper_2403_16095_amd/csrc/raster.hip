@@ -296,12 +296,13 @@ __device__ __forceinline__ void forward_tile(const RasterBufs& b, Stage<kTilePix
           const float raw = B.y * __builtin_amdgcn_exp2f(e);
           const bool hit = !f.done[k] && raw >= kAlphaMin;
           const float alpha = fminf(kAlphaMax, raw);
-          const float Tn = f.T[k] * (1.f - alpha);
+          const float wa = alpha * f.T[k];
+          const float Tn = f.T[k] - wa;
           const bool stop = hit && Tn < kTStop;
           const bool blend = hit && !stop;
           f.done[k] = f.done[k] || stop;
           if (kStats) f.evaluated[k] = stop ? loc + j + 1 : f.evaluated[k];
-          const float wgt = blend ? alpha * f.T[k] : 0.f;
+          const float wgt = blend ? wa : 0.f;
           f.C0[k] = __builtin_fmaf(wgt, Cc.x, f.C0[k]);
           f.C1[k] = __builtin_fmaf(wgt, Cc.y, f.C1[k]);
           f.C2[k] = __builtin_fmaf(wgt, Cc.z, f.C2[k]);
@@ -433,10 +434,11 @@ __device__ __forceinline__ int block_max(uint32_t lane_max, uint32_t* s_max) {
 // sums Bx = sum_{k>j} w_k x_k / T_{j+1}, dL/dalpha_j = T_j sum_x g_x (x_j - Bx)
 // = T_j (G_j - Bg) with G_j = sum_x g_x x_j and Bg = sum_x g_x Bx; since every
 // Bx moves one Gaussian forward as Bx <- alpha_j x_j + (1 - alpha_j) Bx and
-// the g_x are fixed per pixel, so does Bg <- alpha_j G_j + (1 - alpha_j) Bg,
-// one running sum for all the quantities x (colour, depth, opacity,
-// uncertainty).  T_j = T_{j+1} / (1 - alpha_j) recovers the transmittance
-// from the final one.
+// the g_x are fixed per pixel, so does Bg <- Bg + alpha_j (G_j - Bg) (one
+// multiply-add on the G_j - Bg that dL/dalpha_j needs anyway), one running
+// sum for all the quantities x (colour, depth, opacity, uncertainty).
+// T_j = T_{j+1} / (1 - alpha_j) recovers the transmittance from the final
+// one.
 // A lane first sums its pixels' contributions to a Gaussian, then the wave
 // reduces all of the Gaussian's gradient terms together (wave_sum_many) and
 // issues one atomic instruction.  kParams adds the opacity and colour
@@ -490,7 +492,7 @@ __device__ __forceinline__ void backward_tile(const RasterBufs& b, Stage<kTilePi
           G = __builtin_fmaf(p.gu[k], dz * dz, G + p.go[k]);
         }
         const float dsum = G - p.Bg[k];
-        p.Bg[k] = __builtin_fmaf(alpha, G, oma * p.Bg[k]);
+        p.Bg[k] = __builtin_fmaf(alpha, dsum, p.Bg[k]);
         const float dalpha = Tj * dsum;
         p.T[k] = Tj;
         const bool live = hit && !(raw > kAlphaMax);   // a capped alpha has no gradient
@@ -511,8 +513,12 @@ __device__ __forceinline__ void backward_tile(const RasterBufs& b, Stage<kTilePi
         acc_fma(sxx, pdx, dx);
         acc_fma(sxy, pdx, dy);
         acc_fma(syy, pdy, dy);
-        acc_fma(gdd, wgt, p.gd[k]);
-        if (!kTrack) gdd += 2.f * wgt * dz * p.gu[k] + ((hit && pos1 == p.med1[k]) ? p.gm[k] : 0.f);
+        if (kTrack) {
+          acc_fma(gdd, wgt, p.gd[k]);
+        } else {
+          acc_fma(gdd, wgt, __builtin_fmaf(2.f * dz, p.gu[k], p.gd[k]));
+          gdd += pos1 == p.med1[k] ? p.gm[k] : 0.f;   // the median entry was blended
+        }
         if (kParams) acc(gop, live ? dalpha * g : 0.f);
         if (kParams || kColor) {
           acc_fma(gr, wgt, p.gc0[k]);
