@@ -391,7 +391,8 @@ __global__ __launch_bounds__(kThreads) void project_kernel(GaussianPtrs g, const
         int owner;
         const uint32_t local = pair_tile(wp, k, cam.tiles_x, &owner);
         const float4 r0 = s_r0[64 * wv + owner], r1 = s_r1[64 * wv + owner];
-        const float ox = (float)((local % (uint32_t)cam.tiles_x) * kTile), oy = (float)((local / (uint32_t)cam.tiles_x) * kTile);
+        const float ox = (float)((local % (uint32_t)cam.tiles_x) * kTile),
+                    oy = (float)((local / (uint32_t)cam.tiles_x) * kTile);
         const float4 A = make_float4((r0.x - ox) + r1.z, (r0.y - oy) + r1.w, (-0.5f * kLog2e) * r0.z, r0.w);
         const float4 B = make_float4((-0.5f * kLog2e) * r1.x, r1.y, 0.f, 0.f);
         tile[j] = cam.tile_base + local;
@@ -430,228 +431,241 @@ __global__ __launch_bounds__(kThreads) void project_backward_kernel(GaussianPtrs
                                                                     ViewTable vt, float* rec_grad,
                                                                     const uint32_t* __restrict__ tiles,
                                                                     GradPtrs dg, int param_grads, int atomic_params,
-                                                                    double* pose_acc, float* dens_grad,
+                                                                    int view_loop, double* pose_acc, float* dens_grad,
                                                                     uint32_t* dens_count) {
-  __shared__ float s_pose[4][6];
-  const int v = blockIdx.y;
+  __shared__ float s_pose[2][4][6];
   const int64_t N = g.n;
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  const int64_t m = (int64_t)v * N + i;
-  float gp[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  if (i < N && tiles[m] != 0u) {
-    float4* gr = reinterpret_cast<float4*>(rec_grad + (int64_t)kGradStride * m);
-    const float4 g0 = gr[0], g1 = gr[1], g2 = gr[2];
-    gr[0] = make_float4(0.f, 0.f, 0.f, 0.f);
-    gr[1] = make_float4(0.f, 0.f, 0.f, 0.f);
-    gr[2] = make_float4(0.f, 0.f, 0.f, 0.f);
-    const float dop = g1.y, dd = g1.z;
-    const ViewInfo cam = vt.io[v].info;
-    const float* P = poses + 12 * v;
-    Proj o;
-    // the record was visible in the forward at this pose, so this holds
-    if (project_core(g, i, P, cam, o)) {
-      // power = -(a t^2 + c' dy^2) / 2 with t = dx + k dy, k = b / a and
-      // c' = c - b^2 / a = 1 / Sigma2d_yy (dx, dy = mu - pixel), so
-      // dpower/dmu = -(a t, a k t + c' dy) and dpower/d(a, b, c) =
-      // -(dx^2 / 2, dx dy, dy^2 / 2).
-      const double qa = o.conic[0], qk = o.conic[1] / o.conic[0], qc = 1.0 / o.cov[2];
-      const float dmux = (float)(-qa * (double)g0.x);
-      const float dmuy = (float)(-(qa * qk * (double)g0.x + qc * (double)g0.y));
-      const float da = -0.5f * g0.z, db = -g0.w, dc = -0.5f * g1.x;
-      if (dens_grad) {
-        atomicAdd(dens_grad + i, sqrtf(dmux * dmux + dmuy * dmuy));
-        atomicAdd(dens_count + i, 1u);
-      }
-      const float x = (float)o.p[0], y = (float)o.p[1], z = (float)o.p[2];
-      const float zinv = 1.0f / z, zinv2 = zinv * zinv;
-      // dL/dSigma2d = -Q dQ Q with the off-diagonal conic entry counted twice.
-      const float a = (float)o.conic[0], b = (float)o.conic[1], c = (float)o.conic[2];
-      const float hb = 0.5f * db;
-      const float QG00 = a * da + b * hb, QG01 = a * hb + b * dc;
-      const float QG10 = b * da + c * hb, QG11 = b * hb + c * dc;
-      const float A00 = -(QG00 * a + QG01 * b);
-      const float A01 = -(QG00 * b + QG01 * c);
-      const float A11 = -(QG10 * b + QG11 * c);
-      // Sigma2d = J Sc J^T: dSc = J^T A J, dJ = 2 A J Sc.
-      const float J00 = (float)o.J00, J02 = (float)o.J02, J11 = (float)o.J11, J12 = (float)o.J12;
-      float dS[6];
-      dS[0] = J00 * J00 * A00;
-      dS[1] = J00 * A01 * J11;
-      dS[2] = J00 * (A00 * J02 + A01 * J12);
-      dS[3] = J11 * J11 * A11;
-      dS[4] = J11 * (A01 * J02 + A11 * J12);
-      dS[5] = J02 * J02 * A00 + 2.f * J02 * J12 * A01 + J12 * J12 * A11;
-      float S[6];
+  // view_loop: a lane walks its Gaussian's records of every view, so it owns
+  // the Gaussian's parameter gradients and adds to them without atomics;
+  // otherwise blockIdx.y is the view.
+  const int v_begin = view_loop ? 0 : (int)blockIdx.y;
+  const int v_end = view_loop ? vt.n : v_begin + 1;
+  for (int v = v_begin; v < v_end; ++v) {
+    const int64_t m = (int64_t)v * N + i;
+    float gp[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (i < N && tiles[m] != 0u) {
+      float4* gr = reinterpret_cast<float4*>(rec_grad + (int64_t)kGradStride * m);
+      const float4 g0 = gr[0], g1 = gr[1], g2 = gr[2];
+      gr[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+      gr[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+      gr[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+      const float dop = g1.y, dd = g1.z;
+      const ViewInfo cam = vt.io[v].info;
+      const float* P = poses + 12 * v;
+      Proj o;
+      // the record was visible in the forward at this pose, so this holds
+      if (project_core(g, i, P, cam, o)) {
+        // power = -(a t^2 + c' dy^2) / 2 with t = dx + k dy, k = b / a and
+        // c' = c - b^2 / a = 1 / Sigma2d_yy (dx, dy = mu - pixel), so
+        // dpower/dmu = -(a t, a k t + c' dy) and dpower/d(a, b, c) =
+        // -(dx^2 / 2, dx dy, dy^2 / 2).
+        const double qa = o.conic[0], qk = o.conic[1] / o.conic[0], qc = 1.0 / o.cov[2];
+        const float dmux = (float)(-qa * (double)g0.x);
+        const float dmuy = (float)(-(qa * qk * (double)g0.x + qc * (double)g0.y));
+        const float da = -0.5f * g0.z, db = -g0.w, dc = -0.5f * g1.x;
+        if (dens_grad) {
+          atomicAdd(dens_grad + i, sqrtf(dmux * dmux + dmuy * dmuy));
+          atomicAdd(dens_count + i, 1u);
+        }
+        const float x = (float)o.p[0], y = (float)o.p[1], z = (float)o.p[2];
+        const float zinv = 1.0f / z, zinv2 = zinv * zinv;
+        // dL/dSigma2d = -Q dQ Q with the off-diagonal conic entry counted twice.
+        const float a = (float)o.conic[0], b = (float)o.conic[1], c = (float)o.conic[2];
+        const float hb = 0.5f * db;
+        const float QG00 = a * da + b * hb, QG01 = a * hb + b * dc;
+        const float QG10 = b * da + c * hb, QG11 = b * hb + c * dc;
+        const float A00 = -(QG00 * a + QG01 * b);
+        const float A01 = -(QG00 * b + QG01 * c);
+        const float A11 = -(QG10 * b + QG11 * c);
+        // Sigma2d = J Sc J^T: dSc = J^T A J, dJ = 2 A J Sc.
+        const float J00 = (float)o.J00, J02 = (float)o.J02, J11 = (float)o.J11, J12 = (float)o.J12;
+        float dS[6];
+        dS[0] = J00 * J00 * A00;
+        dS[1] = J00 * A01 * J11;
+        dS[2] = J00 * (A00 * J02 + A01 * J12);
+        dS[3] = J11 * J11 * A11;
+        dS[4] = J11 * (A01 * J02 + A11 * J12);
+        dS[5] = J02 * J02 * A00 + 2.f * J02 * J12 * A01 + J12 * J12 * A11;
+        float S[6];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) S[k] = (float)o.Sc[k];
-      // (J Sc) rows
-      const float JS00 = J00 * S[0] + J02 * S[2], JS02 = J00 * S[2] + J02 * S[5];
-      const float JS11 = J11 * S[3] + J12 * S[4], JS12 = J11 * S[4] + J12 * S[5];
-      const float JS01 = J00 * S[1] + J02 * S[4], JS10 = J11 * S[1] + J12 * S[2];
-      const float dJ00 = 2.f * (A00 * JS00 + A01 * JS10);
-      const float dJ02 = 2.f * (A00 * JS02 + A01 * JS12);
-      const float dJ11 = 2.f * (A01 * JS01 + A11 * JS11);
-      const float dJ12 = 2.f * (A01 * JS02 + A11 * JS12);
-      // Camera-space mean.
-      float dp0 = dmux * cam.fx * zinv;
-      float dp1 = dmuy * cam.fy * zinv;
-      float dp2 = -(dmux * cam.fx * x + dmuy * cam.fy * y) * zinv2 + dd;
-      dp2 -= (dJ00 * cam.fx + dJ11 * cam.fy) * zinv2;
-      if (o.clampx == 0) {
-        dp0 -= dJ02 * cam.fx * zinv2;
-        dp2 += dJ02 * 2.f * cam.fx * x * zinv2 * zinv;
-      } else {
-        dp2 += dJ02 * cam.fx * o.tx * zinv2;
-      }
-      if (o.clampy == 0) {
-        dp1 -= dJ12 * cam.fy * zinv2;
-        dp2 += dJ12 * 2.f * cam.fy * y * zinv2 * zinv;
-      } else {
-        dp2 += dJ12 * cam.fy * o.ty * zinv2;
-      }
-      // View-dependent colour: colour_c = max(0, sum_k sh_kc Y_k(d) + 1/2),
-      // d = v / |v|, v = X - C, C = -R^T t.  dL/dv = (I - d d^T) dL/dd / |v|
-      // reaches the mean (+dL/dv) and the camera centre (-dL/dv); C moves to
-      // C - R^T rho under exp(xi^) T, so dL/drho gains R dL/dv.
-      float dv[3] = {0.f, 0.f, 0.f};
-      if (g.sh) {
-        ShColour sc;
-        sh_colour(g, i, P, sc);
-        const float gcol[3] = {g1.w, g2.x, g2.y};
-        float dc[3];
+        for (int k = 0; k < 6; ++k) S[k] = (float)o.Sc[k];
+        // (J Sc) rows
+        const float JS00 = J00 * S[0] + J02 * S[2], JS02 = J00 * S[2] + J02 * S[5];
+        const float JS11 = J11 * S[3] + J12 * S[4], JS12 = J11 * S[4] + J12 * S[5];
+        const float JS01 = J00 * S[1] + J02 * S[4], JS10 = J11 * S[1] + J12 * S[2];
+        const float dJ00 = 2.f * (A00 * JS00 + A01 * JS10);
+        const float dJ02 = 2.f * (A00 * JS02 + A01 * JS12);
+        const float dJ11 = 2.f * (A01 * JS01 + A11 * JS11);
+        const float dJ12 = 2.f * (A01 * JS02 + A11 * JS12);
+        // Camera-space mean.
+        float dp0 = dmux * cam.fx * zinv;
+        float dp1 = dmuy * cam.fy * zinv;
+        float dp2 = -(dmux * cam.fx * x + dmuy * cam.fy * y) * zinv2 + dd;
+        dp2 -= (dJ00 * cam.fx + dJ11 * cam.fy) * zinv2;
+        if (o.clampx == 0) {
+          dp0 -= dJ02 * cam.fx * zinv2;
+          dp2 += dJ02 * 2.f * cam.fx * x * zinv2 * zinv;
+        } else {
+          dp2 += dJ02 * cam.fx * o.tx * zinv2;
+        }
+        if (o.clampy == 0) {
+          dp1 -= dJ12 * cam.fy * zinv2;
+          dp2 += dJ12 * 2.f * cam.fy * y * zinv2 * zinv;
+        } else {
+          dp2 += dJ12 * cam.fy * o.ty * zinv2;
+        }
+        // View-dependent colour: colour_c = max(0, sum_k sh_kc Y_k(d) + 1/2),
+        // d = v / |v|, v = X - C, C = -R^T t.  dL/dv = (I - d d^T) dL/dd / |v|
+        // reaches the mean (+dL/dv) and the camera centre (-dL/dv); C moves to
+        // C - R^T rho under exp(xi^) T, so dL/drho gains R dL/dv.
+        float dv[3] = {0.f, 0.f, 0.f};
+        if (g.sh) {
+          ShColour sc;
+          sh_colour(g, i, P, sc);
+          const float gcol[3] = {g1.w, g2.x, g2.y};
+          float dc[3];
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) dc[ch] = sc.clamped[ch] ? 0.f : gcol[ch];
-        const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
-        float w[16];
+          for (int ch = 0; ch < 3; ++ch) dc[ch] = sc.clamped[ch] ? 0.f : gcol[ch];
+          const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
+          float w[16];
 #pragma unroll
-        for (int k = 0; k < 16; ++k)
-          w[k] = k < K ? dc[0] * sc.c[3 * k] + dc[1] * sc.c[3 * k + 1] + dc[2] * sc.c[3 * k + 2] : 0.f;
-        const float3 gd = sh_grad(g.sh_degree, sc.d[0], sc.d[1], sc.d[2], w);
-        const float dot = gd.x * sc.d[0] + gd.y * sc.d[1] + gd.z * sc.d[2];
-        dv[0] = (gd.x - sc.d[0] * dot) * sc.inv_len;
-        dv[1] = (gd.y - sc.d[1] * dot) * sc.inv_len;
-        dv[2] = (gd.z - sc.d[2] * dot) * sc.inv_len;
-        if (param_grads && dg.sh) {
-          float* out = dg.sh + (int64_t)3 * K * i;
-          if (!atomic_params && sh_vector(dg.sh, K)) {
-            // 16-byte read-modify-writes of the Gaussian's block (48 scalar
-            // ones took 49 of the 114 us of a 500k-Gaussian degree-3 view)
-            float4* o4 = reinterpret_cast<float4*>(out);
+          for (int k = 0; k < 16; ++k)
+            w[k] = k < K ? dc[0] * sc.c[3 * k] + dc[1] * sc.c[3 * k + 1] + dc[2] * sc.c[3 * k + 2] : 0.f;
+          const float3 gd = sh_grad(g.sh_degree, sc.d[0], sc.d[1], sc.d[2], w);
+          const float dot = gd.x * sc.d[0] + gd.y * sc.d[1] + gd.z * sc.d[2];
+          dv[0] = (gd.x - sc.d[0] * dot) * sc.inv_len;
+          dv[1] = (gd.y - sc.d[1] * dot) * sc.inv_len;
+          dv[2] = (gd.z - sc.d[2] * dot) * sc.inv_len;
+          if (param_grads && dg.sh) {
+            float* out = dg.sh + (int64_t)3 * K * i;
+            if (!atomic_params && sh_vector(dg.sh, K)) {
+              // 16-byte read-modify-writes of the Gaussian's block (48 scalar
+              // ones took 49 of the 114 us of a 500k-Gaussian degree-3 view)
+              float4* o4 = reinterpret_cast<float4*>(out);
 #pragma unroll
-            for (int q = 0; q < 12; ++q) {
-              if (4 * q < 3 * K) {
-                float4 v = o4[q];
-                v.x += dc[(4 * q) % 3] * sc.Y[(4 * q) / 3];
-                v.y += dc[(4 * q + 1) % 3] * sc.Y[(4 * q + 1) / 3];
-                v.z += dc[(4 * q + 2) % 3] * sc.Y[(4 * q + 2) / 3];
-                v.w += dc[(4 * q + 3) % 3] * sc.Y[(4 * q + 3) / 3];
-                o4[q] = v;
+              for (int q = 0; q < 12; ++q) {
+                if (4 * q < 3 * K) {
+                  float4 v = o4[q];
+                  v.x += dc[(4 * q) % 3] * sc.Y[(4 * q) / 3];
+                  v.y += dc[(4 * q + 1) % 3] * sc.Y[(4 * q + 1) / 3];
+                  v.z += dc[(4 * q + 2) % 3] * sc.Y[(4 * q + 2) / 3];
+                  v.w += dc[(4 * q + 3) % 3] * sc.Y[(4 * q + 3) / 3];
+                  o4[q] = v;
+                }
               }
-            }
-          } else {
+            } else {
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
-              if (k < K) {
+              for (int k = 0; k < 16; ++k) {
+                if (k < K) {
 #pragma unroll
-                for (int ch = 0; ch < 3; ++ch) {
-                  const float val = dc[ch] * sc.Y[k];
-                  if (atomic_params) unsafeAtomicAdd(out + 3 * k + ch, val);
-                  else out[3 * k + ch] += val;
+                  for (int ch = 0; ch < 3; ++ch) {
+                    const float val = dc[ch] * sc.Y[k];
+                    if (atomic_params) unsafeAtomicAdd(out + 3 * k + ch, val);
+                    else out[3 * k + ch] += val;
+                  }
                 }
               }
             }
           }
         }
-      }
-      if (param_grads) {
-        // Means: p = W X + t.
-        float dX[3];
+        if (param_grads) {
+          // Means: p = W X + t.
+          float dX[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) dX[k] = P[k] * dp0 + P[3 + k] * dp1 + P[6 + k] * dp2;
-        // dSigma = W^T dSc W (symmetric, full 3x3 for the products below).
-        const float dSf[9] = {dS[0], dS[1], dS[2], dS[1], dS[3], dS[4], dS[2], dS[4], dS[5]};
-        float T1[9], dSig[9];
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-          for (int cc = 0; cc < 3; ++cc)
-            T1[3 * r + cc] = P[r] * dSf[cc] + P[3 + r] * dSf[3 + cc] + P[6 + r] * dSf[6 + cc];
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-          for (int cc = 0; cc < 3; ++cc)
-            dSig[3 * r + cc] = T1[3 * r] * P[cc] + T1[3 * r + 1] * P[3 + cc] + T1[3 * r + 2] * P[6 + cc];
-        // Sigma = sum_k s_k^2 r_k r_k^T.
-        float dls[3], dR[9];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          float quad = 0.f;
+          for (int k = 0; k < 3; ++k) dX[k] = P[k] * dp0 + P[3 + k] * dp1 + P[6 + k] * dp2;
+          // dSigma = W^T dSc W (symmetric, full 3x3 for the products below).
+          const float dSf[9] = {dS[0], dS[1], dS[2], dS[1], dS[3], dS[4], dS[2], dS[4], dS[5]};
+          float T1[9], dSig[9];
 #pragma unroll
           for (int r = 0; r < 3; ++r)
 #pragma unroll
-            for (int cc = 0; cc < 3; ++cc) quad += o.R[3 * r + k] * dSig[3 * r + cc] * o.R[3 * cc + k];
-          dls[k] = 2.f * o.s[k] * o.s[k] * quad;
+            for (int cc = 0; cc < 3; ++cc)
+              T1[3 * r + cc] = P[r] * dSf[cc] + P[3 + r] * dSf[3 + cc] + P[6 + r] * dSf[6 + cc];
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc)
+              dSig[3 * r + cc] = T1[3 * r] * P[cc] + T1[3 * r + 1] * P[3 + cc] + T1[3 * r + 2] * P[6 + cc];
+          // Sigma = sum_k s_k^2 r_k r_k^T.
+          float dls[3], dR[9];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            float quad = 0.f;
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+              for (int cc = 0; cc < 3; ++cc) quad += o.R[3 * r + k] * dSig[3 * r + cc] * o.R[3 * cc + k];
+            dls[k] = 2.f * o.s[k] * o.s[k] * quad;
+          }
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc)
+              dR[3 * r + cc] =
+                  2.f * (dSig[3 * r] * o.R[cc] + dSig[3 * r + 1] * o.R[3 + cc] + dSig[3 * r + 2] * o.R[6 + cc]) *
+                  o.s[cc] * o.s[cc];
+          const float w = o.qn[0], qx = o.qn[1], qy = o.qn[2], qz = o.qn[3];
+          float dq[4];
+          dq[0] = 2.f * (-qz * dR[1] + qy * dR[2] + qz * dR[3] - qx * dR[5] - qy * dR[6] + qx * dR[7]);
+          dq[1] = 2.f * (qy * dR[1] + qz * dR[2] + qy * dR[3] - 2.f * qx * dR[4] - w * dR[5] + qz * dR[6] + w * dR[7] -
+                         2.f * qx * dR[8]);
+          dq[2] = 2.f * (-2.f * qy * dR[0] + qx * dR[1] + w * dR[2] + qx * dR[3] + qz * dR[5] - w * dR[6] + qz * dR[7] -
+                         2.f * qy * dR[8]);
+          dq[3] = 2.f * (-2.f * qz * dR[0] - w * dR[1] + qx * dR[2] + w * dR[3] - 2.f * qz * dR[4] + qy * dR[5] +
+                         qx * dR[6] + qy * dR[7]);
+          const float dotq = o.qn[0] * dq[0] + o.qn[1] * dq[1] + o.qn[2] * dq[2] + o.qn[3] * dq[3];
+          const float dlogit = dop * o.opacity * (1.f - o.opacity);
+          float* outs[5] = {dg.means, dg.log_scales, dg.quats, dg.opacity_logits, dg.rgb};
+          float vals_mean[3] = {dX[0], dX[1], dX[2]};
+          auto put = [&](float* base, int64_t idx, float val) {
+            if (!base) return;
+            if (atomic_params) unsafeAtomicAdd(base + idx, val);
+            else base[idx] += val;
+          };
+          for (int k = 0; k < 3; ++k) vals_mean[k] += dv[k];
+          for (int k = 0; k < 3; ++k) put(outs[0], 3 * i + k, vals_mean[k]);
+          for (int k = 0; k < 3; ++k) put(outs[1], 3 * i + k, dls[k]);
+          for (int k = 0; k < 4; ++k) put(outs[2], 4 * i + k, (dq[k] - o.qn[k] * dotq) * o.qinv);
+          put(outs[3], i, dlogit);
+          if (!g.sh) {
+            put(outs[4], 3 * i + 0, g1.w);
+            put(outs[4], 3 * i + 1, g2.x);
+            put(outs[4], 3 * i + 2, g2.y);
+          }
         }
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-          for (int cc = 0; cc < 3; ++cc)
-            dR[3 * r + cc] = 2.f * (dSig[3 * r] * o.R[cc] + dSig[3 * r + 1] * o.R[3 + cc] + dSig[3 * r + 2] * o.R[6 + cc]) *
-                             o.s[cc] * o.s[cc];
-        const float w = o.qn[0], qx = o.qn[1], qy = o.qn[2], qz = o.qn[3];
-        float dq[4];
-        dq[0] = 2.f * (-qz * dR[1] + qy * dR[2] + qz * dR[3] - qx * dR[5] - qy * dR[6] + qx * dR[7]);
-        dq[1] = 2.f * (qy * dR[1] + qz * dR[2] + qy * dR[3] - 2.f * qx * dR[4] - w * dR[5] + qz * dR[6] + w * dR[7] -
-                       2.f * qx * dR[8]);
-        dq[2] = 2.f * (-2.f * qy * dR[0] + qx * dR[1] + w * dR[2] + qx * dR[3] + qz * dR[5] - w * dR[6] + qz * dR[7] -
-                       2.f * qy * dR[8]);
-        dq[3] = 2.f * (-2.f * qz * dR[0] - w * dR[1] + qx * dR[2] + w * dR[3] - 2.f * qz * dR[4] + qy * dR[5] +
-                       qx * dR[6] + qy * dR[7]);
-        const float dotq = o.qn[0] * dq[0] + o.qn[1] * dq[1] + o.qn[2] * dq[2] + o.qn[3] * dq[3];
-        const float dlogit = dop * o.opacity * (1.f - o.opacity);
-        float* outs[5] = {dg.means, dg.log_scales, dg.quats, dg.opacity_logits, dg.rgb};
-        float vals_mean[3] = {dX[0], dX[1], dX[2]};
-        auto put = [&](float* base, int64_t idx, float val) {
-          if (!base) return;
-          if (atomic_params) unsafeAtomicAdd(base + idx, val);
-          else base[idx] += val;
+        // Pose, left perturbation: drho = dp; dphi = p x dp + 2 vee(skew(Sc dSc)).
+        const float Sf[9] = {S[0], S[1], S[2], S[1], S[3], S[4], S[2], S[4], S[5]};
+        const float dSf[9] = {dS[0], dS[1], dS[2], dS[1], dS[3], dS[4], dS[2], dS[4], dS[5]};
+        auto Mrc = [&](int r, int cc) {
+          return Sf[3 * r] * dSf[cc] + Sf[3 * r + 1] * dSf[3 + cc] + Sf[3 * r + 2] * dSf[6 + cc];
         };
-        for (int k = 0; k < 3; ++k) vals_mean[k] += dv[k];
-        for (int k = 0; k < 3; ++k) put(outs[0], 3 * i + k, vals_mean[k]);
-        for (int k = 0; k < 3; ++k) put(outs[1], 3 * i + k, dls[k]);
-        for (int k = 0; k < 4; ++k) put(outs[2], 4 * i + k, (dq[k] - o.qn[k] * dotq) * o.qinv);
-        put(outs[3], i, dlogit);
-        if (!g.sh) {
-          put(outs[4], 3 * i + 0, g1.w);
-          put(outs[4], 3 * i + 1, g2.x);
-          put(outs[4], 3 * i + 2, g2.y);
-        }
+        gp[0] = dp0 + P[0] * dv[0] + P[1] * dv[1] + P[2] * dv[2];
+        gp[1] = dp1 + P[3] * dv[0] + P[4] * dv[1] + P[5] * dv[2];
+        gp[2] = dp2 + P[6] * dv[0] + P[7] * dv[1] + P[8] * dv[2];
+        gp[3] = y * dp2 - z * dp1 + 2.f * (Mrc(1, 2) - Mrc(2, 1));
+        gp[4] = z * dp0 - x * dp2 + 2.f * (Mrc(2, 0) - Mrc(0, 2));
+        gp[5] = x * dp1 - y * dp0 + 2.f * (Mrc(0, 1) - Mrc(1, 0));
       }
-      // Pose, left perturbation: drho = dp; dphi = p x dp + 2 vee(skew(Sc dSc)).
-      const float Sf[9] = {S[0], S[1], S[2], S[1], S[3], S[4], S[2], S[4], S[5]};
-      const float dSf[9] = {dS[0], dS[1], dS[2], dS[1], dS[3], dS[4], dS[2], dS[4], dS[5]};
-      auto Mrc = [&](int r, int cc) { return Sf[3 * r] * dSf[cc] + Sf[3 * r + 1] * dSf[3 + cc] + Sf[3 * r + 2] * dSf[6 + cc]; };
-      gp[0] = dp0 + P[0] * dv[0] + P[1] * dv[1] + P[2] * dv[2];
-      gp[1] = dp1 + P[3] * dv[0] + P[4] * dv[1] + P[5] * dv[2];
-      gp[2] = dp2 + P[6] * dv[0] + P[7] * dv[1] + P[8] * dv[2];
-      gp[3] = y * dp2 - z * dp1 + 2.f * (Mrc(1, 2) - Mrc(2, 1));
-      gp[4] = z * dp0 - x * dp2 + 2.f * (Mrc(2, 0) - Mrc(0, 2));
-      gp[5] = x * dp1 - y * dp0 + 2.f * (Mrc(0, 1) - Mrc(1, 0));
     }
-  }
-  if (!pose_acc) return;
-  // Workgroup reduction of the six pose terms, then one double atomic each;
-  // pose_finalize_kernel hands the sums to the caller.
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (pose_acc) {
+      // Workgroup reduction of the six pose terms, then one double atomic each;
+      // pose_finalize_kernel hands the sums to the caller.  Views alternate
+      // between two LDS slots, so the next view's writes cannot meet this
+      // view's reads.
+      float (*sp)[6] = s_pose[v & 1];
+      const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    const float t = wave_sum(gp[k]);
-    if (lane == 0) s_pose[w][k] = t;
-  }
-  __syncthreads();
-  if (threadIdx.x < 6) {
-    const float t = s_pose[0][threadIdx.x] + s_pose[1][threadIdx.x] + s_pose[2][threadIdx.x] + s_pose[3][threadIdx.x];
-    if (t != 0.f) atomicAdd(pose_acc + 6 * v + threadIdx.x, (double)t);
+      for (int k = 0; k < 6; ++k) {
+        const float t = wave_sum(gp[k]);
+        if (lane == 0) sp[w][k] = t;
+      }
+      __syncthreads();
+      if (threadIdx.x < 6) {
+        const float t = sp[0][threadIdx.x] + sp[1][threadIdx.x] + sp[2][threadIdx.x] + sp[3][threadIdx.x];
+        if (t != 0.f) atomicAdd(pose_acc + 6 * v + threadIdx.x, (double)t);
+      }
+    }
   }
 }
 
@@ -682,10 +696,14 @@ void launch_project_backward(const GaussianPtrs& g, const float* poses, const Vi
                              const uint32_t* tiles, const GradPtrs& dg, bool param_grads, double* pose_acc,
                              float* dposes, const PoseStep* step, float* dens_grad, uint32_t* dens_count,
                              hipStream_t s) {
-  const dim3 grid((unsigned)std::max<int64_t>(1, (g.n + kThreads - 1) / kThreads), (unsigned)vt.n);
+  // Several views with parameter gradients: one lane per Gaussian over all
+  // views (no atomics on the parameter gradients); else one grid row per view.
+  const bool view_loop = param_grads && vt.n > 1;
+  const dim3 grid((unsigned)std::max<int64_t>(1, (g.n + kThreads - 1) / kThreads), view_loop ? 1u : (unsigned)vt.n);
   const bool pose = dposes || step;
   hipLaunchKernelGGL(project_backward_kernel, grid, dim3(kThreads), 0, s, g, poses, vt, rec_grad, tiles, dg,
-                     param_grads ? 1 : 0, vt.n > 1 ? 1 : 0, pose ? pose_acc : nullptr, dens_grad, dens_count);
+                     param_grads ? 1 : 0, (vt.n > 1 && !view_loop) ? 1 : 0, view_loop ? 1 : 0,
+                     pose ? pose_acc : nullptr, dens_grad, dens_count);
   if (pose)
     hipLaunchKernelGGL(pose_finalize_kernel, dim3((unsigned)vt.n), dim3(64), 0, s, pose_acc, dposes,
                        step ? step->poses : nullptr, step ? step->adam : nullptr,
