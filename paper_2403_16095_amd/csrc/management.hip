@@ -359,7 +359,8 @@ hipError_t run_ranked(const Op& op, int64_t n, uint32_t* totals_host, hipStream_
   hipLaunchKernelGGL(ranked_scan_kernel<kRankKinds>, dim3(1), dim3(kScanThreads), 0, s, r);
   hipLaunchKernelGGL(ranked_emit_kernel<Op>, dim3((unsigned)blocks), dim3(kThreads), 0, s, op, n, r);
   e = hipGetLastError();
-  if (e == hipSuccess) e = hipMemcpyAsync(totals_host, r.totals, sizeof(uint32_t) * kRankKinds, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(totals_host, r.totals, sizeof(uint32_t) * kRankKinds, hipMemcpyDeviceToHost, s);
   const hipError_t f = hipFreeAsync(buf, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   return e != hipSuccess ? e : f;
