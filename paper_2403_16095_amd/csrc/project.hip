@@ -655,11 +655,9 @@ __global__ __launch_bounds__(kThreads) void project_backward_kernel(GaussianPtrs
       // view's reads.
       float (*sp)[6] = s_pose[v & 1];
       const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        const float t = wave_sum(gp[k]);
-        if (lane == 0) sp[w][k] = t;
-      }
+      const float t6 = wave_sum_many<8>(gp);
+      const int idx = reduced_value_index<8>(lane);
+      if ((lane & 7) == 0 && idx < 6) sp[w][idx] = t6;
       __syncthreads();
       if (threadIdx.x < 6) {
         const float t = sp[0][threadIdx.x] + sp[1][threadIdx.x] + sp[2][threadIdx.x] + sp[3][threadIdx.x];
@@ -696,9 +694,10 @@ void launch_project_backward(const GaussianPtrs& g, const float* poses, const Vi
                              const uint32_t* tiles, const GradPtrs& dg, bool param_grads, double* pose_acc,
                              float* dposes, const PoseStep* step, float* dens_grad, uint32_t* dens_count,
                              hipStream_t s) {
-  // Several views with parameter gradients: one lane per Gaussian over all
-  // views (no atomics on the parameter gradients); else one grid row per view.
-  const bool view_loop = param_grads && vt.n > 1;
+  // Several views: one lane per Gaussian over all views (no atomics on the
+  // parameter gradients, one workgroup per Gaussian block instead of one per
+  // (view, block)); one view: one grid row.
+  const bool view_loop = vt.n > 1;
   const dim3 grid((unsigned)std::max<int64_t>(1, (g.n + kThreads - 1) / kThreads), view_loop ? 1u : (unsigned)vt.n);
   const bool pose = dposes || step;
   hipLaunchKernelGGL(project_backward_kernel, grid, dim3(kThreads), 0, s, g, poses, vt, rec_grad, tiles, dg,
