@@ -416,6 +416,7 @@ template <int kPPL>
 struct BwdPix {
   float fx[kPPL], fy[kPPL], T[kPPL], gc0[kPPL], gc1[kPPL], gc2[kPPL], gd[kPPL], go[kPPL], gm[kPPL], gu[kPPL],
       dobs[kPPL];
+  float gu2[kPPL];   // 2 gu
   float Bg[kPPL];   // sum_x g_x Bx, the behind sums weighted by the pixel's upstream gradients
   int walked[kPPL], med1[kPPL];   // one past the last blended entry's / the median's position (0: none)
 };
@@ -496,7 +497,8 @@ __device__ __forceinline__ void backward_tile(const RasterBufs& b, Stage<kTilePi
         const float dalpha = Tj * dsum;
         p.T[k] = Tj;
         const bool live = hit && !(raw > kAlphaMax);   // a capped alpha has no gradient
-        const float dpower = live ? dalpha * raw : 0.f;   // alpha = opacity * exp(power)
+        const float dlive = live ? dalpha : 0.f;
+        const float dpower = dlive * raw;   // alpha = opacity * exp(power)
         // power = -(a dx^2 + 2 b dx dy + c dy^2) / 2 = ln2 (qa t^2 + qc dy^2)
         // with t = dx + k dy, so d power/d mu = 2 ln2 (qa t, qa k t + qc dy)
         // and d power/d(a, b, c) = -(dx^2 / 2, dx dy, dy^2 / 2).  These are
@@ -516,10 +518,10 @@ __device__ __forceinline__ void backward_tile(const RasterBufs& b, Stage<kTilePi
         if (kTrack) {
           acc_fma(gdd, wgt, p.gd[k]);
         } else {
-          acc_fma(gdd, wgt, __builtin_fmaf(2.f * dz, p.gu[k], p.gd[k]));
+          acc_fma(gdd, wgt, __builtin_fmaf(dz, p.gu2[k], p.gd[k]));
           gdd += pos1 == p.med1[k] ? p.gm[k] : 0.f;   // the median entry was blended
         }
-        if (kParams) acc(gop, live ? dalpha * g : 0.f);
+        if (kParams) acc(gop, dlive * g);
         if (kParams || kColor) {
           acc_fma(gr, wgt, p.gc0[k]);
           acc_fma(gg, wgt, p.gc1[k]);
@@ -591,7 +593,7 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
     p.T[k] = 1.f;
     p.walked[k] = 0;
     p.med1[k] = 0;
-    p.gc0[k] = p.gc1[k] = p.gc2[k] = p.gd[k] = p.go[k] = p.gm[k] = p.gu[k] = p.dobs[k] = 0.f;
+    p.gc0[k] = p.gc1[k] = p.gc2[k] = p.gd[k] = p.go[k] = p.gm[k] = p.gu[k] = p.dobs[k] = p.gu2[k] = 0.f;
     p.Bg[k] = 0.f;
     if (pc.inside) {
       const uint4 ps = b.pixel_state[cam.pixel_base + pix];
@@ -614,6 +616,7 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
         if (io.g_opacity) p.go[k] = io.g_opacity[pix];
         if (io.g_median) p.gm[k] = io.g_median[pix];
         if (io.g_uncertainty) p.gu[k] = io.g_uncertainty[pix];
+        p.gu2[k] = 2.f * p.gu[k];
         if (io.depth_obs) p.dobs[k] = io.depth_obs[pix];
       }
       lane_max = max(lane_max, (uint32_t)p.walked[k]);
@@ -695,7 +698,7 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_track_kernel(Raster
       p.gc1[k] = g[k][1];
       p.gc2[k] = g[k][2];
       p.gd[k] = g[k][3];
-      p.go[k] = p.gm[k] = p.gu[k] = p.dobs[k] = 0.f;
+      p.go[k] = p.gm[k] = p.gu[k] = p.dobs[k] = p.gu2[k] = 0.f;
       p.Bg[k] = 0.f;
       lane_max = max(lane_max, (uint32_t)p.walked[k]);
     }
