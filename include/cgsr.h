@@ -176,7 +176,11 @@ cgsr_status cgsr_state_destroy(cgsr_state *st);
  * (the (tile, Gaussian) pairs of one tile: every tile gets a bucket of that
  * many, so max_tiles x max_tile_pairs must stay below 2^32); never
  * shrinks.  Allocation happens here, so a render whose sizes fit does not
- * allocate and can be captured into a HIP graph. */
+ * allocate and can be captured into a HIP graph.  A captured graph reads the
+ * table of cameras and image pointers the state holds when it replays; a call
+ * on the same state with other cameras or images rewrites that table, so
+ * replay after a call with the graph's own cameras and images, or keep one
+ * state per captured loop. */
 cgsr_status cgsr_state_reserve(cgsr_state *st, int64_t max_records, int64_t max_pixels,
                                int64_t max_tiles, int64_t max_tile_pairs);
 

@@ -83,6 +83,11 @@ struct cgsr_state {
   uint2* ranges = nullptr;
   uint32_t* tile_order = nullptr;   // tiles by descending list length, for the blends
   bool order_ok = false;            // tile_order holds the last render's order
+  // tile_order holds the order a fused tracking step of track_order_tiles
+  // tiles took from the previous step's lengths, and nothing has overwritten it
+  bool track_order_ok = false;
+  int32_t track_order_tiles = 0;
+  unsigned long long order_capture = 0;   // the graph capture that last computed it
   bool tiles_dirty = false;   // a render stopped between projection and sort
   // per-tile buckets of pairs, [bucket_tiles][cap_tile_pairs]
   uint64_t* keys[2] = {nullptr, nullptr};
@@ -209,6 +214,7 @@ cgsr_status reserve(cgsr_state* st, int64_t records, int64_t pixels, int64_t til
     dev_free(st->tile_order);
     st->cap_tiles = 0;
     st->order_ok = false;
+    st->track_order_ok = false;
     if ((s = dev_alloc(&st->ranges, tiles))) return s;
     if ((s = dev_alloc(&st->tile_order, tiles))) return s;
     if ((s = dev_alloc(&st->tile_count, tiles * kTileCounterStride))) return s;
@@ -547,10 +553,16 @@ cgsr_status render_impl(cgsr_state* st, const RenderArgs& a, hipStream_t stream)
   // A fused tracking step whose buckets hold at most one key per thread of
   // its blend sorts each bucket inside the blend: one launch fewer.
   const bool sort_here = a.track && a.fused && st->cap_tile_pairs <= kTilePixels / st->settings.fwd_pixels_per_lane;
-  // The blends take the tiles longest list first.  A fused tracking step
-  // orders them from the pair counters only when its launch holds more tiles
-  // than fit the chip at once (a frame of 640x480 fits: its order would only
-  // add a launch).
+  // The blends take the tiles longest list first.  A fused tracking step with
+  // more tiles than fit the chip at once orders them from this render's pair
+  // counters, in a launch of its own.  One with fewer (all its tiles resident
+  // from the start, where the order only spreads the long lists over the
+  // CUs) takes them by the lengths the previous step left in the ranges:
+  // steps follow one another with a pose that moves little, so the order is
+  // computed by every eager step but only by the first such step of a graph
+  // capture, and a captured solve pays for it once per replay.  Whatever the
+  // lengths read, the order is a permutation of the step's tiles, and any
+  // order gives every tile the same result.
   st->order_ok = false;
   const bool order = st->total_tiles < kOrderMaxTiles;
   if (!sort_here) {
@@ -558,10 +570,26 @@ cgsr_status render_impl(cgsr_state* st, const RenderArgs& a, hipStream_t stream)
     if (order) launch_tile_order(st->ranges, nullptr, st->total_tiles, st->tile_order, stream);
     HIP_TRY(hipGetLastError());
     st->order_ok = order;
+    st->track_order_ok = false;
   } else if (order && st->total_tiles >= kOrderMinTiles) {
     launch_tile_order(nullptr, st->tile_count, st->total_tiles, st->tile_order, stream);
     HIP_TRY(hipGetLastError());
     st->order_ok = true;
+    st->track_order_ok = false;
+  } else if (order) {
+    bool fresh = true;
+    if (in_capture) {
+      unsigned long long id = 0;
+      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+      HIP_TRY(hipStreamGetCaptureInfo(stream, &cs, &id));
+      fresh = !st->track_order_ok || st->track_order_tiles != st->total_tiles || id != st->order_capture;
+      st->order_capture = id;
+    }
+    if (fresh) launch_tile_order(st->ranges, nullptr, st->total_tiles, st->tile_order, stream);
+    HIP_TRY(hipGetLastError());
+    st->order_ok = true;
+    st->track_order_ok = true;
+    st->track_order_tiles = st->total_tiles;
   }
   if ((s = mark(CGSR_STAGE_BLEND_FWD))) return s;
   RasterBufs rb = raster_bufs(st, 0);

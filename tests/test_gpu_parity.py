@@ -767,6 +767,80 @@ def test_graph_tracking_replays_match_eager(R):
     assert l1 < 0.5 * l0 and e1 < e0
 
 
+def test_kept_tile_order_across_tile_counts_and_captures(R):
+    """A fused tracking step on a frame that fits the chip orders its tiles by
+    the lengths the previous step left (every eager step, and the first step
+    of each graph capture); steps of another tile count and renders that write
+    their own order in between, eager and between replays of a captured solve
+    fragment, leave the pose gradients those of a fresh state."""
+    say("case: kept tile order, eager and captured, changing tile counts")
+    sc = synth.room_scene(6, 30_000, (5.0, 4.0, 3.0))
+    scd = dev(sc)
+    cam_a = synth.camera(320, 240, 262.5, 262.5, 160, 120)   # 300 tiles
+    cam_b = synth.camera(160, 128, 131.25, 131.25, 80, 64)    # 80 tiles
+    cam_c = synth.camera(480, 320, 393.75, 393.75, 240, 160)  # 600 tiles, rendered without fusion
+    pa, pb = synth.level_room_pose(31), synth.level_room_pose(32)
+    Pa, Pb = R.pose_tensor(*pa), R.pose_tensor(*pb)
+    ref_st = R.State()
+    tgt = {}
+    for name, cam, P in (("a", cam_a, Pa), ("b", cam_b, Pb)):
+        out = R.render(ref_st, scd, P, [cam])[0]
+        tgt[name] = (out["color"].clone(), out["depth"].clone())
+    Pa0 = R.pose_tensor(*synth.perturb_pose(*pa, 41))
+    Pb0 = R.pose_tensor(*synth.perturb_pose(*pb, 42))
+    cams = {"a": (cam_a, Pa0), "b": (cam_b, Pb0)}
+
+    def step(st, name, dp):
+        cam, P0 = cams[name]
+        R.tracking_step(st, scd, P0, [cam], [tgt[name][0]], [tgt[name][1]], dposes=dp)
+
+    ref = {}
+    for name in cams:
+        dp = torch.zeros((1, 6), device="cuda")
+        step(R.State(), name, dp)
+        ref[name] = dp.clone()
+
+    def check(dp, name, label):
+        e = ((dp - ref[name]).abs().max() / ref[name].abs().max()).item()
+        say(label, name, "pose gradient vs fresh state", e)
+        assert e < 1e-4, (label, name, e)
+
+    def eager(st, name, label):
+        dp = torch.zeros((1, 6), device="cuda")
+        step(st, name, dp)
+        check(dp, name, label)
+
+    st = R.State()
+    for name in ("a", "b", "c", "a", "b", "a"):
+        if name == "c":
+            R.render(st, scd, Pa, [cam_c])   # writes an order of its own tile count
+        else:
+            eager(st, name, "eager")
+    st.check()
+    # a captured fragment of two steps on frame a, taken right after an eager
+    # step on the same frame (the capture still computes its own order)
+    dps = [torch.zeros((1, 6), device="cuda") for _ in range(2)]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        for dp in dps:
+            dp.zero_()
+            step(st, "a", dp)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        eager(st, "b", f"between replays {rep}")
+        R.render(st, scd, Pa, [cam_c])
+        # a graph reads the camera table the state holds when it replays:
+        # an eager call on its frame first
+        eager(st, "a", f"between replays {rep}")
+        graph.replay()
+        torch.cuda.synchronize()
+        st.check()
+        for dp in dps:
+            check(dp, "a", f"replay {rep}")
+
+
 def test_wave_lists_within_8x8_binning(R):
     """Each wave walks the Gaussians whose binning rectangle reaches its 8x8
     cell, less those that cannot reach alpha >= 1/255 on the cell: on a scene
