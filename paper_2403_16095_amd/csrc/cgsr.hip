@@ -59,9 +59,11 @@ void dev_free(T*& p) {
 }  // namespace
 
 // Fewest tiles for which a fused tracking step orders its tiles longest
-// first: about the workgroups the chip holds at once (256 CUs x 6).  No
-// launch orders more than kOrderMaxTiles: the one-workgroup order kernel then
-// costs about what it saves (32 frames of mixed resolution, 54k tiles: 0.5 %
+// first from its own pair counters, in a launch of its own: about the
+// workgroups the chip holds at once (256 CUs x 6); below it the step keeps
+// an order taken from the previous step's lengths (render_impl).  No launch
+// orders more than kOrderMaxTiles: the one-workgroup order kernel then costs
+// about what it saves (32 frames of mixed resolution, 54k tiles: 0.5 %
 // slower with the order; eight 1200x680 views, 25.8k tiles: 1.5 % faster).
 constexpr int32_t kOrderMinTiles = 1536;
 constexpr int32_t kOrderMaxTiles = 32768;
