@@ -587,7 +587,7 @@ cgsr_status render_impl(cgsr_state* st, const RenderArgs& a, hipStream_t stream)
       fresh = !st->track_order_ok || st->track_order_tiles != st->total_tiles || id != st->order_capture;
       st->order_capture = id;
     }
-    if (fresh) launch_tile_order(st->ranges, nullptr, st->total_tiles, st->tile_order, stream);
+    if (fresh) launch_tile_order(st->ranges, nullptr, st->total_tiles, st->tile_order, stream, true);
     HIP_TRY(hipGetLastError());
     st->order_ok = true;
     st->track_order_ok = true;

@@ -119,8 +119,11 @@ void launch_segment_sort(const SegSortBufs& b, int32_t total_tiles, hipStream_t 
 void launch_clear_u32(uint32_t* p, int64_t n, hipStream_t s);
 // Tiles by descending list length, in order[tiles]: lengths from the ranges
 // after the sort, or with ranges null from the pair counters (stride
-// kTileCounterStride) before a blend that sorts its own buckets.
-void launch_tile_order(const uint2* ranges, const uint32_t* counts, int32_t tiles, uint32_t* order, hipStream_t s);
+// kTileCounterStride) before a blend that sorts its own buckets.  snake:
+// every other run of 256 positions reversed (for launches whose tiles are all
+// resident at once).
+void launch_tile_order(const uint2* ranges, const uint32_t* counts, int32_t tiles, uint32_t* order, hipStream_t s,
+                       bool snake = false);
 // Pair counter of each tile = the length of its range (undoes the reset of
 // a tracking kernel that sorted its own buckets).
 void launch_restore_counts(uint32_t* tile_count, const uint2* ranges, int32_t tiles, hipStream_t s);

@@ -145,8 +145,15 @@ __global__ __launch_bounds__(kThreads) void clear_kernel(uint32_t* p, int64_t n)
 // 16 bins per octave (the leading bit and the next four), scanned from the
 // longest bin; tiles inside a bin keep the order their atomics left, which
 // changes no tile's result.
+// snake (for launches whose tiles are all resident from the start): every
+// other run of kOrderRound positions is reversed, so that the workgroups
+// dealt one per CU take, CU by CU, a long tile of one run with a short one
+// of the next, and the CUs' summed work comes out more even (a model of the
+// dispatch over measured tracking lists: the fullest CU 1.16x the mean work
+// longest first, 1.10x with the runs reversed).
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderBins = 16 * 33;
+constexpr uint32_t kOrderRound = 256;   // compute units of the chip
 
 __device__ __forceinline__ uint32_t order_bin(uint32_t n) {
   if (n == 0) return 0;
@@ -167,7 +174,7 @@ __device__ __forceinline__ uint32_t tile_length(const uint2* ranges, const uint3
 
 __global__ __launch_bounds__(kOrderThreads) void tile_order_kernel(const uint2* __restrict__ ranges,
                                                                    const uint32_t* __restrict__ counts, int32_t tiles,
-                                                                   uint32_t* __restrict__ order) {
+                                                                   uint32_t* __restrict__ order, int snake) {
   __shared__ uint32_t s_bin[kOrderBins];
   __shared__ uint32_t s_wave[kOrderThreads / kWave];
   for (int i = threadIdx.x; i < kOrderBins; i += kOrderThreads) s_bin[i] = 0u;
@@ -192,8 +199,15 @@ __global__ __launch_bounds__(kOrderThreads) void tile_order_kernel(const uint2* 
   for (int q = 0; q < wv; ++q) base += s_wave[q];
   if (bin >= 0) s_bin[bin] = base + inc - c;
   __syncthreads();
-  for (int t = threadIdx.x; t < tiles; t += kOrderThreads)
-    order[atomicAdd(&s_bin[order_bin(tile_length(ranges, counts, t))], 1u)] = (uint32_t)t;
+  for (int t = threadIdx.x; t < tiles; t += kOrderThreads) {
+    uint32_t pos = atomicAdd(&s_bin[order_bin(tile_length(ranges, counts, t))], 1u);
+    const uint32_t run = pos / kOrderRound;
+    if (snake && (run & 1u)) {   // reversed within the run (which the last one may leave short)
+      const uint32_t first = run * kOrderRound, len = min(kOrderRound, (uint32_t)tiles - first);
+      pos = first + len - 1u - (pos - first);
+    }
+    order[pos] = (uint32_t)t;
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void restore_counts_kernel(uint32_t* tile_count, const uint2* ranges,
@@ -213,10 +227,11 @@ void launch_clear_u32(uint32_t* p, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(clear_kernel, dim3((unsigned)blocks), dim3(kThreads), 0, s, p, n);
 }
 
-void launch_tile_order(const uint2* ranges, const uint32_t* counts, int32_t tiles, uint32_t* order, hipStream_t s) {
+void launch_tile_order(const uint2* ranges, const uint32_t* counts, int32_t tiles, uint32_t* order, hipStream_t s,
+                       bool snake) {
   if (tiles <= 0) return;
   static_assert(kOrderBins <= kOrderThreads, "one bin per thread in the scan");
-  hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderThreads), 0, s, ranges, counts, tiles, order);
+  hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderThreads), 0, s, ranges, counts, tiles, order, snake ? 1 : 0);
 }
 
 void launch_restore_counts(uint32_t* tile_count, const uint2* ranges, int32_t tiles, hipStream_t s) {
