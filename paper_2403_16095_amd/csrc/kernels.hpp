@@ -119,9 +119,10 @@ void launch_segment_sort(const SegSortBufs& b, int32_t total_tiles, hipStream_t 
 void launch_clear_u32(uint32_t* p, int64_t n, hipStream_t s);
 // Tiles by descending list length, in order[tiles]: lengths from the ranges
 // after the sort, or with ranges null from the pair counters (stride
-// kTileCounterStride) before a blend that sorts its own buckets.  snake:
-// every other run of 256 positions reversed (for launches whose tiles are all
-// resident at once).
+// kTileCounterStride) before a blend that sorts its own buckets.  snake
+// (for launches whose tiles are all resident at once, up to 2048 tiles):
+// every other run of 256 positions reversed and the last, short run placed
+// by the work the full runs gave each position.
 void launch_tile_order(const uint2* ranges, const uint32_t* counts, int32_t tiles, uint32_t* order, hipStream_t s,
                        bool snake = false);
 // Pair counter of each tile = the length of its range (undoes the reset of

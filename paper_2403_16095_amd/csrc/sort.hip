@@ -148,12 +148,15 @@ __global__ __launch_bounds__(kThreads) void clear_kernel(uint32_t* p, int64_t n)
 // snake (for launches whose tiles are all resident from the start): every
 // other run of kOrderRound positions is reversed, so that the workgroups
 // dealt one per CU take, CU by CU, a long tile of one run with a short one
-// of the next, and the CUs' summed work comes out more even (a model of the
-// dispatch over measured tracking lists: the fullest CU 1.16x the mean work
-// longest first, 1.10x with the runs reversed).
+// of the next, and the last, short run gives its tiles to the CU positions
+// the full runs loaded least; the CUs' summed work comes out more even (a
+// model of the dispatch over measured tracking lists: the fullest CU 1.16x
+// the mean work longest first, 1.10x with the runs reversed, 1.06x with the
+// last run placed by load).
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderBins = 16 * 33;
 constexpr uint32_t kOrderRound = 256;   // compute units of the chip
+constexpr int kSnakeMaxTiles = 2048;
 
 __device__ __forceinline__ uint32_t order_bin(uint32_t n) {
   if (n == 0) return 0;
@@ -199,14 +202,49 @@ __global__ __launch_bounds__(kOrderThreads) void tile_order_kernel(const uint2* 
   for (int q = 0; q < wv; ++q) base += s_wave[q];
   if (bin >= 0) s_bin[bin] = base + inc - c;
   __syncthreads();
-  for (int t = threadIdx.x; t < tiles; t += kOrderThreads) {
-    uint32_t pos = atomicAdd(&s_bin[order_bin(tile_length(ranges, counts, t))], 1u);
-    const uint32_t run = pos / kOrderRound;
-    if (snake && (run & 1u)) {   // reversed within the run (which the last one may leave short)
-      const uint32_t first = run * kOrderRound, len = min(kOrderRound, (uint32_t)tiles - first);
-      pos = first + len - 1u - (pos - first);
+  if (!snake) {
+    for (int t = threadIdx.x; t < tiles; t += kOrderThreads)
+      order[atomicAdd(&s_bin[order_bin(tile_length(ranges, counts, t))], 1u)] = (uint32_t)t;
+    return;
+  }
+  // snake (tiles <= kSnakeMaxTiles): the full runs of kOrderRound positions
+  // alternate direction; the last, short run's tiles (the shortest, longest
+  // of them first) go to its positions in ascending order of the work the
+  // full runs gave the same CU position.
+  __shared__ uint32_t s_load[kOrderRound], s_perm[kOrderRound];
+  if (threadIdx.x < kOrderRound) s_load[threadIdx.x] = 0u;
+  constexpr int kPer = kSnakeMaxTiles / kOrderThreads;
+  uint32_t rank[kPer], len[kPer];
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int t = threadIdx.x + q * kOrderThreads;
+    len[q] = t < tiles ? tile_length(ranges, counts, t) : 0u;
+    rank[q] = t < tiles ? atomicAdd(&s_bin[order_bin(len[q])], 1u) : 0u;
+  }
+  const uint32_t full = (uint32_t)tiles / kOrderRound * kOrderRound, rem = (uint32_t)tiles - full;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int t = threadIdx.x + q * kOrderThreads;
+    if (t < tiles && rank[q] < full) {
+      const uint32_t run = rank[q] / kOrderRound, j = rank[q] % kOrderRound;
+      const uint32_t pos = (run & 1u) ? run * kOrderRound + kOrderRound - 1u - j : rank[q];
+      order[pos] = (uint32_t)t;
+      atomicAdd(&s_load[pos % kOrderRound], len[q]);
     }
-    order[pos] = (uint32_t)t;
+  }
+  __syncthreads();
+  if (threadIdx.x < rem) {   // rank of the position by (load, position)
+    const uint32_t j = threadIdx.x, key = s_load[j];
+    uint32_t r = 0;
+    for (uint32_t i = 0; i < rem; ++i) r += (s_load[i] < key || (s_load[i] == key && i < j)) ? 1u : 0u;
+    s_perm[r] = j;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int t = threadIdx.x + q * kOrderThreads;
+    if (t < tiles && rank[q] >= full) order[full + s_perm[rank[q] - full]] = (uint32_t)t;
   }
 }
 
@@ -231,7 +269,8 @@ void launch_tile_order(const uint2* ranges, const uint32_t* counts, int32_t tile
                        bool snake) {
   if (tiles <= 0) return;
   static_assert(kOrderBins <= kOrderThreads, "one bin per thread in the scan");
-  hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderThreads), 0, s, ranges, counts, tiles, order, snake ? 1 : 0);
+  hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderThreads), 0, s, ranges, counts, tiles, order,
+                     snake && tiles <= kSnakeMaxTiles ? 1 : 0);
 }
 
 void launch_restore_counts(uint32_t* tile_count, const uint2* ranges, int32_t tiles, hipStream_t s) {
