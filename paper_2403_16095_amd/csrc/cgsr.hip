@@ -559,12 +559,13 @@ cgsr_status render_impl(cgsr_state* st, const RenderArgs& a, hipStream_t stream)
   // more tiles than fit the chip at once orders them from this render's pair
   // counters, in a launch of its own.  One with fewer (all its tiles resident
   // from the start, where the order only spreads the long lists over the
-  // CUs) takes them by the lengths the previous step left in the ranges:
-  // steps follow one another with a pose that moves little, so the order is
-  // computed by every eager step but only by the first such step of a graph
-  // capture, and a captured solve pays for it once per replay.  Whatever the
-  // lengths read, the order is a permutation of the step's tiles, and any
-  // order gives every tile the same result.
+  // CUs) takes them by the work the previous step measured per tile (its
+  // waves' list lengths, kept in the second word of each tile's counter
+  // line): steps follow one another with a pose that moves little, so the
+  // order is computed by every eager step but only by the first such step of
+  // a graph capture, and a captured solve pays for it once per replay.
+  // Whatever the values read, the order is a permutation of the step's
+  // tiles, and any order gives every tile the same result.
   st->order_ok = false;
   const bool order = st->total_tiles < kOrderMaxTiles;
   if (!sort_here) {
@@ -587,7 +588,7 @@ cgsr_status render_impl(cgsr_state* st, const RenderArgs& a, hipStream_t stream)
       fresh = !st->track_order_ok || st->track_order_tiles != st->total_tiles || id != st->order_capture;
       st->order_capture = id;
     }
-    if (fresh) launch_tile_order(st->ranges, nullptr, st->total_tiles, st->tile_order, stream, true);
+    if (fresh) launch_tile_order(nullptr, st->tile_count + 1, st->total_tiles, st->tile_order, stream, true);
     HIP_TRY(hipGetLastError());
     st->order_ok = true;
     st->track_order_ok = true;

@@ -162,7 +162,8 @@ struct RasterBufs {
   // sort would.
   bool sort_here;
   const uint64_t* bucket_keys;   // [T][tile_cap]
-  uint32_t* tile_count;          // [T * kTileCounterStride], reset to zero here
+  uint32_t* tile_count;          // [T * kTileCounterStride], reset to zero here; the fused
+                                 // tracking kernel leaves the tile's work in word 1
   uint32_t* counters;            // kCntRenderPeak reset here
   uint32_t tile_cap;
   // Timing re-runs of a tracking step's kernel leave the pair counters as

@@ -225,6 +225,7 @@ struct FwdPix {
   int64_t pix[kPPL];
   uint32_t med1[kPPL];            // one past the median's position in the tile's list, 0 if none
   uint32_t last[kPPL], evaluated[kPPL], blended[kPPL], wlast[kPPL];
+  uint32_t wave_len;   // entries of the wave's list the walk went through
   float wdom[kPPL], ddom[kPPL];   // kNu: largest weight so far and its depth
   uint32_t dom[kPPL];             // kNu: its record id, kNone if none
   bool inside[kPPL], done[kPPL];
@@ -342,6 +343,7 @@ __device__ __forceinline__ void forward_tile(const RasterBufs& b, Stage<kTilePix
   // a pixel that never stopped evaluated every entry of its wave's list
 #pragma unroll
   for (int k = 0; k < kPPL; ++k) f.evaluated[k] = f.evaluated[k] ? f.evaluated[k] : loc;
+  f.wave_len = loc;
 }
 
 // Everything the forward leaves behind: maps, saved per-pixel state, the
@@ -667,7 +669,7 @@ template <int kPPL, bool kColor, bool kFull>
 __global__ __launch_bounds__(kTilePixels / kPPL) void raster_track_kernel(RasterBufs b) {
   constexpr int L = kTilePixels / kPPL;
   __shared__ Stage<kTilePixels / kPPL / kWave> s;
-  __shared__ uint32_t s_max;
+  __shared__ uint32_t s_max, s_work;
   __shared__ uint32_t s_ids[L];
   // The bucket's keys are ranked before the first batch is staged, so they
   // share the stage's storage (keeping the workgroup's LDS at 25.6 KB, six
@@ -678,6 +680,7 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_track_kernel(Raster
   const int v = view_of_tile(b.views, gtile);
   const ViewIO io = b.views.io[v];
   const float2 org = tile_origin(io.info, gtile);
+  if (threadIdx.x == 0) s_work = 0u;
   const uint2 range = b.sort_here ? sort_own_bucket<L>(b, gtile, s_key, s_ids, &s_max) : b.ranges[gtile];
   prioritise(range.y - range.x, kTrackTilePrio[0], kTrackTilePrio[1], kTrackTilePrio[2]);
   BwdPix<kPPL> p;
@@ -687,6 +690,7 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_track_kernel(Raster
     forward_tile<kPPL, true, false, kFull>(b, s, gtile, io, org, range, b.sort_here ? s_ids : b.vals + range.x, f);
     float g[kPPL][4];
     forward_outputs<kPPL, true, false, kFull>(b, v, io, f, g, false);
+    if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&s_work, f.wave_len);
 #pragma unroll
     for (int k = 0; k < kPPL; ++k) {
       p.fx[k] = f.fx[k];
@@ -704,6 +708,8 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_track_kernel(Raster
     }
   }
   const int nmax = block_max(lane_max, &s_max);
+  // the tile's work for the next step's order: its waves' list lengths
+  if (threadIdx.x == 0) b.tile_count[(size_t)gtile * kTileCounterStride + 1] = s_work;
   const int len = (int)(range.y - range.x);
   backward_tile<kPPL, false, true, kColor>(b, s, range, org, nmax, len <= kBatch ? len : 0, p);
 }
