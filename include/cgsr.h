@@ -180,7 +180,9 @@ cgsr_status cgsr_state_destroy(cgsr_state *st);
  * table of cameras and image pointers the state holds when it replays; a call
  * on the same state with other cameras or images rewrites that table, so
  * replay after a call with the graph's own cameras and images, or keep one
- * state per captured loop. */
+ * state per captured loop (a replay with another table is reported by
+ * cgsr_state_check).  Growing the workspace frees the buffers a graph
+ * captured before then points to: such a graph must not be replayed. */
 cgsr_status cgsr_state_reserve(cgsr_state *st, int64_t max_records, int64_t max_pixels,
                                int64_t max_tiles, int64_t max_tile_pairs);
 
@@ -546,8 +548,13 @@ cgsr_status cgsr_densify_gaussians(int64_t n, const float *grad_accum, const uin
 
 /* Synchronise the stream and report CGSR_ERR_CAPACITY if any render on this
  * state since the previous check (or since creation) overflowed its pair
- * buffer; the message names the most pairs a render needed.  The check then
- * starts a new period (clears the overflow flag and the peak). */
+ * buffer; the message names the most pairs a render needed.  CGSR_ERR_STATE
+ * (reported first) if a launch since the previous check ran with a table of
+ * cameras and image pointers other than the one it was set up with: a graph
+ * captured on this state and replayed after a call with other cameras or
+ * images (see cgsr_state_reserve); that replay's results are not the captured
+ * loop's.  The check then starts a new period (clears both flags and the
+ * peak). */
 cgsr_status cgsr_state_check(cgsr_state *st, void *stream);
 
 /* Synchronise the stream and read the counters of the last render. */

@@ -119,6 +119,7 @@ struct cgsr_state {
     bool event_pending = false;
     ViewIO cached[CGSR_MAX_VIEWS];
     int cached_n = -1;
+    uint32_t hash = 0;   // of the table last uploaded, which dev[n] holds in its first word
   } io[2];
   // stage timing: ev_fwd[k] starts forward stage k, ev_fwd[k + 1] ends it
   hipEvent_t ev_fwd[CGSR_STAGE_BLEND_FWD + 2] = {};
@@ -250,8 +251,15 @@ cgsr_status upload_io(cgsr_state* st, int slot, const ViewIO* io, int n, hipStre
     HIP_TRY(hipEventSynchronize(t.event));
     t.event_pending = false;
   }
+  // FNV-1a of the table, stored after it: launches compare it with their own
+  uint32_t h = 2166136261u;
+  const unsigned char* bytes = reinterpret_cast<const unsigned char*>(io);
+  for (size_t k = 0; k < sizeof(ViewIO) * (size_t)n; ++k) h = (h ^ bytes[k]) * 16777619u;
   std::memcpy(t.pinned, io, sizeof(ViewIO) * n);
-  HIP_TRY(hipMemcpyAsync(t.dev, t.pinned, sizeof(ViewIO) * n, hipMemcpyHostToDevice, stream));
+  std::memset(&t.pinned[n], 0, sizeof(ViewIO));
+  std::memcpy(&t.pinned[n], &h, sizeof(h));
+  HIP_TRY(hipMemcpyAsync(t.dev, t.pinned, sizeof(ViewIO) * (n + 1), hipMemcpyHostToDevice, stream));
+  t.hash = h;
   HIP_TRY(hipEventRecord(t.event, stream));
   t.event_pending = true;
   std::memcpy(t.cached, io, sizeof(ViewIO) * n);
@@ -297,7 +305,7 @@ RasterBufs raster_bufs(cgsr_state* st, int slot) {
   rb.tile_cap = (uint32_t)st->cap_tile_pairs;
   rb.keep_counts = false;
   rb.order = st->order_ok ? st->tile_order : nullptr;
-  rb.views = ViewTable{st->io[slot].dev, st->n_views, (int32_t)st->g.n};
+  rb.views = ViewTable{st->io[slot].dev, st->n_views, (int32_t)st->g.n, st->io[slot].hash};
   rb.total_tiles = st->total_tiles;
   return rb;
 }
@@ -340,9 +348,11 @@ cgsr_status cgsr_state_create(const cgsr_settings* s, cgsr_state** out) {
   if (!r && hipMemset(st->pose_acc, 0, sizeof(double) * 6 * CGSR_MAX_VIEWS) != hipSuccess)
     r = fail(CGSR_ERR_HIP, "hipMemset of pose accumulators failed");
   for (int k = 0; k < 2 && !r; ++k) {
-    r = dev_alloc(&st->io[k].dev, CGSR_MAX_VIEWS);
-    if (!r && hipHostMalloc((void**)&st->io[k].pinned, sizeof(ViewIO) * CGSR_MAX_VIEWS, hipHostMallocDefault) !=
-                  hipSuccess)
+    r = dev_alloc(&st->io[k].dev, CGSR_MAX_VIEWS + 1);
+    if (!r && hipMemset(st->io[k].dev, 0, sizeof(ViewIO) * (CGSR_MAX_VIEWS + 1)) != hipSuccess)
+      r = fail(CGSR_ERR_HIP, "hipMemset of a view table failed");
+    if (!r && hipHostMalloc((void**)&st->io[k].pinned, sizeof(ViewIO) * (CGSR_MAX_VIEWS + 1),
+                            hipHostMallocDefault) != hipSuccess)
       r = fail(CGSR_ERR_OOM, "pinned allocation failed");
     if (!r && hipEventCreateWithFlags(&st->io[k].event, hipEventDisableTiming) != hipSuccess)
       r = fail(CGSR_ERR_HIP, "hipEventCreate failed");
@@ -508,7 +518,7 @@ cgsr_status render_impl(cgsr_state* st, const RenderArgs& a, hipStream_t stream)
     launch_clear_u32(st->counters + kCntRenderPeak, 1, stream);
   }
 
-  const ViewTable vt{st->io[0].dev, a.n_views, (int32_t)a.g->n};
+  const ViewTable vt{st->io[0].dev, a.n_views, (int32_t)a.g->n, st->io[0].hash};
   const bool timed = st->settings.timing && !in_capture;
   auto mark = [&](int k) -> cgsr_status {
     if (timed) HIP_TRY(hipEventRecord(st->ev_fwd[k], stream));
@@ -634,7 +644,7 @@ cgsr_status backward_impl(cgsr_state* st, int slot, bool params, bool track, con
   if (!blend_done) launch_raster_backward(rb, params, track, st->settings.bwd_pixels_per_lane, stream);
   if (timed) HIP_TRY(hipEventRecord(st->ev_bwd[1], stream));
   launch_project_backward(st->g, st->poses, rb.views, st->rec_grad, st->tiles, gp, params, st->pose_acc, dposes, step,
-                          st->dens_grad, st->dens_count, stream);
+                          st->dens_grad, st->dens_count, st->counters, stream);
   HIP_TRY(hipGetLastError());
   if (timed) HIP_TRY(hipEventRecord(st->ev_bwd[2], stream));
   st->bwd_timed = timed;
@@ -1327,13 +1337,18 @@ cgsr_status cgsr_state_check(cgsr_state* st, void* stream) {
   if (!st) return fail(CGSR_ERR_INVALID_ARG, "state is NULL");
   cgsr_status s = set_device(st);
   if (s) return s;
-  HIP_TRY(hipMemcpyAsync(st->counters_pinned, st->counters, sizeof(uint32_t) * 3, hipMemcpyDeviceToHost,
+  HIP_TRY(hipMemcpyAsync(st->counters_pinned, st->counters, sizeof(uint32_t) * 4, hipMemcpyDeviceToHost,
                          (hipStream_t)stream));
   HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
   const uint32_t overflow = st->counters_pinned[kCntOverflow], peak = st->counters_pinned[kCntPeak];
-  // start the next checking period
-  launch_clear_u32(st->counters + kCntOverflow, 2, (hipStream_t)stream);
+  const uint32_t stale = st->counters_pinned[kCntStaleTable];
+  // start the next checking period (words kCntOverflow .. kCntStaleTable)
+  launch_clear_u32(st->counters + kCntOverflow, 3, (hipStream_t)stream);
   HIP_TRY(hipGetLastError());
+  if (stale)
+    return fail(CGSR_ERR_STATE,
+                "a captured graph was replayed after another call on this state rewrote its table of cameras and "
+                "image pointers; that replay's results are not the captured loop's");
   if (overflow)
     return fail(CGSR_ERR_CAPACITY, "a tile needed %u pairs, the buckets hold %lld", peak,
                 (long long)st->cap_tile_pairs);

@@ -56,10 +56,12 @@ struct ViewIO {
 };
 
 struct ViewTable {
-  const ViewIO* io;   // [n] device
+  const ViewIO* io;   // [n] device, followed by one word: the hash of the uploaded table
   int32_t n;          // views
   int32_t n_gauss;    // Gaussians per view (records are view-major)
+  uint32_t hash;      // the hash of the table this launch was set up with
 };
+
 
 // Projected record, 3 x float4 per (view, Gaussian):
 //   a = (mu_x, mu_y, a, k)                  mu = float nearest the mean

@@ -12,9 +12,19 @@ namespace cgsr {
 enum Counter : int {
   kCntOverflow = 1,     // 1 if a render since the last check had a tile over its bucket
   kCntPeak = 2,         // most pairs an overflowing tile needed since the last check
+  kCntStaleTable = 3,   // 1 if a launch since the last check read a view table other than its own
   kCntRenderPeak = 4,   // most pairs an overflowing tile needs in the render in flight (reset by the sort)
 };
 constexpr int kCounterWords = 8;
+
+// A launch replayed from a captured graph reads whatever view table the state
+// holds when it runs; one workgroup compares the table's hash with the one
+// the launch was set up with and raises kCntStaleTable if they differ.
+__device__ __forceinline__ void check_table(const ViewTable& vt, uint32_t* counters) {
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && counters &&
+      reinterpret_cast<const uint32_t*>(vt.io + vt.n)[0] != vt.hash)
+    atomicOr(counters + kCntStaleTable, 1u);
+}
 
 // Every workgroup takes the per-tile counters by atomics; each counter sits on
 // a 128-byte line of its own so that atomics on neighbouring tiles do not queue
@@ -71,7 +81,7 @@ struct PoseStep {
 void launch_project_backward(const GaussianPtrs& g, const float* poses, const ViewTable& vt, float* rec_grad,
                              const uint32_t* tiles, const GradPtrs& dg, bool param_grads, double* pose_acc,
                              float* dposes, const PoseStep* step, float* dens_grad, uint32_t* dens_count,
-                             hipStream_t s);
+                             uint32_t* counters, hipStream_t s);
 
 // Gaussian management (management.hip).  Writable parameter arrays of a set
 // (colour in rgb, or sh with K coefficients per channel).

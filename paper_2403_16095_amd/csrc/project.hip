@@ -310,6 +310,7 @@ __global__ __launch_bounds__(kThreads) void project_kernel(GaussianPtrs g, const
   __shared__ uint32_t s_off[kThreads], s_org[kThreads], s_wid[kThreads];
   __shared__ uint64_t s_key[kThreads];
   __shared__ float4 s_r0[kThreads], s_r1[kThreads];   // record fields the pair test reads
+  check_table(vt, b.counters);
   const int v = blockIdx.y;
   const int64_t N = g.n;
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -432,8 +433,9 @@ __global__ __launch_bounds__(kThreads) void project_backward_kernel(GaussianPtrs
                                                                     const uint32_t* __restrict__ tiles,
                                                                     GradPtrs dg, int param_grads, int atomic_params,
                                                                     int view_loop, double* pose_acc, float* dens_grad,
-                                                                    uint32_t* dens_count) {
+                                                                    uint32_t* dens_count, uint32_t* counters) {
   __shared__ float s_pose[2][4][6];
+  check_table(vt, counters);
   const int64_t N = g.n;
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   // view_loop: a lane walks its Gaussian's records of every view, so it owns
@@ -693,7 +695,7 @@ void launch_project(const GaussianPtrs& g, const float* poses, const ViewTable& 
 void launch_project_backward(const GaussianPtrs& g, const float* poses, const ViewTable& vt, float* rec_grad,
                              const uint32_t* tiles, const GradPtrs& dg, bool param_grads, double* pose_acc,
                              float* dposes, const PoseStep* step, float* dens_grad, uint32_t* dens_count,
-                             hipStream_t s) {
+                             uint32_t* counters, hipStream_t s) {
   // Several views: one lane per Gaussian over all views (no atomics on the
   // parameter gradients, one workgroup per Gaussian block instead of one per
   // (view, block)); one view: one grid row.
@@ -702,7 +704,7 @@ void launch_project_backward(const GaussianPtrs& g, const float* poses, const Vi
   const bool pose = dposes || step;
   hipLaunchKernelGGL(project_backward_kernel, grid, dim3(kThreads), 0, s, g, poses, vt, rec_grad, tiles, dg,
                      param_grads ? 1 : 0, (vt.n > 1 && !view_loop) ? 1 : 0, view_loop ? 1 : 0,
-                     pose ? pose_acc : nullptr, dens_grad, dens_count);
+                     pose ? pose_acc : nullptr, dens_grad, dens_count, counters);
   if (pose)
     hipLaunchKernelGGL(pose_finalize_kernel, dim3((unsigned)vt.n), dim3(64), 0, s, pose_acc, dposes,
                        step ? step->poses : nullptr, step ? step->adam : nullptr,

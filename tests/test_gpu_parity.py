@@ -841,6 +841,63 @@ def test_kept_tile_order_across_tile_counts_and_captures(R):
             check(dp, "a", f"replay {rep}")
 
 
+def test_replay_with_another_camera_table_is_reported(R):
+    """A captured tracking step replayed after an eager call with another
+    (smaller) camera on the same state runs with that call's camera table:
+    cgsr_state_check reports it (CGSR_ERR_STATE) and clears the flag, and a
+    replay after a call with the graph's own camera is correct again."""
+    from paper_2403_16095_amd import binding as B
+    say("case: graph replay with a rewritten camera table")
+    sc = synth.room_scene(7, 20_000, (5.0, 4.0, 3.0))
+    scd = dev(sc)
+    cam_a = synth.camera(320, 240, 262.5, 262.5, 160, 120)
+    cam_b = synth.camera(160, 128, 131.25, 131.25, 80, 64)
+    pa, pb = synth.level_room_pose(51), synth.level_room_pose(52)
+    tgt = {}
+    for name, cam, pose in (("a", cam_a, pa), ("b", cam_b, pb)):
+        out = R.render(R.State(), scd, R.pose_tensor(*pose), [cam])[0]
+        tgt[name] = (cam, R.pose_tensor(*synth.perturb_pose(*pose, 61)), out["color"].clone(), out["depth"].clone())
+
+    def step(st, name, dp):
+        cam, P0, tc, td = tgt[name]
+        R.tracking_step(st, scd, P0, [cam], [tc], [td], dposes=dp)
+
+    ref = torch.zeros((1, 6), device="cuda")
+    step(R.State(), "a", ref)
+    st = R.State()
+    scratch = torch.zeros((1, 6), device="cuda")
+    for name in ("b", "a"):   # size the state for both frames, then leave frame a's table
+        step(st, name, scratch)
+    st.check()
+    dp = torch.zeros((1, 6), device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        dp.zero_()
+        step(st, "a", dp)
+    torch.cuda.synchronize()
+
+    def replay_matches():
+        graph.replay()
+        torch.cuda.synchronize()
+        st.check()
+        e = ((dp - ref).abs().max() / ref.abs().max()).item()
+        say("replay pose gradient vs fresh state", e)
+        assert e < 1e-4
+
+    replay_matches()
+    step(st, "b", scratch)   # rewrites the table
+    graph.replay()
+    torch.cuda.synchronize()
+    with pytest.raises(B.CgsrError) as err:
+        st.check()
+    assert err.value.status == B.CGSR_ERR_STATE
+    st.check()               # the flag was cleared
+    step(st, "a", scratch)   # the graph's own camera again
+    replay_matches()
+
+
 def test_wave_lists_within_8x8_binning(R):
     """Each wave walks the Gaussians whose binning rectangle reaches its 8x8
     cell, less those that cannot reach alpha >= 1/255 on the cell: on a scene
