@@ -300,7 +300,7 @@ class MappingIteration:
             for v in range(self.V):
                 self._views(self.states[v], [v])
 
-    def autotune(self, repeats=3):
+    def autotune(self, repeats=5):
         """The library's render autotuner on this iteration's first state and
         views (after a sizing call, so the gradient images hold real
         gradients); the states made by freeze_capacity then use its pick."""

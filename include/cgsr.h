@@ -412,8 +412,10 @@ cgsr_status cgsr_tracking_step(cgsr_state *st, const cgsr_gaussians *g, int32_t 
  * `repeats` steps without the capacity read-back between two HIP events on
  * the stream (no Adam step, poses unchanged).  A candidate whose buckets
  * exceed one key per lane is timed with the segmented sort it then needs.
- * Stores the fastest in the state's settings and returns them in *out (may
- * be NULL).  Synchronises; not for use under graph capture.
+ * The candidates are timed in two passes and each keeps its faster one (the
+ * first pass also warms the GPU up).  Stores the fastest in the state's
+ * settings and returns them in *out (may be NULL).  Synchronises; not for use
+ * under graph capture.
  */
 cgsr_status cgsr_autotune_tracking(cgsr_state *st, const cgsr_gaussians *g, int32_t n_views, const float *poses,
                                    const cgsr_camera *cams, const float *const *target_color,
@@ -426,9 +428,10 @@ cgsr_status cgsr_autotune_tracking(cgsr_state *st, const cgsr_gaussians *g, int3
  * pixels per lane (1, 2 or 4 each) for a render + backward workload on this
  * state by timing, for each of the nine pairs, one cgsr_render + cgsr_backward
  * with the state's settings (it may grow the buckets), then `repeats` more
- * between two HIP events on the stream without the capacity read-back.  The
+ * between two HIP events on the stream without the capacity read-back, in
+ * two passes over the pairs, each pair keeping its faster one.  The
  * arguments are those of cgsr_render and cgsr_backward.  The tuning runs
- * write the maps and add their gradients to dG and dposes 9 (repeats + 1)
+ * write the maps and add their gradients to dG and dposes 18 (repeats + 1)
  * times: the caller clears those after.
  *
  * Both autotuners keep their picks in the state, keyed by the workload's

@@ -66,6 +66,7 @@ void dev_free(T*& p) {
 // about what it saves (32 frames of mixed resolution, 54k tiles: 0.5 %
 // slower with the order; eight 1200x680 views, 25.8k tiles: 1.5 % faster).
 constexpr int32_t kOrderMinTiles = 1536;
+constexpr int kTunePasses = 2;   // timing passes over an autotuner's candidates
 constexpr int32_t kOrderMaxTiles = 32768;
 
 struct cgsr_state {
@@ -903,9 +904,12 @@ cgsr_status cgsr_autotune_tracking(cgsr_state* st, const cgsr_gaussians* g, int3
     return fail(CGSR_ERR_HIP, "cgsr_autotune_tracking: hipEventCreate failed");
   }
   const int32_t cand[3] = {1, 2, 4};
-  float best = 1e30f;
-  int32_t pick = saved.fwd_pixels_per_lane;
-  for (int c = 0; c < 3 && !s; ++c) {
+  // Two passes over the candidates, each candidate's faster one kept: the
+  // first pass also warms the GPU up, which would otherwise count against
+  // whichever candidate runs first.
+  float time[3] = {1e30f, 1e30f, 1e30f};
+  for (int it = 0; it < kTunePasses * 3 && !s; ++it) {
+    const int c = it % 3;
     // The whole step (projection, sort unless the blend sorts its own
     // buckets, fused blend, projection backward) between two events: a
     // candidate whose buckets no longer fit one key per lane pays for the
@@ -929,15 +933,19 @@ cgsr_status cgsr_autotune_tracking(cgsr_state* st, const cgsr_gaussians* g, int3
     if (!s && e == hipSuccess) e = hipEventSynchronize(ev[1]);
     if (!s && e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
     if (!s && e != hipSuccess) s = fail(CGSR_ERR_HIP, "cgsr_autotune_tracking: %s", hipGetErrorString(e));
-    if (!s && ms < best) {
-      best = ms;
-      pick = cand[c];
-    }
+    if (!s) time[c] = std::min(time[c], ms);
   }
   (void)hipEventDestroy(ev[0]);
   (void)hipEventDestroy(ev[1]);
   st->settings = saved;
   if (s) return s;
+  int32_t pick = cand[0];
+  float best = time[0];
+  for (int c = 1; c < 3; ++c)
+    if (time[c] < best) {
+      best = time[c];
+      pick = cand[c];
+    }
   // the tracking step's forward and pose backward are one fused launch, so
   // one setting serves both
   st->settings.fwd_pixels_per_lane = pick;
@@ -983,9 +991,11 @@ cgsr_status cgsr_autotune_render(cgsr_state* st, const cgsr_gaussians* g, int32_
     return fail(CGSR_ERR_HIP, "cgsr_autotune_render: hipEventCreate failed");
   }
   const int32_t cand[3] = {1, 2, 4};
-  float best = 1e30f;
-  int32_t pick_f = saved.fwd_pixels_per_lane, pick_b = saved.bwd_pixels_per_lane;
-  for (int c = 0; c < 9 && !s; ++c) {
+  // two passes, each pair's faster one kept (see cgsr_autotune_tracking)
+  float time[9];
+  for (float& t : time) t = 1e30f;
+  for (int it = 0; it < kTunePasses * 9 && !s; ++it) {
+    const int c = it % 9;
     // One render + backward with the caller's settings (it may grow the
     // buckets), then the timed ones without the capacity read-back.
     st->settings = saved;
@@ -1007,16 +1017,20 @@ cgsr_status cgsr_autotune_render(cgsr_state* st, const cgsr_gaussians* g, int32_
     if (!s && e == hipSuccess) e = hipEventSynchronize(ev[1]);
     if (!s && e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
     if (!s && e != hipSuccess) s = fail(CGSR_ERR_HIP, "cgsr_autotune_render: %s", hipGetErrorString(e));
-    if (!s && ms < best) {
-      best = ms;
-      pick_f = cand[c / 3];
-      pick_b = cand[c % 3];
-    }
+    if (!s) time[c] = std::min(time[c], ms);
   }
   (void)hipEventDestroy(ev[0]);
   (void)hipEventDestroy(ev[1]);
   st->settings = saved;
   if (s) return s;
+  int32_t pick_f = cand[0], pick_b = cand[0];
+  float best = time[0];
+  for (int c = 1; c < 9; ++c)
+    if (time[c] < best) {
+      best = time[c];
+      pick_f = cand[c / 3];
+      pick_b = cand[c % 3];
+    }
   st->settings.fwd_pixels_per_lane = pick_f;
   st->settings.bwd_pixels_per_lane = pick_b;
   tune_store(st, key, pick_f, pick_b);
