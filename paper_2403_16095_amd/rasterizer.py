@@ -656,9 +656,12 @@ class TrackingSolver:
         cam = prob.cam
         H, W = int(cam["height"]), int(cam["width"])
         dev = prob.target_depth.device
-        self.pose = torch.zeros(12, dtype=torch.float32, device=dev)
-        self.dpose = torch.zeros((1, 6), dtype=torch.float32, device=dev)
-        self.adam = torch.zeros((1, 16), dtype=torch.float32, device=dev)
+        # pose, Adam moments and pose gradient in one buffer (16-byte aligned
+        # views), so that a reset is one elementwise kernel
+        self._buf = torch.zeros(12 + 16 + 6, dtype=torch.float32, device=dev)
+        self.pose = self._buf[0:12]
+        self.adam = self._buf[12:28].view(1, 16)
+        self.dpose = self._buf[28:34].view(1, 6)
         self.dcolor = torch.empty((3, H, W), dtype=torch.float32, device=dev)
         self.ddepth = torch.empty((H, W), dtype=torch.float32, device=dev)
         self.color = torch.empty((3, H, W), dtype=torch.float32, device=dev)
@@ -672,16 +675,18 @@ class TrackingSolver:
         self.graph = None
         self.use_graph = use_graph
         self.pose0 = None if reset_pose is None else reset_pose.reshape(12).clone()
+        self._init = None
+        if self.pose0 is not None:
+            self._init = torch.zeros_like(self._buf)
+            self._init[0:12] = self.pose0
         self.fused = fused
         self.params = adam_params(prob.lr_rho, prob.lr_phi)
         self.cam_arr = [self.cam_s]
 
     def _reset_on_device(self):
-        # elementwise kernels only: a captured graph then holds no memcpy or
-        # memset nodes
-        torch.mul(self.pose0, 1.0, out=self.pose)
-        self.adam.zero_()
-        self.dpose.zero_()
+        # one elementwise kernel (start pose, zero moments and gradient): a
+        # captured graph then holds no memcpy or memset nodes
+        torch.mul(self._init, 1.0, out=self._buf)
 
     def _iteration(self):
         p = self.prob
