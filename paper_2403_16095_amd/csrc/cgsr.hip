@@ -570,9 +570,10 @@ cgsr_status render_impl(cgsr_state* st, const RenderArgs& a, hipStream_t stream)
   // more tiles than fit the chip at once orders them from this render's pair
   // counters, in a launch of its own.  One with fewer (all its tiles resident
   // from the start, where the order only spreads the long lists over the
-  // CUs) takes them by the work the previous step measured per tile (its
-  // waves' list lengths, kept in the second word of each tile's counter
-  // line): steps follow one another with a pose that moves little, so the
+  // CUs) takes them by the work the previous step measured per tile (each
+  // quadrant's list length, kept in words 1..4 of the tile's counter line),
+  // with a quadrant rotation per workgroup that evens out the SIMDs of each
+  // CU: steps follow one another with a pose that moves little, so the
   // order is computed by every eager step but only by the first such step of
   // a graph capture, and a captured solve pays for it once per replay.
   // Whatever the values read, the order is a permutation of the step's

@@ -16,6 +16,9 @@ enum Counter : int {
   kCntRenderPeak = 4,   // most pairs an overflowing tile needs in the render in flight (reset by the sort)
 };
 constexpr int kCounterWords = 8;
+// An entry of a tile order: the tile in the low 30 bits; the top two bits
+// turn the quadrants of a fused tracking workgroup at one pixel per lane.
+constexpr uint32_t kOrderTileMask = 0x3FFFFFFFu;
 
 // A launch replayed from a captured graph reads whatever view table the state
 // holds when it runs; one workgroup compares the table's hash with the one
@@ -131,8 +134,10 @@ void launch_clear_u32(uint32_t* p, int64_t n, hipStream_t s);
 // after the sort, or with ranges null from the pair counters (stride
 // kTileCounterStride) before a blend that sorts its own buckets.  snake
 // (for launches whose tiles are all resident at once, up to 2048 tiles):
-// every other run of 256 positions reversed and the last, short run placed
-// by the work the full runs gave each position.
+// lengths are the sums of counts[0..3] of each tile's line (four quadrants'
+// work), every other run of 256 positions is reversed, the last, short run is
+// placed by the work the full runs gave each position, and each entry gets a
+// quadrant rotation in bits 30..31 (kOrderTileMask keeps the tile).
 void launch_tile_order(const uint2* ranges, const uint32_t* counts, int32_t tiles, uint32_t* order, hipStream_t s,
                        bool snake = false);
 // Pair counter of each tile = the length of its range (undoes the reset of
@@ -173,14 +178,16 @@ struct RasterBufs {
   bool sort_here;
   const uint64_t* bucket_keys;   // [T][tile_cap]
   uint32_t* tile_count;          // [T * kTileCounterStride], reset to zero here; the fused
-                                 // tracking kernel leaves the tile's work in word 1
+                                 // tracking kernel leaves each quadrant's work in words 1..4
   uint32_t* counters;            // kCntRenderPeak reset here
   uint32_t tile_cap;
   // Timing re-runs of a tracking step's kernel leave the pair counters as
   // they are, so every re-run sorts and walks the same buckets.
   bool keep_counts;
   // Tile of each workgroup, longest list first (launch_tile_order), or null
-  // for workgroup b on tile b.
+  // for workgroup b on tile b; entries are masked with kOrderTileMask, and
+  // the fused tracking kernel at one pixel per lane turns its quadrants by
+  // the top two bits.
   const uint32_t* order;
 };
 // ppl: pixels per lane, 1, 2 or 4 (256 / ppl lanes per 16x16 tile).

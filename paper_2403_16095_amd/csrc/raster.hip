@@ -122,7 +122,7 @@ __device__ __forceinline__ bool wave_takes(int w, uint32_t cx0, uint32_t cx1, ui
 // its own (tracking), else the block shares the loads and tests (mapping).
 template <int L, int W, bool kPerWave>
 __device__ __forceinline__ void stage_batch(const RasterBufs& b, Stage<W>& s, const uint32_t* ids, uint32_t pos0,
-                                            int n, float2 org, uint32_t tcx, uint32_t tcy) {
+                                            int n, float2 org, uint32_t tcx, uint32_t tcy, int rot = 0) {
   __syncthreads();
   if constexpr (W == 1) {
     for (int i = threadIdx.x; i < n; i += L) {
@@ -157,7 +157,8 @@ __device__ __forceinline__ void stage_batch(const RasterBufs& b, Stage<W>& s, co
         B.w = __int_as_float((int)(pos0 + i + 1));
         C.w = __uint_as_float(m);
         const uint2 r = b.rect[m];
-        take = wave_takes<W>(wv, r.x & 0xFFFFu, r.x >> 16, r.y & 0xFFFFu, r.y >> 16, tcx, tcy, A, B);
+        take = wave_takes<W>(W == 4 ? ((wv + rot) & 3) : wv, r.x & 0xFFFFu, r.x >> 16, r.y & 0xFFFFu, r.y >> 16, tcx,
+                             tcy, A, B);
       }
       const uint64_t bal = __ballot(take);
       if (take) {
@@ -243,7 +244,7 @@ struct FwdPix {
 template <int kPPL, bool kTrack, bool kNu, bool kFull = true, bool kStats = kFull>
 __device__ __forceinline__ void forward_tile(const RasterBufs& b, Stage<kTilePixels / kPPL / kWave>& s, int gtile,
                                              const ViewIO& io, float2 org, uint2 range, const uint32_t* ids,
-                                             FwdPix<kPPL>& f) {
+                                             FwdPix<kPPL>& f, int rot = 0) {
   constexpr int L = kTilePixels / kPPL;
   constexpr int W = L / kWave;
   const int wv = threadIdx.x / kWave;
@@ -253,7 +254,8 @@ __device__ __forceinline__ void forward_tile(const RasterBufs& b, Stage<kTilePix
   bool lane_done = true;
 #pragma unroll
   for (int k = 0; k < kPPL; ++k) {
-    const PixelCoord pc = pixel_of(cam, gtile, k * L + threadIdx.x);
+    const int q = k * L + threadIdx.x;   // quadrant q / 64, turned by rot
+    const PixelCoord pc = pixel_of(cam, gtile, ((((q >> 6) + rot) & 3) << 6) | (q & 63));
     f.fx[k] = (float)(pc.px - pc.ox);
     f.fy[k] = (float)(pc.py - pc.oy);
     f.inside[k] = pc.inside;
@@ -273,7 +275,7 @@ __device__ __forceinline__ void forward_tile(const RasterBufs& b, Stage<kTilePix
   }
   for (uint32_t base = range.x; base < range.y; base += kBatch) {
     const int n = (int)min((uint32_t)kBatch, range.y - base);
-    stage_batch<L, W, kTrack>(b, s, ids + (base - range.x), base - range.x, n, org, tcx, tcy);
+    stage_batch<L, W, kTrack>(b, s, ids + (base - range.x), base - range.x, n, org, tcx, tcy, rot);
     // the copy's length is the same for the whole wave
     const int nw = (int)__builtin_amdgcn_readfirstlane(s.cnt[wv]);
     if (kTrack && base == range.x) prioritise((uint32_t)nw, kTrackWavePrio[0], kTrackWavePrio[1], kTrackWavePrio[2]);
@@ -451,7 +453,7 @@ __device__ __forceinline__ int block_max(uint32_t lane_max, uint32_t* s_max) {
 // staged_n > 0: the stage already holds list entries [0, staged_n).
 template <int kPPL, bool kParams, bool kTrack, bool kColor = false>
 __device__ __forceinline__ void backward_tile(const RasterBufs& b, Stage<kTilePixels / kPPL / kWave>& s, uint2 range,
-                                              float2 org, int nmax, int staged_n, BwdPix<kPPL>& p) {
+                                              float2 org, int nmax, int staged_n, BwdPix<kPPL>& p, int rot = 0) {
   constexpr int L = kTilePixels / kPPL;
   constexpr int W = L / kWave;
   const int lane = threadIdx.x & 63;
@@ -461,7 +463,7 @@ __device__ __forceinline__ void backward_tile(const RasterBufs& b, Stage<kTilePi
     const int start = max(0, end - kBatch);
     const int n = end - start;
     if (!(start == 0 && end <= staged_n))
-      stage_batch<L, W, kTrack>(b, s, b.vals + range.x + start, start, n, org, tcx, tcy);
+      stage_batch<L, W, kTrack>(b, s, b.vals + range.x + start, start, n, org, tcx, tcy, rot);
     for (int j = (int)__builtin_amdgcn_readfirstlane(s.cnt[wv]) - 1; j >= 0; --j) {
       const float4 A = s.A[wv][j];
       const float4 B = s.B[wv][j];
@@ -558,7 +560,7 @@ __device__ __forceinline__ void backward_tile(const RasterBufs& b, Stage<kTilePi
 template <int kPPL, bool kTrack, bool kNu, bool kStats = true>
 __global__ __launch_bounds__(kTilePixels / kPPL) void raster_forward_kernel(RasterBufs b) {
   __shared__ Stage<kTilePixels / kPPL / kWave> s;
-  const int gtile = b.order ? (int)b.order[blockIdx.x] : (int)blockIdx.x;
+  const int gtile = b.order ? (int)(b.order[blockIdx.x] & kOrderTileMask) : (int)blockIdx.x;
   const int v = view_of_tile(b.views, gtile);
   const ViewIO io = b.views.io[v];
   FwdPix<kPPL> f;
@@ -575,7 +577,7 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_backward_kernel(Ras
   constexpr int L = kTilePixels / kPPL;
   __shared__ Stage<kTilePixels / kPPL / kWave> s;
   __shared__ uint32_t s_max;
-  const int gtile = b.order ? (int)b.order[blockIdx.x] : (int)blockIdx.x;
+  const int gtile = b.order ? (int)(b.order[blockIdx.x] & kOrderTileMask) : (int)blockIdx.x;
   const int v = view_of_tile(b.views, gtile);
   const ViewIO io = b.views.io[v];
   const ViewInfo& cam = io.info;
@@ -669,28 +671,42 @@ template <int kPPL, bool kColor, bool kFull>
 __global__ __launch_bounds__(kTilePixels / kPPL) void raster_track_kernel(RasterBufs b) {
   constexpr int L = kTilePixels / kPPL;
   __shared__ Stage<kTilePixels / kPPL / kWave> s;
-  __shared__ uint32_t s_max, s_work;
+  __shared__ uint32_t s_max;
   __shared__ uint32_t s_ids[L];
   // The bucket's keys are ranked before the first batch is staged, so they
   // share the stage's storage (keeping the workgroup's LDS at 25.6 KB, six
   // workgroups per CU at one pixel per lane).
   static_assert(sizeof(s.A) >= sizeof(uint64_t) * L, "sort keys fit the stage");
   uint64_t* s_key = reinterpret_cast<uint64_t*>(&s.A[0][0]);
-  const int gtile = b.order ? (int)b.order[blockIdx.x] : (int)blockIdx.x;
+  const uint32_t ord = b.order ? b.order[blockIdx.x] : (uint32_t)blockIdx.x;
+  const int gtile = (int)(ord & kOrderTileMask);
+  // one pixel per lane: wave w takes quadrant (w + rot) & 3, a rotation the
+  // order chose per workgroup so that the SIMDs of a CU get even work
+  const int rot = kPPL == 1 ? (int)(ord >> 30) : 0;
   const int v = view_of_tile(b.views, gtile);
   const ViewIO io = b.views.io[v];
   const float2 org = tile_origin(io.info, gtile);
-  if (threadIdx.x == 0) s_work = 0u;
   const uint2 range = b.sort_here ? sort_own_bucket<L>(b, gtile, s_key, s_ids, &s_max) : b.ranges[gtile];
   prioritise(range.y - range.x, kTrackTilePrio[0], kTrackTilePrio[1], kTrackTilePrio[2]);
   BwdPix<kPPL> p;
   uint32_t lane_max = 0;
   {
     FwdPix<kPPL> f;
-    forward_tile<kPPL, true, false, kFull>(b, s, gtile, io, org, range, b.sort_here ? s_ids : b.vals + range.x, f);
+    forward_tile<kPPL, true, false, kFull>(b, s, gtile, io, org, range, b.sort_here ? s_ids : b.vals + range.x, f,
+                                           rot);
     float g[kPPL][4];
     forward_outputs<kPPL, true, false, kFull>(b, v, io, f, g, false);
-    if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&s_work, f.wave_len);
+    // each quadrant's work for the next step's order (word 1 + quadrant of
+    // the tile's counter line)
+    if constexpr (kPPL == 1) {
+      if ((threadIdx.x & (kWave - 1)) == 0)
+        b.tile_count[(size_t)gtile * kTileCounterStride + 1 + ((threadIdx.x / kWave + rot) & 3)] = f.wave_len;
+    } else {
+      constexpr int W = kTilePixels / kPPL / kWave;
+      if ((threadIdx.x & (kWave - 1)) == 0)
+        b.tile_count[(size_t)gtile * kTileCounterStride + 1 + threadIdx.x / kWave] = f.wave_len;
+      if (threadIdx.x < 4 - W) b.tile_count[(size_t)gtile * kTileCounterStride + 1 + W + threadIdx.x] = 0u;
+    }
 #pragma unroll
     for (int k = 0; k < kPPL; ++k) {
       p.fx[k] = f.fx[k];
@@ -708,10 +724,8 @@ __global__ __launch_bounds__(kTilePixels / kPPL) void raster_track_kernel(Raster
     }
   }
   const int nmax = block_max(lane_max, &s_max);
-  // the tile's work for the next step's order: its waves' list lengths
-  if (threadIdx.x == 0) b.tile_count[(size_t)gtile * kTileCounterStride + 1] = s_work;
   const int len = (int)(range.y - range.x);
-  backward_tile<kPPL, false, true, kColor>(b, s, range, org, nmax, len <= kBatch ? len : 0, p);
+  backward_tile<kPPL, false, true, kColor>(b, s, range, org, nmax, len <= kBatch ? len : 0, p, rot);
 }
 
 template <int kPPL>
