@@ -66,6 +66,7 @@ void dev_free(T*& p) {
 // about what it saves (32 frames of mixed resolution, 54k tiles: 0.5 %
 // slower with the order; eight 1200x680 views, 25.8k tiles: 1.5 % faster).
 constexpr int32_t kOrderMinTiles = 1536;
+static_assert(kOrderMinTiles <= kKeptOrderMaxTiles, "every step below kOrderMinTiles tiles can keep its order");
 constexpr int kTunePasses = 2;   // timing passes over an autotuner's candidates
 constexpr int32_t kOrderMaxTiles = 32768;
 
@@ -600,7 +601,7 @@ cgsr_status render_impl(cgsr_state* st, const RenderArgs& a, hipStream_t stream)
       fresh = !st->track_order_ok || st->track_order_tiles != st->total_tiles || id != st->order_capture;
       st->order_capture = id;
     }
-    if (fresh) launch_tile_order(nullptr, st->tile_count + 1, st->total_tiles, st->tile_order, stream, true);
+    if (fresh) launch_tile_order_kept(st->tile_count + 1, st->total_tiles, st->tile_order, stream);
     HIP_TRY(hipGetLastError());
     st->order_ok = true;
     st->track_order_ok = true;

@@ -132,14 +132,17 @@ void launch_segment_sort(const SegSortBufs& b, int32_t total_tiles, hipStream_t 
 void launch_clear_u32(uint32_t* p, int64_t n, hipStream_t s);
 // Tiles by descending list length, in order[tiles]: lengths from the ranges
 // after the sort, or with ranges null from the pair counters (stride
-// kTileCounterStride) before a blend that sorts its own buckets.  snake
-// (for launches whose tiles are all resident at once, up to 2048 tiles):
-// lengths are the sums of counts[0..3] of each tile's line (four quadrants'
-// work), every other run of 256 positions is reversed, the last, short run is
-// placed by the work the full runs gave each position, and each entry gets a
-// quadrant rotation in bits 30..31 (kOrderTileMask keeps the tile).
-void launch_tile_order(const uint2* ranges, const uint32_t* counts, int32_t tiles, uint32_t* order, hipStream_t s,
-                       bool snake = false);
+// kTileCounterStride) before a blend that sorts its own buckets.
+void launch_tile_order(const uint2* ranges, const uint32_t* counts, int32_t tiles, uint32_t* order, hipStream_t s);
+// The order a fused tracking launch whose tiles are all resident at once
+// keeps across steps (1 .. kKeptOrderMaxTiles tiles): lengths are the sums of
+// quads[0..3] of each tile's line (stride kTileCounterStride: the four
+// quadrants' work the previous step measured), every other run of 256
+// positions is reversed, the last, short run is placed by the work the full
+// runs gave each position, and each entry gets a quadrant rotation in bits
+// 30..31 (kOrderTileMask keeps the tile).
+constexpr int32_t kKeptOrderMaxTiles = 2048;
+void launch_tile_order_kept(const uint32_t* quads, int32_t tiles, uint32_t* order, hipStream_t s);
 // Pair counter of each tile = the length of its range (undoes the reset of
 // a tracking kernel that sorted its own buckets).
 void launch_restore_counts(uint32_t* tile_count, const uint2* ranges, int32_t tiles, hipStream_t s);

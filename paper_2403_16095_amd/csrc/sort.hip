@@ -145,21 +145,9 @@ __global__ __launch_bounds__(kThreads) void clear_kernel(uint32_t* p, int64_t n)
 // 16 bins per octave (the leading bit and the next four), scanned from the
 // longest bin; tiles inside a bin keep the order their atomics left, which
 // changes no tile's result.
-// snake (for launches whose tiles are all resident from the start): every
-// other run of kOrderRound positions is reversed, so that the workgroups
-// dealt one per CU take, CU by CU, a long tile of one run with a short one
-// of the next, and the last, short run gives its tiles to the CU positions
-// the full runs loaded least; the CUs' summed work comes out more even (a
-// model of the dispatch over measured tracking lists: the fullest CU 1.16x
-// the mean work longest first, 1.10x with the runs reversed, 1.06x with the
-// last run placed by load).  A tile's length is then the work its four waves
-// measured in the previous step (words 1..4 of its counter line; counts
-// points at word 1), and each entry also takes a quadrant rotation in its top
-// two bits.
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderBins = 16 * 33;
 constexpr uint32_t kOrderRound = 256;   // compute units of the chip
-constexpr int kSnakeMaxTiles = 2048;
 
 __device__ __forceinline__ uint32_t order_bin(uint32_t n) {
   if (n == 0) return 0;
@@ -169,30 +157,19 @@ __device__ __forceinline__ uint32_t order_bin(uint32_t n) {
 }
 
 // A tile's list length: from its range after the sort, or (ranges null) from
-// its pair counter before a blend that sorts its own bucket, or (quads) the
-// sum of the four quadrants' work.  The bin counts and the ranks must both
-// come from this one function, or ranks collide and positions go unwritten.
-__device__ __forceinline__ uint32_t tile_length(const uint2* ranges, const uint32_t* counts, int t, bool quads) {
+// its pair counter before a blend that sorts its own bucket.
+__device__ __forceinline__ uint32_t tile_length(const uint2* ranges, const uint32_t* counts, int t) {
   if (ranges) {
     const uint2 r = ranges[t];
     return r.y - r.x;
   }
-  const uint32_t* c = counts + (size_t)t * kTileCounterStride;
-  return quads ? c[0] + c[1] + c[2] + c[3] : c[0];
+  return counts[(size_t)t * kTileCounterStride];
 }
 
-__global__ __launch_bounds__(kOrderThreads) void tile_order_kernel(const uint2* __restrict__ ranges,
-                                                                   const uint32_t* __restrict__ counts, int32_t tiles,
-                                                                   uint32_t* __restrict__ order, int snake) {
-  __shared__ uint32_t s_bin[kOrderBins];
-  __shared__ uint32_t s_wave[kOrderThreads / kWave];
-  for (int i = threadIdx.x; i < kOrderBins; i += kOrderThreads) s_bin[i] = 0u;
-  __syncthreads();
-  for (int t = threadIdx.x; t < tiles; t += kOrderThreads)
-    atomicAdd(&s_bin[order_bin(tile_length(ranges, counts, t, snake))], 1u);
-  __syncthreads();
-  // exclusive offsets, the longest bin first: thread k takes bin
-  // kOrderBins - 1 - k (kOrderBins <= kOrderThreads)
+// s_bin holds each bin's count on entry and its first position, the longest
+// bin first, on return: thread k scans bin kOrderBins - 1 - k.
+__device__ __forceinline__ void bin_offsets_longest_first(uint32_t* s_bin, uint32_t* s_wave) {
+  static_assert(kOrderBins <= kOrderThreads, "one bin per thread in the scan");
   const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
   const int bin = kOrderBins - 1 - (int)threadIdx.x;
   const uint32_t c = bin >= 0 ? s_bin[bin] : 0u;
@@ -208,23 +185,68 @@ __global__ __launch_bounds__(kOrderThreads) void tile_order_kernel(const uint2* 
   for (int q = 0; q < wv; ++q) base += s_wave[q];
   if (bin >= 0) s_bin[bin] = base + inc - c;
   __syncthreads();
-  if (!snake) {
-    for (int t = threadIdx.x; t < tiles; t += kOrderThreads)
-      order[atomicAdd(&s_bin[order_bin(tile_length(ranges, counts, t, false))], 1u)] = (uint32_t)t;
-    return;
-  }
-  // snake (tiles <= kSnakeMaxTiles): the full runs of kOrderRound positions
-  // alternate direction; the last, short run's tiles (the shortest, longest
-  // of them first) go to its positions in ascending order of the work the
-  // full runs gave the same CU position.
-  __shared__ uint32_t s_load[kOrderRound], s_perm[kOrderRound], s_ord[kSnakeMaxTiles];
+}
+
+__global__ __launch_bounds__(kOrderThreads) void tile_order_kernel(const uint2* __restrict__ ranges,
+                                                                   const uint32_t* __restrict__ counts, int32_t tiles,
+                                                                   uint32_t* __restrict__ order) {
+  __shared__ uint32_t s_bin[kOrderBins];
+  __shared__ uint32_t s_wave[kOrderThreads / kWave];
+  for (int i = threadIdx.x; i < kOrderBins; i += kOrderThreads) s_bin[i] = 0u;
+  __syncthreads();
+  for (int t = threadIdx.x; t < tiles; t += kOrderThreads)
+    atomicAdd(&s_bin[order_bin(tile_length(ranges, counts, t))], 1u);
+  __syncthreads();
+  bin_offsets_longest_first(s_bin, s_wave);
+  for (int t = threadIdx.x; t < tiles; t += kOrderThreads)
+    order[atomicAdd(&s_bin[order_bin(tile_length(ranges, counts, t))], 1u)] = (uint32_t)t;
+}
+
+// The kept order of a launch whose tiles are all resident from the start
+// (tiles <= kKeptOrderMaxTiles).  A tile's length is the work its four waves
+// measured in the previous step: quads[t * kTileCounterStride + k] for
+// quadrant k (words 1..4 of its counter line), read once into LDS.  Longest
+// first as above, then every other run of kOrderRound positions reversed, so
+// that the workgroups dealt one per CU take, CU by CU, a long tile of one run
+// with a short one of the next, and the last, short run's tiles (the
+// shortest, longest of them first) go to its positions in ascending order of
+// the work the full runs gave the same CU position; the CUs' summed work
+// comes out more even (a model of the dispatch over measured tracking lists:
+// the fullest CU 1.16x the mean work longest first, 1.10x with the runs
+// reversed, 1.06x with the last run placed by load).  Each entry then takes a
+// quadrant rotation in its top two bits (below).
+__global__ __launch_bounds__(kOrderThreads) void tile_order_kept_kernel(const uint32_t* __restrict__ quads,
+                                                                        int32_t tiles, uint32_t* __restrict__ order) {
+  __shared__ uint32_t s_bin[kOrderBins];
+  __shared__ uint32_t s_wave[kOrderThreads / kWave];
+  __shared__ uint4 s_quad[kKeptOrderMaxTiles];
+  __shared__ uint32_t s_load[kOrderRound], s_perm[kOrderRound], s_ord[kKeptOrderMaxTiles];
+  constexpr int kPer = kKeptOrderMaxTiles / kOrderThreads;
+  for (int i = threadIdx.x; i < kOrderBins; i += kOrderThreads) s_bin[i] = 0u;
   if (threadIdx.x < kOrderRound) s_load[threadIdx.x] = 0u;
-  constexpr int kPer = kSnakeMaxTiles / kOrderThreads;
-  uint32_t rank[kPer], len[kPer];
+  uint4 qw[kPer];
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {   // every load in flight at once
+    const int t = threadIdx.x + q * kOrderThreads;
+    const uint32_t* c = quads + (size_t)t * kTileCounterStride;
+    qw[q] = t < tiles ? make_uint4(c[0], c[1], c[2], c[3]) : make_uint4(0u, 0u, 0u, 0u);
+  }
+  __syncthreads();
+  uint32_t len[kPer], rank[kPer];
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
     const int t = threadIdx.x + q * kOrderThreads;
-    len[q] = t < tiles ? tile_length(ranges, counts, t, true) : 0u;
+    len[q] = qw[q].x + qw[q].y + qw[q].z + qw[q].w;
+    if (t < tiles) {
+      s_quad[t] = qw[q];
+      atomicAdd(&s_bin[order_bin(len[q])], 1u);
+    }
+  }
+  __syncthreads();
+  bin_offsets_longest_first(s_bin, s_wave);
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int t = threadIdx.x + q * kOrderThreads;
     rank[q] = t < tiles ? atomicAdd(&s_bin[order_bin(len[q])], 1u) : 0u;
   }
   const uint32_t full = (uint32_t)tiles / kOrderRound * kOrderRound, rem = (uint32_t)tiles - full;
@@ -240,11 +262,18 @@ __global__ __launch_bounds__(kOrderThreads) void tile_order_kernel(const uint2* 
     }
   }
   __syncthreads();
-  if (threadIdx.x < rem) {   // rank of the position by (load, position)
-    const uint32_t j = threadIdx.x, key = s_load[j];
+  {   // rank of each last-run position by (load, position): four lanes per position
+    static_assert(kOrderThreads == 4 * kOrderRound, "four lanes rank each position");
+    const uint32_t j = threadIdx.x >> 2, part = threadIdx.x & 3u;
     uint32_t r = 0;
-    for (uint32_t i = 0; i < rem; ++i) r += (s_load[i] < key || (s_load[i] == key && i < j)) ? 1u : 0u;
-    s_perm[r] = j;
+    if (j < rem) {
+      const uint32_t key = s_load[j];
+#pragma unroll 4
+      for (uint32_t i = part; i < rem; i += 4) r += (s_load[i] < key || (s_load[i] == key && i < j)) ? 1u : 0u;
+    }
+    r += __shfl_xor(r, 1);
+    r += __shfl_xor(r, 2);
+    if (j < rem && part == 0) s_perm[r] = j;
   }
   __syncthreads();
 #pragma unroll
@@ -254,30 +283,34 @@ __global__ __launch_bounds__(kOrderThreads) void tile_order_kernel(const uint2* 
   }
   __syncthreads();
   // The workgroups at positions c, c + 256, ... run on one CU, the r-th of
-  // them with its waves on that CU's SIMDs in the order kSimdOf[(w + r) & 3]
-  // (the dispatcher's rule, up to a renaming of the SIMDs).  Each CU's
-  // workgroups in turn take the quadrant rotation that keeps its busiest
-  // SIMD least busy.
-  constexpr uint32_t kSimdOf[4] = {0, 2, 1, 3};
+  // them with its wave w on that CU's SIMD kSimdOf[(w + r) & 3] (the
+  // dispatcher's rule, up to a renaming of the SIMDs).  Wave w takes
+  // quadrant (w + rot) & 3, so SIMD s gets quadrant (kSimdOf[s] + d) & 3 with
+  // d = rot - r (kSimdOf is its own inverse).  Each CU's workgroups in turn
+  // take the d, the first of equals, that keeps the CU's busiest SIMD least
+  // busy.
   if (threadIdx.x < kOrderRound) {
+    constexpr uint32_t kSimdOf[4] = {0, 2, 1, 3};
     uint32_t load[4] = {0u, 0u, 0u, 0u};
     uint32_t r = 0;
     for (uint32_t p = threadIdx.x; p < (uint32_t)tiles; p += kOrderRound, ++r) {
       const uint32_t t = s_ord[p];
-      uint32_t qw[4];
-      for (int k = 0; k < 4; ++k) qw[k] = counts[(size_t)t * kTileCounterStride + k];
+      const uint4 w4 = s_quad[t];
+      const uint32_t qw[4] = {w4.x, w4.y, w4.z, w4.w};
+      uint32_t trial[4][4];   // [d][s]
       uint32_t best = 0xFFFFFFFFu, pick = 0;
-      for (uint32_t rr = 0; rr < 4; ++rr) {
-        uint32_t trial[4] = {load[0], load[1], load[2], load[3]};
-        for (uint32_t w = 0; w < 4; ++w) trial[kSimdOf[(w + r) & 3]] += qw[(w + rr) & 3];
-        const uint32_t m = max(max(trial[0], trial[1]), max(trial[2], trial[3]));
-        if (m < best) {
-          best = m;
-          pick = rr;
-        }
+#pragma unroll
+      for (uint32_t d = 0; d < 4; ++d) {
+#pragma unroll
+        for (uint32_t s4 = 0; s4 < 4; ++s4) trial[d][s4] = load[s4] + qw[(kSimdOf[s4] + d) & 3];
+        const uint32_t m = max(max(trial[d][0], trial[d][1]), max(trial[d][2], trial[d][3]));
+        pick = m < best ? d : pick;
+        best = m < best ? m : best;
       }
-      for (uint32_t w = 0; w < 4; ++w) load[kSimdOf[(w + r) & 3]] += qw[(w + pick) & 3];
-      order[p] = t | (pick << 30);
+#pragma unroll
+      for (uint32_t s4 = 0; s4 < 4; ++s4)
+        load[s4] = pick == 0 ? trial[0][s4] : pick == 1 ? trial[1][s4] : pick == 2 ? trial[2][s4] : trial[3][s4];
+      order[p] = t | (((pick + r) & 3u) << 30);
     }
   }
 }
@@ -299,12 +332,14 @@ void launch_clear_u32(uint32_t* p, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(clear_kernel, dim3((unsigned)blocks), dim3(kThreads), 0, s, p, n);
 }
 
-void launch_tile_order(const uint2* ranges, const uint32_t* counts, int32_t tiles, uint32_t* order, hipStream_t s,
-                       bool snake) {
+void launch_tile_order(const uint2* ranges, const uint32_t* counts, int32_t tiles, uint32_t* order, hipStream_t s) {
   if (tiles <= 0) return;
-  static_assert(kOrderBins <= kOrderThreads, "one bin per thread in the scan");
-  hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderThreads), 0, s, ranges, counts, tiles, order,
-                     snake && tiles <= kSnakeMaxTiles ? 1 : 0);
+  hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderThreads), 0, s, ranges, counts, tiles, order);
+}
+
+void launch_tile_order_kept(const uint32_t* quads, int32_t tiles, uint32_t* order, hipStream_t s) {
+  if (tiles <= 0 || tiles > kKeptOrderMaxTiles) return;   // callers keep within the limit
+  hipLaunchKernelGGL(tile_order_kept_kernel, dim3(1), dim3(kOrderThreads), 0, s, quads, tiles, order);
 }
 
 void launch_restore_counts(uint32_t* tile_count, const uint2* ranges, int32_t tiles, hipStream_t s) {
