@@ -184,30 +184,69 @@ __device__ __forceinline__ constexpr int reduced_value_index(int lane) {
 // the two results of its permlane-swap builtins into one (the IR adds the
 // first result to itself), which would silently drop half of every sum.  The
 // s_nop pairs give the wait states a VALU write needs before a permlane reads
-// the register, and a permlane write before the next VALU reads it.
-__device__ __forceinline__ float swap_add32(float x, float y) {
-  asm volatile("s_nop 1\n\tv_permlane32_swap_b32 %0, %1\n\ts_nop 1" : "+v"(x), "+v"(y));
-  return x + y;
+// the register, and a permlane write before the next VALU reads it.  The
+// swaps of one reduction level touch different registers, so they share one
+// block and one pair of s_nop (up to four swaps a block).
+#define CGSR_PERMLANE_SWAPS(op, n)                                                                     \
+  if constexpr (n == 1) {                                                                              \
+    asm volatile("s_nop 1\n\t" op " %0, %1\n\ts_nop 1" : "+v"(x[0]), "+v"(y[0]));                      \
+  } else if constexpr (n == 2) {                                                                       \
+    asm volatile("s_nop 1\n\t" op " %0, %1\n\t" op " %2, %3\n\ts_nop 1"                                \
+                 : "+v"(x[0]), "+v"(y[0]), "+v"(x[1]), "+v"(y[1]));                                    \
+  } else if constexpr (n == 3) {                                                                       \
+    asm volatile("s_nop 1\n\t" op " %0, %1\n\t" op " %2, %3\n\t" op " %4, %5\n\ts_nop 1"              \
+                 : "+v"(x[0]), "+v"(y[0]), "+v"(x[1]), "+v"(y[1]), "+v"(x[2]), "+v"(y[2]));            \
+  } else {                                                                                             \
+    asm volatile("s_nop 1\n\t" op " %0, %1\n\t" op " %2, %3\n\t" op " %4, %5\n\t" op " %6, %7\n\ts_nop 1" \
+                 : "+v"(x[0]), "+v"(y[0]), "+v"(x[1]), "+v"(y[1]), "+v"(x[2]), "+v"(y[2]), "+v"(x[3]),  \
+                   "+v"(y[3]));                                                                        \
+  }
+
+// x[i] <-> y[i] across the wave halves (lanes 32-63 of x with 0-31 of y).
+template <int N>
+__device__ __forceinline__ void swap_halves32(float* x, float* y) {
+  static_assert(N >= 1, "at least one pair");
+  CGSR_PERMLANE_SWAPS("v_permlane32_swap_b32", (N < 4 ? N : 4))
+  if constexpr (N > 4) swap_halves32<N - 4>(x + 4, y + 4);
 }
 
-__device__ __forceinline__ float swap_add16(float x, float y) {
-  asm volatile("s_nop 1\n\tv_permlane16_swap_b32 %0, %1\n\ts_nop 1" : "+v"(x), "+v"(y));
-  return x + y;
+// The same across the 16-lane rows (rows 1 and 3 of x with rows 0 and 2 of y).
+template <int N>
+__device__ __forceinline__ void swap_halves16(float* x, float* y) {
+  static_assert(N >= 1, "at least one pair");
+  CGSR_PERMLANE_SWAPS("v_permlane16_swap_b32", (N < 4 ? N : 4))
+  if constexpr (N > 4) swap_halves16<N - 4>(x + 4, y + 4);
 }
+#undef CGSR_PERMLANE_SWAPS
 
 template <int NV, int K>
 __device__ __forceinline__ float wave_sum_many(const float (&v)[K]) {
   static_assert((NV == 8 || NV == 16) && K <= NV, "8 or 16 slots");
   const int lane = __lane_id();
+  // first level: value pairs (2p, 2p + 1) that hold a value, swapped and added
+  constexpr int P32 = (K + 1) / 2;
+  float x[P32], y[P32];
+#pragma unroll
+  for (int p = 0; p < P32; ++p) {
+    x[p] = v[2 * p];
+    y[p] = 2 * p + 1 < K ? v[2 * p + 1] : 0.f;
+  }
+  swap_halves32<P32>(x, y);
   float a[NV / 2];
 #pragma unroll
-  for (int p = 0; p < NV / 2; ++p) {
-    if (2 * p >= K) a[p] = 0.f;                                   // both slots empty
-    else a[p] = swap_add32(v[2 * p], 2 * p + 1 < K ? v[2 * p + 1] : 0.f);
+  for (int p = 0; p < NV / 2; ++p) a[p] = p < P32 ? x[p] + y[p] : 0.f;   // both slots empty beyond
+  // second level: pairs (a[2q], a[2q + 1]) that hold a value
+  constexpr int P16 = (K + 3) / 4;
+  float x2[P16], y2[P16];
+#pragma unroll
+  for (int q = 0; q < P16; ++q) {
+    x2[q] = a[2 * q];
+    y2[q] = a[2 * q + 1];
   }
+  swap_halves16<P16>(x2, y2);
   float b[NV / 4];
 #pragma unroll
-  for (int q = 0; q < NV / 4; ++q) b[q] = 4 * q >= K ? 0.f : swap_add16(a[2 * q], a[2 * q + 1]);
+  for (int q = 0; q < NV / 4; ++q) b[q] = q < P16 ? x2[q] + y2[q] : 0.f;
   float c[NV / 8];
   const bool hi8 = lane & 8;
 #pragma unroll
