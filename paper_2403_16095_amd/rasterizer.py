@@ -724,7 +724,11 @@ class TrackingSolver:
         self.adam.zero_()
 
     def prepare(self, pose0: torch.Tensor):
-        """Size the tile buckets from an eager step at pose0 and capture the graph."""
+        """Size the tile buckets from an eager step at pose0 and capture the
+        graph.  A graph that resets its own pose is then replayed once (the
+        first replay of a graph executable runs about 2 % slower than the
+        ones after it, even uploaded) and the pose set back to pose0; a
+        bucket overflow in that replay is reported by the next check()."""
         self.reset(pose0)
         self._iteration()                       # eager, grows the tile buckets
         torch.cuda.synchronize()
@@ -743,6 +747,9 @@ class TrackingSolver:
                         self._iteration()
             torch.cuda.current_stream().wait_stream(side)
             upload_graph(self.graph)
+            if self.pose0 is not None:
+                self.graph.replay()
+                self.reset(pose0)
             torch.cuda.synchronize()
 
     def run(self):
