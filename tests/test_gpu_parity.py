@@ -841,6 +841,66 @@ def test_kept_tile_order_across_tile_counts_and_captures(R):
             check(dp, "a", f"replay {rep}")
 
 
+@pytest.mark.parametrize("width,height", [(640, 512), (800, 480)])
+def test_kept_tile_order_at_full_runs_and_a_long_last_run(R, width, height):
+    """The kept order's edge shapes: 1280 tiles fill five runs of 256 (no last
+    run to place by load), 1500 leave a last run of 220 positions (ranked four
+    lanes to a position).  Steps that take the order (and its quadrant
+    rotations) from the previous step's measured work, eager and replayed from
+    a captured solve fragment, give the pose gradient and loss of a fresh
+    state's step."""
+    tiles = (width // 16) * (height // 16)
+    say("case: kept tile order,", width, "x", height, "=", tiles, "tiles, last run", tiles % 256)
+    sc = synth.room_scene(8, 30_000, (5.0, 4.0, 3.0))
+    scd = dev(sc)
+    cam = synth.camera(width, height, 0.82 * width, 0.82 * width, width / 2, height / 2)
+    pose = synth.level_room_pose(71)
+    out = R.render(R.State(), scd, R.pose_tensor(*pose), [cam])[0]
+    tc, td = out["color"].clone(), out["depth"].clone()
+    P0 = R.pose_tensor(*synth.perturb_pose(*pose, 72))
+
+    def step(st, dp, loss):
+        R.tracking_step(st, scd, P0, [cam], [tc], [td], dposes=dp, loss=loss)
+
+    ref, ref_loss = torch.zeros((1, 6), device="cuda"), torch.zeros(1, device="cuda")
+    step(R.State(), ref, ref_loss)
+    torch.cuda.synchronize()
+
+    def check(dp, loss, label):
+        e = ((dp - ref).abs().max() / ref.abs().max()).item()
+        el = abs(loss.item() - ref_loss.item()) / abs(ref_loss.item())
+        say(label, "pose gradient vs fresh state", e, "loss", el)
+        assert e < 1e-4 and el < 1e-5, (label, e, el)
+
+    st = R.State()
+    for k in range(3):   # the second and third take the order the one before measured
+        dp, loss = torch.zeros((1, 6), device="cuda"), torch.zeros(1, device="cuda")
+        step(st, dp, loss)
+        torch.cuda.synchronize()
+        st.check()
+        check(dp, loss, f"eager step {k}")
+    cap = int(st.stats().pair_capacity)
+    say("bucket capacity", cap)
+    assert cap <= 256, "the fused kernel ranks its own bucket, so the step keeps its order"
+    dps = [torch.zeros((1, 6), device="cuda") for _ in range(2)]
+    losses = [torch.zeros(1, device="cuda") for _ in range(2)]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        for dp, loss in zip(dps, losses):
+            dp.zero_()
+            loss.zero_()
+            step(st, dp, loss)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        st.check()
+        for dp, loss in zip(dps, losses):
+            check(dp, loss, f"replay {rep}")
+
+
 def test_replay_with_another_camera_table_is_reported(R):
     """A captured tracking step replayed after an eager call with another
     (smaller) camera on the same state runs with that call's camera table:
