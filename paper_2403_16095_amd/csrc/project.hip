@@ -52,30 +52,49 @@ struct Proj {
   double opacity;
 };
 
-// Eq. 1-2 for Gaussian i under pose P.  Returns false if the Gaussian is
-// culled (non-finite or zero quaternion, behind the near plane, opacity under
-// 1/255, singular 2-D covariance).
-__device__ bool project_core(const GaussianPtrs& g, int64_t i, const float* P, const ViewInfo& cam,
-                             Proj& o) {
-  const float4 q = reinterpret_cast<const float4*>(g.quats)[i];
-  const double q0 = q.x, q1 = q.y, q2 = q.z, q3 = q.w;
+// The parameters of Eq. 1-2 of one Gaussian, read together: the culling
+// tests of project_core then wait for one memory round trip, not one per
+// parameter (the compiler keeps loads behind the branches they follow).
+struct GaussianIn {
+  float4 q;
+  float ls[3], X[3];
+  float opacity_logit;
+};
+
+__device__ __forceinline__ GaussianIn load_gaussian(const GaussianPtrs& g, int64_t i) {
+  GaussianIn in;
+  in.q = reinterpret_cast<const float4*>(g.quats)[i];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    in.ls[k] = g.log_scales[3 * i + k];
+    in.X[k] = g.means[3 * i + k];
+  }
+  in.opacity_logit = g.opacity_logits[i];
+  return in;
+}
+
+// Eq. 1-2 for a Gaussian (parameters in) under pose P.  Returns false if the
+// Gaussian is culled (non-finite or zero quaternion, behind the near plane,
+// opacity under 1/255, singular 2-D covariance).
+__device__ bool project_core(const GaussianIn& in, const float* P, const ViewInfo& cam, Proj& o) {
+  double W[9], t[3];   // the pose, read before the first test as well
+#pragma unroll
+  for (int k = 0; k < 9; ++k) W[k] = P[k];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) t[r] = P[9 + r];
+  const double q0 = in.q.x, q1 = in.q.y, q2 = in.q.z, q3 = in.q.w;
   const double qn2 = q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3;
   if (!(qn2 > 0.0) || !(qn2 < 1.0e300)) return false;
   o.qinv = 1.0 / sqrt(qn2);
   o.qn[0] = q0 * o.qinv; o.qn[1] = q1 * o.qinv; o.qn[2] = q2 * o.qinv; o.qn[3] = q3 * o.qinv;
   quat_rot(o.qn[0], o.qn[1], o.qn[2], o.qn[3], o.R);
-  const float* ls = g.log_scales + 3 * i;
-  o.s[0] = exp((double)ls[0]); o.s[1] = exp((double)ls[1]); o.s[2] = exp((double)ls[2]);
-  const float* X = g.means + 3 * i;
-  const double X0 = X[0], X1 = X[1], X2 = X[2];
-  double W[9];
+  o.s[0] = exp((double)in.ls[0]); o.s[1] = exp((double)in.ls[1]); o.s[2] = exp((double)in.ls[2]);
+  const double X0 = in.X[0], X1 = in.X[1], X2 = in.X[2];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) W[k] = P[k];
-#pragma unroll
-  for (int r = 0; r < 3; ++r) o.p[r] = W[3 * r] * X0 + W[3 * r + 1] * X1 + W[3 * r + 2] * X2 + (double)P[9 + r];
+  for (int r = 0; r < 3; ++r) o.p[r] = W[3 * r] * X0 + W[3 * r + 1] * X1 + W[3 * r + 2] * X2 + t[r];
   const double z = o.p[2];
   if (!(z > (double)kNearZ)) return false;
-  o.opacity = 1.0f / (1.0f + expf(-g.opacity_logits[i]));
+  o.opacity = 1.0f / (1.0f + expf(-in.opacity_logit));
   if (!(o.opacity >= (double)kAlphaMin)) return false;
   // Sigma = (R S)(R S)^T, then Sc = W Sigma W^T with W the camera rotation.
   double M[9];
@@ -320,8 +339,15 @@ __global__ __launch_bounds__(kThreads) void project_kernel(GaussianPtrs g, const
   if (i < N) {
     const float* P = poses + 12 * v;
     const int64_t m = (int64_t)v * N + i;
+    // every parameter the record needs, colour included, in one round trip
+    const GaussianIn in = load_gaussian(g, i);
+    float rgb[3] = {0.f, 0.f, 0.f};
+    if (!g.sh) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) rgb[k] = g.rgb[3 * i + k];
+    }
     Proj o;
-    if (project_core(g, i, P, cam, o)) {
+    if (project_core(in, P, cam, o)) {
       const double mux = (double)cam.fx * (o.p[0] / o.p[2]) + (double)cam.cx;
       const double muy = (double)cam.fy * (o.p[1] / o.p[2]) + (double)cam.cy;
       // Bounding box of the alpha >= 1/255 ellipse, widened by the margins.
@@ -343,9 +369,9 @@ __global__ __launch_bounds__(kThreads) void project_kernel(GaussianPtrs g, const
           c[1] = sc.col[1];
           c[2] = sc.col[2];
         } else {
-          c[0] = g.rgb[3 * i];
-          c[1] = g.rgb[3 * i + 1];
-          c[2] = g.rgb[3 * i + 2];
+          c[0] = rgb[0];
+          c[1] = rgb[1];
+          c[2] = rgb[2];
         }
         float4* rec = b.rec + kRecF4 * m;
         // The mean is kept as a float pair hi + lo; the blend kernels take it
@@ -449,6 +475,7 @@ __global__ __launch_bounds__(kThreads) void project_backward_kernel(GaussianPtrs
     if (i < N && tiles[m] != 0u) {
       float4* gr = reinterpret_cast<float4*>(rec_grad + (int64_t)kGradStride * m);
       const float4 g0 = gr[0], g1 = gr[1], g2 = gr[2];
+      const GaussianIn in = load_gaussian(g, i);   // with the sums, one round trip
       gr[0] = make_float4(0.f, 0.f, 0.f, 0.f);
       gr[1] = make_float4(0.f, 0.f, 0.f, 0.f);
       gr[2] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -457,7 +484,7 @@ __global__ __launch_bounds__(kThreads) void project_backward_kernel(GaussianPtrs
       const float* P = poses + 12 * v;
       Proj o;
       // the record was visible in the forward at this pose, so this holds
-      if (project_core(g, i, P, cam, o)) {
+      if (project_core(in, P, cam, o)) {
         // power = -(a t^2 + c' dy^2) / 2 with t = dx + k dy, k = b / a and
         // c' = c - b^2 / a = 1 / Sigma2d_yy (dx, dy = mu - pixel), so
         // dpower/dmu = -(a t, a k t + c' dy) and dpower/d(a, b, c) =
