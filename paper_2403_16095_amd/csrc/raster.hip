@@ -301,8 +301,17 @@ __device__ __forceinline__ void forward_tile(const RasterBufs& b, Stage<kTilePix
           const float alpha = fminf(kAlphaMax, raw);
           const float wa = alpha * f.T[k];
           const float Tn = f.T[k] - wa;
-          const bool stop = hit && Tn < kTStop;
-          const bool blend = hit && !stop;
+          // Blend or stop splits the hits.  The issue-bound mapping walks take
+          // it from one compare; the tracking walk, bound by latency, ran
+          // slower that way.
+          bool stop, blend;
+          if constexpr (kTrack) {
+            stop = hit && Tn < kTStop;
+            blend = hit && !stop;
+          } else {
+            blend = hit && Tn >= kTStop;   // Tn is finite
+            stop = hit != blend;
+          }
           f.done[k] = f.done[k] || stop;
           if (kStats) f.evaluated[k] = stop ? loc + j + 1 : f.evaluated[k];
           const float wgt = blend ? wa : 0.f;
