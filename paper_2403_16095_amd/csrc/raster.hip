@@ -221,7 +221,7 @@ __device__ __forceinline__ void stage_batch(const RasterBufs& b, Stage<W>& s, co
 // Per-lane state of the forward walk.
 template <int kPPL>
 struct FwdPix {
-  float fx[kPPL], fy[kPPL], dobs[kPPL], T[kPPL], C0[kPPL], C1[kPPL], C2[kPPL], D[kPPL], O[kPPL], U[kPPL],
+  float fx[kPPL], fy[kPPL], dobs[kPPL], T[kPPL], C0[kPPL], C1[kPPL], C2[kPPL], D[kPPL], U[kPPL],
       Dmed[kPPL];
   int64_t pix[kPPL];
   uint32_t med1[kPPL];            // one past the median's position in the tile's list, 0 if none
@@ -262,7 +262,7 @@ __device__ __forceinline__ void forward_tile(const RasterBufs& b, Stage<kTilePix
     f.pix[k] = (int64_t)pc.py * cam.width + pc.px;
     f.dobs[k] = (!kTrack && io.depth_obs && pc.inside) ? io.depth_obs[f.pix[k]] : 0.f;
     f.T[k] = 1.f;
-    f.C0[k] = f.C1[k] = f.C2[k] = f.D[k] = f.O[k] = f.U[k] = f.Dmed[k] = 0.f;
+    f.C0[k] = f.C1[k] = f.C2[k] = f.D[k] = f.U[k] = f.Dmed[k] = 0.f;
     f.med1[k] = 0;
     f.last[k] = 0;
     f.blended[k] = 0;
@@ -319,7 +319,6 @@ __device__ __forceinline__ void forward_tile(const RasterBufs& b, Stage<kTilePix
           f.C1[k] = __builtin_fmaf(wgt, Cc.y, f.C1[k]);
           f.C2[k] = __builtin_fmaf(wgt, Cc.z, f.C2[k]);
           f.D[k] = __builtin_fmaf(wgt, B.z, f.D[k]);
-          if (kFull) f.O[k] += wgt;
           if (!kTrack) {
             const float dz = B.z - f.dobs[k];
             f.U[k] = __builtin_fmaf(wgt * dz, dz, f.U[k]);
@@ -404,7 +403,9 @@ __device__ __forceinline__ void forward_outputs(const RasterBufs& b, int v, cons
     }
     if (io.depth) io.depth[p] = f.D[k];
     if (!kFull) continue;
-    if (io.opacity) io.opacity[p] = f.O[k];
+    // Eq. 9's sum of the blend weights: each weight is the drop in
+    // transmittance it causes, so the sum is 1 - T (up to rounding)
+    if (io.opacity) io.opacity[p] = 1.f - f.T[k];
     if (io.depth_median) io.depth_median[p] = f.Dmed[k];
     if (io.uncertainty) io.uncertainty[p] = f.U[k];
     // the median's position, or ~0u if it has none
