@@ -600,6 +600,18 @@ cgsr_status cgsr_time_tracking_blend(cgsr_state *st, int32_t reps, void *stream,
 cgsr_status cgsr_debug_buffers(cgsr_state *st, const uint64_t **keys, const uint32_t **sorted_values,
                                const uint32_t **ranges, const float **records, const uint32_t **pixel_state);
 
+/* Debug view of the order in which the last render's blends took their
+ * (view, tile) work items (a device buffer owned by the state, valid until
+ * the next call on it).  *order: [*tiles] entries, the workgroup at position p
+ * taking tile order[p] & 0x3FFFFFFF, longest list first (Sec. 3.1 leaves the
+ * order free: every order gives each tile the same result), or NULL when the
+ * blends took the tiles in their own order.  *kept: 1 when it is the order a
+ * fused tracking step keeps from the work the previous step measured, whose
+ * entries also carry in bits 30-31 the quadrant rotation of that tile's
+ * workgroup, else 0.  Any output pointer may be NULL.  CGSR_ERR_STATE before
+ * the first render. */
+cgsr_status cgsr_debug_tile_order(cgsr_state *st, const uint32_t **order, int32_t *tiles, int32_t *kept);
+
 /* Message of the calling thread's last failure ("" if none). */
 const char *cgsr_last_error(void);
 

@@ -32,7 +32,7 @@ EXPORTED = (
     "cgsr_tracking_step", "cgsr_autotune_tracking", "cgsr_autotune_render", "cgsr_spawn_gaussians",
     "cgsr_compact_gaussians", "cgsr_compact_gaussians_noalloc", "cgsr_set_densify_stats", "cgsr_densify_gaussians",
     "cgsr_state_check", "cgsr_get_stats", "cgsr_get_timings", "cgsr_time_tracking_blend", "cgsr_debug_buffers",
-    "cgsr_last_error", "cgsr_version",
+    "cgsr_debug_tile_order", "cgsr_last_error", "cgsr_version",
 )
 STAGES = ("project", "emit", "sort", "blend_fwd", "blend_bwd", "project_bwd")
 
@@ -159,6 +159,7 @@ def lib() -> C.CDLL:
     L.cgsr_time_tracking_blend.argtypes = [vp, C.c_int32, vp, C.POINTER(C.c_float)]
     L.cgsr_debug_buffers.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
                                      C.POINTER(vp)]
+    L.cgsr_debug_tile_order.argtypes = [vp, C.POINTER(vp), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.cgsr_last_error.argtypes = []
     L.cgsr_last_error.restype = C.c_char_p
     L.cgsr_version.argtypes = []
@@ -368,6 +369,13 @@ def cgsr_debug_buffers(state: int):
     ptrs = [C.c_void_p() for _ in range(5)]
     _check(lib().cgsr_debug_buffers(state, *[C.byref(p) for p in ptrs]))
     return [p.value for p in ptrs]
+
+
+def cgsr_debug_tile_order(state: int):
+    """(device pointer or None, tiles, kept) of the last render's tile order."""
+    ptr, tiles, kept = C.c_void_p(), C.c_int32(), C.c_int32()
+    _check(lib().cgsr_debug_tile_order(state, C.byref(ptr), C.byref(tiles), C.byref(kept)))
+    return ptr.value, tiles.value, kept.value
 
 
 def cgsr_last_error() -> str:

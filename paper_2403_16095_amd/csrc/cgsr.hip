@@ -1428,6 +1428,15 @@ cgsr_status cgsr_debug_buffers(cgsr_state* st, const uint64_t** keys, const uint
   return CGSR_OK;
 }
 
+cgsr_status cgsr_debug_tile_order(cgsr_state* st, const uint32_t** order, int32_t* tiles, int32_t* kept) {
+  if (!st) return fail(CGSR_ERR_INVALID_ARG, "state is NULL");
+  if (!st->have_forward) return fail(CGSR_ERR_STATE, "no forward pass on this state");
+  if (order) *order = st->order_ok ? st->tile_order : nullptr;
+  if (tiles) *tiles = st->total_tiles;
+  if (kept) *kept = st->order_ok && st->track_order_ok ? 1 : 0;
+  return CGSR_OK;
+}
+
 const char* cgsr_last_error(void) { return g_last_error.c_str(); }
 
 const char* cgsr_version(void) { return "cgsr 0.2 (gfx950)"; }

@@ -57,6 +57,7 @@ def test_host_side_argument_checks(lib):
     assert lib.cgsr_pose_adam_step(1, 8, 8, 8, None, None) == B.CGSR_ERR_INVALID_ARG
     assert lib.cgsr_tracking_step(None, None, 1, None, None, None, None, 1.0, 1.0, None, None, None, None,
                                   None) == B.CGSR_ERR_INVALID_ARG
+    assert lib.cgsr_debug_tile_order(None, None, None, None) == B.CGSR_ERR_INVALID_ARG
     # the autotuners check their arguments before timing anything
     assert lib.cgsr_autotune_render(None, None, 1, None, None, None, None, None, None, None, 3, None,
                                     None) == B.CGSR_ERR_INVALID_ARG

@@ -901,6 +901,88 @@ def test_kept_tile_order_at_full_runs_and_a_long_last_run(R, width, height):
             check(dp, loss, f"replay {rep}")
 
 
+def _tile_order(R, st):
+    """(tile of each position, quadrant rotations, kept) of the last render."""
+    from paper_2403_16095_amd import binding as B
+    ptr, tiles, kept = B.cgsr_debug_tile_order(st.handle)
+    if ptr is None:
+        return None, None, kept
+    buf = torch.empty(tiles, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    copy_device(buf, ptr, tiles * 4)
+    e = buf.cpu().numpy().view(np.uint32).astype(np.int64)
+    return e & 0x3FFFFFFF, e >> 30, kept
+
+
+def _tile_lengths(R, st, tiles):
+    from paper_2403_16095_amd import binding as B
+    _, _, ranges, _, _ = B.cgsr_debug_buffers(st.handle)
+    rg = torch.empty((tiles, 2), dtype=torch.int32, device="cuda")
+    copy_device(rg, ranges, tiles * 8)
+    rg = rg.cpu().numpy().astype(np.int64)
+    return rg[:, 1] - rg[:, 0]
+
+
+def _order_bin(n):
+    """The order kernels' length bins: the leading bit and the next four."""
+    out = []
+    for x in np.asarray(n, np.int64).tolist():
+        lead = x.bit_length() - 1
+        frac = (x >> (lead - 4) if lead >= 4 else x << (4 - lead)) & 15
+        out.append(0 if x == 0 else 1 + 16 * lead + frac)
+    return np.array(out, np.int64)
+
+
+def test_tile_orders_are_permutations_longest_first(R):
+    """The order kernels' own output: a render's order (from the sorted
+    ranges) and a fused step's order at 3225 tiles (from the pair counters)
+    take every tile once, with non-increasing length bins; the order a fused
+    step keeps at 1200 tiles takes every tile once and gives each workgroup a
+    quadrant rotation; a launch of more tiles than the order kernels take
+    (11 views, 35 475 tiles) has no order, and the debug view says so."""
+    say("case: tile orders of renders and fused tracking steps")
+    sc = synth.room_scene(0, 100_000, (5.0, 4.0, 3.0))
+    scd = {k: torch.from_numpy(np.ascontiguousarray(v, np.float32)).cuda() for k, v in sc.items()}
+    true = synth.level_room_pose(0)
+    P = R.pose_tensor(*synth.perturb_pose(*true, 1000)).reshape(1, 12)
+    for cam, fused in ((synth.MAPPING_CAMERA, False), (synth.MAPPING_CAMERA, True),
+                       (synth.TRACKING_CAMERA, True)):
+        tiles = ((cam["width"] + 15) // 16) * ((cam["height"] + 15) // 16)
+        st = R.State(count_work=False)
+        tgt = R.render(R.State(), scd, R.pose_tensor(*true), [cam])[0]
+        tc, td = tgt["color"].contiguous(), tgt["depth"].contiguous()
+        if fused:
+            d = torch.zeros((1, 6), device="cuda")
+            R.tracking_step(st, scd, P.clone(), [cam], [tc], [td], dposes=d)
+            torch.cuda.synchronize()
+            st.reserve(tile_pairs=int(st.stats().peak_pairs * 1.5) + 64)
+            for _ in range(2):   # the second step keeps the order the first measured
+                R.tracking_step(st, scd, P.clone(), [cam], [tc], [td], dposes=d)
+        else:
+            R.render(st, scd, P, [cam])
+        torch.cuda.synchronize()
+        st.check()
+        order, rot, kept = _tile_order(R, st)
+        say(cam["width"], "x", cam["height"], "fused" if fused else "render", tiles, "tiles, kept", kept)
+        assert order is not None
+        assert np.array_equal(np.sort(order), np.arange(tiles)), "every tile exactly once"
+        if kept:
+            assert tiles < 1536 and fused
+            assert rot.min() >= 0 and rot.max() <= 3 and len(np.unique(rot)) > 1, "rotations in use"
+        else:
+            assert (rot == 0).all()
+            bins = _order_bin(_tile_lengths(R, st, tiles)[order])
+            assert (np.diff(bins) <= 0).all(), "longest list first"
+    st = R.State(count_work=False)
+    views = 11
+    R.render(st, scd, P.repeat(views, 1), [synth.MAPPING_CAMERA] * views, maps=("color",))
+    torch.cuda.synchronize()
+    st.check()
+    order, _, kept = _tile_order(R, st)
+    say(views, "views: order", order, "kept", kept)
+    assert order is None and kept == 0
+
+
 def test_replay_with_another_camera_table_is_reported(R):
     """A captured tracking step replayed after an eager call with another
     (smaller) camera on the same state runs with that call's camera table:
