@@ -108,7 +108,10 @@ def measured_counters(kernel: str):
     """Committed counter profile of `kernel` (profiles/blend_counters.json:
     HBM bytes per launch from FETCH_SIZE and WRITE_SIZE scaled by a copy
     calibration, VALU wave instructions per launch), or None if the kernel
-    sources changed since it was taken."""
+    sources changed since it was taken.  The figures are per launch of the
+    workload they were taken on (the fused blend: the 640x480 tracking
+    workload; the blend backward: one 1200x680 mapping view), so callers ask
+    only for those."""
     path = os.path.join(ROOT, "profiles", "blend_counters.json")
     try:
         with open(path) as f:
@@ -451,8 +454,10 @@ def run_mapping(args, torch, R, synth, views: int):
     # the dominant kernel: the blend backward to every parameter
     bwd_flops = FLOP_EVAL * st["walked"] + FLOP_BLEND_BWD_MAP * st["blended"]
     bsym = f"raster_backward_kernel<{res['batched']['ppl'][1]}, true, false, false>"
+    # the committed counters are per launch of the single-view workload
     roof = alu_roofline("blend_bwd_map", bsym, bwd_flops, stages["blend_bwd"],
-                        "library HIP events around the stage, 5 eager iterations", measured_counters(bsym))
+                        "library HIP events around the stage, 5 eager iterations",
+                        measured_counters(bsym) if views == 1 else None)
     fwd_flops = FLOP_EVAL * st["evaluations"] + FLOP_BLEND_MAP * st["blended"]
     fwd_tflops = fwd_flops / (stages["blend_fwd"] * 1e-3) / 1e12
     out = {
